@@ -1,0 +1,141 @@
+// Host side of the C ABI declared in include/nlrmm.h: argument validation, context and
+// workspace management, dispatch to the HIP launchers.
+#include "internal.h"
+
+#include <math.h>
+#include <new>
+
+namespace nlrmm {
+
+int ensure_workspace(nlrmm_ctx *ctx, size_t bytes, hipStream_t stream)
+{
+    if (ctx->ws.bytes >= bytes) return NLRMM_OK;
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone)
+        return NLRMM_ENOMEM;   // growing the workspace would allocate inside a capture
+    size_t nb = bytes + bytes / 4 + (1u << 20);
+    void *p = nullptr;
+    // the old buffer may still be read by queued work on any stream
+    if (ctx->ws.ptr) {
+        if (hipDeviceSynchronize() != hipSuccess) return NLRMM_EHIP;
+        if (hipFree(ctx->ws.ptr) != hipSuccess) return NLRMM_EHIP;
+        ctx->ws.ptr = nullptr;
+        ctx->ws.bytes = 0;
+    }
+    if (hipMalloc(&p, nb) != hipSuccess) {
+        (void)hipGetLastError();
+        return NLRMM_ENOMEM;
+    }
+    ctx->ws.ptr = p;
+    ctx->ws.bytes = nb;
+    return NLRMM_OK;
+}
+
+int check_geom(const nlrmm_geom *g)
+{
+    if (!g) return NLRMM_EINVAL;
+    if (g->nx < 1 || g->ny < 1 || g->nx > 16384 || g->ny > 16384) return NLRMM_ESHAPE;
+    if (g->nbins < 1 || g->nbins > 65536) return NLRMM_ESHAPE;
+    if (!(g->d > 0.0) || !(g->ds > 0.0) || !isfinite(g->d) || !isfinite(g->ds)) return NLRMM_EINVAL;
+    if (!isfinite(g->x0) || !isfinite(g->y0) || !isfinite(g->s0)) return NLRMM_EINVAL;
+    return NLRMM_OK;
+}
+
+int check_batch(const nlrmm_batch *b)
+{
+    if (!b) return NLRMM_EINVAL;
+    if (b->nframes < 1 || b->nviews < 1 || b->nviews > (int64_t)1 << 31) return NLRMM_ESHAPE;
+    if (b->nframes > 1 && b->view_off == nullptr) return NLRMM_EINVAL;
+    return NLRMM_OK;
+}
+
+}  // namespace nlrmm
+
+using namespace nlrmm;
+
+extern "C" {
+
+const char *nlrmm_strerror(int code)
+{
+    switch (code) {
+        case NLRMM_OK: return "ok";
+        case NLRMM_EINVAL: return "invalid argument";
+        case NLRMM_ESHAPE: return "inconsistent or unsupported sizes";
+        case NLRMM_EHIP: return "HIP runtime error";
+        case NLRMM_ENOMEM: return "device workspace allocation failed or refused during capture";
+        case NLRMM_ENOTSUP: return "unsupported option";
+        default: return "unknown error";
+    }
+}
+
+int nlrmm_version(void) { return 100; }
+
+int nlrmm_ctx_create(nlrmm_ctx **out, int device)
+{
+    if (!out) return NLRMM_EINVAL;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return NLRMM_EINVAL;
+    nlrmm_ctx *c = new (std::nothrow) nlrmm_ctx();
+    if (!c) return NLRMM_ENOMEM;
+    c->device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        cus > 0)
+        c->cu_count = cus;
+    *out = c;
+    return NLRMM_OK;
+}
+
+void nlrmm_ctx_destroy(nlrmm_ctx *ctx)
+{
+    if (!ctx) return;
+    if (ctx->ws.ptr) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ctx->ws.ptr);
+    }
+    delete ctx;
+}
+
+int nlrmm_project(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                  int32_t ncols, const float *x, const double *theta, float *y, void *stream)
+{
+    if (!ctx || !x || !theta || !y) return NLRMM_EINVAL;
+    if (ncols < 1) return NLRMM_ESHAPE;
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if ((rc = check_batch(batch))) return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    return launch_project(ctx, *geom, *batch, ncols, x, theta, y, nullptr, nullptr, nullptr,
+                          nullptr, (hipStream_t)stream);
+}
+
+int nlrmm_backproject(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                      int32_t ncols, const float *y, const double *theta, float *x, void *stream)
+{
+    if (!ctx || !x || !theta || !y) return NLRMM_EINVAL;
+    if (ncols < 1) return NLRMM_ESHAPE;
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if ((rc = check_batch(batch))) return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    return launch_backproject(ctx, *geom, *batch, ncols, y, theta, x, (hipStream_t)stream);
+}
+
+int nlrmm_project_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                         int32_t ncols, const float *x, const double *theta, float *dy,
+                         float *yproj, const float *g, double *gdot, double *dnorm2,
+                         void *stream)
+{
+    if (!ctx || !x || !theta) return NLRMM_EINVAL;
+    if (!dy && !gdot && !dnorm2) return NLRMM_EINVAL;
+    if (gdot && !g) return NLRMM_EINVAL;
+    if (ncols < 1) return NLRMM_ESHAPE;
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if ((rc = check_batch(batch))) return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    return launch_project(ctx, *geom, *batch, ncols, x, theta, yproj, dy, g, gdot, dnorm2,
+                          (hipStream_t)stream);
+}
+
+}  // extern "C"

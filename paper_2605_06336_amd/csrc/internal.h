@@ -1,0 +1,52 @@
+// Internal declarations shared by the library's translation units (not installed).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include "../../include/nlrmm.h"
+
+namespace nlrmm {
+
+// Per-line packed entry of the edge-driven projector: prefix sum of the line up to
+// walk position i (exclusive) and the two pixel values at positions i, i+1.
+struct __attribute__((aligned(16))) PackEntry {
+    double P;
+    float a;
+    float b;
+};
+
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace nlrmm
+
+struct nlrmm_ctx {
+    int device = 0;
+    nlrmm::Workspace ws;
+    int cu_count = 256;
+};
+
+namespace nlrmm {
+
+// Grow the context workspace to at least `bytes` (refused while `stream` is capturing).
+int ensure_workspace(nlrmm_ctx *ctx, size_t bytes, hipStream_t stream);
+
+int check_geom(const nlrmm_geom *g);
+int check_batch(const nlrmm_batch *b);
+
+// projector launchers (proj.hip); all arguments validated by the caller
+int launch_project(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
+                   const float *x, const double *theta, float *y, float *dy, const float *gres,
+                   double *gdot, double *dnorm2, hipStream_t s);
+int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
+                       const float *y, const double *theta, float *x, hipStream_t s);
+
+}  // namespace nlrmm
+
+#define NLRMM_HIP_CHECK(expr)                       \
+    do {                                            \
+        hipError_t _e = (expr);                     \
+        if (_e != hipSuccess) return NLRMM_EHIP;    \
+    } while (0)

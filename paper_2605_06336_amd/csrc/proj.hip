@@ -1,0 +1,696 @@
+// Strip-area parallel-beam projector family for gfx950: forward projection, exact
+// adjoint and per-view angle derivative of the forward operator H(p) (Section 1, eq.
+// "nonlinear_forward"; the CT operator of Section 6.2 with per-view angles).
+//
+// Model: a[v][j][pix] = (Phi(e_{j+1} - c) - Phi(e_j - c)) / ds, where c is the pixel
+// centre's detector coordinate, e_j = s0 + j ds the bin edges and Phi(t) the area of the
+// pixel square on the side {p.n < c + t} (a piecewise quadratic: ramps of width rho at
+// both ends of a plateau of height h).  The angle derivative follows from the moving
+// strip boundaries: d a / d theta = (M(e_j) - M(e_{j+1})) / ds with M(e) the first
+// moment along t = (-sin, cos) of the chord {p in pixel : p.n = e}.
+//
+// Forward (edge-driven): one lane per detector EDGE e.  The lane accumulates
+//   C(e) = area-weighted image mass on the side p.n < e     (projection)
+//   Mo(e) = sum over pixels of x * M(e)                      (derivative)
+// over the image lines (rows for views closer to the y axis, columns otherwise); on
+// each line at most two pixels straddle the edge, the pixels fully on the left enter
+// through a per-line FP64 prefix sum.  Bins follow as y_j = (C(e_{j+1}) - C(e_j)) / ds
+// and D_j = (Mo(e_j) - Mo(e_{j+1})) / ds.  Every Phi evaluation is shared by the two
+// bins that meet at the edge, so each application evaluates Phi ~2 per edge-line
+// instead of ~2 per (ray, pixel) nonzero.  No atomics; results are deterministic.
+//
+// Backward (pixel-driven gather): one lane per pixel of a 16x16 tile; for chunks of
+// views the tile's detector window is staged in LDS, each pixel evaluates Phi at the
+// <= E edges inside its footprint (bit-identical offsets and Phi to the forward) and
+// gathers its <= E+1 bins.
+#include "internal.h"
+
+#include <math.h>
+
+namespace nlrmm {
+namespace {
+
+constexpr int BLK = 256;          // threads per block: four wave64
+constexpr int BINS = BLK - 1;     // bins produced per forward block (BLK edges)
+constexpr int TILE = 16;          // backward tile side
+constexpr int VCHUNK = 32;        // views staged per backward chunk
+constexpr int WMAX = 64;          // max staged bins per view (backward)
+constexpr int MAX_LINE = 4096;    // max pixels per image line handled by the packer
+
+struct ViewC {
+    double cs, sn, wo;
+    float fwo, fwi, frho, f2wi, fh, fhk;   // Phi constants
+    float inv_ab, Kr, tq, kp, kappa;        // chord-moment constants
+    int steep;                              // |cos| >= |sin|: lines are image rows
+};
+
+__device__ __forceinline__ ViewC make_view(double th, double d)
+{
+    ViewC q;
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    const double a = fabs(cs), b = fabs(sn);
+    const double p = d * a, r = d * b;
+    const double wo = 0.5 * (p + r), wi = 0.5 * fabs(p - r), rho = fmin(p, r);
+    const double h = d / fmax(a, b);
+    q.cs = cs;
+    q.sn = sn;
+    q.wo = wo;
+    q.fwo = (float)wo;
+    q.fwi = (float)wi;
+    q.frho = (float)rho;
+    q.f2wi = (float)(2.0 * wi);
+    q.fh = (float)h;
+    q.fhk = rho > 0.0 ? (float)(0.5 * h / rho) : 0.0f;
+    const double ab = fmax(a * b, 1e-30);
+    q.inv_ab = (float)(1.0 / ab);
+    q.Kr = (float)((b * b - a * a) / (2.0 * ab));
+    q.tq = (float)(0.5 * d * (a - b));
+    const double kappa = (cs * sn >= 0.0) ? 1.0 : -1.0;
+    q.kappa = (float)kappa;
+    q.kp = (float)(a >= b ? -kappa * b / a : kappa * a / b);
+    q.steep = a >= b;
+    return q;
+}
+
+// Cumulative footprint Phi(v) (area of the pixel on the side p.n < c + v), FP32,
+// branch-free: left ramp t1^2 h/(2 rho), plateau h t2, right ramp h (t3 - t3^2/(2 rho)).
+// Explicit rounding intrinsics pin the operation order so the forward and backward
+// kernels produce bit-identical values.
+__device__ __forceinline__ float phi_f(float v, const ViewC &q)
+{
+    const float t1 = fminf(fmaxf(__fadd_rn(v, q.fwo), 0.0f), q.frho);
+    const float t2 = fminf(fmaxf(__fadd_rn(v, q.fwi), 0.0f), q.f2wi);
+    const float t3 = fminf(fmaxf(__fsub_rn(v, q.fwi), 0.0f), q.frho);
+    const float r = __fmul_rn(__fsub_rn(t1, t3), __fadd_rn(t1, t3));
+    return fmaf(r, q.fhk, __fmul_rn(q.fh, __fadd_rn(t2, t3)));
+}
+
+// Chord through the pixel at offset v from its centre: length L and the local midpoint
+// mu of its t-coordinate.  Plateau: mu = v * kp; ramps: the chord cuts a corner whose
+// t-coordinate is sign(v) kappa (d/2)(a - b), and the midpoint moves by Kr per unit of
+// distance from that corner.
+__device__ __forceinline__ void moment_f(float v, const ViewC &q, float &L, float &mu)
+{
+    const float av = fabsf(v);
+    const float dl = fmaxf(q.fwo - av, 0.0f);
+    L = fminf(dl * q.inv_ab, q.fh);
+    const float dr = fminf(dl, q.frho);
+    const float sg = v >= 0.0f ? 1.0f : -1.0f;
+    const float mur = sg * q.kappa * fmaf(dr, q.Kr, q.tq);
+    const float mup = v * q.kp;
+    mu = (av <= q.fwi) ? mup : mur;
+}
+
+__device__ __forceinline__ int frame_of(const int64_t *vo, int F, int64_t v)
+{
+    if (F <= 1 || vo == nullptr) return 0;
+    int lo = 0, hi = F - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (vo[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// e - lc*sl - mc*sm with a fixed rounding sequence (shared by forward and backward).
+__device__ __forceinline__ double edge_coord(double s0, double ds, int64_t j)
+{
+    return __dadd_rn(s0, __dmul_rn((double)j, ds));
+}
+__device__ __forceinline__ double pix_coord(double o, double d, int k)
+{
+    return __dadd_rn(o, __dmul_rn((double)k + 0.5, d));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// preparation: transpose and per-line packs
+// ---------------------------------------------------------------------------
+__global__ void transpose_k(const float *__restrict__ x, float *__restrict__ xT, int nx, int ny)
+{
+    __shared__ float tile[32][33];
+    const int64_t img = blockIdx.z;
+    const float *src = x + img * (int64_t)nx * ny;
+    float *dst = xT + img * (int64_t)nx * ny;
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    for (int r = threadIdx.y; r < 32; r += 8) {
+        const int yy = by + r, xx = bx + threadIdx.x;
+        tile[r][threadIdx.x] = (yy < ny && xx < nx) ? src[(int64_t)yy * nx + xx] : 0.0f;
+    }
+    __syncthreads();
+    for (int r = threadIdx.y; r < 32; r += 8) {
+        const int xx = bx + r, yy = by + threadIdx.x;
+        if (xx < nx && yy < ny) dst[(int64_t)xx * ny + yy] = tile[threadIdx.x][r];
+    }
+}
+
+// One block per (image, line): entries i = -2..n of the line, stored at i + 2:
+// P = sum of pixels 0..i-1 (FP64), a = x_i, b = x_{i+1} (zero outside the line).
+__global__ __launch_bounds__(BLK) void pack_lines_k(const float *__restrict__ src, int n, int nlines,
+                                                    PackEntry *__restrict__ pack,
+                                                    double *__restrict__ tot)
+{
+    __shared__ float sx[MAX_LINE + 2];
+    __shared__ double sP[MAX_LINE + 1];
+    __shared__ double swave[BLK / 64];
+    const int64_t line = blockIdx.x;
+    const int64_t img = blockIdx.y;
+    const float *row = src + (img * nlines + line) * (int64_t)n;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < n; i += BLK) sx[i] = row[i];
+    if (tid < 2) sx[n + tid] = 0.0f;
+    __syncthreads();
+    const int cpt = (n + BLK - 1) / BLK;
+    const int i0 = min(tid * cpt, n), i1 = min(i0 + cpt, n);
+    double ls = 0.0;
+    for (int i = i0; i < i1; ++i) ls += (double)sx[i];
+    // block exclusive scan of ls
+    const int lane = tid & 63, wv = tid >> 6;
+    double incl = ls;
+    for (int off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    if (lane == 63) swave[wv] = incl;
+    __syncthreads();
+    double base = 0.0;
+    for (int w = 0; w < wv; ++w) base += swave[w];
+    double run = base + incl - ls;
+    for (int i = i0; i < i1; ++i) {
+        sP[i] = run;
+        run += (double)sx[i];
+    }
+    if (tid == BLK - 1) sP[n] = run;   // the last thread's chunk ends the line
+    __syncthreads();
+    PackEntry *out = pack + (img * nlines + line) * (int64_t)(n + 3);
+    for (int e = tid; e < n + 3; e += BLK) {
+        const int i = e - 2;
+        PackEntry pe;
+        pe.P = (i > 0) ? sP[i] : 0.0;
+        pe.a = (i >= 0 && i < n) ? sx[i] : 0.0f;
+        pe.b = (i + 1 >= 0 && i + 1 < n) ? sx[i + 1] : 0.0f;
+        out[e] = pe;
+    }
+    if (tid == 0) tot[img * nlines + line] = sP[n];
+}
+
+// Exclusive prefix of the line totals: pre[img][0..nlines].
+__global__ __launch_bounds__(BLK) void line_prefix_k(const double *__restrict__ tot, int nlines,
+                                                     double *__restrict__ pre)
+{
+    __shared__ double swave[BLK / 64];
+    const int64_t img = blockIdx.x;
+    const double *t = tot + img * nlines;
+    double *p = pre + img * (int64_t)(nlines + 1);
+    const int tid = threadIdx.x;
+    const int cpt = (nlines + BLK - 1) / BLK;
+    const int i0 = min(tid * cpt, nlines), i1 = min(i0 + cpt, nlines);
+    double ls = 0.0;
+    for (int i = i0; i < i1; ++i) ls += t[i];
+    const int lane = tid & 63, wv = tid >> 6;
+    double incl = ls;
+    for (int off = 1; off < 64; off <<= 1) {
+        const double u = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += u;
+    }
+    if (lane == 63) swave[wv] = incl;
+    __syncthreads();
+    double run = incl - ls;
+    for (int w = 0; w < wv; ++w) run += swave[w];
+    for (int i = i0; i < i1; ++i) {
+        p[i] = run;
+        run += t[i];
+    }
+    if (tid == BLK - 1) p[nlines] = run;
+}
+
+// ---------------------------------------------------------------------------
+// forward: projection and angle derivative, edge-driven
+// ---------------------------------------------------------------------------
+struct FwdArgs {
+    const PackEntry *rowpack;   // [img][ny][nx+3]
+    const PackEntry *colpack;   // [img][nx][ny+3]
+    const double *rowpre;       // [img][ny+1]
+    const double *colpre;       // [img][nx+1]
+    const double *theta;
+    const int64_t *view_off;
+    int nframes;
+    int64_t V;
+    int nx, ny, nb;
+    double x0, y0, d, s0, ds;
+    int ncols;        // columns in this launch (images = ncols * nframes, column-major)
+    int col_out0;     // global column index of the first column (outputs)
+    int nchunks;      // blocks per view
+    float *y;         // [col][V][nb] or null
+    float *dy;        // [col][V][nb] or null
+    const float *g;   // [V][nb] or null
+    double *part;     // [2][col][V][nchunks] (gdot, dnorm2 partials) or null
+    int64_t part_cols;  // total columns of the partials array
+};
+
+template <int MODE, int NC>
+__global__ __launch_bounds__(BLK) void fwd_edges_k(FwdArgs a)
+{
+    constexpr bool PROJ = (MODE & 1) != 0;
+    constexpr bool MOM = (MODE & 2) != 0;
+    __shared__ double sC[PROJ ? NC : 1][BLK];
+    __shared__ double sM[MOM ? NC : 1][BLK];
+    __shared__ double sred[2][BLK / 64];
+
+    const int tid = threadIdx.x;
+    const int64_t v = blockIdx.x / a.nchunks;
+    const int q = (int)(blockIdx.x - v * a.nchunks);
+    const int c0 = blockIdx.y * NC;
+    const int nc = min(NC, a.ncols - c0);
+    const int f = frame_of(a.view_off, a.nframes, v);
+    const ViewC w = make_view(a.theta[v], a.d);
+    const int64_t j = (int64_t)q * BINS + tid;
+
+    const bool steep = w.steep != 0;
+    const int nlines = steep ? a.ny : a.nx;
+    const int nminor = steep ? a.nx : a.ny;
+    const double line0 = steep ? a.y0 : a.x0;
+    const double minor0 = steep ? a.x0 : a.y0;
+    const double sl = steep ? w.sn : w.cs;
+    const double sm = steep ? w.cs : w.sn;
+    const double tl = steep ? w.cs : -w.sn;
+    const double tm = steep ? -w.sn : w.cs;
+    const bool asc = sm > 0.0;
+    const double step = a.d * fabs(sm);
+    const double inv_step = 1.0 / step;
+    const double cw0 = asc ? (minor0 + 0.5 * a.d) * sm : (minor0 + (nminor - 0.5) * a.d) * sm;
+    const PackEntry *pack = steep ? a.rowpack : a.colpack;
+    const double *pre = steep ? a.rowpre : a.colpre;
+    const int64_t pstride = (int64_t)nlines * (nminor + 3);
+    const int64_t tstride = nlines + 1;
+    const int64_t img0 = (int64_t)c0 * a.nframes + f;
+    const int64_t cstride = a.nframes;   // images between consecutive columns
+
+    double accP[NC], accF[NC], accM[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) accP[c] = accF[c] = accM[c] = 0.0;
+
+    if (j <= a.nb) {
+        const double e = edge_coord(a.s0, a.ds, j);
+        int la, lb;
+        if (sl == 0.0) {
+            la = 0;
+            lb = nlines - 1;
+        } else {
+            const double A = e - w.wo - cw0 - (nminor - 1) * step;
+            const double B = e + w.wo - cw0;
+            const double l1 = (A / sl - line0) / a.d - 0.5;
+            const double l2 = (B / sl - line0) / a.d - 0.5;
+            double lo = fmin(l1, l2), hi = fmax(l1, l2);
+            lo = fmin(fmax(lo, -4.0), nlines + 4.0);
+            hi = fmin(fmax(hi, -4.0), nlines + 4.0);
+            la = min(max((int)floor(lo) - 1, 0), nlines);
+            lb = min(max((int)ceil(hi) + 1, -1), nlines - 1);
+        }
+        const PackEntry *pimg = pack + img0 * pstride;
+        for (int L = la; L <= lb; ++L) {
+            const double lc = pix_coord(line0, a.d, L);
+            const double base = __dsub_rn(e, __dmul_rn(lc, sl));
+            double tf = floor((base - w.wo - cw0) * inv_step);
+            tf = fmin(fmax(tf, -2.0), (double)nminor);
+            int K0 = (int)tf + 1;
+            K0 = min(max(K0, -1), nminor);
+            const int idx = asc ? K0 : nminor - 2 - K0;
+            const int ka = asc ? K0 : idx + 1;
+            const int kb = asc ? K0 + 1 : idx;
+            const double mca = pix_coord(minor0, a.d, ka);
+            const double mcb = pix_coord(minor0, a.d, kb);
+            const float va = __double2float_rn(__dsub_rn(base, __dmul_rn(mca, sm)));
+            const float vb = __double2float_rn(__dsub_rn(base, __dmul_rn(mcb, sm)));
+            float pa = 0.f, pb = 0.f, ma = 0.f, mb = 0.f;
+            if (PROJ) {
+                pa = phi_f(va, w);
+                pb = phi_f(vb, w);
+            }
+            if (MOM) {
+                float La, Lb, mua, mub;
+                moment_f(va, w, La, mua);
+                moment_f(vb, w, Lb, mub);
+                const double tb = lc * tl;
+                ma = La * ((float)(tb + mca * tm) + mua);
+                mb = Lb * ((float)(tb + mcb * tm) + mub);
+            }
+            const PackEntry *pe = pimg + (int64_t)L * (nminor + 3) + (idx + 2);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (c < nc) {
+                    const PackEntry E = pe[c * cstride * pstride];
+                    const float xa = asc ? E.a : E.b;
+                    const float xb = asc ? E.b : E.a;
+                    if (PROJ) {
+                        accP[c] += asc ? E.P : -(E.P + (double)E.a + (double)E.b);
+                        accF[c] += (double)fmaf(xb, pb, xa * pa);
+                    }
+                    if (MOM) accM[c] += (double)fmaf(xb, mb, xa * ma);
+                }
+            }
+        }
+        if (PROJ) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (c < nc) {
+                    const double *lt = pre + (img0 + c * cstride) * tstride;
+                    double add = 0.0;
+                    if (!asc && la <= lb) add += lt[lb + 1] - lt[la];
+                    if (sl > 0.0) add += lt[la];
+                    else if (sl < 0.0) add += lt[nlines] - lt[lb + 1];
+                    accP[c] += add;
+                }
+            }
+        }
+    }
+    const double d2 = a.d * a.d;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (PROJ) sC[c][tid] = d2 * accP[c] + accF[c];
+        if (MOM) sM[c][tid] = accM[c];
+    }
+    __syncthreads();
+
+    const int64_t jb = (int64_t)q * BINS + tid;
+    const bool has_bin = tid < BINS && jb < a.nb;
+    const double inv_ds = 1.0 / a.ds;
+    const float gv = (a.g != nullptr && has_bin) ? a.g[v * a.nb + jb] : 0.0f;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (c >= nc) break;
+        const int64_t col = a.col_out0 + c0 + c;
+        const int64_t o = (col * a.V + v) * a.nb + jb;
+        double Dv = 0.0;
+        if (has_bin) {
+            if (PROJ && a.y) a.y[o] = (float)((sC[c][tid + 1] - sC[c][tid]) * inv_ds);
+            if (MOM) {
+                Dv = (sM[c][tid] - sM[c][tid + 1]) * inv_ds;
+                if (a.dy) a.dy[o] = (float)Dv;
+            }
+        }
+        if (MOM && a.part != nullptr) {
+            double sg = wave_sum(Dv * (double)gv);
+            double sh = wave_sum(Dv * Dv);
+            if ((tid & 63) == 0) {
+                sred[0][tid >> 6] = sg;
+                sred[1][tid >> 6] = sh;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double tg = 0.0, th = 0.0;
+                for (int wv = 0; wv < BLK / 64; ++wv) {
+                    tg += sred[0][wv];
+                    th += sred[1][wv];
+                }
+                const int64_t po = (col * a.V + v) * a.nchunks + q;
+                a.part[po] = tg;
+                a.part[a.part_cols * a.V * a.nchunks + po] = th;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void finalize_parts_k(const double *__restrict__ part, int64_t ncols, int64_t V,
+                                 int nchunks, double *gdot, double *dnorm2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncols * V) return;
+    double sg = 0.0, sh = 0.0;
+    for (int q = 0; q < nchunks; ++q) {
+        sg += part[i * nchunks + q];
+        sh += part[ncols * V * nchunks + i * nchunks + q];
+    }
+    if (gdot) gdot[i] = sg;
+    if (dnorm2) dnorm2[i] = sh;
+}
+
+// ---------------------------------------------------------------------------
+// backward: pixel-driven gather
+// ---------------------------------------------------------------------------
+struct BwdArgs {
+    const float *y;
+    const double *theta;
+    const int64_t *view_off;
+    int nframes;
+    int64_t V;
+    int nx, ny, nb;
+    double x0, y0, d, s0, ds;
+    int tiles_x;
+    int W;           // staged bins per view (<= WMAX)
+    float *x;
+};
+
+template <int E>
+__global__ __launch_bounds__(BLK) void bwd_tiles_k(BwdArgs a)
+{
+    __shared__ ViewC sv[VCHUNK];
+    __shared__ int sj0[VCHUNK];
+    __shared__ float sy[VCHUNK][WMAX];
+    const int tid = threadIdx.x;
+    const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
+    const int64_t img = blockIdx.y;
+    const int64_t col = img / a.nframes;
+    const int f = (int)(img - col * a.nframes);
+    const int k = tx * TILE + (tid % TILE);
+    const int l = ty * TILE + (tid / TILE);
+    const bool active = k < a.nx && l < a.ny;
+    const int64_t v0 = (a.view_off && a.nframes > 1) ? a.view_off[f] : 0;
+    const int64_t v1 = (a.view_off && a.nframes > 1) ? a.view_off[f + 1] : a.V;
+    const float *ycol = a.y + col * a.V * a.nb;
+    const double xc = a.x0 + (tx * TILE + 0.5 * TILE) * a.d;
+    const double yc = a.y0 + (ty * TILE + 0.5 * TILE) * a.d;
+    const double xk = pix_coord(a.x0, a.d, k);
+    const double yl = pix_coord(a.y0, a.d, l);
+    const double d2 = a.d * a.d;
+    double acc = 0.0;
+
+    for (int64_t vb = v0; vb < v1; vb += VCHUNK) {
+        const int nv = (int)min((int64_t)VCHUNK, v1 - vb);
+        if (tid < nv) {
+            const ViewC w = make_view(a.theta[vb + tid], a.d);
+            sv[tid] = w;
+            const double cC = xc * w.cs + yc * w.sn;
+            const double R = (TILE - 1) * 0.5 * a.d * (fabs(w.cs) + fabs(w.sn)) + w.wo;
+            sj0[tid] = (int)floor((cC - R - a.s0) / a.ds) - 1;
+        }
+        __syncthreads();
+        for (int i = tid; i < nv * a.W; i += BLK) {
+            const int vi = i / a.W, jj = i - vi * a.W;
+            const int jbin = sj0[vi] + jj;
+            sy[vi][jj] = (jbin >= 0 && jbin < a.nb) ? ycol[(vb + vi) * a.nb + jbin] : 0.0f;
+        }
+        __syncthreads();
+        if (active) {
+            for (int vi = 0; vi < nv; ++vi) {
+                const ViewC &w = sv[vi];
+                const bool steep = w.steep != 0;
+                const double lc = steep ? yl : xk;
+                const double mc = steep ? xk : yl;
+                const double sl = steep ? w.sn : w.cs;
+                const double sm = steep ? w.cs : w.sn;
+                const double lcs = __dmul_rn(lc, sl);
+                const double mcs = __dmul_rn(mc, sm);
+                const double cc = lcs + mcs;
+                const int64_t jf = (int64_t)floor((cc - w.wo - a.s0) / a.ds);
+                float ph[E + 2];
+                ph[0] = 0.0f;
+#pragma unroll
+                for (int i = 1; i <= E; ++i) {
+                    const double e = edge_coord(a.s0, a.ds, jf + i);
+                    const double base = __dsub_rn(e, lcs);
+                    ph[i] = phi_f(__double2float_rn(__dsub_rn(base, mcs)), w);
+                }
+                int jj = (int)(jf - sj0[vi]);
+                jj = min(max(jj, 0), a.W - (E + 1));
+                const float *yy = &sy[vi][jj];
+                double prev = 0.0;
+#pragma unroll
+                for (int i = 0; i <= E; ++i) {
+                    const double nxt = (i < E) ? (double)ph[i + 1] : d2;
+                    acc += (nxt - prev) * (double)yy[i];
+                    prev = nxt;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (active) {
+        const int64_t o = ((col * a.nframes + f) * (int64_t)a.ny + l) * a.nx + k;
+        a.x[o] = (float)(acc / a.ds);
+    }
+}
+
+int edges_inside(const nlrmm_geom &g)
+{
+    // maximum number of bin edges strictly inside a pixel footprint (width <= d sqrt 2)
+    return (int)ceil(g.d * 1.4142135623730951 / g.ds - 1e-12);
+}
+
+}  // namespace
+
+// Workspace for the forward pass of `gcols` columns.
+static size_t fwd_ws_bytes(const nlrmm_geom &g, int nframes, int gcols, int64_t V, int nchunks,
+                           int ncols_total)
+{
+    const int64_t nimg = (int64_t)gcols * nframes;
+    const int64_t nx = g.nx, ny = g.ny;
+    size_t b = 0;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    b += al(sizeof(float) * nimg * nx * ny);                 // transposed images
+    b += al(sizeof(PackEntry) * nimg * ny * (nx + 3));       // row packs
+    b += al(sizeof(PackEntry) * nimg * nx * (ny + 3));       // column packs
+    b += al(sizeof(double) * nimg * (ny + nx));              // line totals
+    b += al(sizeof(double) * nimg * (ny + 1));               // row-total prefixes
+    b += al(sizeof(double) * nimg * (nx + 1));               // column-total prefixes
+    b += al(sizeof(double) * 2 * (size_t)ncols_total * V * nchunks);   // reduction partials
+    return b;
+}
+
+template <int MODE>
+static void launch_fwd_mode(int NC, dim3 grid, const FwdArgs &a, hipStream_t s)
+{
+    switch (NC) {
+        case 1: fwd_edges_k<MODE, 1><<<grid, BLK, 0, s>>>(a); break;
+        case 2: fwd_edges_k<MODE, 2><<<grid, BLK, 0, s>>>(a); break;
+        case 4: fwd_edges_k<MODE, 4><<<grid, BLK, 0, s>>>(a); break;
+        default: fwd_edges_k<MODE, 8><<<grid, BLK, 0, s>>>(a); break;
+    }
+}
+
+int launch_project(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
+                   const float *x, const double *theta, float *y, float *dy, const float *gres,
+                   double *gdot, double *dnorm2, hipStream_t s)
+{
+    if (g.nx > MAX_LINE || g.ny > MAX_LINE) return NLRMM_ESHAPE;
+    const int F = b.nframes;
+    const int64_t V = b.nviews;
+    const int nchunks = (g.nbins + BINS - 1) / BINS;
+    const bool mom = dy || gdot || dnorm2;
+    const bool proj = y != nullptr;
+    const bool red = gdot || dnorm2;
+    const int GC = 8;                       // columns prepared per group
+    const int gcols = ncols < GC ? ncols : GC;
+    const size_t need = fwd_ws_bytes(g, F, gcols, V, nchunks, red ? ncols : 0);
+    int rc = ensure_workspace(ctx, need, s);
+    if (rc) return rc;
+    const int64_t nx = g.nx, ny = g.ny;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    char *p = (char *)ctx->ws.ptr;
+    float *xT = (float *)p;
+    p += al(sizeof(float) * (int64_t)gcols * F * nx * ny);
+    PackEntry *rowpack = (PackEntry *)p;
+    p += al(sizeof(PackEntry) * (int64_t)gcols * F * ny * (nx + 3));
+    PackEntry *colpack = (PackEntry *)p;
+    p += al(sizeof(PackEntry) * (int64_t)gcols * F * nx * (ny + 3));
+    double *tot = (double *)p;
+    p += al(sizeof(double) * (int64_t)gcols * F * (ny + nx));
+    double *rowpre = (double *)p;
+    p += al(sizeof(double) * (int64_t)gcols * F * (ny + 1));
+    double *colpre = (double *)p;
+    p += al(sizeof(double) * (int64_t)gcols * F * (nx + 1));
+    double *part = red ? (double *)p : nullptr;
+
+    const int64_t npix = nx * ny;
+    for (int cbeg = 0; cbeg < ncols; cbeg += gcols) {
+        const int nc = ncols - cbeg < gcols ? ncols - cbeg : gcols;
+        const int64_t nimg = (int64_t)nc * F;
+        const float *xg = x + (int64_t)cbeg * F * npix;
+        // row packs straight from x; column packs from the transposed images
+        pack_lines_k<<<dim3((unsigned)ny, (unsigned)nimg), BLK, 0, s>>>(xg, (int)nx, (int)ny,
+                                                                       rowpack, tot);
+        transpose_k<<<dim3((unsigned)((nx + 31) / 32), (unsigned)((ny + 31) / 32), (unsigned)nimg),
+                      dim3(32, 8), 0, s>>>(xg, xT, (int)nx, (int)ny);
+        double *ctot = tot + nimg * ny;
+        pack_lines_k<<<dim3((unsigned)nx, (unsigned)nimg), BLK, 0, s>>>(xT, (int)ny, (int)nx,
+                                                                       colpack, ctot);
+        line_prefix_k<<<(unsigned)nimg, BLK, 0, s>>>(tot, (int)ny, rowpre);
+        line_prefix_k<<<(unsigned)nimg, BLK, 0, s>>>(ctot, (int)nx, colpre);
+
+        FwdArgs a;
+        a.rowpack = rowpack;
+        a.colpack = colpack;
+        a.rowpre = rowpre;
+        a.colpre = colpre;
+        a.theta = theta;
+        a.view_off = b.view_off;
+        a.nframes = F;
+        a.V = V;
+        a.nx = g.nx;
+        a.ny = g.ny;
+        a.nb = g.nbins;
+        a.x0 = g.x0;
+        a.y0 = g.y0;
+        a.d = g.d;
+        a.s0 = g.s0;
+        a.ds = g.ds;
+        a.ncols = nc;
+        a.col_out0 = cbeg;
+        a.nchunks = nchunks;
+        a.y = y;
+        a.dy = dy;
+        a.g = gres;
+        a.part = part;
+        a.part_cols = ncols;
+        const int NC = nc >= 8 ? 8 : nc >= 4 ? 4 : nc >= 2 ? 2 : 1;
+        dim3 grid((unsigned)(V * nchunks), (unsigned)((nc + NC - 1) / NC));
+        if (proj && mom) launch_fwd_mode<3>(NC, grid, a, s);
+        else if (mom) launch_fwd_mode<2>(NC, grid, a, s);
+        else launch_fwd_mode<1>(NC, grid, a, s);
+    }
+    if (red) {
+        const int64_t n = (int64_t)ncols * V;
+        finalize_parts_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(part, ncols, V, nchunks,
+                                                                     gdot, dnorm2);
+    }
+    NLRMM_HIP_CHECK(hipGetLastError());
+    return NLRMM_OK;
+}
+
+int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
+                       const float *y, const double *theta, float *x, hipStream_t s)
+{
+    (void)ctx;
+    const int E = edges_inside(g);
+    if (E < 1 || E > 4) return NLRMM_ESHAPE;
+    const int W = (int)ceil((TILE - 1) * g.d * 1.4142135623730951 / g.ds) + E + 4;
+    if (W > WMAX) return NLRMM_ESHAPE;
+    BwdArgs a;
+    a.y = y;
+    a.theta = theta;
+    a.view_off = b.view_off;
+    a.nframes = b.nframes;
+    a.V = b.nviews;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.nb = g.nbins;
+    a.x0 = g.x0;
+    a.y0 = g.y0;
+    a.d = g.d;
+    a.s0 = g.s0;
+    a.ds = g.ds;
+    a.tiles_x = (g.nx + TILE - 1) / TILE;
+    a.W = W;
+    a.x = x;
+    const int tiles_y = (g.ny + TILE - 1) / TILE;
+    dim3 grid((unsigned)(a.tiles_x * tiles_y), (unsigned)((int64_t)ncols * b.nframes));
+    switch (E) {
+        case 1: bwd_tiles_k<1><<<grid, BLK, 0, s>>>(a); break;
+        case 2: bwd_tiles_k<2><<<grid, BLK, 0, s>>>(a); break;
+        case 3: bwd_tiles_k<3><<<grid, BLK, 0, s>>>(a); break;
+        default: bwd_tiles_k<4><<<grid, BLK, 0, s>>>(a); break;
+    }
+    NLRMM_HIP_CHECK(hipGetLastError());
+    return NLRMM_OK;
+}
+
+}  // namespace nlrmm

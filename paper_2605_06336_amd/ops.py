@@ -1,0 +1,141 @@
+"""Python entry points with the C ABI's names, over torch device tensors.
+
+Each function checks dtypes, devices and shapes, then calls the library on the
+current torch stream.  torch provides device memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import Batch, Geom, check
+
+_ctx = {}
+
+
+def context(device: int = 0) -> int:
+    """Library context for a device (created once per process and device)."""
+    if device not in _ctx:
+        h = ctypes.c_void_p()
+        check(_lib.lib().nlrmm_ctx_create(ctypes.byref(h), device), "nlrmm_ctx_create")
+        _ctx[device] = h.value
+    return _ctx[device]
+
+
+def geom(N: int, nb: int, ny: Optional[int] = None, half: float = 1.0,
+         s_half: float = 1.42) -> Geom:
+    """Square-pixel grid on [-half, half] along x (N pixels) and detector [-s_half, s_half]."""
+    ny = N if ny is None else ny
+    d = 2.0 * half / N
+    return Geom(nx=N, ny=ny, x0=-half, y0=-half * ny / N, d=d, nbins=nb, s0=-s_half,
+                ds=2.0 * s_half / nb)
+
+
+class Frames:
+    """Frame structure of a batch: view offsets on the device plus the host count."""
+
+    def __init__(self, view_off, device="cuda"):
+        vo = torch.as_tensor(view_off, dtype=torch.int64)
+        self.nframes = int(vo.numel() - 1)
+        self.nviews = int(vo[-1])
+        self.view_off = vo.to(device)
+        self.host = vo.cpu().numpy()
+
+    def struct(self) -> Batch:
+        return Batch(nframes=self.nframes, nviews=self.nviews,
+                     view_off=self.view_off.data_ptr() if self.nframes > 1 else None)
+
+
+def single(nviews: int) -> Batch:
+    return Batch(nframes=1, nviews=nviews, view_off=None)
+
+
+def _batch(frames, nviews):
+    if frames is None:
+        return single(nviews)
+    if isinstance(frames, Frames):
+        return frames.struct()
+    return frames
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _need(t, dtype, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous CUDA tensor of {dtype}")
+
+
+def project(x: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None,
+            out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = A(theta) x.  x: [..., F, ny, nx] float32 (leading dims = columns); y: [..., V, nb]."""
+    _need(x, torch.float32, "x")
+    _need(theta, torch.float64, "theta")
+    V = theta.numel()
+    b = _batch(frames, V)
+    npix = b.nframes * g.nx * g.ny
+    if x.numel() % npix:
+        raise ValueError("x size is not a multiple of frames*ny*nx")
+    ncols = x.numel() // npix
+    if out is None:
+        out = torch.empty((ncols, V, g.nbins), dtype=torch.float32, device=x.device)
+    _need(out, torch.float32, "out")
+    check(_lib.lib().nlrmm_project(context(x.device.index or 0), ctypes.byref(g), ctypes.byref(b),
+                                   ncols, x.data_ptr(), theta.data_ptr(), out.data_ptr(),
+                                   _stream(x.device)), "nlrmm_project")
+    return out
+
+
+def backproject(y: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None,
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """x = A(theta)^T y.  y: [..., V, nb] float32; x: [ncols, F, ny, nx]."""
+    _need(y, torch.float32, "y")
+    _need(theta, torch.float64, "theta")
+    V = theta.numel()
+    b = _batch(frames, V)
+    if y.numel() % (V * g.nbins):
+        raise ValueError("y size is not a multiple of V*nb")
+    ncols = y.numel() // (V * g.nbins)
+    if out is None:
+        out = torch.empty((ncols, b.nframes, g.ny, g.nx), dtype=torch.float32, device=y.device)
+    _need(out, torch.float32, "out")
+    check(_lib.lib().nlrmm_backproject(context(y.device.index or 0), ctypes.byref(g),
+                                       ctypes.byref(b), ncols, y.data_ptr(), theta.data_ptr(),
+                                       out.data_ptr(), _stream(y.device)), "nlrmm_backproject")
+    return out
+
+
+def project_dtheta(x: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None, *,
+                   want_dy: bool = True, want_y: bool = False, gres: Optional[torch.Tensor] = None,
+                   want_gdot: bool = False, want_dnorm2: bool = False):
+    """Angle derivative D = d(A(theta)x)/d theta_v (per view row) with optional fused outputs.
+
+    Returns a dict with any of: 'dy' [ncols, V, nb], 'y' [ncols, V, nb], 'gdot' [ncols, V]
+    (= <D_v, gres_v>, float64), 'dnorm2' [ncols, V] (= ||D_v||^2, float64)."""
+    _need(x, torch.float32, "x")
+    _need(theta, torch.float64, "theta")
+    V = theta.numel()
+    b = _batch(frames, V)
+    ncols = x.numel() // (b.nframes * g.nx * g.ny)
+    dev = x.device
+    res = {}
+    dy = torch.empty((ncols, V, g.nbins), dtype=torch.float32, device=dev) if want_dy else None
+    yp = torch.empty((ncols, V, g.nbins), dtype=torch.float32, device=dev) if want_y else None
+    gd = torch.empty((ncols, V), dtype=torch.float64, device=dev) if want_gdot else None
+    dn = torch.empty((ncols, V), dtype=torch.float64, device=dev) if want_dnorm2 else None
+    if want_gdot:
+        _need(gres, torch.float32, "gres")
+    ptr = lambda t: t.data_ptr() if t is not None else None
+    check(_lib.lib().nlrmm_project_dtheta(context(dev.index or 0), ctypes.byref(g),
+                                          ctypes.byref(b), ncols, x.data_ptr(), theta.data_ptr(),
+                                          ptr(dy), ptr(yp), ptr(gres), ptr(gd), ptr(dn),
+                                          _stream(dev)), "nlrmm_project_dtheta")
+    for k, t in (("dy", dy), ("y", yp), ("gdot", gd), ("dnorm2", dn)):
+        if t is not None:
+            res[k] = t
+    return res
