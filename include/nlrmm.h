@@ -114,6 +114,113 @@ int nlrmm_project_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_bat
                          float *yproj, const float *g, double *gdot, double *dnorm2,
                          void *stream);
 
+/* ------------------------------------------------------------------------------------
+ * Krylov side of MM-GKS / RMM-GKS (Section 3; supplementary Algs. "enlarge", "compress").
+ * Basis blocks are column-contiguous FP32: V [ncols][n] with n = nframes*ny*nx, and
+ * A V [ncols][m] with m = nviews*nbins.  Grams are FP64 row-major with leading dim ldg.
+ * Psi is the anisotropic TV operator of Section 2.2: per frame the forward differences
+ * along x (ny rows of nx-1) then along y (ny-1 rows of nx), unscaled; with temporal != 0
+ * and nframes > 1 the frame differences ((nframes-1) blocks of ny*nx) follow.
+ * ------------------------------------------------------------------------------------ */
+
+/* MM weights w = ((Psi u)^2 + eps^2)^(-1/2) (Section 3.1, the squared diagonal of P_eps).
+ *   u [nframes][ny][nx] float32 -> w [npsi] float32 (npsi as described above). */
+int nlrmm_tv_weights(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, int32_t temporal,
+                     const float *u, double eps, float *w, void *stream);
+
+/* Weighted regulariser Gram G = (P Psi V)^T (P Psi V) = (Psi V)^T diag(w) (Psi V) for the
+ * first ell (<= 64) columns of V: the R_Psi^T R_Psi of the projected problem (Section 3.2).
+ * Psi V is computed on the fly; FP64 accumulation.  G [ell][ldg] float64 overwritten. */
+int nlrmm_gram_psi(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, int32_t temporal,
+                   int32_t ell, const float *V, const float *w, double *G, int32_t ldg,
+                   void *stream);
+
+/* Projected MM-GKS solve (eq. "reduced_problem") from its Grams:
+ *   GA = (AV)^T AV, GP = (P Psi V)^T P Psi V, rb = (AV)^T b   (FP64, ell <= 56),
+ *   scal = DEVICE {||b||^2, target}.
+ * lambda: lam_fix >= 0 uses it; otherwise the discrepancy principle ||A V z - b|| = target
+ * on the reduced problem (Section 3.2), searched on the log-bracket
+ * [1e-10, 1e10] * tr(GA)/tr(GP) and clamped to its ends (NLRMM_ST_DP_LOW / _HIGH).
+ * Outputs (DEVICE): z [ell]; out[0] = lambda, out[1] = ||A V z - b||^2 of the model. */
+int nlrmm_gks_solve(nlrmm_ctx *ctx, int32_t ell, const double *GA, const double *GP,
+                    int32_t ldg, const double *rb, const double *scal, double lam_fix, double *z,
+                    double *out, int32_t *status, void *stream);
+
+/* One generalized-Krylov expansion (Alg. "enlarge", after u = V z):
+ *   r = A^T (A V z - b) + lambda Psi^T (w * Psi u),  u = V z,
+ *   r <- r - V V^T r twice (CGS2, FP64 dot products), v = r / ||r||,
+ * appended as column ell of V; column ell of A V is set to A(theta) v; the Gram GA gains
+ * row/column ell and rb gains entry ell.  Breakdown (||r_perp|| <= breakdown_tol ||r||)
+ * sets NLRMM_ST_BREAKDOWN (the column is still written).  Capacity: V and AV must hold
+ * ell+1 columns, GA (ell+1) x ldg.  lambda is a DEVICE scalar, z DEVICE [ell]. */
+int nlrmm_gks_expand(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                     const double *theta, int32_t ell, int32_t temporal, float *V, float *AV,
+                     const double *z, const float *b, const float *w, const double *lambda,
+                     double *GA, int32_t ldg, double *rb, double breakdown_tol,
+                     int32_t *status, void *stream);
+
+/* Recycling compression (Alg. "compress", Section 3.3): W = right singular vectors of the
+ * kmin-1 largest singular values of H = [R_A; sqrt(lambda) R_Psi] (eigenvectors of
+ * GA + lambda GP, sign: largest-magnitude entry positive), c = z - W W^T z and
+ *   V <- V [W, c/||c||],  A V <- A V [W, c/||c||],  z <- [W^T z; ||c||]
+ * (u = V z is unchanged).  GA and rb are transformed accordingly.  When ||c|| <= 1e-12 ||z||
+ * the last column is zero and NLRMM_ST_COMPRESS_SKIP is set.  n, m: column lengths of V
+ * and A V.  lambda DEVICE scalar; z DEVICE [ell] in, [kmin] out. */
+int nlrmm_recycle_compress(nlrmm_ctx *ctx, int64_t n, int64_t m, int32_t ell, int32_t kmin,
+                           float *V, float *AV, double *GA, const double *GP, int32_t ldg,
+                           double *rb, const double *lambda, double *z, int32_t *status,
+                           void *stream);
+
+/* ------------------------------------------------------------------------------------
+ * Outer driver: NL-RMM-GKS (Alg. "nl_rmmgks_two_solves", high-regularisation solve off).
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+    int32_t kmin, kmax;      /* recycling window (2 <= kmin <= 16, kmin < kmax <= 55) */
+    int32_t solves;          /* projected solves per Enlarge; <= 0 means kmax - kmin */
+    double eps;              /* smoothing of the l1 penalty (> 0) */
+    double tau;              /* discrepancy-principle factor: target = tau * delta */
+    double lam_fix;          /* >= 0: fixed lambda; < 0: discrepancy principle */
+    int32_t param_update;    /* 0: angles fixed (RMM-GKS); 1: Gauss-Newton (Alg. "update_param") */
+    int32_t param_mode;      /* 0: one angle per view; 1: one global shift of all views */
+    int32_t maxiter_p;       /* Gauss-Newton iterations per outer iteration */
+    double mu_rel;           /* damping mu = mu_rel * mean(||D_v||^2) */
+    double c1, beta, alpha0; /* Armijo constant, backtracking factor, first step */
+    int32_t armijo_trials;   /* <= 32 */
+    double breakdown_tol;    /* Krylov breakdown threshold */
+    int32_t temporal;        /* dynamic problems: regulariser includes frame differences */
+} nlrmm_solver_cfg;
+
+typedef struct nlrmm_solver nlrmm_solver;
+
+/* Allocate the solver state for images of nframes frames and up to max_views views
+ * (basis V [kmax+1][n], A V [kmax+1][max_views*nbins], FP64 projected quantities). */
+int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
+                        int64_t max_views, const nlrmm_solver_cfg *cfg, nlrmm_solver **out);
+void nlrmm_solver_destroy(nlrmm_solver *solver);
+
+/* Start basis: kmin+1 Golub-Kahan right vectors of A(theta) from b (full CGS2), u = 0. */
+int nlrmm_solver_init(nlrmm_solver *solver, const nlrmm_batch *batch, const double *theta,
+                      const float *b, void *stream);
+
+/* One outer iteration on the views of `batch` (all views, or one streaming block):
+ * rebase A V = A(theta_k) V; Enlarge (solves projected solves, one append between
+ * consecutive solves); Compress; UPDATE-PARAM (theta updated in place); weights from the
+ * new image; residual with the old operator A(theta_k); CGS2; append.  delta is the noise
+ * norm of these views (discrepancy target tau*delta).  theta, b DEVICE. */
+int nlrmm_solver_outer(nlrmm_solver *solver, const nlrmm_batch *batch, double *theta,
+                       const float *b, double delta, void *stream);
+
+/* DEVICE pointers into the solver: image u [n], basis V, scalars scal[16]
+ * ({||b||^2, target, lambda, model residual^2, ..., [8] GN f0, g^T d, alpha, mu, f}),
+ * status word; ell = current number of basis columns. */
+int nlrmm_solver_state(nlrmm_solver *solver, float **u, float **V, double **scal,
+                       int32_t **status, int32_t *ell);
+
+/* Asynchronous device-to-device copies of the solver state into caller buffers (any may be
+ * NULL): u_out [n] float32, scal_out [16] float64, status_out [1] int32. */
+int nlrmm_solver_read(nlrmm_solver *solver, float *u_out, double *scal_out, int32_t *status_out,
+                      void *stream);
+
 #ifdef __cplusplus
 }
 #endif

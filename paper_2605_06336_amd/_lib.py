@@ -36,6 +36,16 @@ _D = ctypes.c_double
 _GP = ctypes.POINTER(Geom)
 _BP = ctypes.POINTER(Batch)
 
+
+class SolverCfg(ctypes.Structure):
+    _fields_ = [("kmin", ctypes.c_int32), ("kmax", ctypes.c_int32), ("solves", ctypes.c_int32),
+                ("eps", ctypes.c_double), ("tau", ctypes.c_double), ("lam_fix", ctypes.c_double),
+                ("param_update", ctypes.c_int32), ("param_mode", ctypes.c_int32),
+                ("maxiter_p", ctypes.c_int32), ("mu_rel", ctypes.c_double),
+                ("c1", ctypes.c_double), ("beta", ctypes.c_double), ("alpha0", ctypes.c_double),
+                ("armijo_trials", ctypes.c_int32), ("breakdown_tol", ctypes.c_double),
+                ("temporal", ctypes.c_int32)]
+
 # name -> argtypes (all return int except where noted)
 SIGNATURES = {
     "nlrmm_version": [],
@@ -43,6 +53,19 @@ SIGNATURES = {
     "nlrmm_project": [_P, _GP, _BP, _I32, _P, _P, _P, _P],
     "nlrmm_backproject": [_P, _GP, _BP, _I32, _P, _P, _P, _P],
     "nlrmm_project_dtheta": [_P, _GP, _BP, _I32, _P, _P, _P, _P, _P, _P, _P, _P],
+    "nlrmm_tv_weights": [_P, _GP, _I32, _I32, _P, _D, _P, _P],
+    "nlrmm_gram_psi": [_P, _GP, _I32, _I32, _I32, _P, _P, _P, _I32, _P],
+    "nlrmm_gks_solve": [_P, _I32, _P, _P, _I32, _P, _P, _D, _P, _P, _P, _P],
+    "nlrmm_gks_expand": [_P, _GP, _BP, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _I32, _P,
+                         _D, _P, _P],
+    "nlrmm_recycle_compress": [_P, _I64, _I64, _I32, _I32, _P, _P, _P, _P, _I32, _P, _P, _P,
+                               _P, _P],
+    "nlrmm_solver_create": [_P, _GP, _I32, _I64, ctypes.POINTER(SolverCfg),
+                            ctypes.POINTER(ctypes.c_void_p)],
+    "nlrmm_solver_init": [_P, _BP, _P, _P, _P],
+    "nlrmm_solver_outer": [_P, _BP, _P, _P, _D, _P],
+    "nlrmm_solver_state": [_P, _P, _P, _P, _P, _P],
+    "nlrmm_solver_read": [_P, _P, _P, _P, _P],
 }
 
 
@@ -62,6 +85,8 @@ def lib():
         l.nlrmm_strerror.restype = ctypes.c_char_p
         l.nlrmm_ctx_destroy.argtypes = [ctypes.c_void_p]
         l.nlrmm_ctx_destroy.restype = None
+        l.nlrmm_solver_destroy.argtypes = [ctypes.c_void_p]
+        l.nlrmm_solver_destroy.restype = None
         _lib = l
     return _lib
 

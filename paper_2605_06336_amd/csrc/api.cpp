@@ -9,25 +9,30 @@ namespace nlrmm {
 
 int ensure_workspace(nlrmm_ctx *ctx, size_t bytes, hipStream_t stream)
 {
-    if (ctx->ws.bytes >= bytes) return NLRMM_OK;
+    return ensure_buffer(ctx->ws, bytes, stream);
+}
+
+int ensure_buffer(Workspace &ws, size_t bytes, hipStream_t stream)
+{
+    if (ws.bytes >= bytes) return NLRMM_OK;
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone)
         return NLRMM_ENOMEM;   // growing the workspace would allocate inside a capture
     size_t nb = bytes + bytes / 4 + (1u << 20);
     void *p = nullptr;
     // the old buffer may still be read by queued work on any stream
-    if (ctx->ws.ptr) {
+    if (ws.ptr) {
         if (hipDeviceSynchronize() != hipSuccess) return NLRMM_EHIP;
-        if (hipFree(ctx->ws.ptr) != hipSuccess) return NLRMM_EHIP;
-        ctx->ws.ptr = nullptr;
-        ctx->ws.bytes = 0;
+        if (hipFree(ws.ptr) != hipSuccess) return NLRMM_EHIP;
+        ws.ptr = nullptr;
+        ws.bytes = 0;
     }
     if (hipMalloc(&p, nb) != hipSuccess) {
         (void)hipGetLastError();
         return NLRMM_ENOMEM;
     }
-    ctx->ws.ptr = p;
-    ctx->ws.bytes = nb;
+    ws.ptr = p;
+    ws.bytes = nb;
     return NLRMM_OK;
 }
 
@@ -89,10 +94,9 @@ int nlrmm_ctx_create(nlrmm_ctx **out, int device)
 void nlrmm_ctx_destroy(nlrmm_ctx *ctx)
 {
     if (!ctx) return;
-    if (ctx->ws.ptr) {
-        (void)hipDeviceSynchronize();
-        (void)hipFree(ctx->ws.ptr);
-    }
+    if (ctx->ws.ptr || ctx->kws.ptr) (void)hipDeviceSynchronize();
+    if (ctx->ws.ptr) (void)hipFree(ctx->ws.ptr);
+    if (ctx->kws.ptr) (void)hipFree(ctx->kws.ptr);
     delete ctx;
 }
 

@@ -1,0 +1,221 @@
+// Gauss-Newton angle update (Alg. "update_param") and small device-side helpers.
+//
+// Per-view angles: the Jacobian column of theta_v is non-zero only on view v's rows, so
+// J^T J is diagonal with entries h_v = ||D_v||^2 and the damped step is
+//   d_v = -g_v / (h_v + mu),  g_v = <D_v, r_v>,  r = A(theta) u - b,
+// with mu = mu_rel * mean(h).  A single global shift (the paper's experiments) uses
+// g = sum g_v, h = sum h_v.  The Armijo backtracking (one alpha for all angles) is run
+// as a fixed sequence of trial projections; a device flag set by the first accepted
+// trial makes the remaining trials return immediately, so no host round trip is needed.
+#include "internal.h"
+#include "krylov.h"
+
+#include <math.h>
+
+namespace nlrmm {
+namespace {
+
+constexpr int BLK = 256;
+
+__device__ double block_sum2(double v, double *sbuf)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sbuf[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < BLK / 64; ++i) t += sbuf[i];
+    return t;
+}
+
+__global__ __launch_bounds__(BLK) void gn_prepare_k(const double *__restrict__ g,
+                                                    const double *__restrict__ h,
+                                                    const double *__restrict__ rn2, int64_t V,
+                                                    int scalar_mode, double mu_rel,
+                                                    double *__restrict__ dir,
+                                                    double *__restrict__ sc, int *accepted)
+{
+    __shared__ double sbuf[BLK / 64];
+    const int tid = threadIdx.x;
+    double sg = 0.0, sh = 0.0, sr = 0.0;
+    for (int64_t v = tid; v < V; v += BLK) {
+        sg += g[v];
+        sh += h[v];
+        sr += rn2[v];
+    }
+    sg = block_sum2(sg, sbuf);
+    sh = block_sum2(sh, sbuf);
+    sr = block_sum2(sr, sbuf);
+    double gd = 0.0, mu;
+    if (scalar_mode) {
+        mu = mu_rel * sh;
+        const double d = -sg / (sh + mu);
+        for (int64_t v = tid; v < V; v += BLK) dir[v] = d;
+        gd = sg * d;
+    } else {
+        mu = mu_rel * sh / (double)V;
+        double part = 0.0;
+        for (int64_t v = tid; v < V; v += BLK) {
+            const double d = -g[v] / (h[v] + mu);
+            dir[v] = d;
+            part += g[v] * d;
+        }
+        gd = block_sum2(part, sbuf);
+    }
+    if (tid == 0) {
+        sc[0] = 0.5 * sr;   // f0
+        sc[1] = gd;         // g^T d
+        sc[2] = 0.0;        // accepted alpha
+        sc[3] = mu;
+        *accepted = 0;
+    }
+}
+
+__global__ __launch_bounds__(BLK) void armijo_check_k(const double *__restrict__ part_r,
+                                                      int64_t nparts,
+                                                      const double *__restrict__ alphas, int q,
+                                                      double c1, double *__restrict__ sc,
+                                                      int *accepted)
+{
+    __shared__ double sbuf[BLK / 64];
+    if (*accepted) return;   // uniform
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < nparts; i += BLK) s += part_r[i];
+    s = block_sum2(s, sbuf);
+    if (threadIdx.x == 0) {
+        const double f = 0.5 * s;
+        const double a = alphas[q];
+        if (f <= sc[0] + c1 * a * sc[1]) {
+            *accepted = 1;
+            sc[2] = a;
+            sc[4] = f;
+        }
+    }
+}
+
+__global__ void gn_apply_k(double *__restrict__ theta, const double *__restrict__ dir, int64_t V,
+                           const double *__restrict__ sc, const int *__restrict__ accepted,
+                           int *status)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double a = *accepted ? sc[2] : 0.0;
+    if (v < V) theta[v] += a * dir[v];
+    if (v == 0 && !*accepted) atomicOr(status, NLRMM_ST_ARMIJO);
+}
+
+__global__ void scatter_gram_k(const double *__restrict__ col, int ell, double *__restrict__ G,
+                               int ldg, double *__restrict__ rb)
+{
+    // col = [G[0..ell][ell], rb[ell]] from one multi-dot launch
+    const int i = threadIdx.x;
+    if (i <= ell) {
+        G[i * ldg + ell] = col[i];
+        G[ell * ldg + i] = col[i];
+    }
+    if (i == 0) rb[ell] = col[ell + 1];
+}
+
+__global__ void symmetrize_k(double *G, int ldg, int ell)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ell * ell) return;
+    const int i = t / ell, j = t % ell;
+    if (i > j) G[i * ldg + j] = G[j * ldg + i];
+}
+
+__global__ void copy_f64_k(const double *__restrict__ s, double *__restrict__ d, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = s[i];
+}
+
+__global__ void fill_f64_k(double *d, int64_t n, double v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = v;
+}
+
+__global__ void fill_i32_k(int *d, int64_t n, int v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = v;
+}
+
+// dst = src / sqrt(norm2[0]); norm_out[0] = sqrt(norm2[0])
+__global__ void scale_into_k(const float *__restrict__ src, const double *__restrict__ norm2,
+                             int64_t n, float *__restrict__ dst, double *norm_out, int *status)
+{
+    const double nr = sqrt(fmax(norm2[0], 0.0));
+    const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        if (norm_out) norm_out[0] = nr;
+        if (!(nr > 0.0) || !isfinite(nr)) atomicOr(status, NLRMM_ST_NONFINITE);
+    }
+    if (i < n) dst[i] = (float)((double)src[i] * inv);
+}
+
+}  // namespace
+
+#define LAUNCH_OK (hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP)
+
+int k_gn_prepare(const double *g, const double *h, const double *rn2, int64_t V, int scalar_mode,
+                 double mu_rel, double *dir, double *sc, int *accepted, hipStream_t s)
+{
+    gn_prepare_k<<<1, BLK, 0, s>>>(g, h, rn2, V, scalar_mode, mu_rel, dir, sc, accepted);
+    return LAUNCH_OK;
+}
+
+int k_armijo_check(const double *part_r, int64_t nparts, const double *alphas, int q, double c1,
+                   double *sc, int *accepted, hipStream_t s)
+{
+    armijo_check_k<<<1, BLK, 0, s>>>(part_r, nparts, alphas, q, c1, sc, accepted);
+    return LAUNCH_OK;
+}
+
+int k_gn_apply(double *theta, const double *dir, int64_t V, const double *sc,
+               const int *accepted, int *status, hipStream_t s)
+{
+    gn_apply_k<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(theta, dir, V, sc, accepted, status);
+    return LAUNCH_OK;
+}
+
+int k_scatter_gram(const double *col, int ell, double *G, int ldg, double *rb, hipStream_t s)
+{
+    scatter_gram_k<<<1, 128, 0, s>>>(col, ell, G, ldg, rb);
+    return LAUNCH_OK;
+}
+
+int k_symmetrize(double *G, int ldg, int ell, hipStream_t s)
+{
+    symmetrize_k<<<(unsigned)((ell * ell + 255) / 256), 256, 0, s>>>(G, ldg, ell);
+    return LAUNCH_OK;
+}
+
+int k_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s)
+{
+    copy_f64_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, dst, n);
+    return LAUNCH_OK;
+}
+
+int k_fill_f64(double *dst, int64_t n, double value, hipStream_t s)
+{
+    fill_f64_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(dst, n, value);
+    return LAUNCH_OK;
+}
+
+int k_fill_i32(int *dst, int64_t n, int value, hipStream_t s)
+{
+    fill_i32_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(dst, n, value);
+    return LAUNCH_OK;
+}
+
+int k_scale_into(const float *src, const double *norm2, int64_t n, float *dst, double *norm_out,
+                 int *status, hipStream_t s)
+{
+    scale_into_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, norm2, n, dst, norm_out, status);
+    return LAUNCH_OK;
+}
+
+}  // namespace nlrmm

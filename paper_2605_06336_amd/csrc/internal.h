@@ -24,7 +24,8 @@ struct Workspace {
 
 struct nlrmm_ctx {
     int device = 0;
-    nlrmm::Workspace ws;
+    nlrmm::Workspace ws;    // projector packs (reused by every projection)
+    nlrmm::Workspace kws;   // scratch of the standalone Krylov entry points
     int cu_count = 256;
 };
 
@@ -32,11 +33,32 @@ namespace nlrmm {
 
 // Grow the context workspace to at least `bytes` (refused while `stream` is capturing).
 int ensure_workspace(nlrmm_ctx *ctx, size_t bytes, hipStream_t stream);
+int ensure_buffer(Workspace &w, size_t bytes, hipStream_t stream);
 
 int check_geom(const nlrmm_geom *g);
 int check_batch(const nlrmm_batch *b);
 
+// Forward-kernel outputs and modes (see proj.hip).
+struct FwdOptions {
+    float *y = nullptr;            // projection [col][V][nb]
+    float *dy = nullptr;           // angle derivative [col][V][nb]
+    const float *g = nullptr;      // weights of the fused <D_v, g_v>
+    double *gdot = nullptr;        // [col][V]
+    double *dnorm2 = nullptr;      // [col][V]
+    double *rnorm2 = nullptr;      // [col][V] ||y_v - b_v||^2 (residual mode)
+    const float *bres = nullptr;   // residual mode: g := y - b
+    const double *tdir = nullptr;  // trial angles theta + talpha[0] * tdir
+    const double *talpha = nullptr;
+    const int *skip = nullptr;     // device flag: skip the whole call when set
+    double *part_buf = nullptr;    // caller-provided partials [3][col][V][nchunks]
+    bool keep_parts = false;       // leave per-chunk partials unreduced (caller reduces)
+};
+
 // projector launchers (proj.hip); all arguments validated by the caller
+int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
+                      const float *x, const double *theta, const FwdOptions &o, hipStream_t s);
+int fwd_chunks(const nlrmm_geom &g);
+size_t fwd_workspace_bytes(const nlrmm_geom &g, int nframes, int ncols);
 int launch_project(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
                    const float *x, const double *theta, float *y, float *dy, const float *gres,
                    double *gdot, double *dnorm2, hipStream_t s);

@@ -1,0 +1,47 @@
+// Launchers of the Krylov-side and Gauss-Newton kernels (krylov.hip, gn.hip).
+#pragma once
+#include "internal.h"
+
+namespace nlrmm {
+
+int k_psi_weights(const float *u, int nx, int ny, int F, int temporal, float eps, float *w,
+                  hipStream_t s);
+int k_psi_apply(const float *u, int nx, int ny, int F, int temporal, float *out, hipStream_t s);
+int k_tv_grad_add(const float *u, const float *w, int nx, int ny, int F, int temporal,
+                  const double *lamp, float *r, hipStream_t s);
+int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int ny, int F,
+               int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s);
+int k_multidot(const float *X, int64_t ldx, int nv, const float *y, const float *z, int64_t n,
+               double *part, int nblk, double *out, int ostride, hipStream_t s);
+int k_gemv(const float *X, int64_t ldx, int nv, const double *c, double beta, const float *a,
+           double alpha, int64_t n, float *out, hipStream_t s);
+int k_block_update(const float *X, int64_t ldx, int nin, const double *T, int ldt, int kout,
+                   int64_t n, float *Y, int64_t ldy, hipStream_t s);
+int k_copy_cols(const float *src, int64_t lds, float *dst, int64_t ldd, int ncols, int64_t n,
+                hipStream_t s);
+int k_normalize_into(const float *r, const double *scal, double tol, int64_t n, float *vout,
+                     int *status, double *norm_out, hipStream_t s);
+int k_gks_solve(const double *GA, const double *GP, int ldg, const double *rb, const double *scal,
+                int ell, double lam_fix, double *z, double *out, int *status, hipStream_t s);
+int k_compress_eig(const double *GA, const double *GP, int ldg, const double *lam, int ell,
+                   int kmin, const double *z, double *T, int ldt, double *zout, int *kout,
+                   int *status, hipStream_t s);
+int k_gram_transform(double *G, int ldg, double *rb, int ell, const double *T, int ldt,
+                     const int *kp, hipStream_t s);
+
+// small device helpers (gn.hip)
+int k_scatter_gram(const double *col, int ell, double *G, int ldg, double *rb, hipStream_t s);
+int k_symmetrize(double *G, int ldg, int ell, hipStream_t s);
+int k_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);
+int k_gn_prepare(const double *g, const double *h, const double *rn2, int64_t V, int scalar_mode,
+                 double mu_rel, double *dir, double *sc, int *accepted, hipStream_t s);
+int k_armijo_check(const double *part_r, int64_t nparts, const double *alphas, int q, double c1,
+                   double *sc, int *accepted, hipStream_t s);
+int k_gn_apply(double *theta, const double *dir, int64_t V, const double *sc,
+               const int *accepted, int *status, hipStream_t s);
+int k_fill_f64(double *dst, int64_t n, double value, hipStream_t s);
+int k_fill_i32(int *dst, int64_t n, int value, hipStream_t s);
+int k_scale_into(const float *src, const double *norm2, int64_t n, float *dst, double *norm_out,
+                 int *status, hipStream_t s);
+
+}  // namespace nlrmm

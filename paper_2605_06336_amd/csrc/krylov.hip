@@ -1,0 +1,899 @@
+// Krylov-side kernels of MM-GKS / RMM-GKS on gfx950 (Section 3 and supplementary
+// Algorithms "mmgks", "enlarge", "compress"):
+//   * anisotropic TV regulariser Psi (Section 2.2), MM weights w = ((Psi u)^2 + eps^2)^(-1/2)
+//     (Section 3.1) and the regulariser part lam Psi^T (w * Psi u) of the GKS residual;
+//   * FP64-accumulated Gram matrices and multi-dot products over FP32 basis blocks;
+//   * basis GEMV / block updates (u = V z, r -= V h, V <- V T);
+//   * a single-workgroup FP64 solver of the projected problem with lambda chosen by the
+//     discrepancy principle, and the eigen-decomposition used by the recycling compression.
+// Everything that decides (lambda, breakdown, compression size) is decided on the device.
+#include "internal.h"
+#include "krylov.h"
+
+#include <math.h>
+
+namespace nlrmm {
+namespace {
+
+constexpr int BLK = 256;
+constexpr int SOLVE_MAX = 56;   // largest projected problem: two 56x57 FP64 matrices in LDS
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// block-wide sum of a double (all threads receive the result)
+__device__ double block_sum(double v, double *sbuf)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sbuf[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) t += sbuf[i];
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// regulariser
+// ---------------------------------------------------------------------------
+struct TVGeo {
+    int nx, ny, F, temporal;
+    int64_t per_frame;   // ny (nx-1) + (ny-1) nx
+    int64_t dy_off;      // ny (nx-1)
+    int64_t t_off;       // F * per_frame
+};
+
+__device__ __forceinline__ TVGeo tvgeo(int nx, int ny, int F, int temporal)
+{
+    TVGeo g;
+    g.nx = nx;
+    g.ny = ny;
+    g.F = F;
+    g.temporal = temporal && F > 1;
+    g.dy_off = (int64_t)ny * (nx - 1);
+    g.per_frame = g.dy_off + (int64_t)(ny - 1) * nx;
+    g.t_off = (int64_t)F * g.per_frame;
+    return g;
+}
+
+// w = ((Psi u)^2 + eps^2)^(-1/2), one thread per pixel writing its forward differences.
+__global__ void psi_weights_k(const float *__restrict__ u, int nx, int ny, int F, int temporal,
+                              float eps, float *__restrict__ w)
+{
+    const TVGeo g = tvgeo(nx, ny, F, temporal);
+    const int64_t npix = (int64_t)nx * ny;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix * F) return;
+    const int64_t f = i / npix, p = i - f * npix;
+    const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
+    const float uc = u[i];
+    const float e2 = eps * eps;
+    if (k < nx - 1) {
+        const float s = u[i + 1] - uc;
+        w[f * g.per_frame + (int64_t)l * (nx - 1) + k] = 1.0f / sqrtf(s * s + e2);
+    }
+    if (l < ny - 1) {
+        const float s = u[i + nx] - uc;
+        w[f * g.per_frame + g.dy_off + (int64_t)l * nx + k] = 1.0f / sqrtf(s * s + e2);
+    }
+    if (g.temporal && f < F - 1) {
+        const float s = u[i + npix] - uc;
+        w[g.t_off + f * npix + p] = 1.0f / sqrtf(s * s + e2);
+    }
+}
+
+// r += lam * Psi^T (w * Psi u)  (the regulariser part of the normal-equation residual).
+__global__ void tv_grad_add_k(const float *__restrict__ u, const float *__restrict__ w, int nx,
+                              int ny, int F, int temporal, const double *__restrict__ lamp,
+                              float *__restrict__ r)
+{
+    const float lam = (float)lamp[0];
+    const TVGeo g = tvgeo(nx, ny, F, temporal);
+    const int64_t npix = (int64_t)nx * ny;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix * F) return;
+    const int64_t f = i / npix, p = i - f * npix;
+    const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
+    const float uc = u[i];
+    const float *wf = w + f * g.per_frame;
+    float acc = 0.0f;
+    if (k < nx - 1) acc -= wf[(int64_t)l * (nx - 1) + k] * (u[i + 1] - uc);
+    if (k > 0) acc += wf[(int64_t)l * (nx - 1) + k - 1] * (uc - u[i - 1]);
+    if (l < ny - 1) acc -= wf[g.dy_off + (int64_t)l * nx + k] * (u[i + nx] - uc);
+    if (l > 0) acc += wf[g.dy_off + (int64_t)(l - 1) * nx + k] * (uc - u[i - nx]);
+    if (g.temporal) {
+        if (f < F - 1) acc -= w[g.t_off + f * npix + p] * (u[i + npix] - uc);
+        if (f > 0) acc += w[g.t_off + (f - 1) * npix + p] * (uc - u[i - npix]);
+    }
+    r[i] += lam * acc;
+}
+
+// Psi u written out (used by tests and by the VarPro regulariser block).
+__global__ void psi_apply_k(const float *__restrict__ u, int nx, int ny, int F, int temporal,
+                            float *__restrict__ s)
+{
+    const TVGeo g = tvgeo(nx, ny, F, temporal);
+    const int64_t npix = (int64_t)nx * ny;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix * F) return;
+    const int64_t f = i / npix, p = i - f * npix;
+    const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
+    const float uc = u[i];
+    if (k < nx - 1) s[f * g.per_frame + (int64_t)l * (nx - 1) + k] = u[i + 1] - uc;
+    if (l < ny - 1) s[f * g.per_frame + g.dy_off + (int64_t)l * nx + k] = u[i + nx] - uc;
+    if (g.temporal && f < F - 1) s[g.t_off + f * npix + p] = u[i + npix] - uc;
+}
+
+// Weighted regulariser Gram G[i][j] = sum_e w_e (Psi v_i)_e (Psi v_j)_e for the first ell
+// columns of V (column stride ldv), Psi v computed on the fly from V.  Each block handles
+// a strided set of 16-pixel chunks: the chunk's weighted difference rows (<= 48 x ell)
+// are staged in LDS as FP64 and every thread accumulates a 4x4 tile of G in FP64.
+constexpr int GP_PIX = 16;
+constexpr int GP_ROWS = GP_PIX * 3;
+constexpr int GMAX = 64;
+
+__global__ __launch_bounds__(BLK) void gram_psi_k(const float *__restrict__ V, int64_t ldv, int ell,
+                                                  const float *__restrict__ w, int nx, int ny,
+                                                  int F, int temporal, double *__restrict__ part)
+{
+    __shared__ double sB[GP_ROWS][GMAX + 1];
+    const TVGeo g = tvgeo(nx, ny, F, temporal);
+    const int64_t npix = (int64_t)nx * ny;
+    const int64_t ntot = npix * F;
+    const int tid = threadIdx.x;
+    const int ti = tid / 16, tj = tid % 16;    // 4x4 output tile (4 ti .. 4 ti + 3, 4 tj ..)
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    const int64_t nchunks = (ntot + GP_PIX - 1) / GP_PIX;
+    const bool active = 4 * ti < ell && 4 * tj < ell;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        // stage rows: row r = 3 * pixel + {0: dx, 1: dy, 2: dt}
+        for (int t = tid; t < GP_ROWS * ell; t += BLK) {
+            const int c = t / GP_ROWS, r = t - c * GP_ROWS;
+            const int pc = r / 3, kind = r - pc * 3;
+            const int64_t i = ch * GP_PIX + pc;
+            double val = 0.0;
+            if (i < ntot) {
+                const int64_t f = i / npix, p = i - f * npix;
+                const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
+                const float *vc = V + (int64_t)c * ldv;
+                if (kind == 0 && k < nx - 1) {
+                    const float ww = w[f * g.per_frame + (int64_t)l * (nx - 1) + k];
+                    val = sqrt((double)ww) * ((double)vc[i + 1] - (double)vc[i]);
+                } else if (kind == 1 && l < ny - 1) {
+                    const float ww = w[f * g.per_frame + g.dy_off + (int64_t)l * nx + k];
+                    val = sqrt((double)ww) * ((double)vc[i + nx] - (double)vc[i]);
+                } else if (kind == 2 && g.temporal && f < F - 1) {
+                    const float ww = w[g.t_off + f * npix + p];
+                    val = sqrt((double)ww) * ((double)vc[i + npix] - (double)vc[i]);
+                }
+            }
+            sB[r][c] = val;
+        }
+        __syncthreads();
+        if (active) {
+            for (int r = 0; r < GP_ROWS; ++r) {
+                double ra[4], cb[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int ii = 4 * ti + a, jj = 4 * tj + a;
+                    ra[a] = ii < ell ? sB[r][ii] : 0.0;
+                    cb[a] = jj < ell ? sB[r][jj] : 0.0;
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] = fma(ra[a], cb[b], acc[a][b]);
+            }
+        }
+        __syncthreads();
+    }
+    double *out = part + (int64_t)blockIdx.x * ell * ell;
+    if (active) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int ii = 4 * ti + a, jj = 4 * tj + b;
+                if (ii < ell && jj < ell) out[ii * ell + jj] = acc[a][b];
+            }
+    }
+}
+
+// Sum nblk partial ell x ell matrices into G (leading dimension ldg), fixed order.
+__global__ void reduce_gram_k(const double *__restrict__ part, int nblk, int ell,
+                              double *__restrict__ G, int ldg)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ell * ell) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * ell * ell + t];
+    const int i = t / ell, j = t - i * ell;
+    G[i * ldg + j] = s;
+}
+
+// ---------------------------------------------------------------------------
+// multi-dot / GEMV over basis blocks (FP32 storage, FP64 accumulation)
+// ---------------------------------------------------------------------------
+// part[blk][i] = sum over this block's entries of X_i[e] * y[e], i < nv; X_i = X + i*ldx.
+// An extra row (i = nv) accumulates y[e] * z[e] when z != null.
+constexpr int MD_MAX = 72;
+
+__global__ __launch_bounds__(BLK) void multidot_k(const float *__restrict__ X, int64_t ldx, int nv,
+                                                  const float *__restrict__ y,
+                                                  const float *__restrict__ z, int64_t n,
+                                                  double *__restrict__ part)
+{
+    __shared__ double sred[BLK / 64][MD_MAX + 1];
+    const int tid = threadIdx.x;
+    const int nout = nv + (z != nullptr ? 1 : 0);
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int i0 = 0; i0 < nout; i0 += 8) {
+        double acc[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) acc[a] = 0.0;
+        for (int64_t e = (int64_t)blockIdx.x * BLK + tid; e < n; e += (int64_t)gridDim.x * BLK) {
+            const double ye = (double)y[e];
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                const int i = i0 + a;
+                if (i < nv) acc[a] = fma((double)X[(int64_t)i * ldx + e], ye, acc[a]);
+                else if (i == nv && z != nullptr) acc[a] = fma((double)z[e], ye, acc[a]);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const double s = wave_sum(acc[a]);
+            if (lane == 0 && i0 + a < nout) sred[wv][i0 + a] = s;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < nout; i += BLK) {
+        double s = 0.0;
+        for (int w = 0; w < BLK / 64; ++w) s += sred[w][i];
+        part[(int64_t)blockIdx.x * nout + i] = s;
+    }
+}
+
+// out[i * ostride] = sum_b part[b][i] (fixed order); optional scaling.
+__global__ void reduce_vec_k(const double *__restrict__ part, int nblk, int nout,
+                             double *__restrict__ out, int ostride)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nout) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * nout + i];
+    out[(int64_t)i * ostride] = s;
+}
+
+// out[e] = alpha * a[e] + beta * sum_i X_i[e] c_i   (a may be null; c FP64 on the device)
+__global__ __launch_bounds__(BLK) void gemv_k(const float *__restrict__ X, int64_t ldx, int nv,
+                                              const double *__restrict__ c, double beta,
+                                              const float *__restrict__ a, double alpha,
+                                              int64_t n, float *__restrict__ out)
+{
+    __shared__ double sc[MD_MAX];
+    for (int i = threadIdx.x; i < nv; i += BLK) sc[i] = c[i];
+    __syncthreads();
+    for (int64_t e = (int64_t)blockIdx.x * BLK + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * BLK) {
+        double s = 0.0;
+        for (int i = 0; i < nv; ++i) s = fma((double)X[(int64_t)i * ldx + e], sc[i], s);
+        double r = beta * s;
+        if (a) r += alpha * (double)a[e];
+        out[e] = (float)r;
+    }
+}
+
+// r -= V h with h = part-reduced coefficients already in `h` (FP64).
+// (gemv_k with alpha = 1, beta = -1, a = r, out = r covers this.)
+
+// V_new[:, j] = sum_i V[:, i] T[i][j] for j < kout, written to Y (column stride ldy).
+__global__ __launch_bounds__(BLK) void block_update_k(const float *__restrict__ X, int64_t ldx,
+                                                      int nin, const double *__restrict__ T,
+                                                      int ldt, int kout, int64_t n,
+                                                      float *__restrict__ Y, int64_t ldy)
+{
+    __shared__ double sT[MD_MAX * 16];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < nin * kout; i += BLK) {
+        const int r = i / kout, c = i - r * kout;
+        sT[i] = T[r * ldt + c];
+    }
+    __syncthreads();
+    for (int64_t e = (int64_t)blockIdx.x * BLK + tid; e < n; e += (int64_t)gridDim.x * BLK) {
+        double acc[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+        for (int i = 0; i < nin; ++i) {
+            const double xv = (double)X[(int64_t)i * ldx + e];
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (c < kout) acc[c] = fma(xv, sT[i * kout + c], acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (c < kout) Y[(int64_t)c * ldy + e] = (float)acc[c];
+    }
+}
+
+__global__ void copy_cols_k(const float *__restrict__ src, int64_t lds, float *__restrict__ dst,
+                            int64_t ldd, int ncols, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * ncols) return;
+    const int64_t c = t / n, e = t - c * n;
+    dst[c * ldd + e] = src[c * lds + e];
+}
+
+// v = r / ||r|| into column `col` of V; breakdown when ||r_perp|| <= tol ||r_raw||.
+// scal[0] = ||r_raw||^2, scal[1] = ||r_perp||^2 (device).  On breakdown the column is
+// still written (normalised) and the status bit is set.
+__global__ void normalize_into_k(const float *__restrict__ r, const double *__restrict__ scal,
+                                 double tol, int64_t n, float *__restrict__ vout,
+                                 int *__restrict__ status, double *__restrict__ norm_out)
+{
+    const double raw = sqrt(fmax(scal[0], 0.0));
+    const double perp = sqrt(fmax(scal[1], 0.0));
+    const double inv = perp > 0.0 ? 1.0 / perp : 0.0;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) {
+        if (!(perp > tol * raw)) atomicOr(status, NLRMM_ST_BREAKDOWN);
+        if (!isfinite(perp)) atomicOr(status, NLRMM_ST_NONFINITE);
+        if (norm_out) *norm_out = perp;
+    }
+    if (e < n) vout[e] = (float)((double)r[e] * inv);
+}
+
+// ---------------------------------------------------------------------------
+// single-workgroup FP64 dense linear algebra (ell <= 64), all operands in LDS
+// ---------------------------------------------------------------------------
+// In-place lower Cholesky of the n x n matrix A (row stride ld).  Returns via *bad a
+// non-zero value when a pivot was not positive (the pivot is then replaced by a tiny one).
+__device__ void chol_lower(double *A, int n, int ld, int *bad)
+{
+    const int tid = threadIdx.x;
+    for (int j = 0; j < n; ++j) {
+        if (tid == 0) {
+            double p = A[j * ld + j];
+            if (!(p > 0.0)) {
+                *bad = 1;
+                p = 1e-300;
+            }
+            A[j * ld + j] = sqrt(p);
+        }
+        __syncthreads();
+        const double piv = A[j * ld + j];
+        for (int i = j + 1 + tid; i < n; i += blockDim.x) A[i * ld + j] /= piv;
+        __syncthreads();
+        const int m = n - j - 1;
+        for (int t = tid; t < m * m; t += blockDim.x) {
+            const int i = j + 1 + t / m, k = j + 1 + t % m;
+            if (k <= i) A[i * ld + k] -= A[i * ld + j] * A[k * ld + j];
+        }
+        __syncthreads();
+    }
+}
+
+// Solve L X = B in place (B: n x nrhs, row stride ldb), L lower (row stride ld).
+__device__ void trsm_lower(const double *L, int ld, double *B, int ldb, int n, int nrhs)
+{
+    const int tid = threadIdx.x;
+    for (int j = 0; j < n; ++j) {
+        for (int c = tid; c < nrhs; c += blockDim.x) B[j * ldb + c] /= L[j * ld + j];
+        __syncthreads();
+        const int m = n - j - 1;
+        for (int t = tid; t < m * nrhs; t += blockDim.x) {
+            const int i = j + 1 + t / nrhs, c = t % nrhs;
+            B[i * ldb + c] -= L[i * ld + j] * B[j * ldb + c];
+        }
+        __syncthreads();
+    }
+}
+
+// Solve L^T x = y in place (vector), L lower.
+__device__ void trsv_lower_T(const double *L, int ld, double *x, int n)
+{
+    const int tid = threadIdx.x;
+    for (int j = n - 1; j >= 0; --j) {
+        if (tid == 0) x[j] /= L[j * ld + j];
+        __syncthreads();
+        for (int i = tid; i < j; i += blockDim.x) x[i] -= L[j * ld + i] * x[j];
+        __syncthreads();
+    }
+}
+
+// Cyclic parallel Jacobi eigen-decomposition of the symmetric n x n matrix A (row stride
+// ld, overwritten; eigenvalues end on its diagonal) with eigenvectors accumulated in the
+// columns of U.  Round-robin pairing: n/2 disjoint rotations per round.
+__device__ void jacobi_eig(double *A, double *U, int n, int ld, double *sc, int *spair)
+{
+    const int tid = threadIdx.x;
+    for (int t = tid; t < n * n; t += blockDim.x) {
+        const int i = t / n, j = t % n;
+        U[i * ld + j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (n < 2) return;
+    const int np = (n + 1) & ~1;   // even number of players (a phantom when n is odd)
+    const int npair = np / 2;
+    double *cs = sc;               // [npair] cos
+    double *sn = sc + 32;          // [npair] sin
+    __shared__ int srot;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (tid == 0) srot = 0;
+        __syncthreads();
+        for (int r = 0; r < np - 1; ++r) {
+            if (tid < npair) {
+                int p, q;
+                if (tid == 0) {
+                    p = r;
+                    q = np - 1;
+                } else {
+                    p = (r + tid) % (np - 1);
+                    q = (r - tid + np - 1) % (np - 1);
+                }
+                if (p > q) {
+                    const int t2 = p;
+                    p = q;
+                    q = t2;
+                }
+                double c = 1.0, s = 0.0;
+                if (q < n) {
+                    const double apq = A[p * ld + q];
+                    const double app = A[p * ld + p], aqq = A[q * ld + q];
+                    if (fabs(apq) > 1e-17 * sqrt(fabs(app * aqq)) && apq != 0.0) {
+                        const double tau = (aqq - app) / (2.0 * apq);
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        s = t * c;
+                        srot = 1;
+                    } else {
+                        q = -1;
+                    }
+                } else {
+                    q = -1;
+                }
+                cs[tid] = c;
+                sn[tid] = s;
+                spair[2 * tid] = p;
+                spair[2 * tid + 1] = q;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int t = tid; t < npair * n; t += blockDim.x) {
+                const int k = t / n, j = t % n;
+                const int p = spair[2 * k], q = spair[2 * k + 1];
+                if (q < 0) continue;
+                const double c = cs[k], s = sn[k];
+                const double ap = A[p * ld + j], aq = A[q * ld + j];
+                A[p * ld + j] = c * ap - s * aq;
+                A[q * ld + j] = s * ap + c * aq;
+            }
+            __syncthreads();
+            // columns: A <- A J, U <- U J
+            for (int t = tid; t < npair * n; t += blockDim.x) {
+                const int k = t / n, i = t % n;
+                const int p = spair[2 * k], q = spair[2 * k + 1];
+                if (q < 0) continue;
+                const double c = cs[k], s = sn[k];
+                const double ap = A[i * ld + p], aq = A[i * ld + q];
+                A[i * ld + p] = c * ap - s * aq;
+                A[i * ld + q] = s * ap + c * aq;
+                const double up = U[i * ld + p], uq = U[i * ld + q];
+                U[i * ld + p] = c * up - s * uq;
+                U[i * ld + q] = s * up + c * uq;
+            }
+            __syncthreads();
+        }
+        if (srot == 0) break;
+        __syncthreads();
+    }
+}
+
+// Projected MM-GKS solve (eq. "reduced_problem") from the Grams:
+//   GA = (AV)^T AV, GP = (P Psi V)^T (P Psi V), rb = (AV)^T b, scal = {||b||^2, target}.
+// With GA = L L^T and L^-1 GP L^-T = U diag(gam) U^T, c = L^-1 rb, beta = U^T c:
+//   ||AV z(lam) - b||^2 = sum_i (lam gam_i beta_i / (1 + lam gam_i))^2 + ||b||^2 - ||c||^2,
+//   z(lam) = L^-T U diag(1 / (1 + lam gam)) beta.
+// lam by the discrepancy principle (residual = target) with a log-bracket
+// [1e-10, 1e10] * tr(GA)/tr(GP) and clamping to its ends, or lam = lam_fix >= 0.
+// Outputs: z[0..ell), out[0] = lam, out[1] = ||AVz - b||^2 (model), status bits.
+__global__ __launch_bounds__(BLK) void gks_solve_k(const double *__restrict__ GA,
+                                                   const double *__restrict__ GP, int ldg,
+                                                   const double *__restrict__ rb,
+                                                   const double *__restrict__ scal, int ell,
+                                                   double lam_fix, double *__restrict__ z,
+                                                   double *__restrict__ out,
+                                                   int *__restrict__ status)
+{
+    // LDS: two n x (n+1) matrices (L then U; K then L again) and four vectors.
+    extern __shared__ double sm[];
+    const int n = ell, ld = ell + 1;
+    double *A = sm;                 // L, later U
+    double *K = A + n * ld;         // K, later L again
+    double *c = K + n * ld;         // n
+    double *be = c + n;             // n
+    double *ga = be + n;            // n
+    double *yv = ga + n;            // n
+    double *sc = yv + n;            // 128 scratch
+    __shared__ int spair[64];
+    __shared__ int sbad;
+    __shared__ int sfirst;
+    const int tid = threadIdx.x;
+    if (tid == 0) sbad = 0;
+    for (int t = tid; t < n * n; t += BLK) {
+        const int i = t / n, j = t % n;
+        A[i * ld + j] = GA[i * ldg + j];
+        K[i * ld + j] = GP[i * ldg + j];
+    }
+    for (int i = tid; i < n; i += BLK) c[i] = rb[i];
+    __syncthreads();
+    double trA = 0.0, trP = 0.0;
+    for (int i = 0; i < n; ++i) {
+        trA += A[i * ld + i];
+        trP += K[i * ld + i];
+    }
+    chol_lower(A, n, ld, &sbad);
+    trsm_lower(A, ld, c, 1, n, 1);          // c = L^-1 rb
+    trsm_lower(A, ld, K, ld, n, n);         // X = L^-1 GP
+    for (int t = tid; t < n * n; t += BLK) {
+        const int i = t / n, j = t % n;
+        if (i < j) {
+            const double a = K[i * ld + j];
+            K[i * ld + j] = K[j * ld + i];
+            K[j * ld + i] = a;
+        }
+    }
+    __syncthreads();
+    trsm_lower(A, ld, K, ld, n, n);         // K = L^-1 X^T = L^-1 GP L^-T
+    for (int t = tid; t < n * n; t += BLK) {
+        const int i = t / n, j = t % n;
+        if (i < j) {
+            const double a = 0.5 * (K[i * ld + j] + K[j * ld + i]);
+            K[i * ld + j] = a;
+            K[j * ld + i] = a;
+        }
+    }
+    __syncthreads();
+    jacobi_eig(K, A, n, ld, sc, spair);     // A <- U (L is rebuilt below)
+    for (int i = tid; i < n; i += BLK) {
+        ga[i] = fmax(K[i * ld + i], 0.0);
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s += A[k * ld + i] * c[k];
+        be[i] = s;
+    }
+    __syncthreads();
+    double cn2 = 0.0;
+    for (int i = 0; i < n; ++i) cn2 += c[i] * c[i];
+    const double out2 = fmax(scal[0] - cn2, 0.0);
+    const double t2 = scal[1] * scal[1];
+    auto phi = [&](double lam) {
+        double s = out2;
+        for (int i = 0; i < n; ++i) {
+            const double q = lam * ga[i];
+            const double f = q * be[i] / (1.0 + q);
+            s += f * f;
+        }
+        return s;
+    };
+    double lam;
+    int flag = 0;
+    if (lam_fix >= 0.0) {
+        lam = lam_fix;
+    } else {
+        const double scale = trA / fmax(trP, 1e-300);
+        double lo = log(1e-10 * scale), hi = log(1e10 * scale);
+        if (phi(exp(lo)) >= t2) {
+            lam = exp(lo);
+            flag = NLRMM_ST_DP_LOW;
+        } else if (phi(exp(hi)) <= t2) {
+            lam = exp(hi);
+            flag = NLRMM_ST_DP_HIGH;
+        } else {
+            // BLK-way parallel bracketing: each round shrinks the bracket by BLK + 1
+            for (int round = 0; round < 12; ++round) {
+                const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(BLK + 1);
+                const int above = phi(exp(x)) >= t2;
+                if (tid == 0) sfirst = BLK;
+                __syncthreads();
+                if (above) atomicMin(&sfirst, tid);
+                __syncthreads();
+                const int k = sfirst;
+                const double nlo = (k == 0) ? lo : lo + (hi - lo) * (double)k / (double)(BLK + 1);
+                const double nhi = (k == BLK) ? hi : lo + (hi - lo) * (double)(k + 1) / (double)(BLK + 1);
+                __syncthreads();
+                lo = nlo;
+                hi = nhi;
+                if (hi - lo <= 4e-16 * fmax(1.0, fabs(lo))) break;
+            }
+            lam = exp(0.5 * (lo + hi));
+        }
+    }
+    // y = U diag(1/(1 + lam gam)) beta, then z = L^-T y with L refactored into K's storage
+    for (int i = tid; i < n; i += BLK) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s += A[i * ld + k] * (be[k] / (1.0 + lam * ga[k]));
+        yv[i] = s;
+    }
+    __syncthreads();
+    for (int t = tid; t < n * n; t += BLK) {
+        const int i = t / n, j = t % n;
+        K[i * ld + j] = GA[i * ldg + j];
+    }
+    __syncthreads();
+    chol_lower(K, n, ld, &sbad);
+    trsv_lower_T(K, ld, yv, n);
+    for (int i = tid; i < n; i += BLK) z[i] = yv[i];
+    if (tid == 0) {
+        out[0] = lam;
+        out[1] = phi(lam);
+        int st = flag;
+        if (sbad) st |= NLRMM_ST_NONFINITE;
+        if (!isfinite(lam) || !isfinite(out[1])) st |= NLRMM_ST_NONFINITE;
+        if (st) atomicOr(status, st);
+    }
+}
+
+// Compression (Alg. "compress"): S = GA + lam GP = H^T H with H = [RA; sqrt(lam) RP];
+// W = eigenvectors of the kmin-1 largest eigenvalues of S (= dominant right singular
+// vectors of H), sign rule: largest-magnitude entry positive.  c = z - W W^T z; if
+// ||c|| > 1e-12 ||z|| the transform is T = [W, c/||c||] and z' = [W^T z; ||c||], else
+// T = W, z' = W^T z and the status bit is set.  Writes T (ell x kmin, row stride ldt),
+// z' (zout) and knew (out_k[0]).
+__global__ __launch_bounds__(BLK) void compress_eig_k(const double *__restrict__ GA,
+                                                      const double *__restrict__ GP, int ldg,
+                                                      const double *__restrict__ lamp, int ell,
+                                                      int kmin, const double *__restrict__ zin,
+                                                      double *__restrict__ T, int ldt,
+                                                      double *__restrict__ zout,
+                                                      int *__restrict__ out_k,
+                                                      int *__restrict__ status)
+{
+    extern __shared__ double sm[];
+    const int n = ell, ld = ell + 1;
+    double *S = sm;
+    double *U = S + n * ld;
+    double *sc = U + n * ld;     // 128
+    double *zz = sc + 128;       // n
+    double *wz = zz + n;         // kmin
+    double *cc = wz + kmin;      // n
+    __shared__ int spair[64];
+    __shared__ int order[64];
+    const int tid = threadIdx.x;
+    const double lam = lamp[0];
+    for (int t = tid; t < n * n; t += BLK) {
+        const int i = t / n, j = t % n;
+        S[i * ld + j] = GA[i * ldg + j] + lam * GP[i * ldg + j];
+    }
+    for (int i = tid; i < n; i += BLK) zz[i] = zin[i];
+    __syncthreads();
+    for (int t = tid; t < n * n; t += BLK) {
+        const int i = t / n, j = t % n;
+        if (i < j) {
+            const double a = 0.5 * (S[i * ld + j] + S[j * ld + i]);
+            S[i * ld + j] = a;
+            S[j * ld + i] = a;
+        }
+    }
+    __syncthreads();
+    jacobi_eig(S, U, n, ld, sc, spair);
+    // order eigenvalues descending (rank sort; ties by index)
+    for (int i = tid; i < n; i += BLK) {
+        const double ei = S[i * ld + i];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const double ej = S[j * ld + j];
+            if (ej > ei || (ej == ei && j < i)) ++rank;
+        }
+        order[rank] = i;
+    }
+    __syncthreads();
+    const int kw = kmin - 1;
+    // sign rule and W^T z
+    for (int a = tid; a < kw; a += BLK) {
+        const int col = order[a];
+        int jm = 0;
+        double vm = -1.0;
+        for (int i = 0; i < n; ++i) {
+            const double v = fabs(U[i * ld + col]);
+            if (v > vm) {
+                vm = v;
+                jm = i;
+            }
+        }
+        const double sg = U[jm * ld + col] < 0.0 ? -1.0 : 1.0;
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double v = sg * U[i * ld + col];
+            T[i * ldt + a] = v;
+            s += v * zz[i];
+        }
+        wz[a] = s;
+    }
+    __syncthreads();
+    // c = z - W (W^T z)
+    for (int i = tid; i < n; i += BLK) {
+        double s = zz[i];
+        for (int a = 0; a < kw; ++a) s -= T[i * ldt + a] * wz[a];
+        cc[i] = s;
+    }
+    __syncthreads();
+    double cn = 0.0, zn = 0.0;
+    for (int i = 0; i < n; ++i) {
+        cn += cc[i] * cc[i];
+        zn += zz[i] * zz[i];
+    }
+    cn = sqrt(cn);
+    zn = sqrt(zn);
+    const bool keep = cn > 1e-12 * zn;
+    if (keep) {
+        for (int i = tid; i < n; i += BLK) T[i * ldt + kw] = cc[i] / cn;
+    } else {
+        for (int i = tid; i < n; i += BLK) T[i * ldt + kw] = 0.0;
+    }
+    for (int a = tid; a < kw; a += BLK) zout[a] = wz[a];
+    if (tid == 0) {
+        if (keep) zout[kw] = cn;
+        out_k[0] = keep ? kmin : kw;
+        if (!keep) atomicOr(status, NLRMM_ST_COMPRESS_SKIP);
+    }
+}
+
+// G' = T^T G T (ell -> k), applied to a Gram after compression; rb' = T^T rb.
+__global__ __launch_bounds__(BLK) void gram_transform_k(double *__restrict__ G, int ldg,
+                                                        double *__restrict__ rb, int ell,
+                                                        const double *__restrict__ T, int ldt,
+                                                        const int *__restrict__ kp)
+{
+    extern __shared__ double sm[];
+    const int k = kp[0];
+    double *GT = sm;            // ell x k : G T
+    double *rr = GT + ell * 16; // k
+    const int tid = threadIdx.x;
+    for (int t = tid; t < ell * k; t += BLK) {
+        const int i = t / k, j = t % k;
+        double s = 0.0;
+        for (int m = 0; m < ell; ++m) s += G[i * ldg + m] * T[m * ldt + j];
+        GT[i * 16 + j] = s;
+    }
+    for (int j = tid; j < k; j += BLK) {
+        double s = 0.0;
+        for (int m = 0; m < ell; ++m) s += T[m * ldt + j] * rb[m];
+        rr[j] = s;
+    }
+    __syncthreads();
+    for (int t = tid; t < k * k; t += BLK) {
+        const int i = t / k, j = t % k;
+        double s = 0.0;
+        for (int m = 0; m < ell; ++m) s += T[m * ldt + i] * GT[m * 16 + j];
+        G[i * ldg + j] = s;   // rows/cols beyond k are stale and never read
+    }
+    __syncthreads();
+    for (int j = tid; j < k; j += BLK) rb[j] = rr[j];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static unsigned grid_for(int64_t n, int per = BLK, int64_t cap = 4096)
+{
+    int64_t g = (n + per - 1) / per;
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+int k_psi_weights(const float *u, int nx, int ny, int F, int temporal, float eps, float *w,
+                  hipStream_t s)
+{
+    const int64_t n = (int64_t)nx * ny * F;
+    psi_weights_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(u, nx, ny, F, temporal, eps, w);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_psi_apply(const float *u, int nx, int ny, int F, int temporal, float *out, hipStream_t s)
+{
+    const int64_t n = (int64_t)nx * ny * F;
+    psi_apply_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(u, nx, ny, F, temporal, out);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_tv_grad_add(const float *u, const float *w, int nx, int ny, int F, int temporal,
+                  const double *lamp, float *r, hipStream_t s)
+{
+    const int64_t n = (int64_t)nx * ny * F;
+    tv_grad_add_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(u, w, nx, ny, F, temporal, lamp, r);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int ny, int F,
+               int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s)
+{
+    if (ell > GMAX) return NLRMM_ESHAPE;
+    gram_psi_k<<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal, part);
+    reduce_gram_k<<<(unsigned)((ell * ell + 255) / 256), 256, 0, s>>>(part, nblk, ell, G, ldg);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_multidot(const float *X, int64_t ldx, int nv, const float *y, const float *z, int64_t n,
+               double *part, int nblk, double *out, int ostride, hipStream_t s)
+{
+    const int nout = nv + (z ? 1 : 0);
+    if (nout > MD_MAX) return NLRMM_ESHAPE;
+    multidot_k<<<(unsigned)nblk, BLK, 0, s>>>(X, ldx, nv, y, z, n, part);
+    reduce_vec_k<<<1, 128, 0, s>>>(part, nblk, nout, out, ostride);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_gemv(const float *X, int64_t ldx, int nv, const double *c, double beta, const float *a,
+           double alpha, int64_t n, float *out, hipStream_t s)
+{
+    if (nv > MD_MAX) return NLRMM_ESHAPE;
+    gemv_k<<<grid_for(n), BLK, 0, s>>>(X, ldx, nv, c, beta, a, alpha, n, out);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_block_update(const float *X, int64_t ldx, int nin, const double *T, int ldt, int kout,
+                   int64_t n, float *Y, int64_t ldy, hipStream_t s)
+{
+    if (nin > MD_MAX || kout > 16) return NLRMM_ESHAPE;
+    block_update_k<<<grid_for(n), BLK, 0, s>>>(X, ldx, nin, T, ldt, kout, n, Y, ldy);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_copy_cols(const float *src, int64_t lds, float *dst, int64_t ldd, int ncols, int64_t n,
+                hipStream_t s)
+{
+    const int64_t t = n * ncols;
+    copy_cols_k<<<(unsigned)((t + 255) / 256), 256, 0, s>>>(src, lds, dst, ldd, ncols, n);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_normalize_into(const float *r, const double *scal, double tol, int64_t n, float *vout,
+                     int *status, double *norm_out, hipStream_t s)
+{
+    normalize_into_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(r, scal, tol, n, vout, status,
+                                                                 norm_out);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_gks_solve(const double *GA, const double *GP, int ldg, const double *rb, const double *scal,
+                int ell, double lam_fix, double *z, double *out, int *status, hipStream_t s)
+{
+    if (ell < 1 || ell > SOLVE_MAX) return NLRMM_ESHAPE;
+    const size_t sh = sizeof(double) * (2 * (size_t)ell * (ell + 1) + 4 * ell + 128);
+    gks_solve_k<<<1, BLK, sh, s>>>(GA, GP, ldg, rb, scal, ell, lam_fix, z, out, status);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_compress_eig(const double *GA, const double *GP, int ldg, const double *lam, int ell,
+                   int kmin, const double *z, double *T, int ldt, double *zout, int *kout,
+                   int *status, hipStream_t s)
+{
+    if (ell < 1 || ell > SOLVE_MAX || kmin < 2 || kmin > 16 || kmin > ell) return NLRMM_ESHAPE;
+    const size_t sh = sizeof(double) * (2 * (size_t)ell * (ell + 1) + 128 + 2 * ell + kmin);
+    compress_eig_k<<<1, BLK, sh, s>>>(GA, GP, ldg, lam, ell, kmin, z, T, ldt, zout, kout, status);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_gram_transform(double *G, int ldg, double *rb, int ell, const double *T, int ldt,
+                     const int *kp, hipStream_t s)
+{
+    const size_t sh = sizeof(double) * ((size_t)ell * 16 + 16);
+    gram_transform_k<<<1, BLK, sh, s>>>(G, ldg, rb, ell, T, ldt, kp);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+}  // namespace nlrmm

@@ -252,8 +252,12 @@ struct FwdArgs {
     float *y;         // [col][V][nb] or null
     float *dy;        // [col][V][nb] or null
     const float *g;   // [V][nb] or null
-    double *part;     // [2][col][V][nchunks] (gdot, dnorm2 partials) or null
+    double *part;     // [3][col][V][nchunks] (gdot, dnorm2, rnorm2 partials) or null
     int64_t part_cols;  // total columns of the partials array
+    const float *bres;      // [V][nb]: residual mode, g := y - b (needs the projection)
+    const double *tdir;     // trial angles theta + alpha[0] * tdir (null: theta)
+    const double *talpha;
+    const int *skip;        // when *skip != 0 the launch does nothing
 };
 
 template <int MODE, int NC>
@@ -263,15 +267,17 @@ __global__ __launch_bounds__(BLK) void fwd_edges_k(FwdArgs a)
     constexpr bool MOM = (MODE & 2) != 0;
     __shared__ double sC[PROJ ? NC : 1][BLK];
     __shared__ double sM[MOM ? NC : 1][BLK];
-    __shared__ double sred[2][BLK / 64];
+    __shared__ double sred[3][BLK / 64];
 
+    if (a.skip != nullptr && *a.skip != 0) return;   // uniform over the launch
     const int tid = threadIdx.x;
     const int64_t v = blockIdx.x / a.nchunks;
     const int q = (int)(blockIdx.x - v * a.nchunks);
     const int c0 = blockIdx.y * NC;
     const int nc = min(NC, a.ncols - c0);
     const int f = frame_of(a.view_off, a.nframes, v);
-    const ViewC w = make_view(a.theta[v], a.d);
+    const double th = a.tdir != nullptr ? a.theta[v] + a.talpha[0] * a.tdir[v] : a.theta[v];
+    const ViewC w = make_view(th, a.d);
     const int64_t j = (int64_t)q * BINS + tid;
 
     const bool steep = w.steep != 0;
@@ -383,37 +389,48 @@ __global__ __launch_bounds__(BLK) void fwd_edges_k(FwdArgs a)
     const int64_t jb = (int64_t)q * BINS + tid;
     const bool has_bin = tid < BINS && jb < a.nb;
     const double inv_ds = 1.0 / a.ds;
-    const float gv = (a.g != nullptr && has_bin) ? a.g[v * a.nb + jb] : 0.0f;
+    const float gv_in = (a.g != nullptr && has_bin) ? a.g[v * a.nb + jb] : 0.0f;
+    const float bv = (a.bres != nullptr && has_bin) ? a.bres[v * a.nb + jb] : 0.0f;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         if (c >= nc) break;
         const int64_t col = a.col_out0 + c0 + c;
         const int64_t o = (col * a.V + v) * a.nb + jb;
-        double Dv = 0.0;
+        double yv = 0.0, Dv = 0.0;
         if (has_bin) {
-            if (PROJ && a.y) a.y[o] = (float)((sC[c][tid + 1] - sC[c][tid]) * inv_ds);
+            if (PROJ) {
+                yv = (sC[c][tid + 1] - sC[c][tid]) * inv_ds;
+                if (a.y) a.y[o] = (float)yv;
+            }
             if (MOM) {
                 Dv = (sM[c][tid] - sM[c][tid + 1]) * inv_ds;
                 if (a.dy) a.dy[o] = (float)Dv;
             }
         }
-        if (MOM && a.part != nullptr) {
-            double sg = wave_sum(Dv * (double)gv);
-            double sh = wave_sum(Dv * Dv);
+        if (a.part != nullptr) {
+            const double rv = (a.bres != nullptr && has_bin) ? yv - (double)bv : 0.0;
+            const double gv = a.bres != nullptr ? rv : (double)gv_in;
+            const double sg = wave_sum(Dv * gv);
+            const double sh = wave_sum(Dv * Dv);
+            const double sr = wave_sum(rv * rv);
             if ((tid & 63) == 0) {
                 sred[0][tid >> 6] = sg;
                 sred[1][tid >> 6] = sh;
+                sred[2][tid >> 6] = sr;
             }
             __syncthreads();
             if (tid == 0) {
-                double tg = 0.0, th = 0.0;
+                double tg = 0.0, th2 = 0.0, tr = 0.0;
                 for (int wv = 0; wv < BLK / 64; ++wv) {
                     tg += sred[0][wv];
-                    th += sred[1][wv];
+                    th2 += sred[1][wv];
+                    tr += sred[2][wv];
                 }
                 const int64_t po = (col * a.V + v) * a.nchunks + q;
+                const int64_t ps = a.part_cols * a.V * a.nchunks;
                 a.part[po] = tg;
-                a.part[a.part_cols * a.V * a.nchunks + po] = th;
+                a.part[ps + po] = th2;
+                a.part[2 * ps + po] = tr;
             }
             __syncthreads();
         }
@@ -421,17 +438,22 @@ __global__ __launch_bounds__(BLK) void fwd_edges_k(FwdArgs a)
 }
 
 __global__ void finalize_parts_k(const double *__restrict__ part, int64_t ncols, int64_t V,
-                                 int nchunks, double *gdot, double *dnorm2)
+                                 int nchunks, double *gdot, double *dnorm2, double *rnorm2,
+                                 const int *skip)
 {
+    if (skip != nullptr && *skip != 0) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ncols * V) return;
-    double sg = 0.0, sh = 0.0;
+    const int64_t ps = ncols * V * nchunks;
+    double sg = 0.0, sh = 0.0, sr = 0.0;
     for (int q = 0; q < nchunks; ++q) {
         sg += part[i * nchunks + q];
-        sh += part[ncols * V * nchunks + i * nchunks + q];
+        sh += part[ps + i * nchunks + q];
+        sr += part[2 * ps + i * nchunks + q];
     }
     if (gdot) gdot[i] = sg;
     if (dnorm2) dnorm2[i] = sh;
+    if (rnorm2) rnorm2[i] = sr;
 }
 
 // ---------------------------------------------------------------------------
@@ -571,20 +593,36 @@ int launch_project(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, in
                    const float *x, const double *theta, float *y, float *dy, const float *gres,
                    double *gdot, double *dnorm2, hipStream_t s)
 {
+    FwdOptions o;
+    o.y = y;
+    o.dy = dy;
+    o.g = gres;
+    o.gdot = gdot;
+    o.dnorm2 = dnorm2;
+    return launch_project_ex(ctx, g, b, ncols, x, theta, o, s);
+}
+
+int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
+                      const float *x, const double *theta, const FwdOptions &o, hipStream_t s)
+{
     if (g.nx > MAX_LINE || g.ny > MAX_LINE) return NLRMM_ESHAPE;
     const int F = b.nframes;
     const int64_t V = b.nviews;
     const int nchunks = (g.nbins + BINS - 1) / BINS;
-    const bool mom = dy || gdot || dnorm2;
-    const bool proj = y != nullptr;
-    const bool red = gdot || dnorm2;
+    const bool mom = o.dy || o.gdot || o.dnorm2;
+    const bool proj = o.y != nullptr || o.bres != nullptr;
+    const bool red = o.gdot || o.dnorm2 || o.rnorm2;
+    if (o.bres && !proj) return NLRMM_ENOTSUP;
     const int GC = 8;                       // columns prepared per group
     const int gcols = ncols < GC ? ncols : GC;
-    const size_t need = fwd_ws_bytes(g, F, gcols, V, nchunks, red ? ncols : 0);
+    size_t need = fwd_ws_bytes(g, F, gcols, V, nchunks, 0);
+    const size_t part_bytes = red ? sizeof(double) * 3 * (size_t)ncols * V * nchunks : 0;
+    double *part = o.part_buf;
+    if (red && part == nullptr) need += part_bytes + 256;
     int rc = ensure_workspace(ctx, need, s);
     if (rc) return rc;
     const int64_t nx = g.nx, ny = g.ny;
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     char *p = (char *)ctx->ws.ptr;
     float *xT = (float *)p;
     p += al(sizeof(float) * (int64_t)gcols * F * nx * ny);
@@ -598,7 +636,7 @@ int launch_project(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, in
     p += al(sizeof(double) * (int64_t)gcols * F * (ny + 1));
     double *colpre = (double *)p;
     p += al(sizeof(double) * (int64_t)gcols * F * (nx + 1));
-    double *part = red ? (double *)p : nullptr;
+    if (red && part == nullptr) part = (double *)p;
 
     const int64_t npix = nx * ny;
     for (int cbeg = 0; cbeg < ncols; cbeg += gcols) {
@@ -636,24 +674,37 @@ int launch_project(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, in
         a.ncols = nc;
         a.col_out0 = cbeg;
         a.nchunks = nchunks;
-        a.y = y;
-        a.dy = dy;
-        a.g = gres;
-        a.part = part;
+        a.y = o.y;
+        a.dy = o.dy;
+        a.g = o.g;
+        a.part = red ? part : nullptr;
         a.part_cols = ncols;
+        a.bres = o.bres;
+        a.tdir = o.tdir;
+        a.talpha = o.talpha;
+        a.skip = o.skip;
         const int NC = nc >= 8 ? 8 : nc >= 4 ? 4 : nc >= 2 ? 2 : 1;
         dim3 grid((unsigned)(V * nchunks), (unsigned)((nc + NC - 1) / NC));
         if (proj && mom) launch_fwd_mode<3>(NC, grid, a, s);
         else if (mom) launch_fwd_mode<2>(NC, grid, a, s);
         else launch_fwd_mode<1>(NC, grid, a, s);
     }
-    if (red) {
+    if (red && (o.gdot || o.dnorm2 || o.rnorm2) && !o.keep_parts) {
         const int64_t n = (int64_t)ncols * V;
         finalize_parts_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(part, ncols, V, nchunks,
-                                                                     gdot, dnorm2);
+                                                                     o.gdot, o.dnorm2, o.rnorm2,
+                                                                     o.skip);
     }
     NLRMM_HIP_CHECK(hipGetLastError());
     return NLRMM_OK;
+}
+
+int fwd_chunks(const nlrmm_geom &g) { return (g.nbins + BINS - 1) / BINS; }
+
+size_t fwd_workspace_bytes(const nlrmm_geom &g, int nframes, int ncols)
+{
+    const int gcols = ncols < 8 ? ncols : 8;
+    return fwd_ws_bytes(g, nframes, gcols, 1, 1, 0);
 }
 
 int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,

@@ -1,0 +1,557 @@
+// Native driver of NL-RMM-GKS on one device stream (Alg. "nl_rmmgks_two_solves" with the
+// high-regularisation solve off, Alg. "rmmgks" with one Enlarge/Compress cycle per outer
+// iteration, Alg. "update_param" for the angles).  Every decision (lambda, breakdown,
+// compression size, Armijo step) is taken by device kernels; the host only sequences
+// launches, so an outer iteration can be captured in a HIP graph and replayed.
+//
+// Basis storage: V [kmax+1][n] and A V [kmax+1][m] column-contiguous FP32; Psi V is not
+// stored (the weighted regulariser Gram recomputes Psi v from V on the fly).  Small
+// projected quantities (Grams, coefficients, lambda) live on the device in FP64.
+#include "internal.h"
+#include "krylov.h"
+
+#include <math.h>
+#include <new>
+#include <vector>
+
+namespace nlrmm {
+
+enum {
+    S_BNORM2 = 0,   // ||b||^2
+    S_TARGET = 1,   // tau * delta
+    S_LAM = 2,      // lambda of the last projected solve
+    S_RES2 = 3,     // model residual ||AVz - b||^2 of the last solve
+    S_GN = 8,       // [f0, g^T d, alpha, mu, f_accepted] of the last Gauss-Newton step
+    S_NB = 16,      // scalars
+};
+
+struct Solver {
+    nlrmm_ctx *ctx = nullptr;
+    nlrmm_geom g{};
+    int F = 1;
+    int64_t maxV = 0;
+    nlrmm_solver_cfg cfg{};
+    int64_t n = 0, npsi = 0, mmax = 0;
+    int kcap = 0;   // kmax + 1 columns
+    int ld = 0;     // Gram leading dimension
+    int ell = 0;    // current number of basis columns (host bookkeeping)
+    int md_blocks = 512, gram_blocks = 256, nchunks = 1;
+    // device buffers
+    float *V = nullptr, *AV = nullptr, *Vtmp = nullptr, *u = nullptr, *r = nullptr,
+          *rho = nullptr, *w = nullptr;
+    double *GA = nullptr, *GP = nullptr, *rb = nullptr, *z = nullptr, *T = nullptr,
+           *zt = nullptr, *sc = nullptr, *hb = nullptr, *hb2 = nullptr, *gv = nullptr,
+           *hv = nullptr, *rv = nullptr, *dir = nullptr, *alphas = nullptr, *thk = nullptr,
+           *part_md = nullptr, *part_gram = nullptr, *part_fwd = nullptr, *gkb = nullptr;
+    int *status = nullptr, *kout = nullptr, *accepted = nullptr;
+    std::vector<void *> allocs;
+
+    template <typename T_>
+    int alloc(T_ **p, size_t count)
+    {
+        void *q = nullptr;
+        if (hipMalloc(&q, sizeof(T_) * (count ? count : 1)) != hipSuccess) {
+            (void)hipGetLastError();
+            return NLRMM_ENOMEM;
+        }
+        allocs.push_back(q);
+        *p = (T_ *)q;
+        return NLRMM_OK;
+    }
+    ~Solver()
+    {
+        if (!allocs.empty()) (void)hipDeviceSynchronize();
+        for (void *p : allocs) (void)hipFree(p);
+    }
+};
+
+}  // namespace nlrmm
+
+struct nlrmm_solver : nlrmm::Solver {};
+
+namespace nlrmm {
+
+#define RC(x)                      \
+    do {                           \
+        int _rc = (x);             \
+        if (_rc) return _rc;       \
+    } while (0)
+
+static int64_t m_of(const Solver &S, const nlrmm_batch &b) { return b.nviews * S.g.nbins; }
+
+// G_A = (AV)^T AV and rb = (AV)^T b for the first ell columns, plus ||b||^2.
+static int gram_from_scratch(Solver &S, int ell, int64_t m, const float *b, hipStream_t s)
+{
+    for (int j = 0; j < ell; ++j)
+        RC(k_multidot(S.AV, m, j + 1, S.AV + (int64_t)j * m, nullptr, m, S.part_md, S.md_blocks,
+                      S.GA + j, S.ld, s));
+    RC(k_symmetrize(S.GA, S.ld, ell, s));
+    RC(k_multidot(S.AV, m, ell, b, b, m, S.part_md, S.md_blocks, S.hb, 1, s));
+    // hb = [rb (ell), ||b||^2]
+    RC(k_copy_f64(S.hb, S.rb, ell, s));
+    RC(k_copy_f64(S.hb + ell, S.sc + S_BNORM2, 1, s));
+    return NLRMM_OK;
+}
+
+// r <- r - V V^T r twice (CGS2) against the first ell columns; hb[ell] = ||r_in||^2,
+// hb[ell+1] = ||r_out||^2; then V[:, ell] = r_out / ||r_out|| with the breakdown test.
+static int cgs2_append(Solver &S, int ell, hipStream_t s)
+{
+    RC(k_multidot(S.V, S.n, ell, S.r, S.r, S.n, S.part_md, S.md_blocks, S.hb, 1, s));
+    RC(k_gemv(S.V, S.n, ell, S.hb, -1.0, S.r, 1.0, S.n, S.r, s));
+    RC(k_multidot(S.V, S.n, ell, S.r, nullptr, S.n, S.part_md, S.md_blocks, S.hb2, 1, s));
+    RC(k_gemv(S.V, S.n, ell, S.hb2, -1.0, S.r, 1.0, S.n, S.r, s));
+    RC(k_multidot(S.V, S.n, 0, S.r, S.r, S.n, S.part_md, S.md_blocks, S.hb + ell + 1, 1, s));
+    RC(k_normalize_into(S.r, S.hb + ell, S.cfg.breakdown_tol, S.n, S.V + (int64_t)ell * S.n,
+                        S.status, nullptr, s));
+    return NLRMM_OK;
+}
+
+// r = A^T (A V z - b) + lam Psi^T (w * Psi u), with u = V z already in S.u.
+static int mm_residual(Solver &S, const nlrmm_batch &b, const double *theta, int ell,
+                       const float *bvec, hipStream_t s)
+{
+    const int64_t m = m_of(S, b);
+    RC(k_gemv(S.AV, m, ell, S.z, 1.0, bvec, -1.0, m, S.rho, s));
+    RC(launch_backproject(S.ctx, S.g, b, 1, S.rho, theta, S.r, s));
+    RC(k_tv_grad_add(S.u, S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.sc + S_LAM, S.r, s));
+    return NLRMM_OK;
+}
+
+// Append one GKS direction (Alg. "enlarge" body after u = V z): residual, CGS2, A v and the
+// new row of the data Gram.
+static int expand(Solver &S, const nlrmm_batch &b, const double *theta, const float *bvec,
+                  hipStream_t s)
+{
+    const int ell = S.ell;
+    const int64_t m = m_of(S, b);
+    RC(mm_residual(S, b, theta, ell, bvec, s));
+    RC(cgs2_append(S, ell, s));
+    RC(launch_project(S.ctx, S.g, b, 1, S.V + (int64_t)ell * S.n, theta, S.AV + (int64_t)ell * m,
+                      nullptr, nullptr, nullptr, nullptr, s));
+    RC(k_multidot(S.AV, m, ell + 1, S.AV + (int64_t)ell * m, bvec, m, S.part_md, S.md_blocks,
+                  S.hb2, 1, s));
+    RC(k_scatter_gram(S.hb2, ell, S.GA, S.ld, S.rb, s));
+    S.ell = ell + 1;
+    return NLRMM_OK;
+}
+
+// One projected solve on the current basis: weights from u, weighted regulariser Gram,
+// lambda and z, then u = V z.
+static int projected_solve(Solver &S, hipStream_t s)
+{
+    RC(k_psi_weights(S.u, S.g.nx, S.g.ny, S.F, S.cfg.temporal, (float)S.cfg.eps, S.w, s));
+    RC(k_gram_psi(S.V, S.n, S.ell, S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.part_gram,
+                  S.gram_blocks, S.GP, S.ld, s));
+    RC(k_gks_solve(S.GA, S.GP, S.ld, S.rb, S.sc + S_BNORM2, S.ell, S.cfg.lam_fix, S.z,
+                   S.sc + S_LAM, S.status, s));
+    RC(k_gemv(S.V, S.n, S.ell, S.z, 1.0, nullptr, 0.0, S.n, S.u, s));
+    return NLRMM_OK;
+}
+
+// Alg. "compress": basis -> kmin columns, A V transformed alongside, z -> z'.
+static int compress(Solver &S, const nlrmm_batch &b, hipStream_t s)
+{
+    const int kmin = S.cfg.kmin;
+    const int64_t m = m_of(S, b);
+    RC(k_compress_eig(S.GA, S.GP, S.ld, S.sc + S_LAM, S.ell, kmin, S.z, S.T, kmin, S.zt,
+                      S.kout, S.status, s));
+    RC(k_block_update(S.V, S.n, S.ell, S.T, kmin, kmin, S.n, S.Vtmp, S.n, s));
+    RC(k_copy_cols(S.Vtmp, S.n, S.V, S.n, kmin, S.n, s));
+    RC(k_block_update(S.AV, m, S.ell, S.T, kmin, kmin, m, S.Vtmp, m, s));
+    RC(k_copy_cols(S.Vtmp, m, S.AV, m, kmin, m, s));
+    RC(k_gram_transform(S.GA, S.ld, S.rb, S.ell, S.T, kmin, S.kout, s));
+    RC(k_copy_f64(S.zt, S.z, kmin, s));
+    S.ell = kmin;
+    RC(k_gemv(S.V, S.n, kmin, S.z, 1.0, nullptr, 0.0, S.n, S.u, s));
+    return NLRMM_OK;
+}
+
+// Alg. "update_param" with u fixed: damped Gauss-Newton, Armijo on one global alpha.
+static int gn_update(Solver &S, const nlrmm_batch &b, double *theta, const float *bvec,
+                     hipStream_t s)
+{
+    const int64_t V = b.nviews;
+    const int nch = fwd_chunks(S.g);
+    for (int it = 0; it < S.cfg.maxiter_p; ++it) {
+        FwdOptions o;
+        o.bres = bvec;
+        o.gdot = S.gv;
+        o.dnorm2 = S.hv;
+        o.rnorm2 = S.rv;
+        o.part_buf = S.part_fwd;
+        RC(launch_project_ex(S.ctx, S.g, b, 1, S.u, theta, o, s));
+        RC(k_gn_prepare(S.gv, S.hv, S.rv, V, S.cfg.param_mode, S.cfg.mu_rel, S.dir, S.sc + S_GN,
+                        S.accepted, s));
+        for (int q = 0; q < S.cfg.armijo_trials; ++q) {
+            FwdOptions t;
+            t.bres = bvec;
+            t.rnorm2 = S.rv;   // not finalised (keep_parts); partials are summed directly
+            t.part_buf = S.part_fwd;
+            t.keep_parts = true;
+            t.tdir = S.dir;
+            t.talpha = S.alphas + q;
+            t.skip = S.accepted;
+            RC(launch_project_ex(S.ctx, S.g, b, 1, S.u, theta, t, s));
+            RC(k_armijo_check(S.part_fwd + 2 * V * nch, V * nch, S.alphas, q, S.cfg.c1,
+                              S.sc + S_GN, S.accepted, s));
+        }
+        RC(k_gn_apply(theta, S.dir, V, S.sc + S_GN, S.accepted, S.status, s));
+    }
+    return NLRMM_OK;
+}
+
+static int solver_outer(Solver &S, const nlrmm_batch &b, double *theta, const float *bvec,
+                        double delta, hipStream_t s)
+{
+    const int64_t V = b.nviews;
+    const int64_t m = m_of(S, b);
+    if (V > S.maxV) return NLRMM_ESHAPE;
+    // theta_k: the operator H_k of this outer iteration
+    RC(k_copy_f64(theta, S.thk, V, s));
+    RC(k_fill_f64(S.sc + S_TARGET, 1, S.cfg.tau * delta, s));
+    // rebase A V on the current views and angles
+    RC(launch_project(S.ctx, S.g, b, S.ell, S.V, S.thk, S.AV, nullptr, nullptr, nullptr,
+                      nullptr, s));
+    RC(gram_from_scratch(S, S.ell, m, bvec, s));
+    const int nsolve = S.cfg.solves;
+    for (int t = 0; t < nsolve; ++t) {
+        RC(projected_solve(S, s));
+        if (t < nsolve - 1) RC(expand(S, b, S.thk, bvec, s));
+    }
+    RC(compress(S, b, s));
+    if (S.cfg.param_update == 1) RC(gn_update(S, b, theta, bvec, s));
+    // weights from u_{k+1}; residual with the old operator H_k; project out; append
+    RC(k_psi_weights(S.u, S.g.nx, S.g.ny, S.F, S.cfg.temporal, (float)S.cfg.eps, S.w, s));
+    RC(mm_residual(S, b, S.thk, S.ell, bvec, s));
+    RC(cgs2_append(S, S.ell, s));
+    S.ell += 1;
+    (void)m;
+    return NLRMM_OK;
+}
+
+// Golub-Kahan bidiagonalisation from b (k right vectors, CGS2 on both sides); u = 0.
+static int solver_init(Solver &S, const nlrmm_batch &b, const double *theta, const float *bvec,
+                       hipStream_t s)
+{
+    const int k = S.cfg.kmin + 1;
+    const int64_t m = m_of(S, b);
+    if (b.nviews > S.maxV) return NLRMM_ESHAPE;
+    float *U = S.AV;   // left vectors stored where A V lives later
+    double *nrm = S.gkb;   // [0..k) alpha_i, [k..2k) beta_i
+    RC(k_fill_i32(S.status, 1, 0, s));
+    RC(k_fill_f64(S.z, S.kcap, 0.0, s));
+    // u_1 = b / ||b||
+    RC(k_multidot(S.V, S.n, 0, bvec, bvec, m, S.part_md, S.md_blocks, S.hb, 1, s));
+    RC(k_scale_into(bvec, S.hb, m, U, nrm + k, S.status, s));
+    for (int i = 0; i < k; ++i) {
+        // v = A^T u_i - beta_i v_{i-1}, reorthogonalised against V, normalised
+        RC(launch_backproject(S.ctx, S.g, b, 1, U + (int64_t)i * m, theta, S.r, s));
+        if (i > 0)
+            RC(k_gemv(S.V + (int64_t)(i - 1) * S.n, S.n, 1, nrm + k + i, -1.0, S.r, 1.0, S.n,
+                      S.r, s));
+        if (i > 0) {
+            RC(k_multidot(S.V, S.n, i, S.r, nullptr, S.n, S.part_md, S.md_blocks, S.hb, 1, s));
+            RC(k_gemv(S.V, S.n, i, S.hb, -1.0, S.r, 1.0, S.n, S.r, s));
+            RC(k_multidot(S.V, S.n, i, S.r, nullptr, S.n, S.part_md, S.md_blocks, S.hb, 1, s));
+            RC(k_gemv(S.V, S.n, i, S.hb, -1.0, S.r, 1.0, S.n, S.r, s));
+        }
+        RC(k_multidot(S.V, S.n, 0, S.r, S.r, S.n, S.part_md, S.md_blocks, S.hb, 1, s));
+        RC(k_scale_into(S.r, S.hb, S.n, S.V + (int64_t)i * S.n, nrm + i, S.status, s));
+        if (i == k - 1) break;
+        // p = A v_i - alpha_i u_i, reorthogonalised against U, normalised
+        RC(launch_project(S.ctx, S.g, b, 1, S.V + (int64_t)i * S.n, theta, S.rho, nullptr,
+                          nullptr, nullptr, nullptr, s));
+        RC(k_gemv(U + (int64_t)i * m, m, 1, nrm + i, -1.0, S.rho, 1.0, m, S.rho, s));
+        RC(k_multidot(U, m, i + 1, S.rho, nullptr, m, S.part_md, S.md_blocks, S.hb, 1, s));
+        RC(k_gemv(U, m, i + 1, S.hb, -1.0, S.rho, 1.0, m, S.rho, s));
+        RC(k_multidot(U, m, i + 1, S.rho, nullptr, m, S.part_md, S.md_blocks, S.hb, 1, s));
+        RC(k_gemv(U, m, i + 1, S.hb, -1.0, S.rho, 1.0, m, S.rho, s));
+        RC(k_multidot(U, m, 0, S.rho, S.rho, m, S.part_md, S.md_blocks, S.hb, 1, s));
+        RC(k_scale_into(S.rho, S.hb, m, U + (int64_t)(i + 1) * m, nrm + k + i + 1, S.status, s));
+    }
+    S.ell = k;
+    RC(k_gemv(S.V, S.n, 1, S.z, 0.0, nullptr, 0.0, S.n, S.u, s));   // u = 0
+    return NLRMM_OK;
+}
+
+}  // namespace nlrmm
+
+using namespace nlrmm;
+
+extern "C" {
+
+int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
+                        int64_t max_views, const nlrmm_solver_cfg *cfg, nlrmm_solver **out)
+{
+    if (!ctx || !geom || !cfg || !out) return NLRMM_EINVAL;
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if (nframes < 1 || max_views < 1) return NLRMM_ESHAPE;
+    nlrmm_solver_cfg c = *cfg;
+    if (c.kmin < 2 || c.kmin > 16 || c.kmax <= c.kmin || c.kmax > 55) return NLRMM_ESHAPE;
+    if (c.solves <= 0) c.solves = c.kmax - c.kmin;
+    if (c.kmin + c.solves > c.kmax + 1 || c.solves < 1) return NLRMM_ESHAPE;
+    if (c.armijo_trials < 0 || c.armijo_trials > 32 || c.maxiter_p < 0) return NLRMM_EINVAL;
+    if (!(c.eps > 0.0) || !(c.tau > 0.0)) return NLRMM_EINVAL;
+    if (c.param_update < 0 || c.param_update > 1) return NLRMM_ENOTSUP;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    nlrmm_solver *S = new (std::nothrow) nlrmm_solver();
+    if (!S) return NLRMM_ENOMEM;
+    S->ctx = ctx;
+    S->g = *geom;
+    S->F = nframes;
+    S->maxV = max_views;
+    S->cfg = c;
+    S->n = (int64_t)nframes * geom->nx * geom->ny;
+    S->mmax = max_views * geom->nbins;
+    S->kcap = c.kmax + 1;
+    S->ld = S->kcap;
+    S->nchunks = fwd_chunks(*geom);
+    const int64_t big = S->n > S->mmax ? S->n : S->mmax;
+    const int64_t npsi_max = (int64_t)nframes * 2 * geom->nx * geom->ny + (int64_t)nframes * geom->nx * geom->ny;
+    if ((rc = S->alloc(&S->V, (size_t)S->kcap * S->n)) ||
+        (rc = S->alloc(&S->AV, (size_t)S->kcap * S->mmax)) ||
+        (rc = S->alloc(&S->Vtmp, (size_t)c.kmin * big)) || (rc = S->alloc(&S->u, S->n)) ||
+        (rc = S->alloc(&S->r, S->n)) || (rc = S->alloc(&S->rho, S->mmax)) ||
+        (rc = S->alloc(&S->w, npsi_max)) || (rc = S->alloc(&S->GA, S->ld * S->ld)) ||
+        (rc = S->alloc(&S->GP, S->ld * S->ld)) || (rc = S->alloc(&S->rb, S->ld)) ||
+        (rc = S->alloc(&S->z, S->ld)) || (rc = S->alloc(&S->T, S->ld * c.kmin)) ||
+        (rc = S->alloc(&S->zt, S->ld)) || (rc = S->alloc(&S->sc, S_NB)) ||
+        (rc = S->alloc(&S->hb, S->ld + 4)) || (rc = S->alloc(&S->hb2, S->ld + 4)) ||
+        (rc = S->alloc(&S->gv, max_views)) || (rc = S->alloc(&S->hv, max_views)) ||
+        (rc = S->alloc(&S->rv, max_views)) || (rc = S->alloc(&S->dir, max_views)) ||
+        (rc = S->alloc(&S->alphas, 32)) || (rc = S->alloc(&S->thk, max_views)) ||
+        (rc = S->alloc(&S->part_md, (size_t)S->md_blocks * 72)) ||
+        (rc = S->alloc(&S->part_gram, (size_t)S->gram_blocks * 64 * 64)) ||
+        (rc = S->alloc(&S->part_fwd, (size_t)3 * max_views * S->nchunks)) ||
+        (rc = S->alloc(&S->gkb, 2 * (size_t)S->kcap + 2)) || (rc = S->alloc(&S->status, 1)) ||
+        (rc = S->alloc(&S->kout, 1)) || (rc = S->alloc(&S->accepted, 1))) {
+        delete S;
+        return rc;
+    }
+    double al[32];
+    for (int q = 0; q < 32; ++q) al[q] = c.alpha0 * pow(c.beta, q);
+    if (hipMemcpy(S->alphas, al, sizeof(al), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(S->sc, 0, sizeof(double) * S_NB) != hipSuccess ||
+        hipMemset(S->status, 0, sizeof(int)) != hipSuccess ||
+        hipMemset(S->GA, 0, sizeof(double) * S->ld * S->ld) != hipSuccess ||
+        hipMemset(S->GP, 0, sizeof(double) * S->ld * S->ld) != hipSuccess) {
+        delete S;
+        return NLRMM_EHIP;
+    }
+    // size the projector workspace for the widest call (rebase of kmin+1 columns)
+    rc = ensure_workspace(ctx, fwd_workspace_bytes(*geom, nframes, c.kmin + 1), nullptr);
+    if (rc) {
+        delete S;
+        return rc;
+    }
+    *out = S;
+    return NLRMM_OK;
+}
+
+void nlrmm_solver_destroy(nlrmm_solver *S) { delete S; }
+
+int nlrmm_solver_init(nlrmm_solver *S, const nlrmm_batch *batch, const double *theta,
+                      const float *b, void *stream)
+{
+    if (!S || !theta || !b) return NLRMM_EINVAL;
+    int rc = check_batch(batch);
+    if (rc) return rc;
+    if (batch->nframes != S->F) return NLRMM_ESHAPE;
+    return solver_init(*S, *batch, theta, b, (hipStream_t)stream);
+}
+
+int nlrmm_solver_outer(nlrmm_solver *S, const nlrmm_batch *batch, double *theta, const float *b,
+                       double delta, void *stream)
+{
+    if (!S || !theta || !b) return NLRMM_EINVAL;
+    if (!(delta >= 0.0)) return NLRMM_EINVAL;
+    int rc = check_batch(batch);
+    if (rc) return rc;
+    if (batch->nframes != S->F) return NLRMM_ESHAPE;
+    if (S->ell != S->cfg.kmin + 1) return NLRMM_EINVAL;   // not initialised
+    return solver_outer(*S, *batch, theta, b, delta, (hipStream_t)stream);
+}
+
+int nlrmm_solver_state(nlrmm_solver *S, float **u, float **V, double **scal, int32_t **status,
+                       int32_t *ell)
+{
+    if (!S) return NLRMM_EINVAL;
+    if (u) *u = S->u;
+    if (V) *V = S->V;
+    if (scal) *scal = S->sc;
+    if (status) *status = S->status;
+    if (ell) *ell = S->ell;
+    return NLRMM_OK;
+}
+
+int nlrmm_solver_read(nlrmm_solver *S, float *u_out, double *scal_out, int32_t *status_out,
+                      void *stream)
+{
+    if (!S) return NLRMM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (u_out &&
+        hipMemcpyAsync(u_out, S->u, sizeof(float) * S->n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return NLRMM_EHIP;
+    if (scal_out && hipMemcpyAsync(scal_out, S->sc, sizeof(double) * S_NB,
+                                   hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return NLRMM_EHIP;
+    if (status_out && hipMemcpyAsync(status_out, S->status, sizeof(int32_t),
+                                     hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return NLRMM_EHIP;
+    return NLRMM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// standalone Krylov entry points (scratch from the context's Krylov workspace)
+// ---------------------------------------------------------------------------
+namespace nlrmm {
+
+// Carve a non-owning Solver view with scratch in ctx->kws.
+static int scratch_view(nlrmm_ctx *ctx, Solver &S, int64_t n, int64_t m, int kcap, int kmin,
+                        hipStream_t s)
+{
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const int64_t big = n > m ? n : m;
+    const size_t bytes = al(sizeof(float) * n) * 2 + al(sizeof(float) * m) +
+                         al(sizeof(float) * (size_t)kmin * big) +
+                         al(sizeof(double) * (size_t)S.md_blocks * 72) +
+                         al(sizeof(double) * (size_t)S.gram_blocks * 64 * 64) +
+                         al(sizeof(double) * (kcap + 4)) * 2 + al(sizeof(double) * kcap * 16) +
+                         al(sizeof(double) * (kcap + 4)) + al(sizeof(int) * 4) + 4096;
+    int rc = ensure_buffer(ctx->kws, bytes, s);
+    if (rc) return rc;
+    char *p = (char *)ctx->kws.ptr;
+    auto take = [&](size_t b) {
+        char *q = p;
+        p += al(b);
+        return (void *)q;
+    };
+    S.u = (float *)take(sizeof(float) * n);
+    S.r = (float *)take(sizeof(float) * n);
+    S.rho = (float *)take(sizeof(float) * m);
+    S.Vtmp = (float *)take(sizeof(float) * (size_t)kmin * big);
+    S.part_md = (double *)take(sizeof(double) * (size_t)S.md_blocks * 72);
+    S.part_gram = (double *)take(sizeof(double) * (size_t)S.gram_blocks * 64 * 64);
+    S.hb = (double *)take(sizeof(double) * (kcap + 4));
+    S.hb2 = (double *)take(sizeof(double) * (kcap + 4));
+    S.T = (double *)take(sizeof(double) * kcap * 16);
+    S.zt = (double *)take(sizeof(double) * (kcap + 4));
+    S.kout = (int *)take(sizeof(int) * 4);
+    S.ctx = ctx;
+    S.n = n;
+    return NLRMM_OK;
+}
+
+}  // namespace nlrmm
+
+extern "C" {
+
+int nlrmm_tv_weights(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, int32_t temporal,
+                     const float *u, double eps, float *w, void *stream)
+{
+    if (!ctx || !u || !w || !(eps > 0.0)) return NLRMM_EINVAL;
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if (nframes < 1) return NLRMM_ESHAPE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    return k_psi_weights(u, geom->nx, geom->ny, nframes, temporal, (float)eps, w,
+                         (hipStream_t)stream);
+}
+
+int nlrmm_gram_psi(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, int32_t temporal,
+                   int32_t ell, const float *V, const float *w, double *G, int32_t ldg,
+                   void *stream)
+{
+    if (!ctx || !V || !w || !G) return NLRMM_EINVAL;
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if (nframes < 1 || ell < 1 || ell > 64 || ldg < ell) return NLRMM_ESHAPE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    Solver S;
+    const int64_t n = (int64_t)nframes * geom->nx * geom->ny;
+    if ((rc = scratch_view(ctx, S, n, 1, ell + 1, 2, (hipStream_t)stream))) return rc;
+    return k_gram_psi(V, n, ell, w, geom->nx, geom->ny, nframes, temporal, S.part_gram,
+                      S.gram_blocks, G, ldg, (hipStream_t)stream);
+}
+
+int nlrmm_gks_solve(nlrmm_ctx *ctx, int32_t ell, const double *GA, const double *GP,
+                    int32_t ldg, const double *rb, const double *scal, double lam_fix, double *z,
+                    double *out, int32_t *status, void *stream)
+{
+    if (!ctx || !GA || !GP || !rb || !scal || !z || !out || !status) return NLRMM_EINVAL;
+    if (ell < 1 || ell > 56 || ldg < ell) return NLRMM_ESHAPE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    return k_gks_solve(GA, GP, ldg, rb, scal, ell, lam_fix, z, out, status, (hipStream_t)stream);
+}
+
+int nlrmm_gks_expand(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                     const double *theta, int32_t ell, int32_t temporal, float *V, float *AV,
+                     const double *z, const float *b, const float *w, const double *lambda,
+                     double *GA, int32_t ldg, double *rb, double breakdown_tol,
+                     int32_t *status, void *stream)
+{
+    if (!ctx || !theta || !V || !AV || !z || !b || !w || !lambda || !GA || !rb || !status)
+        return NLRMM_EINVAL;
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if ((rc = check_batch(batch))) return rc;
+    if (ell < 1 || ell > 55 || ldg < ell + 1) return NLRMM_ESHAPE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    hipStream_t s = (hipStream_t)stream;
+    Solver S;
+    const int64_t n = (int64_t)batch->nframes * geom->nx * geom->ny;
+    const int64_t m = batch->nviews * geom->nbins;
+    if ((rc = scratch_view(ctx, S, n, m, ell + 2, 2, s))) return rc;
+    S.g = *geom;
+    S.F = batch->nframes;
+    S.cfg.temporal = temporal;
+    S.cfg.breakdown_tol = breakdown_tol;
+    S.V = V;
+    S.AV = AV;
+    S.GA = GA;
+    S.ld = ldg;
+    S.rb = rb;
+    S.w = w ? const_cast<float *>(w) : nullptr;
+    S.status = status;
+    S.ell = ell;
+    // z and lambda are read through the solver's scalar slots: point them at the caller's
+    S.z = const_cast<double *>(z);
+    S.sc = const_cast<double *>(lambda) - S_LAM;
+    if ((rc = k_gemv(V, n, ell, z, 1.0, nullptr, 0.0, n, S.u, s))) return rc;
+    return expand(S, *batch, theta, b, s);
+}
+
+int nlrmm_recycle_compress(nlrmm_ctx *ctx, int64_t n, int64_t m, int32_t ell, int32_t kmin,
+                           float *V, float *AV, double *GA, const double *GP, int32_t ldg,
+                           double *rb, const double *lambda, double *z, int32_t *status,
+                           void *stream)
+{
+    if (!ctx || !V || !AV || !GA || !GP || !rb || !lambda || !z || !status) return NLRMM_EINVAL;
+    if (n < 1 || m < 1 || kmin < 2 || kmin > 16 || ell < kmin || ell > 56 || ldg < ell)
+        return NLRMM_ESHAPE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    hipStream_t s = (hipStream_t)stream;
+    Solver S;
+    int rc = scratch_view(ctx, S, n, m, ell + 2, kmin, s);
+    if (rc) return rc;
+    S.V = V;
+    S.AV = AV;
+    S.GA = GA;
+    S.GP = const_cast<double *>(GP);
+    S.ld = ldg;
+    S.rb = rb;
+    S.z = z;
+    S.sc = const_cast<double *>(lambda) - S_LAM;
+    S.status = status;
+    S.ell = ell;
+    S.cfg.kmin = kmin;
+    nlrmm_batch b{1, m, nullptr};
+    S.g.nbins = 1;   // m_of(S, b) = nviews * nbins = m
+    return compress(S, b, s);
+}
+
+}  // extern "C"

@@ -139,3 +139,79 @@ def project_dtheta(x: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None, *
         if t is not None:
             res[k] = t
     return res
+
+
+# ---------------------------------------------------------------------------
+# Krylov primitives
+# ---------------------------------------------------------------------------
+def _p(t):
+    return None if t is None else t.data_ptr()
+
+
+def tv_weights(u: torch.Tensor, g: Geom, nframes: int = 1, temporal: bool = False,
+               eps: float = 1e-3, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """w = ((Psi u)^2 + eps^2)^(-1/2) over the anisotropic TV differences."""
+    _need(u, torch.float32, "u")
+    npsi = nframes * (g.ny * (g.nx - 1) + (g.ny - 1) * g.nx)
+    if temporal and nframes > 1:
+        npsi += (nframes - 1) * g.nx * g.ny
+    if out is None:
+        out = torch.empty(npsi, dtype=torch.float32, device=u.device)
+    check(_lib.lib().nlrmm_tv_weights(context(u.device.index or 0), ctypes.byref(g), nframes,
+                                      int(temporal), u.data_ptr(), eps, out.data_ptr(),
+                                      _stream(u.device)), "nlrmm_tv_weights")
+    return out
+
+
+def gram_psi(V: torch.Tensor, w: torch.Tensor, g: Geom, ell: int, nframes: int = 1,
+             temporal: bool = False) -> torch.Tensor:
+    """(Psi V)^T diag(w) (Psi V) for the first ell columns of V ([>=ell, n] float32)."""
+    _need(V, torch.float32, "V")
+    G = torch.empty((ell, ell), dtype=torch.float64, device=V.device)
+    check(_lib.lib().nlrmm_gram_psi(context(V.device.index or 0), ctypes.byref(g), nframes,
+                                    int(temporal), ell, V.data_ptr(), w.data_ptr(), G.data_ptr(),
+                                    ell, _stream(V.device)), "nlrmm_gram_psi")
+    return G
+
+
+def gks_solve(GA, GP, rb, scal, ell, lam_fix=-1.0, status=None):
+    """Projected solve with the discrepancy principle; returns (z [ell], out [2], status)."""
+    dev = GA.device
+    z = torch.empty(ell, dtype=torch.float64, device=dev)
+    out = torch.empty(2, dtype=torch.float64, device=dev)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+    check(_lib.lib().nlrmm_gks_solve(context(dev.index or 0), ell, GA.data_ptr(), GP.data_ptr(),
+                                     GA.shape[1], rb.data_ptr(), scal.data_ptr(), lam_fix,
+                                     z.data_ptr(), out.data_ptr(), status.data_ptr(),
+                                     _stream(dev)), "nlrmm_gks_solve")
+    return z, out, status
+
+
+def gks_expand(V, AV, z, b, w, lam, GA, rb, theta, g: Geom, ell: int, frames=None,
+               temporal=False, breakdown_tol=1e-10, status=None):
+    """Append GKS direction ell to V / AV and extend GA, rb in place (see nlrmm_gks_expand)."""
+    dev = V.device
+    bt = _batch(frames, theta.numel())
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+    check(_lib.lib().nlrmm_gks_expand(context(dev.index or 0), ctypes.byref(g), ctypes.byref(bt),
+                                      theta.data_ptr(), ell, int(temporal), V.data_ptr(),
+                                      AV.data_ptr(), z.data_ptr(), b.data_ptr(), w.data_ptr(),
+                                      lam.data_ptr(), GA.data_ptr(), GA.shape[1], rb.data_ptr(),
+                                      breakdown_tol, status.data_ptr(), _stream(dev)),
+          "nlrmm_gks_expand")
+    return status
+
+
+def recycle_compress(V, AV, GA, GP, rb, lam, z, ell: int, kmin: int, status=None):
+    """Compress the basis to kmin columns in place (see nlrmm_recycle_compress)."""
+    dev = V.device
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+    check(_lib.lib().nlrmm_recycle_compress(context(dev.index or 0), V.shape[1], AV.shape[1], ell,
+                                            kmin, V.data_ptr(), AV.data_ptr(), GA.data_ptr(),
+                                            GP.data_ptr(), GA.shape[1], rb.data_ptr(),
+                                            lam.data_ptr(), z.data_ptr(), status.data_ptr(),
+                                            _stream(dev)), "nlrmm_recycle_compress")
+    return status

@@ -1,0 +1,89 @@
+"""Python handle of the native NL-RMM-GKS driver (nlrmm_solver_* in the C ABI).
+
+The outer iteration (rebase, Enlarge, Compress, Gauss-Newton angles, residual append)
+runs entirely in the library on the current torch stream; this class only owns the
+handle and marshals tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import torch
+
+from . import _lib, ops
+from ._lib import SolverCfg, check
+
+
+@dataclasses.dataclass
+class Config:
+    kmin: int = 5
+    kmax: int = 30
+    solves: int = 0              # <= 0: kmax - kmin
+    eps: float = 1e-3
+    tau: float = 1.01
+    lam_fix: float = -1.0        # < 0: discrepancy principle
+    param_update: int = 1        # 0 none, 1 Gauss-Newton (AltMin)
+    param_mode: int = 0          # 0 per-view, 1 global shift
+    maxiter_p: int = 1
+    mu_rel: float = 1e-6
+    c1: float = 1e-4
+    beta: float = 0.5
+    alpha0: float = 1.0
+    armijo_trials: int = 10
+    breakdown_tol: float = 1e-10
+    temporal: int = 0
+
+    def struct(self) -> SolverCfg:
+        return SolverCfg(**dataclasses.asdict(self))
+
+
+class Solver:
+    def __init__(self, g: ops.Geom, nframes: int, max_views: int, cfg: Config, device: int = 0):
+        self.g = g
+        self.nframes = nframes
+        self.cfg = cfg
+        self.device = torch.device("cuda", device)
+        self.n = nframes * g.nx * g.ny
+        h = ctypes.c_void_p()
+        c = cfg.struct()
+        check(_lib.lib().nlrmm_solver_create(ops.context(device), ctypes.byref(g), nframes,
+                                             max_views, ctypes.byref(c), ctypes.byref(h)),
+              "nlrmm_solver_create")
+        self.h = h.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            torch.cuda.synchronize(self.device)
+            _lib.lib().nlrmm_solver_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def init(self, theta: torch.Tensor, b: torch.Tensor, frames=None) -> None:
+        bt = ops._batch(frames, theta.numel())
+        check(_lib.lib().nlrmm_solver_init(self.h, ctypes.byref(bt), theta.data_ptr(),
+                                           b.data_ptr(), self._stream()), "nlrmm_solver_init")
+
+    def outer(self, theta: torch.Tensor, b: torch.Tensor, delta: float, frames=None) -> None:
+        """One outer iteration; theta (float64, device) is updated in place."""
+        bt = ops._batch(frames, theta.numel())
+        check(_lib.lib().nlrmm_solver_outer(self.h, ctypes.byref(bt), theta.data_ptr(),
+                                            b.data_ptr(), float(delta), self._stream()),
+              "nlrmm_solver_outer")
+
+    def read(self):
+        """(u [n] float32, scalars [16] float64, status [1] int32) as new device tensors."""
+        u = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        sc = torch.empty(16, dtype=torch.float64, device=self.device)
+        st = torch.empty(1, dtype=torch.int32, device=self.device)
+        check(_lib.lib().nlrmm_solver_read(self.h, u.data_ptr(), sc.data_ptr(), st.data_ptr(),
+                                           self._stream()), "nlrmm_solver_read")
+        return u, sc, st

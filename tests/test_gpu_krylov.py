@@ -1,0 +1,208 @@
+"""GPU parity of the Krylov-side entry points and of the NL-RMM-GKS outer loop against the
+FP64 oracle.  Bars: primitives on identical FP64 inputs to ~1e-9; the loop after a fixed
+number of outer iterations: ||u_gpu - u_ora|| / ||u_ora|| <= 1e-3, max |theta diff| <= 1e-4 rad."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import method as M  # noqa: E402
+from oracle import projector as P  # noqa: E402
+from paper_2605_06336_amd import ops, synth  # noqa: E402
+from paper_2605_06336_amd.solver import Config, Solver  # noqa: E402
+
+
+def dev(a, dt):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt).cuda()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def small(N=48, nb=69, V=40, seed=0, F=1, temporal=False):
+    rng = np.random.default_rng(seed)
+    if F == 1:
+        vo = np.array([0, V], dtype=np.int64)
+    else:
+        vo = np.concatenate([[0], np.cumsum(rng.integers(5, 12, F))]).astype(np.int64)
+    geo = M.Geometry(N=N, nb=nb, view_off=vo, temporal=temporal)
+    x = synth.ellipse_image(N, [0.1, -0.3], [0.0, 0.2], [0.5, 0.2], [0.3, 0.25], [0.3, 1.0],
+                            [1.0, 0.5])
+    x = np.stack([np.roll(x, 2 * f, axis=1) for f in range(geo.F)])
+    th = rng.uniform(0, math.pi, geo.V)
+    return geo, x.reshape(-1), th, rng
+
+
+@pytest.mark.parametrize("F,temporal", [(1, 0), (3, 1)])
+def test_tv_weights_and_gram(F, temporal):
+    geo, x, th, rng = small(N=40, nb=59, F=F, temporal=bool(temporal))
+    g = ops.geom(geo.N, geo.nb)
+    u = (x + 0.05 * rng.standard_normal(x.size)).astype(np.float32)
+    w = ops.tv_weights(dev(u, torch.float32), g, geo.F, bool(temporal), eps=1e-2).cpu().numpy()
+    w_ref = M.weights(geo, u.astype(np.float64), 1e-2)
+    assert w.shape == w_ref.shape
+    assert rel(w, w_ref) <= 1e-6
+    ell = 13
+    V = rng.standard_normal((ell, geo.n)).astype(np.float32)
+    G = ops.gram_psi(dev(V, torch.float32), dev(w, torch.float32), g, ell, geo.F,
+                     bool(temporal)).cpu().numpy()
+    PV = M.psi_cols(geo, V.T.astype(np.float64))
+    G_ref = PV.T @ (w.astype(np.float64)[:, None] * PV)
+    assert rel(G, G_ref) <= 1e-12
+
+
+@pytest.mark.parametrize("ell,noise,lam_fix", [(6, 0.01, -1.0), (20, 0.05, -1.0), (33, 0.01, -1.0),
+                                               (12, 0.01, 0.37)])
+def test_gks_solve_matches_oracle(ell, noise, lam_fix):
+    geo, x, th, rng = small()
+    b, e = M.make_data(geo, x, th, rng.standard_normal(geo.m), noise)
+    V = M.gkb_basis(geo, th, b, min(ell, 8))
+    if ell > V.shape[1]:
+        V, _ = np.linalg.qr(np.column_stack([V, rng.standard_normal((geo.n, ell - V.shape[1]))]))
+    AV = M.A_cols(geo, th, V)
+    PV = M.psi_cols(geo, V)
+    w = M.weights(geo, x + 0.02 * rng.standard_normal(geo.n), 1e-3)
+    st = M.State(V=V, AV=AV, PV=PV, u=np.zeros(geo.n), theta=th)
+    target = 1.01 * np.linalg.norm(e)
+    cfg = M.Config(lam_fix=None if lam_fix < 0 else lam_fix)
+    z_ref, lam_ref, _, _, flag_ref = M.projected_solve(st, b, w, cfg, target)
+    GA = AV.T @ AV
+    GP = PV.T @ (w[:, None] * PV)
+    rb = AV.T @ b
+    scal = np.array([b @ b, target])
+    z, out, status = ops.gks_solve(dev(GA, torch.float64), dev(GP, torch.float64),
+                                   dev(rb, torch.float64), dev(scal, torch.float64), ell, lam_fix)
+    z = z.cpu().numpy()
+    lam = out.cpu().numpy()[0]
+    assert int(status.cpu()[0]) == flag_ref
+    assert abs(lam - lam_ref) <= 1e-8 * lam_ref
+    assert rel(V @ z, V @ z_ref) <= 1e-7
+    if lam_fix < 0 and flag_ref == 0:
+        res = np.linalg.norm(AV @ z - b)
+        assert abs(res - target) <= 1e-8 * target
+
+
+def test_gks_expand_and_compress_match_oracle():
+    geo, x, th, rng = small(N=40, nb=59, V=30)
+    g = ops.geom(geo.N, geo.nb)
+    b, e = M.make_data(geo, x, th, rng.standard_normal(geo.m), 0.01)
+    b32 = b.astype(np.float32)
+    ell, kmax, kmin = 6, 12, 4
+    V = M.gkb_basis(geo, th, b32.astype(np.float64), ell)
+    V32 = V.astype(np.float32)
+    Vd = torch.zeros((kmax, geo.n), dtype=torch.float32, device="cuda")
+    Vd[:ell] = dev(V32.T, torch.float32)
+    AVd = torch.zeros((kmax, geo.m), dtype=torch.float32, device="cuda")
+    tht = dev(th, torch.float64)
+    AVd[:ell] = ops.project(Vd[:ell].contiguous().view(ell, 1, geo.N, geo.N), tht, g).view(ell, -1)
+    V64 = Vd[:ell].cpu().numpy().astype(np.float64).T
+    AV64 = AVd[:ell].cpu().numpy().astype(np.float64).T
+    GA = np.zeros((kmax, kmax))
+    GA[:ell, :ell] = AV64.T @ AV64
+    rb = np.zeros(kmax)
+    rb[:ell] = AV64.T @ b32.astype(np.float64)
+    z = rng.standard_normal(ell) * 0.1
+    u = (V64 @ z).astype(np.float32)
+    w = M.weights(geo, u.astype(np.float64), 1e-3).astype(np.float32)
+    lam = 0.02
+    GAd, rbd = dev(GA, torch.float64), dev(rb, torch.float64)
+    lamd = dev(np.array([lam]), torch.float64)
+    status = ops.gks_expand(Vd, AVd, dev(z, torch.float64), dev(b32, torch.float32),
+                            dev(w, torch.float32), lamd, GAd, rbd, tht, g, ell)
+    torch.cuda.synchronize()
+    # oracle: residual from the same FP32 basis, CGS2, normalise
+    st = M.State(V=V64, AV=AV64, PV=M.psi_cols(geo, V64), u=V64 @ z, theta=th)
+    r = M.mm_residual(geo, th, st, b32.astype(np.float64), w.astype(np.float64), lam, z)
+    v_ref = M.cgs2(V64, r)
+    v_ref /= np.linalg.norm(v_ref)
+    v = Vd[ell].cpu().numpy().astype(np.float64)
+    assert int(status.cpu()[0]) == 0
+    assert rel(v, v_ref) <= 2e-5
+    Av = AVd[ell].cpu().numpy().astype(np.float64)
+    assert rel(Av, M.A(geo, th, v)) <= 1e-5
+    GAn = GAd.cpu().numpy()
+    AVn = AVd[:ell + 1].cpu().numpy().astype(np.float64).T
+    assert rel(GAn[:ell + 1, :ell + 1], AVn.T @ AVn) <= 1e-12
+    assert abs(rbd.cpu().numpy()[ell] - AVn[:, ell] @ b32.astype(np.float64)) <= 1e-10 * np.abs(rb).max()
+    # compress the (ell+1)-column basis to kmin with a DP-free lambda and a GP from weights
+    ell1 = ell + 1
+    PV = M.psi_cols(geo, Vd[:ell1].cpu().numpy().astype(np.float64).T)
+    GP = PV.T @ (w.astype(np.float64)[:, None] * PV)
+    GPf = np.zeros((kmax, kmax))
+    GPf[:ell1, :ell1] = GP
+    z1 = np.concatenate([z, [0.05]])
+    V_before = Vd[:ell1].cpu().numpy().astype(np.float64).T
+    u_before = V_before @ z1
+    zd = torch.zeros(kmax, dtype=torch.float64, device="cuda")
+    zd[:ell1] = dev(z1, torch.float64)
+    st2 = ops.recycle_compress(Vd, AVd, GAd, dev(GPf, torch.float64), rbd, lamd, zd, ell1, kmin)
+    torch.cuda.synchronize()
+    Vn = Vd[:kmin].cpu().numpy().astype(np.float64).T
+    zn = zd[:kmin].cpu().numpy()
+    assert int(st2.cpu()[0]) == 0
+    assert np.linalg.norm(Vn.T @ Vn - np.eye(kmin)) <= 1e-5
+    assert rel(Vn @ zn, u_before) <= 1e-5
+    # oracle compress on the same inputs (RA, RP from the Grams' Cholesky factors)
+    RA = np.linalg.cholesky(AVn.T @ AVn).T
+    RP = np.linalg.cholesky(GP).T
+    ost = M.State(V=V_before, AV=AVn, PV=PV, u=u_before, theta=th)
+    Vold = ost.V.copy()
+    M.compress(ost, RA, RP, lam, z1, kmin)
+    s = np.linalg.svd(ost.V.T @ Vn, compute_uv=False)
+    assert np.min(s) > 1 - 1e-5
+    assert rel(zn, ost.z) <= 1e-5
+    assert rel(AVd[:kmin].cpu().numpy().astype(np.float64).T, AVn @ (Vold.T @ Vn)) <= 1e-5
+
+
+def run_pair(key, N=None, outer=None, kmax=None, trace=False):
+    wl = synth.WORKLOADS[key]
+    inst = synth.draw(wl, N=N)
+    N = inst.x_true.shape[-1]
+    outer = outer or wl.outer
+    kmax = kmax or wl.kmax
+    geo = M.Geometry(N=N, nb=wl.nb, view_off=inst.view_off)
+    x64 = inst.x_true.reshape(-1)
+    b_ora, e_ora = M.make_data(geo, x64, inst.theta_true, inst.g, wl.noise)
+    cfg = M.Config(kmin=wl.kmin, kmax=kmax, eps=wl.eps)
+    # GPU data: own projector, same noise direction
+    g = ops.geom(N, wl.nb)
+    x32 = inst.x_true.astype(np.float32)
+    bex = ops.project(dev(x32, torch.float32), dev(inst.theta_true, torch.float64),
+                      g).cpu().numpy().reshape(-1).astype(np.float64)
+    e = wl.noise * np.linalg.norm(bex) * inst.g / np.linalg.norm(inst.g)
+    b_gpu = dev((bex + e).astype(np.float32), torch.float32)
+    th = dev(inst.theta_nom, torch.float64)
+    sol = Solver(g, 1, geo.V, Config(kmin=wl.kmin, kmax=kmax, eps=wl.eps))
+    sol.init(th, b_gpu)
+    ora_log = []
+    st = M.init_state(geo, inst.theta_nom, b_ora, cfg)
+    out = []
+    for k in range(outer):
+        M.outer_step(geo, st, b_ora, np.linalg.norm(e_ora), cfg)
+        sol.outer(th, b_gpu, float(np.linalg.norm(e)))
+        if trace or k == outer - 1:
+            u, sc, status = sol.read()
+            u = u.cpu().numpy().astype(np.float64)
+            du = rel(u, st.u)
+            dth = float(np.max(np.abs(th.cpu().numpy() - st.theta)))
+            lam = float(sc.cpu().numpy()[2])
+            out.append((k, du, dth, lam, st.lam, int(status.cpu()[0]), st.status))
+            print(f"outer {k}: u rel diff {du:.3e}  theta max diff {dth:.3e}  lam gpu {lam:.6e} "
+                  f"ora {st.lam:.6e} status {int(status.cpu()[0])}/{st.status}", flush=True)
+    sol.close()
+    rre_ora = np.linalg.norm(st.u - x64) / np.linalg.norm(x64)
+    return out, rre_ora
+
+
+def test_loop_parity_c1():
+    """64x64, 90 views, 91 bins, 20 outer iterations, basis cap 30 (the FP64 CPU workload)."""
+    out, rre = run_pair("c1", trace=True)
+    k, du, dth, *_ = out[-1]
+    print(f"c1 final: u rel diff {du:.3e}, theta max diff {dth:.3e} rad, oracle RRE {rre:.4f}")
+    assert du <= 1e-3
+    assert dth <= 1e-4
