@@ -59,6 +59,7 @@ int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
                       const float *x, const double *theta, const FwdOptions &o, hipStream_t s);
 int fwd_chunks(const nlrmm_geom &g);
 size_t fwd_workspace_bytes(const nlrmm_geom &g, int nframes, int ncols);
+size_t bwd_workspace_bytes(const nlrmm_geom &g, const nlrmm_batch &b, int ncols, int cu_count);
 int launch_project(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
                    const float *x, const double *theta, float *y, float *dy, const float *gres,
                    double *gdot, double *dnorm2, hipStream_t s);

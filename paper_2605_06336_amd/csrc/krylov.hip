@@ -16,7 +16,8 @@ namespace nlrmm {
 namespace {
 
 constexpr int BLK = 256;
-constexpr int SOLVE_MAX = 56;   // largest projected problem: two 56x57 FP64 matrices in LDS
+constexpr int SOLVE_MAX = 56;
+constexpr int SOLVE_NT = 256;   // threads of the single-workgroup projected solves   // largest projected problem: two 56x57 FP64 matrices in LDS
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
@@ -209,16 +210,19 @@ __global__ __launch_bounds__(BLK) void gram_psi_k(const float *__restrict__ V, i
     }
 }
 
-// Sum nblk partial ell x ell matrices into G (leading dimension ldg), fixed order.
-__global__ void reduce_gram_k(const double *__restrict__ part, int nblk, int ell,
-                              double *__restrict__ G, int ldg)
+// Sum nblk partial ell x ell matrices into G (leading dimension ldg): one wave per entry,
+// fixed summation order.
+__global__ __launch_bounds__(64) void reduce_gram_k(const double *__restrict__ part, int nblk,
+                                                    int ell, double *__restrict__ G, int ldg)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ell * ell) return;
+    const int t = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * ell * ell + t];
-    const int i = t / ell, j = t - i * ell;
-    G[i * ldg + j] = s;
+    for (int b = threadIdx.x; b < nblk; b += 64) s += part[(int64_t)b * ell * ell + t];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) {
+        const int i = t / ell, j = t - i * ell;
+        G[i * ldg + j] = s;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -264,15 +268,17 @@ __global__ __launch_bounds__(BLK) void multidot_k(const float *__restrict__ X, i
     }
 }
 
-// out[i * ostride] = sum_b part[b][i] (fixed order); optional scaling.
-__global__ void reduce_vec_k(const double *__restrict__ part, int nblk, int nout,
-                             double *__restrict__ out, int ostride)
+// out[i * ostride] = sum_b part[b][i]: one wave per output, lane-strided partial sums
+// and a fixed butterfly, so the result is independent of scheduling.
+__global__ __launch_bounds__(64) void reduce_vec_k(const double *__restrict__ part, int nblk,
+                                                   int nout, double *__restrict__ out,
+                                                   int ostride)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nout) return;
+    const int i = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * nout + i];
-    out[(int64_t)i * ostride] = s;
+    for (int b = threadIdx.x; b < nblk; b += 64) s += part[(int64_t)b * nout + i];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) out[(int64_t)i * ostride] = s;
 }
 
 // out[e] = alpha * a[e] + beta * sum_i X_i[e] c_i   (a may be null; c FP64 on the device)
@@ -429,9 +435,16 @@ __device__ void jacobi_eig(double *A, double *U, int n, int ld, double *sc, int 
     double *cs = sc;               // [npair] cos
     double *sn = sc + 32;          // [npair] sin
     __shared__ int srot;
+    __shared__ double sdmax;
     for (int sweep = 0; sweep < 40; ++sweep) {
-        if (tid == 0) srot = 0;
+        if (tid == 0) {
+            srot = 0;
+            double dm = 0.0;
+            for (int i = 0; i < n; ++i) dm = fmax(dm, fabs(A[i * ld + i]));
+            sdmax = dm;
+        }
         __syncthreads();
+        const double floor_abs = 1e-14 * sdmax;   // below the rounding noise of A
         for (int r = 0; r < np - 1; ++r) {
             if (tid < npair) {
                 int p, q;
@@ -451,7 +464,7 @@ __device__ void jacobi_eig(double *A, double *U, int n, int ld, double *sc, int 
                 if (q < n) {
                     const double apq = A[p * ld + q];
                     const double app = A[p * ld + p], aqq = A[q * ld + q];
-                    if (fabs(apq) > 1e-17 * sqrt(fabs(app * aqq)) && apq != 0.0) {
+                    if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) {
                         const double tau = (aqq - app) / (2.0 * apq);
                         const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         c = 1.0 / sqrt(1.0 + t * t);
@@ -508,7 +521,7 @@ __device__ void jacobi_eig(double *A, double *U, int n, int ld, double *sc, int 
 // lam by the discrepancy principle (residual = target) with a log-bracket
 // [1e-10, 1e10] * tr(GA)/tr(GP) and clamping to its ends, or lam = lam_fix >= 0.
 // Outputs: z[0..ell), out[0] = lam, out[1] = ||AVz - b||^2 (model), status bits.
-__global__ __launch_bounds__(BLK) void gks_solve_k(const double *__restrict__ GA,
+__global__ __launch_bounds__(SOLVE_NT) void gks_solve_k(const double *__restrict__ GA,
                                                    const double *__restrict__ GP, int ldg,
                                                    const double *__restrict__ rb,
                                                    const double *__restrict__ scal, int ell,
@@ -531,12 +544,12 @@ __global__ __launch_bounds__(BLK) void gks_solve_k(const double *__restrict__ GA
     __shared__ int sfirst;
     const int tid = threadIdx.x;
     if (tid == 0) sbad = 0;
-    for (int t = tid; t < n * n; t += BLK) {
+    for (int t = tid; t < n * n; t += SOLVE_NT) {
         const int i = t / n, j = t % n;
         A[i * ld + j] = GA[i * ldg + j];
         K[i * ld + j] = GP[i * ldg + j];
     }
-    for (int i = tid; i < n; i += BLK) c[i] = rb[i];
+    for (int i = tid; i < n; i += SOLVE_NT) c[i] = rb[i];
     __syncthreads();
     double trA = 0.0, trP = 0.0;
     for (int i = 0; i < n; ++i) {
@@ -546,7 +559,7 @@ __global__ __launch_bounds__(BLK) void gks_solve_k(const double *__restrict__ GA
     chol_lower(A, n, ld, &sbad);
     trsm_lower(A, ld, c, 1, n, 1);          // c = L^-1 rb
     trsm_lower(A, ld, K, ld, n, n);         // X = L^-1 GP
-    for (int t = tid; t < n * n; t += BLK) {
+    for (int t = tid; t < n * n; t += SOLVE_NT) {
         const int i = t / n, j = t % n;
         if (i < j) {
             const double a = K[i * ld + j];
@@ -556,7 +569,7 @@ __global__ __launch_bounds__(BLK) void gks_solve_k(const double *__restrict__ GA
     }
     __syncthreads();
     trsm_lower(A, ld, K, ld, n, n);         // K = L^-1 X^T = L^-1 GP L^-T
-    for (int t = tid; t < n * n; t += BLK) {
+    for (int t = tid; t < n * n; t += SOLVE_NT) {
         const int i = t / n, j = t % n;
         if (i < j) {
             const double a = 0.5 * (K[i * ld + j] + K[j * ld + i]);
@@ -566,7 +579,7 @@ __global__ __launch_bounds__(BLK) void gks_solve_k(const double *__restrict__ GA
     }
     __syncthreads();
     jacobi_eig(K, A, n, ld, sc, spair);     // A <- U (L is rebuilt below)
-    for (int i = tid; i < n; i += BLK) {
+    for (int i = tid; i < n; i += SOLVE_NT) {
         ga[i] = fmax(K[i * ld + i], 0.0);
         double s = 0.0;
         for (int k = 0; k < n; ++k) s += A[k * ld + i] * c[k];
@@ -600,17 +613,17 @@ __global__ __launch_bounds__(BLK) void gks_solve_k(const double *__restrict__ GA
             lam = exp(hi);
             flag = NLRMM_ST_DP_HIGH;
         } else {
-            // BLK-way parallel bracketing: each round shrinks the bracket by BLK + 1
+            // NT-way parallel bracketing: each round shrinks the bracket by NT + 1
             for (int round = 0; round < 12; ++round) {
-                const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(BLK + 1);
+                const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(SOLVE_NT + 1);
                 const int above = phi(exp(x)) >= t2;
-                if (tid == 0) sfirst = BLK;
+                if (tid == 0) sfirst = SOLVE_NT;
                 __syncthreads();
                 if (above) atomicMin(&sfirst, tid);
                 __syncthreads();
                 const int k = sfirst;
-                const double nlo = (k == 0) ? lo : lo + (hi - lo) * (double)k / (double)(BLK + 1);
-                const double nhi = (k == BLK) ? hi : lo + (hi - lo) * (double)(k + 1) / (double)(BLK + 1);
+                const double nlo = (k == 0) ? lo : lo + (hi - lo) * (double)k / (double)(SOLVE_NT + 1);
+                const double nhi = (k == SOLVE_NT) ? hi : lo + (hi - lo) * (double)(k + 1) / (double)(SOLVE_NT + 1);
                 __syncthreads();
                 lo = nlo;
                 hi = nhi;
@@ -620,20 +633,20 @@ __global__ __launch_bounds__(BLK) void gks_solve_k(const double *__restrict__ GA
         }
     }
     // y = U diag(1/(1 + lam gam)) beta, then z = L^-T y with L refactored into K's storage
-    for (int i = tid; i < n; i += BLK) {
+    for (int i = tid; i < n; i += SOLVE_NT) {
         double s = 0.0;
         for (int k = 0; k < n; ++k) s += A[i * ld + k] * (be[k] / (1.0 + lam * ga[k]));
         yv[i] = s;
     }
     __syncthreads();
-    for (int t = tid; t < n * n; t += BLK) {
+    for (int t = tid; t < n * n; t += SOLVE_NT) {
         const int i = t / n, j = t % n;
         K[i * ld + j] = GA[i * ldg + j];
     }
     __syncthreads();
     chol_lower(K, n, ld, &sbad);
     trsv_lower_T(K, ld, yv, n);
-    for (int i = tid; i < n; i += BLK) z[i] = yv[i];
+    for (int i = tid; i < n; i += SOLVE_NT) z[i] = yv[i];
     if (tid == 0) {
         out[0] = lam;
         out[1] = phi(lam);
@@ -650,7 +663,7 @@ __global__ __launch_bounds__(BLK) void gks_solve_k(const double *__restrict__ GA
 // ||c|| > 1e-12 ||z|| the transform is T = [W, c/||c||] and z' = [W^T z; ||c||], else
 // T = W, z' = W^T z and the status bit is set.  Writes T (ell x kmin, row stride ldt),
 // z' (zout) and knew (out_k[0]).
-__global__ __launch_bounds__(BLK) void compress_eig_k(const double *__restrict__ GA,
+__global__ __launch_bounds__(SOLVE_NT) void compress_eig_k(const double *__restrict__ GA,
                                                       const double *__restrict__ GP, int ldg,
                                                       const double *__restrict__ lamp, int ell,
                                                       int kmin, const double *__restrict__ zin,
@@ -671,13 +684,13 @@ __global__ __launch_bounds__(BLK) void compress_eig_k(const double *__restrict__
     __shared__ int order[64];
     const int tid = threadIdx.x;
     const double lam = lamp[0];
-    for (int t = tid; t < n * n; t += BLK) {
+    for (int t = tid; t < n * n; t += SOLVE_NT) {
         const int i = t / n, j = t % n;
         S[i * ld + j] = GA[i * ldg + j] + lam * GP[i * ldg + j];
     }
-    for (int i = tid; i < n; i += BLK) zz[i] = zin[i];
+    for (int i = tid; i < n; i += SOLVE_NT) zz[i] = zin[i];
     __syncthreads();
-    for (int t = tid; t < n * n; t += BLK) {
+    for (int t = tid; t < n * n; t += SOLVE_NT) {
         const int i = t / n, j = t % n;
         if (i < j) {
             const double a = 0.5 * (S[i * ld + j] + S[j * ld + i]);
@@ -688,7 +701,7 @@ __global__ __launch_bounds__(BLK) void compress_eig_k(const double *__restrict__
     __syncthreads();
     jacobi_eig(S, U, n, ld, sc, spair);
     // order eigenvalues descending (rank sort; ties by index)
-    for (int i = tid; i < n; i += BLK) {
+    for (int i = tid; i < n; i += SOLVE_NT) {
         const double ei = S[i * ld + i];
         int rank = 0;
         for (int j = 0; j < n; ++j) {
@@ -700,7 +713,7 @@ __global__ __launch_bounds__(BLK) void compress_eig_k(const double *__restrict__
     __syncthreads();
     const int kw = kmin - 1;
     // sign rule and W^T z
-    for (int a = tid; a < kw; a += BLK) {
+    for (int a = tid; a < kw; a += SOLVE_NT) {
         const int col = order[a];
         int jm = 0;
         double vm = -1.0;
@@ -722,7 +735,7 @@ __global__ __launch_bounds__(BLK) void compress_eig_k(const double *__restrict__
     }
     __syncthreads();
     // c = z - W (W^T z)
-    for (int i = tid; i < n; i += BLK) {
+    for (int i = tid; i < n; i += SOLVE_NT) {
         double s = zz[i];
         for (int a = 0; a < kw; ++a) s -= T[i * ldt + a] * wz[a];
         cc[i] = s;
@@ -737,11 +750,11 @@ __global__ __launch_bounds__(BLK) void compress_eig_k(const double *__restrict__
     zn = sqrt(zn);
     const bool keep = cn > 1e-12 * zn;
     if (keep) {
-        for (int i = tid; i < n; i += BLK) T[i * ldt + kw] = cc[i] / cn;
+        for (int i = tid; i < n; i += SOLVE_NT) T[i * ldt + kw] = cc[i] / cn;
     } else {
-        for (int i = tid; i < n; i += BLK) T[i * ldt + kw] = 0.0;
+        for (int i = tid; i < n; i += SOLVE_NT) T[i * ldt + kw] = 0.0;
     }
-    for (int a = tid; a < kw; a += BLK) zout[a] = wz[a];
+    for (int a = tid; a < kw; a += SOLVE_NT) zout[a] = wz[a];
     if (tid == 0) {
         if (keep) zout[kw] = cn;
         out_k[0] = keep ? kmin : kw;
@@ -823,7 +836,7 @@ int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int
 {
     if (ell > GMAX) return NLRMM_ESHAPE;
     gram_psi_k<<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal, part);
-    reduce_gram_k<<<(unsigned)((ell * ell + 255) / 256), 256, 0, s>>>(part, nblk, ell, G, ldg);
+    reduce_gram_k<<<(unsigned)(ell * ell), 64, 0, s>>>(part, nblk, ell, G, ldg);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 
@@ -833,7 +846,7 @@ int k_multidot(const float *X, int64_t ldx, int nv, const float *y, const float 
     const int nout = nv + (z ? 1 : 0);
     if (nout > MD_MAX) return NLRMM_ESHAPE;
     multidot_k<<<(unsigned)nblk, BLK, 0, s>>>(X, ldx, nv, y, z, n, part);
-    reduce_vec_k<<<1, 128, 0, s>>>(part, nblk, nout, out, ostride);
+    reduce_vec_k<<<(unsigned)nout, 64, 0, s>>>(part, nblk, nout, out, ostride);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 
@@ -874,7 +887,7 @@ int k_gks_solve(const double *GA, const double *GP, int ldg, const double *rb, c
 {
     if (ell < 1 || ell > SOLVE_MAX) return NLRMM_ESHAPE;
     const size_t sh = sizeof(double) * (2 * (size_t)ell * (ell + 1) + 4 * ell + 128);
-    gks_solve_k<<<1, BLK, sh, s>>>(GA, GP, ldg, rb, scal, ell, lam_fix, z, out, status);
+    gks_solve_k<<<1, SOLVE_NT, sh, s>>>(GA, GP, ldg, rb, scal, ell, lam_fix, z, out, status);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 
@@ -884,7 +897,7 @@ int k_compress_eig(const double *GA, const double *GP, int ldg, const double *la
 {
     if (ell < 1 || ell > SOLVE_MAX || kmin < 2 || kmin > 16 || kmin > ell) return NLRMM_ESHAPE;
     const size_t sh = sizeof(double) * (2 * (size_t)ell * (ell + 1) + 128 + 2 * ell + kmin);
-    compress_eig_k<<<1, BLK, sh, s>>>(GA, GP, ldg, lam, ell, kmin, z, T, ldt, zout, kout, status);
+    compress_eig_k<<<1, SOLVE_NT, sh, s>>>(GA, GP, ldg, lam, ell, kmin, z, T, ldt, zout, kout, status);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 

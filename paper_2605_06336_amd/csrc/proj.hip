@@ -470,6 +470,8 @@ struct BwdArgs {
     int tiles_x;
     int W;           // staged bins per view (<= WMAX)
     float *x;
+    int nsplit;      // views of a frame split over blockIdx.z; partial images when > 1
+    float *part;     // [nsplit][col][frame][ny][nx] partial images (nsplit > 1)
 };
 
 template <int E>
@@ -486,8 +488,11 @@ __global__ __launch_bounds__(BLK) void bwd_tiles_k(BwdArgs a)
     const int k = tx * TILE + (tid % TILE);
     const int l = ty * TILE + (tid / TILE);
     const bool active = k < a.nx && l < a.ny;
-    const int64_t v0 = (a.view_off && a.nframes > 1) ? a.view_off[f] : 0;
-    const int64_t v1 = (a.view_off && a.nframes > 1) ? a.view_off[f + 1] : a.V;
+    const int64_t fv0 = (a.view_off && a.nframes > 1) ? a.view_off[f] : 0;
+    const int64_t fv1 = (a.view_off && a.nframes > 1) ? a.view_off[f + 1] : a.V;
+    const int split = blockIdx.z;
+    const int64_t v0 = fv0 + ((fv1 - fv0) * split) / a.nsplit;
+    const int64_t v1 = fv0 + ((fv1 - fv0) * (split + 1)) / a.nsplit;
     const float *ycol = a.y + col * a.V * a.nb;
     const double xc = a.x0 + (tx * TILE + 0.5 * TILE) * a.d;
     const double yc = a.y0 + (ty * TILE + 0.5 * TILE) * a.d;
@@ -548,8 +553,23 @@ __global__ __launch_bounds__(BLK) void bwd_tiles_k(BwdArgs a)
     }
     if (active) {
         const int64_t o = ((col * a.nframes + f) * (int64_t)a.ny + l) * a.nx + k;
-        a.x[o] = (float)(acc / a.ds);
+        if (a.nsplit > 1) {
+            const int64_t tot = (int64_t)gridDim.y * a.nx * a.ny;
+            a.part[split * tot + o] = (float)(acc / a.ds);
+        } else {
+            a.x[o] = (float)(acc / a.ds);
+        }
     }
+}
+
+__global__ void sum_splits_k(const float *__restrict__ part, int nsplit, int64_t n,
+                             float *__restrict__ x)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int k = 0; k < nsplit; ++k) s += (double)part[k * n + i];
+    x[i] = (float)s;
 }
 
 int edges_inside(const nlrmm_geom &g)
@@ -707,10 +727,29 @@ size_t fwd_workspace_bytes(const nlrmm_geom &g, int nframes, int ncols)
     return fwd_ws_bytes(g, nframes, gcols, 1, 1, 0);
 }
 
+int bwd_splits(const nlrmm_geom &g, const nlrmm_batch &b, int ncols, int cu_count)
+{
+    const int64_t tiles = (int64_t)((g.nx + TILE - 1) / TILE) * ((g.ny + TILE - 1) / TILE);
+    const int64_t waves = tiles * ncols * b.nframes * (BLK / 64);
+    const int64_t target = (int64_t)6 * 4 * cu_count;   // ~6 resident waves per SIMD
+    int64_t ns = (target + waves - 1) / waves;
+    const int64_t vper = b.nviews / b.nframes;
+    if (ns > vper / 16) ns = vper / 16;
+    if (ns > 8) ns = 8;
+    if (ns < 1) ns = 1;
+    return (int)ns;
+}
+
+size_t bwd_workspace_bytes(const nlrmm_geom &g, const nlrmm_batch &b, int ncols, int cu_count)
+{
+    const int ns = bwd_splits(g, b, ncols, cu_count);
+    if (ns <= 1) return 0;
+    return sizeof(float) * (size_t)ns * ncols * b.nframes * g.nx * g.ny;
+}
+
 int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
                        const float *y, const double *theta, float *x, hipStream_t s)
 {
-    (void)ctx;
     const int E = edges_inside(g);
     if (E < 1 || E > 4) return NLRMM_ESHAPE;
     const int W = (int)ceil((TILE - 1) * g.d * 1.4142135623730951 / g.ds) + E + 4;
@@ -732,13 +771,25 @@ int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b
     a.tiles_x = (g.nx + TILE - 1) / TILE;
     a.W = W;
     a.x = x;
+    a.nsplit = bwd_splits(g, b, ncols, ctx->cu_count);
+    a.part = nullptr;
+    if (a.nsplit > 1) {
+        int rc = ensure_workspace(ctx, bwd_workspace_bytes(g, b, ncols, ctx->cu_count), s);
+        if (rc) return rc;
+        a.part = (float *)ctx->ws.ptr;
+    }
     const int tiles_y = (g.ny + TILE - 1) / TILE;
-    dim3 grid((unsigned)(a.tiles_x * tiles_y), (unsigned)((int64_t)ncols * b.nframes));
+    dim3 grid((unsigned)(a.tiles_x * tiles_y), (unsigned)((int64_t)ncols * b.nframes),
+              (unsigned)a.nsplit);
     switch (E) {
         case 1: bwd_tiles_k<1><<<grid, BLK, 0, s>>>(a); break;
         case 2: bwd_tiles_k<2><<<grid, BLK, 0, s>>>(a); break;
         case 3: bwd_tiles_k<3><<<grid, BLK, 0, s>>>(a); break;
         default: bwd_tiles_k<4><<<grid, BLK, 0, s>>>(a); break;
+    }
+    if (a.nsplit > 1) {
+        const int64_t n = (int64_t)ncols * b.nframes * g.nx * g.ny;
+        sum_splits_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a.part, a.nsplit, n, x);
     }
     NLRMM_HIP_CHECK(hipGetLastError());
     return NLRMM_OK;

@@ -341,7 +341,13 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
         return NLRMM_EHIP;
     }
     // size the projector workspace for the widest call (rebase of kmin+1 columns)
-    rc = ensure_workspace(ctx, fwd_workspace_bytes(*geom, nframes, c.kmin + 1), nullptr);
+    {
+        nlrmm_batch bb{nframes, max_views, nullptr};
+        size_t need = fwd_workspace_bytes(*geom, nframes, c.kmin + 1);
+        const size_t nb2 = bwd_workspace_bytes(*geom, bb, 1, ctx->cu_count);
+        if (nb2 > need) need = nb2;
+        rc = ensure_workspace(ctx, need, nullptr);
+    }
     if (rc) {
         delete S;
         return rc;
