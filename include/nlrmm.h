@@ -114,6 +114,20 @@ int nlrmm_project_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_bat
                          float *yproj, const float *g, double *gdot, double *dnorm2,
                          void *stream);
 
+/* Backprojection that adds into x (x += A(theta)^T y) when accumulate != 0; otherwise
+ * identical to nlrmm_backproject.  Used to sum the adjoints of measurement blocks. */
+int nlrmm_backproject_acc(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                          int32_t ncols, const float *y, const double *theta, float *x,
+                          int32_t accumulate, void *stream);
+
+/* Data residual of the forward model (eq. "nonlinear_forward"): r = A(theta) x - b for one
+ * image, computed in the projection kernel (the projection itself is never stored).
+ *   b [nviews][nbins] float32; r [nviews][nbins] float32 or NULL;
+ *   rnorm2 [nviews] float64 or NULL: ||r_v||^2 per view (FP64 accumulation). */
+int nlrmm_project_residual(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                           const float *x, const double *theta, const float *b, float *r,
+                           double *rnorm2, void *stream);
+
 /* ------------------------------------------------------------------------------------
  * Krylov side of MM-GKS / RMM-GKS (Section 3; supplementary Algs. "enlarge", "compress").
  * Basis blocks are column-contiguous FP32: V [ncols][n] with n = nframes*ny*nx, and
@@ -180,7 +194,8 @@ typedef struct {
     double eps;              /* smoothing of the l1 penalty (> 0) */
     double tau;              /* discrepancy-principle factor: target = tau * delta */
     double lam_fix;          /* >= 0: fixed lambda; < 0: discrepancy principle */
-    int32_t param_update;    /* 0: angles fixed (RMM-GKS); 1: Gauss-Newton (Alg. "update_param") */
+    int32_t param_update;    /* 0: angles fixed (RMM-GKS); 1: AltMin Gauss-Newton (Alg. "update_param");
+                                2: variable projection (Section 4.2, Alg. "update_varpro") */
     int32_t param_mode;      /* 0: one angle per view; 1: one global shift of all views */
     int32_t maxiter_p;       /* Gauss-Newton iterations per outer iteration */
     double mu_rel;           /* damping mu = mu_rel * mean(||D_v||^2) */

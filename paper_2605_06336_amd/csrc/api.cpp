@@ -142,4 +142,36 @@ int nlrmm_project_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_bat
                           (hipStream_t)stream);
 }
 
+int nlrmm_backproject_acc(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                          int32_t ncols, const float *y, const double *theta, float *x,
+                          int32_t accumulate, void *stream)
+{
+    if (!ctx || !x || !theta || !y) return NLRMM_EINVAL;
+    if (ncols < 1) return NLRMM_ESHAPE;
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if ((rc = check_batch(batch))) return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    return launch_backproject(ctx, *geom, *batch, ncols, y, theta, x, (hipStream_t)stream,
+                              accumulate ? 1 : 0);
+}
+
+int nlrmm_project_residual(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                           const float *x, const double *theta, const float *b, float *r,
+                           double *rnorm2, void *stream)
+{
+    if (!ctx || !x || !theta || !b) return NLRMM_EINVAL;
+    if (!r && !rnorm2) return NLRMM_EINVAL;
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if ((rc = check_batch(batch))) return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    FwdOptions o;
+    o.bres = b;
+    o.y = r;
+    o.write_resid = true;
+    o.rnorm2 = rnorm2;
+    return launch_project_ex(ctx, *geom, *batch, 1, x, theta, o, (hipStream_t)stream);
+}
+
 }  // extern "C"

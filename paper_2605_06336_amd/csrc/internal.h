@@ -52,6 +52,7 @@ struct FwdOptions {
     const int *skip = nullptr;     // device flag: skip the whole call when set
     double *part_buf = nullptr;    // caller-provided partials [3][col][V][nchunks]
     bool keep_parts = false;       // leave per-chunk partials unreduced (caller reduces)
+    bool write_resid = false;      // with bres: y receives y - b
 };
 
 // projector launchers (proj.hip); all arguments validated by the caller
@@ -64,7 +65,8 @@ int launch_project(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, in
                    const float *x, const double *theta, float *y, float *dy, const float *gres,
                    double *gdot, double *dnorm2, hipStream_t s);
 int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
-                       const float *y, const double *theta, float *x, hipStream_t s);
+                       const float *y, const double *theta, float *x, hipStream_t s,
+                       int accumulate = 0);
 
 }  // namespace nlrmm
 

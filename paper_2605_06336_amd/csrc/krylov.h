@@ -12,7 +12,8 @@ int k_tv_grad_add(const float *u, const float *w, int nx, int ny, int F, int tem
 int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int ny, int F,
                int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s);
 int k_multidot(const float *X, int64_t ldx, int nv, const float *y, const float *z, int64_t n,
-               double *part, int nblk, double *out, int ostride, hipStream_t s);
+               double *part, int nblk, double *out, int ostride, hipStream_t s,
+               const int *skip = nullptr);
 int k_gemv(const float *X, int64_t ldx, int nv, const double *c, double beta, const float *a,
            double alpha, int64_t n, float *out, hipStream_t s);
 int k_block_update(const float *X, int64_t ldx, int nin, const double *T, int ldt, int kout,
@@ -41,6 +42,15 @@ int k_gn_apply(double *theta, const double *dir, int64_t V, const double *sc,
                const int *accepted, int *status, hipStream_t s);
 int k_fill_f64(double *dst, int64_t n, double value, hipStream_t s);
 int k_fill_i32(int *dst, int64_t n, int value, hipStream_t s);
+int k_view_dots(const float *X, int64_t ldx, int k, const float *e, int nb, int64_t V, double *out,
+                hipStream_t s);
+int k_varpro_reduced(const double *GA, int ldg, const double *GP, const double *ab,
+                     const double *lamp, const double *bn2, int k, double *yout, double *Mout,
+                     double *sc, const double *alphas, int trial, double c1, int *accepted,
+                     int *status, hipStream_t s);
+int k_varpro_dir(const double *M, int k, const double *gd, const double *en2, const double *ETr,
+                 const double *Ate, int64_t V, double mu_rel, double *Yw, double *dir, double *sc,
+                 int *status, hipStream_t s);
 int k_scale_into(const float *src, const double *norm2, int64_t n, float *dst, double *norm_out,
                  int *status, hipStream_t s);
 

@@ -235,8 +235,9 @@ constexpr int MD_MAX = 72;
 __global__ __launch_bounds__(BLK) void multidot_k(const float *__restrict__ X, int64_t ldx, int nv,
                                                   const float *__restrict__ y,
                                                   const float *__restrict__ z, int64_t n,
-                                                  double *__restrict__ part)
+                                                  double *__restrict__ part, const int *skip)
 {
+    if (skip != nullptr && *skip != 0) return;
     __shared__ double sred[BLK / 64][MD_MAX + 1];
     const int tid = threadIdx.x;
     const int nout = nv + (z != nullptr ? 1 : 0);
@@ -272,8 +273,9 @@ __global__ __launch_bounds__(BLK) void multidot_k(const float *__restrict__ X, i
 // and a fixed butterfly, so the result is independent of scheduling.
 __global__ __launch_bounds__(64) void reduce_vec_k(const double *__restrict__ part, int nblk,
                                                    int nout, double *__restrict__ out,
-                                                   int ostride)
+                                                   int ostride, const int *skip)
 {
+    if (skip != nullptr && *skip != 0) return;
     const int i = blockIdx.x;
     double s = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 64) s += part[(int64_t)b * nout + i];
@@ -841,12 +843,12 @@ int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int
 }
 
 int k_multidot(const float *X, int64_t ldx, int nv, const float *y, const float *z, int64_t n,
-               double *part, int nblk, double *out, int ostride, hipStream_t s)
+               double *part, int nblk, double *out, int ostride, hipStream_t s, const int *skip)
 {
     const int nout = nv + (z ? 1 : 0);
     if (nout > MD_MAX) return NLRMM_ESHAPE;
-    multidot_k<<<(unsigned)nblk, BLK, 0, s>>>(X, ldx, nv, y, z, n, part);
-    reduce_vec_k<<<(unsigned)nout, 64, 0, s>>>(part, nblk, nout, out, ostride);
+    multidot_k<<<(unsigned)nblk, BLK, 0, s>>>(X, ldx, nv, y, z, n, part, skip);
+    reduce_vec_k<<<(unsigned)nout, 64, 0, s>>>(part, nblk, nout, out, ostride, skip);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 

@@ -258,6 +258,7 @@ struct FwdArgs {
     const double *tdir;     // trial angles theta + alpha[0] * tdir (null: theta)
     const double *talpha;
     const int *skip;        // when *skip != 0 the launch does nothing
+    int write_resid;        // with bres: store y - b into y
 };
 
 template <int MODE, int NC>
@@ -400,7 +401,7 @@ __global__ __launch_bounds__(BLK) void fwd_edges_k(FwdArgs a)
         if (has_bin) {
             if (PROJ) {
                 yv = (sC[c][tid + 1] - sC[c][tid]) * inv_ds;
-                if (a.y) a.y[o] = (float)yv;
+                if (a.y) a.y[o] = (float)(a.write_resid ? yv - (double)bv : yv);
             }
             if (MOM) {
                 Dv = (sM[c][tid] - sM[c][tid + 1]) * inv_ds;
@@ -472,6 +473,7 @@ struct BwdArgs {
     float *x;
     int nsplit;      // views of a frame split over blockIdx.z; partial images when > 1
     float *part;     // [nsplit][col][frame][ny][nx] partial images (nsplit > 1)
+    int accumulate;  // x += result instead of x = result
 };
 
 template <int E>
@@ -557,17 +559,18 @@ __global__ __launch_bounds__(BLK) void bwd_tiles_k(BwdArgs a)
             const int64_t tot = (int64_t)gridDim.y * a.nx * a.ny;
             a.part[split * tot + o] = (float)(acc / a.ds);
         } else {
-            a.x[o] = (float)(acc / a.ds);
+            const double prev = a.accumulate ? (double)a.x[o] : 0.0;
+            a.x[o] = (float)(prev + acc / a.ds);
         }
     }
 }
 
 __global__ void sum_splits_k(const float *__restrict__ part, int nsplit, int64_t n,
-                             float *__restrict__ x)
+                             float *__restrict__ x, int accumulate)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double s = 0.0;
+    double s = accumulate ? (double)x[i] : 0.0;
     for (int k = 0; k < nsplit; ++k) s += (double)part[k * n + i];
     x[i] = (float)s;
 }
@@ -703,6 +706,7 @@ int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
         a.tdir = o.tdir;
         a.talpha = o.talpha;
         a.skip = o.skip;
+        a.write_resid = o.write_resid ? 1 : 0;
         const int NC = nc >= 8 ? 8 : nc >= 4 ? 4 : nc >= 2 ? 2 : 1;
         dim3 grid((unsigned)(V * nchunks), (unsigned)((nc + NC - 1) / NC));
         if (proj && mom) launch_fwd_mode<3>(NC, grid, a, s);
@@ -748,7 +752,8 @@ size_t bwd_workspace_bytes(const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
 }
 
 int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
-                       const float *y, const double *theta, float *x, hipStream_t s)
+                       const float *y, const double *theta, float *x, hipStream_t s,
+                       int accumulate)
 {
     const int E = edges_inside(g);
     if (E < 1 || E > 4) return NLRMM_ESHAPE;
@@ -773,6 +778,7 @@ int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b
     a.x = x;
     a.nsplit = bwd_splits(g, b, ncols, ctx->cu_count);
     a.part = nullptr;
+    a.accumulate = accumulate;
     if (a.nsplit > 1) {
         int rc = ensure_workspace(ctx, bwd_workspace_bytes(g, b, ncols, ctx->cu_count), s);
         if (rc) return rc;
@@ -789,7 +795,7 @@ int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b
     }
     if (a.nsplit > 1) {
         const int64_t n = (int64_t)ncols * b.nframes * g.nx * g.ny;
-        sum_splits_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a.part, a.nsplit, n, x);
+        sum_splits_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a.part, a.nsplit, n, x, accumulate);
     }
     NLRMM_HIP_CHECK(hipGetLastError());
     return NLRMM_OK;

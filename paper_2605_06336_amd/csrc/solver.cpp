@@ -43,6 +43,10 @@ struct Solver {
            *zt = nullptr, *sc = nullptr, *hb = nullptr, *hb2 = nullptr, *gv = nullptr,
            *hv = nullptr, *rv = nullptr, *dir = nullptr, *alphas = nullptr, *thk = nullptr,
            *part_md = nullptr, *part_gram = nullptr, *part_fwd = nullptr, *gkb = nullptr;
+    // VarPro buffers
+    float *Ahat = nullptr, *evec = nullptr;
+    double *vp_GA = nullptr, *vp_ab = nullptr, *vp_M = nullptr, *vp_y = nullptr, *vp_gd = nullptr,
+           *vp_en2 = nullptr, *vp_ETr = nullptr, *vp_Ate = nullptr, *vp_Y = nullptr;
     int *status = nullptr, *kout = nullptr, *accepted = nullptr;
     std::vector<void *> allocs;
 
@@ -201,6 +205,69 @@ static int gn_update(Solver &S, const nlrmm_batch &b, double *theta, const float
     return NLRMM_OK;
 }
 
+// k x k Gram of A_hat and A_hat^T b (vp_GA, vp_ab).
+static int varpro_grams(Solver &S, int k, int64_t m, const float *bvec, hipStream_t s,
+                        const int *skip)
+{
+    for (int j = 0; j < k; ++j)
+        RC(k_multidot(S.Ahat, m, j + 1, S.Ahat + (int64_t)j * m, nullptr, m, S.part_md,
+                      S.md_blocks, S.vp_GA + j, S.ld, s, skip));
+    RC(k_multidot(S.Ahat, m, k, bvec, nullptr, m, S.part_md, S.md_blocks, S.vp_ab, 1, s, skip));
+    return NLRMM_OK;
+}
+
+// VarPro angle update on the compressed basis (k = kmin columns), weights from u.
+static int varpro_update(Solver &S, const nlrmm_batch &b, double *theta, const float *bvec,
+                         hipStream_t s)
+{
+    const int k = S.ell;
+    const int64_t V = b.nviews;
+    const int64_t m = m_of(S, b);
+    RC(k_psi_weights(S.u, S.g.nx, S.g.ny, S.F, S.cfg.temporal, (float)S.cfg.eps, S.w, s));
+    RC(k_gram_psi(S.V, S.n, k, S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.part_gram,
+                  S.gram_blocks, S.GP, S.ld, s));
+    double *sc = S.sc + S_GN;
+    for (int it = 0; it < S.cfg.maxiter_p; ++it) {
+        RC(launch_project(S.ctx, S.g, b, k, S.V, theta, S.Ahat, nullptr, nullptr, nullptr,
+                          nullptr, s));
+        RC(varpro_grams(S, k, m, bvec, s, nullptr));
+        RC(k_varpro_reduced(S.vp_GA, S.ld, S.GP, S.vp_ab, S.sc + S_LAM, S.sc + S_BNORM2, k,
+                            S.vp_y, S.vp_M, sc, S.alphas, -1, S.cfg.c1, S.accepted, S.status, s));
+        // u_hat = V y, r = A_hat y - b
+        RC(k_gemv(S.V, S.n, k, S.vp_y, 1.0, nullptr, 0.0, S.n, S.r, s));
+        RC(k_gemv(S.Ahat, m, k, S.vp_y, 1.0, bvec, -1.0, m, S.rho, s));
+        FwdOptions o;
+        o.dy = S.evec;
+        o.g = S.rho;
+        o.gdot = S.vp_gd;
+        o.dnorm2 = S.vp_en2;
+        o.part_buf = S.part_fwd;
+        RC(launch_project_ex(S.ctx, S.g, b, 1, S.r, theta, o, s));
+        FwdOptions oc;
+        oc.g = S.rho;
+        oc.gdot = S.vp_ETr;
+        oc.part_buf = S.part_fwd;
+        RC(launch_project_ex(S.ctx, S.g, b, k, S.V, theta, oc, s));
+        RC(k_view_dots(S.Ahat, m, k, S.evec, S.g.nbins, V, S.vp_Ate, s));
+        RC(k_varpro_dir(S.vp_M, k, S.vp_gd, S.vp_en2, S.vp_ETr, S.vp_Ate, V, S.cfg.mu_rel, S.vp_Y,
+                        S.dir, sc, S.status, s));
+        for (int q = 0; q < S.cfg.armijo_trials; ++q) {
+            FwdOptions t;
+            t.y = S.Ahat;
+            t.tdir = S.dir;
+            t.talpha = S.alphas + q;
+            t.skip = S.accepted;
+            RC(launch_project_ex(S.ctx, S.g, b, k, S.V, theta, t, s));
+            RC(varpro_grams(S, k, m, bvec, s, S.accepted));
+            RC(k_varpro_reduced(S.vp_GA, S.ld, S.GP, S.vp_ab, S.sc + S_LAM, S.sc + S_BNORM2, k,
+                                S.vp_y, S.vp_M, sc, S.alphas, q, S.cfg.c1, S.accepted, S.status,
+                                s));
+        }
+        RC(k_gn_apply(theta, S.dir, V, sc, S.accepted, S.status, s));
+    }
+    return NLRMM_OK;
+}
+
 static int solver_outer(Solver &S, const nlrmm_batch &b, double *theta, const float *bvec,
                         double delta, hipStream_t s)
 {
@@ -221,6 +288,7 @@ static int solver_outer(Solver &S, const nlrmm_batch &b, double *theta, const fl
     }
     RC(compress(S, b, s));
     if (S.cfg.param_update == 1) RC(gn_update(S, b, theta, bvec, s));
+    if (S.cfg.param_update == 2) RC(varpro_update(S, b, theta, bvec, s));
     // weights from u_{k+1}; residual with the old operator H_k; project out; append
     RC(k_psi_weights(S.u, S.g.nx, S.g.ny, S.F, S.cfg.temporal, (float)S.cfg.eps, S.w, s));
     RC(mm_residual(S, b, S.thk, S.ell, bvec, s));
@@ -294,7 +362,7 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
     if (c.kmin + c.solves > c.kmax + 1 || c.solves < 1) return NLRMM_ESHAPE;
     if (c.armijo_trials < 0 || c.armijo_trials > 32 || c.maxiter_p < 0) return NLRMM_EINVAL;
     if (!(c.eps > 0.0) || !(c.tau > 0.0)) return NLRMM_EINVAL;
-    if (c.param_update < 0 || c.param_update > 1) return NLRMM_ENOTSUP;
+    if (c.param_update < 0 || c.param_update > 2) return NLRMM_ENOTSUP;
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
     nlrmm_solver *S = new (std::nothrow) nlrmm_solver();
     if (!S) return NLRMM_ENOMEM;
@@ -324,9 +392,16 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
         (rc = S->alloc(&S->alphas, 32)) || (rc = S->alloc(&S->thk, max_views)) ||
         (rc = S->alloc(&S->part_md, (size_t)S->md_blocks * 72)) ||
         (rc = S->alloc(&S->part_gram, (size_t)S->gram_blocks * 64 * 64)) ||
-        (rc = S->alloc(&S->part_fwd, (size_t)3 * max_views * S->nchunks)) ||
+        (rc = S->alloc(&S->part_fwd, (size_t)3 * c.kmin * max_views * S->nchunks)) ||
         (rc = S->alloc(&S->gkb, 2 * (size_t)S->kcap + 2)) || (rc = S->alloc(&S->status, 1)) ||
-        (rc = S->alloc(&S->kout, 1)) || (rc = S->alloc(&S->accepted, 1))) {
+        (rc = S->alloc(&S->kout, 1)) || (rc = S->alloc(&S->accepted, 1)) ||
+        (rc = S->alloc(&S->Ahat, (size_t)c.kmin * S->mmax)) || (rc = S->alloc(&S->evec, S->mmax)) ||
+        (rc = S->alloc(&S->vp_GA, S->ld * S->ld)) || (rc = S->alloc(&S->vp_ab, S->ld)) ||
+        (rc = S->alloc(&S->vp_M, 16 * 16)) || (rc = S->alloc(&S->vp_y, 16)) ||
+        (rc = S->alloc(&S->vp_gd, max_views)) || (rc = S->alloc(&S->vp_en2, max_views)) ||
+        (rc = S->alloc(&S->vp_ETr, (size_t)c.kmin * max_views)) ||
+        (rc = S->alloc(&S->vp_Ate, (size_t)c.kmin * max_views)) ||
+        (rc = S->alloc(&S->vp_Y, (size_t)c.kmin * max_views))) {
         delete S;
         return rc;
     }

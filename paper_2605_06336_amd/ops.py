@@ -215,3 +215,35 @@ def recycle_compress(V, AV, GA, GP, rb, lam, z, ell: int, kmin: int, status=None
                                             lam.data_ptr(), z.data_ptr(), status.data_ptr(),
                                             _stream(dev)), "nlrmm_recycle_compress")
     return status
+
+
+def project_residual(x: torch.Tensor, theta: torch.Tensor, b: torch.Tensor, g: Geom, frames=None,
+                     want_r: bool = True, want_rnorm2: bool = True):
+    """r = A(theta) x - b and/or per-view ||r_v||^2 (float64), one image."""
+    _need(x, torch.float32, "x")
+    _need(theta, torch.float64, "theta")
+    _need(b, torch.float32, "b")
+    V = theta.numel()
+    bt = _batch(frames, V)
+    r = torch.empty((V, g.nbins), dtype=torch.float32, device=x.device) if want_r else None
+    rn = torch.empty(V, dtype=torch.float64, device=x.device) if want_rnorm2 else None
+    check(_lib.lib().nlrmm_project_residual(context(x.device.index or 0), ctypes.byref(g),
+                                            ctypes.byref(bt), x.data_ptr(), theta.data_ptr(),
+                                            b.data_ptr(), _p(r), _p(rn), _stream(x.device)),
+          "nlrmm_project_residual")
+    return r, rn
+
+
+def backproject_into(y: torch.Tensor, theta: torch.Tensor, g: Geom, out: torch.Tensor,
+                     frames=None, accumulate: bool = True) -> torch.Tensor:
+    """out (+)= A(theta)^T y."""
+    _need(y, torch.float32, "y")
+    _need(out, torch.float32, "out")
+    V = theta.numel()
+    bt = _batch(frames, V)
+    ncols = y.numel() // (V * g.nbins)
+    check(_lib.lib().nlrmm_backproject_acc(context(y.device.index or 0), ctypes.byref(g),
+                                           ctypes.byref(bt), ncols, y.data_ptr(),
+                                           theta.data_ptr(), out.data_ptr(), int(accumulate),
+                                           _stream(y.device)), "nlrmm_backproject_acc")
+    return out
