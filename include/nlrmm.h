@@ -225,6 +225,13 @@ int nlrmm_solver_init(nlrmm_solver *solver, const nlrmm_batch *batch, const doub
 int nlrmm_solver_outer(nlrmm_solver *solver, const nlrmm_batch *batch, double *theta,
                        const float *b, double delta, void *stream);
 
+/* Launch policy.  per_frame = 0 (default): every operator application covers all frames
+ * and columns in one launch.  per_frame = 1: one launch per (column, frame) on that frame's
+ * views (the plain per-frame path, same arithmetic); view_off_host (host) [nframes+1]
+ * gives the frames' view offsets. */
+int nlrmm_solver_set_launch(nlrmm_solver *solver, int32_t per_frame, const int64_t *view_off_host,
+                            int32_t nframes);
+
 /* DEVICE pointers into the solver: image u [n], basis V, scalars scal[16]
  * ({||b||^2, target, lambda, model residual^2, ..., [8] GN f0, g^T d, alpha, mu, f}),
  * status word; ell = current number of basis columns. */

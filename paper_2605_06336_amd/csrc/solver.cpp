@@ -49,6 +49,9 @@ struct Solver {
            *vp_en2 = nullptr, *vp_ETr = nullptr, *vp_Ate = nullptr, *vp_Y = nullptr;
     int *status = nullptr, *kout = nullptr, *accepted = nullptr;
     std::vector<void *> allocs;
+    // plain mode: one launch per frame (and per column) instead of one batched launch
+    int plain = 0;
+    std::vector<int64_t> vo_host;
 
     template <typename T_>
     int alloc(T_ **p, size_t count)
@@ -82,6 +85,68 @@ namespace nlrmm {
     } while (0)
 
 static int64_t m_of(const Solver &S, const nlrmm_batch &b) { return b.nviews * S.g.nbins; }
+
+static bool per_frame(const Solver &S, const nlrmm_batch &b)
+{
+    return S.plain && b.nframes > 1 && (int64_t)S.vo_host.size() == (int64_t)b.nframes + 1;
+}
+
+// Projection of ncols columns with the solver's launch policy.  In plain mode every
+// (column, frame) pair is its own launch on its frame's views.
+static int proj(Solver &S, const nlrmm_batch &b, int ncols, const float *x, const double *theta,
+                const FwdOptions &o, hipStream_t s)
+{
+    if (!per_frame(S, b)) return launch_project_ex(S.ctx, S.g, b, ncols, x, theta, o, s);
+    const int F = b.nframes;
+    const int64_t npix = (int64_t)S.g.nx * S.g.ny, nb = S.g.nbins, V = b.nviews;
+    const int nch = fwd_chunks(S.g);
+    for (int c = 0; c < ncols; ++c) {
+        for (int f = 0; f < F; ++f) {
+            const int64_t v0 = S.vo_host[f], nv = S.vo_host[f + 1] - v0;
+            if (nv <= 0) continue;
+            nlrmm_batch fb{1, nv, nullptr};
+            FwdOptions q = o;
+            const int64_t yo = (int64_t)c * V * nb + v0 * nb;
+            if (o.y) q.y = o.y + yo;
+            if (o.dy) q.dy = o.dy + yo;
+            if (o.g) q.g = o.g + v0 * nb;
+            if (o.bres) q.bres = o.bres + v0 * nb;
+            if (o.gdot) q.gdot = o.gdot + (int64_t)c * V + v0;
+            if (o.dnorm2) q.dnorm2 = o.dnorm2 + (int64_t)c * V + v0;
+            if (o.rnorm2) q.rnorm2 = o.rnorm2 + (int64_t)c * V + v0;
+            if (o.tdir) q.tdir = o.tdir + v0;
+            if (o.part_buf) q.part_buf = o.part_buf + 3 * ((int64_t)c * V + v0) * nch;
+            RC(launch_project_ex(S.ctx, S.g, fb, 1, x + ((int64_t)c * F + f) * npix, theta + v0, q,
+                                 s));
+        }
+    }
+    return NLRMM_OK;
+}
+
+static int proj_plain(Solver &S, const nlrmm_batch &b, int ncols, const float *x,
+                      const double *theta, float *y, hipStream_t s)
+{
+    FwdOptions o;
+    o.y = y;
+    return proj(S, b, ncols, x, theta, o, s);
+}
+
+static int bproj(Solver &S, const nlrmm_batch &b, const float *y, const double *theta, float *x,
+                 hipStream_t s)
+{
+    if (!per_frame(S, b)) return launch_backproject(S.ctx, S.g, b, 1, y, theta, x, s);
+    const int64_t npix = (int64_t)S.g.nx * S.g.ny, nb = S.g.nbins;
+    for (int f = 0; f < b.nframes; ++f) {
+        const int64_t v0 = S.vo_host[f], nv = S.vo_host[f + 1] - v0;
+        if (nv <= 0) {
+            RC(k_gemv(S.V, 1, 0, nullptr, 0.0, nullptr, 0.0, npix, x + f * npix, s));   // zero
+            continue;
+        }
+        nlrmm_batch fb{1, nv, nullptr};
+        RC(launch_backproject(S.ctx, S.g, fb, 1, y + v0 * nb, theta + v0, x + f * npix, s));
+    }
+    return NLRMM_OK;
+}
 
 // G_A = (AV)^T AV and rb = (AV)^T b for the first ell columns, plus ||b||^2.
 static int gram_from_scratch(Solver &S, int ell, int64_t m, const float *b, hipStream_t s)
@@ -117,7 +182,7 @@ static int mm_residual(Solver &S, const nlrmm_batch &b, const double *theta, int
 {
     const int64_t m = m_of(S, b);
     RC(k_gemv(S.AV, m, ell, S.z, 1.0, bvec, -1.0, m, S.rho, s));
-    RC(launch_backproject(S.ctx, S.g, b, 1, S.rho, theta, S.r, s));
+    RC(bproj(S, b, S.rho, theta, S.r, s));
     RC(k_tv_grad_add(S.u, S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.sc + S_LAM, S.r, s));
     return NLRMM_OK;
 }
@@ -131,8 +196,7 @@ static int expand(Solver &S, const nlrmm_batch &b, const double *theta, const fl
     const int64_t m = m_of(S, b);
     RC(mm_residual(S, b, theta, ell, bvec, s));
     RC(cgs2_append(S, ell, s));
-    RC(launch_project(S.ctx, S.g, b, 1, S.V + (int64_t)ell * S.n, theta, S.AV + (int64_t)ell * m,
-                      nullptr, nullptr, nullptr, nullptr, s));
+    RC(proj_plain(S, b, 1, S.V + (int64_t)ell * S.n, theta, S.AV + (int64_t)ell * m, s));
     RC(k_multidot(S.AV, m, ell + 1, S.AV + (int64_t)ell * m, bvec, m, S.part_md, S.md_blocks,
                   S.hb2, 1, s));
     RC(k_scatter_gram(S.hb2, ell, S.GA, S.ld, S.rb, s));
@@ -184,22 +248,21 @@ static int gn_update(Solver &S, const nlrmm_batch &b, double *theta, const float
         o.dnorm2 = S.hv;
         o.rnorm2 = S.rv;
         o.part_buf = S.part_fwd;
-        RC(launch_project_ex(S.ctx, S.g, b, 1, S.u, theta, o, s));
+        RC(proj(S, b, 1, S.u, theta, o, s));
         RC(k_gn_prepare(S.gv, S.hv, S.rv, V, S.cfg.param_mode, S.cfg.mu_rel, S.dir, S.sc + S_GN,
                         S.accepted, s));
         for (int q = 0; q < S.cfg.armijo_trials; ++q) {
             FwdOptions t;
             t.bres = bvec;
-            t.rnorm2 = S.rv;   // not finalised (keep_parts); partials are summed directly
+            t.rnorm2 = S.rv;   // per-view ||r_v||^2 at the trial angles
             t.part_buf = S.part_fwd;
-            t.keep_parts = true;
             t.tdir = S.dir;
             t.talpha = S.alphas + q;
             t.skip = S.accepted;
-            RC(launch_project_ex(S.ctx, S.g, b, 1, S.u, theta, t, s));
-            RC(k_armijo_check(S.part_fwd + 2 * V * nch, V * nch, S.alphas, q, S.cfg.c1,
-                              S.sc + S_GN, S.accepted, s));
+            RC(proj(S, b, 1, S.u, theta, t, s));
+            RC(k_armijo_check(S.rv, V, S.alphas, q, S.cfg.c1, S.sc + S_GN, S.accepted, s));
         }
+        (void)nch;
         RC(k_gn_apply(theta, S.dir, V, S.sc + S_GN, S.accepted, S.status, s));
     }
     return NLRMM_OK;
@@ -212,6 +275,7 @@ static int varpro_grams(Solver &S, int k, int64_t m, const float *bvec, hipStrea
     for (int j = 0; j < k; ++j)
         RC(k_multidot(S.Ahat, m, j + 1, S.Ahat + (int64_t)j * m, nullptr, m, S.part_md,
                       S.md_blocks, S.vp_GA + j, S.ld, s, skip));
+    RC(k_symmetrize(S.vp_GA, S.ld, k, s));
     RC(k_multidot(S.Ahat, m, k, bvec, nullptr, m, S.part_md, S.md_blocks, S.vp_ab, 1, s, skip));
     return NLRMM_OK;
 }
@@ -228,8 +292,7 @@ static int varpro_update(Solver &S, const nlrmm_batch &b, double *theta, const f
                   S.gram_blocks, S.GP, S.ld, s));
     double *sc = S.sc + S_GN;
     for (int it = 0; it < S.cfg.maxiter_p; ++it) {
-        RC(launch_project(S.ctx, S.g, b, k, S.V, theta, S.Ahat, nullptr, nullptr, nullptr,
-                          nullptr, s));
+        RC(proj_plain(S, b, k, S.V, theta, S.Ahat, s));
         RC(varpro_grams(S, k, m, bvec, s, nullptr));
         RC(k_varpro_reduced(S.vp_GA, S.ld, S.GP, S.vp_ab, S.sc + S_LAM, S.sc + S_BNORM2, k,
                             S.vp_y, S.vp_M, sc, S.alphas, -1, S.cfg.c1, S.accepted, S.status, s));
@@ -242,12 +305,12 @@ static int varpro_update(Solver &S, const nlrmm_batch &b, double *theta, const f
         o.gdot = S.vp_gd;
         o.dnorm2 = S.vp_en2;
         o.part_buf = S.part_fwd;
-        RC(launch_project_ex(S.ctx, S.g, b, 1, S.r, theta, o, s));
+        RC(proj(S, b, 1, S.r, theta, o, s));
         FwdOptions oc;
         oc.g = S.rho;
         oc.gdot = S.vp_ETr;
         oc.part_buf = S.part_fwd;
-        RC(launch_project_ex(S.ctx, S.g, b, k, S.V, theta, oc, s));
+        RC(proj(S, b, k, S.V, theta, oc, s));
         RC(k_view_dots(S.Ahat, m, k, S.evec, S.g.nbins, V, S.vp_Ate, s));
         RC(k_varpro_dir(S.vp_M, k, S.vp_gd, S.vp_en2, S.vp_ETr, S.vp_Ate, V, S.cfg.mu_rel, S.vp_Y,
                         S.dir, sc, S.status, s));
@@ -257,7 +320,7 @@ static int varpro_update(Solver &S, const nlrmm_batch &b, double *theta, const f
             t.tdir = S.dir;
             t.talpha = S.alphas + q;
             t.skip = S.accepted;
-            RC(launch_project_ex(S.ctx, S.g, b, k, S.V, theta, t, s));
+            RC(proj(S, b, k, S.V, theta, t, s));
             RC(varpro_grams(S, k, m, bvec, s, S.accepted));
             RC(k_varpro_reduced(S.vp_GA, S.ld, S.GP, S.vp_ab, S.sc + S_LAM, S.sc + S_BNORM2, k,
                                 S.vp_y, S.vp_M, sc, S.alphas, q, S.cfg.c1, S.accepted, S.status,
@@ -278,8 +341,7 @@ static int solver_outer(Solver &S, const nlrmm_batch &b, double *theta, const fl
     RC(k_copy_f64(theta, S.thk, V, s));
     RC(k_fill_f64(S.sc + S_TARGET, 1, S.cfg.tau * delta, s));
     // rebase A V on the current views and angles
-    RC(launch_project(S.ctx, S.g, b, S.ell, S.V, S.thk, S.AV, nullptr, nullptr, nullptr,
-                      nullptr, s));
+    RC(proj_plain(S, b, S.ell, S.V, S.thk, S.AV, s));
     RC(gram_from_scratch(S, S.ell, m, bvec, s));
     const int nsolve = S.cfg.solves;
     for (int t = 0; t < nsolve; ++t) {
@@ -314,7 +376,7 @@ static int solver_init(Solver &S, const nlrmm_batch &b, const double *theta, con
     RC(k_scale_into(bvec, S.hb, m, U, nrm + k, S.status, s));
     for (int i = 0; i < k; ++i) {
         // v = A^T u_i - beta_i v_{i-1}, reorthogonalised against V, normalised
-        RC(launch_backproject(S.ctx, S.g, b, 1, U + (int64_t)i * m, theta, S.r, s));
+        RC(bproj(S, b, U + (int64_t)i * m, theta, S.r, s));
         if (i > 0)
             RC(k_gemv(S.V + (int64_t)(i - 1) * S.n, S.n, 1, nrm + k + i, -1.0, S.r, 1.0, S.n,
                       S.r, s));
@@ -328,8 +390,7 @@ static int solver_init(Solver &S, const nlrmm_batch &b, const double *theta, con
         RC(k_scale_into(S.r, S.hb, S.n, S.V + (int64_t)i * S.n, nrm + i, S.status, s));
         if (i == k - 1) break;
         // p = A v_i - alpha_i u_i, reorthogonalised against U, normalised
-        RC(launch_project(S.ctx, S.g, b, 1, S.V + (int64_t)i * S.n, theta, S.rho, nullptr,
-                          nullptr, nullptr, nullptr, s));
+        RC(proj_plain(S, b, 1, S.V + (int64_t)i * S.n, theta, S.rho, s));
         RC(k_gemv(U + (int64_t)i * m, m, 1, nrm + i, -1.0, S.rho, 1.0, m, S.rho, s));
         RC(k_multidot(U, m, i + 1, S.rho, nullptr, m, S.part_md, S.md_blocks, S.hb, 1, s));
         RC(k_gemv(U, m, i + 1, S.hb, -1.0, S.rho, 1.0, m, S.rho, s));
@@ -453,6 +514,17 @@ int nlrmm_solver_outer(nlrmm_solver *S, const nlrmm_batch *batch, double *theta,
     if (batch->nframes != S->F) return NLRMM_ESHAPE;
     if (S->ell != S->cfg.kmin + 1) return NLRMM_EINVAL;   // not initialised
     return solver_outer(*S, *batch, theta, b, delta, (hipStream_t)stream);
+}
+
+int nlrmm_solver_set_launch(nlrmm_solver *S, int32_t per_frame, const int64_t *view_off_host,
+                            int32_t nframes)
+{
+    if (!S) return NLRMM_EINVAL;
+    if (per_frame && (!view_off_host || nframes != S->F)) return NLRMM_EINVAL;
+    S->plain = per_frame ? 1 : 0;
+    S->vo_host.clear();
+    if (per_frame) S->vo_host.assign(view_off_host, view_off_host + nframes + 1);
+    return NLRMM_OK;
 }
 
 int nlrmm_solver_state(nlrmm_solver *S, float **u, float **V, double **scal, int32_t **status,

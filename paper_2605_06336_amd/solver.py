@@ -64,6 +64,18 @@ class Solver:
         except Exception:
             pass
 
+    def set_per_frame(self, view_off_host=None) -> None:
+        """Plain per-frame launches (view_off_host given) or batched launches (None)."""
+        import numpy as np
+        if view_off_host is None:
+            check(_lib.lib().nlrmm_solver_set_launch(self.h, 0, None, self.nframes),
+                  "nlrmm_solver_set_launch")
+            return
+        self._vo = np.ascontiguousarray(view_off_host, dtype=np.int64)
+        check(_lib.lib().nlrmm_solver_set_launch(
+            self.h, 1, self._vo.ctypes.data_as(ctypes.c_void_p), self.nframes),
+            "nlrmm_solver_set_launch")
+
     def _stream(self):
         return torch.cuda.current_stream(self.device).cuda_stream
 
@@ -87,3 +99,23 @@ class Solver:
         check(_lib.lib().nlrmm_solver_read(self.h, u.data_ptr(), sc.data_ptr(), st.data_ptr(),
                                            self._stream()), "nlrmm_solver_read")
         return u, sc, st
+
+
+class OuterGraph:
+    """One outer iteration captured as a HIP graph (torch.cuda.CUDAGraph) and replayed.
+
+    The solver's state, theta and b live at fixed device addresses, so every replay
+    performs the next outer iteration.  An eager outer iteration must have run first so
+    that every workspace is allocated before capture (allocation is refused while a stream
+    is capturing)."""
+
+    def __init__(self, solver: Solver, theta: torch.Tensor, b: torch.Tensor, delta: float,
+                 frames=None):
+        self.graph = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize(solver.device)
+        with torch.cuda.graph(self.graph):
+            solver.outer(theta, b, delta, frames)
+        torch.cuda.synchronize(solver.device)
+
+    def replay(self) -> None:
+        self.graph.replay()
