@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--reps", type=int, default=20, help="repetitions per operator timing")
+    ap.add_argument("--gram-precision", type=int, default=0, choices=(0, 1, 2),
+                    help="regulariser Gram: 0 FP64 vector, 1 FP32 MFMA, 2 BF16 MFMA")
     return ap.parse_args()
 
 
@@ -62,7 +64,7 @@ def main():
     b = torch.as_tensor((bex + e).astype(np.float32), device=dev)
     theta = torch.as_tensor(inst.theta_nom.copy(), device=dev)
 
-    cfg = Config(kmin=wl.kmin, kmax=wl.kmax, eps=wl.eps)
+    cfg = Config(kmin=wl.kmin, kmax=wl.kmax, eps=wl.eps, gram_precision=args.gram_precision)
     sol = Solver(g, 1, V, cfg)
     sol.init(theta, b)
     for _ in range(args.warmup):

@@ -144,10 +144,12 @@ int nlrmm_tv_weights(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, in
 
 /* Weighted regulariser Gram G = (P Psi V)^T (P Psi V) = (Psi V)^T diag(w) (Psi V) for the
  * first ell (<= 64) columns of V: the R_Psi^T R_Psi of the projected problem (Section 3.2).
- * Psi V is computed on the fly; FP64 accumulation.  G [ell][ldg] float64 overwritten. */
+ * Psi V is computed on the fly.  precision: 0 = FP64 products and accumulation (VALU);
+ * 1 = FP32 MFMA (32x32x2) with FP32 accumulation per 64-pixel chunk, FP64 across chunks;
+ * 2 = BF16 MFMA operands (32x32x8), same accumulation.  G [ell][ldg] float64 overwritten. */
 int nlrmm_gram_psi(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, int32_t temporal,
                    int32_t ell, const float *V, const float *w, double *G, int32_t ldg,
-                   void *stream);
+                   int32_t precision, void *stream);
 
 /* Projected MM-GKS solve (eq. "reduced_problem") from its Grams:
  *   GA = (AV)^T AV, GP = (P Psi V)^T P Psi V, rb = (AV)^T b   (FP64, ell <= 56),
@@ -203,6 +205,7 @@ typedef struct {
     int32_t armijo_trials;   /* <= 32 */
     double breakdown_tol;    /* Krylov breakdown threshold */
     int32_t temporal;        /* dynamic problems: regulariser includes frame differences */
+    int32_t gram_precision;  /* regulariser Gram: 0 FP64, 1 FP32 MFMA, 2 BF16 MFMA (nlrmm_gram_psi) */
 } nlrmm_solver_cfg;
 
 typedef struct nlrmm_solver nlrmm_solver;

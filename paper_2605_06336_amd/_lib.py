@@ -44,7 +44,7 @@ class SolverCfg(ctypes.Structure):
                 ("maxiter_p", ctypes.c_int32), ("mu_rel", ctypes.c_double),
                 ("c1", ctypes.c_double), ("beta", ctypes.c_double), ("alpha0", ctypes.c_double),
                 ("armijo_trials", ctypes.c_int32), ("breakdown_tol", ctypes.c_double),
-                ("temporal", ctypes.c_int32)]
+                ("temporal", ctypes.c_int32), ("gram_precision", ctypes.c_int32)]
 
 # name -> argtypes (all return int except where noted)
 SIGNATURES = {
@@ -56,7 +56,7 @@ SIGNATURES = {
     "nlrmm_backproject_acc": [_P, _GP, _BP, _I32, _P, _P, _P, _I32, _P],
     "nlrmm_project_residual": [_P, _GP, _BP, _P, _P, _P, _P, _P, _P],
     "nlrmm_tv_weights": [_P, _GP, _I32, _I32, _P, _D, _P, _P],
-    "nlrmm_gram_psi": [_P, _GP, _I32, _I32, _I32, _P, _P, _P, _I32, _P],
+    "nlrmm_gram_psi": [_P, _GP, _I32, _I32, _I32, _P, _P, _P, _I32, _I32, _P],
     "nlrmm_gks_solve": [_P, _I32, _P, _P, _I32, _P, _P, _D, _P, _P, _P, _P],
     "nlrmm_gks_expand": [_P, _GP, _BP, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _I32, _P,
                          _D, _P, _P],

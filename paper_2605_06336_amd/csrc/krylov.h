@@ -9,8 +9,10 @@ int k_psi_weights(const float *u, int nx, int ny, int F, int temporal, float eps
 int k_psi_apply(const float *u, int nx, int ny, int F, int temporal, float *out, hipStream_t s);
 int k_tv_grad_add(const float *u, const float *w, int nx, int ny, int F, int temporal,
                   const double *lamp, float *r, hipStream_t s);
+// mode: 0 FP64 VALU, 1 FP32 MFMA, 2 BF16 MFMA (FP32 accumulation per chunk, FP64 across)
 int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int ny, int F,
-               int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s);
+               int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s,
+               int mode = 0);
 int k_multidot(const float *X, int64_t ldx, int nv, const float *y, const float *z, int64_t n,
                double *part, int nblk, double *out, int ostride, hipStream_t s,
                const int *skip = nullptr);
@@ -22,8 +24,10 @@ int k_copy_cols(const float *src, int64_t lds, float *dst, int64_t ldd, int ncol
                 hipStream_t s);
 int k_normalize_into(const float *r, const double *scal, double tol, int64_t n, float *vout,
                      int *status, double *norm_out, hipStream_t s);
+// method: 0 Jacobi eigen-decomposition (4 waves), 1 single-wave tridiagonal form
 int k_gks_solve(const double *GA, const double *GP, int ldg, const double *rb, const double *scal,
-                int ell, double lam_fix, double *z, double *out, int *status, hipStream_t s);
+                int ell, double lam_fix, double *z, double *out, int *status, hipStream_t s,
+                int method = 1);
 int k_compress_eig(const double *GA, const double *GP, int ldg, const double *lam, int ell,
                    int kmin, const double *z, double *T, int ldt, double *zout, int *kout,
                    int *status, hipStream_t s);

@@ -210,6 +210,115 @@ __global__ __launch_bounds__(BLK) void gram_psi_k(const float *__restrict__ V, i
     }
 }
 
+// MFMA variant of the weighted regulariser Gram (B^T B with B = sqrt(w) * Psi V, B of
+// up to 192 rows per 64-pixel chunk and <= 64 columns).  The chunk's rows are staged in
+// LDS as FP32; each of the four waves owns one 32x32 tile of the (padded) 64x64 result and
+// runs v_mfma_f32_32x32x2f32 (FP32 operands) or v_mfma_f32_32x32x8bf16_1k (BF16 operands,
+// round-to-nearest-even) with FP32 accumulation over the chunk, flushed into FP64
+// accumulators after every chunk.  Output layout of the 32x32 MFMA: element (i, j) lives in
+// lane j + 32 ((i/4) mod 2), register (i mod 4) + 4 (i / 8).
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+constexpr int MP = 64;            // pixels per chunk
+constexpr int MR = 3 * MP;        // rows per chunk (dx, dy, dt)
+constexpr int MLD = 64 + 4;       // LDS row stride (floats)
+
+__device__ __forceinline__ short bf16_rne(float f)
+{
+    unsigned u = __float_as_uint(f);
+    const unsigned lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (short)(u >> 16);
+}
+
+template <bool BF16>
+__global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__ V, int64_t ldv,
+                                                       int ell, const float *__restrict__ w,
+                                                       int nx, int ny, int F, int temporal,
+                                                       double *__restrict__ part)
+{
+    __shared__ float sB[MR][MLD];
+    __shared__ float sw[MR];
+    const TVGeo g = tvgeo(nx, ny, F, temporal);
+    const int64_t npix = (int64_t)nx * ny;
+    const int64_t ntot = npix * F;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int ti = wv >> 1, tj = wv & 1;   // this wave's 32x32 tile
+    double accd[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accd[r] = 0.0;
+    const int64_t nchunks = (ntot + MP - 1) / MP;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t i0 = ch * MP;
+        // square roots of the chunk's weights (zero where the difference does not exist)
+        for (int r = tid; r < MR; r += BLK) {
+            const int pc = r / 3, kind = r - pc * 3;
+            const int64_t i = i0 + pc;
+            float v = 0.0f;
+            if (i < ntot) {
+                const int64_t f = i / npix, p = i - f * npix;
+                const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
+                if (kind == 0 && k < nx - 1) v = w[f * g.per_frame + (int64_t)l * (nx - 1) + k];
+                else if (kind == 1 && l < ny - 1) v = w[f * g.per_frame + g.dy_off + (int64_t)l * nx + k];
+                else if (kind == 2 && g.temporal && f < F - 1) v = w[g.t_off + f * npix + p];
+            }
+            sw[r] = sqrtf(v);
+        }
+        __syncthreads();
+        // weighted differences of every column (zero columns pad to 64)
+        for (int t = tid; t < MP * 64; t += BLK) {
+            const int c = t / MP, pc = t - c * MP;
+            const int64_t i = i0 + pc;
+            float dx = 0.0f, dy = 0.0f, dt = 0.0f;
+            if (c < ell && i < ntot) {
+                const int64_t f = i / npix, p = i - f * npix;
+                const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
+                const float *vc = V + (int64_t)c * ldv;
+                const float x0 = vc[i];
+                if (k < nx - 1) dx = vc[i + 1] - x0;
+                if (l < ny - 1) dy = vc[i + nx] - x0;
+                if (g.temporal && f < F - 1) dt = vc[i + npix] - x0;
+            }
+            sB[3 * pc + 0][c] = sw[3 * pc + 0] * dx;
+            sB[3 * pc + 1][c] = sw[3 * pc + 1] * dy;
+            sB[3 * pc + 2][c] = sw[3 * pc + 2] * dt;
+        }
+        __syncthreads();
+        f32x16 acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+        const int ca = 32 * ti + (lane & 31), cb = 32 * tj + (lane & 31);
+        if (BF16) {
+            for (int k0 = 0; k0 < MR; k0 += 8) {
+                s16x4 a, b;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = k0 + 4 * (lane >> 5) + q;
+                    a[q] = bf16_rne(sB[row][ca]);
+                    b[q] = bf16_rne(sB[row][cb]);
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+            }
+        } else {
+            for (int k0 = 0; k0 < MR; k0 += 2) {
+                const int row = k0 + (lane >> 5);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(sB[row][ca], sB[row][cb], acc, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) accd[r] += (double)acc[r];
+        __syncthreads();
+    }
+    double *out = part + (int64_t)blockIdx.x * ell * ell;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = 32 * ti + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int j = 32 * tj + (lane & 31);
+        if (i < ell && j < ell) out[i * ell + j] = accd[r];
+    }
+}
+
 // Sum nblk partial ell x ell matrices into G (leading dimension ldg): one wave per entry,
 // fixed summation order.
 __global__ __launch_bounds__(64) void reduce_gram_k(const double *__restrict__ part, int nblk,
@@ -659,6 +768,293 @@ __global__ __launch_bounds__(SOLVE_NT) void gks_solve_k(const double *__restrict
     }
 }
 
+// Projected MM-GKS solve, single-wave tridiagonal form (same mathematics as gks_solve_k).
+// With GA = L L^T (augmented Cholesky of [[GA, rb], [rb^T, ||b||^2]] also gives c = L^-1 rb
+// and out2 = ||b||^2 - ||c||^2) and K = L^-1 GP L^-T, a reflector H0 maps c to s ||c|| e1
+// and Householder tridiagonalisation of H0 K H0 (which leaves e1 fixed) gives T = Q^T K Q.
+// With y = (I + lam T)^-1 e1 one has ||AV z(lam) - b||^2 = out2 + ||c||^2 ||e1 - y||^2, and
+// the pivots of the bottom-up elimination of I + lam T,
+//   D_{n-1} = 1 + lam d_{n-1},  D_i = 1 + lam d_i - lam^2 e_i^2 / D_{i+1},
+// give y_0 = 1 / D_0 and y_i = -(lam e_{i-1} / D_i) y_{i-1}, so ||e1 - y||^2 is a sum of
+// nonnegative terms accumulated in the same O(ell) sweep (no eigenvectors).  Each lane
+// evaluates one lam; a 65-way bracket search runs on the log-bracket of the discrepancy
+// principle.  z = L^-T Q (I + lam T)^-1 (s ||c|| e1).
+constexpr int TRI_NT = 64;
+
+__device__ __forceinline__ double wsum64(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(TRI_NT) void gks_solve_tri_k(const double *__restrict__ GA,
+                                                         const double *__restrict__ GP, int ldg,
+                                                         const double *__restrict__ rb,
+                                                         const double *__restrict__ scal, int ell,
+                                                         double lam_fix, double *__restrict__ z,
+                                                         double *__restrict__ out,
+                                                         int *__restrict__ status)
+{
+    extern __shared__ double sm[];
+    const int n = ell, n1 = ell + 1;
+    const int lda = n1 + 1, ldk = n + 1;
+    double *A = sm;                   // n1 x lda: augmented matrix -> Cholesky factor
+    double *K = A + n1 * lda;         // n x ldk: K, then reflectors stored below the diagonal
+    double *vv = K + n * ldk;         // n: current reflector
+    double *ww = vv + n;              // n
+    double *tau = ww + n;             // n: tau_j of reflector j (j = 0 is H0, j >= 1 tridiag)
+    double *dd = tau + n;             // n: diagonal of T
+    double *ee = dd + n;              // n: sub-diagonal of T
+    double *yv = ee + n;              // n
+    double *h0 = yv + n;              // n: reflector H0
+    __shared__ int sbad;
+    __shared__ int sfirst;
+    const int tid = threadIdx.x;
+    if (tid == 0) sbad = 0;
+    for (int t = tid; t < n * n; t += TRI_NT) {
+        const int i = t / n, j = t - (t / n) * n;
+        A[i * lda + j] = GA[i * ldg + j];
+        K[i * ldk + j] = GP[i * ldg + j];
+    }
+    for (int i = tid; i < n; i += TRI_NT) {
+        A[i * lda + n] = rb[i];
+        A[n * lda + i] = rb[i];
+    }
+    if (tid == 0) A[n * lda + n] = scal[0];
+    __syncthreads();
+    double trA = 0.0, trP = 0.0;
+    for (int i = 0; i < n; ++i) {
+        trA += A[i * lda + i];
+        trP += K[i * ldk + i];
+    }
+    // 1. augmented Cholesky (right-looking, lower); the last pivot is left unrooted (= out2)
+    for (int j = 0; j < n1; ++j) {
+        if (tid == 0 && j < n) {
+            double p = A[j * lda + j];
+            if (!(p > 0.0)) {
+                sbad = 1;
+                p = 1e-300;
+            }
+            A[j * lda + j] = sqrt(p);
+        }
+        __syncthreads();
+        if (j == n) break;
+        const double piv = A[j * lda + j];
+        for (int i = j + 1 + tid; i < n1; i += TRI_NT) A[i * lda + j] /= piv;
+        __syncthreads();
+        const int m = n1 - j - 1;
+        for (int t = tid; t < m * m; t += TRI_NT) {
+            const int i = j + 1 + t / m, k = j + 1 + t % m;
+            if (k <= i) A[i * lda + k] -= A[i * lda + j] * A[k * lda + j];
+        }
+        __syncthreads();
+    }
+    double cn2 = 0.0;
+    for (int k = 0; k < n; ++k) cn2 += A[n * lda + k] * A[n * lda + k];
+    const double out2 = fmax(scal[0] - cn2, 0.0);
+    const double cn = sqrt(cn2);
+    // 2. K = L^-1 GP L^-T (column sweeps, one column per lane)
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int k = 0; k < n; ++k) {
+            const double lkk = A[k * lda + k];
+            for (int c = tid; c < n; c += TRI_NT) K[k * ldk + c] /= lkk;
+            __syncthreads();
+            for (int c = tid; c < n; c += TRI_NT) {
+                const double xk = K[k * ldk + c];
+                for (int i = k + 1; i < n; ++i) K[i * ldk + c] -= A[i * lda + k] * xk;
+            }
+            __syncthreads();
+        }
+        for (int t = tid; t < n * n; t += TRI_NT) {
+            const int i = t / n, j = t - (t / n) * n;
+            if (i < j) {
+                const double a = K[i * ldk + j];
+                K[i * ldk + j] = K[j * ldk + i];
+                K[j * ldk + i] = a;
+            }
+        }
+        __syncthreads();
+    }
+    for (int t = tid; t < n * n; t += TRI_NT) {
+        const int i = t / n, j = t - (t / n) * n;
+        if (i < j) {
+            const double a = 0.5 * (K[i * ldk + j] + K[j * ldk + i]);
+            K[i * ldk + j] = a;
+            K[j * ldk + i] = a;
+        }
+    }
+    __syncthreads();
+    // 3. H0 = I - tau0 v v^T with H0 c = s ||c|| e1 (s = -sign(c0)); K <- H0 K H0
+    double sgn = 1.0;
+    {
+        const double c0 = A[n * lda + 0];
+        sgn = (c0 >= 0.0) ? -1.0 : 1.0;
+        for (int i = tid; i < n; i += TRI_NT) h0[i] = A[n * lda + i] - (i == 0 ? sgn * cn : 0.0);
+        __syncthreads();
+        double vtv = 0.0;
+        for (int i = 0; i < n; ++i) vtv += h0[i] * h0[i];
+        const double t0 = vtv > 0.0 ? 2.0 / vtv : 0.0;
+        if (tid == 0) tau[0] = t0;
+        // p = t0 K v, mu = t0/2 p^T v, w = p - mu v, K -= v w^T + w v^T
+        double pi = 0.0;
+        if (tid < n) {
+            for (int k = 0; k < n; ++k) pi += K[tid * ldk + k] * h0[k];
+            pi *= t0;
+        }
+        const double mu = 0.5 * t0 * wsum64(tid < n ? pi * h0[tid] : 0.0);
+        if (tid < n) ww[tid] = pi - mu * h0[tid];
+        __syncthreads();
+        if (tid < n) {
+            const double vi = h0[tid], wi = ww[tid];
+            for (int k = 0; k < n; ++k) K[tid * ldk + k] -= vi * ww[k] + wi * h0[k];
+        }
+        __syncthreads();
+    }
+    // 4. Householder tridiagonalisation (reflector j acts on indices j+1 .. n-1)
+    for (int j = 0; j + 2 < n; ++j) {
+        const double xi = (tid > j && tid < n) ? K[tid * ldk + j] : 0.0;
+        const double s2 = wsum64(xi * xi);
+        const double x0 = K[(j + 1) * ldk + j];
+        const double tail = s2 - x0 * x0;
+        double tj = 0.0, alpha = x0;
+        if (tail > 0.0) {
+            const double sigma = sqrt(s2);
+            alpha = (x0 >= 0.0) ? -sigma : sigma;
+            const double v0 = x0 - alpha;
+            tj = 2.0 / (tail + v0 * v0);
+            if (tid > j && tid < n) vv[tid] = (tid == j + 1) ? v0 : xi;
+        }
+        if (tid == 0) {
+            dd[j] = K[j * ldk + j];
+            ee[j] = alpha;
+            tau[j + 1] = tj;
+        }
+        __syncthreads();
+        if (tj != 0.0) {
+            double pi = 0.0;
+            if (tid > j && tid < n) {
+                for (int k = j + 1; k < n; ++k) pi += K[tid * ldk + k] * vv[k];
+                pi *= tj;
+            }
+            const double mu = 0.5 * tj * wsum64((tid > j && tid < n) ? pi * vv[tid] : 0.0);
+            if (tid > j && tid < n) ww[tid] = pi - mu * vv[tid];
+            __syncthreads();
+            if (tid > j && tid < n) {
+                const double vi = vv[tid], wi = ww[tid];
+                for (int k = j + 1; k < n; ++k) K[tid * ldk + k] -= vi * ww[k] + wi * vv[k];
+            }
+            __syncthreads();
+        }
+        // keep the reflector in column j below the sub-diagonal position (v_{j+1} included)
+        if (tid > j && tid < n) K[tid * ldk + j] = (tj != 0.0) ? vv[tid] : 0.0;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (n >= 2) {
+            dd[n - 2] = K[(n - 2) * ldk + (n - 2)];
+            ee[n - 2] = K[(n - 1) * ldk + (n - 2)];
+            if (n >= 3) tau[n - 1] = 0.0;
+        }
+        dd[n - 1] = K[(n - 1) * ldk + (n - 1)];
+        ee[n - 1] = 0.0;
+    }
+    __syncthreads();
+    // 5. discrepancy principle on the tridiagonal form
+    auto phi = [&](double lam) {
+        // backward sweep: D_i pivots, E_i = D_i - 1, R_1 = sum_{i>=1} (y_i / y_0)^2
+        double D = 1.0 + lam * dd[n - 1], E = lam * dd[n - 1], R = 0.0;
+        for (int i = n - 2; i >= 0; --i) {
+            const double b = lam * ee[i];
+            const double b2 = b * b;
+            R = b2 / (D * D) * (1.0 + R);
+            E = lam * dd[i] - b2 / D;
+            D = 1.0 + E;
+        }
+        return out2 + cn2 * (E * E + R) / (D * D);
+    };
+    const double t2 = scal[1] * scal[1];
+    double lam;
+    int flag = 0;
+    if (lam_fix >= 0.0) {
+        lam = lam_fix;
+    } else {
+        const double scale = trA / fmax(trP, 1e-300);
+        double lo = log(1e-10 * scale), hi = log(1e10 * scale);
+        const double plo = phi(exp(lo)), phh = phi(exp(hi));
+        if (plo >= t2) {
+            lam = exp(lo);
+            flag = NLRMM_ST_DP_LOW;
+        } else if (phh <= t2) {
+            lam = exp(hi);
+            flag = NLRMM_ST_DP_HIGH;
+        } else {
+            for (int round = 0; round < 12; ++round) {
+                const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(TRI_NT + 1);
+                const int above = phi(exp(x)) >= t2;
+                if (tid == 0) sfirst = TRI_NT;
+                __syncthreads();
+                if (above) atomicMin(&sfirst, tid);
+                __syncthreads();
+                const int k = sfirst;
+                const double nlo = (k == 0) ? lo : lo + (hi - lo) * (double)k / (double)(TRI_NT + 1);
+                const double nhi = (k == TRI_NT) ? hi : lo + (hi - lo) * (double)(k + 1) / (double)(TRI_NT + 1);
+                __syncthreads();
+                lo = nlo;
+                hi = nhi;
+                if (hi - lo <= 4e-16 * fmax(1.0, fabs(lo))) break;
+            }
+            lam = exp(0.5 * (lo + hi));
+        }
+    }
+    // 6. y = (I + lam T)^-1 (s ||c|| e1) by a tridiagonal LDL^T solve (one lane)
+    if (tid == 0) {
+        // forward elimination, pivots kept in ww
+        ww[0] = 1.0 + lam * dd[0];
+        yv[0] = sgn * cn;
+        for (int i = 1; i < n; ++i) {
+            const double l = lam * ee[i - 1] / ww[i - 1];
+            ww[i] = 1.0 + lam * dd[i] - l * lam * ee[i - 1];
+            yv[i] = -l * yv[i - 1];
+        }
+        yv[n - 1] /= ww[n - 1];
+        for (int i = n - 2; i >= 0; --i) yv[i] = (yv[i] - lam * ee[i] * yv[i + 1]) / ww[i];
+    }
+    __syncthreads();
+    // apply the tridiagonalisation reflectors in reverse order, then H0
+    for (int j = n - 3; j >= 0; --j) {
+        const double tj = tau[j + 1];
+        if (tj == 0.0) continue;
+        const double vi = (tid > j && tid < n) ? K[tid * ldk + j] : 0.0;
+        const double dot = wsum64(vi * ((tid > j && tid < n) ? yv[tid] : 0.0));
+        __syncthreads();
+        if (tid > j && tid < n) yv[tid] -= tj * dot * vi;
+        __syncthreads();
+    }
+    {
+        const double vi = tid < n ? h0[tid] : 0.0;
+        const double dot = wsum64(vi * (tid < n ? yv[tid] : 0.0));
+        __syncthreads();
+        if (tid < n) yv[tid] -= tau[0] * dot * vi;
+        __syncthreads();
+    }
+    // 7. z = L^-T y
+    for (int j = n - 1; j >= 0; --j) {
+        if (tid == 0) yv[j] /= A[j * lda + j];
+        __syncthreads();
+        for (int i = tid; i < j; i += TRI_NT) yv[i] -= A[j * lda + i] * yv[j];
+        __syncthreads();
+    }
+    for (int i = tid; i < n; i += TRI_NT) z[i] = yv[i];
+    if (tid == 0) {
+        out[0] = lam;
+        out[1] = phi(lam);
+        int st = flag;
+        if (sbad) st |= NLRMM_ST_NONFINITE;
+        if (!isfinite(lam) || !isfinite(out[1])) st |= NLRMM_ST_NONFINITE;
+        if (st) atomicOr(status, st);
+    }
+}
+
 // Compression (Alg. "compress"): S = GA + lam GP = H^T H with H = [RA; sqrt(lam) RP];
 // W = eigenvectors of the kmin-1 largest eigenvalues of S (= dominant right singular
 // vectors of H), sign rule: largest-magnitude entry positive.  c = z - W W^T z; if
@@ -834,10 +1230,15 @@ int k_tv_grad_add(const float *u, const float *w, int nx, int ny, int F, int tem
 }
 
 int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int ny, int F,
-               int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s)
+               int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s, int mode)
 {
     if (ell > GMAX) return NLRMM_ESHAPE;
-    gram_psi_k<<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal, part);
+    if (mode == 1)
+        gram_psi_mfma_k<false><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal, part);
+    else if (mode == 2)
+        gram_psi_mfma_k<true><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal, part);
+    else
+        gram_psi_k<<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal, part);
     reduce_gram_k<<<(unsigned)(ell * ell), 64, 0, s>>>(part, nblk, ell, G, ldg);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
@@ -885,9 +1286,16 @@ int k_normalize_into(const float *r, const double *scal, double tol, int64_t n, 
 }
 
 int k_gks_solve(const double *GA, const double *GP, int ldg, const double *rb, const double *scal,
-                int ell, double lam_fix, double *z, double *out, int *status, hipStream_t s)
+                int ell, double lam_fix, double *z, double *out, int *status, hipStream_t s,
+                int method)
 {
     if (ell < 1 || ell > SOLVE_MAX) return NLRMM_ESHAPE;
+    if (method == 1) {
+        const size_t sh = sizeof(double) * ((size_t)(ell + 1) * (ell + 2) + (size_t)ell * (ell + 1) +
+                                            7 * (size_t)ell);
+        gks_solve_tri_k<<<1, TRI_NT, sh, s>>>(GA, GP, ldg, rb, scal, ell, lam_fix, z, out, status);
+        return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+    }
     const size_t sh = sizeof(double) * (2 * (size_t)ell * (ell + 1) + 4 * ell + 128);
     gks_solve_k<<<1, SOLVE_NT, sh, s>>>(GA, GP, ldg, rb, scal, ell, lam_fix, z, out, status);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;

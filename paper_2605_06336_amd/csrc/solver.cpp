@@ -210,7 +210,7 @@ static int projected_solve(Solver &S, hipStream_t s)
 {
     RC(k_psi_weights(S.u, S.g.nx, S.g.ny, S.F, S.cfg.temporal, (float)S.cfg.eps, S.w, s));
     RC(k_gram_psi(S.V, S.n, S.ell, S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.part_gram,
-                  S.gram_blocks, S.GP, S.ld, s));
+                  S.gram_blocks, S.GP, S.ld, s, S.cfg.gram_precision));
     RC(k_gks_solve(S.GA, S.GP, S.ld, S.rb, S.sc + S_BNORM2, S.ell, S.cfg.lam_fix, S.z,
                    S.sc + S_LAM, S.status, s));
     RC(k_gemv(S.V, S.n, S.ell, S.z, 1.0, nullptr, 0.0, S.n, S.u, s));
@@ -289,7 +289,7 @@ static int varpro_update(Solver &S, const nlrmm_batch &b, double *theta, const f
     const int64_t m = m_of(S, b);
     RC(k_psi_weights(S.u, S.g.nx, S.g.ny, S.F, S.cfg.temporal, (float)S.cfg.eps, S.w, s));
     RC(k_gram_psi(S.V, S.n, k, S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.part_gram,
-                  S.gram_blocks, S.GP, S.ld, s));
+                  S.gram_blocks, S.GP, S.ld, s, S.cfg.gram_precision));
     double *sc = S.sc + S_GN;
     for (int it = 0; it < S.cfg.maxiter_p; ++it) {
         RC(proj_plain(S, b, k, S.V, theta, S.Ahat, s));
@@ -424,6 +424,7 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
     if (c.armijo_trials < 0 || c.armijo_trials > 32 || c.maxiter_p < 0) return NLRMM_EINVAL;
     if (!(c.eps > 0.0) || !(c.tau > 0.0)) return NLRMM_EINVAL;
     if (c.param_update < 0 || c.param_update > 2) return NLRMM_ENOTSUP;
+    if (c.gram_precision < 0 || c.gram_precision > 2) return NLRMM_ENOTSUP;
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
     nlrmm_solver *S = new (std::nothrow) nlrmm_solver();
     if (!S) return NLRMM_ENOMEM;
@@ -617,9 +618,10 @@ int nlrmm_tv_weights(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, in
 
 int nlrmm_gram_psi(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, int32_t temporal,
                    int32_t ell, const float *V, const float *w, double *G, int32_t ldg,
-                   void *stream)
+                   int32_t precision, void *stream)
 {
     if (!ctx || !V || !w || !G) return NLRMM_EINVAL;
+    if (precision < 0 || precision > 2) return NLRMM_ENOTSUP;
     int rc = check_geom(geom);
     if (rc) return rc;
     if (nframes < 1 || ell < 1 || ell > 64 || ldg < ell) return NLRMM_ESHAPE;
@@ -628,7 +630,7 @@ int nlrmm_gram_psi(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, int3
     const int64_t n = (int64_t)nframes * geom->nx * geom->ny;
     if ((rc = scratch_view(ctx, S, n, 1, ell + 1, 2, (hipStream_t)stream))) return rc;
     return k_gram_psi(V, n, ell, w, geom->nx, geom->ny, nframes, temporal, S.part_gram,
-                      S.gram_blocks, G, ldg, (hipStream_t)stream);
+                      S.gram_blocks, G, ldg, (hipStream_t)stream, precision);
 }
 
 int nlrmm_gks_solve(nlrmm_ctx *ctx, int32_t ell, const double *GA, const double *GP,

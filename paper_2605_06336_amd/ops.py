@@ -164,13 +164,14 @@ def tv_weights(u: torch.Tensor, g: Geom, nframes: int = 1, temporal: bool = Fals
 
 
 def gram_psi(V: torch.Tensor, w: torch.Tensor, g: Geom, ell: int, nframes: int = 1,
-             temporal: bool = False) -> torch.Tensor:
-    """(Psi V)^T diag(w) (Psi V) for the first ell columns of V ([>=ell, n] float32)."""
+             temporal: bool = False, precision: int = 0) -> torch.Tensor:
+    """(Psi V)^T diag(w) (Psi V) for the first ell columns of V ([>=ell, n] float32).
+    precision: 0 FP64, 1 FP32 MFMA, 2 BF16 MFMA."""
     _need(V, torch.float32, "V")
     G = torch.empty((ell, ell), dtype=torch.float64, device=V.device)
     check(_lib.lib().nlrmm_gram_psi(context(V.device.index or 0), ctypes.byref(g), nframes,
                                     int(temporal), ell, V.data_ptr(), w.data_ptr(), G.data_ptr(),
-                                    ell, _stream(V.device)), "nlrmm_gram_psi")
+                                    ell, precision, _stream(V.device)), "nlrmm_gram_psi")
     return G
 
 

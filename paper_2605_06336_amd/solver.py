@@ -33,6 +33,7 @@ class Config:
     armijo_trials: int = 10
     breakdown_tol: float = 1e-10
     temporal: int = 0
+    gram_precision: int = 0      # 0 FP64, 1 FP32 MFMA, 2 BF16 MFMA
 
     def struct(self) -> SolverCfg:
         return SolverCfg(**dataclasses.asdict(self))

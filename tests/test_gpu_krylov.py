@@ -56,6 +56,22 @@ def test_tv_weights_and_gram(F, temporal):
     assert rel(G, G_ref) <= 1e-12
 
 
+@pytest.mark.parametrize("ell,F,temporal", [(7, 1, 0), (40, 1, 0), (64, 1, 0), (33, 3, 1)])
+def test_gram_mfma_precisions(ell, F, temporal):
+    """FP32-MFMA and BF16-MFMA regulariser Grams against the FP64 definition."""
+    geo, x, th, rng = small(N=72, nb=103, F=F, temporal=bool(temporal))
+    g = ops.geom(geo.N, geo.nb)
+    u = (x + 0.05 * rng.standard_normal(x.size)).astype(np.float32)
+    w = ops.tv_weights(dev(u, torch.float32), g, geo.F, bool(temporal), eps=1e-3)
+    V = np.linalg.qr(rng.standard_normal((geo.n, ell)))[0].T.astype(np.float32)
+    Vd = dev(V, torch.float32)
+    PV = M.psi_cols(geo, V.T.astype(np.float64))
+    G_ref = PV.T @ (w.cpu().numpy().astype(np.float64)[:, None] * PV)
+    for prec, tol in ((0, 1e-12), (1, 1e-6), (2, 3e-3)):
+        G = ops.gram_psi(Vd, w, g, ell, geo.F, bool(temporal), precision=prec).cpu().numpy()
+        assert rel(G, G_ref) <= tol, (prec, rel(G, G_ref))
+
+
 @pytest.mark.parametrize("ell,noise,lam_fix", [(6, 0.01, -1.0), (20, 0.05, -1.0), (33, 0.01, -1.0),
                                                (12, 0.01, 0.37)])
 def test_gks_solve_matches_oracle(ell, noise, lam_fix):
@@ -159,7 +175,7 @@ def test_gks_expand_and_compress_match_oracle():
     assert rel(AVd[:kmin].cpu().numpy().astype(np.float64).T, AVn @ (Vold.T @ Vn)) <= 1e-5
 
 
-def run_pair(key, N=None, outer=None, kmax=None, trace=False):
+def run_pair(key, N=None, outer=None, kmax=None, trace=False, gram_precision=0):
     wl = synth.WORKLOADS[key]
     inst = synth.draw(wl, N=N)
     N = inst.x_true.shape[-1]
@@ -177,7 +193,8 @@ def run_pair(key, N=None, outer=None, kmax=None, trace=False):
     e = wl.noise * np.linalg.norm(bex) * inst.g / np.linalg.norm(inst.g)
     b_gpu = dev((bex + e).astype(np.float32), torch.float32)
     th = dev(inst.theta_nom, torch.float64)
-    sol = Solver(g, 1, geo.V, Config(kmin=wl.kmin, kmax=kmax, eps=wl.eps))
+    sol = Solver(g, 1, geo.V, Config(kmin=wl.kmin, kmax=kmax, eps=wl.eps,
+                                     gram_precision=gram_precision))
     sol.init(th, b_gpu)
     ora_log = []
     st = M.init_state(geo, inst.theta_nom, b_ora, cfg)
@@ -199,9 +216,11 @@ def run_pair(key, N=None, outer=None, kmax=None, trace=False):
     return out, rre_ora
 
 
-def test_loop_parity_c1():
-    """64x64, 90 views, 91 bins, 20 outer iterations, basis cap 30 (the FP64 CPU workload)."""
-    out, rre = run_pair("c1", trace=True)
+@pytest.mark.parametrize("gram_precision", [0, 1])
+def test_loop_parity_c1(gram_precision):
+    """64x64, 90 views, 91 bins, 20 outer iterations, basis cap 30 (the FP64 CPU workload);
+    regulariser Gram in FP64 on the vector units, or on the FP32 matrix cores."""
+    out, rre = run_pair("c1", trace=True, gram_precision=gram_precision)
     k, du, dth, *_ = out[-1]
     print(f"c1 final: u rel diff {du:.3e}, theta max diff {dth:.3e} rad, oracle RRE {rre:.4f}")
     assert du <= 1e-3
