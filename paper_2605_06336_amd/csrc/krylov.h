@@ -24,7 +24,8 @@ int k_copy_cols(const float *src, int64_t lds, float *dst, int64_t ldd, int ncol
                 hipStream_t s);
 int k_normalize_into(const float *r, const double *scal, double tol, int64_t n, float *vout,
                      int *status, double *norm_out, hipStream_t s);
-// method: 0 Jacobi eigen-decomposition (4 waves), 1 single-wave tridiagonal form
+// method: 0 Jacobi eigen-decomposition (4 waves), 1 register-resident tridiagonal form,
+// 2 LDS tridiagonal form
 int k_gks_solve(const double *GA, const double *GP, int ldg, const double *rb, const double *scal,
                 int ell, double lam_fix, double *z, double *out, int *status, hipStream_t s,
                 int method = 1);

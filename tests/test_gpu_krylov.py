@@ -73,7 +73,8 @@ def test_gram_mfma_precisions(ell, F, temporal):
 
 
 @pytest.mark.parametrize("ell,noise,lam_fix", [(6, 0.01, -1.0), (20, 0.05, -1.0), (33, 0.01, -1.0),
-                                               (12, 0.01, 0.37)])
+                                               (12, 0.01, 0.37), (1, 0.01, -1.0), (2, 0.05, -1.0),
+                                               (47, 0.01, -1.0), (55, 0.01, -1.0)])
 def test_gks_solve_matches_oracle(ell, noise, lam_fix):
     geo, x, th, rng = small()
     b, e = M.make_data(geo, x, th, rng.standard_normal(geo.m), noise)
