@@ -5,15 +5,21 @@ One step = one outer iteration of NL-RMM-GKS (AltMin, per-view angles) on the 25
 expansions, each with a projection and a backprojection), Compress, Gauss-Newton angle
 update with Armijo trials, residual append.  Inputs are resident in HBM before timing.
 
-Also reported: Gsamples/s of the projector family (one sample = one nonzero (ray, pixel)
-weight applied) at the same workload, the roofline of the dominant kernel, and the FP64
-oracle timed on a bounded sample on the host.
+Also reported:
+  * Gsamples/s of the projector family (one sample = one nonzero (ray, pixel) weight
+    applied) at the same workload, per call and per kernel (HIP events on the launch stream);
+  * the roofline of the dominant kernel (the forward-weights kernel of the projection);
+  * outer it/s of the 32-frame dynamic workload, batched (one launch over all frames, the
+    outer iteration replayed as a HIP graph) against plain (per-frame launches, eager), with
+    the difference of the two reconstructions after the same iterations;
+  * the FP64 oracle timed on a bounded sample on the host.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-dynamic]
+       python bench.py --ops-only     (operators and a copy calibration only, for counters)
 """
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -25,7 +31,8 @@ sys.path.insert(0, ROOT)
 
 FP32_NONPACKED_PEAK_TFLOPS = 78.6   # 256 CU x 64 FP32 FMA lanes x 2 flop x 2.4 GHz
 FLOP_PER_SAMPLE = 10.0              # algorithmic FP32 flops per applied strip-area weight
-HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd_edges_c2.json")
+COPY_BYTES = 256 << 20              # calibration copy for the HBM byte counters
 
 
 def parse():
@@ -34,63 +41,50 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dynamic", action="store_true", help="skip the batched-vs-plain leg")
+    ap.add_argument("--ops-only", action="store_true",
+                    help="only the operator timings and the copy calibration")
     ap.add_argument("--reps", type=int, default=20, help="repetitions per operator timing")
-    ap.add_argument("--gram-precision", type=int, default=0, choices=(0, 1, 2),
+    ap.add_argument("--gram-precision", type=int, default=1, choices=(0, 1, 2),
                     help="regulariser Gram: 0 FP64 vector, 1 FP32 MFMA, 2 BF16 MFMA")
     return ap.parse_args()
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no "
-              "multi-GPU mode in this build", file=sys.stderr)
-        sys.exit(2)
-    import torch
-    from paper_2605_06336_amd import metrics, ops, synth
-    from paper_2605_06336_amd.solver import Config, Solver
+def source_digest():
+    """Digest of the projector source: counters recorded for another version are void."""
+    with open(os.path.join(ROOT, "paper_2605_06336_amd", "csrc", "proj.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
-    wl = synth.WORKLOADS["c2"]
-    inst = synth.draw(wl)
-    N, nb, V = wl.N, wl.nb, wl.n_views
-    g = ops.geom(N, nb)
+
+def make_data(torch, ops, inst, wl, g, fr=None):
     dev = torch.device("cuda", 0)
-    stream = torch.cuda.current_stream(dev)
     x32 = torch.as_tensor(inst.x_true.astype(np.float32), device=dev)
     th_true = torch.as_tensor(inst.theta_true, device=dev)
-    bex = ops.project(x32, th_true, g).cpu().numpy().reshape(-1).astype(np.float64)
+    bex = ops.project(x32, th_true, g, fr).cpu().numpy().reshape(-1).astype(np.float64)
     e = wl.noise * np.linalg.norm(bex) * inst.g / np.linalg.norm(inst.g)
-    delta = float(np.linalg.norm(e))
     b = torch.as_tensor((bex + e).astype(np.float32), device=dev)
-    theta = torch.as_tensor(inst.theta_nom.copy(), device=dev)
+    return x32, th_true, b, float(np.linalg.norm(e))
 
-    cfg = Config(kmin=wl.kmin, kmax=wl.kmax, eps=wl.eps, gram_precision=args.gram_precision)
-    sol = Solver(g, 1, V, cfg)
-    sol.init(theta, b)
-    for _ in range(args.warmup):
-        sol.outer(theta, b, delta)
+
+def timed_steps(torch, step, steps, stream, label):
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
-    for k in range(args.steps):
-        sol.outer(theta, b, delta)
-        print(f"# step {k + 1}/{args.steps} enqueued", file=sys.stderr, flush=True)
+    for k in range(steps):
+        step()
+        print(f"# {label} step {k + 1}/{steps} enqueued", file=sys.stderr, flush=True)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gpu_ms = e0.elapsed_time(e1)
-    ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
-    u, sc, status = sol.read()
-    torch.cuda.synchronize()
-    x_true = inst.x_true.reshape(-1)
-    rre = float(np.linalg.norm(u.cpu().numpy() - x_true) / np.linalg.norm(x_true))
-    dth0 = inst.theta_true - inst.theta_nom
-    perr = float(np.linalg.norm(theta.cpu().numpy() - inst.theta_true) / np.linalg.norm(dth0))
-    sol.close()
+    return max(e0.elapsed_time(e1), wall * 1e3) / steps
 
-    # ---- projector family at the same workload -------------------------------------
+
+def operators(torch, ops, metrics, inst, wl, g, x32, th_true, b, reps, stream):
+    """Per-call and per-kernel times of project / backproject / dtheta at one workload."""
+    dev = x32.device
+    N, nb, V = wl.N, wl.nb, wl.n_views
     nnz = metrics.nnz(N, nb, inst.theta_true)
     y = torch.empty((1, V, nb), dtype=torch.float32, device=dev)
     xb = torch.empty((1, 1, N, N), dtype=torch.float32, device=dev)
@@ -102,42 +96,170 @@ def main():
         a0 = torch.cuda.Event(enable_timing=True)
         a1 = torch.cuda.Event(enable_timing=True)
         a0.record(stream)
-        for _ in range(args.reps):
+        for _ in range(reps):
             fn()
         a1.record(stream)
         torch.cuda.synchronize()
-        return a0.elapsed_time(a1) / args.reps
+        return a0.elapsed_time(a1) / reps
 
-    t_proj = timed(lambda: ops.project(x32, th_true, g, out=y))
-    t_back = timed(lambda: ops.backproject(ysrc, th_true, g, out=xb))
-    t_dth = timed(lambda: ops.project_dtheta(x32, th_true, g, want_dy=True))
-    gs = {
-        "project": nnz / (t_proj * 1e-3) / 1e9,
-        "backproject": nnz / (t_back * 1e-3) / 1e9,
-        "dtheta": nnz / (t_dth * 1e-3) / 1e9,
-    }
-    # dominant kernel: the backprojection (one kernel per call; launched as often as the
-    # projection in every Krylov expansion and once more per outer iteration)
-    dom_ms = t_back
-    achieved = nnz * FLOP_PER_SAMPLE / (dom_ms * 1e-3) / 1e12
-    roofline = {
-        "bound": "alu",
-        "kernel": "bwd_tiles_k (nlrmm_backproject)",
-        "achieved": round(achieved, 3),
-        "peak": FP32_NONPACKED_PEAK_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(achieved / FP32_NONPACKED_PEAK_TFLOPS, 4),
-        "traffic": None,
-        "launch_ms": round(dom_ms, 5),
-        "samples_per_launch": int(nnz),
-    }
+    def kernel_avg(fn, which):
+        tot = 0.0
+        for _ in range(reps):
+            fn()
+            tot += ops.kernel_ms(which)
+        return tot / reps
 
-    # ---- FP64 oracle on a bounded sample ---------------------------------------------
+    proj = lambda: ops.project(x32, th_true, g, out=y)              # noqa: E731
+    back = lambda: ops.backproject(ysrc, th_true, g, out=xb)        # noqa: E731
+    dth = lambda: ops.project_dtheta(x32, th_true, g, want_dy=True)  # noqa: E731
+    call_ms = {"project": timed(proj), "backproject": timed(back), "dtheta": timed(dth)}
+    ops.set_kernel_timing(True)
+    proj()
+    back()
+    kern_ms = {"fwd_edges_k": kernel_avg(proj, "project"),
+               "bwd_tiles_k": kernel_avg(back, "backproject")}
+    ops.set_kernel_timing(False)
+    return nnz, call_ms, kern_ms
+
+
+def copy_calibration(torch):
+    """A plain device copy of known size: the scale of the HBM byte counters."""
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def traffic_for(kernel):
+    """HBM bytes per launch of `kernel` from committed counter runs, or None when absent or
+    recorded for another version of the projector source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("source_sha") != source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def dynamic_leg(torch, ops, synth, Config, OuterGraph, Solver, steps, warmup, gram_precision):
+    """Outer it/s of the 32-frame dynamic workload: batched + graph replay vs plain."""
+    wl = synth.WORKLOADS["c4"]
+    inst = synth.draw(wl)
+    fr = ops.Frames(inst.view_off)
+    g = ops.geom(wl.N, wl.nb)
+    _, _, b, delta = make_data(torch, ops, inst, wl, g, fr)
+    stream = torch.cuda.current_stream()
+    V = int(inst.view_off[-1])
+    out = {}
+    us = {}
+    for mode in ("plain", "batched"):
+        cfg = Config(kmin=wl.kmin, kmax=wl.kmax, eps=wl.eps, temporal=1,
+                     gram_precision=gram_precision)
+        sol = Solver(g, wl.frames, V, cfg)
+        if mode == "plain":
+            sol.set_per_frame(inst.view_off)
+        th = torch.as_tensor(inst.theta_nom.copy(), device="cuda")
+        sol.init(th, b, fr)
+        for _ in range(warmup):
+            sol.outer(th, b, delta, fr)
+        if mode == "batched":
+            gr = OuterGraph(sol, th, b, delta, fr)
+            step = gr.replay
+        else:
+            step = lambda: sol.outer(th, b, delta, fr)   # noqa: E731
+        ms = timed_steps(torch, step, steps, stream, f"dynamic {mode}")
+        u, _, status = sol.read()
+        torch.cuda.synchronize()
+        us[mode] = u.cpu().numpy().astype(np.float64)
+        x_true = inst.x_true.reshape(-1)
+        out[mode] = {"outer_it_s": round(1000.0 / ms, 4), "ms_per_step": round(ms, 3),
+                     "rre": round(float(np.linalg.norm(us[mode] - x_true) /
+                                        np.linalg.norm(x_true)), 5),
+                     "status": int(status.cpu()[0])}
+        sol.close()
+    out["speedup"] = round(out["batched"]["outer_it_s"] / out["plain"]["outer_it_s"], 3)
+    out["u_rel_diff_batched_vs_plain"] = float(
+        np.linalg.norm(us["batched"] - us["plain"]) / np.linalg.norm(us["plain"]))
+    out["workload"] = (f"c4: 32 frames of 256x256 (moving ellipses), {V} views in total "
+                       f"(30..120 per frame, golden-angle), 363 bins, 2% noise, ANISO-TV with "
+                       f"frame differences, kmin {wl.kmin} kmax {wl.kmax}; "
+                       f"{warmup} warm-up + {steps} timed outer iterations per mode")
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build "
+              "measures the path on a single device and has no multi-GPU mode", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2605_06336_amd import metrics, ops, synth
+    from paper_2605_06336_amd.solver import Config, OuterGraph, Solver
+
+    wl = synth.WORKLOADS["c2"]
+    inst = synth.draw(wl)
+    V = wl.n_views
+    g = ops.geom(wl.N, wl.nb)
+    stream = torch.cuda.current_stream()
+    x32, th_true, b, delta = make_data(torch, ops, inst, wl, g)
+
+    if args.ops_only:
+        nnz, call_ms, kern_ms = operators(torch, ops, metrics, inst, wl, g, x32, th_true, b,
+                                          args.reps, stream)
+        copy_calibration(torch)
+        print(json.dumps({"ops_only": True, "nnz": int(nnz), "call_ms": call_ms,
+                          "kernel_ms": kern_ms, "copy_bytes": COPY_BYTES,
+                          "source_sha": source_digest()}), flush=True)
+        return
+
+    theta = torch.as_tensor(inst.theta_nom.copy(), device="cuda")
+    cfg = Config(kmin=wl.kmin, kmax=wl.kmax, eps=wl.eps, gram_precision=args.gram_precision)
+    sol = Solver(g, 1, V, cfg)
+    sol.init(theta, b)
+    for _ in range(args.warmup):
+        sol.outer(theta, b, delta)
+    ms_per_step = timed_steps(torch, lambda: sol.outer(theta, b, delta), args.steps, stream,
+                              "c2")
+    u, sc, status = sol.read()
+    torch.cuda.synchronize()
+    x_true = inst.x_true.reshape(-1)
+    rre = float(np.linalg.norm(u.cpu().numpy() - x_true) / np.linalg.norm(x_true))
+    dth0 = inst.theta_true - inst.theta_nom
+    perr = float(np.linalg.norm(theta.cpu().numpy() - inst.theta_true) / np.linalg.norm(dth0))
+    sol.close()
+
+    nnz, call_ms, kern_ms = operators(torch, ops, metrics, inst, wl, g, x32, th_true, b,
+                                      args.reps, stream)
+    gs = {k: round(nnz / (v * 1e-3) / 1e9, 2) for k, v in call_ms.items()}
+    gs_kernel = {k: round(nnz / (v * 1e-3) / 1e9, 2) for k, v in kern_ms.items()}
+
+    def roof(kernel, ms):
+        achieved = nnz * FLOP_PER_SAMPLE / (ms * 1e-3) / 1e12
+        return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3),
+                "peak": FP32_NONPACKED_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_NONPACKED_PEAK_TFLOPS, 4),
+                "traffic": traffic_for(kernel), "launch_ms": round(ms, 5),
+                "samples_per_launch": int(nnz), "flop_per_sample": FLOP_PER_SAMPLE}
+
+    # dominant kernel of the outer iteration: the forward-weights kernel of the projection
+    roofline = roof("fwd_edges_k", kern_ms["fwd_edges_k"])
+    roofline_bwd = roof("bwd_tiles_k", kern_ms["bwd_tiles_k"])
+
+    dyn = None
+    if not args.no_dynamic:
+        dyn = dynamic_leg(torch, ops, synth, Config, OuterGraph, Solver, max(3, args.steps // 2),
+                          2, args.gram_precision)
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import method as OM
         from oracle import projector as OP
-        geo = OM.Geometry(N=N, nb=nb, view_off=inst.view_off)
+        geo = OM.Geometry(N=wl.N, nb=wl.nb, view_off=inst.view_off)
         b_ora, e_ora = OM.make_data(geo, x_true, inst.theta_true, inst.g, wl.noise)
         ocfg = OM.Config(kmin=wl.kmin, kmax=wl.kmax, eps=wl.eps)
         st = OM.init_state(geo, inst.theta_nom, b_ora, ocfg)
@@ -146,8 +268,8 @@ def main():
         csec = time.perf_counter() - c0
         cpu = {"value": round(1.0 / csec, 5), "unit": "outer it/s", "cores": OP.max_threads(),
                "kind": "oracle",
-               "sample": f"one outer iteration (first after the GKB start basis) of the same "
-                         f"workload, {csec:.1f} s"}
+               "sample": f"one outer iteration (the first after the GKB start basis) of the "
+                         f"same 256x256 / 360-view workload in FP64 on the host, {csec:.1f} s"}
 
     out = {
         "metric": "proj+backproj+∂θ Gsamples/s & outer it/s, batched vs plain, relL2≤1e-5",
@@ -164,16 +286,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": "c2-256px-360v: 256x256 image of 25 seeded ellipses, 360 views "
                                "(nominal + N(0,1 deg)), 363 bins, 1% noise, AltMin NL-RMM-GKS "
-                               "kmin 5 kmax 40, TV, discrepancy principle",
+                               "kmin 5 kmax 40, TV, discrepancy principle, FP32 projector, "
+                               f"regulariser Gram precision {args.gram_precision}, FP64 "
+                               "projected solves",
                    "global_batch": 1, "parallelism": "none"},
-        "gsamples_per_s": {k: round(v, 2) for k, v in gs.items()},
-        "operator_ms": {"project": round(t_proj, 5), "backproject": round(t_back, 5),
-                        "dtheta": round(t_dth, 5)},
+        "gsamples_per_s": gs,
+        "gsamples_per_s_kernel": gs_kernel,
+        "operator_ms": {k: round(v, 5) for k, v in call_ms.items()},
+        "kernel_ms": {k: round(v, 5) for k, v in kern_ms.items()},
         "nnz": int(nnz),
         "quality": {"rre": round(rre, 5), "angle_err_rel": round(perr, 5),
                     "outer_done": args.warmup + args.steps,
                     "lambda": float(sc.cpu().numpy()[2]), "status": int(status.cpu()[0])},
+        "batched_vs_plain": dyn,
         "roofline": roofline,
+        "roofline_backproject": roofline_bwd,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -82,6 +82,16 @@ int nlrmm_version(void);
 int nlrmm_ctx_create(nlrmm_ctx **out, int device);
 void nlrmm_ctx_destroy(nlrmm_ctx *ctx);
 
+/* Measurement aid (no part of the method).  With timing enabled, every projection records a
+ * pair of HIP events on its launch stream around its forward-weights kernel (which = 0), and
+ * every backprojection around its pixel-tile kernel (which = 1); the pair of the most recent
+ * launch is kept (for a multi-group projection, the last group's).  nlrmm_ctx_kernel_ms waits
+ * for that launch's stop event and returns its duration in milliseconds; NLRMM_EINVAL if no
+ * such launch has been recorded since timing was enabled.  Events are created by
+ * nlrmm_ctx_set_timing (so enable it outside graph capture) and freed by nlrmm_ctx_destroy. */
+int nlrmm_ctx_set_timing(nlrmm_ctx *ctx, int enable);
+int nlrmm_ctx_kernel_ms(nlrmm_ctx *ctx, int which, float *ms);
+
 /* Forward projection y = A(theta) x (the forward operator H(p)u of Section 1,
  * eq. "nonlinear_forward"; applied to every column for the basis block A V of
  * Section 3.2).

@@ -50,6 +50,8 @@ class SolverCfg(ctypes.Structure):
 SIGNATURES = {
     "nlrmm_version": [],
     "nlrmm_ctx_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int],
+    "nlrmm_ctx_set_timing": [_P, _I32],
+    "nlrmm_ctx_kernel_ms": [_P, _I32, ctypes.POINTER(ctypes.c_float)],
     "nlrmm_project": [_P, _GP, _BP, _I32, _P, _P, _P, _P],
     "nlrmm_backproject": [_P, _GP, _BP, _I32, _P, _P, _P, _P],
     "nlrmm_project_dtheta": [_P, _GP, _BP, _I32, _P, _P, _P, _P, _P, _P, _P, _P],

@@ -54,6 +54,13 @@ int check_batch(const nlrmm_batch *b)
     return NLRMM_OK;
 }
 
+
+void timing_mark(nlrmm_ctx *ctx, int which, int stop, hipStream_t s)
+{
+    if (!ctx->timing) return;
+    if (hipEventRecord(ctx->tev[which][stop], s) == hipSuccess && stop) ctx->tev_set[which] = 1;
+}
+
 }  // namespace nlrmm
 
 using namespace nlrmm;
@@ -91,9 +98,37 @@ int nlrmm_ctx_create(nlrmm_ctx **out, int device)
     return NLRMM_OK;
 }
 
+int nlrmm_ctx_set_timing(nlrmm_ctx *ctx, int enable)
+{
+    if (!ctx) return NLRMM_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    if (enable && !ctx->timing) {
+        for (auto &pr : ctx->tev)
+            for (auto &e : pr)
+                if (!e && hipEventCreate(&e) != hipSuccess) return NLRMM_EHIP;
+        ctx->tev_set[0] = ctx->tev_set[1] = 0;
+    }
+    ctx->timing = enable ? 1 : 0;
+    return NLRMM_OK;
+}
+
+int nlrmm_ctx_kernel_ms(nlrmm_ctx *ctx, int which, float *ms)
+{
+    if (!ctx || !ms || which < 0 || which > 1) return NLRMM_EINVAL;
+    if (!ctx->tev_set[which]) return NLRMM_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    if (hipEventSynchronize(ctx->tev[which][1]) != hipSuccess) return NLRMM_EHIP;
+    if (hipEventElapsedTime(ms, ctx->tev[which][0], ctx->tev[which][1]) != hipSuccess)
+        return NLRMM_EHIP;
+    return NLRMM_OK;
+}
+
 void nlrmm_ctx_destroy(nlrmm_ctx *ctx)
 {
     if (!ctx) return;
+    for (auto &pr : ctx->tev)
+        for (auto &e : pr)
+            if (e) (void)hipEventDestroy(e);
     if (ctx->ws.ptr || ctx->kws.ptr) (void)hipDeviceSynchronize();
     if (ctx->ws.ptr) (void)hipFree(ctx->ws.ptr);
     if (ctx->kws.ptr) (void)hipFree(ctx->kws.ptr);

@@ -27,6 +27,10 @@ struct nlrmm_ctx {
     nlrmm::Workspace ws;    // projector packs (reused by every projection)
     nlrmm::Workspace kws;   // scratch of the standalone Krylov entry points
     int cu_count = 256;
+    // optional event timing of the dominant projector kernels (measurement aid)
+    int timing = 0;
+    hipEvent_t tev[2][2] = {};   // [kernel][start, stop]; 0 forward weights, 1 backprojection
+    int tev_set[2] = {0, 0};
 };
 
 namespace nlrmm {
@@ -36,6 +40,9 @@ int ensure_workspace(nlrmm_ctx *ctx, size_t bytes, hipStream_t stream);
 int ensure_buffer(Workspace &w, size_t bytes, hipStream_t stream);
 
 int check_geom(const nlrmm_geom *g);
+
+// Record the start / stop event of timed kernel `which` on stream s (no-op unless enabled).
+void timing_mark(nlrmm_ctx *ctx, int which, int stop, hipStream_t s);
 int check_batch(const nlrmm_batch *b);
 
 // Forward-kernel outputs and modes (see proj.hip).

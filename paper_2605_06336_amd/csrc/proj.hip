@@ -709,9 +709,11 @@ int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
         a.write_resid = o.write_resid ? 1 : 0;
         const int NC = nc >= 8 ? 8 : nc >= 4 ? 4 : nc >= 2 ? 2 : 1;
         dim3 grid((unsigned)(V * nchunks), (unsigned)((nc + NC - 1) / NC));
+        timing_mark(ctx, 0, 0, s);
         if (proj && mom) launch_fwd_mode<3>(NC, grid, a, s);
         else if (mom) launch_fwd_mode<2>(NC, grid, a, s);
         else launch_fwd_mode<1>(NC, grid, a, s);
+        timing_mark(ctx, 0, 1, s);
     }
     if (red && (o.gdot || o.dnorm2 || o.rnorm2) && !o.keep_parts) {
         const int64_t n = (int64_t)ncols * V;
@@ -787,12 +789,14 @@ int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b
     const int tiles_y = (g.ny + TILE - 1) / TILE;
     dim3 grid((unsigned)(a.tiles_x * tiles_y), (unsigned)((int64_t)ncols * b.nframes),
               (unsigned)a.nsplit);
+    timing_mark(ctx, 1, 0, s);
     switch (E) {
         case 1: bwd_tiles_k<1><<<grid, BLK, 0, s>>>(a); break;
         case 2: bwd_tiles_k<2><<<grid, BLK, 0, s>>>(a); break;
         case 3: bwd_tiles_k<3><<<grid, BLK, 0, s>>>(a); break;
         default: bwd_tiles_k<4><<<grid, BLK, 0, s>>>(a); break;
     }
+    timing_mark(ctx, 1, 1, s);
     if (a.nsplit > 1) {
         const int64_t n = (int64_t)ncols * b.nframes * g.nx * g.ny;
         sum_splits_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a.part, a.nsplit, n, x, accumulate);

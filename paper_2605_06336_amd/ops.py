@@ -26,6 +26,20 @@ def context(device: int = 0) -> int:
     return _ctx[device]
 
 
+def set_kernel_timing(enable: bool, device: int = 0) -> None:
+    """Enable event timing of the forward-weights and backprojection kernels (measurement)."""
+    check(_lib.lib().nlrmm_ctx_set_timing(context(device), int(enable)), "nlrmm_ctx_set_timing")
+
+
+def kernel_ms(which: str, device: int = 0) -> float:
+    """Duration of the most recent 'project' (forward-weights) or 'backproject' (pixel-tile)
+    kernel launch, from HIP events on its launch stream; waits for that launch."""
+    ms = ctypes.c_float()
+    check(_lib.lib().nlrmm_ctx_kernel_ms(context(device), {"project": 0, "backproject": 1}[which],
+                                         ctypes.byref(ms)), "nlrmm_ctx_kernel_ms")
+    return float(ms.value)
+
+
 def geom(N: int, nb: int, ny: Optional[int] = None, half: float = 1.0,
          s_half: float = 1.42) -> Geom:
     """Square-pixel grid on [-half, half] along x (N pixels) and detector [-s_half, s_half]."""
