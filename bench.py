@@ -145,15 +145,30 @@ def traffic_for(kernel):
     return rec.get("bytes_per_launch")
 
 
+def autotune(torch, ops, g, x, theta, b, kmin, fr=None):
+    """Tune the projector launch shapes for the column counts the solver uses (one column for
+    the Krylov expansions, kmin + 1 for the rebase) and for the backprojection."""
+    npix = g.nx * g.ny * (fr.nframes if fr is not None else 1)
+    xs = x.reshape(-1)[:npix]
+    ops.autotune_project(xs, theta, g, fr)
+    ops.autotune_project(xs.repeat(kmin + 1), theta, g, fr)
+    ops.autotune_backproject(b, theta, g, fr)
+    V = theta.numel()
+    return {"fwd_waves_per_block_1col": ops.tune_query("project", g, V, 1, fr),
+            f"fwd_waves_per_block_{kmin + 1}col": ops.tune_query("project", g, V, kmin + 1, fr),
+            "bwd_view_split": ops.tune_query("backproject", g, V, 1, fr)}
+
+
 def dynamic_leg(torch, ops, synth, Config, OuterGraph, Solver, steps, warmup, gram_precision):
     """Outer it/s of the 32-frame dynamic workload: batched + graph replay vs plain."""
     wl = synth.WORKLOADS["c4"]
     inst = synth.draw(wl)
     fr = ops.Frames(inst.view_off)
     g = ops.geom(wl.N, wl.nb)
-    _, _, b, delta = make_data(torch, ops, inst, wl, g, fr)
+    x32, th_true, b, delta = make_data(torch, ops, inst, wl, g, fr)
     stream = torch.cuda.current_stream()
     V = int(inst.view_off[-1])
+    tuned = autotune(torch, ops, g, x32, th_true, b, wl.kmin, fr)
     out = {}
     us = {}
     for mode in ("plain", "batched"):
@@ -184,6 +199,7 @@ def dynamic_leg(torch, ops, synth, Config, OuterGraph, Solver, steps, warmup, gr
     out["speedup"] = round(out["batched"]["outer_it_s"] / out["plain"]["outer_it_s"], 3)
     out["u_rel_diff_batched_vs_plain"] = float(
         np.linalg.norm(us["batched"] - us["plain"]) / np.linalg.norm(us["plain"]))
+    out["autotune_batched"] = tuned
     out["workload"] = (f"c4: 32 frames of 256x256 (moving ellipses), {V} views in total "
                        f"(30..120 per frame, golden-angle), 363 bins, 2% noise, ANISO-TV with "
                        f"frame differences, kmin {wl.kmin} kmax {wl.kmax}; "
@@ -207,12 +223,13 @@ def main():
     g = ops.geom(wl.N, wl.nb)
     stream = torch.cuda.current_stream()
     x32, th_true, b, delta = make_data(torch, ops, inst, wl, g)
+    tuned = autotune(torch, ops, g, x32, th_true, b, wl.kmin)
 
     if args.ops_only:
         nnz, call_ms, kern_ms = operators(torch, ops, metrics, inst, wl, g, x32, th_true, b,
                                           args.reps, stream)
         copy_calibration(torch)
-        print(json.dumps({"ops_only": True, "nnz": int(nnz), "call_ms": call_ms,
+        print(json.dumps({"ops_only": True, "autotune": tuned, "nnz": int(nnz), "call_ms": call_ms,
                           "kernel_ms": kern_ms, "copy_bytes": COPY_BYTES,
                           "source_sha": source_digest()}), flush=True)
         return
@@ -298,6 +315,7 @@ def main():
         "quality": {"rre": round(rre, 5), "angle_err_rel": round(perr, 5),
                     "outer_done": args.warmup + args.steps,
                     "lambda": float(sc.cpu().numpy()[2]), "status": int(status.cpu()[0])},
+        "autotune": tuned,
         "batched_vs_plain": dyn,
         "roofline": roofline,
         "roofline_backproject": roofline_bwd,

@@ -82,6 +82,29 @@ int nlrmm_version(void);
 int nlrmm_ctx_create(nlrmm_ctx **out, int device);
 void nlrmm_ctx_destroy(nlrmm_ctx *ctx);
 
+/* Autotuner of the projector launch shapes (the batching design: tile and ray-block shapes
+ * chosen by measurement).  nlrmm_autotune_project computes y = A(theta) x exactly like
+ * nlrmm_project while timing each forward block shape (1, 2, 4 or 8 waves sharing each
+ * detector edge's image lines) with HIP events on `stream`, and keeps the fastest for this
+ * geometry, batch and column-group size in the context; nlrmm_autotune_backproject does the
+ * same for the backprojection's view split (1, 2, 4 or 8 partial images, bounded by 16 views
+ * per split and frame) and leaves x = A(theta)^T y.  Candidates differ only in the order of
+ * FP64 partial sums.  Both synchronize `stream` and return NLRMM_EINVAL while it is being
+ * captured.  Later calls with the same shapes (operators, solver, graph captures) use the
+ * choice.  nlrmm_ctx_set_tune_file loads choices stored in `path` (lines of
+ * "kind nx ny nbins nframes nviews ncols choice"; kind 0 forward, 1 backprojection) and appends
+ * every new choice there; NULL stops appending.  nlrmm_tune_query returns the stored choice
+ * for a shape in *choice (0 when none: the built-in default is used). */
+int nlrmm_autotune_project(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                           int32_t ncols, const float *x, const double *theta, float *y,
+                           void *stream);
+int nlrmm_autotune_backproject(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                               int32_t ncols, const float *y, const double *theta, float *x,
+                               void *stream);
+int nlrmm_ctx_set_tune_file(nlrmm_ctx *ctx, const char *path);
+int nlrmm_tune_query(nlrmm_ctx *ctx, int32_t kind, const nlrmm_geom *geom,
+                     const nlrmm_batch *batch, int32_t ncols, int32_t *choice);
+
 /* Measurement aid (no part of the method).  With timing enabled, every projection records a
  * pair of HIP events on its launch stream around its forward-weights kernel (which = 0), and
  * every backprojection around its pixel-tile kernel (which = 1); the pair of the most recent

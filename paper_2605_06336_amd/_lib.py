@@ -51,6 +51,10 @@ SIGNATURES = {
     "nlrmm_version": [],
     "nlrmm_ctx_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int],
     "nlrmm_ctx_set_timing": [_P, _I32],
+    "nlrmm_autotune_project": [_P, _GP, _BP, _I32, _P, _P, _P, _P],
+    "nlrmm_autotune_backproject": [_P, _GP, _BP, _I32, _P, _P, _P, _P],
+    "nlrmm_ctx_set_tune_file": [_P, ctypes.c_char_p],
+    "nlrmm_tune_query": [_P, _I32, _GP, _BP, _I32, ctypes.POINTER(ctypes.c_int32)],
     "nlrmm_ctx_kernel_ms": [_P, _I32, ctypes.POINTER(ctypes.c_float)],
     "nlrmm_project": [_P, _GP, _BP, _I32, _P, _P, _P, _P],
     "nlrmm_backproject": [_P, _GP, _BP, _I32, _P, _P, _P, _P],

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnlrmm.so")
-SOURCES = ["api.cpp", "proj.hip", "krylov.hip", "gn.hip", "varpro.hip", "solver.cpp"]
+SOURCES = ["api.cpp", "proj.hip", "krylov.hip", "gn.hip", "varpro.hip", "solver.cpp", "tune.cpp"]
 ARCH = os.environ.get("NLRMM_ARCH", "gfx950")
 
 FLAGS = [

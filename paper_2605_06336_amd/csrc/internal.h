@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
+
+#include <string>
+#include <vector>
 #include "../../include/nlrmm.h"
 
 namespace nlrmm {
@@ -20,6 +23,14 @@ struct Workspace {
     size_t bytes = 0;
 };
 
+// Launch-shape cache of the autotuner: one entry per operator kind and problem shape.
+enum TuneKind { TUNE_FWD_SEG = 0, TUNE_BWD_SPLIT = 1 };
+struct TuneEntry {
+    int kind, nx, ny, nb, nframes, nc;
+    int64_t nviews;
+    int choice;
+};
+
 }  // namespace nlrmm
 
 struct nlrmm_ctx {
@@ -31,6 +42,11 @@ struct nlrmm_ctx {
     int timing = 0;
     hipEvent_t tev[2][2] = {};   // [kernel][start, stop]; 0 forward weights, 1 backprojection
     int tev_set[2] = {0, 0};
+    // autotuner: cached launch shapes, a candidate forced while tuning, optional cache file
+    std::vector<nlrmm::TuneEntry> tune;
+    int force_fwd_seg = 0;
+    int force_bwd_split = 0;
+    std::string tune_path;
 };
 
 namespace nlrmm {
@@ -40,6 +56,16 @@ int ensure_workspace(nlrmm_ctx *ctx, size_t bytes, hipStream_t stream);
 int ensure_buffer(Workspace &w, size_t bytes, hipStream_t stream);
 
 int check_geom(const nlrmm_geom *g);
+
+// Autotuner cache: the tuned choice for a shape (0 when none) and storing a new one.
+int tune_lookup(const nlrmm_ctx *ctx, int kind, const nlrmm_geom &g, const nlrmm_batch &b, int nc);
+void tune_store(nlrmm_ctx *ctx, int kind, const nlrmm_geom &g, const nlrmm_batch &b, int nc,
+                int choice);
+// Forward: waves per block sharing an edge's lines (1, 2, 4 or 8); column bucket of a group.
+int fwd_seg_for(const nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int nc_bucket);
+int fwd_nc_bucket(int nc);
+// Backprojection: candidates of the view split and the largest one (workspace bound).
+int bwd_split_max(const nlrmm_geom &g, const nlrmm_batch &b);
 
 // Record the start / stop event of timed kernel `which` on stream s (no-op unless enabled).
 void timing_mark(nlrmm_ctx *ctx, int which, int stop, hipStream_t s);

@@ -31,7 +31,8 @@ namespace nlrmm {
 namespace {
 
 constexpr int BLK = 256;          // threads per block: four wave64
-constexpr int BINS = BLK - 1;     // bins produced per forward block (BLK edges)
+constexpr int BINS = 63;          // bins produced per forward block (64 edges, one per lane)
+constexpr int FSEG_DEFAULT = 4;   // forward: waves per block sharing each edge's lines
 constexpr int TILE = 16;          // backward tile side
 constexpr int VCHUNK = 32;        // views staged per backward chunk
 constexpr int WMAX = 64;          // max staged bins per view (backward)
@@ -261,17 +262,17 @@ struct FwdArgs {
     int write_resid;        // with bres: store y - b into y
 };
 
-template <int MODE, int NC>
-__global__ __launch_bounds__(BLK) void fwd_edges_k(FwdArgs a)
+template <int MODE, int NC, int FSEG>
+__global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
 {
     constexpr bool PROJ = (MODE & 1) != 0;
     constexpr bool MOM = (MODE & 2) != 0;
-    __shared__ double sC[PROJ ? NC : 1][BLK];
-    __shared__ double sM[MOM ? NC : 1][BLK];
-    __shared__ double sred[3][BLK / 64];
+    __shared__ double sC[PROJ ? NC : 1][FSEG][64];
+    __shared__ double sM[MOM ? NC : 1][FSEG][64];
 
     if (a.skip != nullptr && *a.skip != 0) return;   // uniform over the launch
     const int tid = threadIdx.x;
+    const int lane = tid & 63, seg = tid >> 6;
     const int64_t v = blockIdx.x / a.nchunks;
     const int q = (int)(blockIdx.x - v * a.nchunks);
     const int c0 = blockIdx.y * NC;
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(BLK) void fwd_edges_k(FwdArgs a)
     const int f = frame_of(a.view_off, a.nframes, v);
     const double th = a.tdir != nullptr ? a.theta[v] + a.talpha[0] * a.tdir[v] : a.theta[v];
     const ViewC w = make_view(th, a.d);
-    const int64_t j = (int64_t)q * BINS + tid;
+    const int64_t j = (int64_t)q * BINS + lane;
 
     const bool steep = w.steep != 0;
     const int nlines = steep ? a.ny : a.nx;
@@ -323,7 +324,11 @@ __global__ __launch_bounds__(BLK) void fwd_edges_k(FwdArgs a)
             lb = min(max((int)ceil(hi) + 1, -1), nlines - 1);
         }
         const PackEntry *pimg = pack + img0 * pstride;
-        for (int L = la; L <= lb; ++L) {
+        // this wave's contiguous share of the edge's line range
+        const int len = lb - la + 1;
+        const int sa = len > 0 ? la + (len * seg) / FSEG : la;
+        const int sb = len > 0 ? la + (len * (seg + 1)) / FSEG - 1 : lb;
+        for (int L = sa; L <= sb; ++L) {
             const double lc = pix_coord(line0, a.d, L);
             const double base = __dsub_rn(e, __dmul_rn(lc, sl));
             double tf = floor((base - w.wo - cw0) * inv_step);
@@ -365,7 +370,7 @@ __global__ __launch_bounds__(BLK) void fwd_edges_k(FwdArgs a)
                 }
             }
         }
-        if (PROJ) {
+        if (PROJ && seg == 0) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 if (c < nc) {
@@ -382,13 +387,24 @@ __global__ __launch_bounds__(BLK) void fwd_edges_k(FwdArgs a)
     const double d2 = a.d * a.d;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        if (PROJ) sC[c][tid] = d2 * accP[c] + accF[c];
-        if (MOM) sM[c][tid] = accM[c];
+        if (PROJ) sC[c][seg][lane] = d2 * accP[c] + accF[c];
+        if (MOM) sM[c][seg][lane] = accM[c];
     }
     __syncthreads();
-
-    const int64_t jb = (int64_t)q * BINS + tid;
-    const bool has_bin = tid < BINS && jb < a.nb;
+    if (seg != 0) return;
+    // wave 0: C(e) of its 64 edges (segments summed in a fixed order), then 63 bins
+    double Ce[NC], Me[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        Ce[c] = Me[c] = 0.0;
+#pragma unroll
+        for (int sg = 0; sg < FSEG; ++sg) {
+            if (PROJ) Ce[c] += sC[c][sg][lane];
+            if (MOM) Me[c] += sM[c][sg][lane];
+        }
+    }
+    const int64_t jb = (int64_t)q * BINS + lane;
+    const bool has_bin = lane < BINS && jb < a.nb;
     const double inv_ds = 1.0 / a.ds;
     const float gv_in = (a.g != nullptr && has_bin) ? a.g[v * a.nb + jb] : 0.0f;
     const float bv = (a.bres != nullptr && has_bin) ? a.bres[v * a.nb + jb] : 0.0f;
@@ -397,14 +413,17 @@ __global__ __launch_bounds__(BLK) void fwd_edges_k(FwdArgs a)
         if (c >= nc) break;
         const int64_t col = a.col_out0 + c0 + c;
         const int64_t o = (col * a.V + v) * a.nb + jb;
+        // neighbouring edge's total through a lane shift (lane 63 has no bin)
+        const double Cn = __shfl_down(Ce[c], 1, 64);
+        const double Mn = __shfl_down(Me[c], 1, 64);
         double yv = 0.0, Dv = 0.0;
         if (has_bin) {
             if (PROJ) {
-                yv = (sC[c][tid + 1] - sC[c][tid]) * inv_ds;
+                yv = (Cn - Ce[c]) * inv_ds;
                 if (a.y) a.y[o] = (float)(a.write_resid ? yv - (double)bv : yv);
             }
             if (MOM) {
-                Dv = (sM[c][tid] - sM[c][tid + 1]) * inv_ds;
+                Dv = (Me[c] - Mn) * inv_ds;
                 if (a.dy) a.dy[o] = (float)Dv;
             }
         }
@@ -414,26 +433,13 @@ __global__ __launch_bounds__(BLK) void fwd_edges_k(FwdArgs a)
             const double sg = wave_sum(Dv * gv);
             const double sh = wave_sum(Dv * Dv);
             const double sr = wave_sum(rv * rv);
-            if ((tid & 63) == 0) {
-                sred[0][tid >> 6] = sg;
-                sred[1][tid >> 6] = sh;
-                sred[2][tid >> 6] = sr;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                double tg = 0.0, th2 = 0.0, tr = 0.0;
-                for (int wv = 0; wv < BLK / 64; ++wv) {
-                    tg += sred[0][wv];
-                    th2 += sred[1][wv];
-                    tr += sred[2][wv];
-                }
+            if (lane == 0) {
                 const int64_t po = (col * a.V + v) * a.nchunks + q;
                 const int64_t ps = a.part_cols * a.V * a.nchunks;
-                a.part[po] = tg;
-                a.part[ps + po] = th2;
-                a.part[2 * ps + po] = tr;
+                a.part[po] = sg;
+                a.part[ps + po] = sh;
+                a.part[2 * ps + po] = sr;
             }
-            __syncthreads();
         }
     }
 }
@@ -601,14 +607,25 @@ static size_t fwd_ws_bytes(const nlrmm_geom &g, int nframes, int gcols, int64_t 
     return b;
 }
 
+template <int MODE, int NC>
+static void launch_fwd_seg(int seg, dim3 grid, const FwdArgs &a, hipStream_t s)
+{
+    switch (seg) {
+        case 1: fwd_edges_k<MODE, NC, 1><<<grid, 64, 0, s>>>(a); break;
+        case 2: fwd_edges_k<MODE, NC, 2><<<grid, 128, 0, s>>>(a); break;
+        case 8: fwd_edges_k<MODE, NC, 8><<<grid, 512, 0, s>>>(a); break;
+        default: fwd_edges_k<MODE, NC, 4><<<grid, 256, 0, s>>>(a); break;
+    }
+}
+
 template <int MODE>
-static void launch_fwd_mode(int NC, dim3 grid, const FwdArgs &a, hipStream_t s)
+static void launch_fwd_mode(int NC, int seg, dim3 grid, const FwdArgs &a, hipStream_t s)
 {
     switch (NC) {
-        case 1: fwd_edges_k<MODE, 1><<<grid, BLK, 0, s>>>(a); break;
-        case 2: fwd_edges_k<MODE, 2><<<grid, BLK, 0, s>>>(a); break;
-        case 4: fwd_edges_k<MODE, 4><<<grid, BLK, 0, s>>>(a); break;
-        default: fwd_edges_k<MODE, 8><<<grid, BLK, 0, s>>>(a); break;
+        case 1: launch_fwd_seg<MODE, 1>(seg, grid, a, s); break;
+        case 2: launch_fwd_seg<MODE, 2>(seg, grid, a, s); break;
+        case 4: launch_fwd_seg<MODE, 4>(seg, grid, a, s); break;
+        default: launch_fwd_seg<MODE, 8>(seg, grid, a, s); break;
     }
 }
 
@@ -707,12 +724,13 @@ int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
         a.talpha = o.talpha;
         a.skip = o.skip;
         a.write_resid = o.write_resid ? 1 : 0;
-        const int NC = nc >= 8 ? 8 : nc >= 4 ? 4 : nc >= 2 ? 2 : 1;
+        const int NC = fwd_nc_bucket(nc);
+        const int seg = fwd_seg_for(ctx, g, b, NC);
         dim3 grid((unsigned)(V * nchunks), (unsigned)((nc + NC - 1) / NC));
         timing_mark(ctx, 0, 0, s);
-        if (proj && mom) launch_fwd_mode<3>(NC, grid, a, s);
-        else if (mom) launch_fwd_mode<2>(NC, grid, a, s);
-        else launch_fwd_mode<1>(NC, grid, a, s);
+        if (proj && mom) launch_fwd_mode<3>(NC, seg, grid, a, s);
+        else if (mom) launch_fwd_mode<2>(NC, seg, grid, a, s);
+        else launch_fwd_mode<1>(NC, seg, grid, a, s);
         timing_mark(ctx, 0, 1, s);
     }
     if (red && (o.gdot || o.dnorm2 || o.rnorm2) && !o.keep_parts) {
@@ -733,6 +751,25 @@ size_t fwd_workspace_bytes(const nlrmm_geom &g, int nframes, int ncols)
     return fwd_ws_bytes(g, nframes, gcols, 1, 1, 0);
 }
 
+int fwd_nc_bucket(int nc) { return nc >= 8 ? 8 : nc >= 4 ? 4 : nc >= 2 ? 2 : 1; }
+
+int fwd_seg_for(const nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int nc_bucket)
+{
+    if (ctx->force_fwd_seg) return ctx->force_fwd_seg;
+    const int t = tune_lookup(ctx, TUNE_FWD_SEG, g, b, nc_bucket);
+    return t ? t : FSEG_DEFAULT;
+}
+
+// Largest view split: at most 8 partial images, at least 16 views per split and frame.
+int bwd_split_max(const nlrmm_geom &, const nlrmm_batch &b)
+{
+    int64_t ns = (b.nviews / b.nframes) / 16;
+    if (ns > 8) ns = 8;
+    if (ns < 1) ns = 1;
+    return (int)ns;
+}
+
+// Default view split (without a tuned choice): about 6 resident waves per SIMD.
 int bwd_splits(const nlrmm_geom &g, const nlrmm_batch &b, int ncols, int cu_count)
 {
     const int64_t tiles = (int64_t)((g.nx + TILE - 1) / TILE) * ((g.ny + TILE - 1) / TILE);
@@ -746,9 +783,12 @@ int bwd_splits(const nlrmm_geom &g, const nlrmm_batch &b, int ncols, int cu_coun
     return (int)ns;
 }
 
+// Workspace bound of any view split the backprojection may use for this shape.
 size_t bwd_workspace_bytes(const nlrmm_geom &g, const nlrmm_batch &b, int ncols, int cu_count)
 {
-    const int ns = bwd_splits(g, b, ncols, cu_count);
+    const int ns = bwd_split_max(g, b) > bwd_splits(g, b, ncols, cu_count)
+                       ? bwd_split_max(g, b)
+                       : bwd_splits(g, b, ncols, cu_count);
     if (ns <= 1) return 0;
     return sizeof(float) * (size_t)ns * ncols * b.nframes * g.nx * g.ny;
 }
@@ -778,7 +818,12 @@ int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b
     a.tiles_x = (g.nx + TILE - 1) / TILE;
     a.W = W;
     a.x = x;
-    a.nsplit = bwd_splits(g, b, ncols, ctx->cu_count);
+    if (ctx->force_bwd_split) {
+        a.nsplit = ctx->force_bwd_split;
+    } else {
+        const int t = tune_lookup(ctx, TUNE_BWD_SPLIT, g, b, ncols);
+        a.nsplit = t ? t : bwd_splits(g, b, ncols, ctx->cu_count);
+    }
     a.part = nullptr;
     a.accumulate = accumulate;
     if (a.nsplit > 1) {

@@ -124,6 +124,61 @@ def backproject(y: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None,
     return out
 
 
+def autotune_project(x: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None,
+                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Same result as project(); also times the forward block shapes for this shape and
+    keeps the fastest in the device's context (synchronizes the stream)."""
+    _need(x, torch.float32, "x")
+    _need(theta, torch.float64, "theta")
+    V = theta.numel()
+    b = _batch(frames, V)
+    ncols = x.numel() // (b.nframes * g.nx * g.ny)
+    if out is None:
+        out = torch.empty((ncols, V, g.nbins), dtype=torch.float32, device=x.device)
+    check(_lib.lib().nlrmm_autotune_project(context(x.device.index or 0), ctypes.byref(g),
+                                            ctypes.byref(b), ncols, x.data_ptr(),
+                                            theta.data_ptr(), out.data_ptr(), _stream(x.device)),
+          "nlrmm_autotune_project")
+    return out
+
+
+def autotune_backproject(y: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None,
+                         out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Same result as backproject(); also times the view splits for this shape and keeps the
+    fastest in the device's context (synchronizes the stream)."""
+    _need(y, torch.float32, "y")
+    _need(theta, torch.float64, "theta")
+    V = theta.numel()
+    b = _batch(frames, V)
+    ncols = y.numel() // (V * g.nbins)
+    if out is None:
+        out = torch.empty((ncols, b.nframes, g.ny, g.nx), dtype=torch.float32, device=y.device)
+    check(_lib.lib().nlrmm_autotune_backproject(context(y.device.index or 0), ctypes.byref(g),
+                                                ctypes.byref(b), ncols, y.data_ptr(),
+                                                theta.data_ptr(), out.data_ptr(),
+                                                _stream(y.device)), "nlrmm_autotune_backproject")
+    return out
+
+
+def tune_query(kind: str, g: Geom, nviews: int, ncols: int = 1, frames=None,
+               device: int = 0) -> int:
+    """Tuned launch shape for 'project' (waves per forward block) or 'backproject' (view
+    split) at this shape; 0 when none is stored."""
+    b = _batch(frames, nviews)
+    c = ctypes.c_int32()
+    check(_lib.lib().nlrmm_tune_query(context(device), {"project": 0, "backproject": 1}[kind],
+                                      ctypes.byref(g), ctypes.byref(b), ncols, ctypes.byref(c)),
+          "nlrmm_tune_query")
+    return int(c.value)
+
+
+def set_tune_file(path: Optional[str], device: int = 0) -> None:
+    """Load tuned shapes from `path` and append new ones there (None: stop appending)."""
+    check(_lib.lib().nlrmm_ctx_set_tune_file(context(device),
+                                             None if path is None else path.encode()),
+          "nlrmm_ctx_set_tune_file")
+
+
 def project_dtheta(x: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None, *,
                    want_dy: bool = True, want_y: bool = False, gres: Optional[torch.Tensor] = None,
                    want_gdot: bool = False, want_dnorm2: bool = False):

@@ -38,5 +38,14 @@ def test_host_validation_without_device():
     assert lib.nlrmm_backproject(None, ctypes.byref(g), ctypes.byref(b), 1, 1, 1, 1, None) == -1
     assert lib.nlrmm_project_dtheta(None, ctypes.byref(g), ctypes.byref(b), 1, 1, 1,
                                     None, None, None, None, None, None) == -1
+    assert lib.nlrmm_autotune_project(None, ctypes.byref(g), ctypes.byref(b), 1, 1, 1, 1,
+                                      None) == -1
+    assert lib.nlrmm_autotune_backproject(None, ctypes.byref(g), ctypes.byref(b), 1, 1, 1, 1,
+                                          None) == -1
+    assert lib.nlrmm_ctx_set_tune_file(None, b"x") == -1
+    c = ctypes.c_int32()
+    assert lib.nlrmm_tune_query(None, 0, ctypes.byref(g), ctypes.byref(b), 1,
+                                ctypes.byref(c)) == -1
+    assert lib.nlrmm_ctx_set_timing(None, 1) == -1
     assert lib.nlrmm_strerror(-2) == b"inconsistent or unsupported sizes"
     assert lib.nlrmm_version() >= 100

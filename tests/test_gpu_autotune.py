@@ -1,0 +1,98 @@
+"""GPU tests of the launch-shape autotuner: every forward block shape and every backprojection
+view split computes the operator to the FP32 bar against the FP64 oracle; the tuner returns
+the operator's result, stores a valid choice, and choices loaded from a cache file are used."""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import projector as P  # noqa: E402
+from paper_2605_06336_amd import ops, synth  # noqa: E402
+
+TOL = 1e-5
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def problem(N, nb, V, ncols, F=1, seed=3):
+    rng = np.random.default_rng(seed)
+    if F == 1:
+        vo, fr = None, None
+    else:
+        vo = np.concatenate([[0], np.cumsum(rng.integers(40, 70, F))]).astype(np.int64)
+        fr = ops.Frames(vo)
+        V = int(vo[-1])
+    th = synth.random_angles(V, seed)
+    x = synth.random_image(N, seed=seed + 1, frames=F * ncols).reshape(ncols, F, N, N)
+    ys = synth.random_sinogram(V * ncols, nb, seed=seed + 2).reshape(ncols, V, nb)
+    return vo, fr, th, x.astype(np.float32), ys.astype(np.float32)
+
+
+@pytest.mark.parametrize("N,nb,V,ncols,F", [(96, 139, 70, 1, 1), (80, 117, 0, 3, 3)])
+def test_every_shape_matches_oracle(tmp_path, N, nb, V, ncols, F):
+    vo, fr, th, x, ys = problem(N, nb, V, ncols, F)
+    Vt = th.size
+    g = ops.geom(N, nb)
+    xt, tht, yt = dev(x, torch.float32), dev(th, torch.float64), dev(ys, torch.float32)
+    y_ref = P.project(x.astype(np.float64), th, nb, vo)
+    xb_ref = P.backproject(ys.astype(np.float64), th, N, vo).reshape(ncols, F, N, N)
+    D_ref = P.dtheta(x.astype(np.float64), th, nb, vo)
+    nc = 8 if ncols >= 8 else 4 if ncols >= 4 else 2 if ncols >= 2 else 1
+    max_split = max(1, min(8, (Vt // F) // 16))
+    path = str(tmp_path / "tune.txt")
+    for seg in (1, 2, 4, 8):
+        with open(path, "w") as f:
+            f.write(f"0 {N} {N} {nb} {F} {nc} {Vt} {seg}\n")
+        ops.set_tune_file(path)
+        assert ops.tune_query("project", g, Vt, ncols, fr) == seg
+        y = ops.project(xt, tht, g, fr).cpu().numpy()
+        assert rel(y, y_ref) <= TOL, (seg, rel(y, y_ref))
+        D = ops.project_dtheta(xt, tht, g, fr, want_dy=True)["dy"].cpu().numpy()
+        assert rel(D, D_ref) <= TOL, (seg, rel(D, D_ref))
+        print(f"forward waves/block {seg}: y {rel(y, y_ref):.2e} D {rel(D, D_ref):.2e}", flush=True)
+    split = 1
+    while split <= max_split:
+        with open(path, "w") as f:
+            f.write(f"1 {N} {N} {nb} {F} {ncols} {Vt} {split}\n")
+        ops.set_tune_file(path)
+        assert ops.tune_query("backproject", g, Vt, ncols, fr) == split
+        xb = ops.backproject(yt, tht, g, fr).cpu().numpy()
+        assert rel(xb, xb_ref) <= TOL, (split, rel(xb, xb_ref))
+        print(f"backprojection split {split}: {rel(xb, xb_ref):.2e}", flush=True)
+        split *= 2
+    ops.set_tune_file(None)
+
+
+def test_tuner_returns_operator_and_stores_choice(tmp_path):
+    N, nb, V, ncols = 128, 183, 90, 2
+    vo, fr, th, x, ys = problem(N, nb, V, ncols, seed=21)
+    g = ops.geom(N, nb)
+    xt, tht, yt = dev(x, torch.float32), dev(th, torch.float64), dev(ys, torch.float32)
+    path = str(tmp_path / "tune.txt")
+    ops.set_tune_file(path)
+    y = ops.autotune_project(xt, tht, g).cpu().numpy()
+    xb = ops.autotune_backproject(yt, tht, g).cpu().numpy()
+    ops.set_tune_file(None)
+    assert rel(y, P.project(x.astype(np.float64), th, nb)) <= TOL
+    assert rel(xb, P.backproject(ys.astype(np.float64), th, N).reshape(xb.shape)) <= TOL
+    seg = ops.tune_query("project", g, V, ncols)
+    split = ops.tune_query("backproject", g, V, ncols)
+    assert seg in (1, 2, 4, 8)
+    assert 1 <= split <= 8
+    lines = open(path).read().split("\n")
+    assert f"0 {N} {N} {nb} 1 2 {V} {seg}" in lines
+    assert f"1 {N} {N} {nb} 1 {ncols} {V} {split}" in lines
+    # the tuned shapes stay in use and give the same operator
+    y2 = ops.project(xt, tht, g).cpu().numpy()
+    assert rel(y2, y) <= 1e-7
+    assert os.path.getsize(path) > 0
