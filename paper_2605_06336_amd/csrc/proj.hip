@@ -27,6 +27,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace nlrmm {
 namespace {
 
@@ -328,48 +330,58 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
         const int len = lb - la + 1;
         const int sa = len > 0 ? la + (len * seg) / FSEG : la;
         const int sb = len > 0 ? la + (len * (seg + 1)) / FSEG - 1 : lb;
-        for (int L = sa; L <= sb; ++L) {
-            const double lc = pix_coord(line0, a.d, L);
-            const double base = __dsub_rn(e, __dmul_rn(lc, sl));
-            double tf = floor((base - w.wo - cw0) * inv_step);
-            tf = fmin(fmax(tf, -2.0), (double)nminor);
-            int K0 = (int)tf + 1;
-            K0 = min(max(K0, -1), nminor);
-            const int idx = asc ? K0 : nminor - 2 - K0;
-            const int ka = asc ? K0 : idx + 1;
-            const int kb = asc ? K0 + 1 : idx;
-            const double mca = pix_coord(minor0, a.d, ka);
-            const double mcb = pix_coord(minor0, a.d, kb);
-            const float va = __double2float_rn(__dsub_rn(base, __dmul_rn(mca, sm)));
-            const float vb = __double2float_rn(__dsub_rn(base, __dmul_rn(mcb, sm)));
-            float pa = 0.f, pb = 0.f, ma = 0.f, mb = 0.f;
-            if (PROJ) {
-                pa = phi_f(va, w);
-                pb = phi_f(vb, w);
-            }
-            if (MOM) {
-                float La, Lb, mua, mub;
-                moment_f(va, w, La, mua);
-                moment_f(vb, w, Lb, mub);
-                const double tb = lc * tl;
-                ma = La * ((float)(tb + mca * tm) + mua);
-                mb = Lb * ((float)(tb + mcb * tm) + mub);
-            }
-            const PackEntry *pe = pimg + (int64_t)L * (nminor + 3) + (idx + 2);
+        // Walk position of the edge on line L, in pixel steps from the first straddling
+        // candidate: q(L) = (e - lc(L) sl - wo - cw0) / step, linear in L.  K0 = floor(q) + 1
+        // is the first pixel the edge straddles, and the edge's offsets from the centres of
+        // pixels K0 and K0 + 1 (in walk order) are wo + (q - K0) step and that minus step, in
+        // both walk directions.
+        const double dq = -a.d * sl * inv_step;
+        double q = sa <= sb ? (__dsub_rn(e, __dmul_rn(pix_coord(line0, a.d, sa), sl)) - w.wo -
+                               cw0) * inv_step
+                            : 0.0;
+        const float stepf = (float)step, wof = (float)w.wo;
+        auto walk = [&](auto ascending) __attribute__((always_inline)) {
+            constexpr bool ASC = decltype(ascending)::value;
+            for (int L = sa; L <= sb; ++L, q += dq) {
+                const double tf = fmin(fmax(floor(q), -2.0), (double)nminor);
+                const int K0 = min((int)tf + 1, nminor);
+                const float va = fmaf((float)(q - (double)K0), stepf, wof);
+                const float vb = va - stepf;
+                const int idx = ASC ? K0 : nminor - 2 - K0;
+                float pa = 0.f, pb = 0.f, ma = 0.f, mb = 0.f;
+                if (PROJ) {
+                    pa = phi_f(va, w);
+                    pb = phi_f(vb, w);
+                }
+                if (MOM) {
+                    const int ka = ASC ? K0 : idx + 1;
+                    const int kb = ASC ? K0 + 1 : idx;
+                    const double lc = pix_coord(line0, a.d, L);
+                    const double tb = lc * tl;
+                    float La, Lb, mua, mub;
+                    moment_f(va, w, La, mua);
+                    moment_f(vb, w, Lb, mub);
+                    ma = La * ((float)(tb + pix_coord(minor0, a.d, ka) * tm) + mua);
+                    mb = Lb * ((float)(tb + pix_coord(minor0, a.d, kb) * tm) + mub);
+                }
+                const PackEntry *pe = pimg + (int64_t)L * (nminor + 3) + (idx + 2);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                if (c < nc) {
-                    const PackEntry E = pe[c * cstride * pstride];
-                    const float xa = asc ? E.a : E.b;
-                    const float xb = asc ? E.b : E.a;
-                    if (PROJ) {
-                        accP[c] += asc ? E.P : -(E.P + (double)E.a + (double)E.b);
-                        accF[c] += (double)fmaf(xb, pb, xa * pa);
+                for (int c = 0; c < NC; ++c) {
+                    if (c < nc) {
+                        const PackEntry E = pe[c * cstride * pstride];
+                        const float xa = ASC ? E.a : E.b;
+                        const float xb = ASC ? E.b : E.a;
+                        if (PROJ) {
+                            accP[c] += ASC ? E.P : -(E.P + (double)(E.a + E.b));
+                            accF[c] += (double)fmaf(xb, pb, xa * pa);
+                        }
+                        if (MOM) accM[c] += (double)fmaf(xb, mb, xa * ma);
                     }
-                    if (MOM) accM[c] += (double)fmaf(xb, mb, xa * ma);
                 }
             }
-        }
+        };
+        if (asc) walk(std::true_type{});
+        else walk(std::false_type{});
         if (PROJ && seg == 0) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
