@@ -13,9 +13,12 @@ int k_tv_grad_add(const float *u, const float *w, int nx, int ny, int F, int tem
 int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int ny, int F,
                int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s,
                int mode = 0);
+// part: nblk * MD_PART_STRIDE doubles of partials followed by a zero-initialised counter
+// (md_part_doubles(nblk) doubles in all); the counter is zero again after every launch.
 int k_multidot(const float *X, int64_t ldx, int nv, const float *y, const float *z, int64_t n,
                double *part, int nblk, double *out, int ostride, hipStream_t s,
                const int *skip = nullptr);
+inline size_t md_part_doubles(int nblk) { return (size_t)nblk * 72 + 8; }
 int k_gemv(const float *X, int64_t ldx, int nv, const double *c, double beta, const float *a,
            double alpha, int64_t n, float *out, hipStream_t s);
 int k_block_update(const float *X, int64_t ldx, int nin, const double *T, int ldt, int kout,

@@ -343,13 +343,21 @@ __global__ __launch_bounds__(64) void reduce_gram_k(const double *__restrict__ p
 // An extra row (i = nv) accumulates y[e] * z[e] when z != null.
 constexpr int MD_MAX = 72;
 
+// Inner products out[i * ostride] = <X_i, y> (i < nv) and <z, y> (i == nv when z is given),
+// FP64 accumulation.  Each block reduces its share of the elements for groups of 8 outputs
+// through LDS, writes per-block partials, and the last block to finish (device-scope counter
+// after a release fence) sums the partials of every output in block order, so the result does
+// not depend on scheduling.  The counter lives after the partials (part + cap * MD_MAX), is
+// zero between launches and is reset by that last block.
 __global__ __launch_bounds__(BLK) void multidot_k(const float *__restrict__ X, int64_t ldx, int nv,
                                                   const float *__restrict__ y,
                                                   const float *__restrict__ z, int64_t n,
-                                                  double *__restrict__ part, const int *skip)
+                                                  double *part, int cap, double *__restrict__ out,
+                                                  int ostride, const int *skip)
 {
     if (skip != nullptr && *skip != 0) return;
-    __shared__ double sred[BLK / 64][MD_MAX + 1];
+    __shared__ double sacc[8][BLK];
+    __shared__ int last;
     const int tid = threadIdx.x;
     const int nout = nv + (z != nullptr ? 1 : 0);
     const int lane = tid & 63, wv = tid >> 6;
@@ -367,31 +375,33 @@ __global__ __launch_bounds__(BLK) void multidot_k(const float *__restrict__ X, i
             }
         }
 #pragma unroll
-        for (int a = 0; a < 8; ++a) {
-            const double s = wave_sum(acc[a]);
-            if (lane == 0 && i0 + a < nout) sred[wv][i0 + a] = s;
+        for (int a = 0; a < 8; ++a) sacc[a][tid] = acc[a];
+        __syncthreads();
+        {
+            const int a = tid >> 5, l = tid & 31;   // 32 threads per output of the group
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < BLK / 32; ++k) s += sacc[a][l + 32 * k];
+            for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
+            if (l == 0 && i0 + a < nout) part[(int64_t)blockIdx.x * nout + i0 + a] = s;
         }
+        __syncthreads();
     }
+    unsigned *cnt = reinterpret_cast<unsigned *>(part + (int64_t)cap * MD_MAX);
+    __threadfence();
     __syncthreads();
-    for (int i = tid; i < nout; i += BLK) {
+    if (tid == 0) last = (atomicAdd(cnt, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    const int nblk = gridDim.x;
+    for (int i = wv; i < nout; i += BLK / 64) {
         double s = 0.0;
-        for (int w = 0; w < BLK / 64; ++w) s += sred[w][i];
-        part[(int64_t)blockIdx.x * nout + i] = s;
+        for (int b = lane; b < nblk; b += 64) s += part[(int64_t)b * nout + i];
+        s = wave_sum(s);
+        if (lane == 0) out[(int64_t)i * ostride] = s;
     }
-}
-
-// out[i * ostride] = sum_b part[b][i]: one wave per output, lane-strided partial sums
-// and a fixed butterfly, so the result is independent of scheduling.
-__global__ __launch_bounds__(64) void reduce_vec_k(const double *__restrict__ part, int nblk,
-                                                   int nout, double *__restrict__ out,
-                                                   int ostride, const int *skip)
-{
-    if (skip != nullptr && *skip != 0) return;
-    const int i = blockIdx.x;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 64) s += part[(int64_t)b * nout + i];
-    s = wave_sum(s);
-    if (threadIdx.x == 0) out[(int64_t)i * ostride] = s;
+    if (tid == 0) *cnt = 0u;
 }
 
 // out[e] = alpha * a[e] + beta * sum_i X_i[e] c_i   (a may be null; c FP64 on the device)
@@ -1682,9 +1692,12 @@ int k_multidot(const float *X, int64_t ldx, int nv, const float *y, const float 
                double *part, int nblk, double *out, int ostride, hipStream_t s, const int *skip)
 {
     const int nout = nv + (z ? 1 : 0);
-    if (nout > MD_MAX) return NLRMM_ESHAPE;
-    multidot_k<<<(unsigned)nblk, BLK, 0, s>>>(X, ldx, nv, y, z, n, part, skip);
-    reduce_vec_k<<<(unsigned)nout, 64, 0, s>>>(part, nblk, nout, out, ostride, skip);
+    if (nout > MD_MAX || nblk < 1) return NLRMM_ESHAPE;
+    // at least two elements per thread, at most the partials' capacity
+    int64_t g = (n + 2 * BLK - 1) / (2 * BLK);
+    if (g > nblk) g = nblk;
+    if (g < 1) g = 1;
+    multidot_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, nv, y, z, n, part, nblk, out, ostride, skip);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 

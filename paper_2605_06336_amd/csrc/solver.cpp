@@ -452,7 +452,7 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
         (rc = S->alloc(&S->gv, max_views)) || (rc = S->alloc(&S->hv, max_views)) ||
         (rc = S->alloc(&S->rv, max_views)) || (rc = S->alloc(&S->dir, max_views)) ||
         (rc = S->alloc(&S->alphas, 32)) || (rc = S->alloc(&S->thk, max_views)) ||
-        (rc = S->alloc(&S->part_md, (size_t)S->md_blocks * 72)) ||
+        (rc = S->alloc(&S->part_md, md_part_doubles(S->md_blocks))) ||
         (rc = S->alloc(&S->part_gram, (size_t)S->gram_blocks * 64 * 64)) ||
         (rc = S->alloc(&S->part_fwd, (size_t)3 * c.kmin * max_views * S->nchunks)) ||
         (rc = S->alloc(&S->gkb, 2 * (size_t)S->kcap + 2)) || (rc = S->alloc(&S->status, 1)) ||
@@ -472,6 +472,7 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
     if (hipMemcpy(S->alphas, al, sizeof(al), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(S->sc, 0, sizeof(double) * S_NB) != hipSuccess ||
         hipMemset(S->status, 0, sizeof(int)) != hipSuccess ||
+        hipMemset(S->part_md, 0, sizeof(double) * md_part_doubles(S->md_blocks)) != hipSuccess ||
         hipMemset(S->GA, 0, sizeof(double) * S->ld * S->ld) != hipSuccess ||
         hipMemset(S->GP, 0, sizeof(double) * S->ld * S->ld) != hipSuccess) {
         delete S;
@@ -572,7 +573,7 @@ static int scratch_view(nlrmm_ctx *ctx, Solver &S, int64_t n, int64_t m, int kca
     const int64_t big = n > m ? n : m;
     const size_t bytes = al(sizeof(float) * n) * 2 + al(sizeof(float) * m) +
                          al(sizeof(float) * (size_t)kmin * big) +
-                         al(sizeof(double) * (size_t)S.md_blocks * 72) +
+                         al(sizeof(double) * md_part_doubles(S.md_blocks)) +
                          al(sizeof(double) * (size_t)S.gram_blocks * 64 * 64) +
                          al(sizeof(double) * (kcap + 4)) * 2 + al(sizeof(double) * kcap * 16) +
                          al(sizeof(double) * (kcap + 4)) + al(sizeof(int) * 4) + 4096;
@@ -588,7 +589,10 @@ static int scratch_view(nlrmm_ctx *ctx, Solver &S, int64_t n, int64_t m, int kca
     S.r = (float *)take(sizeof(float) * n);
     S.rho = (float *)take(sizeof(float) * m);
     S.Vtmp = (float *)take(sizeof(float) * (size_t)kmin * big);
-    S.part_md = (double *)take(sizeof(double) * (size_t)S.md_blocks * 72);
+    S.part_md = (double *)take(sizeof(double) * md_part_doubles(S.md_blocks));
+    // the partials' completion counter must start at zero (a fill kernel: capturable)
+    if ((rc = k_fill_i32(reinterpret_cast<int *>(S.part_md + (size_t)S.md_blocks * 72), 2, 0, s)))
+        return rc;
     S.part_gram = (double *)take(sizeof(double) * (size_t)S.gram_blocks * 64 * 64);
     S.hb = (double *)take(sizeof(double) * (kcap + 4));
     S.hb2 = (double *)take(sizeof(double) * (kcap + 4));
