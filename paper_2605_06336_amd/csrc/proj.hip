@@ -19,10 +19,14 @@
 // bins that meet at the edge, so each application evaluates Phi ~2 per edge-line
 // instead of ~2 per (ray, pixel) nonzero.  No atomics; results are deterministic.
 //
+// Forward lanes of one block are 64 consecutive edges; the block's waves split each edge's
+// line range (1..8 waves, tuned per shape) and their partial sums meet in LDS.
+//
 // Backward (pixel-driven gather): one lane per pixel of a 16x16 tile; for chunks of
-// views the tile's detector window is staged in LDS, each pixel evaluates Phi at the
-// <= E edges inside its footprint (bit-identical offsets and Phi to the forward) and
-// gathers its <= E+1 bins.
+// views the tile's detector window is staged in LDS, each pixel locates its footprint
+// in bin units relative to the tile centre (FP64), evaluates Phi at the <= E edges inside
+// it (FP32 offsets) and gathers its <= E+1 bins.  Same weight function as the forward;
+// the two are transposes up to FP32 rounding of the offsets.
 #include "internal.h"
 
 #include <math.h>
@@ -78,8 +82,9 @@ __device__ __forceinline__ ViewC make_view(double th, double d)
 
 // Cumulative footprint Phi(v) (area of the pixel on the side p.n < c + v), FP32,
 // branch-free: left ramp t1^2 h/(2 rho), plateau h t2, right ramp h (t3 - t3^2/(2 rho)).
-// Explicit rounding intrinsics pin the operation order so the forward and backward
-// kernels produce bit-identical values.
+// The forward and backward kernels evaluate the same function of the same offsets; they form
+// the offsets with different (both FP64-positioned) arithmetic, so the two operators are
+// transposes of each other up to FP32 rounding of the offsets.
 __device__ __forceinline__ float phi_f(float v, const ViewC &q)
 {
     const float t1 = fminf(fmaxf(__fadd_rn(v, q.fwo), 0.0f), q.frho);
@@ -494,10 +499,19 @@ struct BwdArgs {
     int accumulate;  // x += result instead of x = result
 };
 
+// Per-view constants of one backward tile: the footprint start of the tile centre in bin
+// units, split as jb (staged-window index of its bin) + T0 in [0, 1), and the bin-unit steps
+// of one pixel along x and y.
+struct BView {
+    double T0, ax, ay;
+    int jb;
+    float fwo, fwi, frho, f2wi, fh, fhk;
+};
+
 template <int E>
 __global__ __launch_bounds__(BLK) void bwd_tiles_k(BwdArgs a)
 {
-    __shared__ ViewC sv[VCHUNK];
+    __shared__ BView sv[VCHUNK];
     __shared__ int sj0[VCHUNK];
     __shared__ float sy[VCHUNK][WMAX];
     const int tid = threadIdx.x;
@@ -505,8 +519,9 @@ __global__ __launch_bounds__(BLK) void bwd_tiles_k(BwdArgs a)
     const int64_t img = blockIdx.y;
     const int64_t col = img / a.nframes;
     const int f = (int)(img - col * a.nframes);
-    const int k = tx * TILE + (tid % TILE);
-    const int l = ty * TILE + (tid / TILE);
+    const int kl = tid % TILE, ll = tid / TILE;
+    const int k = tx * TILE + kl;
+    const int l = ty * TILE + ll;
     const bool active = k < a.nx && l < a.ny;
     const int64_t fv0 = (a.view_off && a.nframes > 1) ? a.view_off[f] : 0;
     const int64_t fv1 = (a.view_off && a.nframes > 1) ? a.view_off[f + 1] : a.V;
@@ -516,19 +531,34 @@ __global__ __launch_bounds__(BLK) void bwd_tiles_k(BwdArgs a)
     const float *ycol = a.y + col * a.V * a.nb;
     const double xc = a.x0 + (tx * TILE + 0.5 * TILE) * a.d;
     const double yc = a.y0 + (ty * TILE + 0.5 * TILE) * a.d;
-    const double xk = pix_coord(a.x0, a.d, k);
-    const double yl = pix_coord(a.y0, a.d, l);
-    const double d2 = a.d * a.d;
+    // pixel centre relative to the tile centre, in pixels
+    const double pk = kl + 0.5 - 0.5 * TILE, pl = ll + 0.5 - 0.5 * TILE;
+    const float d2 = (float)(a.d * a.d);
+    const float fds = (float)a.ds;
     double acc = 0.0;
 
     for (int64_t vb = v0; vb < v1; vb += VCHUNK) {
         const int nv = (int)min((int64_t)VCHUNK, v1 - vb);
         if (tid < nv) {
             const ViewC w = make_view(a.theta[vb + tid], a.d);
-            sv[tid] = w;
             const double cC = xc * w.cs + yc * w.sn;
             const double R = (TILE - 1) * 0.5 * a.d * (fabs(w.cs) + fabs(w.sn)) + w.wo;
-            sj0[tid] = (int)floor((cC - R - a.s0) / a.ds) - 1;
+            const int j0 = (int)floor((cC - R - a.s0) / a.ds) - 1;
+            const double T = (cC - w.wo - a.s0) / a.ds;
+            const double Tf = floor(T);
+            BView q;
+            q.T0 = T - Tf;
+            q.ax = a.d * w.cs / a.ds;
+            q.ay = a.d * w.sn / a.ds;
+            q.jb = (int)Tf - j0;
+            q.fwo = w.fwo;
+            q.fwi = w.fwi;
+            q.frho = w.frho;
+            q.f2wi = w.f2wi;
+            q.fh = w.fh;
+            q.fhk = w.fhk;
+            sv[tid] = q;
+            sj0[tid] = j0;
         }
         __syncthreads();
         for (int i = tid; i < nv * a.W; i += BLK) {
@@ -539,34 +569,31 @@ __global__ __launch_bounds__(BLK) void bwd_tiles_k(BwdArgs a)
         __syncthreads();
         if (active) {
             for (int vi = 0; vi < nv; ++vi) {
-                const ViewC &w = sv[vi];
-                const bool steep = w.steep != 0;
-                const double lc = steep ? yl : xk;
-                const double mc = steep ? xk : yl;
-                const double sl = steep ? w.sn : w.cs;
-                const double sm = steep ? w.cs : w.sn;
-                const double lcs = __dmul_rn(lc, sl);
-                const double mcs = __dmul_rn(mc, sm);
-                const double cc = lcs + mcs;
-                const int64_t jf = (int64_t)floor((cc - w.wo - a.s0) / a.ds);
-                float ph[E + 2];
-                ph[0] = 0.0f;
+                const BView &q = sv[vi];
+                // footprint start of this pixel in bin units: jb + t, split into bin and
+                // fraction f; edge i of the window then sits at (i - f) ds - wo from the centre
+                const double t = fma(pk, q.ax, fma(pl, q.ay, q.T0));
+                const double tf = floor(t);
+                const float fr = (float)(t - tf);
+                int jj = q.jb + (int)tf;
+                jj = min(max(jj, 0), a.W - (E + 1));
+                ViewC w;
+                w.fwo = q.fwo;
+                w.fwi = q.fwi;
+                w.frho = q.frho;
+                w.f2wi = q.f2wi;
+                w.fh = q.fh;
+                w.fhk = q.fhk;
+                const float *yy = &sy[vi][jj];
+                float prev = 0.0f, sum = 0.0f;
 #pragma unroll
                 for (int i = 1; i <= E; ++i) {
-                    const double e = edge_coord(a.s0, a.ds, jf + i);
-                    const double base = __dsub_rn(e, lcs);
-                    ph[i] = phi_f(__double2float_rn(__dsub_rn(base, mcs)), w);
+                    const float ph = phi_f(fmaf((float)i - fr, fds, -q.fwo), w);
+                    sum = fmaf(ph - prev, yy[i - 1], sum);
+                    prev = ph;
                 }
-                int jj = (int)(jf - sj0[vi]);
-                jj = min(max(jj, 0), a.W - (E + 1));
-                const float *yy = &sy[vi][jj];
-                double prev = 0.0;
-#pragma unroll
-                for (int i = 0; i <= E; ++i) {
-                    const double nxt = (i < E) ? (double)ph[i + 1] : d2;
-                    acc += (nxt - prev) * (double)yy[i];
-                    prev = nxt;
-                }
+                sum = fmaf(d2 - prev, yy[E], sum);
+                acc += (double)sum;
             }
         }
         __syncthreads();
