@@ -140,40 +140,32 @@ __device__ __forceinline__ T wave_sum(T v)
 }
 
 // ---------------------------------------------------------------------------
-// preparation: transpose and per-line packs
+// preparation: per-line packs of rows and columns
 // ---------------------------------------------------------------------------
-__global__ void transpose_k(const float *__restrict__ x, float *__restrict__ xT, int nx, int ny)
-{
-    __shared__ float tile[32][33];
-    const int64_t img = blockIdx.z;
-    const float *src = x + img * (int64_t)nx * ny;
-    float *dst = xT + img * (int64_t)nx * ny;
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
-    for (int r = threadIdx.y; r < 32; r += 8) {
-        const int yy = by + r, xx = bx + threadIdx.x;
-        tile[r][threadIdx.x] = (yy < ny && xx < nx) ? src[(int64_t)yy * nx + xx] : 0.0f;
-    }
-    __syncthreads();
-    for (int r = threadIdx.y; r < 32; r += 8) {
-        const int xx = bx + r, yy = by + threadIdx.x;
-        if (xx < nx && yy < ny) dst[(int64_t)xx * ny + yy] = tile[threadIdx.x][r];
-    }
-}
-
-// One block per (image, line): entries i = -2..n of the line, stored at i + 2:
-// P = sum of pixels 0..i-1 (FP64), a = x_i, b = x_{i+1} (zero outside the line).
-__global__ __launch_bounds__(BLK) void pack_lines_k(const float *__restrict__ src, int n, int nlines,
-                                                    PackEntry *__restrict__ pack,
-                                                    double *__restrict__ tot)
+// One block per (image, line), rows (blockIdx.x < ny) and columns (the rest) of the image
+// in one launch: entries i = -2..n of the line, stored at i + 2: P = sum of pixels 0..i-1
+// (FP64), a = x_i, b = x_{i+1} (zero outside the line); tot = the line's sum.
+__global__ __launch_bounds__(BLK) void pack_lines_k(const float *__restrict__ x, int nx, int ny,
+                                                    PackEntry *__restrict__ rowpack,
+                                                    PackEntry *__restrict__ colpack,
+                                                    double *__restrict__ rowtot,
+                                                    double *__restrict__ coltot)
 {
     __shared__ float sx[MAX_LINE + 2];
     __shared__ double sP[MAX_LINE + 1];
     __shared__ double swave[BLK / 64];
-    const int64_t line = blockIdx.x;
+    const bool is_row = (int)blockIdx.x < ny;
+    const int64_t line = is_row ? blockIdx.x : blockIdx.x - ny;
+    const int n = is_row ? nx : ny;
+    const int nlines = is_row ? ny : nx;
     const int64_t img = blockIdx.y;
-    const float *row = src + (img * nlines + line) * (int64_t)n;
+    const float *src = x + img * (int64_t)nx * ny;
+    const int64_t step = is_row ? 1 : nx;
+    const float *row = src + (is_row ? line * nx : line);
+    PackEntry *pack = is_row ? rowpack : colpack;
+    double *tot = is_row ? rowtot : coltot;
     const int tid = threadIdx.x;
-    for (int i = tid; i < n; i += BLK) sx[i] = row[i];
+    for (int i = tid; i < n; i += BLK) sx[i] = row[i * step];
     if (tid < 2) sx[n + tid] = 0.0f;
     __syncthreads();
     const int cpt = (n + BLK - 1) / BLK;
@@ -210,11 +202,18 @@ __global__ __launch_bounds__(BLK) void pack_lines_k(const float *__restrict__ sr
     if (tid == 0) tot[img * nlines + line] = sP[n];
 }
 
-// Exclusive prefix of the line totals: pre[img][0..nlines].
-__global__ __launch_bounds__(BLK) void line_prefix_k(const double *__restrict__ tot, int nlines,
-                                                     double *__restrict__ pre)
+// Exclusive prefix of the line totals: pre[img][0..nlines]; blockIdx.y selects rows (0) or
+// columns (1).
+__global__ __launch_bounds__(BLK) void line_prefix_k(const double *__restrict__ rowtot,
+                                                     const double *__restrict__ coltot, int nx,
+                                                     int ny, double *__restrict__ rowpre,
+                                                     double *__restrict__ colpre)
 {
     __shared__ double swave[BLK / 64];
+    const bool rows = blockIdx.y == 0;
+    const double *tot = rows ? rowtot : coltot;
+    const int nlines = rows ? ny : nx;
+    double *pre = rows ? rowpre : colpre;
     const int64_t img = blockIdx.x;
     const double *t = tot + img * nlines;
     double *p = pre + img * (int64_t)(nlines + 1);
@@ -636,7 +635,6 @@ static size_t fwd_ws_bytes(const nlrmm_geom &g, int nframes, int gcols, int64_t 
     const int64_t nx = g.nx, ny = g.ny;
     size_t b = 0;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    b += al(sizeof(float) * nimg * nx * ny);                 // transposed images
     b += al(sizeof(PackEntry) * nimg * ny * (nx + 3));       // row packs
     b += al(sizeof(PackEntry) * nimg * nx * (ny + 3));       // column packs
     b += al(sizeof(double) * nimg * (ny + nx));              // line totals
@@ -703,8 +701,6 @@ int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
     const int64_t nx = g.nx, ny = g.ny;
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     char *p = (char *)ctx->ws.ptr;
-    float *xT = (float *)p;
-    p += al(sizeof(float) * (int64_t)gcols * F * nx * ny);
     PackEntry *rowpack = (PackEntry *)p;
     p += al(sizeof(PackEntry) * (int64_t)gcols * F * ny * (nx + 3));
     PackEntry *colpack = (PackEntry *)p;
@@ -722,16 +718,12 @@ int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
         const int nc = ncols - cbeg < gcols ? ncols - cbeg : gcols;
         const int64_t nimg = (int64_t)nc * F;
         const float *xg = x + (int64_t)cbeg * F * npix;
-        // row packs straight from x; column packs from the transposed images
-        pack_lines_k<<<dim3((unsigned)ny, (unsigned)nimg), BLK, 0, s>>>(xg, (int)nx, (int)ny,
-                                                                       rowpack, tot);
-        transpose_k<<<dim3((unsigned)((nx + 31) / 32), (unsigned)((ny + 31) / 32), (unsigned)nimg),
-                      dim3(32, 8), 0, s>>>(xg, xT, (int)nx, (int)ny);
+        // row and column packs of every image in one launch, then both line prefixes
         double *ctot = tot + nimg * ny;
-        pack_lines_k<<<dim3((unsigned)nx, (unsigned)nimg), BLK, 0, s>>>(xT, (int)ny, (int)nx,
-                                                                       colpack, ctot);
-        line_prefix_k<<<(unsigned)nimg, BLK, 0, s>>>(tot, (int)ny, rowpre);
-        line_prefix_k<<<(unsigned)nimg, BLK, 0, s>>>(ctot, (int)nx, colpre);
+        pack_lines_k<<<dim3((unsigned)(ny + nx), (unsigned)nimg), BLK, 0, s>>>(
+            xg, (int)nx, (int)ny, rowpack, colpack, tot, ctot);
+        line_prefix_k<<<dim3((unsigned)nimg, 2), BLK, 0, s>>>(tot, ctot, (int)nx, (int)ny, rowpre,
+                                                             colpre);
 
         FwdArgs a;
         a.rowpack = rowpack;
