@@ -97,9 +97,16 @@ size_t bwd_workspace_bytes(const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
 int launch_project(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
                    const float *x, const double *theta, float *y, float *dy, const float *gres,
                    double *gdot, double *dnorm2, hipStream_t s);
+// Optional epilogue of a one-column backprojection: x += lam * Psi^T (w * Psi u).
+struct TvEpilogue {
+    const float *u = nullptr;
+    const float *w = nullptr;
+    const double *lamp = nullptr;   // device scalar lambda
+    int temporal = 0;
+};
 int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
                        const float *y, const double *theta, float *x, hipStream_t s,
-                       int accumulate = 0);
+                       int accumulate = 0, const TvEpilogue *tv = nullptr);
 
 }  // namespace nlrmm
 

@@ -13,14 +13,28 @@ int k_tv_grad_add(const float *u, const float *w, int nx, int ny, int F, int tem
 int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int ny, int F,
                int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s,
                int mode = 0);
-// part: nblk * MD_PART_STRIDE doubles of partials followed by a zero-initialised counter
-// (md_part_doubles(nblk) doubles in all); the counter is zero again after every launch.
+// part: per-block partials, md_part_doubles(nblk) doubles.
 int k_multidot(const float *X, int64_t ldx, int nv, const float *y, const float *z, int64_t n,
                double *part, int nblk, double *out, int ostride, hipStream_t s,
                const int *skip = nullptr);
-inline size_t md_part_doubles(int nblk) { return (size_t)nblk * 72 + 8; }
+inline size_t md_part_doubles(int nblk) { return (size_t)nblk * 72; }
 int k_gemv(const float *X, int64_t ldx, int nv, const double *c, double beta, const float *a,
            double alpha, int64_t n, float *out, hipStream_t s);
+// Two gemv_k jobs in one launch.
+int k_gemv2(const float *X0, int64_t ldx0, int nv0, const double *c0, double beta0,
+            const float *a0, double alpha0, int64_t n0, float *out0, const float *X1,
+            int64_t ldx1, int nv1, const double *c1, double beta1, const float *a1,
+            double alpha1, int64_t n1, float *out1, hipStream_t s);
+// r <- r - X c, scal[1] = ||r||^2, vout = r / ||r|| with the breakdown test against
+// sqrt(scal[0]) (two launches; part holds nblk per-block partials).
+int k_gemv_norm_normalize(const float *X, int64_t ldx, int nv, const double *c, float *r,
+                          int64_t n, double *part, int nblk, double *scal, double tol,
+                          float *vout, int *status, hipStream_t s);
+// New row / column ell of the data Gram and rb[ell]: <X_i, xnew> for i <= ell (X's column
+// ell is xnew) and <b, xnew>, written straight into G (both triangles) and rb.
+int k_multidot_gram_col(const float *X, int64_t ldx, int ell, const float *xnew, const float *b,
+                        int64_t n, double *part, int nblk, double *G, int ldg, double *rb,
+                        hipStream_t s);
 int k_block_update(const float *X, int64_t ldx, int nin, const double *T, int ldt, int kout,
                    int64_t n, float *Y, int64_t ldy, hipStream_t s);
 int k_copy_cols(const float *src, int64_t lds, float *dst, int64_t ldd, int ncols, int64_t n,

@@ -9,6 +9,7 @@
 // Everything that decides (lambda, breakdown, compression size) is decided on the device.
 #include "internal.h"
 #include "krylov.h"
+#include "tv.h"
 
 #include <math.h>
 
@@ -45,26 +46,6 @@ __device__ double block_sum(double v, double *sbuf)
 // ---------------------------------------------------------------------------
 // regulariser
 // ---------------------------------------------------------------------------
-struct TVGeo {
-    int nx, ny, F, temporal;
-    int64_t per_frame;   // ny (nx-1) + (ny-1) nx
-    int64_t dy_off;      // ny (nx-1)
-    int64_t t_off;       // F * per_frame
-};
-
-__device__ __forceinline__ TVGeo tvgeo(int nx, int ny, int F, int temporal)
-{
-    TVGeo g;
-    g.nx = nx;
-    g.ny = ny;
-    g.F = F;
-    g.temporal = temporal && F > 1;
-    g.dy_off = (int64_t)ny * (nx - 1);
-    g.per_frame = g.dy_off + (int64_t)(ny - 1) * nx;
-    g.t_off = (int64_t)F * g.per_frame;
-    return g;
-}
-
 // w = ((Psi u)^2 + eps^2)^(-1/2), one thread per pixel writing its forward differences.
 __global__ void psi_weights_k(const float *__restrict__ u, int nx, int ny, int F, int temporal,
                               float eps, float *__restrict__ w)
@@ -98,23 +79,9 @@ __global__ void tv_grad_add_k(const float *__restrict__ u, const float *__restri
 {
     const float lam = (float)lamp[0];
     const TVGeo g = tvgeo(nx, ny, F, temporal);
-    const int64_t npix = (int64_t)nx * ny;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= npix * F) return;
-    const int64_t f = i / npix, p = i - f * npix;
-    const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
-    const float uc = u[i];
-    const float *wf = w + f * g.per_frame;
-    float acc = 0.0f;
-    if (k < nx - 1) acc -= wf[(int64_t)l * (nx - 1) + k] * (u[i + 1] - uc);
-    if (k > 0) acc += wf[(int64_t)l * (nx - 1) + k - 1] * (uc - u[i - 1]);
-    if (l < ny - 1) acc -= wf[g.dy_off + (int64_t)l * nx + k] * (u[i + nx] - uc);
-    if (l > 0) acc += wf[g.dy_off + (int64_t)(l - 1) * nx + k] * (uc - u[i - nx]);
-    if (g.temporal) {
-        if (f < F - 1) acc -= w[g.t_off + f * npix + p] * (u[i + npix] - uc);
-        if (f > 0) acc += w[g.t_off + (f - 1) * npix + p] * (uc - u[i - npix]);
-    }
-    r[i] += lam * acc;
+    if (i >= (int64_t)nx * ny * F) return;
+    r[i] += lam * tv_grad_at(u, w, g, i);
 }
 
 // Psi u written out (used by tests and by the VarPro regulariser block).
@@ -222,8 +189,8 @@ __global__ __launch_bounds__(BLK) void gram_psi_k(const float *__restrict__ V, i
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 constexpr int MP = 64;            // pixels per chunk
-constexpr int MR = 3 * MP;        // rows per chunk (dx, dy, dt)
-constexpr int MLD = 64 + 4;       // LDS row stride (floats)
+constexpr int MRMAX = 3 * MP;     // rows per chunk (dx, dy and, with frame differences, dt)
+constexpr int MLDR = MRMAX + 1;   // LDS column stride (floats, odd: conflict-free columns)
 
 __device__ __forceinline__ short bf16_rne(float f)
 {
@@ -233,91 +200,147 @@ __device__ __forceinline__ short bf16_rne(float f)
     return (short)(u >> 16);
 }
 
+// G_Psi = (sqrt(w) Psi V)^T (sqrt(w) Psi V) on the matrix cores.  A chunk of MP pixels gives
+// KIND * MP rows (the weighted differences of every column) staged column-major in LDS; each
+// wave multiplies one 32 x 32 tile of the (at most 64 x 64) Gram over the chunk's rows with
+// FP32 accumulation, flushed to FP64 per chunk.  Only tiles on or above the diagonal are
+// formed: for ell <= 32 the four waves split the rows of the single tile, otherwise waves
+// 0..2 take the tiles (0,0), (0,1), (1,1).  Per-block partials go to part[block][ell][ell]
+// (both triangles).
 template <bool BF16>
 __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__ V, int64_t ldv,
                                                        int ell, const float *__restrict__ w,
                                                        int nx, int ny, int F, int temporal,
                                                        double *__restrict__ part)
 {
-    __shared__ float sB[MR][MLD];
-    __shared__ float sw[MR];
+    __shared__ __align__(16) float sB[64][MLDR];
     const TVGeo g = tvgeo(nx, ny, F, temporal);
+    const int KIND = g.temporal ? 3 : 2;
+    const int MR = KIND * MP;
     const int64_t npix = (int64_t)nx * ny;
     const int64_t ntot = npix * F;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
-    const int ti = wv >> 1, tj = wv & 1;   // this wave's 32x32 tile
+    const int pc = lane, cg = wv;          // staging: pixel of the chunk, column group
+    // padded columns stay zero
+    for (int t = tid; t < 64 * MLDR; t += BLK) {
+        const int c = t / MLDR;
+        if (c >= ell) sB[c][t - c * MLDR] = 0.0f;
+    }
+    // this wave's tile and row slice
+    const bool single = ell <= 32;
+    const int ti = single ? 0 : (wv == 2 ? 1 : 0);
+    const int tj = single ? 0 : (wv == 0 ? 0 : 1);
+    const bool busy = single || wv < 3;
+    const int nsl = single ? 4 : 1, sl = single ? wv : 0;
     double accd[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) accd[r] = 0.0;
     const int64_t nchunks = (ntot + MP - 1) / MP;
     for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-        const int64_t i0 = ch * MP;
-        // square roots of the chunk's weights (zero where the difference does not exist)
-        for (int r = tid; r < MR; r += BLK) {
-            const int pc = r / 3, kind = r - pc * 3;
-            const int64_t i = i0 + pc;
-            float v = 0.0f;
-            if (i < ntot) {
-                const int64_t f = i / npix, p = i - f * npix;
-                const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
-                if (kind == 0 && k < nx - 1) v = w[f * g.per_frame + (int64_t)l * (nx - 1) + k];
-                else if (kind == 1 && l < ny - 1) v = w[f * g.per_frame + g.dy_off + (int64_t)l * nx + k];
-                else if (kind == 2 && g.temporal && f < F - 1) v = w[g.t_off + f * npix + p];
+        const int64_t i = ch * MP + pc;
+        float w0 = 0.f, w1 = 0.f, w2 = 0.f;
+        int64_t ox = -1, oy = -1, ot = -1;   // neighbour offsets of the existing differences
+        if (i < ntot) {
+            const int64_t f = i / npix, p = i - f * npix;
+            const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
+            if (k < nx - 1) {
+                w0 = sqrtf(w[f * g.per_frame + (int64_t)l * (nx - 1) + k]);
+                ox = 1;
             }
-            sw[r] = sqrtf(v);
-        }
-        __syncthreads();
-        // weighted differences of every column (zero columns pad to 64)
-        for (int t = tid; t < MP * 64; t += BLK) {
-            const int c = t / MP, pc = t - c * MP;
-            const int64_t i = i0 + pc;
-            float dx = 0.0f, dy = 0.0f, dt = 0.0f;
-            if (c < ell && i < ntot) {
-                const int64_t f = i / npix, p = i - f * npix;
-                const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
-                const float *vc = V + (int64_t)c * ldv;
-                const float x0 = vc[i];
-                if (k < nx - 1) dx = vc[i + 1] - x0;
-                if (l < ny - 1) dy = vc[i + nx] - x0;
-                if (g.temporal && f < F - 1) dt = vc[i + npix] - x0;
+            if (l < ny - 1) {
+                w1 = sqrtf(w[f * g.per_frame + g.dy_off + (int64_t)l * nx + k]);
+                oy = nx;
             }
-            sB[3 * pc + 0][c] = sw[3 * pc + 0] * dx;
-            sB[3 * pc + 1][c] = sw[3 * pc + 1] * dy;
-            sB[3 * pc + 2][c] = sw[3 * pc + 2] * dt;
+            if (g.temporal && f < F - 1) {
+                w2 = sqrtf(w[g.t_off + f * npix + p]);
+                ot = npix;
+            }
         }
-        __syncthreads();
-        f32x16 acc;
+        // four columns per step, all their loads issued before any use
+        for (int c0 = cg; c0 < ell; c0 += 4 * (BLK / 64)) {
+            float x0[4], x1[4], x2[4], x3[4];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-        const int ca = 32 * ti + (lane & 31), cb = 32 * tj + (lane & 31);
-        if (BF16) {
-            for (int k0 = 0; k0 < MR; k0 += 8) {
-                s16x4 a, b;
+            for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u * (BLK / 64);
+                const bool ok = c < ell && i < ntot;
+                const float *vc = V + (int64_t)(ok ? c : 0) * ldv;
+                x0[u] = ok ? vc[i] : 0.0f;
+                x1[u] = (ok && ox > 0) ? vc[i + ox] : x0[u];
+                x2[u] = (ok && oy > 0) ? vc[i + oy] : x0[u];
+                x3[u] = (ok && ot > 0) ? vc[i + ot] : x0[u];
+            }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int row = k0 + 4 * (lane >> 5) + q;
-                    a[q] = bf16_rne(sB[row][ca]);
-                    b[q] = bf16_rne(sB[row][cb]);
+            for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u * (BLK / 64);
+                if (c < ell) {
+                    float *col = &sB[c][KIND * pc];
+                    col[0] = w0 * (x1[u] - x0[u]);
+                    col[1] = w1 * (x2[u] - x0[u]);
+                    if (KIND == 3) col[2] = w2 * (x3[u] - x0[u]);
                 }
-                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-            }
-        } else {
-            for (int k0 = 0; k0 < MR; k0 += 2) {
-                const int row = k0 + (lane >> 5);
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(sB[row][ca], sB[row][cb], acc, 0, 0, 0);
             }
         }
+        __syncthreads();
+        if (busy) {
+            f32x16 acc;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) accd[r] += (double)acc[r];
+            for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+            const int ca = 32 * ti + (lane & 31), cb = 32 * tj + (lane & 31);
+            const int kbeg = (MR * sl) / nsl, kend = (MR * (sl + 1)) / nsl;
+            if (BF16) {
+                for (int k0 = kbeg; k0 < kend; k0 += 8) {
+                    s16x4 av, bv;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int row = k0 + 4 * (lane >> 5) + q;
+                        av[q] = bf16_rne(row < kend ? sB[ca][row] : 0.0f);
+                        bv[q] = bf16_rne(row < kend ? sB[cb][row] : 0.0f);
+                    }
+                    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+                }
+            } else {
+                for (int k0 = kbeg; k0 < kend; k0 += 2) {
+                    const int row = k0 + (lane >> 5);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(sB[ca][row], sB[cb][row], acc, 0,
+                                                               0, 0);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) accd[r] += (double)acc[r];
+        }
         __syncthreads();
     }
     double *out = part + (int64_t)blockIdx.x * ell * ell;
+    if (single) {
+        // the four row slices of tile (0,0) meet in LDS (the staging area is free after the
+        // last chunk's barrier), summed in slice order
+        double *sacc = reinterpret_cast<double *>(&sB[0][0]);   // [3][16][64]
+        if (wv > 0) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int i = 32 * ti + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int j = 32 * tj + (lane & 31);
-        if (i < ell && j < ell) out[i * ell + j] = accd[r];
+            for (int r = 0; r < 16; ++r) sacc[((wv - 1) * 16 + r) * 64 + lane] = accd[r];
+        }
+        __syncthreads();
+        if (wv == 0) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const double v = ((accd[r] + sacc[r * 64 + lane]) + sacc[(16 + r) * 64 + lane]) +
+                                 sacc[(32 + r) * 64 + lane];
+                const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int j = lane & 31;
+                if (i < ell && j < ell) out[i * ell + j] = v;
+            }
+        }
+    } else if (busy) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = 32 * ti + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const int j = 32 * tj + (lane & 31);
+            if (i < ell && j < ell) {
+                out[i * ell + j] = accd[r];
+                if (ti != tj) out[j * ell + i] = accd[r];
+            }
+        }
     }
 }
 
@@ -343,24 +366,55 @@ __global__ __launch_bounds__(64) void reduce_gram_k(const double *__restrict__ p
 // An extra row (i = nv) accumulates y[e] * z[e] when z != null.
 constexpr int MD_MAX = 72;
 
-// Inner products out[i * ostride] = <X_i, y> (i < nv) and <z, y> (i == nv when z is given),
-// FP64 accumulation.  Each block reduces its share of the elements for groups of 8 outputs
-// through LDS, writes per-block partials, and the last block to finish (device-scope counter
-// after a release fence) sums the partials of every output in block order, so the result does
-// not depend on scheduling.  The counter lives after the partials (part + cap * MD_MAX), is
-// zero between launches and is reset by that last block.
+// Inner products <X_i, y> (i < nv) and <z, y> (i == nv when z is given), FP64 accumulation:
+// per-block partials part[block][i].  Each block reduces its share of the elements for
+// groups of 8 outputs through LDS (32 threads per output, then a 32-lane butterfly).
 __global__ __launch_bounds__(BLK) void multidot_k(const float *__restrict__ X, int64_t ldx, int nv,
                                                   const float *__restrict__ y,
                                                   const float *__restrict__ z, int64_t n,
-                                                  double *part, int cap, double *__restrict__ out,
-                                                  int ostride, const int *skip)
+                                                  double *__restrict__ part, const int *skip)
 {
     if (skip != nullptr && *skip != 0) return;
     __shared__ double sacc[8][BLK];
-    __shared__ int last;
     const int tid = threadIdx.x;
     const int nout = nv + (z != nullptr ? 1 : 0);
-    const int lane = tid & 63, wv = tid >> 6;
+    auto block_reduce = [&](int i0, const double (&acc)[8]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) sacc[a][tid] = acc[a];
+        __syncthreads();
+        const int a = tid >> 5, l = tid & 31;   // 32 threads per output of the group
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < BLK / 32; ++k) s += sacc[a][l + 32 * k];
+        for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
+        if (l == 0 && i0 + a < nout) part[(int64_t)blockIdx.x * nout + i0 + a] = s;
+        __syncthreads();
+    };
+    if ((int64_t)gridDim.x * BLK >= n) {
+        // at most one element per thread: issue every load first, then reduce by groups
+        // (the FP64 product of two floats is exact)
+        const int64_t e = (int64_t)blockIdx.x * BLK + tid;
+        const bool in = e < n;
+        const float ye = in ? y[e] : 0.0f;
+        float xv[MD_MAX];
+#pragma unroll
+        for (int i = 0; i < MD_MAX; ++i) {
+            float v = 0.0f;
+            if (i < nv) v = in ? X[(int64_t)i * ldx + e] : 0.0f;
+            else if (i == nv && z != nullptr) v = in ? z[e] : 0.0f;
+            xv[i] = v;
+        }
+#pragma unroll
+        for (int i0 = 0; i0 < MD_MAX; i0 += 8) {
+            if (i0 < nout) {
+                double acc[8];
+#pragma unroll
+                for (int a = 0; a < 8; ++a) acc[a] = (double)xv[i0 + a] * (double)ye;
+                block_reduce(i0, acc);
+            }
+        }
+        return;
+    }
     for (int i0 = 0; i0 < nout; i0 += 8) {
         double acc[8];
 #pragma unroll
@@ -374,41 +428,44 @@ __global__ __launch_bounds__(BLK) void multidot_k(const float *__restrict__ X, i
                 else if (i == nv && z != nullptr) acc[a] = fma((double)z[e], ye, acc[a]);
             }
         }
-#pragma unroll
-        for (int a = 0; a < 8; ++a) sacc[a][tid] = acc[a];
-        __syncthreads();
-        {
-            const int a = tid >> 5, l = tid & 31;   // 32 threads per output of the group
-            double s = 0.0;
-#pragma unroll
-            for (int k = 0; k < BLK / 32; ++k) s += sacc[a][l + 32 * k];
-            for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
-            if (l == 0 && i0 + a < nout) part[(int64_t)blockIdx.x * nout + i0 + a] = s;
-        }
-        __syncthreads();
+        block_reduce(i0, acc);
     }
-    unsigned *cnt = reinterpret_cast<unsigned *>(part + (int64_t)cap * MD_MAX);
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) last = (atomicAdd(cnt, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    const int nblk = gridDim.x;
-    for (int i = wv; i < nout; i += BLK / 64) {
-        double s = 0.0;
-        for (int b = lane; b < nblk; b += 64) s += part[(int64_t)b * nout + i];
-        s = wave_sum(s);
-        if (lane == 0) out[(int64_t)i * ostride] = s;
-    }
-    if (tid == 0) *cnt = 0u;
 }
 
-// out[e] = alpha * a[e] + beta * sum_i X_i[e] c_i   (a may be null; c FP64 on the device)
+// out[i * ostride] = sum_b part[b][i]: one wave per output, lane-strided partial sums
+// and a fixed butterfly, so the result is independent of scheduling.
+__global__ __launch_bounds__(64) void reduce_vec_k(const double *__restrict__ part, int nblk,
+                                                   int nout, double *__restrict__ out,
+                                                   int ostride, const int *skip,
+                                                   double *__restrict__ G, int ldg,
+                                                   double *__restrict__ rb)
+{
+    if (skip != nullptr && *skip != 0) return;
+    const int i = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 64) s += part[(int64_t)b * nout + i];
+    s = wave_sum(s);
+    if (threadIdx.x != 0) return;
+    if (G == nullptr) {
+        out[(int64_t)i * ostride] = s;
+    } else {
+        // new row / column ell = nout - 2 of a symmetric Gram, last output into rb[ell]
+        const int ell = nout - 2;
+        if (i <= ell) {
+            G[i * ldg + ell] = s;
+            G[ell * ldg + i] = s;
+        } else {
+            rb[ell] = s;
+        }
+    }
+}
+
+// out[e] = alpha * a[e] + beta * sum_i X_i[e] c_i   (a may be null or equal to out; c FP64
+// on the device)
 __global__ __launch_bounds__(BLK) void gemv_k(const float *__restrict__ X, int64_t ldx, int nv,
                                               const double *__restrict__ c, double beta,
-                                              const float *__restrict__ a, double alpha,
-                                              int64_t n, float *__restrict__ out)
+                                              const float *a, double alpha, int64_t n,
+                                              float *out)
 {
     __shared__ double sc[MD_MAX];
     for (int i = threadIdx.x; i < nv; i += BLK) sc[i] = c[i];
@@ -421,6 +478,96 @@ __global__ __launch_bounds__(BLK) void gemv_k(const float *__restrict__ X, int64
         if (a) r += alpha * (double)a[e];
         out[e] = (float)r;
     }
+}
+
+// Two independent gemv_k jobs in one launch (blocks [0, g0) do the first).
+struct GemvJob {
+    const float *X;
+    int64_t ldx;
+    int nv;
+    const double *c;
+    double beta;
+    const float *a;
+    double alpha;
+    int64_t n;
+    float *out;
+};
+
+__global__ __launch_bounds__(BLK) void gemv2_k(GemvJob j0, GemvJob j1, unsigned g0)
+{
+    __shared__ double sc[MD_MAX];
+    const bool first = blockIdx.x < g0;
+    const GemvJob &j = first ? j0 : j1;
+    const int64_t blk = first ? blockIdx.x : blockIdx.x - g0;
+    const int64_t nblk = first ? g0 : gridDim.x - g0;
+    for (int i = threadIdx.x; i < j.nv; i += BLK) sc[i] = j.c[i];
+    __syncthreads();
+    for (int64_t e = blk * BLK + threadIdx.x; e < j.n; e += nblk * BLK) {
+        double s = 0.0;
+        for (int i = 0; i < j.nv; ++i) s = fma((double)j.X[(int64_t)i * j.ldx + e], sc[i], s);
+        double r = j.beta * s;
+        if (j.a) r += j.alpha * (double)j.a[e];
+        j.out[e] = (float)r;
+    }
+}
+
+// out = r - X c (as gemv_k with beta = -1, alpha = 1, a = r), plus per-block partial sums of
+// out^2 (FP64) in part[block].
+__global__ __launch_bounds__(BLK) void gemv_norm_k(const float *__restrict__ X, int64_t ldx, int nv,
+                                                   const double *__restrict__ c,
+                                                   const float *r, int64_t n, float *out,
+                                                   double *__restrict__ part)
+{
+    __shared__ double sc[MD_MAX];
+    __shared__ double sw[BLK / 64];
+    for (int i = threadIdx.x; i < nv; i += BLK) sc[i] = c[i];
+    __syncthreads();
+    double q = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * BLK + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * BLK) {
+        double s = 0.0;
+        for (int i = 0; i < nv; ++i) s = fma((double)X[(int64_t)i * ldx + e], sc[i], s);
+        const float o = (float)(-1.0 * s + 1.0 * (double)r[e]);
+        out[e] = o;
+        q = fma((double)o, (double)o, q);
+    }
+    q = wave_sum(q);
+    if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < BLK / 64; ++w) t += sw[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+// scal[1] = sum_b part[b] (same fixed order in every block), then as normalize_into_k:
+// vout = r / sqrt(scal[1]) with the breakdown test against sqrt(scal[0]).
+__global__ __launch_bounds__(BLK) void normalize_red_k(const float *__restrict__ r,
+                                                       const double *__restrict__ part, int nblk,
+                                                       double *__restrict__ scal, double tol,
+                                                       int64_t n, float *__restrict__ vout,
+                                                       int *__restrict__ status)
+{
+    __shared__ double stot;
+    if (threadIdx.x < 64) {
+        double t = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += 64) t += part[b];
+        t = wave_sum(t);
+        if (threadIdx.x == 0) stot = t;
+    }
+    __syncthreads();
+    const double tot = stot;
+    const double raw = sqrt(fmax(scal[0], 0.0));
+    const double perp = sqrt(fmax(tot, 0.0));
+    const double inv = perp > 0.0 ? 1.0 / perp : 0.0;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) {
+        scal[1] = tot;
+        if (!(perp > tol * raw)) atomicOr(status, NLRMM_ST_BREAKDOWN);
+        if (!isfinite(perp)) atomicOr(status, NLRMM_ST_NONFINITE);
+    }
+    if (e < n) vout[e] = (float)((double)r[e] * inv);
 }
 
 // r -= V h with h = part-reduced coefficients already in `h` (FP64).
@@ -1693,11 +1840,53 @@ int k_multidot(const float *X, int64_t ldx, int nv, const float *y, const float 
 {
     const int nout = nv + (z ? 1 : 0);
     if (nout > MD_MAX || nblk < 1) return NLRMM_ESHAPE;
-    // at least two elements per thread, at most the partials' capacity
-    int64_t g = (n + 2 * BLK - 1) / (2 * BLK);
+    // one element per thread at most, at most the partials' capacity
+    int64_t g = (n + BLK - 1) / BLK;
     if (g > nblk) g = nblk;
     if (g < 1) g = 1;
-    multidot_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, nv, y, z, n, part, nblk, out, ostride, skip);
+    multidot_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, nv, y, z, n, part, skip);
+    reduce_vec_k<<<(unsigned)nout, 64, 0, s>>>(part, (int)g, nout, out, ostride, skip, nullptr, 0,
+                                               nullptr);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_multidot_gram_col(const float *X, int64_t ldx, int ell, const float *xnew, const float *b,
+                        int64_t n, double *part, int nblk, double *G, int ldg, double *rb,
+                        hipStream_t s)
+{
+    const int nout = ell + 2;
+    if (nout > MD_MAX || nblk < 1) return NLRMM_ESHAPE;
+    int64_t g = (n + BLK - 1) / BLK;
+    if (g > nblk) g = nblk;
+    if (g < 1) g = 1;
+    multidot_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, ell + 1, xnew, b, n, part, nullptr);
+    reduce_vec_k<<<(unsigned)nout, 64, 0, s>>>(part, (int)g, nout, nullptr, 0, nullptr, G, ldg,
+                                               rb);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_gemv2(const float *X0, int64_t ldx0, int nv0, const double *c0, double beta0,
+            const float *a0, double alpha0, int64_t n0, float *out0, const float *X1,
+            int64_t ldx1, int nv1, const double *c1, double beta1, const float *a1,
+            double alpha1, int64_t n1, float *out1, hipStream_t s)
+{
+    if (nv0 > MD_MAX || nv1 > MD_MAX) return NLRMM_ESHAPE;
+    const unsigned g0 = grid_for(n0), g1 = grid_for(n1);
+    gemv2_k<<<g0 + g1, BLK, 0, s>>>(GemvJob{X0, ldx0, nv0, c0, beta0, a0, alpha0, n0, out0},
+                                    GemvJob{X1, ldx1, nv1, c1, beta1, a1, alpha1, n1, out1}, g0);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_gemv_norm_normalize(const float *X, int64_t ldx, int nv, const double *c, float *r,
+                          int64_t n, double *part, int nblk, double *scal, double tol,
+                          float *vout, int *status, hipStream_t s)
+{
+    if (nv > MD_MAX) return NLRMM_ESHAPE;
+    int64_t g = grid_for(n);
+    if (g > nblk) g = nblk;
+    gemv_norm_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, nv, c, r, n, r, part);
+    normalize_red_k<<<(unsigned)((n + BLK - 1) / BLK), BLK, 0, s>>>(r, part, (int)g, scal, tol, n,
+                                                                    vout, status);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 

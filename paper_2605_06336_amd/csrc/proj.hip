@@ -28,6 +28,7 @@
 // it (FP32 offsets) and gathers its <= E+1 bins.  Same weight function as the forward;
 // the two are transposes up to FP32 rounding of the offsets.
 #include "internal.h"
+#include "tv.h"
 
 #include <math.h>
 
@@ -496,6 +497,7 @@ struct BwdArgs {
     int nsplit;      // views of a frame split over blockIdx.z; partial images when > 1
     float *part;     // [nsplit][col][frame][ny][nx] partial images (nsplit > 1)
     int accumulate;  // x += result instead of x = result
+    TvEpilogue tv;   // one column: x += lam Psi^T (w Psi u) (tv.u null: none)
 };
 
 // Per-view constants of one backward tile: the footprint start of the tile centre in bin
@@ -604,19 +606,27 @@ __global__ __launch_bounds__(BLK) void bwd_tiles_k(BwdArgs a)
             a.part[split * tot + o] = (float)(acc / a.ds);
         } else {
             const double prev = a.accumulate ? (double)a.x[o] : 0.0;
-            a.x[o] = (float)(prev + acc / a.ds);
+            float v = (float)(prev + acc / a.ds);
+            if (a.tv.u != nullptr)
+                v += (float)a.tv.lamp[0] *
+                     tv_grad_at(a.tv.u, a.tv.w, tvgeo(a.nx, a.ny, a.nframes, a.tv.temporal), o);
+            a.x[o] = v;
         }
     }
 }
 
 __global__ void sum_splits_k(const float *__restrict__ part, int nsplit, int64_t n,
-                             float *__restrict__ x, int accumulate)
+                             float *__restrict__ x, int accumulate, TvEpilogue tv, int nx, int ny,
+                             int nframes)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double s = accumulate ? (double)x[i] : 0.0;
     for (int k = 0; k < nsplit; ++k) s += (double)part[k * n + i];
-    x[i] = (float)s;
+    float v = (float)s;
+    if (tv.u != nullptr)
+        v += (float)tv.lamp[0] * tv_grad_at(tv.u, tv.w, tvgeo(nx, ny, nframes, tv.temporal), i);
+    x[i] = v;
 }
 
 int edges_inside(const nlrmm_geom &g)
@@ -826,8 +836,9 @@ size_t bwd_workspace_bytes(const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
 
 int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
                        const float *y, const double *theta, float *x, hipStream_t s,
-                       int accumulate)
+                       int accumulate, const TvEpilogue *tv)
 {
+    if (tv && tv->u && ncols != 1) return NLRMM_ENOTSUP;
     const int E = edges_inside(g);
     if (E < 1 || E > 4) return NLRMM_ESHAPE;
     const int W = (int)ceil((TILE - 1) * g.d * 1.4142135623730951 / g.ds) + E + 4;
@@ -857,6 +868,7 @@ int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b
     }
     a.part = nullptr;
     a.accumulate = accumulate;
+    a.tv = tv ? *tv : TvEpilogue();
     if (a.nsplit > 1) {
         int rc = ensure_workspace(ctx, bwd_workspace_bytes(g, b, ncols, ctx->cu_count), s);
         if (rc) return rc;
@@ -875,7 +887,8 @@ int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b
     timing_mark(ctx, 1, 1, s);
     if (a.nsplit > 1) {
         const int64_t n = (int64_t)ncols * b.nframes * g.nx * g.ny;
-        sum_splits_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a.part, a.nsplit, n, x, accumulate);
+        sum_splits_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a.part, a.nsplit, n, x, accumulate,
+                                                                 a.tv, g.nx, g.ny, b.nframes);
     }
     NLRMM_HIP_CHECK(hipGetLastError());
     return NLRMM_OK;

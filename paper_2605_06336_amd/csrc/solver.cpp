@@ -36,6 +36,7 @@ struct Solver {
     int ld = 0;     // Gram leading dimension
     int ell = 0;    // current number of basis columns (host bookkeeping)
     int md_blocks = 512, gram_blocks = 256, nchunks = 1;
+    bool rho_ready = false;   // rho = A V z - b already formed for the next residual
     // device buffers
     float *V = nullptr, *AV = nullptr, *Vtmp = nullptr, *u = nullptr, *r = nullptr,
           *rho = nullptr, *w = nullptr;
@@ -169,10 +170,9 @@ static int cgs2_append(Solver &S, int ell, hipStream_t s)
     RC(k_multidot(S.V, S.n, ell, S.r, S.r, S.n, S.part_md, S.md_blocks, S.hb, 1, s));
     RC(k_gemv(S.V, S.n, ell, S.hb, -1.0, S.r, 1.0, S.n, S.r, s));
     RC(k_multidot(S.V, S.n, ell, S.r, nullptr, S.n, S.part_md, S.md_blocks, S.hb2, 1, s));
-    RC(k_gemv(S.V, S.n, ell, S.hb2, -1.0, S.r, 1.0, S.n, S.r, s));
-    RC(k_multidot(S.V, S.n, 0, S.r, S.r, S.n, S.part_md, S.md_blocks, S.hb + ell + 1, 1, s));
-    RC(k_normalize_into(S.r, S.hb + ell, S.cfg.breakdown_tol, S.n, S.V + (int64_t)ell * S.n,
-                        S.status, nullptr, s));
+    RC(k_gemv_norm_normalize(S.V, S.n, ell, S.hb2, S.r, S.n, S.part_md, S.md_blocks * 72,
+                             S.hb + ell, S.cfg.breakdown_tol, S.V + (int64_t)ell * S.n, S.status,
+                             s));
     return NLRMM_OK;
 }
 
@@ -181,7 +181,17 @@ static int mm_residual(Solver &S, const nlrmm_batch &b, const double *theta, int
                        const float *bvec, hipStream_t s)
 {
     const int64_t m = m_of(S, b);
-    RC(k_gemv(S.AV, m, ell, S.z, 1.0, bvec, -1.0, m, S.rho, s));
+    if (!S.rho_ready) RC(k_gemv(S.AV, m, ell, S.z, 1.0, bvec, -1.0, m, S.rho, s));
+    S.rho_ready = false;
+    if (!per_frame(S, b)) {
+        // one launch pair: backprojection with the TV-gradient term as its epilogue
+        TvEpilogue tv;
+        tv.u = S.u;
+        tv.w = S.w;
+        tv.lamp = S.sc + S_LAM;
+        tv.temporal = S.cfg.temporal;
+        return launch_backproject(S.ctx, S.g, b, 1, S.rho, theta, S.r, s, 0, &tv);
+    }
     RC(bproj(S, b, S.rho, theta, S.r, s));
     RC(k_tv_grad_add(S.u, S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.sc + S_LAM, S.r, s));
     return NLRMM_OK;
@@ -197,22 +207,30 @@ static int expand(Solver &S, const nlrmm_batch &b, const double *theta, const fl
     RC(mm_residual(S, b, theta, ell, bvec, s));
     RC(cgs2_append(S, ell, s));
     RC(proj_plain(S, b, 1, S.V + (int64_t)ell * S.n, theta, S.AV + (int64_t)ell * m, s));
-    RC(k_multidot(S.AV, m, ell + 1, S.AV + (int64_t)ell * m, bvec, m, S.part_md, S.md_blocks,
-                  S.hb2, 1, s));
-    RC(k_scatter_gram(S.hb2, ell, S.GA, S.ld, S.rb, s));
+    RC(k_multidot_gram_col(S.AV, m, ell, S.AV + (int64_t)ell * m, bvec, m, S.part_md,
+                           S.md_blocks, S.GA, S.ld, S.rb, s));
     S.ell = ell + 1;
     return NLRMM_OK;
 }
 
 // One projected solve on the current basis: weights from u, weighted regulariser Gram,
 // lambda and z, then u = V z.
-static int projected_solve(Solver &S, hipStream_t s)
+static int projected_solve(Solver &S, hipStream_t s, const nlrmm_batch *b = nullptr,
+                           const float *bvec = nullptr)
 {
     RC(k_psi_weights(S.u, S.g.nx, S.g.ny, S.F, S.cfg.temporal, (float)S.cfg.eps, S.w, s));
     RC(k_gram_psi(S.V, S.n, S.ell, S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.part_gram,
                   S.gram_blocks, S.GP, S.ld, s, S.cfg.gram_precision));
     RC(k_gks_solve(S.GA, S.GP, S.ld, S.rb, S.sc + S_BNORM2, S.ell, S.cfg.lam_fix, S.z,
                    S.sc + S_LAM, S.status, s));
+    if (b && bvec) {
+        // u = V z and the data residual A V z - b of the expansion that follows, one launch
+        const int64_t m = m_of(S, *b);
+        RC(k_gemv2(S.V, S.n, S.ell, S.z, 1.0, nullptr, 0.0, S.n, S.u, S.AV, m, S.ell, S.z, 1.0,
+                   bvec, -1.0, m, S.rho, s));
+        S.rho_ready = true;
+        return NLRMM_OK;
+    }
     RC(k_gemv(S.V, S.n, S.ell, S.z, 1.0, nullptr, 0.0, S.n, S.u, s));
     return NLRMM_OK;
 }
@@ -345,8 +363,9 @@ static int solver_outer(Solver &S, const nlrmm_batch &b, double *theta, const fl
     RC(gram_from_scratch(S, S.ell, m, bvec, s));
     const int nsolve = S.cfg.solves;
     for (int t = 0; t < nsolve; ++t) {
-        RC(projected_solve(S, s));
-        if (t < nsolve - 1) RC(expand(S, b, S.thk, bvec, s));
+        const bool more = t < nsolve - 1;
+        RC(projected_solve(S, s, more ? &b : nullptr, more ? bvec : nullptr));
+        if (more) RC(expand(S, b, S.thk, bvec, s));
     }
     RC(compress(S, b, s));
     if (S.cfg.param_update == 1) RC(gn_update(S, b, theta, bvec, s));
@@ -472,7 +491,6 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
     if (hipMemcpy(S->alphas, al, sizeof(al), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(S->sc, 0, sizeof(double) * S_NB) != hipSuccess ||
         hipMemset(S->status, 0, sizeof(int)) != hipSuccess ||
-        hipMemset(S->part_md, 0, sizeof(double) * md_part_doubles(S->md_blocks)) != hipSuccess ||
         hipMemset(S->GA, 0, sizeof(double) * S->ld * S->ld) != hipSuccess ||
         hipMemset(S->GP, 0, sizeof(double) * S->ld * S->ld) != hipSuccess) {
         delete S;
@@ -590,9 +608,6 @@ static int scratch_view(nlrmm_ctx *ctx, Solver &S, int64_t n, int64_t m, int kca
     S.rho = (float *)take(sizeof(float) * m);
     S.Vtmp = (float *)take(sizeof(float) * (size_t)kmin * big);
     S.part_md = (double *)take(sizeof(double) * md_part_doubles(S.md_blocks));
-    // the partials' completion counter must start at zero (a fill kernel: capturable)
-    if ((rc = k_fill_i32(reinterpret_cast<int *>(S.part_md + (size_t)S.md_blocks * 72), 2, 0, s)))
-        return rc;
     S.part_gram = (double *)take(sizeof(double) * (size_t)S.gram_blocks * 64 * 64);
     S.hb = (double *)take(sizeof(double) * (kcap + 4));
     S.hb2 = (double *)take(sizeof(double) * (kcap + 4));
