@@ -46,9 +46,10 @@ int k_normalize_into(const float *r, const double *scal, double tol, int64_t n, 
 int k_gks_solve(const double *GA, const double *GP, int ldg, const double *rb, const double *scal,
                 int ell, double lam_fix, double *z, double *out, int *status, hipStream_t s,
                 int method = 1);
+// method: 0 Jacobi (4 waves), 1 tridiagonal + Sturm bisection + inverse iteration (1 wave)
 int k_compress_eig(const double *GA, const double *GP, int ldg, const double *lam, int ell,
                    int kmin, const double *z, double *T, int ldt, double *zout, int *kout,
-                   int *status, hipStream_t s);
+                   int *status, hipStream_t s, int method = 1);
 int k_gram_transform(double *G, int ldg, double *rb, int ell, const double *T, int ldt,
                      const int *kp, hipStream_t s);
 

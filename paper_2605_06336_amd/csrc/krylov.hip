@@ -1647,6 +1647,244 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
     }
 }
 
+// Number of eigenvalues of the symmetric tridiagonal T (diagonal dd, off-diagonal ee) below
+// x: sign changes of the leading-minor sequence p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}
+// (p_{-1} = 0, p_0 = 1), i.e. the negative pivots of the LDL^T factorisation of T - x I,
+// without divisions; the pair (p_i, p_{i-1}) is rescaled by powers of two to stay in range.
+template <int NB>
+__device__ __forceinline__ int sturm_below(double x, const double (&dd)[NB], const double (&ee)[NB])
+{
+    double p1 = 1.0, p2 = 0.0;   // p_{i-1}, p_{i-2}
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const double em = i > 0 ? ee[i - 1] : 0.0;
+        double p = fma(dd[i] - x, p1, -(em * em) * p2);
+        // an exact zero counts as a sign change (x treated as just above the root)
+        if ((p < 0.0) != (p1 < 0.0) || p == 0.0) ++cnt;
+        if (p == 0.0) p = -copysign(0x1p-600, p1);
+        p2 = p1;
+        p1 = p;
+        if (i & 1) {
+            const double m = fmax(fabs(p1), fabs(p2));
+            if (m > 0x1p200) {
+                p1 *= 0x1p-200;
+                p2 *= 0x1p-200;
+            } else if (m < 0x1p-200) {
+                p1 *= 0x1p200;
+                p2 *= 0x1p200;
+            }
+        }
+    }
+    return cnt;
+}
+
+// Compression in one wave (same result as compress_eig_k): S = GA + lam GP is reduced to a
+// tridiagonal T = Q^T S Q (Householder, reflectors kept in registers), the kmin - 1 largest
+// eigenvalues of T are found by 65-way Sturm bisection, lane t computes the eigenvector of
+// eigenvalue t by two steps of inverse iteration (LDL^T of T - mu I, pivots perturbed away
+// from zero), the vectors are orthonormalised in order (classical Gram-Schmidt, twice) and
+// mapped back by Q.  The sign rule, W^T z, the remainder c and the outputs follow
+// compress_eig_k.  S is padded to NB with zeros: the padding adds zero eigenvalues below
+// the positive ones that are wanted.
+template <int NB>
+__global__ __launch_bounds__(64) void compress_reg_k(const double *__restrict__ GA,
+                                                    const double *__restrict__ GP, int ldg,
+                                                    const double *__restrict__ lamp, int ell,
+                                                    int kmin, const double *__restrict__ zin,
+                                                    double *__restrict__ T, int ldt,
+                                                    double *__restrict__ zout,
+                                                    int *__restrict__ out_k,
+                                                    int *__restrict__ status)
+{
+    constexpr int LD = NB + 2;
+    constexpr int KW = 15;   // kmin - 1 <= 15
+    __shared__ double sX[NB * LD];   // symmetrisation, then the reflectors (row j: reflector j)
+    __shared__ double sY[16 * LD];   // eigenvectors of T (row t)
+    __shared__ double sv[64], sw[64], sdd[64], see[64], stau[64], smu[16], swz[16];
+    const int n = ell;
+    const int lane = threadIdx.x;
+    const bool row = lane < NB;
+    const int kw = kmin - 1;
+    const double lam = lamp[0];
+    double p[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+        p[c] = (lane < n && c < n) ? GA[lane * ldg + c] + lam * GP[lane * ldg + c] : 0.0;
+    // symmetrise through LDS
+    if (row) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) sX[c * LD + lane] = p[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NB; ++c) p[c] = row ? 0.5 * (p[c] + sX[lane * LD + c]) : 0.0;
+    __syncthreads();
+    // 1. tridiagonalise
+    TriSteps<0, NB>::run(p, lane, sv, sw, sdd, see, stau);
+    {
+        const double d2 = lane_bcast(p[NB - 2], NB - 2);
+        const double e2 = lane_bcast(p[NB - 2], NB - 1);
+        const double d1 = lane_bcast(p[NB - 1], NB - 1);
+        sdd[NB - 2] = d2;
+        see[NB - 2] = e2;
+        sdd[NB - 1] = d1;
+        see[NB - 1] = 0.0;
+        stau[NB - 2] = 0.0;
+        stau[NB - 1] = 0.0;
+    }
+    if (row) {
+#pragma unroll
+        for (int j = 0; j + 2 < NB; ++j) sX[j * LD + lane] = (lane > j) ? p[j] : 0.0;
+    }
+    __syncthreads();
+    double dd[NB], ee[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        dd[k] = sdd[k];
+        ee[k] = see[k];
+    }
+    // 2. the kw largest eigenvalues by bisection on Gershgorin bounds
+    double glo = 0.0, ghi = 0.0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const double r = fabs(ee[i]) + (i > 0 ? fabs(ee[i - 1]) : 0.0);
+        glo = i == 0 ? dd[i] - r : fmin(glo, dd[i] - r);
+        ghi = i == 0 ? dd[i] + r : fmax(ghi, dd[i] + r);
+    }
+    const double span = fmax(ghi - glo, 1e-300);
+    glo -= 1e-12 * span;
+    ghi += 1e-12 * span;
+    for (int t = 0; t < kw; ++t) {
+        // smallest x with #(eig < x) >= NB - t, i.e. just above the (t+1)-th largest
+        const int need = NB - t;
+        double lo = glo, hi = ghi;
+        for (int round = 0; round < 14; ++round) {
+            const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+            const unsigned long long m = __ballot(sturm_below<NB>(x, dd, ee) >= need);
+            const int k = m ? (__ffsll((unsigned long long)m) - 1) : 64;
+            const double nlo = (k == 0) ? lo : lo + (hi - lo) * (double)k / 65.0;
+            const double nhi = (k == 64) ? hi : lo + (hi - lo) * (double)(k + 1) / 65.0;
+            lo = nlo;
+            hi = nhi;
+            if (hi - lo <= 2e-16 * fmax(fabs(lo), fabs(hi))) break;
+        }
+        if (lane == 0) smu[t] = 0.5 * (lo + hi);
+    }
+    __syncthreads();
+    // 3. inverse iteration, lane t < kw for eigenvalue t (tridiagonal basis)
+    double y[NB];
+    {
+        const double mu = lane < kw ? smu[lane] : 0.0;
+        const double tiny = 0x1p-52 * fmax(fabs(mu), span);
+        double q[NB];
+        // LDL^T pivots of T - mu I
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            double v = dd[i] - mu;
+            if (i > 0) v -= ee[i - 1] * ee[i - 1] / q[i - 1];
+            if (fabs(v) < tiny) v = v < 0.0 ? -tiny : tiny;
+            q[i] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) y[i] = i < n ? 1.0 + 1e-3 * i : 0.0;
+        for (int it = 0; it < 2; ++it) {
+            // solve L D L^T y = y: forward (unit L, l_i = e_{i-1} / q_{i-1}), diagonal, back
+#pragma unroll
+            for (int i = 1; i < NB; ++i) y[i] -= (ee[i - 1] / q[i - 1]) * y[i - 1];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) y[i] /= q[i];
+#pragma unroll
+            for (int i = NB - 2; i >= 0; --i) y[i] -= (ee[i] / q[i]) * y[i + 1];
+            double nrm = 0.0;
+#pragma unroll
+            for (int i = 0; i < NB; ++i) nrm = fma(y[i], y[i], nrm);
+            const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+#pragma unroll
+            for (int i = 0; i < NB; ++i) y[i] *= inv;
+        }
+    }
+    // 4. vectors to LDS rows sX[t][*]; orthonormalise in order across lanes (component per
+    //    lane), classical Gram-Schmidt applied twice
+    if (lane < kw) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) sY[lane * LD + i] = y[i];
+    }
+    __syncthreads();
+    double wv[KW];   // lane i holds component i of every vector
+#pragma unroll
+    for (int t = 0; t < KW; ++t) wv[t] = (t < kw && row) ? sY[t * LD + lane] : 0.0;
+#pragma unroll
+    for (int t = 0; t < KW; ++t) {
+        if (t < kw) {
+            for (int pass = 0; pass < 2; ++pass) {
+                double cf[KW];
+#pragma unroll
+                for (int s2 = 0; s2 < KW; ++s2) cf[s2] = s2 < t ? wave_sum_dpp(wv[s2] * wv[t]) : 0.0;
+#pragma unroll
+                for (int s2 = 0; s2 < KW; ++s2)
+                    if (s2 < t) wv[t] = fma(-cf[s2], wv[s2], wv[t]);
+            }
+            const double nn = wave_sum_dpp(wv[t] * wv[t]);
+            wv[t] *= nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+        }
+    }
+    // 5. back to the basis of S: w = H_1 ... H_{NB-2} y
+#pragma unroll
+    for (int j = NB - 3; j >= 0; --j) {
+        const double tj = stau[j];
+        if (tj != 0.0) {
+            const double vi = row ? sX[j * LD + lane] : 0.0;
+#pragma unroll
+            for (int t = 0; t < KW; ++t) {
+                if (t < kw) {
+                    const double dot = wave_sum_dpp(vi * wv[t]);
+                    wv[t] = fma(-tj * dot, vi, wv[t]);
+                }
+            }
+        }
+    }
+    // 6. sign rule (largest magnitude positive, first such index), W^T z, remainder c
+    const double zl = lane < n ? zin[lane] : 0.0;
+#pragma unroll
+    for (int t = 0; t < KW; ++t) {
+        if (t < kw) {
+            double am = fabs(wv[t]);
+            int im = lane;
+            for (int off = 32; off > 0; off >>= 1) {
+                const double oa = __shfl_xor(am, off, 64);
+                const int oi = __shfl_xor(im, off, 64);
+                if (oa > am || (oa == am && oi < im)) {
+                    am = oa;
+                    im = oi;
+                }
+            }
+            const double vm = __shfl(wv[t], im, 64);
+            if (vm < 0.0) wv[t] = -wv[t];
+            const double wz = wave_sum_dpp(wv[t] * zl);
+            if (lane == 0) swz[t] = wz;
+            if (lane < n) T[lane * ldt + t] = wv[t];
+        }
+    }
+    __syncthreads();
+    double cl = zl;
+#pragma unroll
+    for (int t = 0; t < KW; ++t)
+        if (t < kw) cl = fma(-swz[t], wv[t], cl);
+    const double cn = sqrt(wave_sum_dpp(cl * cl));
+    const double zn = sqrt(wave_sum_dpp(zl * zl));
+    const bool keep = cn > 1e-12 * zn;
+    if (lane < n) T[lane * ldt + kw] = keep ? cl / cn : 0.0;
+    if (lane < kw) zout[lane] = swz[lane];
+    if (lane == 0) {
+        if (keep) zout[kw] = cn;
+        out_k[0] = keep ? kmin : kw;
+        int st = keep ? 0 : NLRMM_ST_COMPRESS_SKIP;
+        if (!isfinite(cn)) st |= NLRMM_ST_NONFINITE;
+        if (st) atomicOr(status, st);
+    }
+}
+
 // Compression (Alg. "compress"): S = GA + lam GP = H^T H with H = [RA; sqrt(lam) RP];
 // W = eigenvectors of the kmin-1 largest eigenvalues of S (= dominant right singular
 // vectors of H), sign rule: largest-magnitude entry positive.  c = z - W W^T z; if
@@ -1959,9 +2197,29 @@ int k_gks_solve(const double *GA, const double *GP, int ldg, const double *rb, c
 
 int k_compress_eig(const double *GA, const double *GP, int ldg, const double *lam, int ell,
                    int kmin, const double *z, double *T, int ldt, double *zout, int *kout,
-                   int *status, hipStream_t s)
+                   int *status, hipStream_t s, int method)
 {
     if (ell < 1 || ell > SOLVE_MAX || kmin < 2 || kmin > 16 || kmin > ell) return NLRMM_ESHAPE;
+    if (method == 1) {
+        const int nb = (ell + 8) / 8 * 8;
+        switch (nb) {
+#define NLRMM_CMP_CASE(NB)                                                                  \
+    case NB:                                                                                \
+        compress_reg_k<NB><<<1, 64, 0, s>>>(GA, GP, ldg, lam, ell, kmin, z, T, ldt, zout, kout, \
+                                            status);                                        \
+        break;
+            NLRMM_CMP_CASE(8)
+            NLRMM_CMP_CASE(16)
+            NLRMM_CMP_CASE(24)
+            NLRMM_CMP_CASE(32)
+            NLRMM_CMP_CASE(40)
+            NLRMM_CMP_CASE(48)
+            NLRMM_CMP_CASE(56)
+#undef NLRMM_CMP_CASE
+        default: return NLRMM_ESHAPE;
+        }
+        return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+    }
     const size_t sh = sizeof(double) * (2 * (size_t)ell * (ell + 1) + 128 + 2 * ell + kmin);
     compress_eig_k<<<1, SOLVE_NT, sh, s>>>(GA, GP, ldg, lam, ell, kmin, z, T, ldt, zout, kout, status);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;

@@ -226,3 +226,41 @@ def test_loop_parity_c1(gram_precision):
     print(f"c1 final: u rel diff {du:.3e}, theta max diff {dth:.3e} rad, oracle RRE {rre:.4f}")
     assert du <= 1e-3
     assert dth <= 1e-4
+
+
+@pytest.mark.parametrize("ell,kmin", [(6, 2), (20, 5), (41, 5), (48, 16), (55, 16)])
+def test_compress_sizes_match_oracle(ell, kmin):
+    """Compression at every padded size of the one-wave kernel, kmin up to 16, against the
+    oracle's SVD-based Alg. "compress" on the same FP64 Grams."""
+    rng = np.random.default_rng(ell * 100 + kmin)
+    n, m = 300, 400
+    V = np.linalg.qr(rng.standard_normal((n, ell)))[0].astype(np.float32).astype(np.float64)
+    AV = rng.standard_normal((m, ell)).astype(np.float32).astype(np.float64)
+    Pm = rng.standard_normal((2 * n, ell)) * 0.3
+    GA = AV.T @ AV
+    GP = Pm.T @ Pm
+    z = rng.standard_normal(ell)
+    lam = 0.7
+    kmax = 56
+    Vd = torch.zeros((kmax, n), dtype=torch.float32, device="cuda")
+    Vd[:ell] = dev(V.T, torch.float32)
+    AVd = torch.zeros((kmax, m), dtype=torch.float32, device="cuda")
+    AVd[:ell] = dev(AV.T, torch.float32)
+    GAf = np.zeros((kmax, kmax))
+    GAf[:ell, :ell] = GA
+    GPf = np.zeros((kmax, kmax))
+    GPf[:ell, :ell] = GP
+    zd = torch.zeros(kmax, dtype=torch.float64, device="cuda")
+    zd[:ell] = dev(z, torch.float64)
+    rbd = torch.zeros(kmax, dtype=torch.float64, device="cuda")
+    st = ops.recycle_compress(Vd, AVd, dev(GAf, torch.float64), dev(GPf, torch.float64), rbd,
+                              dev(np.array([lam]), torch.float64), zd, ell, kmin)
+    torch.cuda.synchronize()
+    assert int(st.cpu()[0]) == 0
+    Vn = Vd[:kmin].cpu().numpy().astype(np.float64).T
+    zn = zd[:kmin].cpu().numpy()
+    ost = M.State(V=V.copy(), AV=AV.copy(), PV=np.zeros((1, ell)), u=V @ z, theta=np.zeros(1))
+    T_ref = M.compress(ost, np.linalg.cholesky(GA).T, np.linalg.cholesky(GP).T, lam, z, kmin)
+    print(f"compress ell={ell} kmin={kmin}: V {rel(Vn, V @ T_ref):.2e} z {rel(zn, ost.z):.2e}")
+    assert rel(Vn, V @ T_ref) <= 1e-5
+    assert rel(zn, ost.z) <= 1e-5
