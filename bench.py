@@ -3,7 +3,8 @@
 One step = one outer iteration of NL-RMM-GKS (AltMin, per-view angles) on the 256x256 /
 360-view / 363-bin workload: rebase A V, Enlarge (35 projected solves, 34 Krylov
 expansions, each with a projection and a backprojection), Compress, Gauss-Newton angle
-update with Armijo trials, residual append.  Inputs are resident in HBM before timing.
+update with Armijo trials, residual append.  Inputs are resident in HBM before timing.  The
+rate of the same iteration captured once as a HIP graph and replayed is reported beside it.
 
 Also reported:
   * Gsamples/s of the projector family (one sample = one nonzero (ray, pixel) weight
@@ -242,6 +243,11 @@ def main():
         sol.outer(theta, b, delta)
     ms_per_step = timed_steps(torch, lambda: sol.outer(theta, b, delta), args.steps, stream,
                               "c2")
+    # the same iteration captured once as a HIP graph and replayed (bitwise equal to eager
+    # execution), reported beside the eager rate
+    graph_steps = max(2, args.steps // 2)
+    graph = OuterGraph(sol, theta, b, delta)
+    ms_graph = timed_steps(torch, graph.replay, graph_steps, stream, "c2 graph")
     u, sc, status = sol.read()
     torch.cuda.synchronize()
     x_true = inst.x_true.reshape(-1)
@@ -307,13 +313,14 @@ def main():
                                f"regulariser Gram precision {args.gram_precision}, FP64 "
                                "projected solves",
                    "global_batch": 1, "parallelism": "none"},
+        "graph_replay_outer_it_s": round(1000.0 / ms_graph, 4),
         "gsamples_per_s": gs,
         "gsamples_per_s_kernel": gs_kernel,
         "operator_ms": {k: round(v, 5) for k, v in call_ms.items()},
         "kernel_ms": {k: round(v, 5) for k, v in kern_ms.items()},
         "nnz": int(nnz),
         "quality": {"rre": round(rre, 5), "angle_err_rel": round(perr, 5),
-                    "outer_done": args.warmup + args.steps,
+                    "outer_done": args.warmup + args.steps + graph_steps,
                     "lambda": float(sc.cpu().numpy()[2]), "status": int(status.cpu()[0])},
         "autotune": tuned,
         "batched_vs_plain": dyn,

@@ -100,9 +100,10 @@ int launch_project(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, in
 // Optional epilogue of a one-column backprojection: x += lam * Psi^T (w * Psi u).
 struct TvEpilogue {
     const float *u = nullptr;
-    const float *w = nullptr;
+    const float *w = nullptr;       // null: weights formed from u with eps
     const double *lamp = nullptr;   // device scalar lambda
     int temporal = 0;
+    float e2 = 0.0f;                // eps^2
 };
 int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
                        const float *y, const double *theta, float *x, hipStream_t s,

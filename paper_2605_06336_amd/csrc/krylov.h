@@ -7,12 +7,14 @@ namespace nlrmm {
 int k_psi_weights(const float *u, int nx, int ny, int F, int temporal, float eps, float *w,
                   hipStream_t s);
 int k_psi_apply(const float *u, int nx, int ny, int F, int temporal, float *out, hipStream_t s);
+// w == nullptr: the weights are formed from u with eps (equal to k_psi_weights' values)
 int k_tv_grad_add(const float *u, const float *w, int nx, int ny, int F, int temporal,
-                  const double *lamp, float *r, hipStream_t s);
+                  const double *lamp, float *r, hipStream_t s, float eps = 0.0f);
 // mode: 0 FP64 VALU, 1 FP32 MFMA, 2 BF16 MFMA (FP32 accumulation per chunk, FP64 across)
+// w == nullptr (modes 1, 2): the weights are formed from u with eps inside the kernel
 int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int ny, int F,
                int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s,
-               int mode = 0);
+               int mode = 0, const float *u = nullptr, float eps = 0.0f);
 // part: per-block partials, md_part_doubles(nblk) doubles.
 int k_multidot(const float *X, int64_t ldx, int nv, const float *y, const float *z, int64_t n,
                double *part, int nblk, double *out, int ostride, hipStream_t s,

@@ -29,6 +29,33 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+__device__ __forceinline__ double lane_bcast(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes, the same value (and summation order) in every lane.  Must be called
+// with all lanes active.
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);   // row_half_mirror
+    v += dpp_mov<0x140>(v);   // row_mirror
+    return (lane_bcast(v, 0) + lane_bcast(v, 16)) + (lane_bcast(v, 32) + lane_bcast(v, 48));
+}
+
+
 // block-wide sum of a double (all threads receive the result)
 __device__ double block_sum(double v, double *sbuf)
 {
@@ -58,30 +85,22 @@ __global__ void psi_weights_k(const float *__restrict__ u, int nx, int ny, int F
     const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
     const float uc = u[i];
     const float e2 = eps * eps;
-    if (k < nx - 1) {
-        const float s = u[i + 1] - uc;
-        w[f * g.per_frame + (int64_t)l * (nx - 1) + k] = 1.0f / sqrtf(s * s + e2);
-    }
-    if (l < ny - 1) {
-        const float s = u[i + nx] - uc;
-        w[f * g.per_frame + g.dy_off + (int64_t)l * nx + k] = 1.0f / sqrtf(s * s + e2);
-    }
-    if (g.temporal && f < F - 1) {
-        const float s = u[i + npix] - uc;
-        w[g.t_off + f * npix + p] = 1.0f / sqrtf(s * s + e2);
-    }
+    if (k < nx - 1) w[f * g.per_frame + (int64_t)l * (nx - 1) + k] = tv_weight(u[i + 1] - uc, e2);
+    if (l < ny - 1)
+        w[f * g.per_frame + g.dy_off + (int64_t)l * nx + k] = tv_weight(u[i + nx] - uc, e2);
+    if (g.temporal && f < F - 1) w[g.t_off + f * npix + p] = tv_weight(u[i + npix] - uc, e2);
 }
 
 // r += lam * Psi^T (w * Psi u)  (the regulariser part of the normal-equation residual).
 __global__ void tv_grad_add_k(const float *__restrict__ u, const float *__restrict__ w, int nx,
                               int ny, int F, int temporal, const double *__restrict__ lamp,
-                              float *__restrict__ r)
+                              float *__restrict__ r, float e2)
 {
     const float lam = (float)lamp[0];
     const TVGeo g = tvgeo(nx, ny, F, temporal);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)nx * ny * F) return;
-    r[i] += lam * tv_grad_at(u, w, g, i);
+    r[i] += lam * tv_grad_at(u, w, g, i, e2);
 }
 
 // Psi u written out (used by tests and by the VarPro regulariser block).
@@ -211,7 +230,8 @@ template <bool BF16>
 __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__ V, int64_t ldv,
                                                        int ell, const float *__restrict__ w,
                                                        int nx, int ny, int F, int temporal,
-                                                       double *__restrict__ part)
+                                                       double *__restrict__ part,
+                                                       const float *__restrict__ u, float e2)
 {
     __shared__ __align__(16) float sB[64][MLDR];
     const TVGeo g = tvgeo(nx, ny, F, temporal);
@@ -244,16 +264,21 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
         if (i < ntot) {
             const int64_t f = i / npix, p = i - f * npix;
             const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
+            // weights stored in w, or formed from u (the same values)
+            const float uc = u != nullptr ? u[i] : 0.0f;
             if (k < nx - 1) {
-                w0 = sqrtf(w[f * g.per_frame + (int64_t)l * (nx - 1) + k]);
+                w0 = sqrtf(u != nullptr ? tv_weight(u[i + 1] - uc, e2)
+                                        : w[f * g.per_frame + (int64_t)l * (nx - 1) + k]);
                 ox = 1;
             }
             if (l < ny - 1) {
-                w1 = sqrtf(w[f * g.per_frame + g.dy_off + (int64_t)l * nx + k]);
+                w1 = sqrtf(u != nullptr ? tv_weight(u[i + nx] - uc, e2)
+                                        : w[f * g.per_frame + g.dy_off + (int64_t)l * nx + k]);
                 oy = nx;
             }
             if (g.temporal && f < F - 1) {
-                w2 = sqrtf(w[g.t_off + f * npix + p]);
+                w2 = sqrtf(u != nullptr ? tv_weight(u[i + npix] - uc, e2)
+                                        : w[g.t_off + f * npix + p]);
                 ot = npix;
             }
         }
@@ -368,25 +393,27 @@ constexpr int MD_MAX = 72;
 
 // Inner products <X_i, y> (i < nv) and <z, y> (i == nv when z is given), FP64 accumulation:
 // per-block partials part[block][i].  Each block reduces its share of the elements for
-// groups of 8 outputs through LDS (32 threads per output, then a 32-lane butterfly).
+// groups of 16 outputs through LDS (16 threads per output, then a 16-lane butterfly).
 __global__ __launch_bounds__(BLK) void multidot_k(const float *__restrict__ X, int64_t ldx, int nv,
                                                   const float *__restrict__ y,
                                                   const float *__restrict__ z, int64_t n,
                                                   double *__restrict__ part, const int *skip)
 {
     if (skip != nullptr && *skip != 0) return;
-    __shared__ double sacc[8][BLK];
+    constexpr int GRP = 16;            // outputs reduced per LDS round
+    __shared__ double sacc[GRP][BLK];
     const int tid = threadIdx.x;
     const int nout = nv + (z != nullptr ? 1 : 0);
-    auto block_reduce = [&](int i0, const double (&acc)[8]) __attribute__((always_inline)) {
+    auto block_reduce = [&](int i0, const double (&acc)[GRP]) __attribute__((always_inline)) {
 #pragma unroll
-        for (int a = 0; a < 8; ++a) sacc[a][tid] = acc[a];
+        for (int a = 0; a < GRP; ++a) sacc[a][tid] = acc[a];
         __syncthreads();
-        const int a = tid >> 5, l = tid & 31;   // 32 threads per output of the group
+        constexpr int TPO = BLK / GRP;            // threads per output of the group
+        const int a = tid / TPO, l = tid % TPO;
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < BLK / 32; ++k) s += sacc[a][l + 32 * k];
-        for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
+        for (int k = 0; k < BLK / TPO; ++k) s += sacc[a][l + TPO * k];
+        for (int off = TPO / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, TPO);
         if (l == 0 && i0 + a < nout) part[(int64_t)blockIdx.x * nout + i0 + a] = s;
         __syncthreads();
     };
@@ -405,24 +432,24 @@ __global__ __launch_bounds__(BLK) void multidot_k(const float *__restrict__ X, i
             xv[i] = v;
         }
 #pragma unroll
-        for (int i0 = 0; i0 < MD_MAX; i0 += 8) {
+        for (int i0 = 0; i0 < MD_MAX; i0 += GRP) {
             if (i0 < nout) {
-                double acc[8];
+                double acc[GRP];
 #pragma unroll
-                for (int a = 0; a < 8; ++a) acc[a] = (double)xv[i0 + a] * (double)ye;
+                for (int a = 0; a < GRP; ++a) acc[a] = i0 + a < MD_MAX ? (double)xv[i0 + a] * (double)ye : 0.0;
                 block_reduce(i0, acc);
             }
         }
         return;
     }
-    for (int i0 = 0; i0 < nout; i0 += 8) {
-        double acc[8];
+    for (int i0 = 0; i0 < nout; i0 += GRP) {
+        double acc[GRP];
 #pragma unroll
-        for (int a = 0; a < 8; ++a) acc[a] = 0.0;
+        for (int a = 0; a < GRP; ++a) acc[a] = 0.0;
         for (int64_t e = (int64_t)blockIdx.x * BLK + tid; e < n; e += (int64_t)gridDim.x * BLK) {
             const double ye = (double)y[e];
 #pragma unroll
-            for (int a = 0; a < 8; ++a) {
+            for (int a = 0; a < GRP; ++a) {
                 const int i = i0 + a;
                 if (i < nv) acc[a] = fma((double)X[(int64_t)i * ldx + e], ye, acc[a]);
                 else if (i == nv && z != nullptr) acc[a] = fma((double)z[e], ye, acc[a]);
@@ -1225,32 +1252,6 @@ __global__ __launch_bounds__(TRI_NT) void gks_solve_tri_k(const double *__restri
 //   ||AV z(lam) - b||^2 = out2 + ||c||^2 (Q^2 + S_1) / P_0^2,  Q = lam d_0 P_1 - lam^2 e_0^2 P_2,
 // where Q / P_1 = D_0 - 1 and S_1 / P_1^2 = sum_{i>=1} (y_i / y_0)^2 in the notation above;
 // P, S are rescaled by powers of two so that they stay in range.
-__device__ __forceinline__ double lane_bcast(double v, int l)
-{
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v)
-{
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-// Sum over the 64 lanes, the same value (and summation order) in every lane.  Must be called
-// with all lanes active.
-__device__ __forceinline__ double wave_sum_dpp(double v)
-{
-    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
-    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
-    v += dpp_mov<0x141>(v);   // row_half_mirror
-    v += dpp_mov<0x140>(v);   // row_mirror
-    return (lane_bcast(v, 0) + lane_bcast(v, 16)) + (lane_bcast(v, 32) + lane_bcast(v, 48));
-}
-
 // Compile-time loop: calls f(std::integral_constant<int, I>) for I = B .. E-1, so that loop
 // bodies too large for the unroller still see constant register indices.
 template <int B, int E>
@@ -2052,21 +2053,27 @@ int k_psi_apply(const float *u, int nx, int ny, int F, int temporal, float *out,
 }
 
 int k_tv_grad_add(const float *u, const float *w, int nx, int ny, int F, int temporal,
-                  const double *lamp, float *r, hipStream_t s)
+                  const double *lamp, float *r, hipStream_t s, float eps)
 {
     const int64_t n = (int64_t)nx * ny * F;
-    tv_grad_add_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(u, w, nx, ny, F, temporal, lamp, r);
+    tv_grad_add_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(u, w, nx, ny, F, temporal, lamp, r,
+                                                             eps * eps);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 
 int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int ny, int F,
-               int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s, int mode)
+               int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s, int mode,
+               const float *u, float eps)
 {
     if (ell > GMAX) return NLRMM_ESHAPE;
+    if (w == nullptr && (u == nullptr || mode == 0)) return NLRMM_EINVAL;
+    const float e2 = eps * eps;
     if (mode == 1)
-        gram_psi_mfma_k<false><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal, part);
+        gram_psi_mfma_k<false><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal,
+                                                              part, w ? nullptr : u, e2);
     else if (mode == 2)
-        gram_psi_mfma_k<true><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal, part);
+        gram_psi_mfma_k<true><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal,
+                                                             part, w ? nullptr : u, e2);
     else
         gram_psi_k<<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal, part);
     reduce_gram_k<<<(unsigned)(ell * ell), 64, 0, s>>>(part, nblk, ell, G, ldg);

@@ -609,7 +609,8 @@ __global__ __launch_bounds__(BLK) void bwd_tiles_k(BwdArgs a)
             float v = (float)(prev + acc / a.ds);
             if (a.tv.u != nullptr)
                 v += (float)a.tv.lamp[0] *
-                     tv_grad_at(a.tv.u, a.tv.w, tvgeo(a.nx, a.ny, a.nframes, a.tv.temporal), o);
+                     tv_grad_at(a.tv.u, a.tv.w, tvgeo(a.nx, a.ny, a.nframes, a.tv.temporal), o,
+                                a.tv.e2);
             a.x[o] = v;
         }
     }
@@ -625,7 +626,8 @@ __global__ void sum_splits_k(const float *__restrict__ part, int nsplit, int64_t
     for (int k = 0; k < nsplit; ++k) s += (double)part[k * n + i];
     float v = (float)s;
     if (tv.u != nullptr)
-        v += (float)tv.lamp[0] * tv_grad_at(tv.u, tv.w, tvgeo(nx, ny, nframes, tv.temporal), i);
+        v += (float)tv.lamp[0] *
+             tv_grad_at(tv.u, tv.w, tvgeo(nx, ny, nframes, tv.temporal), i, tv.e2);
     x[i] = v;
 }
 

@@ -37,6 +37,7 @@ struct Solver {
     int ell = 0;    // current number of basis columns (host bookkeeping)
     int md_blocks = 512, gram_blocks = 256, nchunks = 1;
     bool rho_ready = false;   // rho = A V z - b already formed for the next residual
+    bool w_from_u = true;     // weights of u may be formed on the fly (false: caller's w)
     // device buffers
     float *V = nullptr, *AV = nullptr, *Vtmp = nullptr, *u = nullptr, *r = nullptr,
           *rho = nullptr, *w = nullptr;
@@ -177,9 +178,12 @@ static int cgs2_append(Solver &S, int ell, hipStream_t s)
 }
 
 // r = A^T (A V z - b) + lam Psi^T (w * Psi u), with u = V z already in S.u.
+// weights_of_u: the weights are those of the current u (formed on the fly); otherwise the
+// stored S.w (the weights of the step's solve).
 static int mm_residual(Solver &S, const nlrmm_batch &b, const double *theta, int ell,
-                       const float *bvec, hipStream_t s)
+                       const float *bvec, hipStream_t s, bool weights_of_u = false)
 {
+    const bool inl = weights_of_u && S.w_from_u;
     const int64_t m = m_of(S, b);
     if (!S.rho_ready) RC(k_gemv(S.AV, m, ell, S.z, 1.0, bvec, -1.0, m, S.rho, s));
     S.rho_ready = false;
@@ -187,13 +191,15 @@ static int mm_residual(Solver &S, const nlrmm_batch &b, const double *theta, int
         // one launch pair: backprojection with the TV-gradient term as its epilogue
         TvEpilogue tv;
         tv.u = S.u;
-        tv.w = S.w;
+        tv.w = inl ? nullptr : S.w;   // null: weights of u formed in the epilogue
         tv.lamp = S.sc + S_LAM;
         tv.temporal = S.cfg.temporal;
+        tv.e2 = (float)S.cfg.eps * (float)S.cfg.eps;
         return launch_backproject(S.ctx, S.g, b, 1, S.rho, theta, S.r, s, 0, &tv);
     }
     RC(bproj(S, b, S.rho, theta, S.r, s));
-    RC(k_tv_grad_add(S.u, S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.sc + S_LAM, S.r, s));
+    RC(k_tv_grad_add(S.u, inl ? nullptr : S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal,
+                     S.sc + S_LAM, S.r, s, (float)S.cfg.eps));
     return NLRMM_OK;
 }
 
@@ -218,6 +224,8 @@ static int expand(Solver &S, const nlrmm_batch &b, const double *theta, const fl
 static int projected_solve(Solver &S, hipStream_t s, const nlrmm_batch *b = nullptr,
                            const float *bvec = nullptr)
 {
+    // this step's weights (from the u the solve starts from): the Gram and, in the expansion
+    // that follows, the residual use them (Alg. "enlarge")
     RC(k_psi_weights(S.u, S.g.nx, S.g.ny, S.F, S.cfg.temporal, (float)S.cfg.eps, S.w, s));
     RC(k_gram_psi(S.V, S.n, S.ell, S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.part_gram,
                   S.gram_blocks, S.GP, S.ld, s, S.cfg.gram_precision));
@@ -370,9 +378,9 @@ static int solver_outer(Solver &S, const nlrmm_batch &b, double *theta, const fl
     RC(compress(S, b, s));
     if (S.cfg.param_update == 1) RC(gn_update(S, b, theta, bvec, s));
     if (S.cfg.param_update == 2) RC(varpro_update(S, b, theta, bvec, s));
-    // weights from u_{k+1}; residual with the old operator H_k; project out; append
-    RC(k_psi_weights(S.u, S.g.nx, S.g.ny, S.F, S.cfg.temporal, (float)S.cfg.eps, S.w, s));
-    RC(mm_residual(S, b, S.thk, S.ell, bvec, s));
+    // weights from u_{k+1} (formed inside the residual); residual with the old operator H_k;
+    // project out; append
+    RC(mm_residual(S, b, S.thk, S.ell, bvec, s, true));
     RC(cgs2_append(S, S.ell, s));
     S.ell += 1;
     (void)m;
@@ -690,6 +698,7 @@ int nlrmm_gks_expand(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *
     S.ld = ldg;
     S.rb = rb;
     S.w = w ? const_cast<float *>(w) : nullptr;
+    S.w_from_u = false;   // the residual uses the caller's weights
     S.status = status;
     S.ell = ell;
     // z and lambda are read through the solver's scalar slots: point them at the caller's

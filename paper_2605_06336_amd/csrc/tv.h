@@ -29,18 +29,52 @@ __device__ __forceinline__ TVGeo tvgeo(int nx, int ny, int F, int temporal)
     return g;
 }
 
-// (Psi^T (w * Psi u))_i for pixel i of the stacked frames.
+// MM weight of one difference d of Psi u: ((d)^2 + eps^2)^(-1/2) (Section 3.1), FP32.
+__device__ __forceinline__ float tv_weight(float d, float e2) { return 1.0f / sqrtf(d * d + e2); }
+
+// (Psi^T (w * Psi u))_i for pixel i of the stacked frames; with w == nullptr the weights
+// are formed from u itself (tv_weight with e2 = eps^2), equal to the stored ones.
 __device__ __forceinline__ float tv_grad_at(const float *__restrict__ u,
                                             const float *__restrict__ w, const TVGeo &g,
-                                            int64_t i)
+                                            int64_t i, float e2 = 0.0f)
 {
     const int64_t npix = (int64_t)g.nx * g.ny;
     const int nx = g.nx, ny = g.ny;
     const int64_t f = i / npix, p = i - f * npix;
     const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
     const float uc = u[i];
-    const float *wf = w + f * g.per_frame;
     float acc = 0.0f;
+    if (w == nullptr) {
+        float d;
+        if (k < nx - 1) {
+            d = u[i + 1] - uc;
+            acc -= tv_weight(d, e2) * d;
+        }
+        if (k > 0) {
+            d = uc - u[i - 1];
+            acc += tv_weight(d, e2) * d;
+        }
+        if (l < ny - 1) {
+            d = u[i + nx] - uc;
+            acc -= tv_weight(d, e2) * d;
+        }
+        if (l > 0) {
+            d = uc - u[i - nx];
+            acc += tv_weight(d, e2) * d;
+        }
+        if (g.temporal) {
+            if (f < g.F - 1) {
+                d = u[i + npix] - uc;
+                acc -= tv_weight(d, e2) * d;
+            }
+            if (f > 0) {
+                d = uc - u[i - npix];
+                acc += tv_weight(d, e2) * d;
+            }
+        }
+        return acc;
+    }
+    const float *wf = w + f * g.per_frame;
     if (k < nx - 1) acc -= wf[(int64_t)l * (nx - 1) + k] * (u[i + 1] - uc);
     if (k > 0) acc += wf[(int64_t)l * (nx - 1) + k - 1] * (uc - u[i - 1]);
     if (l < ny - 1) acc -= wf[g.dy_off + (int64_t)l * nx + k] * (u[i + nx] - uc);

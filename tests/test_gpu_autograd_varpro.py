@@ -108,7 +108,7 @@ def test_streaming_loss_matches_unblocked():
     L2.backward()
     r_ref = P.project(x.astype(np.float64), th, nb) - b
     assert abs(float(L1.detach()) - 0.5 * np.sum(r_ref ** 2)) <= 1e-5 * float(L1.detach())
-    assert abs(float(L1) - float(L2)) <= 1e-5 * float(L1)
+    assert abs(float(L1.detach()) - float(L2.detach())) <= 1e-5 * float(L1.detach())
     assert rel(x1.grad.cpu().numpy(), x2.grad.cpu().numpy().astype(np.float64)) <= 1e-5
     assert rel(t1.grad.cpu().numpy(), t2.grad.cpu().numpy()) <= 1e-5
 
