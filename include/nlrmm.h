@@ -214,11 +214,14 @@ int nlrmm_gks_expand(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *
  *   V <- V [W, c/||c||],  A V <- A V [W, c/||c||],  z <- [W^T z; ||c||]
  * (u = V z is unchanged).  GA and rb are transformed accordingly.  When ||c|| <= 1e-12 ||z||
  * the last column is zero and NLRMM_ST_COMPRESS_SKIP is set.  n, m: column lengths of V
- * and A V.  lambda DEVICE scalar; z DEVICE [ell] in, [kmin] out. */
+ * and A V.  lambda DEVICE scalar; z DEVICE [ell] in, [kmin] out.  precision of the basis
+ * products V [W, c] and A V [W, c]: 0 FP32 operands with FP64 accumulation, 2 BF16 operands
+ * with FP32 accumulation on the matrix cores (the mixed-precision path); other values
+ * return NLRMM_ENOTSUP.  The eigen-problem is FP64 in both. */
 int nlrmm_recycle_compress(nlrmm_ctx *ctx, int64_t n, int64_t m, int32_t ell, int32_t kmin,
                            float *V, float *AV, double *GA, const double *GP, int32_t ldg,
-                           double *rb, const double *lambda, double *z, int32_t *status,
-                           void *stream);
+                           double *rb, const double *lambda, double *z, int32_t precision,
+                           int32_t *status, void *stream);
 
 /* ------------------------------------------------------------------------------------
  * Outer driver: NL-RMM-GKS (Alg. "nl_rmmgks_two_solves", high-regularisation solve off).
@@ -239,6 +242,7 @@ typedef struct {
     double breakdown_tol;    /* Krylov breakdown threshold */
     int32_t temporal;        /* dynamic problems: regulariser includes frame differences */
     int32_t gram_precision;  /* regulariser Gram: 0 FP64, 1 FP32 MFMA, 2 BF16 MFMA (nlrmm_gram_psi) */
+    int32_t compress_precision; /* compression basis products: 0 FP32/FP64-accumulate, 2 BF16 MFMA */
 } nlrmm_solver_cfg;
 
 typedef struct nlrmm_solver nlrmm_solver;

@@ -44,7 +44,8 @@ class SolverCfg(ctypes.Structure):
                 ("maxiter_p", ctypes.c_int32), ("mu_rel", ctypes.c_double),
                 ("c1", ctypes.c_double), ("beta", ctypes.c_double), ("alpha0", ctypes.c_double),
                 ("armijo_trials", ctypes.c_int32), ("breakdown_tol", ctypes.c_double),
-                ("temporal", ctypes.c_int32), ("gram_precision", ctypes.c_int32)]
+                ("temporal", ctypes.c_int32), ("gram_precision", ctypes.c_int32),
+                ("compress_precision", ctypes.c_int32)]
 
 # name -> argtypes (all return int except where noted)
 SIGNATURES = {
@@ -67,7 +68,7 @@ SIGNATURES = {
     "nlrmm_gks_expand": [_P, _GP, _BP, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _I32, _P,
                          _D, _P, _P],
     "nlrmm_recycle_compress": [_P, _I64, _I64, _I32, _I32, _P, _P, _P, _P, _I32, _P, _P, _P,
-                               _P, _P],
+                               _I32, _P, _P],
     "nlrmm_solver_create": [_P, _GP, _I32, _I64, ctypes.POINTER(SolverCfg),
                             ctypes.POINTER(ctypes.c_void_p)],
     "nlrmm_solver_init": [_P, _BP, _P, _P, _P],

@@ -37,8 +37,10 @@ int k_gemv_norm_normalize(const float *X, int64_t ldx, int nv, const double *c, 
 int k_multidot_gram_col(const float *X, int64_t ldx, int ell, const float *xnew, const float *b,
                         int64_t n, double *part, int nblk, double *G, int ldg, double *rb,
                         hipStream_t s);
+// precision 0: FP32 operands, FP64 accumulation (vector units); 2: BF16 operands, FP32
+// accumulation (matrix cores)
 int k_block_update(const float *X, int64_t ldx, int nin, const double *T, int ldt, int kout,
-                   int64_t n, float *Y, int64_t ldy, hipStream_t s);
+                   int64_t n, float *Y, int64_t ldy, hipStream_t s, int precision = 0);
 int k_copy_cols(const float *src, int64_t lds, float *dst, int64_t ldd, int ncols, int64_t n,
                 hipStream_t s);
 int k_normalize_into(const float *r, const double *scal, double tol, int64_t n, float *vout,

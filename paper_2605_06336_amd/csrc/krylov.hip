@@ -629,6 +629,46 @@ __global__ __launch_bounds__(BLK) void block_update_k(const float *__restrict__ 
     }
 }
 
+// Y[c][e] = sum_i X[i][e] T[i][c] (c < kout <= 16) with BF16 operands on the matrix cores
+// and FP32 accumulation (the basis GEMM V [W, c] of the mixed-precision path).  One wave
+// per 32 pixels: D = A B with A[c][i] = T[i][c] (32 x 8 per step, rows c >= kout zero) and
+// B[i][e] = X[i][e] (8 x 32), v_mfma_f32_32x32x8bf16_1k; lane l then holds pixel l % 32 of
+// outputs c = 8 (r / 4) + 4 (l / 32) + r % 4, r < 16, so the stores are coalesced.
+__global__ __launch_bounds__(BLK) void block_update_bf16_k(const float *__restrict__ X,
+                                                           int64_t ldx, int nin,
+                                                           const double *__restrict__ T, int ldt,
+                                                           int kout, int64_t n,
+                                                           float *__restrict__ Y, int64_t ldy)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t e0 = ((int64_t)blockIdx.x * (BLK / 64) + wv) * 32;
+    if (e0 >= n) return;   // whole wave
+    const int m = lane & 31, kq = 4 * (lane >> 5);
+    const int64_t e = e0 + m;
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    for (int i0 = 0; i0 < nin; i0 += 8) {
+        s16x4 av, bv;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = i0 + kq + q;
+            const float t = (i < nin && m < kout) ? (float)T[i * ldt + m] : 0.0f;
+            const float x = (i < nin && e < n) ? X[(int64_t)i * ldx + e] : 0.0f;
+            av[q] = bf16_rne(t);
+            bv[q] = bf16_rne(x);
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+    }
+    if (e < n) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int c = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            if (c < kout) Y[(int64_t)c * ldy + e] = acc[r];
+        }
+    }
+}
+
 __global__ void copy_cols_k(const float *__restrict__ src, int64_t lds, float *__restrict__ dst,
                             int64_t ldd, int ncols, int64_t n)
 {
@@ -2144,9 +2184,15 @@ int k_gemv(const float *X, int64_t ldx, int nv, const double *c, double beta, co
 }
 
 int k_block_update(const float *X, int64_t ldx, int nin, const double *T, int ldt, int kout,
-                   int64_t n, float *Y, int64_t ldy, hipStream_t s)
+                   int64_t n, float *Y, int64_t ldy, hipStream_t s, int precision)
 {
     if (nin > MD_MAX || kout > 16) return NLRMM_ESHAPE;
+    if (precision == 2) {
+        const int64_t per = 32 * (BLK / 64);
+        block_update_bf16_k<<<(unsigned)((n + per - 1) / per), BLK, 0, s>>>(X, ldx, nin, T, ldt,
+                                                                           kout, n, Y, ldy);
+        return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+    }
     block_update_k<<<grid_for(n), BLK, 0, s>>>(X, ldx, nin, T, ldt, kout, n, Y, ldy);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }

@@ -250,9 +250,11 @@ static int compress(Solver &S, const nlrmm_batch &b, hipStream_t s)
     const int64_t m = m_of(S, b);
     RC(k_compress_eig(S.GA, S.GP, S.ld, S.sc + S_LAM, S.ell, kmin, S.z, S.T, kmin, S.zt,
                       S.kout, S.status, s));
-    RC(k_block_update(S.V, S.n, S.ell, S.T, kmin, kmin, S.n, S.Vtmp, S.n, s));
+    RC(k_block_update(S.V, S.n, S.ell, S.T, kmin, kmin, S.n, S.Vtmp, S.n, s,
+                      S.cfg.compress_precision));
     RC(k_copy_cols(S.Vtmp, S.n, S.V, S.n, kmin, S.n, s));
-    RC(k_block_update(S.AV, m, S.ell, S.T, kmin, kmin, m, S.Vtmp, m, s));
+    RC(k_block_update(S.AV, m, S.ell, S.T, kmin, kmin, m, S.Vtmp, m, s,
+                      S.cfg.compress_precision));
     RC(k_copy_cols(S.Vtmp, m, S.AV, m, kmin, m, s));
     RC(k_gram_transform(S.GA, S.ld, S.rb, S.ell, S.T, kmin, S.kout, s));
     RC(k_copy_f64(S.zt, S.z, kmin, s));
@@ -452,6 +454,7 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
     if (!(c.eps > 0.0) || !(c.tau > 0.0)) return NLRMM_EINVAL;
     if (c.param_update < 0 || c.param_update > 2) return NLRMM_ENOTSUP;
     if (c.gram_precision < 0 || c.gram_precision > 2) return NLRMM_ENOTSUP;
+    if (c.compress_precision != 0 && c.compress_precision != 2) return NLRMM_ENOTSUP;
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
     nlrmm_solver *S = new (std::nothrow) nlrmm_solver();
     if (!S) return NLRMM_ENOMEM;
@@ -710,10 +713,11 @@ int nlrmm_gks_expand(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *
 
 int nlrmm_recycle_compress(nlrmm_ctx *ctx, int64_t n, int64_t m, int32_t ell, int32_t kmin,
                            float *V, float *AV, double *GA, const double *GP, int32_t ldg,
-                           double *rb, const double *lambda, double *z, int32_t *status,
-                           void *stream)
+                           double *rb, const double *lambda, double *z, int32_t precision,
+                           int32_t *status, void *stream)
 {
     if (!ctx || !V || !AV || !GA || !GP || !rb || !lambda || !z || !status) return NLRMM_EINVAL;
+    if (precision != 0 && precision != 2) return NLRMM_ENOTSUP;
     if (n < 1 || m < 1 || kmin < 2 || kmin > 16 || ell < kmin || ell > 56 || ldg < ell)
         return NLRMM_ESHAPE;
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
@@ -732,6 +736,7 @@ int nlrmm_recycle_compress(nlrmm_ctx *ctx, int64_t n, int64_t m, int32_t ell, in
     S.status = status;
     S.ell = ell;
     S.cfg.kmin = kmin;
+    S.cfg.compress_precision = precision;
     nlrmm_batch b{1, m, nullptr};
     S.g.nbins = 1;   // m_of(S, b) = nviews * nbins = m
     return compress(S, b, s);

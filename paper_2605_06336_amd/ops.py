@@ -274,16 +274,19 @@ def gks_expand(V, AV, z, b, w, lam, GA, rb, theta, g: Geom, ell: int, frames=Non
     return status
 
 
-def recycle_compress(V, AV, GA, GP, rb, lam, z, ell: int, kmin: int, status=None):
-    """Compress the basis to kmin columns in place (see nlrmm_recycle_compress)."""
+def recycle_compress(V, AV, GA, GP, rb, lam, z, ell: int, kmin: int, status=None,
+                     precision: int = 0):
+    """Compress the basis to kmin columns in place (see nlrmm_recycle_compress); precision 2
+    forms the basis products with BF16 operands on the matrix cores."""
     dev = V.device
     if status is None:
         status = torch.zeros(1, dtype=torch.int32, device=dev)
     check(_lib.lib().nlrmm_recycle_compress(context(dev.index or 0), V.shape[1], AV.shape[1], ell,
                                             kmin, V.data_ptr(), AV.data_ptr(), GA.data_ptr(),
                                             GP.data_ptr(), GA.shape[1], rb.data_ptr(),
-                                            lam.data_ptr(), z.data_ptr(), status.data_ptr(),
-                                            _stream(dev)), "nlrmm_recycle_compress")
+                                            lam.data_ptr(), z.data_ptr(), precision,
+                                            status.data_ptr(), _stream(dev)),
+          "nlrmm_recycle_compress")
     return status
 
 

@@ -34,6 +34,7 @@ class Config:
     breakdown_tol: float = 1e-10
     temporal: int = 0
     gram_precision: int = 0      # 0 FP64, 1 FP32 MFMA, 2 BF16 MFMA
+    compress_precision: int = 0  # compression basis products: 0 FP32 (FP64 accumulate), 2 BF16 MFMA
 
     def struct(self) -> SolverCfg:
         return SolverCfg(**dataclasses.asdict(self))

@@ -264,3 +264,43 @@ def test_compress_sizes_match_oracle(ell, kmin):
     print(f"compress ell={ell} kmin={kmin}: V {rel(Vn, V @ T_ref):.2e} z {rel(zn, ost.z):.2e}")
     assert rel(Vn, V @ T_ref) <= 1e-5
     assert rel(zn, ost.z) <= 1e-5
+
+
+@pytest.mark.parametrize("ell,kmin", [(20, 5), (55, 16)])
+def test_compress_bf16_products(ell, kmin):
+    """The mixed-precision compression (BF16 operands, FP32 accumulation on the matrix cores
+    for V [W, c] and A V [W, c]) against the FP32/FP64 one on the same inputs: relL2 of the new
+    bases and of u = V z within the BF16 basis-path bar 3e-3; z (FP64 eigen-problem) equal."""
+    rng = np.random.default_rng(ell + 7 * kmin)
+    n, m, kmax = 5000, 3000, 56
+    V = np.linalg.qr(rng.standard_normal((n, ell)))[0].astype(np.float32)
+    AV = rng.standard_normal((m, ell)).astype(np.float32)
+    Pm = rng.standard_normal((2 * n, ell)) * 0.3
+    GAf = np.zeros((kmax, kmax))
+    GAf[:ell, :ell] = AV.T.astype(np.float64) @ AV.astype(np.float64)
+    GPf = np.zeros((kmax, kmax))
+    GPf[:ell, :ell] = Pm.T @ Pm
+    z = rng.standard_normal(ell)
+    outs = []
+    for prec in (0, 2):
+        Vd = torch.zeros((kmax, n), dtype=torch.float32, device="cuda")
+        Vd[:ell] = dev(V.T, torch.float32)
+        AVd = torch.zeros((kmax, m), dtype=torch.float32, device="cuda")
+        AVd[:ell] = dev(AV.T, torch.float32)
+        zd = torch.zeros(kmax, dtype=torch.float64, device="cuda")
+        zd[:ell] = dev(z, torch.float64)
+        st = ops.recycle_compress(Vd, AVd, dev(GAf, torch.float64), dev(GPf, torch.float64),
+                                  torch.zeros(kmax, dtype=torch.float64, device="cuda"),
+                                  dev(np.array([0.5]), torch.float64), zd, ell, kmin,
+                                  precision=prec)
+        torch.cuda.synchronize()
+        assert int(st.cpu()[0]) == 0
+        outs.append((Vd[:kmin].cpu().numpy().astype(np.float64),
+                     AVd[:kmin].cpu().numpy().astype(np.float64), zd[:kmin].cpu().numpy()))
+    (V0, A0, z0), (V2, A2, z2) = outs
+    u0, u2 = V0.T @ z0, V2.T @ z2
+    print(f"bf16 compress ell={ell} kmin={kmin}: V {rel(V2, V0):.2e} AV {rel(A2, A0):.2e} "
+          f"u {rel(u2, u0):.2e}")
+    assert rel(V2, V0) <= 3e-3 and rel(A2, A0) <= 3e-3 and rel(u2, u0) <= 3e-3
+    assert rel(z2, z0) <= 1e-12
+    assert rel(u0, V.astype(np.float64) @ z) <= 1e-5

@@ -82,6 +82,42 @@ def test_streaming_parity_scaled_c5():
     assert abs(ae_g - ae_o) <= 0.05 * ae_o
 
 
+def test_streaming_mixed_precision_policy_scaled_c5():
+    """The c5 precision policy (BF16-operand matrix-core Grams and compression products, FP32
+    accumulation; FP32 projector; FP64 solves) on the scaled streaming workload: its result
+    against the FP64 oracle, with reconstruction and angle errors within 10 % of the
+    oracle's."""
+    wl = dataclasses.replace(synth.WORKLOADS["c5"], N=128, nb=181, n_views=180, blocks=8,
+                             kmax=20)
+    inst = synth.draw(wl)
+    geo = M.Geometry(N=wl.N, nb=wl.nb, view_off=inst.view_off)
+    b_ora, e_ora = M.make_data(geo, inst.x_true.reshape(-1), inst.theta_true, inst.g, wl.noise)
+    st = M.run_streaming(geo, b_ora, e_ora, inst.theta_nom, inst.blocks,
+                         M.Config(kmin=5, kmax=wl.kmax, eps=wl.eps), passes=2)
+    g = ops.geom(wl.N, wl.nb)
+    bex = ops.project(dev(inst.x_true.astype(np.float32), torch.float32),
+                      dev(inst.theta_true, torch.float64), g).cpu().numpy().reshape(-1)
+    bex = bex.astype(np.float64)
+    e = wl.noise * np.linalg.norm(bex) * inst.g / np.linalg.norm(inst.g)
+    S = Streaming(g, inst.blocks, Config(kmin=5, kmax=wl.kmax, eps=wl.eps, gram_precision=2,
+                                         compress_precision=2))
+    S.load(inst.theta_nom, (bex + e).astype(np.float32), e)
+    S.init()
+    S.run(passes=2)
+    u = S.image().cpu().numpy()
+    th = S.angles()
+    S.solver.close()
+    x_true = inst.x_true.reshape(-1)
+    rre_g, rre_o = rel(u, x_true), rel(st.u, x_true)
+    ae_g = np.linalg.norm(th - inst.theta_true)
+    ae_o = np.linalg.norm(st.theta - inst.theta_true)
+    print(f"streaming, BF16 Grams and compression products: vs FP64 oracle u {rel(u, st.u):.3e} "
+          f"theta {float(np.max(np.abs(th - st.theta))):.3e}; RRE gpu {rre_g:.4f} ora {rre_o:.4f}; "
+          f"angle err gpu {ae_g:.4e} ora {ae_o:.4e}")
+    assert abs(rre_g - rre_o) <= 0.10 * rre_o
+    assert abs(ae_g - ae_o) <= 0.10 * ae_o
+
+
 def test_full_size_c5_operators_on_sampled_views():
     wl = synth.WORKLOADS["c5"]
     N, nb = wl.N, wl.nb
