@@ -87,7 +87,7 @@ void nlrmm_ctx_destroy(nlrmm_ctx *ctx);
  * nlrmm_project while timing each forward block shape (1, 2, 4 or 8 waves sharing each
  * detector edge's image lines) with HIP events on `stream`, and keeps the fastest for this
  * geometry, batch and column-group size in the context; nlrmm_autotune_backproject does the
- * same for the backprojection's view split (1, 2, 4 or 8 partial images, bounded by 16 views
+ * same for the backprojection's view split (1, 2, 4, 8 or 16 partial images, bounded by 16 views
  * per split and frame) and leaves x = A(theta)^T y.  Candidates differ only in the order of
  * FP64 partial sums.  Both synchronize `stream` and return NLRMM_EINVAL while it is being
  * captured.  Later calls with the same shapes (operators, solver, graph captures) use the

@@ -47,7 +47,8 @@ constexpr int MAX_LINE = 4096;    // max pixels per image line handled by the pa
 
 struct ViewC {
     double cs, sn, wo;
-    float fwo, fwi, frho, f2wi, fh, fhk;   // Phi constants
+    float fwo, fwi, frho, f2wi, fh;   // Phi constants
+    float fk;                         // 1 / (2 rho) (0 when rho = 0): ramps of Phi / h
     float inv_ab, Kr, tq, kp, kappa;        // chord-moment constants
     int steep;                              // |cos| >= |sin|: lines are image rows
 };
@@ -69,7 +70,7 @@ __device__ __forceinline__ ViewC make_view(double th, double d)
     q.frho = (float)rho;
     q.f2wi = (float)(2.0 * wi);
     q.fh = (float)h;
-    q.fhk = rho > 0.0 ? (float)(0.5 * h / rho) : 0.0f;
+    q.fk = rho > 0.0 ? (float)(0.5 / rho) : 0.0f;
     const double ab = fmax(a * b, 1e-30);
     q.inv_ab = (float)(1.0 / ab);
     q.Kr = (float)((b * b - a * a) / (2.0 * ab));
@@ -81,18 +82,19 @@ __device__ __forceinline__ ViewC make_view(double th, double d)
     return q;
 }
 
-// Cumulative footprint Phi(v) (area of the pixel on the side p.n < c + v), FP32,
-// branch-free: left ramp t1^2 h/(2 rho), plateau h t2, right ramp h (t3 - t3^2/(2 rho)).
-// The forward and backward kernels evaluate the same function of the same offsets; they form
-// the offsets with different (both FP64-positioned) arithmetic, so the two operators are
-// transposes of each other up to FP32 rounding of the offsets.
-__device__ __forceinline__ float phi_f(float v, const ViewC &q)
+// Cumulative footprint Phi(v): area of the pixel on the side p.n < c + v, a left ramp
+// t1^2 h / (2 rho), a plateau h t2 and a right ramp h (t3 - t3^2 / (2 rho)).  phi_h returns
+// Phi(v) / h from the three shifted offsets u1 = v + wo, u2 = v + wi, u3 = v - wi, each t
+// clamped by one median; the caller applies the factor h once per sum.  The forward and
+// backward kernels evaluate this function of offsets formed with different (both
+// FP64-positioned) arithmetic, so the two operators are transposes of each other up to FP32
+// rounding of the offsets.
+__device__ __forceinline__ float phi_h(float u1, float u2, float u3, const ViewC &q)
 {
-    const float t1 = fminf(fmaxf(__fadd_rn(v, q.fwo), 0.0f), q.frho);
-    const float t2 = fminf(fmaxf(__fadd_rn(v, q.fwi), 0.0f), q.f2wi);
-    const float t3 = fminf(fmaxf(__fsub_rn(v, q.fwi), 0.0f), q.frho);
-    const float r = __fmul_rn(__fsub_rn(t1, t3), __fadd_rn(t1, t3));
-    return fmaf(r, q.fhk, __fmul_rn(q.fh, __fadd_rn(t2, t3)));
+    const float t1 = __builtin_amdgcn_fmed3f(u1, 0.0f, q.frho);
+    const float t2 = __builtin_amdgcn_fmed3f(u2, 0.0f, q.f2wi);
+    const float t3 = __builtin_amdgcn_fmed3f(u3, 0.0f, q.frho);
+    return fmaf(q.fk, t1 * t1, fmaf(t3, fmaf(-q.fk, t3, 1.0f), t2));
 }
 
 // Chord through the pixel at offset v from its centre: length L and the local midpoint
@@ -145,10 +147,14 @@ __device__ __forceinline__ T wave_sum(T v)
 // ---------------------------------------------------------------------------
 // One block per (image, line), rows (blockIdx.x < ny) and columns (the rest) of the image
 // in one launch: entries i = -2..n of the line, stored at i + 2: P = sum of pixels 0..i-1
-// (FP64), a = x_i, b = x_{i+1} (zero outside the line); tot = the line's sum.
+// (FP64), a = x_i, b = x_{i+1} (zero outside the line); tot = the line's sum.  The mirrored
+// pack holds the same entries for the reversed line (pixel i of it is pixel n-1-i), so a
+// walk against the pixel order reads its prefix directly.
 __global__ __launch_bounds__(BLK) void pack_lines_k(const float *__restrict__ x, int nx, int ny,
                                                     PackEntry *__restrict__ rowpack,
                                                     PackEntry *__restrict__ colpack,
+                                                    PackEntry *__restrict__ rowpack_m,
+                                                    PackEntry *__restrict__ colpack_m,
                                                     double *__restrict__ rowtot,
                                                     double *__restrict__ coltot)
 {
@@ -191,14 +197,20 @@ __global__ __launch_bounds__(BLK) void pack_lines_k(const float *__restrict__ x,
     }
     if (tid == BLK - 1) sP[n] = run;   // the last thread's chunk ends the line
     __syncthreads();
-    PackEntry *out = pack + (img * nlines + line) * (int64_t)(n + 3);
+    const int64_t lofs = (img * nlines + line) * (int64_t)(n + 3);
+    PackEntry *out = pack + lofs;
+    PackEntry *outm = (is_row ? rowpack_m : colpack_m) + lofs;
     for (int e = tid; e < n + 3; e += BLK) {
         const int i = e - 2;
-        PackEntry pe;
+        PackEntry pe, pm;
         pe.P = (i > 0) ? sP[i] : 0.0;
         pe.a = (i >= 0 && i < n) ? sx[i] : 0.0f;
         pe.b = (i + 1 >= 0 && i + 1 < n) ? sx[i + 1] : 0.0f;
+        pm.P = (i > 0) ? sP[n] - sP[n - i] : 0.0;
+        pm.a = (i >= 0 && i < n) ? sx[n - 1 - i] : 0.0f;
+        pm.b = (i + 1 >= 0 && i + 1 < n) ? sx[n - 2 - i] : 0.0f;
         out[e] = pe;
+        outm[e] = pm;
     }
     if (tid == 0) tot[img * nlines + line] = sP[n];
 }
@@ -246,6 +258,8 @@ __global__ __launch_bounds__(BLK) void line_prefix_k(const double *__restrict__ 
 struct FwdArgs {
     const PackEntry *rowpack;   // [img][ny][nx+3]
     const PackEntry *colpack;   // [img][nx][ny+3]
+    const PackEntry *rowpack_m; // mirrored lines, same layout
+    const PackEntry *colpack_m;
     const double *rowpre;       // [img][ny+1]
     const double *colpre;       // [img][nx+1]
     const double *theta;
@@ -279,7 +293,8 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
 
     if (a.skip != nullptr && *a.skip != 0) return;   // uniform over the launch
     const int tid = threadIdx.x;
-    const int lane = tid & 63, seg = tid >> 6;
+    const int lane = tid & 63;
+    const int seg = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, uniform
     const int64_t v = blockIdx.x / a.nchunks;
     const int q = (int)(blockIdx.x - v * a.nchunks);
     const int c0 = blockIdx.y * NC;
@@ -302,7 +317,9 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
     const double step = a.d * fabs(sm);
     const double inv_step = 1.0 / step;
     const double cw0 = asc ? (minor0 + 0.5 * a.d) * sm : (minor0 + (nminor - 0.5) * a.d) * sm;
-    const PackEntry *pack = steep ? a.rowpack : a.colpack;
+    // descending walks read the mirrored packs, so every walk advances through its pack
+    const PackEntry *pack = steep ? (asc ? a.rowpack : a.rowpack_m)
+                                  : (asc ? a.colpack : a.colpack_m);
     const double *pre = steep ? a.rowpre : a.colpre;
     const int64_t pstride = (int64_t)nlines * (nminor + 3);
     const int64_t tstride = nlines + 1;
@@ -313,54 +330,82 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
 #pragma unroll
     for (int c = 0; c < NC; ++c) accP[c] = accF[c] = accM[c] = 0.0;
 
-    if (j <= a.nb) {
-        const double e = edge_coord(a.s0, a.ds, j);
-        int la, lb;
+    // The line range an edge touches (lines outside it lie wholly on one side of the edge),
+    // then the wave's union of its edges' ranges, split evenly over the block's waves: every
+    // lane walks the same lines, so one pack load of the wave reads one line's neighbouring
+    // entries.  On a line outside an edge's own range the walk's clamped entry gives exactly
+    // 0 or the line's total, the value the line contributes.
+    const bool live = j <= a.nb;
+    const double e = edge_coord(a.s0, a.ds, j);
+    int la = nlines, lb = -1;   // lanes without an edge take no part in the union
+    if (live) {
         if (sl == 0.0) {
             la = 0;
             lb = nlines - 1;
         } else {
             const double A = e - w.wo - cw0 - (nminor - 1) * step;
             const double B = e + w.wo - cw0;
-            const double l1 = (A / sl - line0) / a.d - 0.5;
-            const double l2 = (B / sl - line0) / a.d - 0.5;
+            // reciprocals instead of divisions: the range is padded by a line either side
+            const double isl = 1.0 / sl, id = 1.0 / a.d;
+            const double l1 = (A * isl - line0) * id - 0.5;
+            const double l2 = (B * isl - line0) * id - 0.5;
             double lo = fmin(l1, l2), hi = fmax(l1, l2);
             lo = fmin(fmax(lo, -4.0), nlines + 4.0);
             hi = fmin(fmax(hi, -4.0), nlines + 4.0);
             la = min(max((int)floor(lo) - 1, 0), nlines);
             lb = min(max((int)ceil(hi) + 1, -1), nlines - 1);
         }
-        const PackEntry *pimg = pack + img0 * pstride;
-        // this wave's contiguous share of the edge's line range
-        const int len = lb - la + 1;
-        const int sa = len > 0 ? la + (len * seg) / FSEG : la;
-        const int sb = len > 0 ? la + (len * (seg + 1)) / FSEG - 1 : lb;
-        // Walk position of the edge on line L, in pixel steps from the first straddling
-        // candidate: q(L) = (e - lc(L) sl - wo - cw0) / step, linear in L.  K0 = floor(q) + 1
-        // is the first pixel the edge straddles, and the edge's offsets from the centres of
-        // pixels K0 and K0 + 1 (in walk order) are wo + (q - K0) step and that minus step, in
-        // both walk directions.
+    }
+    int WA = la, WB = lb;
+    for (int off = 32; off > 0; off >>= 1) {
+        WA = min(WA, __shfl_xor(WA, off, 64));
+        WB = max(WB, __shfl_xor(WB, off, 64));
+    }
+    WA = __builtin_amdgcn_readfirstlane(WA);
+    WB = __builtin_amdgcn_readfirstlane(WB);
+    {
+        // this wave's share of the union
+        const int len = WB - WA + 1;
+        const int sa = len > 0 ? WA + (len * seg) / FSEG : WA;
+        const int sb = len > 0 ? WA + (len * (seg + 1)) / FSEG - 1 : WB;
+        // Walk position of the edge on line L, in pixel steps (walk order):
+        // q(L) = (e - lc(L) sl - wo - cw0) / step, linear in L.  The first pixel the edge
+        // straddles is K0 = floor(q) + 1, clamped to [-1, n]; with r = q + 2 the pack entry
+        // index K0 + 2 = 1 + clamp(trunc(r), 0, n + 1) (truncation equals floor wherever the
+        // clamp does not bind).  The offsets of the edge from the centres of pixels K0 and
+        // K0 + 1 are va = wo + (q - K0) step and va - step; every clamp argument of Phi is
+        // an FMA of the fractional walk position r - (K0 + 1).
         const double dq = -a.d * sl * inv_step;
-        double q = sa <= sb ? (__dsub_rn(e, __dmul_rn(pix_coord(line0, a.d, sa), sl)) - w.wo -
-                               cw0) * inv_step
+        double r = sa <= sb ? (__dsub_rn(e, __dmul_rn(pix_coord(line0, a.d, sa), sl)) - w.wo -
+                               cw0) * inv_step + 2.0
                             : 0.0;
-        const float stepf = (float)step, wof = (float)w.wo;
+        const float stepf = (float)step;
+        const float c0a = (float)(w.wo - step);            // va = c0a + dr * step
+        const float c1a = (float)(2.0 * w.wo - step);      // va + wo
+        const float c2a = (float)(w.wo - step + (double)w.fwi);
+        const float c3a = (float)(w.wo - step - (double)w.fwi);
+        const float c1b = (float)(2.0 * w.wo - 2.0 * step);   // vb + wo, vb = va - step
+        const float c2b = (float)(w.wo - 2.0 * step + (double)w.fwi);
+        const float c3b = (float)(w.wo - 2.0 * step - (double)w.fwi);
+        const PackEntry *pline = pack + img0 * pstride + (int64_t)sa * (nminor + 3) + 1;
         auto walk = [&](auto ascending) __attribute__((always_inline)) {
             constexpr bool ASC = decltype(ascending)::value;
-            for (int L = sa; L <= sb; ++L, q += dq) {
-                const double tf = fmin(fmax(floor(q), -2.0), (double)nminor);
-                const int K0 = min((int)tf + 1, nminor);
-                const float va = fmaf((float)(q - (double)K0), stepf, wof);
-                const float vb = va - stepf;
-                const int idx = ASC ? K0 : nminor - 2 - K0;
+            for (int L = sa; L <= sb; ++L, r += dq, pline += nminor + 3) {
+                const int K1 = min(max((int)r, 0), nminor + 1);   // K0 + 1
+                const float dr = (float)(r - (double)K1);
                 float pa = 0.f, pb = 0.f, ma = 0.f, mb = 0.f;
                 if (PROJ) {
-                    pa = phi_f(va, w);
-                    pb = phi_f(vb, w);
+                    pa = phi_h(fmaf(dr, stepf, c1a), fmaf(dr, stepf, c2a), fmaf(dr, stepf, c3a),
+                               w);
+                    pb = phi_h(fmaf(dr, stepf, c1b), fmaf(dr, stepf, c2b), fmaf(dr, stepf, c3b),
+                               w);
                 }
                 if (MOM) {
-                    const int ka = ASC ? K0 : idx + 1;
-                    const int kb = ASC ? K0 + 1 : idx;
+                    const int K0 = K1 - 1;
+                    const int ka = ASC ? K0 : nminor - 1 - K0;
+                    const int kb = ASC ? K0 + 1 : nminor - 2 - K0;
+                    const float va = fmaf(dr, stepf, c0a);
+                    const float vb = va - stepf;
                     const double lc = pix_coord(line0, a.d, L);
                     const double tb = lc * tl;
                     float La, Lb, mua, mub;
@@ -369,38 +414,45 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
                     ma = La * ((float)(tb + pix_coord(minor0, a.d, ka) * tm) + mua);
                     mb = Lb * ((float)(tb + pix_coord(minor0, a.d, kb) * tm) + mub);
                 }
-                const PackEntry *pe = pimg + (int64_t)L * (nminor + 3) + (idx + 2);
+                const PackEntry *pe = pline + (unsigned)K1;
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     if (c < nc) {
                         const PackEntry E = pe[c * cstride * pstride];
-                        const float xa = ASC ? E.a : E.b;
-                        const float xb = ASC ? E.b : E.a;
                         if (PROJ) {
-                            accP[c] += ASC ? E.P : -(E.P + (double)(E.a + E.b));
-                            accF[c] += (double)fmaf(xb, pb, xa * pa);
+                            accP[c] += E.P;
+                            accF[c] += (double)fmaf(E.b, pb, E.a * pa);
                         }
-                        if (MOM) accM[c] += (double)fmaf(xb, mb, xa * ma);
+                        if (MOM) accM[c] += (double)fmaf(E.b, mb, E.a * ma);
                     }
                 }
             }
         };
         if (asc) walk(std::true_type{});
         else walk(std::false_type{});
-        if (PROJ && seg == 0) {
+        if (PROJ && seg == 0 && live) {
+            // lines outside the union that lie wholly on the lower side of this edge: for
+            // sl > 0 the lines below la, for sl < 0 the lines above lb
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 if (c < nc) {
                     const double *lt = pre + (img0 + c * cstride) * tstride;
                     double add = 0.0;
-                    if (!asc && la <= lb) add += lt[lb + 1] - lt[la];
-                    if (sl > 0.0) add += lt[la];
-                    else if (sl < 0.0) add += lt[nlines] - lt[lb + 1];
+                    if (sl > 0.0) {
+                        add += lt[min(la, WA)];
+                        if (la > WB + 1) add += lt[la] - lt[WB + 1];
+                    } else if (sl < 0.0) {
+                        if (lb + 1 < WA) add += lt[WA] - lt[lb + 1];
+                        add += lt[nlines] - lt[max(lb + 1, WB + 1)];
+                    }
                     accP[c] += add;
                 }
             }
         }
     }
+    const double hq = (double)w.fh;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) accF[c] *= hq;
     const double d2 = a.d * a.d;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -501,18 +553,28 @@ struct BwdArgs {
 };
 
 // Per-view constants of one backward tile: the footprint start of the tile centre in bin
-// units, split as jb (staged-window index of its bin) + T0 in [0, 1), and the bin-unit steps
-// of one pixel along x and y.
+// units, split as jb (staged-window index of its bin) + a fraction in [0, 1), stored as
+// T0 = fraction + TSHIFT and jb - TSHIFT so that every pixel's start T0 + pk ax + pl ay is
+// positive (its truncation is its floor); the bin-unit steps of one pixel along x and
+// y; for edge i of the window the three clamp arguments of Phi / h at fraction 0
+// (i ds, i ds - wo + wi, i ds - wo - wi); h and d^2 / h.
+constexpr int TSHIFT = 64;
+template <int E>
 struct BView {
     double T0, ax, ay;
     int jb;
-    float fwo, fwi, frho, f2wi, fh, fhk;
+    float cq[E][3];
+    float frho, f2wi, fk, fh, dh;
 };
 
+// One thread per pixel pair (kl, ll) and (kl, ll + 8) of a 16x16 tile: the per-view constants
+// staged in LDS serve two pixels per read.
+constexpr int BWD_BLK = TILE * TILE / 2;
+
 template <int E>
-__global__ __launch_bounds__(BLK) void bwd_tiles_k(BwdArgs a)
+__global__ __launch_bounds__(BWD_BLK) void bwd_tiles_k(BwdArgs a)
 {
-    __shared__ BView sv[VCHUNK];
+    __shared__ BView<E> sv[VCHUNK];
     __shared__ int sj0[VCHUNK];
     __shared__ float sy[VCHUNK][WMAX];
     const int tid = threadIdx.x;
@@ -520,10 +582,10 @@ __global__ __launch_bounds__(BLK) void bwd_tiles_k(BwdArgs a)
     const int64_t img = blockIdx.y;
     const int64_t col = img / a.nframes;
     const int f = (int)(img - col * a.nframes);
-    const int kl = tid % TILE, ll = tid / TILE;
+    const int kl = tid % TILE, ll = tid / TILE;   // ll in [0, TILE / 2)
     const int k = tx * TILE + kl;
-    const int l = ty * TILE + ll;
-    const bool active = k < a.nx && l < a.ny;
+    const int l0 = ty * TILE + ll, l1 = l0 + TILE / 2;
+    const bool act0 = k < a.nx && l0 < a.ny, act1 = k < a.nx && l1 < a.ny;
     const int64_t fv0 = (a.view_off && a.nframes > 1) ? a.view_off[f] : 0;
     const int64_t fv1 = (a.view_off && a.nframes > 1) ? a.view_off[f + 1] : a.V;
     const int split = blockIdx.z;
@@ -532,11 +594,10 @@ __global__ __launch_bounds__(BLK) void bwd_tiles_k(BwdArgs a)
     const float *ycol = a.y + col * a.V * a.nb;
     const double xc = a.x0 + (tx * TILE + 0.5 * TILE) * a.d;
     const double yc = a.y0 + (ty * TILE + 0.5 * TILE) * a.d;
-    // pixel centre relative to the tile centre, in pixels
+    // pixel centres relative to the tile centre, in pixels
     const double pk = kl + 0.5 - 0.5 * TILE, pl = ll + 0.5 - 0.5 * TILE;
-    const float d2 = (float)(a.d * a.d);
-    const float fds = (float)a.ds;
-    double acc = 0.0;
+    const double hl = 0.5 * TILE;   // row offset of the second pixel
+    double acc0 = 0.0, acc1 = 0.0;
 
     for (int64_t vb = v0; vb < v1; vb += VCHUNK) {
         const int nv = (int)min((int64_t)VCHUNK, v1 - vb);
@@ -547,60 +608,77 @@ __global__ __launch_bounds__(BLK) void bwd_tiles_k(BwdArgs a)
             const int j0 = (int)floor((cC - R - a.s0) / a.ds) - 1;
             const double T = (cC - w.wo - a.s0) / a.ds;
             const double Tf = floor(T);
-            BView q;
-            q.T0 = T - Tf;
+            BView<E> q;
+            q.T0 = (T - Tf) + TSHIFT;
             q.ax = a.d * w.cs / a.ds;
             q.ay = a.d * w.sn / a.ds;
-            q.jb = (int)Tf - j0;
-            q.fwo = w.fwo;
-            q.fwi = w.fwi;
+            q.jb = (int)Tf - j0 - TSHIFT;
+            const double wi = (double)w.fwi;
+            for (int i = 1; i <= E; ++i) {
+                q.cq[i - 1][0] = (float)(i * a.ds);
+                q.cq[i - 1][1] = (float)(i * a.ds - w.wo + wi);
+                q.cq[i - 1][2] = (float)(i * a.ds - w.wo - wi);
+            }
             q.frho = w.frho;
             q.f2wi = w.f2wi;
+            q.fk = w.fk;
             q.fh = w.fh;
-            q.fhk = w.fhk;
+            q.dh = (float)(a.d * a.d / (double)w.fh);
             sv[tid] = q;
             sj0[tid] = j0;
         }
         __syncthreads();
-        for (int i = tid; i < nv * a.W; i += BLK) {
+        for (int i = tid; i < nv * a.W; i += BWD_BLK) {
             const int vi = i / a.W, jj = i - vi * a.W;
             const int jbin = sj0[vi] + jj;
             sy[vi][jj] = (jbin >= 0 && jbin < a.nb) ? ycol[(vb + vi) * a.nb + jbin] : 0.0f;
         }
         __syncthreads();
-        if (active) {
-            for (int vi = 0; vi < nv; ++vi) {
-                const BView &q = sv[vi];
-                // footprint start of this pixel in bin units: jb + t, split into bin and
-                // fraction f; edge i of the window then sits at (i - f) ds - wo from the centre
-                const double t = fma(pk, q.ax, fma(pl, q.ay, q.T0));
-                const double tf = floor(t);
-                const float fr = (float)(t - tf);
-                int jj = q.jb + (int)tf;
+        const float fds = (float)a.ds;
+        float accf0 = 0.0f, accf1 = 0.0f;   // this chunk's views in FP32, chunks summed in FP64
+        for (int vi = 0; vi < nv; ++vi) {
+            const BView<E> &q = sv[vi];
+            ViewC w;
+            w.frho = q.frho;
+            w.f2wi = q.f2wi;
+            w.fk = q.fk;
+            // footprint start of each pixel in bin units (shifted positive): window bin jj
+            // and fraction fr; edge i of the window sits at (i - fr) ds - wo from the pixel's
+            // centre
+            const double t0 = fma(pk, q.ax, fma(pl, q.ay, q.T0));
+            const double t1 = fma(hl, q.ay, t0);
+            float sum[2];
+#pragma unroll
+            for (int px = 0; px < 2; ++px) {
+                const double t = px == 0 ? t0 : t1;
+                const float fr = (float)__builtin_amdgcn_fract(t);
+                int jj = q.jb + (int)t;
                 jj = min(max(jj, 0), a.W - (E + 1));
-                ViewC w;
-                w.fwo = q.fwo;
-                w.fwi = q.fwi;
-                w.frho = q.frho;
-                w.f2wi = q.f2wi;
-                w.fh = q.fh;
-                w.fhk = q.fhk;
                 const float *yy = &sy[vi][jj];
-                float prev = 0.0f, sum = 0.0f;
+                float prev = 0.0f, sm = 0.0f;
 #pragma unroll
                 for (int i = 1; i <= E; ++i) {
-                    const float ph = phi_f(fmaf((float)i - fr, fds, -q.fwo), w);
-                    sum = fmaf(ph - prev, yy[i - 1], sum);
+                    const float ph = phi_h(fmaf(-fr, fds, q.cq[i - 1][0]),
+                                           fmaf(-fr, fds, q.cq[i - 1][1]),
+                                           fmaf(-fr, fds, q.cq[i - 1][2]), w);
+                    sm = fmaf(ph - prev, yy[i - 1], sm);
                     prev = ph;
                 }
-                sum = fmaf(d2 - prev, yy[E], sum);
-                acc += (double)sum;
+                sum[px] = fmaf(q.dh - prev, yy[E], sm);
             }
+            accf0 = fmaf(q.fh, sum[0], accf0);
+            accf1 = fmaf(q.fh, sum[1], accf1);
         }
+        acc0 += (double)accf0;
+        acc1 += (double)accf1;
         __syncthreads();
     }
-    if (active) {
-        const int64_t o = ((col * a.nframes + f) * (int64_t)a.ny + l) * a.nx + k;
+    const int64_t ibase = (col * a.nframes + f) * (int64_t)a.ny;
+#pragma unroll
+    for (int px = 0; px < 2; ++px) {
+        if (!(px == 0 ? act0 : act1)) continue;
+        const double acc = px == 0 ? acc0 : acc1;
+        const int64_t o = (ibase + (px == 0 ? l0 : l1)) * a.nx + k;
         if (a.nsplit > 1) {
             const int64_t tot = (int64_t)gridDim.y * a.nx * a.ny;
             a.part[split * tot + o] = (float)(acc / a.ds);
@@ -647,8 +725,8 @@ static size_t fwd_ws_bytes(const nlrmm_geom &g, int nframes, int gcols, int64_t 
     const int64_t nx = g.nx, ny = g.ny;
     size_t b = 0;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    b += al(sizeof(PackEntry) * nimg * ny * (nx + 3));       // row packs
-    b += al(sizeof(PackEntry) * nimg * nx * (ny + 3));       // column packs
+    b += 2 * al(sizeof(PackEntry) * nimg * ny * (nx + 3));   // row packs, direct and mirrored
+    b += 2 * al(sizeof(PackEntry) * nimg * nx * (ny + 3));   // column packs, likewise
     b += al(sizeof(double) * nimg * (ny + nx));              // line totals
     b += al(sizeof(double) * nimg * (ny + 1));               // row-total prefixes
     b += al(sizeof(double) * nimg * (nx + 1));               // column-total prefixes
@@ -715,7 +793,11 @@ int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
     char *p = (char *)ctx->ws.ptr;
     PackEntry *rowpack = (PackEntry *)p;
     p += al(sizeof(PackEntry) * (int64_t)gcols * F * ny * (nx + 3));
+    PackEntry *rowpack_m = (PackEntry *)p;
+    p += al(sizeof(PackEntry) * (int64_t)gcols * F * ny * (nx + 3));
     PackEntry *colpack = (PackEntry *)p;
+    p += al(sizeof(PackEntry) * (int64_t)gcols * F * nx * (ny + 3));
+    PackEntry *colpack_m = (PackEntry *)p;
     p += al(sizeof(PackEntry) * (int64_t)gcols * F * nx * (ny + 3));
     double *tot = (double *)p;
     p += al(sizeof(double) * (int64_t)gcols * F * (ny + nx));
@@ -733,13 +815,15 @@ int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
         // row and column packs of every image in one launch, then both line prefixes
         double *ctot = tot + nimg * ny;
         pack_lines_k<<<dim3((unsigned)(ny + nx), (unsigned)nimg), BLK, 0, s>>>(
-            xg, (int)nx, (int)ny, rowpack, colpack, tot, ctot);
+            xg, (int)nx, (int)ny, rowpack, colpack, rowpack_m, colpack_m, tot, ctot);
         line_prefix_k<<<dim3((unsigned)nimg, 2), BLK, 0, s>>>(tot, ctot, (int)nx, (int)ny, rowpre,
                                                              colpre);
 
         FwdArgs a;
         a.rowpack = rowpack;
         a.colpack = colpack;
+        a.rowpack_m = rowpack_m;
+        a.colpack_m = colpack_m;
         a.rowpre = rowpre;
         a.colpre = colpre;
         a.theta = theta;
@@ -807,7 +891,7 @@ int fwd_seg_for(const nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
 int bwd_split_max(const nlrmm_geom &, const nlrmm_batch &b)
 {
     int64_t ns = (b.nviews / b.nframes) / 16;
-    if (ns > 8) ns = 8;
+    if (ns > 16) ns = 16;
     if (ns < 1) ns = 1;
     return (int)ns;
 }
@@ -816,12 +900,12 @@ int bwd_split_max(const nlrmm_geom &, const nlrmm_batch &b)
 int bwd_splits(const nlrmm_geom &g, const nlrmm_batch &b, int ncols, int cu_count)
 {
     const int64_t tiles = (int64_t)((g.nx + TILE - 1) / TILE) * ((g.ny + TILE - 1) / TILE);
-    const int64_t waves = tiles * ncols * b.nframes * (BLK / 64);
+    const int64_t waves = tiles * ncols * b.nframes * (BWD_BLK / 64);
     const int64_t target = (int64_t)6 * 4 * cu_count;   // ~6 resident waves per SIMD
     int64_t ns = (target + waves - 1) / waves;
     const int64_t vper = b.nviews / b.nframes;
     if (ns > vper / 16) ns = vper / 16;
-    if (ns > 8) ns = 8;
+    if (ns > 16) ns = 16;
     if (ns < 1) ns = 1;
     return (int)ns;
 }
@@ -881,10 +965,10 @@ int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b
               (unsigned)a.nsplit);
     timing_mark(ctx, 1, 0, s);
     switch (E) {
-        case 1: bwd_tiles_k<1><<<grid, BLK, 0, s>>>(a); break;
-        case 2: bwd_tiles_k<2><<<grid, BLK, 0, s>>>(a); break;
-        case 3: bwd_tiles_k<3><<<grid, BLK, 0, s>>>(a); break;
-        default: bwd_tiles_k<4><<<grid, BLK, 0, s>>>(a); break;
+        case 1: bwd_tiles_k<1><<<grid, BWD_BLK, 0, s>>>(a); break;
+        case 2: bwd_tiles_k<2><<<grid, BWD_BLK, 0, s>>>(a); break;
+        case 3: bwd_tiles_k<3><<<grid, BWD_BLK, 0, s>>>(a); break;
+        default: bwd_tiles_k<4><<<grid, BWD_BLK, 0, s>>>(a); break;
     }
     timing_mark(ctx, 1, 1, s);
     if (a.nsplit > 1) {

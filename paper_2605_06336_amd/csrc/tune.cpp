@@ -1,6 +1,6 @@
 // Autotuner of the projector launch shapes.  The forward kernel can split each edge's lines
 // over 1, 2, 4 or 8 waves of a block, and the backprojection can split each frame's views
-// over 1..8 partial images; which is fastest depends on the shape (grid size, views per
+// over 1..16 partial images; which is fastest depends on the shape (grid size, views per
 // frame, columns) and on the device.  The tuner runs the real operator once per candidate,
 // times it with HIP events on the caller's stream and keeps the fastest in the context (and,
 // when a cache file is set, appends it there).  Every candidate computes the same operator;

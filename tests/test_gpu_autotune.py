@@ -48,7 +48,7 @@ def test_every_shape_matches_oracle(tmp_path, N, nb, V, ncols, F):
     xb_ref = P.backproject(ys.astype(np.float64), th, N, vo).reshape(ncols, F, N, N)
     D_ref = P.dtheta(x.astype(np.float64), th, nb, vo)
     nc = 8 if ncols >= 8 else 4 if ncols >= 4 else 2 if ncols >= 2 else 1
-    max_split = max(1, min(8, (Vt // F) // 16))
+    max_split = max(1, min(16, (Vt // F) // 16))
     path = str(tmp_path / "tune.txt")
     for seg in (1, 2, 4, 8):
         with open(path, "w") as f:
@@ -88,7 +88,7 @@ def test_tuner_returns_operator_and_stores_choice(tmp_path):
     seg = ops.tune_query("project", g, V, ncols)
     split = ops.tune_query("backproject", g, V, ncols)
     assert seg in (1, 2, 4, 8)
-    assert 1 <= split <= 8
+    assert 1 <= split <= 16
     lines = open(path).read().split("\n")
     assert f"0 {N} {N} {nb} 1 2 {V} {seg}" in lines
     assert f"1 {N} {N} {nb} 1 {ncols} {V} {split}" in lines
