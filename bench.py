@@ -13,9 +13,13 @@ Also reported:
   * outer it/s of the 32-frame dynamic workload, batched (one launch over all frames, the
     outer iteration replayed as a HIP graph) against plain (per-frame launches, eager), with
     the difference of the two reconstructions after the same iterations;
+  * Gsamples/s of the three operators at the shape of every workload (64x64 up to
+    2048x2048 / 1440 views, and one 22-view block of the streaming workload);
+  * outer it/s of VarPro NL-RMM-GKS on the 512x512 / 720-view workload;
   * the FP64 oracle timed on a bounded sample on the host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-dynamic]
+                       [--no-workloads]
        python bench.py --ops-only     (operators and a copy calibration only, for counters)
 """
 import argparse
@@ -43,6 +47,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dynamic", action="store_true", help="skip the batched-vs-plain leg")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the operator rates at every workload shape and the VarPro leg")
     ap.add_argument("--ops-only", action="store_true",
                     help="only the operator timings and the copy calibration")
     ap.add_argument("--reps", type=int, default=20, help="repetitions per operator timing")
@@ -158,6 +164,94 @@ def autotune(torch, ops, g, x, theta, b, kmin, fr=None):
     return {"fwd_waves_per_block_1col": ops.tune_query("project", g, V, 1, fr),
             f"fwd_waves_per_block_{kmin + 1}col": ops.tune_query("project", g, V, kmin + 1, fr),
             "bwd_view_split": ops.tune_query("backproject", g, V, 1, fr)}
+
+
+def workload_operators(torch, ops, metrics, synth, reps):
+    """Gsamples/s of the three operators (one column) at the shape of every workload: its
+    grid, bins, views and frames, with the workload's true angles and a random image and
+    sinogram; for the streaming workload also one block of its views.  The launch shapes are
+    tuned for each shape first; nnz is counted exactly."""
+    dev = torch.device("cuda", 0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(12345)
+    stream = torch.cuda.current_stream()
+    out = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        for _ in range(reps):
+            fn()
+        a1.record(stream)
+        torch.cuda.synchronize()
+        return a0.elapsed_time(a1) / reps
+
+    cases = [("c1", None), ("c2", None), ("c3", None), ("c4", None), ("c5", None),
+             ("c5", 0)]
+    for key, block in cases:
+        wl = synth.WORKLOADS[key]
+        inst = synth.draw(wl, with_image=False)
+        th_host = inst.theta_true if block is None else inst.theta_true[inst.blocks[block]]
+        V = th_host.size
+        F = wl.frames
+        fr = ops.Frames(inst.view_off) if F > 1 else None
+        g = ops.geom(wl.N, wl.nb)
+        th = torch.as_tensor(th_host, device=dev)
+        x = torch.rand((1, F, wl.N, wl.N), generator=gen, device=dev, dtype=torch.float32)
+        y = torch.randn((1, V, wl.nb), generator=gen, device=dev, dtype=torch.float32)
+        nnz = metrics.nnz_torch(torch, wl.N, wl.nb, th_host, device=dev)
+        ops.autotune_project(x, th, g, fr)
+        ops.autotune_backproject(y, th, g, fr)
+        yo = torch.empty_like(y)
+        xo = torch.empty_like(x)
+        ms = {"project": timed(lambda: ops.project(x, th, g, fr, out=yo)),
+              "backproject": timed(lambda: ops.backproject(y, th, g, fr, out=xo)),
+              "dtheta": timed(lambda: ops.project_dtheta(x, th, g, fr, want_dy=True))}
+        name = key if block is None else f"{key}_block{block}"
+        out[name] = {"grid": f"{F}x{wl.N}x{wl.N}" if F > 1 else f"{wl.N}x{wl.N}",
+                     "views": int(V), "bins": wl.nb, "nnz": int(nnz),
+                     "gsamples_per_s": {k: round(nnz / (v * 1e-3) / 1e9, 1)
+                                        for k, v in ms.items()},
+                     "ms": {k: round(v, 4) for k, v in ms.items()}}
+        print(f"# operators at {name}: {out[name]['gsamples_per_s']}", file=sys.stderr,
+              flush=True)
+        del x, y, xo, yo
+    torch.cuda.synchronize()
+    return out
+
+
+def varpro_leg(torch, ops, synth, Config, Solver, steps, warmup, gram_precision):
+    """Outer it/s of VarPro NL-RMM-GKS on the 512x512 / 720-view / 725-bin workload (S = 15
+    projected solves per outer iteration, kmax 25)."""
+    wl = synth.WORKLOADS["c3"]
+    inst = synth.draw(wl)
+    g = ops.geom(wl.N, wl.nb)
+    x32, th_true, b, delta = make_data(torch, ops, inst, wl, g)
+    autotune(torch, ops, g, x32, th_true, b, wl.kmin)
+    stream = torch.cuda.current_stream()
+    theta = torch.as_tensor(inst.theta_nom.copy(), device="cuda")
+    cfg = Config(kmin=wl.kmin, kmax=wl.kmax, solves=wl.solves, eps=wl.eps, param_update=2,
+                 gram_precision=gram_precision)
+    sol = Solver(g, 1, wl.n_views, cfg)
+    sol.init(theta, b)
+    for _ in range(warmup):
+        sol.outer(theta, b, delta)
+    ms = timed_steps(torch, lambda: sol.outer(theta, b, delta), steps, stream, "c3 varpro")
+    u, _, status = sol.read()
+    torch.cuda.synchronize()
+    x_true = inst.x_true.reshape(-1)
+    rre = float(np.linalg.norm(u.cpu().numpy() - x_true) / np.linalg.norm(x_true))
+    dth0 = inst.theta_true - inst.theta_nom
+    perr = float(np.linalg.norm(theta.cpu().numpy() - inst.theta_true) / np.linalg.norm(dth0))
+    sol.close()
+    return {"outer_it_s": round(1000.0 / ms, 4), "ms_per_step": round(ms, 3),
+            "rre": round(rre, 5), "angle_err_rel": round(perr, 5), "status": int(status.cpu()[0]),
+            "workload": f"c3: 512x512, 720 views, 725 bins, VarPro, S = {wl.solves}, kmax "
+                        f"{wl.kmax}, regulariser Gram precision {gram_precision}; {warmup} "
+                        f"warm-up + {steps} timed outer iterations"}
 
 
 def dynamic_leg(torch, ops, synth, Config, OuterGraph, Solver, steps, warmup, gram_precision):
@@ -278,6 +372,12 @@ def main():
         dyn = dynamic_leg(torch, ops, synth, Config, OuterGraph, Solver, max(3, args.steps // 2),
                           2, args.gram_precision)
 
+    per_workload = varpro = None
+    if not args.no_workloads:
+        per_workload = workload_operators(torch, ops, metrics, synth, max(3, args.reps // 4))
+        varpro = varpro_leg(torch, ops, synth, Config, Solver, max(3, args.steps // 2), 2,
+                            args.gram_precision)
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import method as OM
@@ -324,6 +424,8 @@ def main():
                     "lambda": float(sc.cpu().numpy()[2]), "status": int(status.cpu()[0])},
         "autotune": tuned,
         "batched_vs_plain": dyn,
+        "operators_by_workload": per_workload,
+        "varpro_c3": varpro,
         "roofline": roofline,
         "roofline_backproject": roofline_bwd,
         "cpu_baseline": cpu,

@@ -255,6 +255,27 @@ __global__ __launch_bounds__(BLK) void line_prefix_k(const double *__restrict__ 
 // ---------------------------------------------------------------------------
 // forward: projection and angle derivative, edge-driven
 // ---------------------------------------------------------------------------
+// Work item (view v, chunk q of 63 bins) of forward block b out of T = views x chunks.
+// Blocks are dealt to the 8 XCDs in turn (b mod 8), so consecutive blocks sit on different
+// L2 caches; the first T - T mod 8 blocks are renumbered so that each XCD takes a contiguous
+// run w of items, and runs are ordered by groups of 16 neighbouring views, chunk, view: the
+// blocks an XCD holds at once work on the same chunk of nearly the same angles, whose edges
+// cross nearly the same pack entries.
+constexpr int FWD_XCDS = 8, FWD_VGROUP = 16;
+__device__ __forceinline__ void fwd_block_item(int64_t b, int64_t T, int nchunks, int64_t &v,
+                                               int &q)
+{
+    const int64_t body = T - T % FWD_XCDS;
+    const int64_t w = b < body ? (b % FWD_XCDS) * (body / FWD_XCDS) + b / FWD_XCDS : b;
+    const int64_t V = T / nchunks;
+    const int64_t gitems = (int64_t)FWD_VGROUP * nchunks;
+    const int64_t g = w / gitems;
+    const int64_t gsz = min((int64_t)FWD_VGROUP, V - g * FWD_VGROUP);
+    const int64_t rem = w - g * gitems;
+    q = (int)(rem / gsz);
+    v = g * FWD_VGROUP + rem % gsz;
+}
+
 struct FwdArgs {
     const PackEntry *rowpack;   // [img][ny][nx+3]
     const PackEntry *colpack;   // [img][nx][ny+3]
@@ -295,8 +316,9 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int seg = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, uniform
-    const int64_t v = blockIdx.x / a.nchunks;
-    const int q = (int)(blockIdx.x - v * a.nchunks);
+    int64_t v;
+    int q;
+    fwd_block_item(blockIdx.x, gridDim.x, a.nchunks, v, q);
     const int c0 = blockIdx.y * NC;
     const int nc = min(NC, a.ncols - c0);
     const int f = frame_of(a.view_off, a.nframes, v);

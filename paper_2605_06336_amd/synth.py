@@ -98,7 +98,7 @@ WORKLOADS = {
 class Instance:
     """One drawn problem instance (all arrays host numpy)."""
     wl: Workload
-    x_true: np.ndarray          # float64 [frames, N, N]
+    x_true: Optional[np.ndarray]   # float64 [frames, N, N] (None: drawn without the image)
     theta_nom: np.ndarray       # float64 [V]
     theta_true: np.ndarray      # float64 [V]
     view_off: np.ndarray        # int64 [frames + 1]
@@ -122,8 +122,10 @@ def ellipse_image(N: int, cx, cy, a, b, phi, rho, sub: int = 4) -> np.ndarray:
     return img.reshape(N, sub, N, sub).mean(axis=(1, 3))
 
 
-def draw(wl: Workload, N: Optional[int] = None) -> Instance:
-    """Draw the instance of a workload.  ``N`` overrides the grid (for scaled tests)."""
+def draw(wl: Workload, N: Optional[int] = None, with_image: bool = True) -> Instance:
+    """Draw the instance of a workload.  ``N`` overrides the grid (for scaled tests);
+    ``with_image=False`` skips building the phantom (x_true is None) and draws everything
+    else identically (the random stream does not depend on the image)."""
     rng = np.random.Generator(np.random.PCG64(wl.seed))
     N = wl.N if N is None else N
     ne = wl.n_ellipses
@@ -142,14 +144,15 @@ def draw(wl: Workload, N: Optional[int] = None) -> Instance:
         golden = math.pi * (math.sqrt(5.0) - 1.0) / 2.0
         V = int(counts.sum())
         theta_nom = np.mod(start + golden * np.arange(V), math.pi)
-        frames = [ellipse_image(N, cx + t * vx, cy + t * vy, a, b, phi, rho)
-                  for t in range(wl.frames)]
-        x_true = np.stack(frames)
+        x_true = None
+        if with_image:
+            x_true = np.stack([ellipse_image(N, cx + t * vx, cy + t * vy, a, b, phi, rho)
+                               for t in range(wl.frames)])
         view_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
     else:
         V = wl.n_views
         theta_nom = np.arange(V) * (math.pi / V)
-        x_true = ellipse_image(N, cx, cy, a, b, phi, rho)[None]
+        x_true = ellipse_image(N, cx, cy, a, b, phi, rho)[None] if with_image else None
         view_off = np.array([0, V], dtype=np.int64)
     theta_true = theta_nom + rng.normal(0.0, math.radians(wl.sigma_deg), V)
     blocks = None
