@@ -243,6 +243,13 @@ typedef struct {
     int32_t temporal;        /* dynamic problems: regulariser includes frame differences */
     int32_t gram_precision;  /* regulariser Gram: 0 FP64, 1 FP32 MFMA, 2 BF16 MFMA (nlrmm_gram_psi) */
     int32_t compress_precision; /* compression basis products: 0 FP32/FP64-accumulate, 2 BF16 MFMA */
+    double lam_hi;           /* > 0: the optional high-regularisation solve of Section 4.3 (Alg.
+                                "nl_rmmgks_two_solves"): after Compress, one RMM-GKS cycle with
+                                lambda fixed at lam_hi (solves projected solves from the
+                                compressed basis and u_{k+1}) gives u_hat, which the parameter
+                                update uses instead of u_{k+1} (VarPro: with its compressed basis
+                                and lam_hi); the image, basis, lambda and residual carried to the
+                                next outer iteration stay those of the primary solve.  <= 0: off */
 } nlrmm_solver_cfg;
 
 typedef struct nlrmm_solver nlrmm_solver;

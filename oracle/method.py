@@ -13,7 +13,8 @@ Each function follows the paper's algorithm in the paper's order:
   * UPDATE-PARAM ............. Alg. "update_param" (damped Gauss-Newton + Armijo)
   * VarPro ................... Section 4.2 eqs. "u_closed_form", "GN_system", supplementary
                                Alg. "update_varpro"
-  * NL-RMM-GKS ............... Alg. "nl_rmmgks_two_solves" (high-regularisation solve off)
+  * NL-RMM-GKS ............... Alg. "nl_rmmgks_two_solves", with the optional
+                               high-regularisation solve of Section 4.3 (lam_hi)
   * s-NL-RMM-GKS ............. Alg. "s_nl_rmmgks_final"
   * dynamic ANISO-TV ......... Section 7 (operator D1, block-diagonal H)
 
@@ -25,7 +26,9 @@ Readings where the paper is silent (all listed in the design notes):
   right singular vectors plus the normalised remainder of u; GN damping
   mu = 1e-6 * mean(diag), c1 = 1e-4, beta = 1/2, alpha0 = 1, 10 trials,
   one global alpha, maxiter_p = 1; VarPro weights B = diag(sqrt(w)) Psi V with w
-  from the current image; GKB start basis of kmin+1 vectors from b, u0 = 0.
+  from the current image; GKB start basis of kmin+1 vectors from b, u0 = 0; the
+  high-regularisation solve is one RMM-GKS cycle of S fixed-lambda solves from the
+  compressed primary basis (kmin columns) and u_{k+1}.
 """
 from __future__ import annotations
 
@@ -171,6 +174,7 @@ class Config:
     tau: float = 1.01                 # DP safety factor
     dp_iters: int = 200
     lam_fix: Optional[float] = None   # fixed lambda instead of DP
+    lam_hi: Optional[float] = None    # high-regularisation solve for the parameter update
     gn: str = "altmin"                # "altmin" | "varpro" | "none"
     param_mode: str = "per_view"      # "per_view" | "scalar" (one global shift)
     maxiter_p: int = 1
@@ -438,10 +442,37 @@ def init_state(geo: Geometry, theta0, b, cfg: Config) -> State:
                  theta=np.array(theta0, dtype=np.float64))
 
 
+def hi_solve(geo: Geometry, theta_k, st: State, b, cfg: Config) -> State:
+    """The optional high-regularisation solve of Alg. "nl_rmmgks_two_solves" (Section 4.3):
+    one RMM-GKS cycle (Alg. "rmmgks") with lambda fixed at lam_hi, started from the primary
+    image u_{k+1} and its compressed basis V_kmin (copies; the primary state is untouched):
+    S projected solves on kmin, kmin+1, ... columns with an expansion between consecutive
+    solves (Alg. "enlarge"), then Compress when the VarPro update needs the compressed basis
+    (Compress leaves u = V z unchanged, so AltMin takes u_hat from the last solve).  Returns
+    the state holding u_hat, its basis and lam_hi, which only the parameter update uses."""
+    hs = State(V=st.V.copy(), AV=st.AV.copy(), PV=st.PV.copy(), u=st.u.copy(),
+               theta=st.theta.copy())
+    hcfg = dataclasses.replace(cfg, lam_fix=cfg.lam_hi)
+    S = cfg.S
+    for t in range(S):
+        w = weights(geo, hs.u, cfg.eps)
+        z, lam, RA, RP, flag = projected_solve(hs, b, w, hcfg, None)
+        hs.status |= flag
+        hs.z, hs.lam = z, lam
+        hs.u = hs.V @ z
+        if t < S - 1:
+            r = mm_residual(geo, theta_k, hs, b, w, lam, z)
+            append_direction(geo, theta_k, hs, r, cfg)
+    if cfg.gn == "varpro":
+        compress(hs, RA, RP, hs.lam, hs.z, cfg.kmin)
+    return hs
+
+
 def outer_step(geo: Geometry, st: State, b, delta, cfg: Config):
-    """One outer iteration of NL-RMM-GKS (Alg. "nl_rmmgks_two_solves", high-regularisation
-    solve off): rebase A V at theta_k, Enlarge (S solves, S-1 appends), Compress,
-    UPDATE-PARAM, weights from u_{k+1}, residual with the old operator H_k, append."""
+    """One outer iteration of NL-RMM-GKS (Alg. "nl_rmmgks_two_solves"): rebase A V at
+    theta_k, Enlarge (S solves, S-1 appends), Compress, the optional high-regularisation
+    solve (cfg.lam_hi), UPDATE-PARAM on u_{k+1} (or on u_hat when lam_hi is set), weights
+    from u_{k+1}, residual with the old operator H_k and lambda_k, append."""
     theta_k = st.theta.copy()
     st.AV = A_cols(geo, theta_k, st.V)
     target = cfg.tau * delta
@@ -456,11 +487,17 @@ def outer_step(geo: Geometry, st: State, b, delta, cfg: Config):
             r = mm_residual(geo, theta_k, st, b, w, lam, z)
             append_direction(geo, theta_k, st, r, cfg)
     compress(st, RA, RP, st.lam, st.z, cfg.kmin)
+    # the state the parameter update works on: the primary one, or the smoother estimate of
+    # the high-regularisation solve (its basis is discarded afterwards)
+    ps = st
+    if cfg.lam_hi is not None:
+        ps = hi_solve(geo, theta_k, st, b, cfg)
+        st.status |= ps.status
     if cfg.gn == "altmin":
-        theta_new, flag, info = gn_altmin(geo, theta_k, st.u, b, cfg)
+        theta_new, flag, info = gn_altmin(geo, theta_k, ps.u, b, cfg)
     elif cfg.gn == "varpro":
-        w = weights(geo, st.u, cfg.eps)
-        theta_new, flag, info = gn_varpro(geo, theta_k, st.V, b, w, st.PV, st.lam, cfg)
+        w = weights(geo, ps.u, cfg.eps)
+        theta_new, flag, info = gn_varpro(geo, theta_k, ps.V, b, w, ps.PV, ps.lam, cfg)
     else:
         theta_new, flag, info = theta_k, 0, {}
     st.status |= flag
@@ -468,7 +505,8 @@ def outer_step(geo: Geometry, st: State, b, delta, cfg: Config):
     r = mm_residual(geo, theta_k, st, b, w, st.lam, st.z)
     append_direction(geo, theta_k, st, r, cfg, with_projection=False)
     st.theta = theta_new
-    st.log.append(dict(lam=st.lam, alpha=info.get("alpha"), status=st.status))
+    st.log.append(dict(lam=st.lam, alpha=info.get("alpha"), status=st.status,
+                       u_hat=None if ps is st else ps.u))
     return st
 
 

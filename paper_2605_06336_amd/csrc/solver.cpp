@@ -21,6 +21,7 @@ enum {
     S_TARGET = 1,   // tau * delta
     S_LAM = 2,      // lambda of the last projected solve
     S_RES2 = 3,     // model residual ||AVz - b||^2 of the last solve
+    S_LAMK = 4,     // lambda_k of the primary solve while the high-regularisation solve runs
     S_GN = 8,       // [f0, g^T d, alpha, mu, f_accepted] of the last Gauss-Newton step
     S_NB = 16,      // scalars
 };
@@ -40,7 +41,8 @@ struct Solver {
     bool w_from_u = true;     // weights of u may be formed on the fly (false: caller's w)
     // device buffers
     float *V = nullptr, *AV = nullptr, *Vtmp = nullptr, *u = nullptr, *r = nullptr,
-          *rho = nullptr, *w = nullptr;
+          *rho = nullptr, *w = nullptr, *uh = nullptr;
+    double *zh = nullptr;   // coefficients of the high-regularisation solve
     double *GA = nullptr, *GP = nullptr, *rb = nullptr, *z = nullptr, *T = nullptr,
            *zt = nullptr, *sc = nullptr, *hb = nullptr, *hb2 = nullptr, *gv = nullptr,
            *hv = nullptr, *rv = nullptr, *dir = nullptr, *alphas = nullptr, *thk = nullptr,
@@ -359,6 +361,59 @@ static int varpro_update(Solver &S, const nlrmm_batch &b, double *theta, const f
     return NLRMM_OK;
 }
 
+// The optional high-regularisation solve of Alg. "nl_rmmgks_two_solves" (Section 4.3), run
+// after Compress: one RMM-GKS cycle with lambda fixed at lam_hi from the compressed basis
+// V_kmin and u_{k+1}, then the parameter update on its image u_hat (VarPro: on its own
+// compressed basis, in Vtmp, and lam_hi).  Its basis grows in the columns kmin.. of V and
+// A V, which the primary state does not use after Compress, and in the data Gram (rebuilt
+// by the next rebase); it keeps its own image and coefficients (uh, zh) and saves the
+// primary lambda, so V_kmin, A V_kmin, u, z and lambda_k leave unchanged.
+static int hi_solve_update(Solver &S, const nlrmm_batch &b, double *theta, const float *bvec,
+                           hipStream_t s)
+{
+    const int ell0 = S.ell;
+    float *const u0 = S.u;
+    double *const z0 = S.z;
+    const double lam_fix0 = S.cfg.lam_fix;
+    RC(k_copy_f64(S.sc + S_LAM, S.sc + S_LAMK, 1, s));
+    RC(k_copy_cols(u0, S.n, S.uh, S.n, 1, S.n, s));
+    S.u = S.uh;
+    S.z = S.zh;
+    S.cfg.lam_fix = S.cfg.lam_hi;
+    S.rho_ready = false;
+    int rc = NLRMM_OK;
+    const int nsolve = S.cfg.solves;
+    for (int t = 0; t < nsolve && !rc; ++t) {
+        const bool more = t < nsolve - 1;
+        rc = projected_solve(S, s, more ? &b : nullptr, more ? bvec : nullptr);
+        if (!rc && more) rc = expand(S, b, S.thk, bvec, s);
+    }
+    if (!rc && S.cfg.param_update == 1) rc = gn_update(S, b, theta, bvec, s);
+    if (!rc && S.cfg.param_update == 2) {
+        // compressed basis of this solve into Vtmp; VarPro rebuilds A V_hat itself
+        const int kmin = S.cfg.kmin;
+        rc = k_compress_eig(S.GA, S.GP, S.ld, S.sc + S_LAM, S.ell, kmin, S.z, S.T, kmin, S.zt,
+                            S.kout, S.status, s);
+        if (!rc)
+            rc = k_block_update(S.V, S.n, S.ell, S.T, kmin, kmin, S.n, S.Vtmp, S.n, s,
+                                S.cfg.compress_precision);
+        if (!rc) {
+            float *const V0 = S.V;
+            S.V = S.Vtmp;
+            S.ell = kmin;
+            rc = varpro_update(S, b, theta, bvec, s);
+            S.V = V0;
+        }
+    }
+    S.u = u0;
+    S.z = z0;
+    S.cfg.lam_fix = lam_fix0;
+    S.ell = ell0;
+    S.rho_ready = false;
+    if (rc) return rc;
+    return k_copy_f64(S.sc + S_LAMK, S.sc + S_LAM, 1, s);
+}
+
 static int solver_outer(Solver &S, const nlrmm_batch &b, double *theta, const float *bvec,
                         double delta, hipStream_t s)
 {
@@ -378,8 +433,12 @@ static int solver_outer(Solver &S, const nlrmm_batch &b, double *theta, const fl
         if (more) RC(expand(S, b, S.thk, bvec, s));
     }
     RC(compress(S, b, s));
-    if (S.cfg.param_update == 1) RC(gn_update(S, b, theta, bvec, s));
-    if (S.cfg.param_update == 2) RC(varpro_update(S, b, theta, bvec, s));
+    if (S.cfg.lam_hi > 0.0) {
+        RC(hi_solve_update(S, b, theta, bvec, s));
+    } else {
+        if (S.cfg.param_update == 1) RC(gn_update(S, b, theta, bvec, s));
+        if (S.cfg.param_update == 2) RC(varpro_update(S, b, theta, bvec, s));
+    }
     // weights from u_{k+1} (formed inside the residual); residual with the old operator H_k;
     // project out; append
     RC(mm_residual(S, b, S.thk, S.ell, bvec, s, true));
@@ -452,6 +511,7 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
     if (c.kmin + c.solves > c.kmax + 1 || c.solves < 1) return NLRMM_ESHAPE;
     if (c.armijo_trials < 0 || c.armijo_trials > 32 || c.maxiter_p < 0) return NLRMM_EINVAL;
     if (!(c.eps > 0.0) || !(c.tau > 0.0)) return NLRMM_EINVAL;
+    if (c.lam_hi > 0.0 && !(c.lam_hi < HUGE_VAL)) return NLRMM_EINVAL;
     if (c.param_update < 0 || c.param_update > 2) return NLRMM_ENOTSUP;
     if (c.gram_precision < 0 || c.gram_precision > 2) return NLRMM_ENOTSUP;
     if (c.compress_precision != 0 && c.compress_precision != 2) return NLRMM_ENOTSUP;
@@ -473,6 +533,7 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
     if ((rc = S->alloc(&S->V, (size_t)S->kcap * S->n)) ||
         (rc = S->alloc(&S->AV, (size_t)S->kcap * S->mmax)) ||
         (rc = S->alloc(&S->Vtmp, (size_t)c.kmin * big)) || (rc = S->alloc(&S->u, S->n)) ||
+        (rc = S->alloc(&S->uh, S->n)) || (rc = S->alloc(&S->zh, S->ld)) ||
         (rc = S->alloc(&S->r, S->n)) || (rc = S->alloc(&S->rho, S->mmax)) ||
         (rc = S->alloc(&S->w, npsi_max)) || (rc = S->alloc(&S->GA, S->ld * S->ld)) ||
         (rc = S->alloc(&S->GP, S->ld * S->ld)) || (rc = S->alloc(&S->rb, S->ld)) ||

@@ -35,6 +35,7 @@ class Config:
     temporal: int = 0
     gram_precision: int = 0      # 0 FP64, 1 FP32 MFMA, 2 BF16 MFMA
     compress_precision: int = 0  # compression basis products: 0 FP32 (FP64 accumulate), 2 BF16 MFMA
+    lam_hi: float = 0.0          # > 0: high-regularisation solve feeding the parameter update
 
     def struct(self) -> SolverCfg:
         return SolverCfg(**dataclasses.asdict(self))

@@ -176,7 +176,8 @@ def test_gks_expand_and_compress_match_oracle():
     assert rel(AVd[:kmin].cpu().numpy().astype(np.float64).T, AVn @ (Vold.T @ Vn)) <= 1e-5
 
 
-def run_pair(key, N=None, outer=None, kmax=None, trace=False, gram_precision=0):
+def run_pair(key, N=None, outer=None, kmax=None, trace=False, gram_precision=0, lam_hi=None,
+             gn="altmin"):
     wl = synth.WORKLOADS[key]
     inst = synth.draw(wl, N=N)
     N = inst.x_true.shape[-1]
@@ -185,7 +186,7 @@ def run_pair(key, N=None, outer=None, kmax=None, trace=False, gram_precision=0):
     geo = M.Geometry(N=N, nb=wl.nb, view_off=inst.view_off)
     x64 = inst.x_true.reshape(-1)
     b_ora, e_ora = M.make_data(geo, x64, inst.theta_true, inst.g, wl.noise)
-    cfg = M.Config(kmin=wl.kmin, kmax=kmax, eps=wl.eps)
+    cfg = M.Config(kmin=wl.kmin, kmax=kmax, eps=wl.eps, lam_hi=lam_hi, gn=gn)
     # GPU data: own projector, same noise direction
     g = ops.geom(N, wl.nb)
     x32 = inst.x_true.astype(np.float32)
@@ -195,7 +196,9 @@ def run_pair(key, N=None, outer=None, kmax=None, trace=False, gram_precision=0):
     b_gpu = dev((bex + e).astype(np.float32), torch.float32)
     th = dev(inst.theta_nom, torch.float64)
     sol = Solver(g, 1, geo.V, Config(kmin=wl.kmin, kmax=kmax, eps=wl.eps,
-                                     gram_precision=gram_precision))
+                                     gram_precision=gram_precision,
+                                     lam_hi=lam_hi if lam_hi is not None else 0.0,
+                                     param_update={"altmin": 1, "varpro": 2}[gn]))
     sol.init(th, b_gpu)
     ora_log = []
     st = M.init_state(geo, inst.theta_nom, b_ora, cfg)
@@ -224,6 +227,19 @@ def test_loop_parity_c1(gram_precision):
     out, rre = run_pair("c1", trace=True, gram_precision=gram_precision)
     k, du, dth, *_ = out[-1]
     print(f"c1 final: u rel diff {du:.3e}, theta max diff {dth:.3e} rad, oracle RRE {rre:.4f}")
+    assert du <= 1e-3
+    assert dth <= 1e-4
+
+
+@pytest.mark.parametrize("gn", ["altmin", "varpro"])
+def test_loop_parity_c1_high_regularisation(gn):
+    """The optional high-regularisation solve (Section 4.3, lam_hi = 3e-3, about twice the DP
+    lambda of this workload): 8 outer iterations of the c1 workload, AltMin or VarPro angle
+    update on u_hat, against the oracle."""
+    out, rre = run_pair("c1", outer=8, trace=True, lam_hi=3e-3, gn=gn)
+    k, du, dth, *_ = out[-1]
+    print(f"c1 lam_hi {gn}: u rel diff {du:.3e}, theta max diff {dth:.3e} rad, "
+          f"oracle RRE {rre:.4f}")
     assert du <= 1e-3
     assert dth <= 1e-4
 

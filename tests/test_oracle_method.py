@@ -5,6 +5,7 @@ path, the majorant properties of Section 3.1, the descent property of the
 image update with lambda fixed, quadratic convergence of Gauss-Newton on a
 zero-residual problem, and finite differences of the VarPro reduced objective.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -286,3 +287,56 @@ def test_altmin_reduces_angle_error_on_small_problem():
     e0 = np.linalg.norm(th_nom - th_true)
     assert np.linalg.norm(st.theta - th_true) < 0.6 * e0
     assert np.linalg.norm(st.V.T @ st.V - np.eye(st.V.shape[1])) < 1e-10
+
+
+def test_hi_solve_matches_dense_fixed_lambda_steps():
+    """High-regularisation solve (Section 4.3): from a compressed basis V and u in its span,
+    two fixed-lambda MM-GKS steps written out with dense A and Psi (normal equations of the
+    reduced problem, residual with the step's weights, two Gram-Schmidt passes); the primary
+    state is left as it was."""
+    geo, x, th, _, b, _ = small_problem(N=12, nb=19, V=10)
+    A, _ = P.dense(geo.N, geo.nb, th)
+    Psi = dense_psi(geo)
+    lam, eps = 0.3, 1e-2
+    cfg = M.Config(kmin=3, kmax=6, solves=2, eps=eps, lam_hi=lam, gn="altmin")
+    rng = np.random.default_rng(8)
+    V, _ = np.linalg.qr(rng.standard_normal((geo.n, cfg.kmin)))
+    u0 = V @ rng.standard_normal(cfg.kmin)
+    st = M.State(V=V.copy(), AV=A @ V, PV=Psi @ V, u=u0.copy(), theta=th.copy())
+    hs = M.hi_solve(geo, th, st, b, cfg)
+
+    def wts(u):
+        return 1.0 / np.sqrt((Psi @ u) ** 2 + eps ** 2)
+
+    def solve(B, w):
+        AB, PB = A @ B, Psi @ B
+        return np.linalg.solve(AB.T @ AB + lam * PB.T @ (w[:, None] * PB), AB.T @ b)
+
+    w0 = wts(u0)
+    u1 = V @ solve(V, w0)
+    r = A.T @ (A @ u1 - b) + lam * Psi.T @ (w0 * (Psi @ u1))
+    for _ in range(2):
+        r = r - V @ (V.T @ r)
+    V2 = np.column_stack([V, r / np.linalg.norm(r)])
+    u2 = V2 @ solve(V2, wts(u1))
+    assert np.linalg.norm(hs.u - u2) <= 1e-9 * np.linalg.norm(u2)
+    assert hs.lam == lam and hs.V.shape[1] == cfg.kmin + 1
+    assert np.array_equal(st.V, V) and np.array_equal(st.u, u0)
+
+
+def test_hi_solve_leaves_primary_trajectory():
+    """With the angles fixed, the high-regularisation solve changes nothing the outer iteration
+    carries (its image only feeds the parameter update), and its image is smoother (smaller
+    total variation) than the primary one for lam_hi well above the DP lambda."""
+    geo, x, th_nom, _, b, e = small_problem(N=16, nb=23, V=14)
+    delta = np.linalg.norm(e)
+    base = M.Config(kmin=3, kmax=10, gn="none")
+    st0 = M.run(geo, b, delta, th_nom, base, 3)
+    hi = dataclasses.replace(base, lam_hi=100.0 * st0.lam)
+    st1 = M.run(geo, b, delta, th_nom, hi, 3)
+    assert np.array_equal(st0.u, st1.u) and np.array_equal(st0.V, st1.V)
+    assert st0.lam == st1.lam
+    uh = st1.log[-1]["u_hat"]
+    assert uh is not None and st0.log[-1]["u_hat"] is None
+    tv = lambda u: float(np.sum(np.abs(M.psi(geo, u))))   # noqa: E731
+    assert tv(uh) < tv(st1.u)
