@@ -16,6 +16,10 @@ Also reported:
   * Gsamples/s of the three operators at the shape of every workload (64x64 up to
     2048x2048 / 1440 views, and one 22-view block of the streaming workload);
   * outer it/s of VarPro NL-RMM-GKS on the 512x512 / 720-view workload;
+  * ms per forward + backward of the autograd data loss at that workload;
+  * outer it/s of the 256x256 iteration under each precision policy (FP64 Grams, FP32
+    matrix-core Grams, BF16 matrix-core Grams and compression products);
+  * ms per block of streaming NL-RMM-GKS at 2048x2048 / 1440 views in 64 blocks;
   * the FP64 oracle timed on a bounded sample on the host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-dynamic]
@@ -254,6 +258,102 @@ def varpro_leg(torch, ops, synth, Config, Solver, steps, warmup, gram_precision)
                         f"warm-up + {steps} timed outer iterations"}
 
 
+def autograd_leg(torch, ops, synth, reps):
+    """ms per forward + backward of the data loss 1/2 ||A(theta) x - b||^2 through the
+    autograd Function (gradients for x and theta) at the 512x512 / 720-view workload."""
+    from paper_2605_06336_amd import autograd as AG
+    wl = synth.WORKLOADS["c3"]
+    inst = synth.draw(wl, with_image=False)
+    g = ops.geom(wl.N, wl.nb)
+    dev = torch.device("cuda", 0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    x = torch.rand((1, wl.N, wl.N), generator=gen, device=dev, dtype=torch.float32)
+    b = torch.randn((wl.n_views, wl.nb), generator=gen, device=dev, dtype=torch.float32)
+    th0 = torch.as_tensor(inst.theta_true, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        xr = x.clone().requires_grad_(True)
+        th = th0.clone().requires_grad_(True)
+        y = AG.project(xr, th, g)
+        loss = 0.5 * ((y.view(wl.n_views, wl.nb) - b) ** 2).sum()
+        loss.backward()
+        return xr.grad, th.grad
+
+    step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"ms_forward_backward": round(ms, 4),
+            "workload": "c3 shape: 512x512, 720 views, 725 bins; loss 1/2||A(theta)x - b||^2, "
+                        "gradients for x (backprojection) and theta (fused per-view <D, g>)"}
+
+
+def precision_leg(torch, ops, synth, Config, Solver, steps, warmup):
+    """Outer it/s of the c2 iteration under each precision policy of the Krylov side."""
+    wl = synth.WORKLOADS["c2"]
+    inst = synth.draw(wl)
+    g = ops.geom(wl.N, wl.nb)
+    x32, th_true, b, delta = make_data(torch, ops, inst, wl, g)
+    stream = torch.cuda.current_stream()
+    x_true = inst.x_true.reshape(-1)
+    out = {}
+    for name, gp, cp in (("fp64_grams", 0, 0), ("fp32_mfma_grams", 1, 0),
+                         ("bf16_mfma_grams_and_compression", 2, 2)):
+        theta = torch.as_tensor(inst.theta_nom.copy(), device="cuda")
+        sol = Solver(g, 1, wl.n_views, Config(kmin=wl.kmin, kmax=wl.kmax, eps=wl.eps,
+                                              gram_precision=gp, compress_precision=cp))
+        sol.init(theta, b)
+        for _ in range(warmup):
+            sol.outer(theta, b, delta)
+        ms = timed_steps(torch, lambda: sol.outer(theta, b, delta), steps, stream,
+                         f"c2 {name}")
+        u, _, _ = sol.read()
+        torch.cuda.synchronize()
+        rre = float(np.linalg.norm(u.cpu().numpy() - x_true) / np.linalg.norm(x_true))
+        sol.close()
+        out[name] = {"outer_it_s": round(1000.0 / ms, 4), "rre": round(rre, 5)}
+    return out
+
+
+def streaming_leg(torch, ops, synth, Config, steps):
+    """ms per block of s-NL-RMM-GKS at the full streaming shape (2048x2048, 1440 views in 64
+    blocks of 22-23, 2897 bins, kmax 50, BF16 Grams and compression products).  The image is
+    random (timing at fixed iteration counts does not depend on it)."""
+    from paper_2605_06336_amd.streaming import Streaming
+    wl = synth.WORKLOADS["c5"]
+    inst = synth.draw(wl, with_image=False)
+    g = ops.geom(wl.N, wl.nb)
+    dev = torch.device("cuda", 0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    x = torch.rand((1, 1, wl.N, wl.N), generator=gen, device=dev, dtype=torch.float32)
+    bex = ops.project(x, torch.as_tensor(inst.theta_true, device=dev), g).cpu().numpy()
+    bex = bex.reshape(-1).astype(np.float64)
+    e = wl.noise * np.linalg.norm(bex) * inst.g / np.linalg.norm(inst.g)
+    cfg = Config(kmin=wl.kmin, kmax=wl.kmax, eps=wl.eps, gram_precision=2, compress_precision=2)
+    st = Streaming(g, inst.blocks, cfg)
+    st.load(inst.theta_nom, bex + e, e)
+    st.init()
+    st.run(1, max_blocks=1)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ms = timed_steps(torch, lambda: st.solver.outer(*st._block(1), st.deltas[1]), steps, stream,
+                     "c5 block")
+    st.solver.close()
+    return {"ms_per_block": round(ms, 3), "blocks_per_pass": len(inst.blocks),
+            "pass_s_estimate": round(ms * len(inst.blocks) / 1000.0, 3),
+            "workload": "c5 shape: 2048x2048, 1440 views in 64 blocks, 2897 bins, kmax 50, "
+                        "BF16 Grams and compression products; random image"}
+
+
 def dynamic_leg(torch, ops, synth, Config, OuterGraph, Solver, steps, warmup, gram_precision):
     """Outer it/s of the 32-frame dynamic workload: batched + graph replay vs plain."""
     wl = synth.WORKLOADS["c4"]
@@ -372,11 +472,14 @@ def main():
         dyn = dynamic_leg(torch, ops, synth, Config, OuterGraph, Solver, max(3, args.steps // 2),
                           2, args.gram_precision)
 
-    per_workload = varpro = None
+    per_workload = varpro = autograd_r = precision = streaming = None
     if not args.no_workloads:
         per_workload = workload_operators(torch, ops, metrics, synth, max(3, args.reps // 4))
         varpro = varpro_leg(torch, ops, synth, Config, Solver, max(3, args.steps // 2), 2,
                             args.gram_precision)
+        autograd_r = autograd_leg(torch, ops, synth, max(3, args.reps // 2))
+        precision = precision_leg(torch, ops, synth, Config, Solver, max(3, args.steps // 2), 2)
+        streaming = streaming_leg(torch, ops, synth, Config, 3)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -426,6 +529,9 @@ def main():
         "batched_vs_plain": dyn,
         "operators_by_workload": per_workload,
         "varpro_c3": varpro,
+        "autograd_c3": autograd_r,
+        "precision_policy_c2": precision,
+        "streaming_c5": streaming,
         "roofline": roofline,
         "roofline_backproject": roofline_bwd,
         "cpu_baseline": cpu,

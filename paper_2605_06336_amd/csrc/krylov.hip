@@ -210,6 +210,7 @@ typedef short s16x4 __attribute__((ext_vector_type(4)));
 constexpr int MP = 64;            // pixels per chunk
 constexpr int MRMAX = 3 * MP;     // rows per chunk (dx, dy and, with frame differences, dt)
 constexpr int MLDR = MRMAX + 1;   // LDS column stride (floats, odd: conflict-free columns)
+constexpr int MLDH = MRMAX + 4;   // BF16 column stride (shorts; 8-byte units odd)
 
 __device__ __forceinline__ short bf16_rne(float f)
 {
@@ -233,7 +234,11 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
                                                        double *__restrict__ part,
                                                        const float *__restrict__ u, float e2)
 {
-    __shared__ __align__(16) float sB[64][MLDR];
+    // the chunk's weighted differences, column-major: FP32, or BF16 rounded once at staging
+    // (four consecutive rows of a column are then one 8-byte MFMA operand)
+    using Elem = typename std::conditional<BF16, short, float>::type;
+    constexpr int LD = BF16 ? MLDH : MLDR;
+    __shared__ __align__(16) Elem sB[64][LD];
     const TVGeo g = tvgeo(nx, ny, F, temporal);
     const int KIND = g.temporal ? 3 : 2;
     const int MR = KIND * MP;
@@ -243,9 +248,9 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
     const int lane = tid & 63, wv = tid >> 6;
     const int pc = lane, cg = wv;          // staging: pixel of the chunk, column group
     // padded columns stay zero
-    for (int t = tid; t < 64 * MLDR; t += BLK) {
-        const int c = t / MLDR;
-        if (c >= ell) sB[c][t - c * MLDR] = 0.0f;
+    for (int t = tid; t < 64 * LD; t += BLK) {
+        const int c = t / LD;
+        if (c >= ell) sB[c][t - c * LD] = Elem(0);
     }
     // this wave's tile and row slice
     const bool single = ell <= 32;
@@ -299,10 +304,17 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
             for (int u = 0; u < 4; ++u) {
                 const int c = c0 + u * (BLK / 64);
                 if (c < ell) {
-                    float *col = &sB[c][KIND * pc];
-                    col[0] = w0 * (x1[u] - x0[u]);
-                    col[1] = w1 * (x2[u] - x0[u]);
-                    if (KIND == 3) col[2] = w2 * (x3[u] - x0[u]);
+                    Elem *col = &sB[c][KIND * pc];
+                    const float d0 = w0 * (x1[u] - x0[u]), d1 = w1 * (x2[u] - x0[u]);
+                    if constexpr (BF16) {
+                        col[0] = bf16_rne(d0);
+                        col[1] = bf16_rne(d1);
+                        if (KIND == 3) col[2] = bf16_rne(w2 * (x3[u] - x0[u]));
+                    } else {
+                        col[0] = d0;
+                        col[1] = d1;
+                        if (KIND == 3) col[2] = w2 * (x3[u] - x0[u]);
+                    }
                 }
             }
         }
@@ -313,15 +325,12 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
             for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
             const int ca = 32 * ti + (lane & 31), cb = 32 * tj + (lane & 31);
             const int kbeg = (MR * sl) / nsl, kend = (MR * (sl + 1)) / nsl;
-            if (BF16) {
+            if constexpr (BF16) {
+                // row slices are multiples of 8 (MR in {128, 192}, split in 1 or 4 parts)
                 for (int k0 = kbeg; k0 < kend; k0 += 8) {
-                    s16x4 av, bv;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int row = k0 + 4 * (lane >> 5) + q;
-                        av[q] = bf16_rne(row < kend ? sB[ca][row] : 0.0f);
-                        bv[q] = bf16_rne(row < kend ? sB[cb][row] : 0.0f);
-                    }
+                    const int row = k0 + 4 * (lane >> 5);
+                    const s16x4 av = *reinterpret_cast<const s16x4 *>(&sB[ca][row]);
+                    const s16x4 bv = *reinterpret_cast<const s16x4 *>(&sB[cb][row]);
                     acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
                 }
             } else {
@@ -340,6 +349,7 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
     if (single) {
         // the four row slices of tile (0,0) meet in LDS (the staging area is free after the
         // last chunk's barrier), summed in slice order
+        static_assert(sizeof(sB) >= 3 * 16 * 64 * sizeof(double), "staging too small");
         double *sacc = reinterpret_cast<double *>(&sB[0][0]);   // [3][16][64]
         if (wv > 0) {
 #pragma unroll
@@ -442,17 +452,47 @@ __global__ __launch_bounds__(BLK) void multidot_k(const float *__restrict__ X, i
         }
         return;
     }
+    // several elements per thread: 16-byte loads when every column is 16-byte aligned and
+    // n is a multiple of 4 (four times the bytes in flight per load)
+    const bool vec4 = (ldx % 4) == 0 && (n % 4) == 0 &&
+                      (reinterpret_cast<uintptr_t>(X) % 16) == 0 &&
+                      (reinterpret_cast<uintptr_t>(y) % 16) == 0 &&
+                      (z == nullptr || (reinterpret_cast<uintptr_t>(z) % 16) == 0);
     for (int i0 = 0; i0 < nout; i0 += GRP) {
         double acc[GRP];
 #pragma unroll
         for (int a = 0; a < GRP; ++a) acc[a] = 0.0;
-        for (int64_t e = (int64_t)blockIdx.x * BLK + tid; e < n; e += (int64_t)gridDim.x * BLK) {
-            const double ye = (double)y[e];
+        if (vec4) {
+            const int64_t n4 = n / 4, ld4 = ldx / 4;
+            const float4 *X4 = reinterpret_cast<const float4 *>(X);
+            const float4 *y4 = reinterpret_cast<const float4 *>(y);
+            const float4 *z4 = reinterpret_cast<const float4 *>(z);
+            for (int64_t e = (int64_t)blockIdx.x * BLK + tid; e < n4;
+                 e += (int64_t)gridDim.x * BLK) {
+                const float4 yv = y4[e];
 #pragma unroll
-            for (int a = 0; a < GRP; ++a) {
-                const int i = i0 + a;
-                if (i < nv) acc[a] = fma((double)X[(int64_t)i * ldx + e], ye, acc[a]);
-                else if (i == nv && z != nullptr) acc[a] = fma((double)z[e], ye, acc[a]);
+                for (int a = 0; a < GRP; ++a) {
+                    const int i = i0 + a;
+                    float4 xv = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (i < nv) xv = X4[(int64_t)i * ld4 + e];
+                    else if (i == nv && z != nullptr) xv = z4[e];
+                    double t = acc[a];
+                    t = fma((double)xv.x, (double)yv.x, t);
+                    t = fma((double)xv.y, (double)yv.y, t);
+                    t = fma((double)xv.z, (double)yv.z, t);
+                    acc[a] = fma((double)xv.w, (double)yv.w, t);
+                }
+            }
+        } else {
+            for (int64_t e = (int64_t)blockIdx.x * BLK + tid; e < n;
+                 e += (int64_t)gridDim.x * BLK) {
+                const double ye = (double)y[e];
+#pragma unroll
+                for (int a = 0; a < GRP; ++a) {
+                    const int i = i0 + a;
+                    if (i < nv) acc[a] = fma((double)X[(int64_t)i * ldx + e], ye, acc[a]);
+                    else if (i == nv && z != nullptr) acc[a] = fma((double)z[e], ye, acc[a]);
+                }
             }
         }
         block_reduce(i0, acc);

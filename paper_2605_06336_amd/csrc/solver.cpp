@@ -529,6 +529,14 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
     S->ld = S->kcap;
     S->nchunks = fwd_chunks(*geom);
     const int64_t big = S->n > S->mmax ? S->n : S->mmax;
+    // enough blocks for the inner products and the regulariser Gram to keep every CU busy on
+    // large images (a few elements per thread, 16 pixel chunks per Gram block); the defaults
+    // serve images up to 512x512
+    {
+        const int64_t md = (big + 1023) / 1024, gb = (S->n / 64 + 15) / 16;
+        S->md_blocks = (int)(md < 512 ? 512 : md > 2048 ? 2048 : md);
+        S->gram_blocks = (int)(gb < 256 ? 256 : gb > 2048 ? 2048 : gb);
+    }
     const int64_t npsi_max = (int64_t)nframes * 2 * geom->nx * geom->ny + (int64_t)nframes * geom->nx * geom->ny;
     if ((rc = S->alloc(&S->V, (size_t)S->kcap * S->n)) ||
         (rc = S->alloc(&S->AV, (size_t)S->kcap * S->mmax)) ||
