@@ -262,6 +262,7 @@ __global__ __launch_bounds__(BLK) void line_prefix_k(const double *__restrict__ 
 // blocks an XCD holds at once work on the same chunk of nearly the same angles, whose edges
 // cross nearly the same pack entries.
 constexpr int FWD_XCDS = 8, FWD_VGROUP = 16;
+constexpr int FWD_UNROLL = 4;   // pack entries in flight per step of the forward walk
 __device__ __forceinline__ void fwd_block_item(int64_t b, int64_t T, int nchunks, int64_t &v,
                                                int &q)
 {
@@ -322,8 +323,27 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
     const int c0 = blockIdx.y * NC;
     const int nc = min(NC, a.ncols - c0);
     const int f = frame_of(a.view_off, a.nframes, v);
-    const double th = a.tdir != nullptr ? a.theta[v] + a.talpha[0] * a.tdir[v] : a.theta[v];
-    const ViewC w = make_view(th, a.d);
+    // The view constants, each edge's line range and the wave union of the ranges are the same
+    // for every wave of the block (the waves share the block's 64 edges): wave 0 forms them
+    // and hands them to the others through LDS.
+    struct Shared {
+        ViewC w;
+        double inv_step;
+        int la[64], lb[64];
+        int WA, WB;
+    };
+    __shared__ Shared sh;
+    const bool first = FSEG == 1 || seg == 0;
+    ViewC w;
+    if (first) {
+        const double th = a.tdir != nullptr ? a.theta[v] + a.talpha[0] * a.tdir[v] : a.theta[v];
+        w = make_view(th, a.d);
+        if (FSEG > 1 && lane == 0) sh.w = w;
+    }
+    if (FSEG > 1) {
+        __syncthreads();
+        if (!first) w = sh.w;
+    }
     const int64_t j = (int64_t)q * BINS + lane;
 
     const bool steep = w.steep != 0;
@@ -337,7 +357,11 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
     const double tm = steep ? -w.sn : w.cs;
     const bool asc = sm > 0.0;
     const double step = a.d * fabs(sm);
-    const double inv_step = 1.0 / step;
+    double inv_step;
+    if (first) {
+        inv_step = 1.0 / step;
+        if (FSEG > 1 && lane == 0) sh.inv_step = inv_step;
+    }
     const double cw0 = asc ? (minor0 + 0.5 * a.d) * sm : (minor0 + (nminor - 0.5) * a.d) * sm;
     // descending walks read the mirrored packs, so every walk advances through its pack
     const PackEntry *pack = steep ? (asc ? a.rowpack : a.rowpack_m)
@@ -360,7 +384,8 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
     const bool live = j <= a.nb;
     const double e = edge_coord(a.s0, a.ds, j);
     int la = nlines, lb = -1;   // lanes without an edge take no part in the union
-    if (live) {
+    int WA, WB;
+    if (first && live) {
         if (sl == 0.0) {
             la = 0;
             lb = nlines - 1;
@@ -378,10 +403,31 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
             lb = min(max((int)ceil(hi) + 1, -1), nlines - 1);
         }
     }
-    int WA = la, WB = lb;
-    for (int off = 32; off > 0; off >>= 1) {
-        WA = min(WA, __shfl_xor(WA, off, 64));
-        WB = max(WB, __shfl_xor(WB, off, 64));
+    if (first) {
+        WA = la;
+        WB = lb;
+        for (int off = 32; off > 0; off >>= 1) {
+            WA = min(WA, __shfl_xor(WA, off, 64));
+            WB = max(WB, __shfl_xor(WB, off, 64));
+        }
+        if (FSEG > 1) {
+            sh.la[lane] = la;
+            sh.lb[lane] = lb;
+            if (lane == 0) {
+                sh.WA = WA;
+                sh.WB = WB;
+            }
+        }
+    }
+    if (FSEG > 1) {
+        __syncthreads();
+        if (!first) {
+            inv_step = sh.inv_step;
+            la = sh.la[lane];
+            lb = sh.lb[lane];
+            WA = sh.WA;
+            WB = sh.WB;
+        }
     }
     WA = __builtin_amdgcn_readfirstlane(WA);
     WB = __builtin_amdgcn_readfirstlane(WB);
@@ -392,11 +438,10 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
         const int sb = len > 0 ? WA + (len * (seg + 1)) / FSEG - 1 : WB;
         // Walk position of the edge on line L, in pixel steps (walk order):
         // q(L) = (e - lc(L) sl - wo - cw0) / step, linear in L.  The first pixel the edge
-        // straddles is K0 = floor(q) + 1, clamped to [-1, n]; with r = q + 2 the pack entry
-        // index K0 + 2 = 1 + clamp(trunc(r), 0, n + 1) (truncation equals floor wherever the
-        // clamp does not bind).  The offsets of the edge from the centres of pixels K0 and
-        // K0 + 1 are va = wo + (q - K0) step and va - step; every clamp argument of Phi is
-        // an FMA of the fractional walk position r - (K0 + 1).
+        // straddles is K0 = floor(q) + 1; with r = q + 2 clamped to [0, n + 1] the pack entry
+        // index is K0 + 2 = 1 + trunc(r) and r - trunc(r) its fraction.  The offsets of the
+        // edge from the centres of pixels K0 and K0 + 1 are va = wo + (q - K0) step and
+        // va - step; every clamp argument of Phi is an FMA of that fraction.
         const double dq = -a.d * sl * inv_step;
         double r = sa <= sb ? (__dsub_rn(e, __dmul_rn(pix_coord(line0, a.d, sa), sl)) - w.wo -
                                cw0) * inv_step + 2.0
@@ -412,9 +457,18 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
         const PackEntry *pline = pack + img0 * pstride + (int64_t)sa * (nminor + 3) + 1;
         auto walk = [&](auto ascending) __attribute__((always_inline)) {
             constexpr bool ASC = decltype(ascending)::value;
-            for (int L = sa; L <= sb; ++L, r += dq, pline += nminor + 3) {
-                const int K1 = min(max((int)r, 0), nminor + 1);   // K0 + 1
-                const float dr = (float)(r - (double)K1);
+            // Entry of line L at walk position rl: clamping the position itself is exact
+            // (beyond [0, n + 1] the entry's pixels are padding, or the edge lies past the
+            // footprint of pixel 0); K1 = K0 + 1 and the fraction dr.
+            auto locate = [&](double rl, int &K1, float &dr) __attribute__((always_inline)) {
+                const double rc = fmin(fmax(rl, 0.0), (double)(nminor + 1));
+                K1 = (int)rc;
+                dr = (float)__builtin_amdgcn_fract(rc);
+            };
+            // x * Phi / h (and the chord moments) of the two straddled pixels of a located
+            // line into the FP32 sums fF / fM of its pair of lines; the prefix into accP
+            auto apply = [&](int L, int K1, float dr, const PackEntry (&E)[NC], float (&fF)[NC],
+                             float (&fM)[NC]) __attribute__((always_inline)) {
                 float pa = 0.f, pb = 0.f, ma = 0.f, mb = 0.f;
                 if (PROJ) {
                     pa = phi_h(fmaf(dr, stepf, c1a), fmaf(dr, stepf, c2a), fmaf(dr, stepf, c3a),
@@ -436,18 +490,70 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
                     ma = La * ((float)(tb + pix_coord(minor0, a.d, ka) * tm) + mua);
                     mb = Lb * ((float)(tb + pix_coord(minor0, a.d, kb) * tm) + mub);
                 }
-                const PackEntry *pe = pline + (unsigned)K1;
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
-                    if (c < nc) {
-                        const PackEntry E = pe[c * cstride * pstride];
+                    if (c == 0 || c < nc) {
                         if (PROJ) {
-                            accP[c] += E.P;
-                            accF[c] += (double)fmaf(E.b, pb, E.a * pa);
+                            accP[c] += E[c].P;
+                            fF[c] = fmaf(E[c].b, pb, fmaf(E[c].a, pa, fF[c]));
                         }
-                        if (MOM) accM[c] += (double)fmaf(E.b, mb, E.a * ma);
+                        if (MOM) fM[c] = fmaf(E[c].b, mb, fmaf(E[c].a, ma, fM[c]));
                     }
                 }
+            };
+            auto fetch = [&](const PackEntry *pl, int K1, PackEntry (&E)[NC])
+                             __attribute__((always_inline)) {
+                const PackEntry *pe = pl + (unsigned)K1;
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    if (c == 0 || c < nc) E[c] = pe[c * cstride * pstride];   // nc >= 1
+            };
+            auto flush = [&](const float (&fF)[NC], const float (&fM)[NC])
+                             __attribute__((always_inline)) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    if (PROJ) accF[c] += (double)fF[c];
+                    if (MOM) accM[c] += (double)fM[c];
+                }
+            };
+            const int lstride = nminor + 3;
+            int L = sa;
+            // U lines per step, every load issued before any line's arithmetic (the loads
+            // wait on L2; several in flight hide that latency); U * NC entries per step
+            constexpr int U = FWD_UNROLL / NC > 1 ? FWD_UNROLL / NC : 1;
+            for (; L + U - 1 <= sb; L += U) {
+                double rr[U];
+                int K1[U];
+                float dr[U];
+                PackEntry E[U][NC];
+                rr[0] = r;
+#pragma unroll
+                for (int u = 1; u < U; ++u) rr[u] = rr[u - 1] + dq;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    locate(rr[u], K1[u], dr[u]);
+                    fetch(pline + u * lstride, K1[u], E[u]);
+                }
+                float fF[NC], fM[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) fF[c] = fM[c] = 0.0f;
+#pragma unroll
+                for (int u = 0; u < U; ++u) apply(L + u, K1[u], dr[u], E[u], fF, fM);
+                flush(fF, fM);
+                r = rr[U - 1] + dq;
+                pline += U * lstride;
+            }
+            for (; L <= sb; ++L, r += dq, pline += lstride) {
+                int K1a;
+                float dra;
+                locate(r, K1a, dra);
+                PackEntry Ea[NC];
+                fetch(pline, K1a, Ea);
+                float fF[NC], fM[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) fF[c] = fM[c] = 0.0f;
+                apply(L, K1a, dra, Ea, fF, fM);
+                flush(fF, fM);
             }
         };
         if (asc) walk(std::true_type{});

@@ -36,7 +36,7 @@ struct Solver {
     int kcap = 0;   // kmax + 1 columns
     int ld = 0;     // Gram leading dimension
     int ell = 0;    // current number of basis columns (host bookkeeping)
-    int md_blocks = 512, gram_blocks = 256, nchunks = 1;
+    int md_blocks = 512, gram_blocks = 512, nchunks = 1;
     bool rho_ready = false;   // rho = A V z - b already formed for the next residual
     bool w_from_u = true;     // weights of u may be formed on the fly (false: caller's w)
     // device buffers
@@ -531,11 +531,11 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
     const int64_t big = S->n > S->mmax ? S->n : S->mmax;
     // enough blocks for the inner products and the regulariser Gram to keep every CU busy on
     // large images (a few elements per thread, 16 pixel chunks per Gram block); the defaults
-    // serve images up to 512x512
+    // serve images up to 512x512 (512 Gram blocks measured best at 256x256)
     {
         const int64_t md = (big + 1023) / 1024, gb = (S->n / 64 + 15) / 16;
         S->md_blocks = (int)(md < 512 ? 512 : md > 2048 ? 2048 : md);
-        S->gram_blocks = (int)(gb < 256 ? 256 : gb > 2048 ? 2048 : gb);
+        S->gram_blocks = (int)(gb < 512 ? 512 : gb > 2048 ? 2048 : gb);
     }
     const int64_t npsi_max = (int64_t)nframes * 2 * geom->nx * geom->ny + (int64_t)nframes * geom->nx * geom->ny;
     if ((rc = S->alloc(&S->V, (size_t)S->kcap * S->n)) ||
