@@ -264,6 +264,21 @@ void nlrmm_solver_destroy(nlrmm_solver *solver);
 int nlrmm_solver_init(nlrmm_solver *solver, const nlrmm_batch *batch, const double *theta,
                       const float *b, void *stream);
 
+/* Parameter initialisation by a coarse grid search over one global angle offset (the paper's
+ * experiments section, "Parameter initialization"): a Golub-Kahan basis V of ell0 vectors
+ * from b at the angles theta (the bidiagonalisation of nlrmm_solver_init), then for each
+ * candidate offset shifts[c] the residual of the reduced least-squares problem
+ * res2[c] = min_z ||A(theta + shifts[c]) V z - b||^2 (FP64 data Gram, Cholesky), and
+ * theta += shifts[best] with best the smallest residual (first index on ties).
+ * theta DEVICE [views], updated in place; shifts DEVICE [ncand] (radians); res2 DEVICE
+ * [ncand] or NULL (then ncand <= max_views); best DEVICE int32 or NULL.  1 <= ell0 <=
+ * min(kmax + 1, 56).  The solver's basis and image are left in an unspecified state: call
+ * nlrmm_solver_init at the chosen angles afterwards.  A rank-deficient basis leaves a
+ * candidate's residual at ||b||^2. */
+int nlrmm_solver_grid_search(nlrmm_solver *solver, const nlrmm_batch *batch, double *theta,
+                             const float *b, const double *shifts, int32_t ncand, int32_t ell0,
+                             double *res2, int32_t *best, void *stream);
+
 /* One outer iteration on the views of `batch` (all views, or one streaming block):
  * rebase A V = A(theta_k) V; Enlarge (solves projected solves, one append between
  * consecutive solves); Compress; UPDATE-PARAM (theta updated in place); weights from the

@@ -13,6 +13,8 @@ Each function follows the paper's algorithm in the paper's order:
   * UPDATE-PARAM ............. Alg. "update_param" (damped Gauss-Newton + Armijo)
   * VarPro ................... Section 4.2 eqs. "u_closed_form", "GN_system", supplementary
                                Alg. "update_varpro"
+  * grid-search start ........ experiments section, "Parameter initialization" (one
+                               global offset, reduced least squares on a GKB basis)
   * NL-RMM-GKS ............... Alg. "nl_rmmgks_two_solves", with the optional
                                high-regularisation solve of Section 4.3 (lam_hi)
   * s-NL-RMM-GKS ............. Alg. "s_nl_rmmgks_final"
@@ -435,6 +437,25 @@ def gn_varpro(geo: Geometry, theta, V, b, w, PV, lam, cfg: Config):
 # ----------------------------------------------------------------------------
 # drivers
 # ----------------------------------------------------------------------------
+def grid_search_shift(geo: Geometry, theta_nom, b, shifts, ell0: int = 10, V=None):
+    """Parameter initialisation of the experiments section ("Parameter initialization"): a
+    GKB basis V of ell0 vectors at the nominal geometry (or the given V); for every candidate
+    global offset s on a coarse grid, the reduced problem min_z ||H(theta_nom + s) V z - b||
+    (least squares, unregularised: ell0 is small); the candidate with the smallest data
+    residual (first on ties).  Returns (theta_nom + s_best, residuals^2, best index)."""
+    if V is None:
+        V = gkb_basis(geo, theta_nom, b, ell0)
+    res2 = []
+    for s in shifts:
+        AV = A_cols(geo, theta_nom + s, V)
+        z, *_ = np.linalg.lstsq(AV, b, rcond=None)
+        r = AV @ z - b
+        res2.append(float(r @ r))
+    res2 = np.array(res2)
+    best = int(np.argmin(res2))
+    return np.asarray(theta_nom) + shifts[best], res2, best
+
+
 def init_state(geo: Geometry, theta0, b, cfg: Config) -> State:
     """GKB basis of kmin+1 vectors at the starting angles, u0 = 0."""
     V = gkb_basis(geo, theta0, b, cfg.kmin + 1)

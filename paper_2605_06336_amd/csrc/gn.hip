@@ -156,6 +156,61 @@ __global__ void scale_into_k(const float *__restrict__ src, const double *__rest
     if (i < n) dst[i] = (float)((double)src[i] * inv);
 }
 
+
+// Residual of the reduced least-squares problem of one grid candidate:
+// min_z ||A V z - b||^2 = ||b||^2 - rb^T G^-1 rb with G = (A V)^T A V = L L^T and rb =
+// (A V)^T b, i.e. ||b||^2 - ||L^-1 rb||^2 (one thread; ell <= 56).  A non-positive pivot
+// (rank-deficient basis) leaves the candidate's residual at ||b||^2.
+__global__ void grid_residual_k(const double *__restrict__ G, int ldg,
+                                const double *__restrict__ rb, const double *__restrict__ bnorm2,
+                                int ell, double *__restrict__ res2)
+{
+    __shared__ double L[56][56];
+    __shared__ double y[56];
+    if (threadIdx.x != 0) return;
+    double fit = 0.0;
+    bool ok = true;
+    for (int i = 0; i < ell && ok; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            double sum = G[i * ldg + j];
+            for (int k = 0; k < j; ++k) sum -= L[i][k] * L[j][k];
+            if (i == j) {
+                if (!(sum > 0.0)) {
+                    ok = false;
+                    break;
+                }
+                L[i][i] = sqrt(sum);
+            } else {
+                L[i][j] = sum / L[j][j];
+            }
+        }
+        if (!ok) break;
+        double t = rb[i];
+        for (int k = 0; k < i; ++k) t -= L[i][k] * y[k];
+        y[i] = t / L[i][i];
+        fit += y[i] * y[i];
+    }
+    res2[0] = ok ? bnorm2[0] - fit : bnorm2[0];
+}
+
+// The smallest residual of the candidates (first index on ties) and theta_v += s_best.
+__global__ void grid_pick_k(const double *__restrict__ res2, int ncand,
+                            const double *__restrict__ shifts, double *__restrict__ theta,
+                            int64_t V, int *__restrict__ best)
+{
+    __shared__ int sbest;
+    if (threadIdx.x == 0) {
+        int k = 0;
+        for (int c = 1; c < ncand; ++c)
+            if (res2[c] < res2[k]) k = c;
+        sbest = k;
+        if (best != nullptr) best[0] = k;
+    }
+    __syncthreads();
+    const double sh = shifts[sbest];
+    for (int64_t v = threadIdx.x; v < V; v += blockDim.x) theta[v] += sh;
+}
+
 }  // namespace
 
 #define LAUNCH_OK (hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP)
@@ -196,6 +251,21 @@ int k_symmetrize(double *G, int ldg, int ell, hipStream_t s)
 int k_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s)
 {
     copy_f64_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, dst, n);
+    return LAUNCH_OK;
+}
+
+int k_grid_residual(const double *G, int ldg, const double *rb, const double *bnorm2, int ell,
+                    double *res2, hipStream_t s)
+{
+    if (ell < 1 || ell > 56) return NLRMM_ESHAPE;
+    grid_residual_k<<<1, 64, 0, s>>>(G, ldg, rb, bnorm2, ell, res2);
+    return LAUNCH_OK;
+}
+
+int k_grid_pick(const double *res2, int ncand, const double *shifts, double *theta, int64_t V,
+                int *best, hipStream_t s)
+{
+    grid_pick_k<<<1, 256, 0, s>>>(res2, ncand, shifts, theta, V, best);
     return LAUNCH_OK;
 }
 

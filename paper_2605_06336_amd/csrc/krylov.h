@@ -68,6 +68,10 @@ int k_armijo_check(const double *part_r, int64_t nparts, const double *alphas, i
 int k_gn_apply(double *theta, const double *dir, int64_t V, const double *sc,
                const int *accepted, int *status, hipStream_t s);
 int k_fill_f64(double *dst, int64_t n, double value, hipStream_t s);
+int k_grid_residual(const double *G, int ldg, const double *rb, const double *bnorm2, int ell,
+                    double *res2, hipStream_t s);
+int k_grid_pick(const double *res2, int ncand, const double *shifts, double *theta, int64_t V,
+                int *best, hipStream_t s);
 int k_fill_i32(int *dst, int64_t n, int value, hipStream_t s);
 int k_view_dots(const float *X, int64_t ldx, int k, const float *e, int nb, int64_t V, double *out,
                 hipStream_t s);

@@ -450,9 +450,9 @@ static int solver_outer(Solver &S, const nlrmm_batch &b, double *theta, const fl
 
 // Golub-Kahan bidiagonalisation from b (k right vectors, CGS2 on both sides); u = 0.
 static int solver_init(Solver &S, const nlrmm_batch &b, const double *theta, const float *bvec,
-                       hipStream_t s)
+                       hipStream_t s, int kvec = 0)
 {
-    const int k = S.cfg.kmin + 1;
+    const int k = kvec > 0 ? kvec : S.cfg.kmin + 1;
     const int64_t m = m_of(S, b);
     if (b.nviews > S.maxV) return NLRMM_ESHAPE;
     float *U = S.AV;   // left vectors stored where A V lives later
@@ -490,6 +490,32 @@ static int solver_init(Solver &S, const nlrmm_batch &b, const double *theta, con
     S.ell = k;
     RC(k_gemv(S.V, S.n, 1, S.z, 0.0, nullptr, 0.0, S.n, S.u, s));   // u = 0
     return NLRMM_OK;
+}
+
+// Parameter initialisation by a coarse grid search over a global angle offset (the
+// experiments section): a GKB basis of ell0 vectors from b at the nominal angles, then for
+// every candidate s_c the reduced least-squares residual min_z ||A(theta + s_c) V z - b||^2
+// (one multi-column projection at the shifted angles, the data Gram, a Cholesky), and
+// theta += s_best.
+static int grid_search(Solver &S, const nlrmm_batch &b, double *theta, const float *bvec,
+                       const double *shifts, int ncand, int ell0, double *res2, int *best,
+                       hipStream_t s)
+{
+    const int64_t V = b.nviews;
+    const int64_t m = m_of(S, b);
+    RC(solver_init(S, b, theta, bvec, s, ell0));
+    // trial-angle projections theta + shifts[c] * 1 of the basis, into the A V storage
+    RC(k_fill_f64(S.dir, V, 1.0, s));
+    for (int c = 0; c < ncand; ++c) {
+        FwdOptions o;
+        o.y = S.AV;
+        o.tdir = S.dir;
+        o.talpha = shifts + c;
+        RC(proj(S, b, ell0, S.V, theta, o, s));
+        RC(gram_from_scratch(S, ell0, m, bvec, s));
+        RC(k_grid_residual(S.GA, S.ld, S.rb, S.sc + S_BNORM2, ell0, res2 + c, s));
+    }
+    return k_grid_pick(res2, ncand, shifts, theta, V, best, s);
 }
 
 }  // namespace nlrmm
@@ -602,6 +628,23 @@ int nlrmm_solver_init(nlrmm_solver *S, const nlrmm_batch *batch, const double *t
     if (rc) return rc;
     if (batch->nframes != S->F) return NLRMM_ESHAPE;
     return solver_init(*S, *batch, theta, b, (hipStream_t)stream);
+}
+
+int nlrmm_solver_grid_search(nlrmm_solver *S, const nlrmm_batch *batch, double *theta,
+                             const float *b, const double *shifts, int32_t ncand, int32_t ell0,
+                             double *res2, int32_t *best, void *stream)
+{
+    if (!S || !theta || !b || !shifts) return NLRMM_EINVAL;
+    int rc = check_batch(batch);
+    if (rc) return rc;
+    if (batch->nframes != S->F) return NLRMM_ESHAPE;
+    if (ncand < 1 || ell0 < 1 || ell0 > S->kcap || ell0 > 56) return NLRMM_ESHAPE;
+    if (res2 == nullptr) {
+        if (ncand > S->maxV) return NLRMM_EINVAL;
+        res2 = S->gv;   // scratch of max_views doubles
+    }
+    return grid_search(*S, *batch, theta, b, shifts, ncand, ell0, res2, best,
+                       (hipStream_t)stream);
 }
 
 int nlrmm_solver_outer(nlrmm_solver *S, const nlrmm_batch *batch, double *theta, const float *b,

@@ -87,6 +87,23 @@ class Solver:
         check(_lib.lib().nlrmm_solver_init(self.h, ctypes.byref(bt), theta.data_ptr(),
                                            b.data_ptr(), self._stream()), "nlrmm_solver_init")
 
+    def grid_search(self, theta: torch.Tensor, b: torch.Tensor, shifts: torch.Tensor,
+                    ell0: int = 10, frames=None):
+        """Coarse grid search of one global angle offset (nlrmm_solver_grid_search): theta
+        (float64, device) is shifted in place by the best candidate; returns (res2 [ncand]
+        float64, best [1] int32) device tensors.  Call init() at the new angles afterwards."""
+        bt = ops._batch(frames, theta.numel())
+        shifts = shifts.to(device=theta.device, dtype=torch.float64).contiguous()
+        res2 = torch.empty(shifts.numel(), dtype=torch.float64, device=theta.device)
+        best = torch.empty(1, dtype=torch.int32, device=theta.device)
+        check(_lib.lib().nlrmm_solver_grid_search(self.h, ctypes.byref(bt), theta.data_ptr(),
+                                                  b.data_ptr(), shifts.data_ptr(),
+                                                  int(shifts.numel()), int(ell0),
+                                                  res2.data_ptr(), best.data_ptr(),
+                                                  self._stream()),
+              "nlrmm_solver_grid_search")
+        return res2, best
+
     def outer(self, theta: torch.Tensor, b: torch.Tensor, delta: float, frames=None) -> None:
         """One outer iteration; theta (float64, device) is updated in place."""
         bt = ops._batch(frames, theta.numel())

@@ -320,3 +320,42 @@ def test_compress_bf16_products(ell, kmin):
     assert rel(V2, V0) <= 3e-3 and rel(A2, A0) <= 3e-3 and rel(u2, u0) <= 3e-3
     assert rel(z2, z0) <= 1e-12
     assert rel(u0, V.astype(np.float64) @ z) <= 1e-5
+
+
+def test_grid_search_matches_oracle():
+    """Coarse grid search of one global offset (nlrmm_solver_grid_search) on the c1 workload
+    with its per-view angle errors plus a 0.8 degree offset: the reduced residual of every
+    candidate against the oracle (GKB basis of 10 vectors in both; the residual is ||b||^2
+    minus a fit of nearly equal size, so the bar is absolute: 1e-6 ||b||^2, FP32 basis
+    vectors), the same best candidate, and theta shifted by it."""
+    wl = synth.WORKLOADS["c1"]
+    inst = synth.draw(wl)
+    N = wl.N
+    geo = M.Geometry(N=N, nb=wl.nb, view_off=inst.view_off)
+    s_true = math.radians(0.8)
+    th_data = inst.theta_true + s_true
+    g = ops.geom(N, wl.nb)
+    x32 = inst.x_true.astype(np.float32)
+    bex = ops.project(dev(x32, torch.float32), dev(th_data, torch.float64),
+                      g).cpu().numpy().reshape(-1).astype(np.float64)
+    e = wl.noise * np.linalg.norm(bex) * inst.g / np.linalg.norm(inst.g)
+    b32 = (bex + e).astype(np.float32)
+    shifts = np.radians(np.arange(-2.0, 2.01, 0.25))
+    _, res_ora, best_ora = M.grid_search_shift(geo, inst.theta_nom, b32.astype(np.float64),
+                                               shifts, ell0=10)
+    sol = Solver(g, 1, geo.V, Config(kmin=wl.kmin, kmax=wl.kmax, eps=wl.eps))
+    th = dev(inst.theta_nom, torch.float64)
+    res2, best = sol.grid_search(th, dev(b32, torch.float32), dev(shifts, torch.float64), 10)
+    torch.cuda.synchronize()
+    sol.close()
+    res2 = res2.cpu().numpy()
+    bb = float(b32.astype(np.float64) @ b32.astype(np.float64))
+    err = float(np.max(np.abs(res2 - res_ora))) / bb
+    order = np.sort(res_ora)
+    print(f"grid search: max |res2 diff| / ||b||^2 {err:.2e}, best gpu {int(best.cpu()[0])} "
+          f"ora {best_ora} ({math.degrees(shifts[best_ora]):+.2f} deg), runner-up gap "
+          f"{(order[1] - order[0]) / bb:.2e}", flush=True)
+    assert err <= 1e-6
+    if (order[1] - order[0]) / bb > 1e-5:
+        assert int(best.cpu()[0]) == best_ora
+    assert np.array_equal(th.cpu().numpy(), inst.theta_nom + shifts[int(best.cpu()[0])])

@@ -340,3 +340,35 @@ def test_hi_solve_leaves_primary_trajectory():
     assert uh is not None and st0.log[-1]["u_hat"] is None
     tv = lambda u: float(np.sum(np.abs(M.psi(geo, u))))   # noqa: E731
     assert tv(uh) < tv(st1.u)
+
+
+def test_grid_search_offset_sign_and_residual():
+    """Coarse grid search of the experiments section on a basis that contains the image:
+    noise-free data from the angles offset by s*, so the reduced residual vanishes at s*
+    (and only there on the grid), and the returned angles are the nominal ones plus s*.
+    (With the GKB basis at the nominal angles a global offset of a parallel-beam operator is
+    an image rotation that the basis absorbs; see the next test for that basis.)"""
+    geo, x, th_nom, _, _, _ = small_problem(N=16, nb=23, V=20)
+    s_true = math.radians(1.5)
+    b = M.A(geo, th_nom + s_true, x)
+    rng = np.random.default_rng(4)
+    V, _ = np.linalg.qr(np.column_stack([x, rng.standard_normal((geo.n, 5))]))
+    shifts = np.radians(np.arange(-3.0, 3.01, 0.5))
+    th0, res2, best = M.grid_search_shift(geo, th_nom, b, shifts, V=V)
+    assert shifts[best] == s_true
+    assert np.array_equal(th0, th_nom + s_true)
+    assert res2[best] <= 1e-20 * (b @ b)
+    assert np.min(np.delete(res2, best)) > 1e-8 * (b @ b)
+
+
+def test_grid_search_residual_bounds():
+    """Each candidate's reduced residual lies between the full-space least-squares residual
+    of the same operator (dense, tiny problem) and ||b||^2."""
+    geo, x, th_nom, _, b, _ = small_problem(N=8, nb=13, V=12)
+    shifts = np.radians(np.array([-2.0, 0.0, 2.0]))
+    _, res2, _ = M.grid_search_shift(geo, th_nom, b, shifts, ell0=6)
+    for s, r2 in zip(shifts, res2):
+        A, _ = P.dense(geo.N, geo.nb, th_nom + s)
+        xf, *_ = np.linalg.lstsq(A, b, rcond=None)
+        full = float(np.sum((A @ xf - b) ** 2))
+        assert full - 1e-9 * (b @ b) <= r2 <= b @ b
