@@ -7,8 +7,9 @@ update with Armijo trials, residual append.  Inputs are resident in HBM before t
 rate of the same iteration captured once as a HIP graph and replayed is reported beside it.
 
 Also reported:
-  * Gsamples/s of the projector family (one sample = one nonzero (ray, pixel) weight
-    applied) at the same workload, per call and per kernel (HIP events on the launch stream);
+  * Gsamples/s of the projector family (project, backproject, angle derivative and its
+    transpose; one sample = one nonzero (ray, pixel) weight applied) at the same workload,
+    per call and per kernel (HIP events on the launch stream);
   * the roofline of the dominant kernel (the forward-weights kernel of the projection);
   * outer it/s of the 32-frame dynamic workload, batched (one launch over all frames, the
     outer iteration replayed as a HIP graph) against plain (per-frame launches, eager), with
@@ -123,7 +124,9 @@ def operators(torch, ops, metrics, inst, wl, g, x32, th_true, b, reps, stream):
     proj = lambda: ops.project(x32, th_true, g, out=y)              # noqa: E731
     back = lambda: ops.backproject(ysrc, th_true, g, out=xb)        # noqa: E731
     dth = lambda: ops.project_dtheta(x32, th_true, g, want_dy=True)  # noqa: E731
-    call_ms = {"project": timed(proj), "backproject": timed(back), "dtheta": timed(dth)}
+    dtt = lambda: ops.backproject_dtheta(ysrc, th_true, g, out=xb)   # noqa: E731
+    call_ms = {"project": timed(proj), "backproject": timed(back), "dtheta": timed(dth),
+               "dtheta_transpose": timed(dtt)}
     ops.set_kernel_timing(True)
     proj()
     back()
@@ -213,7 +216,8 @@ def workload_operators(torch, ops, metrics, synth, reps):
         xo = torch.empty_like(x)
         ms = {"project": timed(lambda: ops.project(x, th, g, fr, out=yo)),
               "backproject": timed(lambda: ops.backproject(y, th, g, fr, out=xo)),
-              "dtheta": timed(lambda: ops.project_dtheta(x, th, g, fr, want_dy=True))}
+              "dtheta": timed(lambda: ops.project_dtheta(x, th, g, fr, want_dy=True)),
+              "dtheta_transpose": timed(lambda: ops.backproject_dtheta(y, th, g, fr, out=xo))}
         name = key if block is None else f"{key}_block{block}"
         out[name] = {"grid": f"{F}x{wl.N}x{wl.N}" if F > 1 else f"{wl.N}x{wl.N}",
                      "views": int(V), "bins": wl.nb, "nnz": int(nnz),

@@ -132,6 +132,16 @@ int nlrmm_backproject(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch 
                       int32_t ncols, const float *y, const double *theta, float *x,
                       void *stream);
 
+/* Transpose of the angle derivative: x = D(theta)^T r = sum_v (dA_v/dtheta_v)^T r_v, the
+ * H_p^T r term of the full-space sensitivity equation of Section 4.2 (eq. "sensitivity") for
+ * a global angle offset (per-view terms: r zero outside view v).  Per view, bin j carries
+ * (M(e_j) - M(e_{j+1})) / ds with M the chord first moment (the weights of
+ * nlrmm_project_dtheta), gathered per pixel; no atomics.
+ *   r [ncols][nviews][nbins] float32 ; x [ncols][nframes][ny][nx] float32, overwritten */
+int nlrmm_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                             int32_t ncols, const float *r, const double *theta, float *x,
+                             void *stream);
+
 /* Angle derivative of the projection, D[v][j] = d y[v][j] / d theta_v: the Jacobian
  * columns H_{p_i} u of Alg. "update_param" (view v's column has nonzeros only on view
  * v's rows).  Optional outputs (any may be NULL, at least one must be given):

@@ -38,7 +38,7 @@ def _load():
         ip = ctypes.POINTER(ctypes.c_int64)
         sig = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, ip,
                ctypes.c_int, dp, dp, dp, ctypes.c_int]
-        for name in ("ora_project", "ora_backproject", "ora_dtheta"):
+        for name in ("ora_project", "ora_backproject", "ora_dtheta", "ora_dtheta_t"):
             f = getattr(lib, name)
             f.argtypes = sig
             f.restype = ctypes.c_int
@@ -123,6 +123,21 @@ def dtheta(x, theta, nb, view_off=None, nthreads=0):
     xs = np.ascontiguousarray(x.reshape((-1, F, N, N)))
     d = _run("ora_dtheta", xs, theta, (xs.shape[0], V, nb), N, nb, vo, nthreads)
     return d if x.ndim == 4 else d[0]
+
+
+def dtheta_t(r, theta, N, view_off=None, nthreads=0):
+    """x = D(theta)^T r, the transpose of ``dtheta`` (sum over views of the angle-derivative
+    weights times r).  Same shapes as ``backproject``."""
+    r = np.asarray(r, dtype=np.float64)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    V, nb = r.shape[-2], r.shape[-1]
+    vo = _vo(view_off, V)
+    F = vo.shape[0] - 1
+    rs = np.ascontiguousarray(r.reshape((-1, V, nb)))
+    x = _run("ora_dtheta_t", rs, theta, (rs.shape[0], F, N, N), N, nb, vo, nthreads)
+    if r.ndim == 3:
+        return x
+    return x[0, 0] if F == 1 else x[0]
 
 
 def dense(N, nb, theta):

@@ -252,6 +252,52 @@ int ora_dtheta(int N, int nb, double s0, double ds, int nframes, const int64_t *
     return 0;
 }
 
+/* x = D(theta)^T r with D the angle derivative above: x[pix] = sum over views v of frame f
+ * and bins j of (M(e_j) - M(e_{j+1})) / ds * r[v][j] (the same weights as ora_dtheta,
+ * gathered per pixel), for every column. */
+int ora_dtheta_t(int N, int nb, double s0, double ds, int nframes, const int64_t *view_off,
+                 int ncols, const double *r, const double *theta, double *x, int nthreads)
+{
+    const geom_t g = {N, nb, s0, ds};
+    const double D = 2.0 / N;
+    const int V = (int)view_off[nframes];
+    const int64_t npix = (int64_t)N * N;
+    set_threads(nthreads);
+    view_t *qs = (view_t *)malloc(sizeof(view_t) * (size_t)(V > 0 ? V : 1));
+    for (int v = 0; v < V; ++v) qs[v] = view_make(theta[v], D);
+    for (int col = 0; col < ncols; ++col) {
+        const double *rc = r + (int64_t)col * V * nb;
+        double *xc = x + (int64_t)col * nframes * npix;
+        for (int f = 0; f < nframes; ++f) {
+            double *xf = xc + (int64_t)f * npix;
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int l = 0; l < N; ++l) {
+                const double yl = -1.0 + (l + 0.5) * D;
+                for (int k = 0; k < N; ++k) {
+                    const double xk = -1.0 + (k + 0.5) * D;
+                    double acc = 0.0;
+                    for (int64_t v = view_off[f]; v < view_off[f + 1]; ++v) {
+                        const view_t *q = &qs[v];
+                        const double cc = xk * q->c + yl * q->s;
+                        const double tc = -xk * q->s + yl * q->c;
+                        int jlo, jhi;
+                        bin_range(cc, q, &g, &jlo, &jhi);
+                        for (int j = jlo; j <= jhi; ++j) {
+                            const double e0 = s0 + j * ds, e1 = s0 + (j + 1) * ds;
+                            const double dw = (chord_moment(e0 - cc, tc, q) -
+                                               chord_moment(e1 - cc, tc, q)) / ds;
+                            acc += dw * rc[v * nb + j];
+                        }
+                    }
+                    xf[(int64_t)l * N + k] = acc;
+                }
+            }
+        }
+    }
+    free(qs);
+    return 0;
+}
+
 /* Dense A(theta) (V*nb x N*N) and dA/dtheta (same shape) for tiny grids. */
 int ora_dense(int N, int nb, double s0, double ds, int V, const double *theta,
               double *A, double *dA)

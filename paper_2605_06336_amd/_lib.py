@@ -59,6 +59,7 @@ SIGNATURES = {
     "nlrmm_ctx_kernel_ms": [_P, _I32, ctypes.POINTER(ctypes.c_float)],
     "nlrmm_project": [_P, _GP, _BP, _I32, _P, _P, _P, _P],
     "nlrmm_backproject": [_P, _GP, _BP, _I32, _P, _P, _P, _P],
+    "nlrmm_backproject_dtheta": [_P, _GP, _BP, _I32, _P, _P, _P, _P],
     "nlrmm_project_dtheta": [_P, _GP, _BP, _I32, _P, _P, _P, _P, _P, _P, _P, _P],
     "nlrmm_backproject_acc": [_P, _GP, _BP, _I32, _P, _P, _P, _I32, _P],
     "nlrmm_project_residual": [_P, _GP, _BP, _P, _P, _P, _P, _P, _P],

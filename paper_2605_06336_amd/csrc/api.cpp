@@ -160,6 +160,20 @@ int nlrmm_backproject(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch 
     return launch_backproject(ctx, *geom, *batch, ncols, y, theta, x, (hipStream_t)stream);
 }
 
+int nlrmm_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                             int32_t ncols, const float *r, const double *theta, float *x,
+                             void *stream)
+{
+    if (!ctx || !x || !theta || !r) return NLRMM_EINVAL;
+    if (ncols < 1) return NLRMM_ESHAPE;
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if ((rc = check_batch(batch))) return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    return launch_backproject_dtheta(ctx, *geom, *batch, ncols, r, theta, x,
+                                     (hipStream_t)stream);
+}
+
 int nlrmm_project_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
                          int32_t ncols, const float *x, const double *theta, float *dy,
                          float *yproj, const float *g, double *gdot, double *dnorm2,

@@ -108,6 +108,9 @@ struct TvEpilogue {
 int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
                        const float *y, const double *theta, float *x, hipStream_t s,
                        int accumulate = 0, const TvEpilogue *tv = nullptr);
+int launch_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
+                              int ncols, const float *y, const double *theta, float *x,
+                              hipStream_t s);
 
 }  // namespace nlrmm
 

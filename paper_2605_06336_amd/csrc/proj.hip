@@ -822,6 +822,130 @@ __global__ __launch_bounds__(BWD_BLK) void bwd_tiles_k(BwdArgs a)
     }
 }
 
+// x = D(theta)^T r: the transpose of the angle derivative (per view, bin j carries
+// (M(e_j) - M(e_{j+1})) / ds with M the chord first moment), gathered per pixel like the
+// backprojection.  Per pixel and view the edges inside the footprint (at most E) carry
+// M_i = L_i (t_c + mu_i) and the bins give sum_i M_i (r[jj + i] - r[jj + i - 1]) (the moments
+// at the two bounding edges vanish).  One thread per pixel pair of a 16x16 tile, 32-view
+// chunks with their windows of r and per-view constants staged in LDS; no view split.
+template <int E>
+struct BMView {
+    double T0, ax, ay;   // footprint start (shifted positive), bin-unit steps per pixel
+    int jb;
+    float tc0, tkx, tly;  // t-coordinate of the tile centre and its steps per pixel
+    float cm[E];          // edge i offset from the pixel centre at fraction 0: i ds - wo
+    float fwo, fwi, frho, fh, inv_ab, Kr, tq, kp, kappa;
+};
+
+template <int E>
+__global__ __launch_bounds__(BWD_BLK) void bwd_moment_tiles_k(BwdArgs a)
+{
+    __shared__ BMView<E> sv[VCHUNK];
+    __shared__ int sj0[VCHUNK];
+    __shared__ float sy[VCHUNK][WMAX];
+    const int tid = threadIdx.x;
+    const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
+    const int64_t img = blockIdx.y;
+    const int64_t col = img / a.nframes;
+    const int f = (int)(img - col * a.nframes);
+    const int kl = tid % TILE, ll = tid / TILE;
+    const int k = tx * TILE + kl;
+    const int l0 = ty * TILE + ll, l1 = l0 + TILE / 2;
+    const bool act0 = k < a.nx && l0 < a.ny, act1 = k < a.nx && l1 < a.ny;
+    const int64_t v0 = (a.view_off && a.nframes > 1) ? a.view_off[f] : 0;
+    const int64_t v1 = (a.view_off && a.nframes > 1) ? a.view_off[f + 1] : a.V;
+    const float *ycol = a.y + col * a.V * a.nb;
+    const double xc = a.x0 + (tx * TILE + 0.5 * TILE) * a.d;
+    const double yc = a.y0 + (ty * TILE + 0.5 * TILE) * a.d;
+    const double pk = kl + 0.5 - 0.5 * TILE, pl = ll + 0.5 - 0.5 * TILE;
+    const double hl = 0.5 * TILE;
+    double acc0 = 0.0, acc1 = 0.0;
+
+    for (int64_t vb = v0; vb < v1; vb += VCHUNK) {
+        const int nv = (int)min((int64_t)VCHUNK, v1 - vb);
+        if (tid < nv) {
+            const ViewC w = make_view(a.theta[vb + tid], a.d);
+            const double cC = xc * w.cs + yc * w.sn;
+            const double R = (TILE - 1) * 0.5 * a.d * (fabs(w.cs) + fabs(w.sn)) + w.wo;
+            const int j0 = (int)floor((cC - R - a.s0) / a.ds) - 1;
+            const double T = (cC - w.wo - a.s0) / a.ds;
+            const double Tf = floor(T);
+            BMView<E> q;
+            q.T0 = (T - Tf) + TSHIFT;
+            q.ax = a.d * w.cs / a.ds;
+            q.ay = a.d * w.sn / a.ds;
+            q.jb = (int)Tf - j0 - TSHIFT;
+            q.tc0 = (float)(-xc * w.sn + yc * w.cs);
+            q.tkx = (float)(-a.d * w.sn);
+            q.tly = (float)(a.d * w.cs);
+            for (int i = 1; i <= E; ++i) q.cm[i - 1] = (float)(i * a.ds - w.wo);
+            q.fwo = w.fwo;
+            q.fwi = w.fwi;
+            q.frho = w.frho;
+            q.fh = w.fh;
+            q.inv_ab = w.inv_ab;
+            q.Kr = w.Kr;
+            q.tq = w.tq;
+            q.kp = w.kp;
+            q.kappa = w.kappa;
+            sv[tid] = q;
+            sj0[tid] = j0;
+        }
+        __syncthreads();
+        for (int i = tid; i < nv * a.W; i += BWD_BLK) {
+            const int vi = i / a.W, jj = i - vi * a.W;
+            const int jbin = sj0[vi] + jj;
+            sy[vi][jj] = (jbin >= 0 && jbin < a.nb) ? ycol[(vb + vi) * a.nb + jbin] : 0.0f;
+        }
+        __syncthreads();
+        const float fds = (float)a.ds;
+        float accf0 = 0.0f, accf1 = 0.0f;
+        for (int vi = 0; vi < nv; ++vi) {
+            const BMView<E> &q = sv[vi];
+            ViewC w;
+            w.fwo = q.fwo;
+            w.fwi = q.fwi;
+            w.frho = q.frho;
+            w.fh = q.fh;
+            w.inv_ab = q.inv_ab;
+            w.Kr = q.Kr;
+            w.tq = q.tq;
+            w.kp = q.kp;
+            w.kappa = q.kappa;
+            const double t0 = fma(pk, q.ax, fma(pl, q.ay, q.T0));
+            const double t1 = fma(hl, q.ay, t0);
+            const float tcp0 = fmaf((float)pk, q.tkx, fmaf((float)pl, q.tly, q.tc0));
+            const float tcp1 = fmaf((float)hl, q.tly, tcp0);
+            float sum[2];
+#pragma unroll
+            for (int px = 0; px < 2; ++px) {
+                const double t = px == 0 ? t0 : t1;
+                const float tc = px == 0 ? tcp0 : tcp1;
+                const float fr = (float)__builtin_amdgcn_fract(t);
+                int jj = q.jb + (int)t;
+                jj = min(max(jj, 0), a.W - (E + 1));
+                const float *yy = &sy[vi][jj];
+                float sm = 0.0f;
+#pragma unroll
+                for (int i = 1; i <= E; ++i) {
+                    float L, mu;
+                    moment_f(fmaf(-fr, fds, q.cm[i - 1]), w, L, mu);
+                    sm = fmaf(L * (tc + mu), yy[i] - yy[i - 1], sm);
+                }
+                sum[px] = sm;
+            }
+            accf0 += sum[0];
+            accf1 += sum[1];
+        }
+        acc0 += (double)accf0;
+        acc1 += (double)accf1;
+        __syncthreads();
+    }
+    const int64_t ibase = (col * a.nframes + f) * (int64_t)a.ny;
+    if (act0) a.x[(ibase + l0) * a.nx + k] = (float)(acc0 / a.ds);
+    if (act1) a.x[(ibase + l1) * a.nx + k] = (float)(acc1 / a.ds);
+}
+
 __global__ void sum_splits_k(const float *__restrict__ part, int nsplit, int64_t n,
                              float *__restrict__ x, int accumulate, TvEpilogue tv, int nx, int ny,
                              int nframes)
@@ -1046,6 +1170,47 @@ size_t bwd_workspace_bytes(const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
                        : bwd_splits(g, b, ncols, cu_count);
     if (ns <= 1) return 0;
     return sizeof(float) * (size_t)ns * ncols * b.nframes * g.nx * g.ny;
+}
+
+int launch_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
+                              int ncols, const float *y, const double *theta, float *x,
+                              hipStream_t s)
+{
+    const int E = edges_inside(g);
+    if (E < 1 || E > 4) return NLRMM_ESHAPE;
+    const int W = (int)ceil((TILE - 1) * g.d * 1.4142135623730951 / g.ds) + E + 4;
+    if (W > WMAX) return NLRMM_ESHAPE;
+    BwdArgs a;
+    a.y = y;
+    a.theta = theta;
+    a.view_off = b.view_off;
+    a.nframes = b.nframes;
+    a.V = b.nviews;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.nb = g.nbins;
+    a.x0 = g.x0;
+    a.y0 = g.y0;
+    a.d = g.d;
+    a.s0 = g.s0;
+    a.ds = g.ds;
+    a.tiles_x = (g.nx + TILE - 1) / TILE;
+    a.W = W;
+    a.x = x;
+    a.nsplit = 1;
+    a.part = nullptr;
+    a.accumulate = 0;
+    a.tv = TvEpilogue();
+    const int tiles_y = (g.ny + TILE - 1) / TILE;
+    dim3 grid((unsigned)(a.tiles_x * tiles_y), (unsigned)((int64_t)ncols * b.nframes), 1);
+    switch (E) {
+        case 1: bwd_moment_tiles_k<1><<<grid, BWD_BLK, 0, s>>>(a); break;
+        case 2: bwd_moment_tiles_k<2><<<grid, BWD_BLK, 0, s>>>(a); break;
+        case 3: bwd_moment_tiles_k<3><<<grid, BWD_BLK, 0, s>>>(a); break;
+        default: bwd_moment_tiles_k<4><<<grid, BWD_BLK, 0, s>>>(a); break;
+    }
+    NLRMM_HIP_CHECK(hipGetLastError());
+    return NLRMM_OK;
 }
 
 int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,

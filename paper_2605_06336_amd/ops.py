@@ -124,6 +124,27 @@ def backproject(y: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None,
     return out
 
 
+def backproject_dtheta(r: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None,
+                       out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """x = D(theta)^T r, the transpose of the angle derivative (nlrmm_backproject_dtheta).
+    r: [..., V, nb] float32; x: [ncols, F, ny, nx]."""
+    _need(r, torch.float32, "r")
+    _need(theta, torch.float64, "theta")
+    V = theta.numel()
+    b = _batch(frames, V)
+    if r.numel() % (V * g.nbins):
+        raise ValueError("r size is not a multiple of V*nb")
+    ncols = r.numel() // (V * g.nbins)
+    if out is None:
+        out = torch.empty((ncols, b.nframes, g.ny, g.nx), dtype=torch.float32, device=r.device)
+    _need(out, torch.float32, "out")
+    check(_lib.lib().nlrmm_backproject_dtheta(context(r.device.index or 0), ctypes.byref(g),
+                                              ctypes.byref(b), ncols, r.data_ptr(),
+                                              theta.data_ptr(), out.data_ptr(),
+                                              _stream(r.device)), "nlrmm_backproject_dtheta")
+    return out
+
+
 def autotune_project(x: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None,
                      out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Same result as project(); also times the forward block shapes for this shape and

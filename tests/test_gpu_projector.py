@@ -158,3 +158,27 @@ def test_deterministic():
     c = ops.backproject(ya, tht, g).cpu().numpy()
     d = ops.backproject(ya, tht, g).cpu().numpy()
     assert np.array_equal(c, d)
+
+
+@pytest.mark.parametrize("N,nb,V,F,ncols", [(5, 7, 6, 1, 1), (37, 53, 9, 1, 1), (100, 283, 12, 1, 3),
+                                            (256, 363, 40, 1, 1), (48, 69, 0, 3, 2)])
+def test_dtheta_transpose_parity(N, nb, V, F, ncols):
+    """x = D(theta)^T r (nlrmm_backproject_dtheta) against the oracle's transposed loop, and
+    the adjoint identity <D x, r> = <x, D^T r> with the device's own derivative."""
+    vo, fr = frames_for(F, N + 7)
+    Vt = int(vo[-1]) if vo is not None else V + len(SPECIAL)
+    th = angles(Vt - len(SPECIAL), seed=N + 3)[:Vt] if vo is None else synth.random_angles(Vt, N)
+    g = ops.geom(N, nb)
+    r = synth.random_sinogram(Vt * ncols, nb, seed=N + 5).reshape(ncols, Vt, nb).astype(np.float32)
+    tht = dev(th, torch.float64)
+    print(f"case N={N} nb={nb} V={Vt} F={F} ncols={ncols}", flush=True)
+    x = ops.backproject_dtheta(dev(r, torch.float32), tht, g, fr).cpu().numpy()
+    x_ref = P.dtheta_t(r.astype(np.float64), th, N, vo).reshape(x.shape)
+    assert rel(x, x_ref) <= TOL, rel(x, x_ref)
+    xs = synth.random_image(N, seed=N + 9, frames=F * ncols).reshape(ncols, F, N, N)
+    D = ops.project_dtheta(dev(xs.astype(np.float32), torch.float32), tht, g, fr,
+                           want_dy=True)["dy"].cpu().numpy().astype(np.float64)
+    xt = ops.backproject_dtheta(dev(r, torch.float32), tht, g, fr).cpu().numpy().astype(np.float64)
+    lhs = float(np.sum(D * r))
+    rhs = float(np.sum(xs.astype(np.float32).astype(np.float64) * xt))
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(D) * np.linalg.norm(r), (lhs, rhs)

@@ -117,3 +117,21 @@ def test_dtheta_finite_differences_and_zero_sum(N, nb):
         errs.append(np.linalg.norm(D - fd) / np.linalg.norm(D))
     assert errs[1] < 1e-4
     assert np.max(np.abs(D.sum(axis=1))) < 1e-12 * np.abs(D).max() * nb
+
+
+def test_dtheta_transpose_by_finite_differences_and_adjoint():
+    """D^T r (the adjoint-derivative operator of the full-space sensitivity equation): for
+    random x, r, <x, D^T r> = d/de <A(theta + e) x, r> at e = 0 (central differences of the
+    area projector, which does not use the chord moments), and <D x, r> = <x, D^T r> against
+    the forward derivative's loop."""
+    rng = np.random.default_rng(12)
+    N, nb, V = 12, 19, 9
+    th = np.concatenate([rng.uniform(0, np.pi, V - 3), [0.0, np.pi / 4, np.pi / 2 + 1e-3]])
+    x = rng.standard_normal((N, N))
+    r = rng.standard_normal((V, nb))
+    xt = P.dtheta_t(r, th, N)
+    lhs = float(np.sum(x * xt))
+    h = 1e-6
+    fd = (np.sum(P.project(x, th + h, nb) * r) - np.sum(P.project(x, th - h, nb) * r)) / (2 * h)
+    assert abs(lhs - fd) <= 1e-6 * (abs(fd) + np.linalg.norm(x) * np.linalg.norm(r) * 1e-3)
+    assert abs(float(np.sum(P.dtheta(x, th, nb) * r)) - lhs) <= 1e-12 * np.abs(xt).sum() * np.abs(x).max()
