@@ -43,6 +43,7 @@ FP32_NONPACKED_PEAK_TFLOPS = 78.6   # 256 CU x 64 FP32 FMA lanes x 2 flop x 2.4 
 FLOP_PER_SAMPLE = 10.0              # algorithmic FP32 flops per applied strip-area weight
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd_edges_c2.json")
 COPY_BYTES = 256 << 20              # calibration copy for the HBM byte counters
+KERNEL_REPS = 10                    # back-to-back launches per event-timed kernel
 
 
 def parse():
@@ -127,7 +128,9 @@ def operators(torch, ops, metrics, inst, wl, g, x32, th_true, b, reps, stream):
     dtt = lambda: ops.backproject_dtheta(ysrc, th_true, g, out=xb)   # noqa: E731
     call_ms = {"project": timed(proj), "backproject": timed(back), "dtheta": timed(dth),
                "dtheta_transpose": timed(dtt)}
-    ops.set_kernel_timing(True)
+    # each timed kernel launched KERNEL_REPS times back to back between its two events, so
+    # that the events' own cost is spread over those launches
+    ops.set_kernel_timing(KERNEL_REPS)
     proj()
     back()
     kern_ms = {"fwd_edges_k": kernel_avg(proj, "project"),

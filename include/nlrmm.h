@@ -105,13 +105,17 @@ int nlrmm_ctx_set_tune_file(nlrmm_ctx *ctx, const char *path);
 int nlrmm_tune_query(nlrmm_ctx *ctx, int32_t kind, const nlrmm_geom *geom,
                      const nlrmm_batch *batch, int32_t ncols, int32_t *choice);
 
-/* Measurement aid (no part of the method).  With timing enabled, every projection records a
- * pair of HIP events on its launch stream around its forward-weights kernel (which = 0), and
- * every backprojection around its pixel-tile kernel (which = 1); the pair of the most recent
- * launch is kept (for a multi-group projection, the last group's).  nlrmm_ctx_kernel_ms waits
- * for that launch's stop event and returns its duration in milliseconds; NLRMM_EINVAL if no
- * such launch has been recorded since timing was enabled.  Events are created by
- * nlrmm_ctx_set_timing (so enable it outside graph capture) and freed by nlrmm_ctx_destroy. */
+/* Measurement aid (no part of the method).  With timing enabled (enable >= 1), every
+ * projection records a pair of HIP events on its launch stream around its forward-weights
+ * kernel (which = 0), and every backprojection around its pixel-tile kernel (which = 1); the
+ * pair of the most recent launch is kept (for a multi-group projection, the last group's).
+ * enable = R > 1 launches the timed kernel R times back to back between the two events
+ * (capped at 1000; the results are unchanged because the repeated kernel recomputes the same
+ * outputs; a backprojection that adds into x is launched once), so that the events' own cost
+ * is spread over R launches.  nlrmm_ctx_kernel_ms waits for the stop event and returns the
+ * duration per launch in milliseconds; NLRMM_EINVAL if no such launch has been recorded
+ * since timing was enabled.  Events are created by nlrmm_ctx_set_timing (so enable it
+ * outside graph capture) and freed by nlrmm_ctx_destroy.  enable = 0 turns timing off. */
 int nlrmm_ctx_set_timing(nlrmm_ctx *ctx, int enable);
 int nlrmm_ctx_kernel_ms(nlrmm_ctx *ctx, int which, float *ms);
 

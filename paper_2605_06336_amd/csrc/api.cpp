@@ -61,6 +61,13 @@ void timing_mark(nlrmm_ctx *ctx, int which, int stop, hipStream_t s)
     if (hipEventRecord(ctx->tev[which][stop], s) == hipSuccess && stop) ctx->tev_set[which] = 1;
 }
 
+int timing_reps(nlrmm_ctx *ctx, int which, bool repeatable)
+{
+    const int r = (ctx->timing > 1 && repeatable) ? ctx->timing : 1;
+    if (ctx->timing) ctx->tev_reps[which] = r;
+    return r;
+}
+
 }  // namespace nlrmm
 
 using namespace nlrmm;
@@ -108,7 +115,7 @@ int nlrmm_ctx_set_timing(nlrmm_ctx *ctx, int enable)
                 if (!e && hipEventCreate(&e) != hipSuccess) return NLRMM_EHIP;
         ctx->tev_set[0] = ctx->tev_set[1] = 0;
     }
-    ctx->timing = enable ? 1 : 0;
+    ctx->timing = enable > 0 ? (enable > 1000 ? 1000 : enable) : 0;
     return NLRMM_OK;
 }
 
@@ -120,6 +127,7 @@ int nlrmm_ctx_kernel_ms(nlrmm_ctx *ctx, int which, float *ms)
     if (hipEventSynchronize(ctx->tev[which][1]) != hipSuccess) return NLRMM_EHIP;
     if (hipEventElapsedTime(ms, ctx->tev[which][0], ctx->tev[which][1]) != hipSuccess)
         return NLRMM_EHIP;
+    *ms /= (float)ctx->tev_reps[which];
     return NLRMM_OK;
 }
 

@@ -42,6 +42,7 @@ struct nlrmm_ctx {
     int timing = 0;
     hipEvent_t tev[2][2] = {};   // [kernel][start, stop]; 0 forward weights, 1 backprojection
     int tev_set[2] = {0, 0};
+    int tev_reps[2] = {1, 1};    // launches of the timed kernel between the recorded pair
     // autotuner: cached launch shapes, a candidate forced while tuning, optional cache file
     std::vector<nlrmm::TuneEntry> tune;
     int force_fwd_seg = 0;
@@ -69,6 +70,9 @@ int bwd_split_max(const nlrmm_geom &g, const nlrmm_batch &b);
 
 // Record the start / stop event of timed kernel `which` on stream s (no-op unless enabled).
 void timing_mark(nlrmm_ctx *ctx, int which, int stop, hipStream_t s);
+// Launches of a timed kernel between its events: the context's repeat count when timing is on
+// and the launch can be repeated without changing its result, else 1.
+int timing_reps(nlrmm_ctx *ctx, int which, bool repeatable);
 int check_batch(const nlrmm_batch *b);
 
 // Forward-kernel outputs and modes (see proj.hip).

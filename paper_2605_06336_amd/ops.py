@@ -26,14 +26,15 @@ def context(device: int = 0) -> int:
     return _ctx[device]
 
 
-def set_kernel_timing(enable: bool, device: int = 0) -> None:
-    """Enable event timing of the forward-weights and backprojection kernels (measurement)."""
+def set_kernel_timing(enable, device: int = 0) -> None:
+    """Event timing of the forward-weights and backprojection kernels (measurement): False
+    off, True on, an int R > 1 launches each timed kernel R times between its events."""
     check(_lib.lib().nlrmm_ctx_set_timing(context(device), int(enable)), "nlrmm_ctx_set_timing")
 
 
 def kernel_ms(which: str, device: int = 0) -> float:
-    """Duration of the most recent 'project' (forward-weights) or 'backproject' (pixel-tile)
-    kernel launch, from HIP events on its launch stream; waits for that launch."""
+    """Duration per launch of the most recent 'project' (forward-weights) or 'backproject'
+    (pixel-tile) kernel, from HIP events on its launch stream; waits for that launch."""
     ms = ctypes.c_float()
     check(_lib.lib().nlrmm_ctx_kernel_ms(context(device), {"project": 0, "backproject": 1}[which],
                                          ctypes.byref(ms)), "nlrmm_ctx_kernel_ms")

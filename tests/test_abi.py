@@ -47,5 +47,9 @@ def test_host_validation_without_device():
     assert lib.nlrmm_tune_query(None, 0, ctypes.byref(g), ctypes.byref(b), 1,
                                 ctypes.byref(c)) == -1
     assert lib.nlrmm_ctx_set_timing(None, 1) == -1
+    assert lib.nlrmm_backproject_dtheta(None, ctypes.byref(g), ctypes.byref(b), 1, 1, 1, 1,
+                                        None) == -1
+    assert lib.nlrmm_solver_grid_search(None, ctypes.byref(b), 1, 1, 1, 3, 10, None, None,
+                                        None) == -1
     assert lib.nlrmm_strerror(-2) == b"inconsistent or unsupported sizes"
     assert lib.nlrmm_version() >= 100
