@@ -852,8 +852,11 @@ __global__ __launch_bounds__(BWD_BLK) void bwd_moment_tiles_k(BwdArgs a)
     const int k = tx * TILE + kl;
     const int l0 = ty * TILE + ll, l1 = l0 + TILE / 2;
     const bool act0 = k < a.nx && l0 < a.ny, act1 = k < a.nx && l1 < a.ny;
-    const int64_t v0 = (a.view_off && a.nframes > 1) ? a.view_off[f] : 0;
-    const int64_t v1 = (a.view_off && a.nframes > 1) ? a.view_off[f + 1] : a.V;
+    const int64_t fv0 = (a.view_off && a.nframes > 1) ? a.view_off[f] : 0;
+    const int64_t fv1 = (a.view_off && a.nframes > 1) ? a.view_off[f + 1] : a.V;
+    const int split = blockIdx.z;
+    const int64_t v0 = fv0 + ((fv1 - fv0) * split) / a.nsplit;
+    const int64_t v1 = fv0 + ((fv1 - fv0) * (split + 1)) / a.nsplit;
     const float *ycol = a.y + col * a.V * a.nb;
     const double xc = a.x0 + (tx * TILE + 0.5 * TILE) * a.d;
     const double yc = a.y0 + (ty * TILE + 0.5 * TILE) * a.d;
@@ -942,8 +945,10 @@ __global__ __launch_bounds__(BWD_BLK) void bwd_moment_tiles_k(BwdArgs a)
         __syncthreads();
     }
     const int64_t ibase = (col * a.nframes + f) * (int64_t)a.ny;
-    if (act0) a.x[(ibase + l0) * a.nx + k] = (float)(acc0 / a.ds);
-    if (act1) a.x[(ibase + l1) * a.nx + k] = (float)(acc1 / a.ds);
+    // one image, or this split's partial image (summed in split order by sum_splits_k)
+    float *out = a.nsplit > 1 ? a.part + split * ((int64_t)gridDim.y * a.nx * a.ny) : a.x;
+    if (act0) out[(ibase + l0) * a.nx + k] = (float)(acc0 / a.ds);
+    if (act1) out[(ibase + l1) * a.nx + k] = (float)(acc1 / a.ds);
 }
 
 __global__ void sum_splits_k(const float *__restrict__ part, int nsplit, int64_t n,
@@ -1202,17 +1207,32 @@ int launch_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_b
     a.tiles_x = (g.nx + TILE - 1) / TILE;
     a.W = W;
     a.x = x;
-    a.nsplit = 1;
+    // the backprojection's view split for this shape (tuned, else its default)
+    {
+        const int t = tune_lookup(ctx, TUNE_BWD_SPLIT, g, b, ncols);
+        a.nsplit = t ? t : bwd_splits(g, b, ncols, ctx->cu_count);
+    }
     a.part = nullptr;
     a.accumulate = 0;
     a.tv = TvEpilogue();
+    if (a.nsplit > 1) {
+        int rc = ensure_workspace(ctx, bwd_workspace_bytes(g, b, ncols, ctx->cu_count), s);
+        if (rc) return rc;
+        a.part = (float *)ctx->ws.ptr;
+    }
     const int tiles_y = (g.ny + TILE - 1) / TILE;
-    dim3 grid((unsigned)(a.tiles_x * tiles_y), (unsigned)((int64_t)ncols * b.nframes), 1);
+    dim3 grid((unsigned)(a.tiles_x * tiles_y), (unsigned)((int64_t)ncols * b.nframes),
+              (unsigned)a.nsplit);
     switch (E) {
         case 1: bwd_moment_tiles_k<1><<<grid, BWD_BLK, 0, s>>>(a); break;
         case 2: bwd_moment_tiles_k<2><<<grid, BWD_BLK, 0, s>>>(a); break;
         case 3: bwd_moment_tiles_k<3><<<grid, BWD_BLK, 0, s>>>(a); break;
         default: bwd_moment_tiles_k<4><<<grid, BWD_BLK, 0, s>>>(a); break;
+    }
+    if (a.nsplit > 1) {
+        const int64_t n = (int64_t)ncols * b.nframes * g.nx * g.ny;
+        sum_splits_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a.part, a.nsplit, n, x, 0,
+                                                                 a.tv, g.nx, g.ny, b.nframes);
     }
     NLRMM_HIP_CHECK(hipGetLastError());
     return NLRMM_OK;
