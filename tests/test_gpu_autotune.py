@@ -96,3 +96,32 @@ def test_tuner_returns_operator_and_stores_choice(tmp_path):
     y2 = ops.project(xt, tht, g).cpu().numpy()
     assert rel(y2, y) <= 1e-7
     assert os.path.getsize(path) > 0
+
+
+def test_kernel_timing_repeats_leave_results_unchanged():
+    """Event timing with back-to-back repeats of the timed kernels (the benchmark's mode)
+    leaves projection, derivative and backprojection outputs bitwise unchanged (also a
+    backprojection that adds into its output, which is launched once), and reports a
+    positive per-launch time."""
+    N, nb, V, ncols = 96, 139, 70, 2
+    vo, fr, th, x, ys = problem(N, nb, V, ncols, seed=5)
+    g = ops.geom(N, nb)
+    xt, tht, yt = dev(x, torch.float32), dev(th, torch.float64), dev(ys, torch.float32)
+    y0 = ops.project(xt, tht, g).cpu().numpy()
+    d0 = ops.project_dtheta(xt, tht, g, want_dy=True)["dy"].cpu().numpy()
+    b0 = ops.backproject(yt, tht, g).cpu().numpy()
+    base = torch.ones((ncols, 1, N, N), dtype=torch.float32, device="cuda")
+    a0 = ops.backproject_into(yt, tht, g, base.clone()).cpu().numpy()
+    ops.set_kernel_timing(7)
+    try:
+        y1 = ops.project(xt, tht, g).cpu().numpy()
+        tp = ops.kernel_ms("project")
+        d1 = ops.project_dtheta(xt, tht, g, want_dy=True)["dy"].cpu().numpy()
+        b1 = ops.backproject(yt, tht, g).cpu().numpy()
+        tb = ops.kernel_ms("backproject")
+        a1 = ops.backproject_into(yt, tht, g, base.clone()).cpu().numpy()   # adds into x
+    finally:
+        ops.set_kernel_timing(False)
+    assert np.array_equal(y0, y1) and np.array_equal(d0, d1) and np.array_equal(b0, b1)
+    assert np.array_equal(a0, a1)
+    assert tp > 0.0 and tb > 0.0
