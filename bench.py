@@ -14,6 +14,8 @@ Also reported:
   * outer it/s of the 32-frame dynamic workload, batched (one launch over all frames, the
     outer iteration replayed as a HIP graph) against plain (per-frame launches, eager), with
     the difference of the two reconstructions after the same iterations;
+  * ms of the full-space sensitivity solve of one global offset (50 CG steps) at the same
+    workload;
   * Gsamples/s of the three operators at the shape of every workload (64x64 up to
     2048x2048 / 1440 views, and one 22-view block of the streaming workload);
   * outer it/s of VarPro NL-RMM-GKS on the 512x512 / 720-view workload;
@@ -455,6 +457,15 @@ def main():
     rre = float(np.linalg.norm(u.cpu().numpy() - x_true) / np.linalg.norm(x_true))
     dth0 = inst.theta_true - inst.theta_nom
     perr = float(np.linalg.norm(theta.cpu().numpy() - inst.theta_true) / np.linalg.norm(dth0))
+    # full-space sensitivity of one global offset at the current image (CG on A^T A + lam R)
+    sens_iters = 50
+    sol.offset_sensitivity(theta, b, iters=sens_iters)
+    sens_ms = timed_steps(torch, lambda: sol.offset_sensitivity(theta, b, iters=sens_iters), 3,
+                          stream, "c2 offset sensitivity")
+    sens_out, _ = sol.offset_sensitivity(theta, b, iters=sens_iters)
+    sensitivity = {"ms_per_solve": round(sens_ms, 3), "cg_iterations": sens_iters,
+                   "ms_per_cg_iteration": round(sens_ms / sens_iters, 4),
+                   "g_h_dp": [float(v) for v in sens_out.cpu().numpy()]}
     sol.close()
 
     nnz, call_ms, kern_ms = operators(torch, ops, metrics, inst, wl, g, x32, th_true, b,
@@ -534,6 +545,7 @@ def main():
                     "lambda": float(sc.cpu().numpy()[2]), "status": int(status.cpu()[0])},
         "autotune": tuned,
         "batched_vs_plain": dyn,
+        "offset_sensitivity_c2": sensitivity,
         "operators_by_workload": per_workload,
         "varpro_c3": varpro,
         "autograd_c3": autograd_r,

@@ -293,6 +293,22 @@ int nlrmm_solver_grid_search(nlrmm_solver *solver, const nlrmm_batch *batch, dou
                              const float *b, const double *shifts, int32_t ncand, int32_t ell0,
                              double *res2, int32_t *best, void *stream);
 
+/* Full-space sensitivity of the variable-projection reduced problem for one global angle
+ * offset p (Section 4.2, eq. "sensitivity"; the paper uses the RMM-GKS image for the closed
+ * form u(p)): with u the solver's current image, w its regulariser weights, lam the current
+ * lambda, r = A(theta) u - b and A_p u = D u (the angle derivative summed over views),
+ *   (A^T A + lam Psi^T diag(w) Psi) u_p = -(D^T r + A^T D u)
+ * by `iters` conjugate-gradient steps from 0, then J_r = D u + A u_p and the Gauss-Newton
+ * scalars out = [g, h, dp] with g = J_r^T r + lam (Psi u_p)^T w Psi u, h = J_r^T J_r +
+ * lam (Psi u_p)^T w Psi u_p, dp = -g / h (eq. "GN_system" for one parameter; 0 when h = 0).
+ * theta, b DEVICE; out DEVICE [3] float64; up DEVICE [n] float32 or NULL (receives u_p).
+ * Needs six spare basis columns (kmax + 1 - current columns >= 6); the basis, image and
+ * lambda carried between outer iterations are unchanged (the weights buffer is
+ * overwritten with the weights of u). */
+int nlrmm_solver_offset_sensitivity(nlrmm_solver *solver, const nlrmm_batch *batch,
+                                    const double *theta, const float *b, int32_t iters,
+                                    double *out, float *up, void *stream);
+
 /* One outer iteration on the views of `batch` (all views, or one streaming block):
  * rebase A V = A(theta_k) V; Enlarge (solves projected solves, one append between
  * consecutive solves); Compress; UPDATE-PARAM (theta updated in place); weights from the

@@ -13,6 +13,7 @@ Each function follows the paper's algorithm in the paper's order:
   * UPDATE-PARAM ............. Alg. "update_param" (damped Gauss-Newton + Armijo)
   * VarPro ................... Section 4.2 eqs. "u_closed_form", "GN_system", supplementary
                                Alg. "update_varpro"
+  * full-space sensitivity ... Section 4.2, eq. "sensitivity" for one global offset (dense)
   * grid-search start ........ experiments section, "Parameter initialization" (one
                                global offset, reduced least squares on a GKB basis)
   * NL-RMM-GKS ............... Alg. "nl_rmmgks_two_solves", with the optional
@@ -454,6 +455,26 @@ def grid_search_shift(geo: Geometry, theta_nom, b, shifts, ell0: int = 10, V=Non
     res2 = np.array(res2)
     best = int(np.argmin(res2))
     return np.asarray(theta_nom) + shifts[best], res2, best
+
+
+def offset_sensitivity(geo: Geometry, theta, u, b, w, lam):
+    """Full-space sensitivity of the VarPro reduced problem for one global angle offset p
+    (Section 4.2, eqs. "u_closed_form", "sensitivity", "GN_system"), dense (tiny grids):
+    M = A^T A + lam Psi^T diag(w) Psi;  M u_p = -(A_p^T r + A^T A_p u) with r = A u - b and
+    A_p = dA/dp = sum over views of dA/dtheta_v (every view moves with p);
+    J_r = A_p u + A u_p, J_s = sqrt(w) Psi u_p;  g = J_r^T r + lam J_s^T s (s = sqrt(w) Psi u),
+    h = J_r^T J_r + lam J_s^T J_s, dp = -g / h.  Returns (u_p, g, h, dp)."""
+    A, dA = P.dense(geo.N, geo.nb, theta)
+    n = geo.n
+    Psi = np.stack([psi(geo, np.eye(n)[:, i]) for i in range(n)], axis=1)
+    M = A.T @ A + lam * Psi.T @ (w[:, None] * Psi)
+    r = A @ u - b
+    up = np.linalg.solve(M, -(dA.T @ r + A.T @ (dA @ u)))
+    Jr = dA @ u + A @ up
+    Pu, Pp = Psi @ u, Psi @ up
+    g = float(Jr @ r + lam * Pp @ (w * Pu))
+    h = float(Jr @ Jr + lam * Pp @ (w * Pp))
+    return up, g, h, -g / h
 
 
 def init_state(geo: Geometry, theta0, b, cfg: Config) -> State:

@@ -75,6 +75,7 @@ SIGNATURES = {
     "nlrmm_solver_init": [_P, _BP, _P, _P, _P],
     "nlrmm_solver_outer": [_P, _BP, _P, _P, _D, _P],
     "nlrmm_solver_grid_search": [_P, _BP, _P, _P, _P, _I32, _I32, _P, _P, _P],
+    "nlrmm_solver_offset_sensitivity": [_P, _BP, _P, _P, _I32, _P, _P, _P],
     "nlrmm_solver_state": [_P, _P, _P, _P, _P, _P],
     "nlrmm_solver_read": [_P, _P, _P, _P, _P],
     "nlrmm_solver_set_launch": [_P, _I32, _P, _I32],

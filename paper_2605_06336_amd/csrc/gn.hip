@@ -211,6 +211,37 @@ __global__ void grid_pick_k(const double *__restrict__ res2, int ncand,
     for (int64_t v = threadIdx.x; v < V; v += blockDim.x) theta[v] += sh;
 }
 
+
+// Conjugate-gradient coefficients kept on the device (c: [0] rr, [1] p^T M p, [2] new rr,
+// [3] alpha, [4] -alpha, [5] beta): mode 0 alpha = rr / p^T M p; mode 1 beta = new rr / rr
+// and rr <- new rr.  A zero denominator (converged) gives a zero coefficient.
+__global__ void cg_coef_k(double *c, int mode)
+{
+    if (threadIdx.x != 0) return;
+    if (mode == 0) {
+        const double a = c[1] != 0.0 ? c[0] / c[1] : 0.0;
+        c[3] = a;
+        c[4] = -a;
+    } else {
+        c[5] = c[0] != 0.0 ? c[2] / c[0] : 0.0;
+        c[0] = c[2];
+    }
+}
+
+// Gauss-Newton step of one global offset from the sensitivity dots: d1 = [J_r^T J_r,
+// r^T J_r], d2 = [u_p^T Psi^T w Psi u, u_p^T Psi^T w Psi u_p]; out = [g, h, dp = -g / h].
+__global__ void offset_gn_k(const double *d1, const double *d2, const double *lamp,
+                            double *out)
+{
+    if (threadIdx.x != 0) return;
+    const double lam = lamp[0];
+    const double g = d1[1] + lam * d2[0];
+    const double h = d1[0] + lam * d2[1];
+    out[0] = g;
+    out[1] = h;
+    out[2] = h > 0.0 ? -g / h : 0.0;
+}
+
 }  // namespace
 
 #define LAUNCH_OK (hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP)
@@ -266,6 +297,19 @@ int k_grid_pick(const double *res2, int ncand, const double *shifts, double *the
                 int *best, hipStream_t s)
 {
     grid_pick_k<<<1, 256, 0, s>>>(res2, ncand, shifts, theta, V, best);
+    return LAUNCH_OK;
+}
+
+int k_cg_coef(double *c, int mode, hipStream_t s)
+{
+    cg_coef_k<<<1, 64, 0, s>>>(c, mode);
+    return LAUNCH_OK;
+}
+
+int k_offset_gn(const double *d1, const double *d2, const double *lamp, double *out,
+                hipStream_t s)
+{
+    offset_gn_k<<<1, 64, 0, s>>>(d1, d2, lamp, out);
     return LAUNCH_OK;
 }
 

@@ -68,6 +68,9 @@ int k_armijo_check(const double *part_r, int64_t nparts, const double *alphas, i
 int k_gn_apply(double *theta, const double *dir, int64_t V, const double *sc,
                const int *accepted, int *status, hipStream_t s);
 int k_fill_f64(double *dst, int64_t n, double value, hipStream_t s);
+int k_cg_coef(double *c, int mode, hipStream_t s);
+int k_offset_gn(const double *d1, const double *d2, const double *lamp, double *out,
+                hipStream_t s);
 int k_grid_residual(const double *G, int ldg, const double *rb, const double *bnorm2, int ell,
                     double *res2, hipStream_t s);
 int k_grid_pick(const double *res2, int ncand, const double *shifts, double *theta, int64_t V,

@@ -43,6 +43,7 @@ struct Solver {
     float *V = nullptr, *AV = nullptr, *Vtmp = nullptr, *u = nullptr, *r = nullptr,
           *rho = nullptr, *w = nullptr, *uh = nullptr;
     double *zh = nullptr;   // coefficients of the high-regularisation solve
+    double *cgs = nullptr;  // scalars of the sensitivity solve
     double *GA = nullptr, *GP = nullptr, *rb = nullptr, *z = nullptr, *T = nullptr,
            *zt = nullptr, *sc = nullptr, *hb = nullptr, *hb2 = nullptr, *gv = nullptr,
            *hv = nullptr, *rv = nullptr, *dir = nullptr, *alphas = nullptr, *thk = nullptr,
@@ -518,6 +519,86 @@ static int grid_search(Solver &S, const nlrmm_batch &b, double *theta, const flo
     return k_grid_pick(res2, ncand, shifts, theta, V, best, s);
 }
 
+// Full-space sensitivity of the VarPro reduced problem for one global angle offset p
+// (Section 4.2, eq. "sensitivity", with u the current RMM-GKS image standing in for the
+// closed form u(p), as the paper does in practice): weights w of u, r = A u - b and A_p u = D u
+// in one projection, right-hand side -(D^T r + A^T D u), then `iters` conjugate-gradient
+// steps on M = A^T A + lam Psi^T diag(w) Psi (one projection and one backprojection with the
+// weighted regulariser term as its epilogue per step) for u_p, J_r = D u + A u_p, and the
+// Gauss-Newton scalars g = J_r^T r + lam u_p^T Psi^T w Psi u, h = J_r^T J_r + lam u_p^T
+// Psi^T w Psi u_p, dp = -g / h.  The vectors live in the spare basis columns (six of V, three
+// of A V), so the solver state carried between outer iterations is untouched.
+static int offset_sensitivity(Solver &S, const nlrmm_batch &b, const double *theta,
+                              const float *bvec, int iters, double *out, float *up_out,
+                              hipStream_t s)
+{
+    const int64_t n = S.n, m = m_of(S, b);
+    const int base = S.ell;
+    if (S.kcap - base < 6) return NLRMM_ESHAPE;
+    float *x = S.V + (int64_t)base * n, *rc = x + n, *p = x + 2 * n, *q = x + 3 * n,
+          *t1 = x + 4 * n, *t2 = x + 5 * n;
+    float *r = S.AV + (int64_t)base * m, *du = r + m, *jr = r + 2 * m;
+    double *c = S.cgs;
+    double *one = c + 6, *d1 = c + 7, *d2 = c + 9;
+    struct {
+        int nx, ny, F, temporal;
+    } const dims{S.g.nx, S.g.ny, S.F, S.cfg.temporal};
+    RC(k_fill_f64(one, 1, 1.0, s));
+    RC(k_psi_weights(S.u, dims.nx, dims.ny, dims.F, dims.temporal, (float)S.cfg.eps, S.w, s));
+    {
+        FwdOptions o;
+        o.y = r;
+        o.bres = bvec;
+        o.write_resid = 1;
+        o.dy = du;
+        RC(launch_project_ex(S.ctx, S.g, b, 1, S.u, theta, o, s));
+    }
+    // rhs = -(D^T r + A^T D u); x = 0, residual = p = rhs
+    RC(launch_backproject_dtheta(S.ctx, S.g, b, 1, r, theta, t1, s));
+    RC(launch_backproject(S.ctx, S.g, b, 1, du, theta, t1, s, 1));
+    RC(k_gemv(t1, n, 1, one, -1.0, nullptr, 0.0, n, rc, s));
+    RC(k_gemv(rc, n, 1, one, 1.0, nullptr, 0.0, n, p, s));
+    RC(k_gemv(rc, n, 1, one, 0.0, nullptr, 0.0, n, x, s));
+    RC(k_multidot(rc, n, 1, rc, nullptr, n, S.part_md, S.md_blocks, c + 0, 1, s));
+    TvEpilogue tv;
+    tv.w = S.w;
+    tv.lamp = S.sc + S_LAM;
+    tv.temporal = S.cfg.temporal;
+    tv.e2 = (float)S.cfg.eps * (float)S.cfg.eps;
+    for (int it = 0; it < iters; ++it) {
+        FwdOptions o;
+        o.y = jr;
+        RC(launch_project_ex(S.ctx, S.g, b, 1, p, theta, o, s));
+        tv.u = p;
+        RC(launch_backproject(S.ctx, S.g, b, 1, jr, theta, q, s, 0, &tv));   // q = M p
+        RC(k_multidot(p, n, 1, q, nullptr, n, S.part_md, S.md_blocks, c + 1, 1, s));
+        RC(k_cg_coef(c, 0, s));
+        RC(k_gemv(p, n, 1, c + 3, 1.0, x, 1.0, n, x, s));     // x += alpha p
+        RC(k_gemv(q, n, 1, c + 4, 1.0, rc, 1.0, n, rc, s));   // r -= alpha M p
+        RC(k_multidot(rc, n, 1, rc, nullptr, n, S.part_md, S.md_blocks, c + 2, 1, s));
+        RC(k_cg_coef(c, 1, s));
+        RC(k_gemv(p, n, 1, c + 5, 1.0, rc, 1.0, n, p, s));    // p = r + beta p
+    }
+    // J_r = D u + A u_p; [J_r^T J_r, r^T J_r]
+    {
+        FwdOptions o;
+        o.y = jr;
+        RC(launch_project_ex(S.ctx, S.g, b, 1, x, theta, o, s));
+    }
+    RC(k_gemv(du, m, 1, one, 1.0, jr, 1.0, m, jr, s));
+    RC(k_multidot(jr, m, 1, jr, r, m, S.part_md, S.md_blocks, d1, 1, s));
+    // [u_p^T Psi^T w Psi u, u_p^T Psi^T w Psi u_p]
+    // zero t1, t2 (scaling a finite vector by 0: the spare columns may hold anything)
+    RC(k_gemv(rc, n, 1, one, 0.0, nullptr, 0.0, n, t1, s));
+    RC(k_gemv(rc, n, 1, one, 0.0, nullptr, 0.0, n, t2, s));
+    RC(k_tv_grad_add(S.u, S.w, dims.nx, dims.ny, dims.F, dims.temporal, one, t1, s));
+    RC(k_tv_grad_add(x, S.w, dims.nx, dims.ny, dims.F, dims.temporal, one, t2, s));
+    RC(k_multidot(t1, n, 2, x, nullptr, n, S.part_md, S.md_blocks, d2, 1, s));
+    RC(k_offset_gn(d1, d2, S.sc + S_LAM, out, s));
+    if (up_out) RC(k_copy_cols(x, n, up_out, n, 1, n, s));
+    return NLRMM_OK;
+}
+
 }  // namespace nlrmm
 
 using namespace nlrmm;
@@ -568,6 +649,7 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
         (rc = S->alloc(&S->AV, (size_t)S->kcap * S->mmax)) ||
         (rc = S->alloc(&S->Vtmp, (size_t)c.kmin * big)) || (rc = S->alloc(&S->u, S->n)) ||
         (rc = S->alloc(&S->uh, S->n)) || (rc = S->alloc(&S->zh, S->ld)) ||
+        (rc = S->alloc(&S->cgs, 16)) ||
         (rc = S->alloc(&S->r, S->n)) || (rc = S->alloc(&S->rho, S->mmax)) ||
         (rc = S->alloc(&S->w, npsi_max)) || (rc = S->alloc(&S->GA, S->ld * S->ld)) ||
         (rc = S->alloc(&S->GP, S->ld * S->ld)) || (rc = S->alloc(&S->rb, S->ld)) ||
@@ -645,6 +727,18 @@ int nlrmm_solver_grid_search(nlrmm_solver *S, const nlrmm_batch *batch, double *
     }
     return grid_search(*S, *batch, theta, b, shifts, ncand, ell0, res2, best,
                        (hipStream_t)stream);
+}
+
+int nlrmm_solver_offset_sensitivity(nlrmm_solver *S, const nlrmm_batch *batch,
+                                    const double *theta, const float *b, int32_t iters,
+                                    double *out, float *up, void *stream)
+{
+    if (!S || !theta || !b || !out) return NLRMM_EINVAL;
+    int rc = check_batch(batch);
+    if (rc) return rc;
+    if (batch->nframes != S->F || batch->nviews > S->maxV) return NLRMM_ESHAPE;
+    if (iters < 1) return NLRMM_EINVAL;
+    return offset_sensitivity(*S, *batch, theta, b, iters, out, up, (hipStream_t)stream);
 }
 
 int nlrmm_solver_outer(nlrmm_solver *S, const nlrmm_batch *batch, double *theta, const float *b,

@@ -104,6 +104,21 @@ class Solver:
               "nlrmm_solver_grid_search")
         return res2, best
 
+    def offset_sensitivity(self, theta: torch.Tensor, b: torch.Tensor, iters: int = 100,
+                           frames=None):
+        """Full-space sensitivity for one global angle offset at the current image
+        (nlrmm_solver_offset_sensitivity): returns ([g, h, dp] float64, u_p float32) device
+        tensors."""
+        bt = ops._batch(frames, theta.numel())
+        out = torch.empty(3, dtype=torch.float64, device=theta.device)
+        up = torch.empty(self.n, dtype=torch.float32, device=theta.device)
+        check(_lib.lib().nlrmm_solver_offset_sensitivity(self.h, ctypes.byref(bt),
+                                                         theta.data_ptr(), b.data_ptr(),
+                                                         int(iters), out.data_ptr(),
+                                                         up.data_ptr(), self._stream()),
+              "nlrmm_solver_offset_sensitivity")
+        return out, up
+
     def outer(self, theta: torch.Tensor, b: torch.Tensor, delta: float, frames=None) -> None:
         """One outer iteration; theta (float64, device) is updated in place."""
         bt = ops._batch(frames, theta.numel())

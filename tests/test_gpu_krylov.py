@@ -359,3 +359,40 @@ def test_grid_search_matches_oracle():
     if (order[1] - order[0]) / bb > 1e-5:
         assert int(best.cpu()[0]) == best_ora
     assert np.array_equal(th.cpu().numpy(), inst.theta_nom + shifts[int(best.cpu()[0])])
+
+
+def test_offset_sensitivity_matches_oracle():
+    """Full-space sensitivity for one global offset (nlrmm_solver_offset_sensitivity) at the
+    image and lambda of one outer iteration, against the dense oracle of eq. "sensitivity" on
+    the same u (FP32 values), weights of u and lambda: u_p, g, h and dp."""
+    N, nb, V = 24, 35, 30
+    rng = np.random.default_rng(31)
+    geo = M.Geometry(N=N, nb=nb, view_off=np.array([0, V], dtype=np.int64))
+    x = synth.ellipse_image(N, [0.1, -0.3], [0.0, 0.2], [0.5, 0.2], [0.3, 0.25], [0.3, 1.0],
+                            [1.0, 0.5]).reshape(-1)
+    th = np.arange(V) * math.pi / V + rng.normal(0, 0.01, V)
+    g = ops.geom(N, nb)
+    b64, e = M.make_data(geo, x, th, rng.standard_normal(geo.m), 0.01)
+    b32 = b64.astype(np.float32)
+    cfg = Config(kmin=3, kmax=12, eps=1e-2, param_update=0)
+    sol = Solver(g, 1, V, cfg)
+    tht, bt = dev(th, torch.float64), dev(b32, torch.float32)
+    sol.init(tht, bt)
+    sol.outer(tht, bt, float(np.linalg.norm(e)))
+    u, sc, _ = sol.read()
+    out, up = sol.offset_sensitivity(tht, bt, iters=400)
+    torch.cuda.synchronize()
+    sol.close()
+    u64 = u.cpu().numpy().astype(np.float64)
+    lam = float(sc.cpu().numpy()[2])
+    w = M.weights(geo, u64, 1e-2)
+    up_ref, g_ref, h_ref, dp_ref = M.offset_sensitivity(geo, th, u64, b32.astype(np.float64), w,
+                                                         lam)
+    o = out.cpu().numpy()
+    up = up.cpu().numpy().astype(np.float64)
+    print(f"offset sensitivity: u_p {rel(up, up_ref):.2e}  g {o[0]:.6e}/{g_ref:.6e}  "
+          f"h {o[1]:.6e}/{h_ref:.6e}  dp {o[2]:.6e}/{dp_ref:.6e}  lam {lam:.3e}", flush=True)
+    assert rel(up, up_ref) <= 1e-3
+    assert abs(o[0] - g_ref) <= 1e-3 * abs(g_ref)
+    assert abs(o[1] - h_ref) <= 1e-3 * abs(h_ref)
+    assert abs(o[2] - dp_ref) <= 2e-3 * abs(dp_ref)

@@ -372,3 +372,30 @@ def test_grid_search_residual_bounds():
         xf, *_ = np.linalg.lstsq(A, b, rcond=None)
         full = float(np.sum((A @ xf - b) ** 2))
         assert full - 1e-9 * (b @ b) <= r2 <= b @ b
+
+
+def test_offset_sensitivity_by_finite_differences():
+    """Full-space sensitivity for a global offset (eq. "sensitivity"): at the closed-form
+    u(p) = M(p)^-1 A(p)^T b of eq. "u_closed_form" (weights fixed), u_p equals the central
+    difference of u(p), and g equals the derivative of the reduced objective
+    f(p) = 1/2 ||A(p) u(p) - b||^2 + lam/2 ||sqrt(w) Psi u(p)||^2."""
+    geo, x, th, _, b, _ = small_problem(N=8, nb=13, V=10)
+    lam = 0.05
+    w = M.weights(geo, x, 0.05)
+    Psi = dense_psi(geo)
+
+    def closed(p):
+        A, _ = P.dense(geo.N, geo.nb, th + p)
+        Mm = A.T @ A + lam * Psi.T @ (w[:, None] * Psi)
+        u = np.linalg.solve(Mm, A.T @ b)
+        f = 0.5 * np.sum((A @ u - b) ** 2) + 0.5 * lam * np.sum(w * (Psi @ u) ** 2)
+        return u, f
+
+    u0, _ = closed(0.0)
+    up, g, hh, dp = M.offset_sensitivity(geo, th, u0, b, w, lam)
+    e = 1e-6
+    (u1, f1), (u2, f2) = closed(e), closed(-e)
+    fd_u = (u1 - u2) / (2 * e)
+    assert np.linalg.norm(up - fd_u) <= 1e-6 * np.linalg.norm(fd_u)
+    assert abs(g - (f1 - f2) / (2 * e)) <= 1e-6 * abs(g)
+    assert hh > 0 and dp == -g / hh
