@@ -51,5 +51,7 @@ def test_host_validation_without_device():
                                         None) == -1
     assert lib.nlrmm_solver_grid_search(None, ctypes.byref(b), 1, 1, 1, 3, 10, None, None,
                                         None) == -1
+    assert lib.nlrmm_solver_offset_sensitivity(None, ctypes.byref(b), 1, 1, 10, 1, None,
+                                               None) == -1
     assert lib.nlrmm_strerror(-2) == b"inconsistent or unsupported sizes"
     assert lib.nlrmm_version() >= 100
