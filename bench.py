@@ -56,7 +56,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dynamic", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--no-workloads", action="store_true",
-                    help="skip the operator rates at every workload shape and the VarPro leg")
+                    help="skip the extra legs: operator rates at every workload shape, VarPro, "
+                         "autograd, precision policy, streaming and the sensitivity solve")
     ap.add_argument("--ops-only", action="store_true",
                     help="only the operator timings and the copy calibration")
     ap.add_argument("--reps", type=int, default=20, help="repetitions per operator timing")
@@ -458,14 +459,16 @@ def main():
     dth0 = inst.theta_true - inst.theta_nom
     perr = float(np.linalg.norm(theta.cpu().numpy() - inst.theta_true) / np.linalg.norm(dth0))
     # full-space sensitivity of one global offset at the current image (CG on A^T A + lam R)
-    sens_iters = 50
-    sol.offset_sensitivity(theta, b, iters=sens_iters)
-    sens_ms = timed_steps(torch, lambda: sol.offset_sensitivity(theta, b, iters=sens_iters), 3,
-                          stream, "c2 offset sensitivity")
-    sens_out, _ = sol.offset_sensitivity(theta, b, iters=sens_iters)
-    sensitivity = {"ms_per_solve": round(sens_ms, 3), "cg_iterations": sens_iters,
-                   "ms_per_cg_iteration": round(sens_ms / sens_iters, 4),
-                   "g_h_dp": [float(v) for v in sens_out.cpu().numpy()]}
+    sensitivity = None
+    if not args.no_workloads:
+        sens_iters = 50
+        sol.offset_sensitivity(theta, b, iters=sens_iters)
+        sens_ms = timed_steps(torch, lambda: sol.offset_sensitivity(theta, b, iters=sens_iters),
+                              3, stream, "c2 offset sensitivity")
+        sens_out, _ = sol.offset_sensitivity(theta, b, iters=sens_iters)
+        sensitivity = {"ms_per_solve": round(sens_ms, 3), "cg_iterations": sens_iters,
+                       "ms_per_cg_iteration": round(sens_ms / sens_iters, 4),
+                       "g_h_dp": [float(v) for v in sens_out.cpu().numpy()]}
     sol.close()
 
     nnz, call_ms, kern_ms = operators(torch, ops, metrics, inst, wl, g, x32, th_true, b,
