@@ -19,14 +19,17 @@
 // bins that meet at the edge, so each application evaluates Phi ~2 per edge-line
 // instead of ~2 per (ray, pixel) nonzero.  No atomics; results are deterministic.
 //
-// Forward lanes of one block are 64 consecutive edges; the block's waves split each edge's
-// line range (1..8 waves, tuned per shape) and their partial sums meet in LDS.
+// Forward lanes of one block are 64 consecutive edges; every wave of the block walks the
+// union of the 64 edges' line ranges (one pack load of a wave reads neighbouring entries of
+// one line), the block's waves split that union (1..8 waves, tuned per shape), four lines
+// per step with their loads in flight together, and their partial sums meet in LDS.
 //
-// Backward (pixel-driven gather): one lane per pixel of a 16x16 tile; for chunks of
+// Backward (pixel-driven gather): one lane per pixel pair of a 16x16 tile; for chunks of
 // views the tile's detector window is staged in LDS, each pixel locates its footprint
 // in bin units relative to the tile centre (FP64), evaluates Phi at the <= E edges inside
 // it (FP32 offsets) and gathers its <= E+1 bins.  Same weight function as the forward;
-// the two are transposes up to FP32 rounding of the offsets.
+// the two are transposes up to FP32 rounding of the offsets.  The derivative's transpose
+// gathers the chord moments at the same edges the same way.
 #include "internal.h"
 #include "tv.h"
 
