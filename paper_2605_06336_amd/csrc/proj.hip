@@ -458,6 +458,16 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
         const float c2b = (float)(w.wo - 2.0 * step + (double)w.fwi);
         const float c3b = (float)(w.wo - 2.0 * step - (double)w.fwi);
         const PackEntry *pline = pack + img0 * pstride + (int64_t)sa * (nminor + 3) + 1;
+        // Along-ray coordinate of the centre of pixel k on line L, affine in both indices:
+        // t(L, k) = tS + (L - sa) d tl + k d tm, with tS the value at (sa, 0) in FP64; each
+        // line takes one FP64 FMA, each pixel one FP32 FMA.
+        double tS = 0.0, dtl = 0.0;
+        float dtmf = 0.0f;
+        if (MOM) {
+            tS = pix_coord(line0, a.d, sa) * tl + pix_coord(minor0, a.d, 0) * tm;
+            dtl = a.d * tl;
+            dtmf = (float)(a.d * tm);
+        }
         auto walk = [&](auto ascending) __attribute__((always_inline)) {
             constexpr bool ASC = decltype(ascending)::value;
             // Entry of line L at walk position rl: clamping the position itself is exact
@@ -481,17 +491,17 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
                 }
                 if (MOM) {
                     const int K0 = K1 - 1;
-                    const int ka = ASC ? K0 : nminor - 1 - K0;
-                    const int kb = ASC ? K0 + 1 : nminor - 2 - K0;
+                    const int ka = ASC ? K0 : nminor - 1 - K0;   // kb = ka + 1 (ka - 1)
                     const float va = fmaf(dr, stepf, c0a);
                     const float vb = va - stepf;
-                    const double lc = pix_coord(line0, a.d, L);
-                    const double tb = lc * tl;
+                    const float tLf = (float)fma((double)(L - sa), dtl, tS);
+                    const float ta = fmaf((float)ka, dtmf, tLf);
+                    const float tb = ASC ? ta + dtmf : ta - dtmf;
                     float La, Lb, mua, mub;
                     moment_f(va, w, La, mua);
                     moment_f(vb, w, Lb, mub);
-                    ma = La * ((float)(tb + pix_coord(minor0, a.d, ka) * tm) + mua);
-                    mb = Lb * ((float)(tb + pix_coord(minor0, a.d, kb) * tm) + mub);
+                    ma = La * (ta + mua);
+                    mb = Lb * (tb + mub);
                 }
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
