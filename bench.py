@@ -46,6 +46,8 @@ FLOP_PER_SAMPLE = 10.0              # algorithmic FP32 flops per applied strip-a
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd_edges_c2.json")
 COPY_BYTES = 256 << 20              # calibration copy for the HBM byte counters
 KERNEL_REPS = 10                    # back-to-back launches per event-timed kernel
+HBM_PEAK_GBS = 8000.0               # MI355X HBM3E
+MFMA_PEAK_TFLOPS = {1: 157.3, 2: 2500.0}   # dense matrix-core peaks: FP32, BF16
 
 
 def parse():
@@ -60,6 +62,8 @@ def parse():
                          "autograd, precision policy, streaming and the sensitivity solve")
     ap.add_argument("--ops-only", action="store_true",
                     help="only the operator timings and the copy calibration")
+    ap.add_argument("--gram-only", action="store_true",
+                    help="only the regulariser-Gram timings on the matrix cores")
     ap.add_argument("--reps", type=int, default=20, help="repetitions per operator timing")
     ap.add_argument("--gram-precision", type=int, default=1, choices=(0, 1, 2),
                     help="regulariser Gram: 0 FP64 vector, 1 FP32 MFMA, 2 BF16 MFMA")
@@ -333,6 +337,49 @@ def precision_leg(torch, ops, synth, Config, Solver, steps, warmup):
     return out
 
 
+def gram_leg(torch, ops, synth, reps):
+    """The weighted regulariser Gram (Psi V)^T diag(w) (Psi V) on the matrix cores at the c2
+    and c5 image sizes with the basis widths their solvers reach (kmax), FP32 and BF16
+    operands.  Algorithmic work: the symmetric half, npsi * ell * (ell + 1) flop; algorithmic
+    bytes: V (4 n ell) and w (4 npsi) read once."""
+    res = {}
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    for name in ("c2", "c5"):
+        wl = synth.WORKLOADS[name]
+        g = ops.geom(wl.N, wl.nb)
+        n = wl.N * wl.N
+        ell = wl.kmax
+        V = torch.randn((ell, n), generator=gen, device="cuda", dtype=torch.float32)
+        u = torch.rand(n, generator=gen, device="cuda", dtype=torch.float32)
+        w = ops.tv_weights(u, g, eps=wl.eps)
+        npsi = w.numel()
+        flop = float(npsi) * ell * (ell + 1)
+        nbytes = 4.0 * n * ell + 4.0 * npsi
+        entry = {"n": n, "ell": ell, "npsi": npsi}
+        for label, prec in (("fp32_mfma", 1), ("bf16_mfma", 2)):
+            for _ in range(2):
+                ops.gram_psi(V, w, g, ell, precision=prec)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                ops.gram_psi(V, w, g, ell, precision=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            tf = flop / (ms * 1e-3) / 1e12
+            gbs = nbytes / (ms * 1e-3) / 1e9
+            entry[label] = {"ms": round(ms, 4), "tflops": round(tf, 2),
+                            "mfma_peak_tflops": MFMA_PEAK_TFLOPS[prec],
+                            "mfma_frac": round(tf / MFMA_PEAK_TFLOPS[prec], 4),
+                            "gb_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        res[name] = entry
+        del V, u, w
+    return res
+
+
 def streaming_leg(torch, ops, synth, Config, steps):
     """ms per block of s-NL-RMM-GKS at the full streaming shape (2048x2048, 1440 views in 64
     blocks of 22-23, 2897 bins, kmax 50, BF16 Grams and compression products).  The image is
@@ -422,6 +469,11 @@ def main():
     from paper_2605_06336_amd import metrics, ops, synth
     from paper_2605_06336_amd.solver import Config, OuterGraph, Solver
 
+    if args.gram_only:
+        print(json.dumps({"gram_only": True, "gram_mfma": gram_leg(torch, ops, synth, args.reps)}),
+              flush=True)
+        return
+
     wl = synth.WORKLOADS["c2"]
     inst = synth.draw(wl)
     V = wl.n_views
@@ -478,10 +530,13 @@ def main():
 
     def roof(kernel, ms):
         achieved = nnz * FLOP_PER_SAMPLE / (ms * 1e-3) / 1e12
+        traffic = traffic_for(kernel)
         return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3),
                 "peak": FP32_NONPACKED_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_NONPACKED_PEAK_TFLOPS, 4),
-                "traffic": traffic_for(kernel), "launch_ms": round(ms, 5),
+                "traffic": traffic,
+                "hbm_gb_s": round(traffic / (ms * 1e-3) / 1e9, 1) if traffic else None,
+                "launch_ms": round(ms, 5),
                 "samples_per_launch": int(nnz), "flop_per_sample": FLOP_PER_SAMPLE}
 
     # dominant kernel of the outer iteration: the forward-weights kernel of the projection
@@ -493,8 +548,9 @@ def main():
         dyn = dynamic_leg(torch, ops, synth, Config, OuterGraph, Solver, max(3, args.steps // 2),
                           2, args.gram_precision)
 
-    per_workload = varpro = autograd_r = precision = streaming = None
+    per_workload = varpro = autograd_r = precision = streaming = gram = None
     if not args.no_workloads:
+        gram = gram_leg(torch, ops, synth, max(3, args.reps // 2))
         per_workload = workload_operators(torch, ops, metrics, synth, max(3, args.reps // 4))
         varpro = varpro_leg(torch, ops, synth, Config, Solver, max(3, args.steps // 2), 2,
                             args.gram_precision)
@@ -554,6 +610,7 @@ def main():
         "autograd_c3": autograd_r,
         "precision_policy_c2": precision,
         "streaming_c5": streaming,
+        "gram_mfma": gram,
         "roofline": roofline,
         "roofline_backproject": roofline_bwd,
         "cpu_baseline": cpu,

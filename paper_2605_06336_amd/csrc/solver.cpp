@@ -91,6 +91,17 @@ namespace nlrmm {
 
 static int64_t m_of(const Solver &S, const nlrmm_batch &b) { return b.nviews * S.g.nbins; }
 
+// Enough blocks for the inner products and the regulariser Gram to keep every CU busy on
+// large images (a few elements per thread, 16 pixel chunks per Gram block); the minimum of
+// 512 serves images up to 512x512 (512 Gram blocks measured best at 256x256).
+static void size_blocks(Solver &S, int64_t n, int64_t m)
+{
+    const int64_t big = n > m ? n : m;
+    const int64_t md = (big + 1023) / 1024, gb = (n / 64 + 15) / 16;
+    S.md_blocks = (int)(md < 512 ? 512 : md > 2048 ? 2048 : md);
+    S.gram_blocks = (int)(gb < 512 ? 512 : gb > 2048 ? 2048 : gb);
+}
+
 static bool per_frame(const Solver &S, const nlrmm_batch &b)
 {
     return S.plain && b.nframes > 1 && (int64_t)S.vo_host.size() == (int64_t)b.nframes + 1;
@@ -636,14 +647,7 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
     S->ld = S->kcap;
     S->nchunks = fwd_chunks(*geom);
     const int64_t big = S->n > S->mmax ? S->n : S->mmax;
-    // enough blocks for the inner products and the regulariser Gram to keep every CU busy on
-    // large images (a few elements per thread, 16 pixel chunks per Gram block); the defaults
-    // serve images up to 512x512 (512 Gram blocks measured best at 256x256)
-    {
-        const int64_t md = (big + 1023) / 1024, gb = (S->n / 64 + 15) / 16;
-        S->md_blocks = (int)(md < 512 ? 512 : md > 2048 ? 2048 : md);
-        S->gram_blocks = (int)(gb < 512 ? 512 : gb > 2048 ? 2048 : gb);
-    }
+    size_blocks(*S, S->n, S->mmax);
     const int64_t npsi_max = (int64_t)nframes * 2 * geom->nx * geom->ny + (int64_t)nframes * geom->nx * geom->ny;
     if ((rc = S->alloc(&S->V, (size_t)S->kcap * S->n)) ||
         (rc = S->alloc(&S->AV, (size_t)S->kcap * S->mmax)) ||
@@ -805,6 +809,7 @@ static int scratch_view(nlrmm_ctx *ctx, Solver &S, int64_t n, int64_t m, int kca
                         hipStream_t s)
 {
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    size_blocks(S, n, m);
     const int64_t big = n > m ? n : m;
     const size_t bytes = al(sizeof(float) * n) * 2 + al(sizeof(float) * m) +
                          al(sizeof(float) * (size_t)kmin * big) +
