@@ -2,10 +2,12 @@
 
 Each check is independent of the oracle's own formulas: polygon clipping for the
 strip-area weights, the projection of the whole square and of a disk in closed
-form, mass conservation, the adjoint identity, rotation/reflection symmetries
-and central finite differences of clipped areas for the angle derivative.
+form, mass conservation, the adjoint identity, rotation/reflection symmetries,
+central finite differences of clipped areas for the angle derivative, and the stored
+hand-derived weights of a 2x2 image (tests/golden/).
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -16,6 +18,38 @@ from tests import brute
 
 SPECIAL = [0.0, math.pi / 4, math.pi / 2, 3 * math.pi / 4, 1e-7, math.pi / 2 - 1e-9,
            0.3, 1.1, 2.0, 2.9, math.pi - 1e-3]
+
+
+def test_golden_strip_weights_2x2():
+    """The stored strip-area weights of a 2x2 image at 0, pi/4 and pi/2 (written out from
+    interval overlaps and corner-triangle areas by tests/golden/make_strip_weights.py) equal
+    the oracle's weights, read as its projection of each unit pixel."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "strip_weights_2x2.txt")
+    names = {"0": 0.0, "pi/4": math.pi / 4, "pi/2": math.pi / 2}
+    want = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            name, j, l, k, w = line.split()
+            want[(name, int(j), int(l), int(k))] = float(w)
+    assert len(want) == 3 * 5 * 4
+    th = np.array(list(names.values()))
+    for l in range(2):
+        for k in range(2):
+            img = np.zeros((2, 2))
+            img[l, k] = 1.0
+            y = P.project(img, th, 5)
+            for v, name in enumerate(names):
+                for j in range(5):
+                    assert abs(y[v, j] - want[(name, j, l, k)]) < 1e-13, (name, j, l, k)
+    # each pixel's weights integrate to its area in every view
+    for name in names:
+        for l in range(2):
+            for k in range(2):
+                tot = sum(want[(name, j, l, k)] for j in range(5)) * (2.84 / 5)
+                assert abs(tot - 1.0) < 1e-13
 
 
 @pytest.mark.parametrize("N,nb", [(8, 13), (6, 11), (10, 9)])
