@@ -11,6 +11,13 @@ pixel's x (y) interval with the bin.  theta = pi/4: s = (x + y) / sqrt 2, and th
 pixel with x + y <= t has area u^2 / 2 (0 <= u <= D), D^2 - (2D - u)^2 / 2 (D <= u <= 2D),
 with u = t - x0 - y0 and (x0, y0) the pixel's lower-left corner.
 
+Also writes dtheta_2x2.txt: d a[v][j][l][k] / d theta_v = (M(e_j) - M(e_{j+1})) / ds, with
+M(e) the integral of p . t (t = (-sin, cos)) along the chord {p in Q : p . n = e} (the
+boundaries of the strip turn with theta, and a point p of a boundary line moves across it at
+rate p . t).  At theta = 0 the chord is the vertical segment x = e across the pixel and
+M(e) = D * (y centre); at theta = pi/2 it is the horizontal segment y = e and
+M(e) = -D * (x centre); M(e) = 0 when the line misses the pixel.
+
 Run from the repository root: python tests/golden/make_strip_weights.py
 """
 import math
@@ -50,6 +57,13 @@ def weight(name, j, l, k):
     return area / DS
 
 
+def moment(name, e, l, k):
+    x0, y0 = -1.0 + k * D, -1.0 + l * D
+    if name == "0":
+        return D * (y0 + 0.5 * D) if x0 < e < x0 + D else 0.0
+    return -D * (x0 + 0.5 * D) if y0 < e < y0 + D else 0.0
+
+
 def main():
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "strip_weights_2x2.txt")
     with open(out, "w") as f:
@@ -61,6 +75,18 @@ def main():
                 for l in range(N):
                     for k in range(N):
                         f.write(f"{name} {j} {l} {k} {weight(name, j, l, k):.17g}\n")
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "dtheta_2x2.txt")
+    with open(out, "w") as f:
+        f.write("# d a[v][j][l][k] / d theta_v of a 2x2 image, 5 bins on [-1.42, 1.42]\n")
+        f.write("# (Section 1, eq. nonlinear_forward; chord moments, see make_strip_weights.py)\n")
+        f.write("# theta j l k derivative\n")
+        for name in ("0", "pi/2"):
+            for j in range(NB):
+                e0, e1 = -1.42 + j * DS, -1.42 + (j + 1) * DS
+                for l in range(N):
+                    for k in range(N):
+                        dv = (moment(name, e0, l, k) - moment(name, e1, l, k)) / DS
+                        f.write(f"{name} {j} {l} {k} {dv:.17g}\n")
 
 
 if __name__ == "__main__":

@@ -1,6 +1,7 @@
 """GPU parity of the projector family (nlrmm_project / _backproject / _project_dtheta)
 against the FP64 oracle on the same seeded inputs.  Bar: relative L2 <= 1e-5 (FP32)."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -39,6 +40,42 @@ CASES = [
     (256, 363, 40, 1, 9),
     (48, 69, 0, 3, 2),
 ]
+
+
+def _golden(name):
+    want = {}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            t, j, l, k, w = line.split()
+            want[(t, int(j), int(l), int(k))] = float(w)
+    return want
+
+
+@pytest.mark.gpu
+def test_golden_2x2_weights_and_derivative():
+    """The library's weights and angle derivatives of a 2x2 image (each unit pixel as one
+    column) against the hand-derived values in tests/golden/, at the FP32 bar."""
+    g = ops.geom(2, 5)
+    x = torch.zeros((4, 1, 2, 2), dtype=torch.float32, device="cuda")
+    for c in range(4):
+        x[c, 0, c // 2, c % 2] = 1.0
+    W = _golden("strip_weights_2x2.txt")
+    names = ["0", "pi/4", "pi/2"]
+    th = dev(np.array([0.0, math.pi / 4, math.pi / 2]), torch.float64)
+    y = ops.project(x, th, g).cpu().numpy().reshape(4, 3, 5)
+    ref = np.array([[[W[(t, j, c // 2, c % 2)] for j in range(5)] for t in names]
+                    for c in range(4)])
+    assert rel(y, ref) <= 1e-5 and np.max(np.abs(y - ref)) < 1e-6
+    Dg = _golden("dtheta_2x2.txt")
+    names = ["0", "pi/2"]
+    th = dev(np.array([0.0, math.pi / 2]), torch.float64)
+    dy = ops.project_dtheta(x, th, g)["dy"].cpu().numpy().reshape(4, 2, 5)
+    ref = np.array([[[Dg[(t, j, c // 2, c % 2)] for j in range(5)] for t in names]
+                    for c in range(4)])
+    assert rel(dy, ref) <= 1e-5 and np.max(np.abs(dy - ref)) < 1e-5
 
 
 def frames_for(F, seed):

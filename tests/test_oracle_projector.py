@@ -52,6 +52,31 @@ def test_golden_strip_weights_2x2():
                 assert abs(tot - 1.0) < 1e-13
 
 
+def test_golden_dtheta_2x2():
+    """The stored angle derivatives of the 2x2 weights at 0 and pi/2 (chord moments of the
+    strip boundaries written out by tests/golden/make_strip_weights.py) equal the oracle's
+    derivative of the projection of each unit pixel; this fixes the sign convention."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "dtheta_2x2.txt")
+    want = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            name, j, l, k, w = line.split()
+            want[(name, int(j), int(l), int(k))] = float(w)
+    assert len(want) == 2 * 5 * 4
+    names = ["0", "pi/2"]
+    th = np.array([0.0, math.pi / 2])
+    for l in range(2):
+        for k in range(2):
+            img = np.zeros((2, 2))
+            img[l, k] = 1.0
+            dy = P.dtheta(img, th, 5)
+            for v, name in enumerate(names):
+                for j in range(5):
+                    assert abs(dy[v, j] - want[(name, j, l, k)]) < 1e-13, (name, j, l, k)
+
+
 @pytest.mark.parametrize("N,nb", [(8, 13), (6, 11), (10, 9)])
 def test_weights_match_polygon_clipping(N, nb):
     th = np.array(SPECIAL + list(synth.random_angles(6, seed=N)))
