@@ -78,6 +78,27 @@ def test_golden_2x2_weights_and_derivative():
     assert rel(dy, ref) <= 1e-5 and np.max(np.abs(dy - ref)) < 1e-5
 
 
+@pytest.mark.gpu
+def test_golden_2x2_transposes():
+    """Backprojection and derivative transpose of every unit sinogram entry of the 2x2 case
+    (one column each) give the hand-derived weights and derivatives read along the pixels."""
+    g = ops.geom(2, 5)
+    W = _golden("strip_weights_2x2.txt")
+    Dg = _golden("dtheta_2x2.txt")
+    for fix, names, fn in ((W, ["0", "pi/4", "pi/2"], ops.backproject),
+                           (Dg, ["0", "pi/2"], ops.backproject_dtheta)):
+        V = len(names)
+        th = dev(np.array([{"0": 0.0, "pi/4": math.pi / 4, "pi/2": math.pi / 2}[t]
+                           for t in names]), torch.float64)
+        y = torch.zeros((V * 5, V, 5), dtype=torch.float32, device="cuda")
+        for c in range(V * 5):
+            y[c, c // 5, c % 5] = 1.0
+        x = fn(y, th, g).cpu().numpy().reshape(V * 5, 2, 2)
+        ref = np.array([[[fix[(names[c // 5], c % 5, l, k)] for k in range(2)]
+                         for l in range(2)] for c in range(V * 5)])
+        assert rel(x, ref) <= 1e-5 and np.max(np.abs(x - ref)) < 1e-5, fn.__name__
+
+
 def frames_for(F, seed):
     if F == 1:
         return None, None
