@@ -459,17 +459,24 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
         const float c3b = (float)(w.wo - 2.0 * step - (double)w.fwi);
         const PackEntry *pline = pack + img0 * pstride + (int64_t)sa * (nminor + 3) + 1;
         // Along-ray coordinate of the centre of pixel k on line L, affine in both indices:
-        // t(L, k) = tS + (L - sa) d tl + k d tm, with tS the value at (sa, 0) in FP64; each
-        // line takes one FP64 FMA, each pixel one FP32 FMA.
-        double tS = 0.0, dtl = 0.0;
-        float dtmf = 0.0f;
+        // t(L, k) = tS + (L - sa) d tl + k d tm, with tS the value at (sa, 0) formed in FP64.
+        // The walk's straddled pixel is k = K1 - 1 (ascending) or n - K1 (descending), so per
+        // walk direction t = tB + (L - sa) d tl + K1 ks with an FP32 base tB and signed step
+        // ks; the coordinates are O(1) on the unit square, so FP32 keeps them to ~1e-7.
+        double tS = 0.0;
+        float dtlf = 0.0f;
         if (MOM) {
             tS = pix_coord(line0, a.d, sa) * tl + pix_coord(minor0, a.d, 0) * tm;
-            dtl = a.d * tl;
-            dtmf = (float)(a.d * tm);
+            dtlf = (float)(a.d * tl);
         }
         auto walk = [&](auto ascending) __attribute__((always_inline)) {
             constexpr bool ASC = decltype(ascending)::value;
+            float tBf = 0.0f, ksf = 0.0f;
+            if (MOM) {
+                const double dtm = a.d * tm;
+                tBf = (float)(ASC ? tS - dtm : tS + (double)nminor * dtm);
+                ksf = (float)(ASC ? dtm : -dtm);
+            }
             // Entry of line L at walk position rl: clamping the position itself is exact
             // (beyond [0, n + 1] the entry's pixels are padding, or the edge lies past the
             // footprint of pixel 0); K1 = K0 + 1 and the fraction dr.
@@ -490,13 +497,11 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
                                w);
                 }
                 if (MOM) {
-                    const int K0 = K1 - 1;
-                    const int ka = ASC ? K0 : nminor - 1 - K0;   // kb = ka + 1 (ka - 1)
                     const float va = fmaf(dr, stepf, c0a);
                     const float vb = va - stepf;
-                    const float tLf = (float)fma((double)(L - sa), dtl, tS);
-                    const float ta = fmaf((float)ka, dtmf, tLf);
-                    const float tb = ASC ? ta + dtmf : ta - dtmf;
+                    const float tLf = fmaf((float)(L - sa), dtlf, tBf);
+                    const float ta = fmaf((float)K1, ksf, tLf);   // straddled pixel a
+                    const float tb = ta + ksf;                      // its neighbour b
                     float La, Lb, mua, mub;
                     moment_f(va, w, La, mua);
                     moment_f(vb, w, Lb, mub);
