@@ -913,10 +913,15 @@ __global__ __launch_bounds__(BWD_BLK) void bwd_moment_tiles_k(BwdArgs a)
             sj0[tid] = j0;
         }
         __syncthreads();
+        // staged as differences r_j - r_{j-1} (r = 0 outside the detector): the same FP32
+        // subtraction the per-pixel sum would make, done once per view
         for (int i = tid; i < nv * a.W; i += BWD_BLK) {
             const int vi = i / a.W, jj = i - vi * a.W;
             const int jbin = sj0[vi] + jj;
-            sy[vi][jj] = (jbin >= 0 && jbin < a.nb) ? ycol[(vb + vi) * a.nb + jbin] : 0.0f;
+            const float *yv = ycol + (vb + vi) * a.nb;
+            const float r1 = (jbin >= 0 && jbin < a.nb) ? yv[jbin] : 0.0f;
+            const float r0 = (jbin >= 1 && jbin - 1 < a.nb) ? yv[jbin - 1] : 0.0f;
+            sy[vi][jj] = r1 - r0;
         }
         __syncthreads();
         const float fds = (float)a.ds;
@@ -951,7 +956,7 @@ __global__ __launch_bounds__(BWD_BLK) void bwd_moment_tiles_k(BwdArgs a)
                 for (int i = 1; i <= E; ++i) {
                     float L, mu;
                     moment_f(fmaf(-fr, fds, q.cm[i - 1]), w, L, mu);
-                    sm = fmaf(L * (tc + mu), yy[i] - yy[i - 1], sm);
+                    sm = fmaf(L * (tc + mu), yy[i], sm);
                 }
                 sum[px] = sm;
             }
