@@ -46,6 +46,15 @@ int check_geom(const nlrmm_geom *g)
     return NLRMM_OK;
 }
 
+int check_op_geom(int ops, const nlrmm_geom *g)
+{
+    const int rc = check_geom(g);
+    if (rc) return rc;
+    if ((ops & NLRMM_OPS_FORWARD) && !fwd_geom_ok(*g)) return NLRMM_ESHAPE;
+    if ((ops & NLRMM_OPS_BACKWARD) && !bwd_geom_ok(*g)) return NLRMM_ESHAPE;
+    return NLRMM_OK;
+}
+
 int check_batch(const nlrmm_batch *b)
 {
     if (!b) return NLRMM_EINVAL;
@@ -87,7 +96,13 @@ const char *nlrmm_strerror(int code)
     }
 }
 
-int nlrmm_version(void) { return 100; }
+int nlrmm_version(void) { return 101; }
+
+int nlrmm_check_geom(int32_t ops, const nlrmm_geom *geom)
+{
+    if (ops & ~(NLRMM_OPS_FORWARD | NLRMM_OPS_BACKWARD)) return NLRMM_EINVAL;
+    return check_op_geom(ops, geom);
+}
 
 int nlrmm_ctx_create(nlrmm_ctx **out, int device)
 {
@@ -146,10 +161,10 @@ void nlrmm_ctx_destroy(nlrmm_ctx *ctx)
 int nlrmm_project(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
                   int32_t ncols, const float *x, const double *theta, float *y, void *stream)
 {
+    int rc = check_op_geom(NLRMM_OPS_FORWARD, geom);
+    if (rc) return rc;
     if (!ctx || !x || !theta || !y) return NLRMM_EINVAL;
     if (ncols < 1) return NLRMM_ESHAPE;
-    int rc = check_geom(geom);
-    if (rc) return rc;
     if ((rc = check_batch(batch))) return rc;
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
     return launch_project(ctx, *geom, *batch, ncols, x, theta, y, nullptr, nullptr, nullptr,
@@ -159,10 +174,10 @@ int nlrmm_project(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *bat
 int nlrmm_backproject(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
                       int32_t ncols, const float *y, const double *theta, float *x, void *stream)
 {
+    int rc = check_op_geom(NLRMM_OPS_BACKWARD, geom);
+    if (rc) return rc;
     if (!ctx || !x || !theta || !y) return NLRMM_EINVAL;
     if (ncols < 1) return NLRMM_ESHAPE;
-    int rc = check_geom(geom);
-    if (rc) return rc;
     if ((rc = check_batch(batch))) return rc;
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
     return launch_backproject(ctx, *geom, *batch, ncols, y, theta, x, (hipStream_t)stream);
@@ -172,10 +187,10 @@ int nlrmm_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm
                              int32_t ncols, const float *r, const double *theta, float *x,
                              void *stream)
 {
+    int rc = check_op_geom(NLRMM_OPS_BACKWARD, geom);
+    if (rc) return rc;
     if (!ctx || !x || !theta || !r) return NLRMM_EINVAL;
     if (ncols < 1) return NLRMM_ESHAPE;
-    int rc = check_geom(geom);
-    if (rc) return rc;
     if ((rc = check_batch(batch))) return rc;
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
     return launch_backproject_dtheta(ctx, *geom, *batch, ncols, r, theta, x,
@@ -187,12 +202,12 @@ int nlrmm_project_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_bat
                          float *yproj, const float *g, double *gdot, double *dnorm2,
                          void *stream)
 {
+    int rc = check_op_geom(NLRMM_OPS_FORWARD, geom);
+    if (rc) return rc;
     if (!ctx || !x || !theta) return NLRMM_EINVAL;
     if (!dy && !gdot && !dnorm2) return NLRMM_EINVAL;
     if (gdot && !g) return NLRMM_EINVAL;
     if (ncols < 1) return NLRMM_ESHAPE;
-    int rc = check_geom(geom);
-    if (rc) return rc;
     if ((rc = check_batch(batch))) return rc;
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
     return launch_project(ctx, *geom, *batch, ncols, x, theta, yproj, dy, g, gdot, dnorm2,
@@ -203,10 +218,10 @@ int nlrmm_backproject_acc(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_ba
                           int32_t ncols, const float *y, const double *theta, float *x,
                           int32_t accumulate, void *stream)
 {
+    int rc = check_op_geom(NLRMM_OPS_BACKWARD, geom);
+    if (rc) return rc;
     if (!ctx || !x || !theta || !y) return NLRMM_EINVAL;
     if (ncols < 1) return NLRMM_ESHAPE;
-    int rc = check_geom(geom);
-    if (rc) return rc;
     if ((rc = check_batch(batch))) return rc;
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
     return launch_backproject(ctx, *geom, *batch, ncols, y, theta, x, (hipStream_t)stream,
@@ -217,10 +232,10 @@ int nlrmm_project_residual(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_b
                            const float *x, const double *theta, const float *b, float *r,
                            double *rnorm2, void *stream)
 {
+    int rc = check_op_geom(NLRMM_OPS_FORWARD, geom);
+    if (rc) return rc;
     if (!ctx || !x || !theta || !b) return NLRMM_EINVAL;
     if (!r && !rnorm2) return NLRMM_EINVAL;
-    int rc = check_geom(geom);
-    if (rc) return rc;
     if ((rc = check_batch(batch))) return rc;
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
     FwdOptions o;

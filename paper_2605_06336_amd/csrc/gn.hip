@@ -136,6 +136,12 @@ __global__ void fill_f64_k(double *d, int64_t n, double v)
     if (i < n) d[i] = v;
 }
 
+__global__ void fill_f32_k(float *d, int64_t n, float v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = v;
+}
+
 __global__ void fill_i32_k(int *d, int64_t n, int v)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -317,6 +323,13 @@ int k_fill_f64(double *dst, int64_t n, double value, hipStream_t s)
 {
     fill_f64_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(dst, n, value);
     return LAUNCH_OK;
+}
+
+int k_fill_f32(float *dst, int64_t n, float value, hipStream_t s)
+{
+    if (n <= 0) return NLRMM_OK;
+    fill_f32_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(dst, n, value);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 
 int k_fill_i32(int *dst, int64_t n, int value, hipStream_t s)

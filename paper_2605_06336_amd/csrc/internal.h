@@ -57,6 +57,8 @@ int ensure_workspace(nlrmm_ctx *ctx, size_t bytes, hipStream_t stream);
 int ensure_buffer(Workspace &w, size_t bytes, hipStream_t stream);
 
 int check_geom(const nlrmm_geom *g);
+// check_geom plus the kernels' limits for the operator families in `ops` (NLRMM_OPS_*)
+int check_op_geom(int ops, const nlrmm_geom *g);
 
 // Autotuner cache: the tuned choice for a shape (0 when none) and storing a new one.
 int tune_lookup(const nlrmm_ctx *ctx, int kind, const nlrmm_geom &g, const nlrmm_batch &b, int nc);
@@ -65,8 +67,10 @@ void tune_store(nlrmm_ctx *ctx, int kind, const nlrmm_geom &g, const nlrmm_batch
 // Forward: waves per block sharing an edge's lines (1, 2, 4 or 8); column bucket of a group.
 int fwd_seg_for(const nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int nc_bucket);
 int fwd_nc_bucket(int nc);
-// Backprojection: candidates of the view split and the largest one (workspace bound).
+// Backprojection: the largest view split (workspace bound) and the split a launch uses
+// (forced, tuned or default, clamped to [1, bwd_split_max]).
 int bwd_split_max(const nlrmm_geom &g, const nlrmm_batch &b);
+int bwd_split_for(const nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols);
 
 // Record the start / stop event of timed kernel `which` on stream s (no-op unless enabled).
 void timing_mark(nlrmm_ctx *ctx, int which, int stop, hipStream_t s);
@@ -91,6 +95,12 @@ struct FwdOptions {
     bool keep_parts = false;       // leave per-chunk partials unreduced (caller reduces)
     bool write_resid = false;      // with bres: y receives y - b
 };
+
+// Geometry limits of the projector kernels (proj.hip): the forward family needs nx, ny <=
+// 4096 (line packs); the backward family needs at most 4 bin edges inside a pixel footprint
+// and a staged window of at most 64 bins per 16-pixel tile (ds >= about 0.38 d).
+int fwd_geom_ok(const nlrmm_geom &g);
+int bwd_geom_ok(const nlrmm_geom &g);
 
 // projector launchers (proj.hip); all arguments validated by the caller
 int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,

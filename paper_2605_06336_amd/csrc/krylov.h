@@ -76,6 +76,7 @@ int k_grid_residual(const double *G, int ldg, const double *rb, const double *bn
 int k_grid_pick(const double *res2, int ncand, const double *shifts, double *theta, int64_t V,
                 int *best, hipStream_t s);
 int k_fill_i32(int *dst, int64_t n, int value, hipStream_t s);
+int k_fill_f32(float *dst, int64_t n, float value, hipStream_t s);
 int k_view_dots(const float *X, int64_t ldx, int k, const float *e, int nb, int64_t V, double *out,
                 hipStream_t s);
 int k_varpro_reduced(const double *GA, int ldg, const double *GP, const double *ab,

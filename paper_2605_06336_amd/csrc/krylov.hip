@@ -9,7 +9,9 @@
 // Everything that decides (lambda, breakdown, compression size) is decided on the device.
 #include "internal.h"
 #include "krylov.h"
+#include "solve_reg_launch.h"
 #include "tv.h"
+#include "wave.h"
 
 #include <math.h>
 
@@ -20,40 +22,13 @@ namespace {
 
 constexpr int BLK = 256;
 constexpr int SOLVE_MAX = 56;
+using wave::dpp_mov;
+using wave::lane_bcast;
+using wave::wave_sum;
+using wave::wave_sum_dpp;
+
 constexpr int SOLVE_NT = 256;   // threads of the single-workgroup projected solves   // largest projected problem: two 56x57 FP64 matrices in LDS
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v)
-{
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__device__ __forceinline__ double lane_bcast(double v, int l)
-{
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v)
-{
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-// Sum over the 64 lanes, the same value (and summation order) in every lane.  Must be called
-// with all lanes active.
-__device__ __forceinline__ double wave_sum_dpp(double v)
-{
-    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
-    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
-    v += dpp_mov<0x141>(v);   // row_half_mirror
-    v += dpp_mov<0x140>(v);   // row_mirror
-    return (lane_bcast(v, 0) + lane_bcast(v, 16)) + (lane_bcast(v, 32) + lane_bcast(v, 48));
-}
 
 
 // block-wide sum of a double (all threads receive the result)
@@ -1321,650 +1296,6 @@ __global__ __launch_bounds__(TRI_NT) void gks_solve_tri_k(const double *__restri
     }
 }
 
-// Register-resident form of the same solve.  One wave; lane i keeps row i of the working
-// matrix in VGPRs, the problem is padded to NB (GA with the identity, GP with zeros, which
-// leaves every quantity of the first ell rows unchanged), and all loops over the padded size
-// are unrolled so that every register index is static.  Column broadcasts go through LDS
-// (one write, then broadcast reads), wave sums through DPP.  The discrepancy residual uses
-// continuants of I + lam T (no divisions):
-//   P_n = 1, P_{n+1} = 0, P_k = (1 + lam d_k) P_{k+1} - lam^2 e_k^2 P_{k+2},
-//   S_n = 0, S_k = lam^2 e_{k-1}^2 (P_{k+1}^2 + S_{k+1}),
-//   ||AV z(lam) - b||^2 = out2 + ||c||^2 (Q^2 + S_1) / P_0^2,  Q = lam d_0 P_1 - lam^2 e_0^2 P_2,
-// where Q / P_1 = D_0 - 1 and S_1 / P_1^2 = sum_{i>=1} (y_i / y_0)^2 in the notation above;
-// P, S are rescaled by powers of two so that they stay in range.
-// Compile-time loop: calls f(std::integral_constant<int, I>) for I = B .. E-1, so that loop
-// bodies too large for the unroller still see constant register indices.
-template <int B, int E>
-struct StaticFor {
-    template <class F>
-    static __device__ __forceinline__ void run(F &&f)
-    {
-        f(std::integral_constant<int, B>{});
-        StaticFor<B + 1, E>::run(f);
-    }
-};
-template <int E>
-struct StaticFor<E, E> {
-    template <class F>
-    static __device__ __forceinline__ void run(F &&)
-    {
-    }
-};
-
-// Empty register pins: force every element of a register array to be materialised here, so
-// that the compiler does not sink the updates of one elimination step into later steps (which
-// keeps the broadcast operands of all steps live at once).
-template <int NB>
-__device__ __forceinline__ void pin_regs(double (&v)[NB])
-{
-#pragma unroll
-    for (int k = 0; k < NB; ++k) asm volatile("" : "+v"(v[k]));
-}
-
-// Reciprocal to full double precision: hardware estimate refined by two Newton steps.
-__device__ __forceinline__ double rcp_nr(double x)
-{
-    double r = __builtin_amdgcn_rcp(x);
-    r = fma(r, fma(-x, r, 1.0), r);
-    r = fma(r, fma(-x, r, 1.0), r);
-    return r;
-}
-
-// X <- L^-1 X for the column held by this lane (p[c] = X[c][lane]); L from the LDS copy
-// sLt[k * LD + c] = L[c][k] with reciprocal diagonal sdi.  Each step first loads its whole
-// broadcast column, so the loads are issued back to back rather than one per update.
-template <int NB, int LD>
-__device__ __forceinline__ void lower_solve_cols(double (&p)[NB], const double *sLt,
-                                                 const double *sdi)
-{
-    StaticFor<0, NB>::run([&](auto K) __attribute__((always_inline)) {
-        constexpr int k = decltype(K)::value;
-        double lc[NB];
-#pragma unroll
-        for (int c = k + 1; c < NB; ++c) lc[c] = sLt[k * LD + c];
-        const double dk = sdi[k];
-        __builtin_amdgcn_sched_barrier(0);
-        p[k] *= dk;
-#pragma unroll
-        for (int c = k + 1; c < NB; ++c) p[c] = fma(-lc[c], p[k], p[c]);
-        pin_regs(p);
-    });
-}
-
-// One Householder step of the tridiagonalisation (column J), with J a compile-time constant so
-// that every register index stays static (the step is too large for the loop unroller).
-template <int J, int NB>
-__device__ __forceinline__ void tri_step(double (&p)[NB], int lane, double *sv, double *sw,
-                                         double *sdd, double *see, double *stau)
-{
-    constexpr int j = J;
-    const double xi = (lane > j) ? p[j] : 0.0;
-    const double s2 = wave_sum_dpp(xi * xi);
-    const double x0 = lane_bcast(p[j], j + 1);
-    const double dj = lane_bcast(p[j], j);
-    const double tail = s2 - x0 * x0;
-    double tj = 0.0, alpha = x0, v0 = 0.0;
-    if (tail > 0.0) {
-        const double sigma = sqrt(s2);
-        alpha = (x0 >= 0.0) ? -sigma : sigma;
-        v0 = x0 - alpha;
-        tj = 2.0 / (tail + v0 * v0);
-    }
-    sdd[j] = dj;
-    see[j] = alpha;
-    stau[j] = tj;
-    const double vi = (tj != 0.0 && lane > j) ? ((lane == j + 1) ? v0 : xi) : 0.0;
-    if (tj != 0.0) {
-        sv[lane] = vi;
-        __syncthreads();
-        double vc[NB];
-#pragma unroll
-        for (int c = j + 1; c < NB; ++c) vc[c] = sv[c];
-        __builtin_amdgcn_sched_barrier(0);
-        double q[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int c = j + 1; c < NB; ++c) q[c & 3] = fma(p[c], vc[c], q[c & 3]);
-        const double pi = tj * ((q[0] + q[1]) + (q[2] + q[3]));
-        const double mu = 0.5 * tj * wave_sum_dpp(pi * vi);
-        const double wi = pi - mu * vi;
-        sw[lane] = wi;
-        __syncthreads();
-        double wc[NB];
-#pragma unroll
-        for (int c = j + 1; c < NB; ++c) wc[c] = sw[c];
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int c = j + 1; c < NB; ++c) p[c] -= vi * wc[c] + wi * vc[c];
-        pin_regs(p);
-        __syncthreads();
-    }
-    p[j] = vi;
-}
-
-template <int J, int NB, bool DONE = (J + 2 >= NB)>
-struct TriSteps {
-    static __device__ __forceinline__ void run(double (&p)[NB], int lane, double *sv, double *sw,
-                                               double *sdd, double *see, double *stau)
-    {
-        tri_step<J, NB>(p, lane, sv, sw, sdd, see, stau);
-        TriSteps<J + 1, NB>::run(p, lane, sv, sw, sdd, see, stau);
-    }
-};
-template <int J, int NB>
-struct TriSteps<J, NB, true> {
-    static __device__ __forceinline__ void run(double (&)[NB], int, double *, double *, double *,
-                                               double *, double *)
-    {
-    }
-};
-
-// ||AV z(lam) - b||^2 from the continuants of I + lam T (see gks_solve_reg_k).
-template <int NB>
-__device__ __forceinline__ double dp_residual(double lam, const double (&dd)[NB],
-                                              const double (&ee)[NB], double out2, double cn2)
-{
-    double P2 = 0.0, P1 = 1.0, S = 0.0;
-#pragma unroll
-    for (int k = NB - 1; k >= 1; --k) {
-        const double bk = lam * ee[k];
-        const double bm = lam * ee[k - 1];
-        const double Pk = fma(fma(lam, dd[k], 1.0), P1, -(bk * bk) * P2);
-        P2 = P1;
-        P1 = Pk;
-        S = (bm * bm) * fma(P2, P2, S);
-        if ((k & 1) == 0 && fabs(P1) > 0x1p200) {
-            P1 *= 0x1p-200;
-            P2 *= 0x1p-200;
-            S *= 0x1p-400;
-        }
-    }
-    const double b0 = lam * ee[0];
-    const double Q = fma(lam * dd[0], P1, -(b0 * b0) * P2);
-    const double P0 = P1 + Q;
-    return out2 + cn2 * (fma(Q, Q, S) / (P0 * P0));
-}
-
-template <int NB>
-__global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__ GA,
-                                                     const double *__restrict__ GP, int ldg,
-                                                     const double *__restrict__ rb,
-                                                     const double *__restrict__ scal, int ell,
-                                                     double lam_fix, double *__restrict__ z,
-                                                     double *__restrict__ out,
-                                                     int *__restrict__ status)
-{
-    constexpr int LD = NB + 2;
-    __shared__ double sLt[NB * LD];   // sLt[k * LD + c] = L[c][k]
-    __shared__ double sX[NB * LD];    // transposes
-    __shared__ double sv[64], sw[64], sc[64], sdd[64], see[64], sy[64], sdi[64], stau[64];
-    const int n = ell;
-    const int lane = threadIdx.x;
-    const bool row = lane < NB;
-    const double trA = wave_sum_dpp(lane < n ? GA[lane * ldg + lane] : 0.0);
-    const double trP = wave_sum_dpp(lane < n ? GP[lane * ldg + lane] : 0.0);
-    double a[NB], p[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c)
-        a[c] = (lane < n && c < n) ? GA[lane * ldg + c] : (lane == c ? 1.0 : 0.0);
-    // 1. Cholesky GA = L L^T (lane i ends with row i of L; its upper part is never read).
-    //    The unscaled column is broadcast while the pivot reciprocal is formed, and the update
-    //    uses A_ij A_kj / pivot, so the square root stays off the dependency chain.
-    int bad = 0;
-    StaticFor<0, NB>::run([&](auto J) __attribute__((always_inline)) {
-        constexpr int j = decltype(J)::value;
-        sv[lane] = a[j];
-        __syncthreads();
-        double lc[NB];
-#pragma unroll
-        for (int k = j + 1; k < NB; ++k) lc[k] = sv[k];
-        double piv = lane_bcast(a[j], j);
-        if (!(piv > 0.0)) {
-            bad = 1;
-            piv = 1e-300;
-        }
-        const double r = 1.0 / piv;
-        __builtin_amdgcn_sched_barrier(0);
-        const double t = a[j] * r;
-#pragma unroll
-        for (int k = j + 1; k < NB; ++k) a[k] = fma(-t, lc[k], a[k]);
-        const double d = sqrt(piv);
-        const double di = 1.0 / d;
-        a[j] = (lane == j) ? d : a[j] * di;
-        sdi[j] = di;
-        pin_regs(a);
-        __syncthreads();
-    });
-    if (row) {
-#pragma unroll
-        for (int k = 0; k < NB; ++k) sLt[k * LD + lane] = a[k];
-    }
-    // lane i < ell: row i of GP (= column i); lane ell: rb
-#pragma unroll
-    for (int c = 0; c < NB; ++c)
-        p[c] = (lane < n && c < n) ? GP[lane * ldg + c] : ((lane == n && c < n) ? rb[c] : 0.0);
-    __syncthreads();
-    // 2. K = L^-1 GP L^-T: column-wise forward substitutions, transposes through LDS
-    lower_solve_cols<NB, LD>(p, sLt, sdi);
-    if (lane == n) {
-#pragma unroll
-        for (int k = 0; k < NB; ++k) sc[k] = p[k];   // c = L^-1 rb
-    }
-    if (row) {
-#pragma unroll
-        for (int k = 0; k < NB; ++k) sX[k * LD + lane] = (lane < n) ? p[k] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NB; ++c) p[c] = row ? sX[lane * LD + c] : 0.0;
-    __syncthreads();
-    lower_solve_cols<NB, LD>(p, sLt, sdi);
-    if (row) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) sX[c * LD + lane] = p[c];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NB; ++c) p[c] = row ? 0.5 * (p[c] + sX[lane * LD + c]) : 0.0;
-    // 3. reflector H0 with H0 c = s ||c|| e1; K <- H0 K H0
-    const double cl = (lane < n) ? sc[lane] : 0.0;
-    const double cn2 = wave_sum_dpp(cl * cl);
-    const double cn = sqrt(cn2);
-    const double out2 = fmax(scal[0] - cn2, 0.0);
-    const double sgn = (sc[0] >= 0.0) ? -1.0 : 1.0;
-    const double hv = cl - ((lane == 0) ? sgn * cn : 0.0);
-    const double vtv = wave_sum_dpp(hv * hv);
-    const double t0 = vtv > 0.0 ? 2.0 / vtv : 0.0;
-    sv[lane] = hv;
-    __syncthreads();
-    {
-        double vc[NB];
-#pragma unroll
-        for (int c = 0; c < NB; ++c) vc[c] = sv[c];
-        __builtin_amdgcn_sched_barrier(0);
-        double q[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int c = 0; c < NB; ++c) q[c & 3] = fma(p[c], vc[c], q[c & 3]);
-        const double pi = t0 * ((q[0] + q[1]) + (q[2] + q[3]));
-        const double mu = 0.5 * t0 * wave_sum_dpp(pi * hv);
-        const double wi = pi - mu * hv;
-        sw[lane] = wi;
-        __syncthreads();
-        double wc[NB];
-#pragma unroll
-        for (int c = 0; c < NB; ++c) wc[c] = sw[c];
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int c = 0; c < NB; ++c) p[c] -= hv * wc[c] + wi * vc[c];
-        pin_regs(p);
-        __syncthreads();
-    }
-    // 4. Householder tridiagonalisation; reflector j kept in register j of lanes > j, and
-    //    stored to row j of sX at the end (sX is free after step 2)
-    TriSteps<0, NB>::run(p, lane, sv, sw, sdd, see, stau);
-    {
-        const double d2 = lane_bcast(p[NB - 2], NB - 2);
-        const double e2 = lane_bcast(p[NB - 2], NB - 1);
-        const double d1 = lane_bcast(p[NB - 1], NB - 1);
-        sdd[NB - 2] = d2;
-        see[NB - 2] = e2;
-        sdd[NB - 1] = d1;
-        see[NB - 1] = 0.0;
-        stau[NB - 2] = 0.0;
-        stau[NB - 1] = 0.0;
-    }
-    if (row) {
-#pragma unroll
-        for (int j = 0; j + 2 < NB; ++j) sX[j * LD + lane] = (lane > j) ? p[j] : 0.0;
-    }
-    __syncthreads();
-    // 5. discrepancy principle.  The padded tail (d = e = 0) leaves P and S unchanged, so the
-    //    sweep runs over the whole padded size with T in registers.
-    double dd[NB], ee[NB];
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        dd[k] = sdd[k];
-        ee[k] = see[k];
-    }
-    auto phi = [&](double lam) { return dp_residual<NB>(lam, dd, ee, out2, cn2); };
-    const double t2 = scal[1] * scal[1];
-    double lam;
-    int flag = 0;
-    if (lam_fix >= 0.0) {
-        lam = lam_fix;
-    } else {
-        const double scale = trA / fmax(trP, 1e-300);
-        double lo = log(1e-10 * scale), hi = log(1e10 * scale);
-        // lanes 0 and 1 evaluate the two bracket ends
-        const double pe = phi(exp(lane == 0 ? lo : hi));
-        const double plo = lane_bcast(pe, 0), phh = lane_bcast(pe, 1);
-        if (plo >= t2) {
-            lam = exp(lo);
-            flag = NLRMM_ST_DP_LOW;
-        } else if (phh <= t2) {
-            lam = exp(hi);
-            flag = NLRMM_ST_DP_HIGH;
-        } else {
-            for (int round = 0; round < 12; ++round) {
-                const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
-                const unsigned long long m = __ballot(phi(exp(x)) >= t2);
-                const int k = m ? (__ffsll((unsigned long long)m) - 1) : 64;
-                const double nlo = (k == 0) ? lo : lo + (hi - lo) * (double)k / 65.0;
-                const double nhi = (k == 64) ? hi : lo + (hi - lo) * (double)(k + 1) / 65.0;
-                lo = nlo;
-                hi = nhi;
-                if (hi - lo <= 4e-16 * fmax(1.0, fabs(lo))) break;
-            }
-            lam = exp(0.5 * (lo + hi));
-        }
-    }
-    const double res2 = phi(lam);
-    // 6. y = (I + lam T)^-1 (s ||c|| e1) from the bottom-up pivots (computed in every lane,
-    //    reciprocals kept in sy), then the reflectors in reverse order and H0
-    {
-        double D = fma(lam, dd[NB - 1], 1.0);
-        double r = rcp_nr(D);
-        sy[NB - 1] = r;
-#pragma unroll
-        for (int i = NB - 2; i >= 0; --i) {
-            const double b = lam * ee[i];
-            D = fma(lam, dd[i], 1.0) - (b * b) * r;
-            r = rcp_nr(D);
-            sy[i] = r;
-        }
-    }
-    __syncthreads();
-    double yl;
-    {
-        double rD[NB];
-#pragma unroll
-        for (int i = 0; i < NB; ++i) rD[i] = sy[i];
-        __builtin_amdgcn_sched_barrier(0);
-        double y = sgn * cn * rD[0];
-        yl = (lane == 0) ? y : 0.0;
-#pragma unroll
-        for (int i = 1; i < NB; ++i) {
-            y = -(lam * ee[i - 1]) * rD[i] * y;
-            yl = (lane == i) ? y : yl;
-        }
-        yl = (lane < n) ? yl : 0.0;
-    }
-#pragma unroll
-    for (int j = NB - 3; j >= 0; --j) {
-        const double tj = stau[j];
-        if (tj != 0.0) {
-            const double vi = row ? sX[j * LD + lane] : 0.0;
-            const double dot = wave_sum_dpp(vi * yl);
-            yl = fma(-tj * dot, vi, yl);
-        }
-    }
-    {
-        const double dot = wave_sum_dpp(hv * yl);
-        yl = fma(-t0 * dot, hv, yl);
-    }
-    // 7. z = L^-T y (lane i reads row i of L^T, i.e. column i of L, once)
-    {
-        double lr[NB];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) lr[j] = row ? sLt[lane * LD + j] : 0.0;
-        double di[NB];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) di[j] = sdi[j];
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int j = NB - 1; j >= 0; --j) {
-            const double zj = lane_bcast(yl, j) * di[j];
-            if (lane == j) yl = zj;
-            else if (lane < j) yl = fma(-lr[j], zj, yl);
-        }
-    }
-    if (lane < n) z[lane] = yl;
-    if (lane == 0) {
-        out[0] = lam;
-        out[1] = res2;
-        int st = flag;
-        if (bad) st |= NLRMM_ST_NONFINITE;
-        if (!isfinite(lam) || !isfinite(res2)) st |= NLRMM_ST_NONFINITE;
-        if (st) atomicOr(status, st);
-    }
-}
-
-// Number of eigenvalues of the symmetric tridiagonal T (diagonal dd, off-diagonal ee) below
-// x: sign changes of the leading-minor sequence p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}
-// (p_{-1} = 0, p_0 = 1), i.e. the negative pivots of the LDL^T factorisation of T - x I,
-// without divisions; the pair (p_i, p_{i-1}) is rescaled by powers of two to stay in range.
-template <int NB>
-__device__ __forceinline__ int sturm_below(double x, const double (&dd)[NB], const double (&ee)[NB])
-{
-    double p1 = 1.0, p2 = 0.0;   // p_{i-1}, p_{i-2}
-    int cnt = 0;
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        const double em = i > 0 ? ee[i - 1] : 0.0;
-        double p = fma(dd[i] - x, p1, -(em * em) * p2);
-        // an exact zero counts as a sign change (x treated as just above the root)
-        if ((p < 0.0) != (p1 < 0.0) || p == 0.0) ++cnt;
-        if (p == 0.0) p = -copysign(0x1p-600, p1);
-        p2 = p1;
-        p1 = p;
-        if (i & 1) {
-            const double m = fmax(fabs(p1), fabs(p2));
-            if (m > 0x1p200) {
-                p1 *= 0x1p-200;
-                p2 *= 0x1p-200;
-            } else if (m < 0x1p-200) {
-                p1 *= 0x1p200;
-                p2 *= 0x1p200;
-            }
-        }
-    }
-    return cnt;
-}
-
-// Compression in one wave (same result as compress_eig_k): S = GA + lam GP is reduced to a
-// tridiagonal T = Q^T S Q (Householder, reflectors kept in registers), the kmin - 1 largest
-// eigenvalues of T are found by 65-way Sturm bisection, lane t computes the eigenvector of
-// eigenvalue t by two steps of inverse iteration (LDL^T of T - mu I, pivots perturbed away
-// from zero), the vectors are orthonormalised in order (classical Gram-Schmidt, twice) and
-// mapped back by Q.  The sign rule, W^T z, the remainder c and the outputs follow
-// compress_eig_k.  S is padded to NB with zeros: the padding adds zero eigenvalues below
-// the positive ones that are wanted.
-template <int NB>
-__global__ __launch_bounds__(64) void compress_reg_k(const double *__restrict__ GA,
-                                                    const double *__restrict__ GP, int ldg,
-                                                    const double *__restrict__ lamp, int ell,
-                                                    int kmin, const double *__restrict__ zin,
-                                                    double *__restrict__ T, int ldt,
-                                                    double *__restrict__ zout,
-                                                    int *__restrict__ out_k,
-                                                    int *__restrict__ status)
-{
-    constexpr int LD = NB + 2;
-    constexpr int KW = 15;   // kmin - 1 <= 15
-    __shared__ double sX[NB * LD];   // symmetrisation, then the reflectors (row j: reflector j)
-    __shared__ double sY[16 * LD];   // eigenvectors of T (row t)
-    __shared__ double sv[64], sw[64], sdd[64], see[64], stau[64], smu[16], swz[16];
-    const int n = ell;
-    const int lane = threadIdx.x;
-    const bool row = lane < NB;
-    const int kw = kmin - 1;
-    const double lam = lamp[0];
-    double p[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c)
-        p[c] = (lane < n && c < n) ? GA[lane * ldg + c] + lam * GP[lane * ldg + c] : 0.0;
-    // symmetrise through LDS
-    if (row) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) sX[c * LD + lane] = p[c];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NB; ++c) p[c] = row ? 0.5 * (p[c] + sX[lane * LD + c]) : 0.0;
-    __syncthreads();
-    // 1. tridiagonalise
-    TriSteps<0, NB>::run(p, lane, sv, sw, sdd, see, stau);
-    {
-        const double d2 = lane_bcast(p[NB - 2], NB - 2);
-        const double e2 = lane_bcast(p[NB - 2], NB - 1);
-        const double d1 = lane_bcast(p[NB - 1], NB - 1);
-        sdd[NB - 2] = d2;
-        see[NB - 2] = e2;
-        sdd[NB - 1] = d1;
-        see[NB - 1] = 0.0;
-        stau[NB - 2] = 0.0;
-        stau[NB - 1] = 0.0;
-    }
-    if (row) {
-#pragma unroll
-        for (int j = 0; j + 2 < NB; ++j) sX[j * LD + lane] = (lane > j) ? p[j] : 0.0;
-    }
-    __syncthreads();
-    double dd[NB], ee[NB];
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        dd[k] = sdd[k];
-        ee[k] = see[k];
-    }
-    // 2. the kw largest eigenvalues by bisection on Gershgorin bounds
-    double glo = 0.0, ghi = 0.0;
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        const double r = fabs(ee[i]) + (i > 0 ? fabs(ee[i - 1]) : 0.0);
-        glo = i == 0 ? dd[i] - r : fmin(glo, dd[i] - r);
-        ghi = i == 0 ? dd[i] + r : fmax(ghi, dd[i] + r);
-    }
-    const double span = fmax(ghi - glo, 1e-300);
-    glo -= 1e-12 * span;
-    ghi += 1e-12 * span;
-    for (int t = 0; t < kw; ++t) {
-        // smallest x with #(eig < x) >= NB - t, i.e. just above the (t+1)-th largest
-        const int need = NB - t;
-        double lo = glo, hi = ghi;
-        for (int round = 0; round < 14; ++round) {
-            const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
-            const unsigned long long m = __ballot(sturm_below<NB>(x, dd, ee) >= need);
-            const int k = m ? (__ffsll((unsigned long long)m) - 1) : 64;
-            const double nlo = (k == 0) ? lo : lo + (hi - lo) * (double)k / 65.0;
-            const double nhi = (k == 64) ? hi : lo + (hi - lo) * (double)(k + 1) / 65.0;
-            lo = nlo;
-            hi = nhi;
-            if (hi - lo <= 2e-16 * fmax(fabs(lo), fabs(hi))) break;
-        }
-        if (lane == 0) smu[t] = 0.5 * (lo + hi);
-    }
-    __syncthreads();
-    // 3. inverse iteration, lane t < kw for eigenvalue t (tridiagonal basis)
-    double y[NB];
-    {
-        const double mu = lane < kw ? smu[lane] : 0.0;
-        const double tiny = 0x1p-52 * fmax(fabs(mu), span);
-        double q[NB];
-        // LDL^T pivots of T - mu I
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            double v = dd[i] - mu;
-            if (i > 0) v -= ee[i - 1] * ee[i - 1] / q[i - 1];
-            if (fabs(v) < tiny) v = v < 0.0 ? -tiny : tiny;
-            q[i] = v;
-        }
-#pragma unroll
-        for (int i = 0; i < NB; ++i) y[i] = i < n ? 1.0 + 1e-3 * i : 0.0;
-        for (int it = 0; it < 2; ++it) {
-            // solve L D L^T y = y: forward (unit L, l_i = e_{i-1} / q_{i-1}), diagonal, back
-#pragma unroll
-            for (int i = 1; i < NB; ++i) y[i] -= (ee[i - 1] / q[i - 1]) * y[i - 1];
-#pragma unroll
-            for (int i = 0; i < NB; ++i) y[i] /= q[i];
-#pragma unroll
-            for (int i = NB - 2; i >= 0; --i) y[i] -= (ee[i] / q[i]) * y[i + 1];
-            double nrm = 0.0;
-#pragma unroll
-            for (int i = 0; i < NB; ++i) nrm = fma(y[i], y[i], nrm);
-            const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
-#pragma unroll
-            for (int i = 0; i < NB; ++i) y[i] *= inv;
-        }
-    }
-    // 4. vectors to LDS rows sX[t][*]; orthonormalise in order across lanes (component per
-    //    lane), classical Gram-Schmidt applied twice
-    if (lane < kw) {
-#pragma unroll
-        for (int i = 0; i < NB; ++i) sY[lane * LD + i] = y[i];
-    }
-    __syncthreads();
-    double wv[KW];   // lane i holds component i of every vector
-#pragma unroll
-    for (int t = 0; t < KW; ++t) wv[t] = (t < kw && row) ? sY[t * LD + lane] : 0.0;
-#pragma unroll
-    for (int t = 0; t < KW; ++t) {
-        if (t < kw) {
-            for (int pass = 0; pass < 2; ++pass) {
-                double cf[KW];
-#pragma unroll
-                for (int s2 = 0; s2 < KW; ++s2) cf[s2] = s2 < t ? wave_sum_dpp(wv[s2] * wv[t]) : 0.0;
-#pragma unroll
-                for (int s2 = 0; s2 < KW; ++s2)
-                    if (s2 < t) wv[t] = fma(-cf[s2], wv[s2], wv[t]);
-            }
-            const double nn = wave_sum_dpp(wv[t] * wv[t]);
-            wv[t] *= nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-        }
-    }
-    // 5. back to the basis of S: w = H_1 ... H_{NB-2} y
-#pragma unroll
-    for (int j = NB - 3; j >= 0; --j) {
-        const double tj = stau[j];
-        if (tj != 0.0) {
-            const double vi = row ? sX[j * LD + lane] : 0.0;
-#pragma unroll
-            for (int t = 0; t < KW; ++t) {
-                if (t < kw) {
-                    const double dot = wave_sum_dpp(vi * wv[t]);
-                    wv[t] = fma(-tj * dot, vi, wv[t]);
-                }
-            }
-        }
-    }
-    // 6. sign rule (largest magnitude positive, first such index), W^T z, remainder c
-    const double zl = lane < n ? zin[lane] : 0.0;
-#pragma unroll
-    for (int t = 0; t < KW; ++t) {
-        if (t < kw) {
-            double am = fabs(wv[t]);
-            int im = lane;
-            for (int off = 32; off > 0; off >>= 1) {
-                const double oa = __shfl_xor(am, off, 64);
-                const int oi = __shfl_xor(im, off, 64);
-                if (oa > am || (oa == am && oi < im)) {
-                    am = oa;
-                    im = oi;
-                }
-            }
-            const double vm = __shfl(wv[t], im, 64);
-            if (vm < 0.0) wv[t] = -wv[t];
-            const double wz = wave_sum_dpp(wv[t] * zl);
-            if (lane == 0) swz[t] = wz;
-            if (lane < n) T[lane * ldt + t] = wv[t];
-        }
-    }
-    __syncthreads();
-    double cl = zl;
-#pragma unroll
-    for (int t = 0; t < KW; ++t)
-        if (t < kw) cl = fma(-swz[t], wv[t], cl);
-    const double cn = sqrt(wave_sum_dpp(cl * cl));
-    const double zn = sqrt(wave_sum_dpp(zl * zl));
-    const bool keep = cn > 1e-12 * zn;
-    if (lane < n) T[lane * ldt + kw] = keep ? cl / cn : 0.0;
-    if (lane < kw) zout[lane] = swz[lane];
-    if (lane == 0) {
-        if (keep) zout[kw] = cn;
-        out_k[0] = keep ? kmin : kw;
-        int st = keep ? 0 : NLRMM_ST_COMPRESS_SKIP;
-        if (!isfinite(cn)) st |= NLRMM_ST_NONFINITE;
-        if (st) atomicOr(status, st);
-    }
-}
 
 // Compression (Alg. "compress"): S = GA + lam GP = H^T H with H = [RA; sqrt(lam) RP];
 // W = eigenvectors of the kmin-1 largest eigenvalues of S (= dominant right singular
@@ -2261,10 +1592,10 @@ int k_gks_solve(const double *GA, const double *GP, int ldg, const double *rb, c
     if (method == 1) {
         const int nb = (ell + 8) / 8 * 8;   // padded size >= ell + 1
         switch (nb) {
-#define NLRMM_REG_CASE(NB)                                                                         \
-    case NB:                                                                                       \
-        gks_solve_reg_k<NB><<<1, 64, 0, s>>>(GA, GP, ldg, rb, scal, ell, lam_fix, z, out, status); \
-        break;
+#define NLRMM_REG_CASE(NB)                                                                        \
+    case NB:                                                                                      \
+        return reg::launch_gks_solve_reg<NB>(GA, GP, ldg, rb, scal, ell, lam_fix, z, out, status, \
+                                             s);
             NLRMM_REG_CASE(8)
             NLRMM_REG_CASE(16)
             NLRMM_REG_CASE(24)
@@ -2275,7 +1606,6 @@ int k_gks_solve(const double *GA, const double *GP, int ldg, const double *rb, c
 #undef NLRMM_REG_CASE
         default: return NLRMM_ESHAPE;
         }
-        return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
     }
     if (method == 2) {
         const size_t sh = sizeof(double) * ((size_t)(ell + 1) * (ell + 2) + (size_t)ell * (ell + 1) +
@@ -2296,11 +1626,10 @@ int k_compress_eig(const double *GA, const double *GP, int ldg, const double *la
     if (method == 1) {
         const int nb = (ell + 8) / 8 * 8;
         switch (nb) {
-#define NLRMM_CMP_CASE(NB)                                                                  \
-    case NB:                                                                                \
-        compress_reg_k<NB><<<1, 64, 0, s>>>(GA, GP, ldg, lam, ell, kmin, z, T, ldt, zout, kout, \
-                                            status);                                        \
-        break;
+#define NLRMM_CMP_CASE(NB)                                                                     \
+    case NB:                                                                                   \
+        return reg::launch_compress_reg<NB>(GA, GP, ldg, lam, ell, kmin, z, T, ldt, zout, kout, \
+                                            status, s);
             NLRMM_CMP_CASE(8)
             NLRMM_CMP_CASE(16)
             NLRMM_CMP_CASE(24)
@@ -2311,7 +1640,6 @@ int k_compress_eig(const double *GA, const double *GP, int ldg, const double *la
 #undef NLRMM_CMP_CASE
         default: return NLRMM_ESHAPE;
         }
-        return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
     }
     const size_t sh = sizeof(double) * (2 * (size_t)ell * (ell + 1) + 128 + 2 * ell + kmin);
     compress_eig_k<<<1, SOLVE_NT, sh, s>>>(GA, GP, ldg, lam, ell, kmin, z, T, ldt, zout, kout, status);

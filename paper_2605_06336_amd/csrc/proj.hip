@@ -995,7 +995,23 @@ int edges_inside(const nlrmm_geom &g)
     return (int)ceil(g.d * 1.4142135623730951 / g.ds - 1e-12);
 }
 
+// Staged detector window of a backward tile, in bins: the footprint of the tile's pixels
+// (TILE - 1 pixel pitches times at most d sqrt 2 between the outer centres), the E + 1 bins of
+// one pixel footprint and a margin of 3 bins for the floor of the window start and rounding.
+int bwd_window(const nlrmm_geom &g)
+{
+    return (int)ceil((TILE - 1) * g.d * 1.4142135623730951 / g.ds) + edges_inside(g) + 4;
+}
+
 }  // namespace
+
+int fwd_geom_ok(const nlrmm_geom &g) { return g.nx <= MAX_LINE && g.ny <= MAX_LINE; }
+
+int bwd_geom_ok(const nlrmm_geom &g)
+{
+    const int E = edges_inside(g);
+    return E >= 1 && E <= 4 && bwd_window(g) <= WMAX;
+}
 
 // Workspace for the forward pass of `gcols` columns.
 static size_t fwd_ws_bytes(const nlrmm_geom &g, int nframes, int gcols, int64_t V, int nchunks,
@@ -1052,7 +1068,7 @@ int launch_project(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, in
 int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
                       const float *x, const double *theta, const FwdOptions &o, hipStream_t s)
 {
-    if (g.nx > MAX_LINE || g.ny > MAX_LINE) return NLRMM_ESHAPE;
+    if (!fwd_geom_ok(g)) return NLRMM_ESHAPE;
     const int F = b.nframes;
     const int64_t V = b.nviews;
     const int nchunks = (g.nbins + BINS - 1) / BINS;
@@ -1172,7 +1188,7 @@ int fwd_seg_for(const nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
     return t ? t : FSEG_DEFAULT;
 }
 
-// Largest view split: at most 8 partial images, at least 16 views per split and frame.
+// Largest view split: at most 16 partial images, at least 16 views per split and frame.
 int bwd_split_max(const nlrmm_geom &, const nlrmm_batch &b)
 {
     int64_t ns = (b.nviews / b.nframes) / 16;
@@ -1195,24 +1211,41 @@ int bwd_splits(const nlrmm_geom &g, const nlrmm_batch &b, int ncols, int cu_coun
     return (int)ns;
 }
 
-// Workspace bound of any view split the backprojection may use for this shape.
-size_t bwd_workspace_bytes(const nlrmm_geom &g, const nlrmm_batch &b, int ncols, int cu_count)
+// Partial images of a view split of `nsplit` (none for a single split).
+static size_t bwd_part_bytes(const nlrmm_geom &g, const nlrmm_batch &b, int ncols, int nsplit)
 {
-    const int ns = bwd_split_max(g, b) > bwd_splits(g, b, ncols, cu_count)
-                       ? bwd_split_max(g, b)
-                       : bwd_splits(g, b, ncols, cu_count);
-    if (ns <= 1) return 0;
-    return sizeof(float) * (size_t)ns * ncols * b.nframes * g.nx * g.ny;
+    if (nsplit <= 1) return 0;
+    return sizeof(float) * (size_t)nsplit * ncols * b.nframes * g.nx * g.ny;
+}
+
+// Workspace bound of any view split the backprojection may use for this shape: every split
+// it launches is clamped to bwd_split_max (bwd_split_for), and the default never exceeds it.
+size_t bwd_workspace_bytes(const nlrmm_geom &g, const nlrmm_batch &b, int ncols, int)
+{
+    return bwd_part_bytes(g, b, ncols, bwd_split_max(g, b));
+}
+
+// View split of one backprojection launch: the split forced by the autotuner, else the tuned
+// choice for this shape, else the default; clamped to [1, bwd_split_max] whatever its source
+// (a tune file may hold a choice made for another device or library version).
+int bwd_split_for(const nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols)
+{
+    int ns = ctx->force_bwd_split;
+    if (ns <= 0) ns = tune_lookup(ctx, TUNE_BWD_SPLIT, g, b, ncols);
+    if (ns <= 0) ns = bwd_splits(g, b, ncols, ctx->cu_count);
+    const int mx = bwd_split_max(g, b);
+    if (ns > mx) ns = mx;
+    if (ns < 1) ns = 1;
+    return ns;
 }
 
 int launch_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
                               int ncols, const float *y, const double *theta, float *x,
                               hipStream_t s)
 {
+    if (!bwd_geom_ok(g)) return NLRMM_ESHAPE;
     const int E = edges_inside(g);
-    if (E < 1 || E > 4) return NLRMM_ESHAPE;
-    const int W = (int)ceil((TILE - 1) * g.d * 1.4142135623730951 / g.ds) + E + 4;
-    if (W > WMAX) return NLRMM_ESHAPE;
+    const int W = bwd_window(g);
     BwdArgs a;
     a.y = y;
     a.theta = theta;
@@ -1230,16 +1263,13 @@ int launch_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_b
     a.tiles_x = (g.nx + TILE - 1) / TILE;
     a.W = W;
     a.x = x;
-    // the backprojection's view split for this shape (tuned, else its default)
-    {
-        const int t = tune_lookup(ctx, TUNE_BWD_SPLIT, g, b, ncols);
-        a.nsplit = t ? t : bwd_splits(g, b, ncols, ctx->cu_count);
-    }
+    // the backprojection's view split for this shape
+    a.nsplit = bwd_split_for(ctx, g, b, ncols);
     a.part = nullptr;
     a.accumulate = 0;
     a.tv = TvEpilogue();
     if (a.nsplit > 1) {
-        int rc = ensure_workspace(ctx, bwd_workspace_bytes(g, b, ncols, ctx->cu_count), s);
+        int rc = ensure_workspace(ctx, bwd_part_bytes(g, b, ncols, a.nsplit), s);
         if (rc) return rc;
         a.part = (float *)ctx->ws.ptr;
     }
@@ -1266,10 +1296,9 @@ int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b
                        int accumulate, const TvEpilogue *tv)
 {
     if (tv && tv->u && ncols != 1) return NLRMM_ENOTSUP;
+    if (!bwd_geom_ok(g)) return NLRMM_ESHAPE;
     const int E = edges_inside(g);
-    if (E < 1 || E > 4) return NLRMM_ESHAPE;
-    const int W = (int)ceil((TILE - 1) * g.d * 1.4142135623730951 / g.ds) + E + 4;
-    if (W > WMAX) return NLRMM_ESHAPE;
+    const int W = bwd_window(g);
     BwdArgs a;
     a.y = y;
     a.theta = theta;
@@ -1287,17 +1316,12 @@ int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b
     a.tiles_x = (g.nx + TILE - 1) / TILE;
     a.W = W;
     a.x = x;
-    if (ctx->force_bwd_split) {
-        a.nsplit = ctx->force_bwd_split;
-    } else {
-        const int t = tune_lookup(ctx, TUNE_BWD_SPLIT, g, b, ncols);
-        a.nsplit = t ? t : bwd_splits(g, b, ncols, ctx->cu_count);
-    }
+    a.nsplit = bwd_split_for(ctx, g, b, ncols);
     a.part = nullptr;
     a.accumulate = accumulate;
     a.tv = tv ? *tv : TvEpilogue();
     if (a.nsplit > 1) {
-        int rc = ensure_workspace(ctx, bwd_workspace_bytes(g, b, ncols, ctx->cu_count), s);
+        int rc = ensure_workspace(ctx, bwd_part_bytes(g, b, ncols, a.nsplit), s);
         if (rc) return rc;
         a.part = (float *)ctx->ws.ptr;
     }

@@ -1,0 +1,21 @@
+// Instantiations of the register-resident projected-problem kernels for padded sizes 8, 16.
+#include "solve_reg.h"
+
+namespace nlrmm {
+namespace reg {
+
+template int launch_gks_solve_reg<8>(const double *, const double *, int, const double *,
+                                          const double *, int, double, double *, double *,
+                                          int *, hipStream_t);
+template int launch_compress_reg<8>(const double *, const double *, int, const double *,
+                                         int, int, const double *, double *, int, double *,
+                                         int *, int *, hipStream_t);
+template int launch_gks_solve_reg<16>(const double *, const double *, int, const double *,
+                                          const double *, int, double, double *, double *,
+                                          int *, hipStream_t);
+template int launch_compress_reg<16>(const double *, const double *, int, const double *,
+                                         int, int, const double *, double *, int, double *,
+                                         int *, int *, hipStream_t);
+
+}  // namespace reg
+}  // namespace nlrmm

@@ -155,7 +155,7 @@ static int bproj(Solver &S, const nlrmm_batch &b, const float *y, const double *
     for (int f = 0; f < b.nframes; ++f) {
         const int64_t v0 = S.vo_host[f], nv = S.vo_host[f + 1] - v0;
         if (nv <= 0) {
-            RC(k_gemv(S.V, 1, 0, nullptr, 0.0, nullptr, 0.0, npix, x + f * npix, s));   // zero
+            RC(k_fill_f32(x + f * npix, npix, 0.0f, s));   // a frame without views
             continue;
         }
         nlrmm_batch fb{1, nv, nullptr};
@@ -500,7 +500,7 @@ static int solver_init(Solver &S, const nlrmm_batch &b, const double *theta, con
         RC(k_scale_into(S.rho, S.hb, m, U + (int64_t)(i + 1) * m, nrm + k + i + 1, S.status, s));
     }
     S.ell = k;
-    RC(k_gemv(S.V, S.n, 1, S.z, 0.0, nullptr, 0.0, S.n, S.u, s));   // u = 0
+    RC(k_fill_f32(S.u, S.n, 0.0f, s));   // u = 0
     return NLRMM_OK;
 }
 
@@ -569,7 +569,7 @@ static int offset_sensitivity(Solver &S, const nlrmm_batch &b, const double *the
     RC(launch_backproject(S.ctx, S.g, b, 1, du, theta, t1, s, 1));
     RC(k_gemv(t1, n, 1, one, -1.0, nullptr, 0.0, n, rc, s));
     RC(k_gemv(rc, n, 1, one, 1.0, nullptr, 0.0, n, p, s));
-    RC(k_gemv(rc, n, 1, one, 0.0, nullptr, 0.0, n, x, s));
+    RC(k_fill_f32(x, n, 0.0f, s));
     RC(k_multidot(rc, n, 1, rc, nullptr, n, S.part_md, S.md_blocks, c + 0, 1, s));
     TvEpilogue tv;
     tv.w = S.w;
@@ -599,9 +599,9 @@ static int offset_sensitivity(Solver &S, const nlrmm_batch &b, const double *the
     RC(k_gemv(du, m, 1, one, 1.0, jr, 1.0, m, jr, s));
     RC(k_multidot(jr, m, 1, jr, r, m, S.part_md, S.md_blocks, d1, 1, s));
     // [u_p^T Psi^T w Psi u, u_p^T Psi^T w Psi u_p]
-    // zero t1, t2 (scaling a finite vector by 0: the spare columns may hold anything)
-    RC(k_gemv(rc, n, 1, one, 0.0, nullptr, 0.0, n, t1, s));
-    RC(k_gemv(rc, n, 1, one, 0.0, nullptr, 0.0, n, t2, s));
+    // the spare columns may hold anything: clear them with a fill (never by scaling)
+    RC(k_fill_f32(t1, n, 0.0f, s));
+    RC(k_fill_f32(t2, n, 0.0f, s));
     RC(k_tv_grad_add(S.u, S.w, dims.nx, dims.ny, dims.F, dims.temporal, one, t1, s));
     RC(k_tv_grad_add(x, S.w, dims.nx, dims.ny, dims.F, dims.temporal, one, t2, s));
     RC(k_multidot(t1, n, 2, x, nullptr, n, S.part_md, S.md_blocks, d2, 1, s));
@@ -619,9 +619,9 @@ extern "C" {
 int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
                         int64_t max_views, const nlrmm_solver_cfg *cfg, nlrmm_solver **out)
 {
-    if (!ctx || !geom || !cfg || !out) return NLRMM_EINVAL;
-    int rc = check_geom(geom);
+    int rc = check_op_geom(NLRMM_OPS_FORWARD | NLRMM_OPS_BACKWARD, geom);
     if (rc) return rc;
+    if (!ctx || !cfg || !out) return NLRMM_EINVAL;
     if (nframes < 1 || max_views < 1) return NLRMM_ESHAPE;
     nlrmm_solver_cfg c = *cfg;
     if (c.kmin < 2 || c.kmin > 16 || c.kmax <= c.kmin || c.kmax > 55) return NLRMM_ESHAPE;
@@ -890,10 +890,10 @@ int nlrmm_gks_expand(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *
                      double *GA, int32_t ldg, double *rb, double breakdown_tol,
                      int32_t *status, void *stream)
 {
+    int rc = check_op_geom(NLRMM_OPS_FORWARD | NLRMM_OPS_BACKWARD, geom);
+    if (rc) return rc;
     if (!ctx || !theta || !V || !AV || !z || !b || !w || !lambda || !GA || !rb || !status)
         return NLRMM_EINVAL;
-    int rc = check_geom(geom);
-    if (rc) return rc;
     if ((rc = check_batch(batch))) return rc;
     if (ell < 1 || ell > 55 || ldg < ell + 1) return NLRMM_ESHAPE;
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;

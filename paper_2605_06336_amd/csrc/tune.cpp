@@ -1,10 +1,11 @@
 // Autotuner of the projector launch shapes.  The forward kernel can split each edge's lines
 // over 1, 2, 4 or 8 waves of a block, and the backprojection can split each frame's views
-// over 1..16 partial images; which is fastest depends on the shape (grid size, views per
-// frame, columns) and on the device.  The tuner runs the real operator once per candidate,
-// times it with HIP events on the caller's stream and keeps the fastest in the context (and,
-// when a cache file is set, appends it there).  Every candidate computes the same operator;
-// only the summation order of FP64 partial sums differs.
+// over 1, 2, 4, 8 or 16 partial images (at most 16 views per split and frame); which is
+// fastest depends on the shape (grid size, views per frame, columns) and on the device.  The
+// tuner runs the real operator once per candidate, times it with HIP events on the caller's
+// stream and keeps the fastest in the context (and, when a cache file is set, appends it
+// there).  Every candidate computes the same operator; only the summation order of FP64
+// partial sums differs.  A stored split larger than a shape allows is clamped at launch.
 #include "internal.h"
 
 #include <stdio.h>
@@ -98,7 +99,8 @@ int nlrmm_ctx_set_tune_file(nlrmm_ctx *ctx, const char *path)
            8) {
         const bool ok = (kind == TUNE_FWD_SEG && (choice == 1 || choice == 2 || choice == 4 ||
                                                   choice == 8)) ||
-                        (kind == TUNE_BWD_SPLIT && choice >= 1 && choice <= 8);
+                        (kind == TUNE_BWD_SPLIT && (choice == 1 || choice == 2 ||
+                                                    choice == 4 || choice == 8 || choice == 16));
         if (!ok || nx < 1 || ny < 1 || nb < 1 || nf < 1 || nv < nf) continue;
         loaded.push_back({kind, nx, ny, nb, nf, nc, (int64_t)nv, choice});
     }
@@ -131,10 +133,11 @@ int nlrmm_autotune_project(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_b
                            int32_t ncols, const float *x, const double *theta, float *y,
                            void *stream)
 {
+    int rc = check_op_geom(NLRMM_OPS_FORWARD, geom);
+    if (rc) return rc;
     if (!ctx || !x || !theta || !y) return NLRMM_EINVAL;
     if (ncols < 1) return NLRMM_ESHAPE;
-    int rc = check_geom(geom);
-    if (rc || (rc = check_batch(batch))) return rc;
+    if ((rc = check_batch(batch))) return rc;
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
     hipStream_t s = (hipStream_t)stream;
     if (capturing(s)) return NLRMM_EINVAL;
@@ -169,10 +172,11 @@ int nlrmm_autotune_backproject(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlr
                                int32_t ncols, const float *y, const double *theta, float *x,
                                void *stream)
 {
+    int rc = check_op_geom(NLRMM_OPS_BACKWARD, geom);
+    if (rc) return rc;
     if (!ctx || !x || !theta || !y) return NLRMM_EINVAL;
     if (ncols < 1) return NLRMM_ESHAPE;
-    int rc = check_geom(geom);
-    if (rc || (rc = check_batch(batch))) return rc;
+    if ((rc = check_batch(batch))) return rc;
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
     hipStream_t s = (hipStream_t)stream;
     if (capturing(s)) return NLRMM_EINVAL;
