@@ -55,14 +55,29 @@ extern "C" {
 #define NLRMM_ST_NONFINITE 16     /* a NaN or Inf was produced */
 #define NLRMM_ST_COMPRESS_SKIP 32 /* u already in span(V W): compressed basis has kmin-1 columns */
 
-/* Image grid and detector.  Square pixels of width d. */
+/* Image grid and detector.  Square pixels of width d.
+ * Limits checked on the host by every entry point (NLRMM_ESHAPE when violated, before
+ * anything is launched):
+ *   all entry points       1 <= nx, ny <= 16384, 1 <= nbins <= 65536, d > 0, ds > 0, finite;
+ *   forward family         nx, ny <= 4096 (nlrmm_project, nlrmm_project_dtheta,
+ *                          nlrmm_project_residual, nlrmm_autotune_project);
+ *   backward family        at most 4 bin edges inside one pixel footprint,
+ *                          ceil(d sqrt(2) / ds - 1e-12) <= 4, and a staged window of
+ *                          ceil(15 d sqrt(2) / ds) + that count + 4 <= 64 bins per 16-pixel
+ *                          tile, i.e. ds >= about 0.38 d (nlrmm_backproject(_acc),
+ *                          nlrmm_backproject_dtheta, nlrmm_autotune_backproject);
+ *   solver, gks_expand     both families.
+ * nlrmm_check_geom reports these limits without a device. */
 typedef struct {
-    int32_t nx, ny;   /* pixels along x (fastest index) and y, 1 .. 16384 */
+    int32_t nx, ny;   /* pixels along x (fastest index) and y */
     double x0, y0;    /* lower-left corner of the image */
     double d;         /* pixel width, > 0 */
-    int32_t nbins;    /* detector bins, 1 .. 65536 */
+    int32_t nbins;    /* detector bins */
     double s0, ds;    /* bin j covers [s0 + j ds, s0 + (j+1) ds), ds > 0 */
 } nlrmm_geom;
+
+#define NLRMM_OPS_FORWARD 1    /* projection, angle derivative, data residual */
+#define NLRMM_OPS_BACKWARD 2   /* backprojection and the derivative's transpose */
 
 /* Frames with their own images and uneven view counts (dynamic problems). */
 typedef struct {
@@ -76,6 +91,12 @@ typedef struct nlrmm_ctx nlrmm_ctx;   /* opaque: device workspace and launch cac
 
 const char *nlrmm_strerror(int code);
 int nlrmm_version(void);
+
+/* Host-only shape check (no context, no device work): NLRMM_OK when the operator families
+ * in `ops` (NLRMM_OPS_* bits) accept `geom`, NLRMM_ESHAPE when a size limit above is
+ * exceeded, NLRMM_EINVAL for a NULL or non-finite geometry or unknown bits.  The entry
+ * points run the same check first. */
+int nlrmm_check_geom(int32_t ops, const nlrmm_geom *geom);
 
 /* Create a context on HIP device `device`.  Allocates nothing yet; workspace grows on
  * the first call that needs it (outside graph capture).  *out receives the handle. */
@@ -92,9 +113,12 @@ void nlrmm_ctx_destroy(nlrmm_ctx *ctx);
  * FP64 partial sums.  Both synchronize `stream` and return NLRMM_EINVAL while it is being
  * captured.  Later calls with the same shapes (operators, solver, graph captures) use the
  * choice.  nlrmm_ctx_set_tune_file loads choices stored in `path` (lines of
- * "kind nx ny nbins nframes nviews ncols choice"; kind 0 forward, 1 backprojection) and appends
- * every new choice there; NULL stops appending.  nlrmm_tune_query returns the stored choice
- * for a shape in *choice (0 when none: the built-in default is used). */
+ * "kind nx ny nbins nframes nviews ncols choice"; kind 0 forward with choice 1, 2, 4 or 8,
+ * kind 1 backprojection with choice 1, 2, 4, 8 or 16; other lines are skipped) and appends
+ * every new choice there; NULL stops appending.  A stored view split above what the shape
+ * allows (16 views per split and frame) is clamped to that bound when the backprojection is
+ * launched.  nlrmm_tune_query returns the stored choice for a shape in *choice (0 when none:
+ * the built-in default is used). */
 int nlrmm_autotune_project(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
                            int32_t ncols, const float *x, const double *theta, float *y,
                            void *stream);

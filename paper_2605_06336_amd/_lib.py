@@ -50,6 +50,7 @@ class SolverCfg(ctypes.Structure):
 # name -> argtypes (all return int except where noted)
 SIGNATURES = {
     "nlrmm_version": [],
+    "nlrmm_check_geom": [_I32, _GP],
     "nlrmm_ctx_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int],
     "nlrmm_ctx_set_timing": [_P, _I32],
     "nlrmm_autotune_project": [_P, _GP, _BP, _I32, _P, _P, _P, _P],

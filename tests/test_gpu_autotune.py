@@ -125,3 +125,32 @@ def test_kernel_timing_repeats_leave_results_unchanged():
     assert np.array_equal(y0, y1) and np.array_equal(d0, d1) and np.array_equal(b0, b1)
     assert np.array_equal(a0, a1)
     assert tp > 0.0 and tb > 0.0
+
+
+def test_stored_split_above_the_bound_is_clamped(tmp_path):
+    """A tune file can hold a view split larger than a shape allows (e.g. one tuned for more
+    views per frame).  The launch clamps it to the shape's bound (16 views per split and
+    frame), so the partial images fit the workspace sized for that bound, and the result
+    still matches the oracle.  A stored 16 is a valid choice and survives a reload."""
+    N, nb, ncols, F = 80, 117, 2, 3
+    vo, fr, th, x, ys = problem(N, nb, 0, ncols, F, seed=9)
+    Vt = th.size
+    bound = max(1, min(16, (Vt // F) // 16))
+    assert bound < 16
+    g = ops.geom(N, nb)
+    tht, yt = dev(th, torch.float64), dev(ys, torch.float32)
+    xb_ref = P.backproject(ys.astype(np.float64), th, N, vo).reshape(ncols, F, N, N)
+    path = str(tmp_path / "tune.txt")
+    with open(path, "w") as f:
+        f.write(f"1 {N} {N} {nb} {F} {ncols} {Vt} 16\n")
+    ops.set_tune_file(path)
+    try:
+        assert ops.tune_query("backproject", g, Vt, ncols, fr) == 16
+        xb = ops.backproject(yt, tht, g, fr).cpu().numpy()
+        Dt = ops.backproject_dtheta(yt, tht, g, fr).cpu().numpy()
+    finally:
+        ops.set_tune_file(None)
+    assert rel(xb, xb_ref) <= TOL, rel(xb, xb_ref)
+    Dt_ref = P.dtheta_t(ys.astype(np.float64), th, N, vo).reshape(Dt.shape)
+    assert rel(Dt, Dt_ref) <= TOL, rel(Dt, Dt_ref)
+    print(f"stored split 16 on a shape bounded at {bound}: {rel(xb, xb_ref):.2e}", flush=True)
