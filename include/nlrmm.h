@@ -160,6 +160,22 @@ int nlrmm_backproject(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch 
                       int32_t ncols, const float *y, const double *theta, float *x,
                       void *stream);
 
+/* Backprojection that allocates nothing (no hipMalloc, hipFree or allocating library call),
+ * for callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  Same operator, arguments, layouts and results as
+ * nlrmm_backproject (bitwise: the same view split and summation order).  The view split's
+ * partial images (split x ncols x nframes x ny x nx float32, none when the shape runs
+ * without a split) are kept in a fixed device array of NLRMM_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on until the process ends; a shape whose split needs
+ * more returns NLRMM_ESHAPE before anything is launched.  The context itself must have been
+ * created beforehand (nlrmm_ctx_create allocates no device memory).  All calls on one GPU
+ * share that array: calls that overlap in time on one GPU (different streams or host
+ * threads) race on it and must be serialised by the caller. */
+#define NLRMM_NOALLOC_SCRATCH_BYTES (64u << 20)
+int nlrmm_backproject_noalloc(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                              int32_t ncols, const float *y, const double *theta, float *x,
+                              void *stream);
+
 /* Transpose of the angle derivative: x = D(theta)^T r = sum_v (dA_v/dtheta_v)^T r_v, the
  * H_p^T r term of the full-space sensitivity equation of Section 4.2 (eq. "sensitivity") for
  * a global angle offset (per-view terms: r zero outside view v).  Per view, bin j carries

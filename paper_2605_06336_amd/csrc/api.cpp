@@ -112,6 +112,10 @@ int nlrmm_ctx_create(nlrmm_ctx **out, int device)
     nlrmm_ctx *c = new (std::nothrow) nlrmm_ctx();
     if (!c) return NLRMM_ENOMEM;
     c->device = device;
+    if (noalloc_scratch_address(device, &c->noalloc_scratch) != NLRMM_OK) {
+        delete c;
+        return NLRMM_EHIP;
+    }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
         cus > 0)

@@ -48,6 +48,8 @@ struct nlrmm_ctx {
     int force_fwd_seg = 0;
     int force_bwd_split = 0;
     std::string tune_path;
+    // device address of this device's fixed scratch array (nlrmm_backproject_noalloc)
+    void *noalloc_scratch = nullptr;
 };
 
 namespace nlrmm {
@@ -57,6 +59,9 @@ int ensure_workspace(nlrmm_ctx *ctx, size_t bytes, hipStream_t stream);
 int ensure_buffer(Workspace &w, size_t bytes, hipStream_t stream);
 
 int check_geom(const nlrmm_geom *g);
+// Device address of the fixed scratch array of nlrmm_backproject_noalloc on `device`, looked
+// up once per device (noalloc.hip).
+int noalloc_scratch_address(int device, void **out);
 // check_geom plus the kernels' limits for the operator families in `ops` (NLRMM_OPS_*)
 int check_op_geom(int ops, const nlrmm_geom *g);
 
@@ -122,6 +127,14 @@ struct TvEpilogue {
 int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
                        const float *y, const double *theta, float *x, hipStream_t s,
                        int accumulate = 0, const TvEpilogue *tv = nullptr);
+// The same with the view split's partial images in a caller buffer of part_cap bytes (no
+// workspace growth; NLRMM_ESHAPE when the split needs more); part_buf null: the workspace.
+int launch_backproject_into(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
+                            const float *y, const double *theta, float *x, hipStream_t s,
+                            int accumulate, const TvEpilogue *tv, float *part_buf,
+                            size_t part_cap);
+// Bytes of partial images the backprojection of this shape uses (0 without a view split).
+size_t bwd_split_bytes(const nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols);
 int launch_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
                               int ncols, const float *y, const double *theta, float *x,
                               hipStream_t s);

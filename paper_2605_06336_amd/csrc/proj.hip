@@ -1295,6 +1295,19 @@ int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b
                        const float *y, const double *theta, float *x, hipStream_t s,
                        int accumulate, const TvEpilogue *tv)
 {
+    return launch_backproject_into(ctx, g, b, ncols, y, theta, x, s, accumulate, tv, nullptr, 0);
+}
+
+size_t bwd_split_bytes(const nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols)
+{
+    return bwd_part_bytes(g, b, ncols, bwd_split_for(ctx, g, b, ncols));
+}
+
+int launch_backproject_into(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
+                            const float *y, const double *theta, float *x, hipStream_t s,
+                            int accumulate, const TvEpilogue *tv, float *part_buf,
+                            size_t part_cap)
+{
     if (tv && tv->u && ncols != 1) return NLRMM_ENOTSUP;
     if (!bwd_geom_ok(g)) return NLRMM_ESHAPE;
     const int E = edges_inside(g);
@@ -1321,9 +1334,16 @@ int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b
     a.accumulate = accumulate;
     a.tv = tv ? *tv : TvEpilogue();
     if (a.nsplit > 1) {
-        int rc = ensure_workspace(ctx, bwd_part_bytes(g, b, ncols, a.nsplit), s);
-        if (rc) return rc;
-        a.part = (float *)ctx->ws.ptr;
+        const size_t need = bwd_part_bytes(g, b, ncols, a.nsplit);
+        if (part_buf) {
+            // caller-provided partial images (never grown here)
+            if (need > part_cap) return NLRMM_ESHAPE;
+            a.part = part_buf;
+        } else {
+            int rc = ensure_workspace(ctx, need, s);
+            if (rc) return rc;
+            a.part = (float *)ctx->ws.ptr;
+        }
     }
     const int tiles_y = (g.ny + TILE - 1) / TILE;
     dim3 grid((unsigned)(a.tiles_x * tiles_y), (unsigned)((int64_t)ncols * b.nframes),

@@ -125,6 +125,28 @@ def backproject(y: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None,
     return out
 
 
+def backproject_noalloc(y: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None,
+                        out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """x = A(theta)^T y without any device allocation by the library
+    (nlrmm_backproject_noalloc: partial images in its fixed scratch).  Same shapes and results
+    as ``backproject``; pass ``out`` to allocate nothing here either."""
+    _need(y, torch.float32, "y")
+    _need(theta, torch.float64, "theta")
+    V = theta.numel()
+    b = _batch(frames, V)
+    if y.numel() % (V * g.nbins):
+        raise ValueError("y size is not a multiple of V*nb")
+    ncols = y.numel() // (V * g.nbins)
+    if out is None:
+        out = torch.empty((ncols, b.nframes, g.ny, g.nx), dtype=torch.float32, device=y.device)
+    _need(out, torch.float32, "out")
+    check(_lib.lib().nlrmm_backproject_noalloc(context(y.device.index or 0), ctypes.byref(g),
+                                               ctypes.byref(b), ncols, y.data_ptr(),
+                                               theta.data_ptr(), out.data_ptr(),
+                                               _stream(y.device)), "nlrmm_backproject_noalloc")
+    return out
+
+
 def backproject_dtheta(r: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None,
                        out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """x = D(theta)^T r, the transpose of the angle derivative (nlrmm_backproject_dtheta).
