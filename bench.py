@@ -7,10 +7,17 @@ update with Armijo trials, residual append.  Inputs are resident in HBM before t
 rate of the same iteration captured once as a HIP graph and replayed is reported beside it.
 
 Also reported:
+  * the in-loop duration per launch of the two projector kernels (HIP events recorded by the
+    library on the launch stream around every single one-column launch during the timed
+    outer iterations), and the roofline of the one with the most time per outer iteration
+    (algorithmic FP32 flops per launch over that duration, against the published FP32 vector
+    peak, with the unpacked-FP32 rate beside it);
+  * parity: the same iteration run for the workload's full outer count against the FP64
+    oracle's run stored under tests/golden, and the four operators against the oracle on the
+    same inputs (in the host-baseline leg);
   * Gsamples/s of the projector family (project, backproject, angle derivative and its
     transpose; one sample = one nonzero (ray, pixel) weight applied) at the same workload,
-    per call and per kernel (HIP events on the launch stream);
-  * the roofline of the dominant kernel (the forward-weights kernel of the projection);
+    per call and per kernel (single launches between HIP events);
   * outer it/s of the 32-frame dynamic workload, batched (one launch over all frames, the
     outer iteration replayed as a HIP graph) against plain (per-frame launches, eager), with
     the difference of the two reconstructions after the same iterations;
@@ -23,7 +30,8 @@ Also reported:
   * outer it/s of the 256x256 iteration under each precision policy (FP64 Grams, FP32
     matrix-core Grams, BF16 matrix-core Grams and compression products);
   * ms per block of streaming NL-RMM-GKS at 2048x2048 / 1440 views in 64 blocks;
-  * the FP64 oracle timed on a bounded sample on the host.
+  * the FP64 oracle timed on a bounded sample on the host: the median of three outer
+    iterations and one application of each operator.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-dynamic]
                        [--no-workloads]
@@ -41,11 +49,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP32_NONPACKED_PEAK_TFLOPS = 78.6   # 256 CU x 64 FP32 FMA lanes x 2 flop x 2.4 GHz
+FP32_VECTOR_PEAK_TFLOPS = 157.3     # published MI355X FP32 vector peak (packed FMA)
+FP32_NONPACKED_PEAK_TFLOPS = 78.6   # 256 CU x 64 FP32 FMA lanes x 2 flop x 2.4 GHz (unpacked)
 FLOP_PER_SAMPLE = 10.0              # algorithmic FP32 flops per applied strip-area weight
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd_edges_c2.json")
+LOOP_FIXTURE = os.path.join(ROOT, "tests", "golden", "loop_c2_oracle.npz")
+TIMING_PERIOD = 4                   # in-loop kernel timing samples every 4th launch
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
 COPY_BYTES = 256 << 20              # calibration copy for the HBM byte counters
-KERNEL_REPS = 10                    # back-to-back launches per event-timed kernel
 HBM_PEAK_GBS = 8000.0               # MI355X HBM3E
 MFMA_PEAK_TFLOPS = {1: 157.3, 2: 2500.0}   # dense matrix-core peaks: FP32, BF16
 
@@ -122,27 +132,22 @@ def operators(torch, ops, metrics, inst, wl, g, x32, th_true, b, reps, stream):
         torch.cuda.synchronize()
         return a0.elapsed_time(a1) / reps
 
-    def kernel_avg(fn, which):
-        tot = 0.0
-        for _ in range(reps):
-            fn()
-            tot += ops.kernel_ms(which)
-        return tot / reps
-
     proj = lambda: ops.project(x32, th_true, g, out=y)              # noqa: E731
     back = lambda: ops.backproject(ysrc, th_true, g, out=xb)        # noqa: E731
     dth = lambda: ops.project_dtheta(x32, th_true, g, want_dy=True)  # noqa: E731
     dtt = lambda: ops.backproject_dtheta(ysrc, th_true, g, out=xb)   # noqa: E731
     call_ms = {"project": timed(proj), "backproject": timed(back), "dtheta": timed(dth),
                "dtheta_transpose": timed(dtt)}
-    # each timed kernel launched KERNEL_REPS times back to back between its two events, so
-    # that the events' own cost is spread over those launches
-    ops.set_kernel_timing(KERNEL_REPS)
-    proj()
-    back()
-    kern_ms = {"fwd_edges_k": kernel_avg(proj, "project"),
-               "bwd_tiles_k": kernel_avg(back, "backproject")}
+    # the two projector kernels alone: HIP events around every single launch
+    ops.set_kernel_timing(-1)
+    for _ in range(reps):
+        proj()
+    fwd_ms, _ = ops.kernel_avg("project")
+    for _ in range(reps):
+        back()
+    bwd_ms, _ = ops.kernel_avg("backproject")
     ops.set_kernel_timing(False)
+    kern_ms = {"fwd_edges_k": fwd_ms, "bwd_tiles_k": bwd_ms}
     return nnz, call_ms, kern_ms
 
 
@@ -157,16 +162,45 @@ def copy_calibration(torch):
 
 
 def traffic_for(kernel):
-    """HBM bytes per launch of `kernel` from committed counter runs, or None when absent or
-    recorded for another version of the projector source."""
+    """HBM bytes per launch of `kernel` at the c2 shape from committed counter runs, or None
+    when absent or recorded for another version of the projector source."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel") != kernel or rec.get("source_sha") != source_digest():
+    if rec.get("source_sha") != source_digest():
         return None
-    return rec.get("bytes_per_launch")
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def loop_parity(torch, ops, inst, wl, g, b, delta, Config, Solver, gram_precision):
+    """The benchmark's iteration run from the GKB start for the workload's full outer count
+    against the FP64 oracle's run stored by tests/golden/make_loops.py: relative L2 of the
+    image and the largest angle difference."""
+    try:
+        fx = np.load(LOOP_FIXTURE)
+    except OSError:
+        return None
+    theta = torch.as_tensor(inst.theta_nom.copy(), device="cuda")
+    sol = Solver(g, 1, wl.n_views, Config(kmin=wl.kmin, kmax=wl.kmax, eps=wl.eps,
+                                          gram_precision=gram_precision))
+    sol.init(theta, b)
+    for _ in range(int(fx["outer"])):
+        sol.outer(theta, b, delta)
+    u, sc, status = sol.read()
+    torch.cuda.synchronize()
+    u = u.cpu().numpy()[::int(fx["stride"])].astype(np.float64)
+    uo = fx["u_sample"].astype(np.float64)
+    out = {"outer_iterations": int(fx["outer"]),
+           "u_rel_l2": float(np.linalg.norm(u - uo) / np.linalg.norm(uo)),
+           "theta_max_abs_rad": float(np.max(np.abs(theta.cpu().numpy() - fx["theta"][-1]))),
+           "lambda_rel": float(abs(float(sc.cpu()[2]) - fx["lam"][-1]) / fx["lam"][-1]),
+           "reference": "FP64 oracle from the exact GKB start (tests/golden/loop_c2_oracle.npz)",
+           "bars": {"u_rel_l2": 1e-3, "theta_max_abs_rad": 1e-4}}
+    sol.close()
+    return out
 
 
 def autotune(torch, ops, g, x, theta, b, kmin, fr=None):
@@ -459,6 +493,61 @@ def dynamic_leg(torch, ops, synth, Config, OuterGraph, Solver, steps, warmup, gr
     return out
 
 
+def cpu_baseline_leg(torch, ops, inst, wl, g, x32, th_true, b, x_true):
+    """The FP64 oracle on the host's cores: the median of three outer iterations of the same
+    workload (after the GKB start) and one application of each operator at its shape; the
+    operators' outputs also give the library's error against FP64 on the same inputs."""
+    from oracle import method as OM
+    from oracle import projector as OP
+    from paper_2605_06336_amd import metrics
+    geo = OM.Geometry(N=wl.N, nb=wl.nb, view_off=inst.view_off)
+    b_ora, e_ora = OM.make_data(geo, x_true, inst.theta_true, inst.g, wl.noise)
+    ocfg = OM.Config(kmin=wl.kmin, kmax=wl.kmax, eps=wl.eps)
+    st = OM.init_state(geo, inst.theta_nom, b_ora, ocfg)
+    secs = []
+    for k in range(3):
+        c0 = time.perf_counter()
+        OM.outer_step(geo, st, b_ora, float(np.linalg.norm(e_ora)), ocfg)
+        secs.append(time.perf_counter() - c0)
+        print(f"# oracle outer iteration {k + 1}/3: {secs[-1]:.1f} s", file=sys.stderr, flush=True)
+    med = float(np.median(secs))
+    # operators at the same shape: the image and angles the library projected, a sinogram
+    x64 = x32.cpu().numpy().astype(np.float64).reshape(wl.N, wl.N)
+    th = th_true.cpu().numpy()
+    ys32 = b.cpu().numpy().reshape(wl.n_views, wl.nb)
+    ys = ys32.astype(np.float64)
+    nnz = metrics.nnz(wl.N, wl.nb, inst.theta_true)
+    ora = {}
+    t = {}
+    for name, fn in (("project", lambda: OP.project(x64, th, wl.nb)),
+                     ("backproject", lambda: OP.backproject(ys, th, wl.N)),
+                     ("dtheta", lambda: OP.dtheta(x64, th, wl.nb)),
+                     ("dtheta_transpose", lambda: OP.dtheta_t(ys, th, wl.N))):
+        c0 = time.perf_counter()
+        ora[name] = fn()
+        t[name] = time.perf_counter() - c0
+    cpu = {"value": round(1.0 / med, 5), "unit": "outer it/s", "cores": OP.max_threads(),
+           "kind": "oracle",
+           "sample": f"median of 3 outer iterations (the first three after the GKB start basis) "
+                     f"of the same 256x256 / 360-view workload in FP64 on the host: "
+                     + ", ".join(f"{v:.1f}" for v in secs) + " s",
+           "operators_gsamples_per_s": {k: round(nnz / v / 1e9, 4) for k, v in t.items()}}
+    dev = torch.device("cuda", 0)
+    bt = torch.as_tensor(ys32, device=dev).view(1, wl.n_views, wl.nb)
+    lib = {"project": ops.project(x32, th_true, g).cpu().numpy(),
+           "backproject": ops.backproject(bt, th_true, g).cpu().numpy(),
+           "dtheta": ops.project_dtheta(x32, th_true, g, want_dy=True)["dy"].cpu().numpy(),
+           "dtheta_transpose": ops.backproject_dtheta(bt, th_true, g).cpu().numpy()}
+
+    def rel(a, ref):
+        a = np.asarray(a, np.float64).reshape(ref.shape)
+        return float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
+
+    op_parity = {k: rel(lib[k], ora[k]) for k in ora}
+    op_parity["bar"] = 1e-5
+    return cpu, op_parity
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -497,10 +586,21 @@ def main():
     sol.init(theta, b)
     for _ in range(args.warmup):
         sol.outer(theta, b, delta)
+    # over the timed steps, every 4th one-column projection and backprojection records a HIP
+    # event pair around its single kernel launch on the launch stream: the in-loop duration
+    # per launch of the two projector kernels (sampled, so that the events cost little)
+    ops.set_kernel_timing(-TIMING_PERIOD)
     ms_per_step = timed_steps(torch, lambda: sol.outer(theta, b, delta), args.steps, stream,
                               "c2")
+    loop_kernels = {}
+    for which, kname in (("project", "fwd_edges_k"), ("backproject", "bwd_tiles_k")):
+        avg, n = ops.kernel_avg(which)
+        loop_kernels[kname] = {"avg_launch_ms": round(avg, 5), "launches_timed": n,
+                               "ms_per_outer_iteration":
+                                   round(avg * n * TIMING_PERIOD / args.steps, 4)}
+    ops.set_kernel_timing(False)
     # the same iteration captured once as a HIP graph and replayed (bitwise equal to eager
-    # execution), reported beside the eager rate
+    # execution, no timing events), reported beside the eager rate
     graph_steps = max(2, args.steps // 2)
     graph = OuterGraph(sol, theta, b, delta)
     ms_graph = timed_steps(torch, graph.replay, graph_steps, stream, "c2 graph")
@@ -522,26 +622,33 @@ def main():
                        "ms_per_cg_iteration": round(sens_ms / sens_iters, 4),
                        "g_h_dp": [float(v) for v in sens_out.cpu().numpy()]}
     sol.close()
+    parity = loop_parity(torch, ops, inst, wl, g, b, delta, Config, Solver, args.gram_precision)
 
     nnz, call_ms, kern_ms = operators(torch, ops, metrics, inst, wl, g, x32, th_true, b,
                                       args.reps, stream)
     gs = {k: round(nnz / (v * 1e-3) / 1e9, 2) for k, v in call_ms.items()}
     gs_kernel = {k: round(nnz / (v * 1e-3) / 1e9, 2) for k, v in kern_ms.items()}
 
-    def roof(kernel, ms):
+    def roof(kernel):
+        ms = loop_kernels[kernel]["avg_launch_ms"]
         achieved = nnz * FLOP_PER_SAMPLE / (ms * 1e-3) / 1e12
         traffic = traffic_for(kernel)
         return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3),
-                "peak": FP32_NONPACKED_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_NONPACKED_PEAK_TFLOPS, 4),
+                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "frac_of_unpacked_fp32": round(achieved / FP32_NONPACKED_PEAK_TFLOPS, 4),
                 "traffic": traffic,
                 "hbm_gb_s": round(traffic / (ms * 1e-3) / 1e9, 1) if traffic else None,
-                "launch_ms": round(ms, 5),
+                "launch_ms": round(ms, 5), "launches_timed": loop_kernels[kernel]["launches_timed"],
+                "timing": f"HIP events around every {TIMING_PERIOD}th single launch in the timed "
+                          "outer iterations",
                 "samples_per_launch": int(nnz), "flop_per_sample": FLOP_PER_SAMPLE}
 
-    # dominant kernel of the outer iteration: the forward-weights kernel of the projection
-    roofline = roof("fwd_edges_k", kern_ms["fwd_edges_k"])
-    roofline_bwd = roof("bwd_tiles_k", kern_ms["bwd_tiles_k"])
+    # dominant kernel: the projector kernel with the most time per outer iteration
+    dominant = max(loop_kernels, key=lambda k: loop_kernels[k]["ms_per_outer_iteration"])
+    other = [k for k in loop_kernels if k != dominant][0]
+    roofline = roof(dominant)
+    roofline_other = roof(other)
 
     dyn = None
     if not args.no_dynamic:
@@ -559,20 +666,9 @@ def main():
         streaming = streaming_leg(torch, ops, synth, Config, 3)
 
     cpu = None
+    op_parity = None
     if not args.no_cpu_baseline:
-        from oracle import method as OM
-        from oracle import projector as OP
-        geo = OM.Geometry(N=wl.N, nb=wl.nb, view_off=inst.view_off)
-        b_ora, e_ora = OM.make_data(geo, x_true, inst.theta_true, inst.g, wl.noise)
-        ocfg = OM.Config(kmin=wl.kmin, kmax=wl.kmax, eps=wl.eps)
-        st = OM.init_state(geo, inst.theta_nom, b_ora, ocfg)
-        c0 = time.perf_counter()
-        OM.outer_step(geo, st, b_ora, float(np.linalg.norm(e_ora)), ocfg)
-        csec = time.perf_counter() - c0
-        cpu = {"value": round(1.0 / csec, 5), "unit": "outer it/s", "cores": OP.max_threads(),
-               "kind": "oracle",
-               "sample": f"one outer iteration (the first after the GKB start basis) of the "
-                         f"same 256x256 / 360-view workload in FP64 on the host, {csec:.1f} s"}
+        cpu, op_parity = cpu_baseline_leg(torch, ops, inst, wl, g, x32, th_true, b, x_true)
 
     out = {
         "metric": "proj+backproj+∂θ Gsamples/s & outer it/s, batched vs plain, relL2≤1e-5",
@@ -612,7 +708,9 @@ def main():
         "streaming_c5": streaming,
         "gram_mfma": gram,
         "roofline": roofline,
-        "roofline_backproject": roofline_bwd,
+        "roofline_" + other: roofline_other,
+        "loop_kernels": loop_kernels,
+        "parity": {"loop_c2": parity, "operators_c2": op_parity},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -139,9 +139,16 @@ int nlrmm_tune_query(nlrmm_ctx *ctx, int32_t kind, const nlrmm_geom *geom,
  * is spread over R launches.  nlrmm_ctx_kernel_ms waits for the stop event and returns the
  * duration per launch in milliseconds; NLRMM_EINVAL if no such launch has been recorded
  * since timing was enabled.  Events are created by nlrmm_ctx_set_timing (so enable it
- * outside graph capture) and freed by nlrmm_ctx_destroy.  enable = 0 turns timing off. */
+ * outside graph capture) and freed by nlrmm_ctx_destroy.  enable = 0 turns timing off.
+ * enable = -P (P = 1 .. 1000) selects per-launch accumulation instead: every P-th eligible
+ * launch (one-column projections without the derivative, reductions or an early-exit flag;
+ * one-column backprojections) records its own event pair around the single kernel launch, up
+ * to 4096 launches per kernel; nlrmm_ctx_kernel_avg waits for the last one, returns the average
+ * duration of the recorded launches in milliseconds and their number, and starts a new
+ * accumulation (NLRMM_EINVAL unless this mode is on). */
 int nlrmm_ctx_set_timing(nlrmm_ctx *ctx, int enable);
 int nlrmm_ctx_kernel_ms(nlrmm_ctx *ctx, int which, float *ms);
+int nlrmm_ctx_kernel_avg(nlrmm_ctx *ctx, int which, float *avg_ms, int32_t *launches);
 
 /* Forward projection y = A(theta) x (the forward operator H(p)u of Section 1,
  * eq. "nonlinear_forward"; applied to every column for the basis block A V of

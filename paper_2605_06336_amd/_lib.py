@@ -58,6 +58,8 @@ SIGNATURES = {
     "nlrmm_ctx_set_tune_file": [_P, ctypes.c_char_p],
     "nlrmm_tune_query": [_P, _I32, _GP, _BP, _I32, ctypes.POINTER(ctypes.c_int32)],
     "nlrmm_ctx_kernel_ms": [_P, _I32, ctypes.POINTER(ctypes.c_float)],
+    "nlrmm_ctx_kernel_avg": [_P, _I32, ctypes.POINTER(ctypes.c_float),
+                             ctypes.POINTER(ctypes.c_int32)],
     "nlrmm_project": [_P, _GP, _BP, _I32, _P, _P, _P, _P],
     "nlrmm_backproject": [_P, _GP, _BP, _I32, _P, _P, _P, _P],
     "nlrmm_backproject_dtheta": [_P, _GP, _BP, _I32, _P, _P, _P, _P],

@@ -64,9 +64,26 @@ int check_batch(const nlrmm_batch *b)
 }
 
 
-void timing_mark(nlrmm_ctx *ctx, int which, int stop, hipStream_t s)
+void timing_mark(nlrmm_ctx *ctx, int which, int stop, hipStream_t s, bool eligible)
 {
     if (!ctx->timing) return;
+    if (ctx->timing < 0) {
+        if (!stop) {
+            if (!eligible) return;
+            const int period = -ctx->timing;
+            const bool take = ctx->acc_seen[which]++ % period == 0;
+            const int i = ctx->acc_used[which];
+            if (take && i < nlrmm_ctx::ACC_CAP &&
+                hipEventRecord(ctx->acc_ev[which][2 * i], s) == hipSuccess)
+                ctx->acc_open[which] = 1;
+        } else if (ctx->acc_open[which]) {
+            const int i = ctx->acc_used[which];
+            if (hipEventRecord(ctx->acc_ev[which][2 * i + 1], s) == hipSuccess)
+                ctx->acc_used[which] = i + 1;
+            ctx->acc_open[which] = 0;
+        }
+        return;
+    }
     if (hipEventRecord(ctx->tev[which][stop], s) == hipSuccess && stop) ctx->tev_set[which] = 1;
 }
 
@@ -128,13 +145,46 @@ int nlrmm_ctx_set_timing(nlrmm_ctx *ctx, int enable)
 {
     if (!ctx) return NLRMM_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    if (enable < -1000) enable = -1000;
     if (enable && !ctx->timing) {
         for (auto &pr : ctx->tev)
             for (auto &e : pr)
                 if (!e && hipEventCreate(&e) != hipSuccess) return NLRMM_EHIP;
         ctx->tev_set[0] = ctx->tev_set[1] = 0;
     }
-    ctx->timing = enable > 0 ? (enable > 1000 ? 1000 : enable) : 0;
+    if (enable < 0) {
+        for (auto &pool : ctx->acc_ev)
+            while ((int)pool.size() < 2 * nlrmm_ctx::ACC_CAP) {
+                hipEvent_t e = nullptr;
+                if (hipEventCreate(&e) != hipSuccess) return NLRMM_EHIP;
+                pool.push_back(e);
+            }
+        for (int k = 0; k < 2; ++k) ctx->acc_used[k] = ctx->acc_seen[k] = ctx->acc_open[k] = 0;
+    }
+    ctx->timing = enable > 0 ? (enable > 1000 ? 1000 : enable) : enable;
+    return NLRMM_OK;
+}
+
+int nlrmm_ctx_kernel_avg(nlrmm_ctx *ctx, int which, float *avg_ms, int32_t *launches)
+{
+    if (!ctx || !avg_ms || which < 0 || which > 1) return NLRMM_EINVAL;
+    if (ctx->timing >= 0) return NLRMM_EINVAL;
+    const int n = ctx->acc_used[which];
+    if (launches) *launches = n;
+    *avg_ms = 0.f;
+    if (n == 0) return NLRMM_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    if (hipEventSynchronize(ctx->acc_ev[which][2 * n - 1]) != hipSuccess) return NLRMM_EHIP;
+    double tot = 0.0;
+    for (int i = 0; i < n; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ctx->acc_ev[which][2 * i], ctx->acc_ev[which][2 * i + 1]) !=
+            hipSuccess)
+            return NLRMM_EHIP;
+        tot += ms;
+    }
+    *avg_ms = (float)(tot / n);
+    ctx->acc_used[which] = ctx->acc_seen[which] = ctx->acc_open[which] = 0;
     return NLRMM_OK;
 }
 
@@ -156,6 +206,8 @@ void nlrmm_ctx_destroy(nlrmm_ctx *ctx)
     for (auto &pr : ctx->tev)
         for (auto &e : pr)
             if (e) (void)hipEventDestroy(e);
+    for (auto &pool : ctx->acc_ev)
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     if (ctx->ws.ptr || ctx->kws.ptr) (void)hipDeviceSynchronize();
     if (ctx->ws.ptr) (void)hipFree(ctx->ws.ptr);
     if (ctx->kws.ptr) (void)hipFree(ctx->kws.ptr);

@@ -43,6 +43,13 @@ struct nlrmm_ctx {
     hipEvent_t tev[2][2] = {};   // [kernel][start, stop]; 0 forward weights, 1 backprojection
     int tev_set[2] = {0, 0};
     int tev_reps[2] = {1, 1};    // launches of the timed kernel between the recorded pair
+    // per-launch accumulation (timing < 0): one event pair per sampled eligible launch, from
+    // a pool created when the mode is enabled; every -timing-th eligible launch is recorded
+    static constexpr int ACC_CAP = 4096;
+    std::vector<hipEvent_t> acc_ev[2];   // [kernel] start, stop of pair i at 2i, 2i + 1
+    int acc_used[2] = {0, 0};
+    int acc_seen[2] = {0, 0};
+    int acc_open[2] = {0, 0};
     // autotuner: cached launch shapes, a candidate forced while tuning, optional cache file
     std::vector<nlrmm::TuneEntry> tune;
     int force_fwd_seg = 0;
@@ -78,7 +85,9 @@ int bwd_split_max(const nlrmm_geom &g, const nlrmm_batch &b);
 int bwd_split_for(const nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols);
 
 // Record the start / stop event of timed kernel `which` on stream s (no-op unless enabled).
-void timing_mark(nlrmm_ctx *ctx, int which, int stop, hipStream_t s);
+// In the per-launch accumulation mode only launches marked eligible (one column, full work)
+// are recorded.
+void timing_mark(nlrmm_ctx *ctx, int which, int stop, hipStream_t s, bool eligible = true);
 // Launches of a timed kernel between its events: the context's repeat count when timing is on
 // and the launch can be repeated without changing its result, else 1.
 int timing_reps(nlrmm_ctx *ctx, int which, bool repeatable);

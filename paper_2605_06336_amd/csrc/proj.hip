@@ -698,40 +698,72 @@ struct BwdArgs {
     TvEpilogue tv;   // one column: x += lam Psi^T (w Psi u) (tv.u null: none)
 };
 
+// Backprojection per pixel and view, summed by parts over the bin edges inside its footprint.
+// With the footprint's bins y_0 .. y_E (E edges inside, offsets v_i of edge i from the pixel
+// centre), x = (1/ds) [sum_i Phi(v_i) (y_{i-1} - y_i) + d^2 y_E].  Writing Phi / h = C + psi
+// with C = d^2 / (2h) (Phi is C + an odd function of v) gives
+//   x ds = (d^2 / 2)(y_0 + y_E) + sum_i psi(v_i) h (y_{i-1} - y_i),
+//   psi(v) = c1 - q |q| / (2 rho),  c1 = med3(v, -wo, wo),  q = c1 - med3(v, -wi, wi),
+// (c1 is the clamped offset; q, the part of it beyond the plateau, is the ramp coordinate:
+// the plateau gives psi = v, a ramp v - (v -+ wi)^2 / (2 rho), outside the footprint
+// psi = +-C; rho = 0 is the box limit with 1 / (2 rho) := 0).  h C = d^2 / 2 is the same for
+// every view, so the window of view v is staged as pairs (h_v (y_{j-1} - y_j), y_j) and one
+// pixel-view costs two medians, a subtraction, a multiplication and two multiply-adds per edge.
+//
 // Per-view constants of one backward tile: the footprint start of the tile centre in bin
 // units, split as jb (staged-window index of its bin) + a fraction in [0, 1), stored as
 // T0 = fraction + TSHIFT and jb - TSHIFT so that every pixel's start T0 + pk ax + pl ay is
-// positive (its truncation is its floor); the bin-unit steps of one pixel along x and
-// y; for edge i of the window the three clamp arguments of Phi / h at fraction 0
-// (i ds, i ds - wo + wi, i ds - wo - wi); h and d^2 / h.
+// positive (its truncation is its floor); the bin-unit steps of one pixel along x and y; for
+// edge i of the window its offset from the pixel centre at fraction 0 (i ds - wo); wo, wi and
+// 1 / (2 rho).
 constexpr int TSHIFT = 64;
 template <int E>
 struct BView {
     double T0, ax, ay;
     int jb;
-    float cq[E][3];
-    float frho, f2wi, fk, fh, dh;
+    float cm[E];
+    float wo, wi, fk;
 };
 
-// One thread per pixel pair (kl, ll) and (kl, ll + 8) of a 16x16 tile: the per-view constants
-// staged in LDS serve two pixels per read.
-constexpr int BWD_BLK = TILE * TILE / 2;
+// One thread per PX pixels of a 16x16 tile, rows ll, ll + 16/PX, ...: the per-view constants
+// staged in LDS serve PX pixels per read.
+template <int PX>
+struct BwdShape {
+    static constexpr int threads = TILE * TILE / PX;
+    static constexpr int rows = TILE / PX;   // row step between a thread's pixels
+};
+constexpr int BWD_PX = 2;
+constexpr int BWD_BLK = BwdShape<BWD_PX>::threads;
 
+// The window of a pixel's footprint lies inside the staged one: with j0 the window's first bin
+// (one bin below the tile footprint's floor) jj = floor(pixel footprint start) - j0 >= 1, and
+// jj + E <= (TILE - 1) d sqrt(2) / ds + 2 + E <= W - 2 (bwd_window), exactly; FP64 rounding of
+// the footprint starts cannot move them by a bin.  Debug builds check it.
 template <int E>
-__global__ __launch_bounds__(BWD_BLK) void bwd_tiles_k(BwdArgs a)
+__device__ __forceinline__ void check_window(int jj, int W)
 {
+#ifdef NLRMM_DEBUG
+    if (jj < 0 || jj + E >= W) __builtin_trap();
+#endif
+}
+
+template <int E, int PX>
+__global__ __launch_bounds__(BwdShape<PX>::threads) void bwd_tiles_k(BwdArgs a)
+{
+    constexpr int NT = BwdShape<PX>::threads;
+    constexpr int RS = BwdShape<PX>::rows;
     __shared__ BView<E> sv[VCHUNK];
     __shared__ int sj0[VCHUNK];
-    __shared__ float sy[VCHUNK][WMAX];
+    __shared__ float sh[VCHUNK];
+    extern __shared__ float2 sy_dyn[];   // [VCHUNK][W] (W staged bins per view, dynamic size):
+                                         // (h (y_{j-1} - y_j), y_j)
     const int tid = threadIdx.x;
     const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
     const int64_t img = blockIdx.y;
     const int64_t col = img / a.nframes;
     const int f = (int)(img - col * a.nframes);
-    const int kl = tid % TILE, ll = tid / TILE;   // ll in [0, TILE / 2)
+    const int kl = tid % TILE, ll = tid / TILE;   // ll in [0, RS)
     const int k = tx * TILE + kl;
-    const int l0 = ty * TILE + ll, l1 = l0 + TILE / 2;
-    const bool act0 = k < a.nx && l0 < a.ny, act1 = k < a.nx && l1 < a.ny;
     const int64_t fv0 = (a.view_off && a.nframes > 1) ? a.view_off[f] : 0;
     const int64_t fv1 = (a.view_off && a.nframes > 1) ? a.view_off[f + 1] : a.V;
     const int split = blockIdx.z;
@@ -742,8 +774,10 @@ __global__ __launch_bounds__(BWD_BLK) void bwd_tiles_k(BwdArgs a)
     const double yc = a.y0 + (ty * TILE + 0.5 * TILE) * a.d;
     // pixel centres relative to the tile centre, in pixels
     const double pk = kl + 0.5 - 0.5 * TILE, pl = ll + 0.5 - 0.5 * TILE;
-    const double hl = 0.5 * TILE;   // row offset of the second pixel
-    double acc0 = 0.0, acc1 = 0.0;
+    double acc[PX];
+#pragma unroll
+    for (int px = 0; px < PX; ++px) acc[px] = 0.0;
+    const float fds = (float)a.ds;
 
     for (int64_t vb = v0; vb < v1; vb += VCHUNK) {
         const int nv = (int)min((int64_t)VCHUNK, v1 - vb);
@@ -759,78 +793,68 @@ __global__ __launch_bounds__(BWD_BLK) void bwd_tiles_k(BwdArgs a)
             q.ax = a.d * w.cs / a.ds;
             q.ay = a.d * w.sn / a.ds;
             q.jb = (int)Tf - j0 - TSHIFT;
-            const double wi = (double)w.fwi;
-            for (int i = 1; i <= E; ++i) {
-                q.cq[i - 1][0] = (float)(i * a.ds);
-                q.cq[i - 1][1] = (float)(i * a.ds - w.wo + wi);
-                q.cq[i - 1][2] = (float)(i * a.ds - w.wo - wi);
-            }
-            q.frho = w.frho;
-            q.f2wi = w.f2wi;
+            for (int i = 1; i <= E; ++i) q.cm[i - 1] = (float)(i * a.ds - w.wo);
+            q.wo = w.fwo;
+            q.wi = w.fwi;
             q.fk = w.fk;
-            q.fh = w.fh;
-            q.dh = (float)(a.d * a.d / (double)w.fh);
             sv[tid] = q;
             sj0[tid] = j0;
+            sh[tid] = w.fh;
         }
         __syncthreads();
-        for (int i = tid; i < nv * a.W; i += BWD_BLK) {
+        for (int i = tid; i < nv * a.W; i += NT) {
             const int vi = i / a.W, jj = i - vi * a.W;
             const int jbin = sj0[vi] + jj;
-            sy[vi][jj] = (jbin >= 0 && jbin < a.nb) ? ycol[(vb + vi) * a.nb + jbin] : 0.0f;
+            const float *yv = ycol + (vb + vi) * a.nb;
+            const float y1 = (jbin >= 0 && jbin < a.nb) ? yv[jbin] : 0.0f;
+            const float y0 = (jbin >= 1 && jbin - 1 < a.nb) ? yv[jbin - 1] : 0.0f;
+            sy_dyn[vi * a.W + jj] = make_float2(sh[vi] * (y0 - y1), y1);
         }
         __syncthreads();
-        const float fds = (float)a.ds;
-        float accf0 = 0.0f, accf1 = 0.0f;   // this chunk's views in FP32, chunks summed in FP64
+        // this chunk's views in FP32 (chunks summed in FP64): y_0 + y_E and the edge terms
+        float ay[PX], ap[PX];
+#pragma unroll
+        for (int px = 0; px < PX; ++px) ay[px] = ap[px] = 0.0f;
         for (int vi = 0; vi < nv; ++vi) {
             const BView<E> &q = sv[vi];
-            ViewC w;
-            w.frho = q.frho;
-            w.f2wi = q.f2wi;
-            w.fk = q.fk;
-            // footprint start of each pixel in bin units (shifted positive): window bin jj
-            // and fraction fr; edge i of the window sits at (i - fr) ds - wo from the pixel's
-            // centre
-            const double t0 = fma(pk, q.ax, fma(pl, q.ay, q.T0));
-            const double t1 = fma(hl, q.ay, t0);
-            float sum[2];
+            // footprint start of each pixel in bin units (shifted positive): window bin jj and
+            // fraction fr; edge i of the window sits at (i - fr) ds - wo from the pixel centre
+            double t = fma(pk, q.ax, fma(pl, q.ay, q.T0));
 #pragma unroll
-            for (int px = 0; px < 2; ++px) {
-                const double t = px == 0 ? t0 : t1;
+            for (int px = 0; px < PX; ++px) {
+                if (px > 0) t = fma((double)RS, q.ay, t);
                 const float fr = (float)__builtin_amdgcn_fract(t);
-                int jj = q.jb + (int)t;
-                jj = min(max(jj, 0), a.W - (E + 1));
-                const float *yy = &sy[vi][jj];
-                float prev = 0.0f, sm = 0.0f;
+                const int jj = q.jb + (int)t;
+                check_window<E>(jj, a.W);
+                const float2 *yy = &sy_dyn[vi * a.W + jj];
+                ay[px] += yy[0].y + yy[E].y;     // times d^2 / 2, applied per chunk
 #pragma unroll
                 for (int i = 1; i <= E; ++i) {
-                    const float ph = phi_h(fmaf(-fr, fds, q.cq[i - 1][0]),
-                                           fmaf(-fr, fds, q.cq[i - 1][1]),
-                                           fmaf(-fr, fds, q.cq[i - 1][2]), w);
-                    sm = fmaf(ph - prev, yy[i - 1], sm);
-                    prev = ph;
+                    const float v = fmaf(-fr, fds, q.cm[i - 1]);
+                    const float c1 = __builtin_amdgcn_fmed3f(v, -q.wo, q.wo);
+                    const float qq = c1 - __builtin_amdgcn_fmed3f(v, -q.wi, q.wi);
+                    const float psi = fmaf(-q.fk, qq * fabsf(qq), c1);
+                    ap[px] = fmaf(psi, yy[i].x, ap[px]);   // psi_i h (y_{i-1} - y_i)
                 }
-                sum[px] = fmaf(q.dh - prev, yy[E], sm);
             }
-            accf0 = fmaf(q.fh, sum[0], accf0);
-            accf1 = fmaf(q.fh, sum[1], accf1);
         }
-        acc0 += (double)accf0;
-        acc1 += (double)accf1;
+        const float hd2 = 0.5f * (float)(a.d * a.d);
+#pragma unroll
+        for (int px = 0; px < PX; ++px) acc[px] += (double)fmaf(hd2, ay[px], ap[px]);
         __syncthreads();
     }
     const int64_t ibase = (col * a.nframes + f) * (int64_t)a.ny;
 #pragma unroll
-    for (int px = 0; px < 2; ++px) {
-        if (!(px == 0 ? act0 : act1)) continue;
-        const double acc = px == 0 ? acc0 : acc1;
-        const int64_t o = (ibase + (px == 0 ? l0 : l1)) * a.nx + k;
+    for (int px = 0; px < PX; ++px) {
+        const int l = ty * TILE + ll + px * RS;
+        if (k >= a.nx || l >= a.ny) continue;
+        const int64_t o = (ibase + l) * a.nx + k;
         if (a.nsplit > 1) {
             const int64_t tot = (int64_t)gridDim.y * a.nx * a.ny;
-            a.part[split * tot + o] = (float)(acc / a.ds);
+            a.part[split * tot + o] = (float)(acc[px] / a.ds);
         } else {
             const double prev = a.accumulate ? (double)a.x[o] : 0.0;
-            float v = (float)(prev + acc / a.ds);
+            float v = (float)(prev + acc[px] / a.ds);
             if (a.tv.u != nullptr)
                 v += (float)a.tv.lamp[0] *
                      tv_grad_at(a.tv.u, a.tv.w, tvgeo(a.nx, a.ny, a.nframes, a.tv.temporal), o,
@@ -855,8 +879,10 @@ struct BMView {
     float fwo, fwi, frho, fh, inv_ab, Kr, tq, kp, kappa;
 };
 
+constexpr int MOM_BLK = TILE * TILE / 2;   // one thread per pixel pair
+
 template <int E>
-__global__ __launch_bounds__(BWD_BLK) void bwd_moment_tiles_k(BwdArgs a)
+__global__ __launch_bounds__(MOM_BLK) void bwd_moment_tiles_k(BwdArgs a)
 {
     __shared__ BMView<E> sv[VCHUNK];
     __shared__ int sj0[VCHUNK];
@@ -915,7 +941,7 @@ __global__ __launch_bounds__(BWD_BLK) void bwd_moment_tiles_k(BwdArgs a)
         __syncthreads();
         // staged as differences r_j - r_{j-1} (r = 0 outside the detector): the same FP32
         // subtraction the per-pixel sum would make, done once per view
-        for (int i = tid; i < nv * a.W; i += BWD_BLK) {
+        for (int i = tid; i < nv * a.W; i += MOM_BLK) {
             const int vi = i / a.W, jj = i - vi * a.W;
             const int jbin = sj0[vi] + jj;
             const float *yv = ycol + (vb + vi) * a.nb;
@@ -948,8 +974,8 @@ __global__ __launch_bounds__(BWD_BLK) void bwd_moment_tiles_k(BwdArgs a)
                 const double t = px == 0 ? t0 : t1;
                 const float tc = px == 0 ? tcp0 : tcp1;
                 const float fr = (float)__builtin_amdgcn_fract(t);
-                int jj = q.jb + (int)t;
-                jj = min(max(jj, 0), a.W - (E + 1));
+                const int jj = q.jb + (int)t;
+                check_window<E>(jj, a.W);
                 const float *yy = &sy[vi][jj];
                 float sm = 0.0f;
 #pragma unroll
@@ -1153,7 +1179,9 @@ int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
         // every output of the kernel is a function of the packs and angles only, so repeated
         // timing launches leave the result unchanged
         const int reps = timing_reps(ctx, 0, true);
-        timing_mark(ctx, 0, 0, s);
+        // per-launch accumulation times full one-column projections only
+        const bool eligible = ncols == 1 && proj && !mom && !red && o.skip == nullptr;
+        timing_mark(ctx, 0, 0, s, eligible);
         for (int rep = 0; rep < reps; ++rep) {
             if (proj && mom) launch_fwd_mode<3>(NC, seg, grid, a, s);
             else if (mom) launch_fwd_mode<2>(NC, seg, grid, a, s);
@@ -1277,10 +1305,10 @@ int launch_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_b
     dim3 grid((unsigned)(a.tiles_x * tiles_y), (unsigned)((int64_t)ncols * b.nframes),
               (unsigned)a.nsplit);
     switch (E) {
-        case 1: bwd_moment_tiles_k<1><<<grid, BWD_BLK, 0, s>>>(a); break;
-        case 2: bwd_moment_tiles_k<2><<<grid, BWD_BLK, 0, s>>>(a); break;
-        case 3: bwd_moment_tiles_k<3><<<grid, BWD_BLK, 0, s>>>(a); break;
-        default: bwd_moment_tiles_k<4><<<grid, BWD_BLK, 0, s>>>(a); break;
+        case 1: bwd_moment_tiles_k<1><<<grid, MOM_BLK, 0, s>>>(a); break;
+        case 2: bwd_moment_tiles_k<2><<<grid, MOM_BLK, 0, s>>>(a); break;
+        case 3: bwd_moment_tiles_k<3><<<grid, MOM_BLK, 0, s>>>(a); break;
+        default: bwd_moment_tiles_k<4><<<grid, MOM_BLK, 0, s>>>(a); break;
     }
     if (a.nsplit > 1) {
         const int64_t n = (int64_t)ncols * b.nframes * g.nx * g.ny;
@@ -1350,13 +1378,13 @@ int launch_backproject_into(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_bat
               (unsigned)a.nsplit);
     // repeated timing launches are harmless unless the kernel adds into x itself
     const int reps = timing_reps(ctx, 1, a.nsplit > 1 || (!accumulate && a.tv.u == nullptr));
-    timing_mark(ctx, 1, 0, s);
+    timing_mark(ctx, 1, 0, s, ncols == 1);
     for (int rep = 0; rep < reps; ++rep) {
         switch (E) {
-            case 1: bwd_tiles_k<1><<<grid, BWD_BLK, 0, s>>>(a); break;
-            case 2: bwd_tiles_k<2><<<grid, BWD_BLK, 0, s>>>(a); break;
-            case 3: bwd_tiles_k<3><<<grid, BWD_BLK, 0, s>>>(a); break;
-            default: bwd_tiles_k<4><<<grid, BWD_BLK, 0, s>>>(a); break;
+            case 1: bwd_tiles_k<1, BWD_PX><<<grid, BWD_BLK, sizeof(float2) * VCHUNK * a.W, s>>>(a); break;
+            case 2: bwd_tiles_k<2, BWD_PX><<<grid, BWD_BLK, sizeof(float2) * VCHUNK * a.W, s>>>(a); break;
+            case 3: bwd_tiles_k<3, BWD_PX><<<grid, BWD_BLK, sizeof(float2) * VCHUNK * a.W, s>>>(a); break;
+            default: bwd_tiles_k<4, BWD_PX><<<grid, BWD_BLK, sizeof(float2) * VCHUNK * a.W, s>>>(a); break;
         }
     }
     timing_mark(ctx, 1, 1, s);

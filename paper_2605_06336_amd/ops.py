@@ -28,7 +28,8 @@ def context(device: int = 0) -> int:
 
 def set_kernel_timing(enable, device: int = 0) -> None:
     """Event timing of the forward-weights and backprojection kernels (measurement): False
-    off, True on, an int R > 1 launches each timed kernel R times between its events."""
+    off, True on, an int R > 1 launches each timed kernel R times between its events, an int
+    -P < 0 records every P-th eligible single launch for kernel_avg."""
     check(_lib.lib().nlrmm_ctx_set_timing(context(device), int(enable)), "nlrmm_ctx_set_timing")
 
 
@@ -39,6 +40,18 @@ def kernel_ms(which: str, device: int = 0) -> float:
     check(_lib.lib().nlrmm_ctx_kernel_ms(context(device), {"project": 0, "backproject": 1}[which],
                                          ctypes.byref(ms)), "nlrmm_ctx_kernel_ms")
     return float(ms.value)
+
+
+def kernel_avg(which: str, device: int = 0):
+    """Per-launch accumulation mode (set_kernel_timing(-P)): (average ms of the recorded
+    single launches of the 'project' or 'backproject' kernel, their number); resets."""
+    ms = ctypes.c_float()
+    n = ctypes.c_int32()
+    check(_lib.lib().nlrmm_ctx_kernel_avg(context(device),
+                                          {"project": 0, "backproject": 1}[which],
+                                          ctypes.byref(ms), ctypes.byref(n)),
+          "nlrmm_ctx_kernel_avg")
+    return float(ms.value), int(n.value)
 
 
 def geom(N: int, nb: int, ny: Optional[int] = None, half: float = 1.0,

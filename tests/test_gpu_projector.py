@@ -26,6 +26,16 @@ def dev(a, dtype):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
 
 
+def per_view(a, b, nb):
+    """Largest relative L2 difference over single views (rows of nb bins) of two sinograms:
+    one bad view cannot hide under the norm of all the others."""
+    a = np.asarray(a, np.float64).reshape(-1, nb)
+    b = np.asarray(b, np.float64).reshape(-1, nb)
+    nrm = np.linalg.norm(b, axis=1)
+    ok = nrm > 0
+    return float(np.max(np.linalg.norm(a - b, axis=1)[ok] / nrm[ok]))
+
+
 def angles(V, seed):
     return np.concatenate([SPECIAL, synth.random_angles(V, seed)])
 
@@ -125,16 +135,25 @@ def test_forward_backward_dtheta_parity(N, nb, V, F, ncols):
     assert rel(y, y_ref) <= TOL, rel(y, y_ref)
     for c in range(ncols):
         assert rel(y[c], y_ref[c]) <= TOL
+    assert per_view(y, y_ref, nb) <= TOL, per_view(y, y_ref, nb)
 
     ys = synth.random_sinogram(Vt * ncols, nb, seed=N + 2).reshape(ncols, Vt, nb).astype(np.float32)
     xb = ops.backproject(dev(ys, torch.float32), tht, g, fr).cpu().numpy()
     xb_ref = P.backproject(ys.astype(np.float64), th, N, vo)
     assert rel(xb, xb_ref.reshape(xb.shape)) <= TOL, rel(xb, xb_ref.reshape(xb.shape))
+    # per image (column and frame) of the backprojection
+    xbi = xb.reshape(ncols * F, -1)
+    xri = xb_ref.reshape(ncols * F, -1)
+    assert max(rel(xbi[i], xri[i]) for i in range(ncols * F)) <= TOL
 
     res = ops.project_dtheta(xt, tht, g, fr, want_dy=True, want_y=True)
     D_ref = P.dtheta(x32.astype(np.float64), th, nb, vo)
-    assert rel(res["dy"].cpu().numpy(), D_ref) <= TOL, rel(res["dy"].cpu().numpy(), D_ref)
+    D = res["dy"].cpu().numpy()
+    assert rel(D, D_ref) <= TOL, rel(D, D_ref)
+    assert per_view(D, D_ref, nb) <= TOL, per_view(D, D_ref, nb)
     assert rel(res["y"].cpu().numpy(), y_ref) <= TOL
+    print(f"  per-view max relL2: projection {per_view(y, y_ref, nb):.2e}, derivative "
+          f"{per_view(D, D_ref, nb):.2e}", flush=True)
 
 
 @pytest.mark.parametrize("N,nb,V", [(64, 91, 25), (256, 363, 60)])
@@ -198,6 +217,8 @@ def test_full_size_c3_projection_and_derivative():
     D_ref = P.dtheta(x32.astype(np.float64), inst.theta_true, wl.nb)
     assert rel(res["y"].cpu().numpy()[0], y_ref) <= TOL
     assert rel(res["dy"].cpu().numpy()[0], D_ref) <= TOL
+    assert per_view(res["y"].cpu().numpy()[0], y_ref, wl.nb) <= TOL
+    assert per_view(res["dy"].cpu().numpy()[0], D_ref, wl.nb) <= TOL
     xb = ops.backproject(dev(y_ref.astype(np.float32), torch.float32), tht, g).cpu().numpy()
     xb_ref = P.backproject(y_ref.astype(np.float32).astype(np.float64), inst.theta_true, wl.N)
     assert rel(xb[0, 0], xb_ref) <= TOL
@@ -233,6 +254,8 @@ def test_dtheta_transpose_parity(N, nb, V, F, ncols):
     x = ops.backproject_dtheta(dev(r, torch.float32), tht, g, fr).cpu().numpy()
     x_ref = P.dtheta_t(r.astype(np.float64), th, N, vo).reshape(x.shape)
     assert rel(x, x_ref) <= TOL, rel(x, x_ref)
+    xi, xri = x.reshape(ncols * F, -1), x_ref.reshape(ncols * F, -1)
+    assert max(rel(xi[i], xri[i]) for i in range(ncols * F)) <= TOL
     xs = synth.random_image(N, seed=N + 9, frames=F * ncols).reshape(ncols, F, N, N)
     D = ops.project_dtheta(dev(xs.astype(np.float32), torch.float32), tht, g, fr,
                            want_dy=True)["dy"].cpu().numpy().astype(np.float64)

@@ -137,6 +137,10 @@ def test_full_size_c5_operators_on_sampled_views():
     D_ref = P.dtheta(x64, th[sample], nb)
     assert rel(y[sample], y_ref) <= 1e-5
     assert rel(D[sample], D_ref) <= 1e-5
+    # every sampled view on its own
+    for i, v in enumerate(sample):
+        assert rel(y[v], y_ref[i]) <= 1e-5, (v, rel(y[v], y_ref[i]))
+        assert rel(D[v], D_ref[i]) <= 1e-5, (v, rel(D[v], D_ref[i]))
     # backprojection of a sinogram that is non-zero on the sampled views only
     ys = np.zeros((wl.n_views, nb), dtype=np.float32)
     ys[sample] = rng.standard_normal((len(sample), nb)).astype(np.float32)
