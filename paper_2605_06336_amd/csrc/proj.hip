@@ -17,7 +17,9 @@
 // through a per-line FP64 prefix sum.  Bins follow as y_j = (C(e_{j+1}) - C(e_j)) / ds
 // and D_j = (Mo(e_j) - Mo(e_{j+1})) / ds.  Every Phi evaluation is shared by the two
 // bins that meet at the edge, so each application evaluates Phi ~2 per edge-line
-// instead of ~2 per (ray, pixel) nonzero.  No atomics; results are deterministic.
+// instead of ~2 per (ray, pixel) nonzero; the even part of Phi (half the pixel area) is
+// carried by the line packs, so only its odd part is evaluated.  No atomics; results are
+// deterministic.
 //
 // Forward lanes of one block are 64 consecutive edges; every wave of the block walks the
 // union of the 64 edges' line ranges (one pack load of a wave reads neighbouring entries of
@@ -26,9 +28,10 @@
 //
 // Backward (pixel-driven gather): one lane per pixel pair of a 16x16 tile; for chunks of
 // views the tile's detector window is staged in LDS, each pixel locates its footprint
-// in bin units relative to the tile centre (FP64), evaluates Phi at the <= E edges inside
-// it (FP32 offsets) and gathers its <= E+1 bins.  Same weight function as the forward;
-// the two are transposes up to FP32 rounding of the offsets.  The derivative's transpose
+// in bin units relative to the tile centre (FP64), evaluates the odd part of Phi at the
+// <= E edges inside it (FP32 offsets) and gathers its <= E+1 bins; the even part enters
+// through the footprint's two end bins.  Same weight function as the forward; the two are
+// transposes up to FP32 rounding of the offsets.  The derivative's transpose
 // gathers the chord moments at the same edges the same way.
 #include "internal.h"
 #include "tv.h"
@@ -85,19 +88,21 @@ __device__ __forceinline__ ViewC make_view(double th, double d)
     return q;
 }
 
-// Cumulative footprint Phi(v): area of the pixel on the side p.n < c + v, a left ramp
-// t1^2 h / (2 rho), a plateau h t2 and a right ramp h (t3 - t3^2 / (2 rho)).  phi_h returns
-// Phi(v) / h from the three shifted offsets u1 = v + wo, u2 = v + wi, u3 = v - wi, each t
-// clamped by one median; the caller applies the factor h once per sum.  The forward and
-// backward kernels evaluate this function of offsets formed with different (both
-// FP64-positioned) arithmetic, so the two operators are transposes of each other up to FP32
-// rounding of the offsets.
-__device__ __forceinline__ float phi_h(float u1, float u2, float u3, const ViewC &q)
+// Cumulative footprint Phi(v): the area of the pixel on the side p.n < c + v, a piecewise
+// quadratic in v (a left ramp of width rho, a plateau of height h, a right ramp) whose even
+// part is the constant d^2 / 2, half the pixel's area.  The forward and backward kernels
+// evaluate its odd part psi_h of offsets formed with different (both FP64-positioned)
+// arithmetic, so the two operators are transposes of each other up to FP32 rounding of the
+// offsets.
+// Phi(v) / h - d^2 / (2 h), the odd part of the cumulative footprint: with c1 the offset
+// clamped to the footprint [-wo, wo] and q = c1 - clamp(v, -wi, wi) its part beyond the
+// plateau, psi = c1 - q |q| / (2 rho) (fk = 1 / (2 rho), 0 when rho = 0).  On the plateau
+// psi = v, on a ramp v -+ (|v| - wi)^2 / (2 rho), outside the footprint +-(wi + rho / 2).
+__device__ __forceinline__ float psi_h(float v, float wo, float wi, float fk)
 {
-    const float t1 = __builtin_amdgcn_fmed3f(u1, 0.0f, q.frho);
-    const float t2 = __builtin_amdgcn_fmed3f(u2, 0.0f, q.f2wi);
-    const float t3 = __builtin_amdgcn_fmed3f(u3, 0.0f, q.frho);
-    return fmaf(q.fk, t1 * t1, fmaf(t3, fmaf(-q.fk, t3, 1.0f), t2));
+    const float c1 = __builtin_amdgcn_fmed3f(v, -wo, wo);
+    const float q = c1 - __builtin_amdgcn_fmed3f(v, -wi, wi);
+    return fmaf(-fk, q * fabsf(q), c1);
 }
 
 // Chord through the pixel at offset v from its centre: length L and the local midpoint
@@ -149,8 +154,10 @@ __device__ __forceinline__ T wave_sum(T v)
 // preparation: per-line packs of rows and columns
 // ---------------------------------------------------------------------------
 // One block per (image, line), rows (blockIdx.x < ny) and columns (the rest) of the image
-// in one launch: entries i = -2..n of the line, stored at i + 2: P = sum of pixels 0..i-1
-// (FP64), a = x_i, b = x_{i+1} (zero outside the line); tot = the line's sum.  The mirrored
+// in one launch: entries i = -2..n of the line, stored at i + 2: a = x_i, b = x_{i+1} (zero
+// outside the line) and P = the sum of pixels 0..i-1 plus (a + b) / 2 (FP64: the prefix up to
+// the middle of the pair, which carries the even part d^2 / 2 of the pair's footprint areas,
+// so that the walk needs only the odd part psi_h); tot = the line's sum.  The mirrored
 // pack holds the same entries for the reversed line (pixel i of it is pixel n-1-i), so a
 // walk against the pixel order reads its prefix directly.
 __global__ __launch_bounds__(BLK) void pack_lines_k(const float *__restrict__ x, int nx, int ny,
@@ -206,12 +213,12 @@ __global__ __launch_bounds__(BLK) void pack_lines_k(const float *__restrict__ x,
     for (int e = tid; e < n + 3; e += BLK) {
         const int i = e - 2;
         PackEntry pe, pm;
-        pe.P = (i > 0) ? sP[i] : 0.0;
         pe.a = (i >= 0 && i < n) ? sx[i] : 0.0f;
         pe.b = (i + 1 >= 0 && i + 1 < n) ? sx[i + 1] : 0.0f;
-        pm.P = (i > 0) ? sP[n] - sP[n - i] : 0.0;
+        pe.P = ((i > 0) ? sP[i] : 0.0) + 0.5 * ((double)pe.a + (double)pe.b);
         pm.a = (i >= 0 && i < n) ? sx[n - 1 - i] : 0.0f;
         pm.b = (i + 1 >= 0 && i + 1 < n) ? sx[n - 2 - i] : 0.0f;
+        pm.P = ((i > 0) ? sP[n] - sP[n - i] : 0.0) + 0.5 * ((double)pm.a + (double)pm.b);
         out[e] = pe;
         outm[e] = pm;
     }
@@ -444,19 +451,13 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
         // straddles is K0 = floor(q) + 1; with r = q + 2 clamped to [0, n + 1] the pack entry
         // index is K0 + 2 = 1 + trunc(r) and r - trunc(r) its fraction.  The offsets of the
         // edge from the centres of pixels K0 and K0 + 1 are va = wo + (q - K0) step and
-        // va - step; every clamp argument of Phi is an FMA of that fraction.
+        // va - step, FMAs of that fraction.
         const double dq = -a.d * sl * inv_step;
         double r = sa <= sb ? (__dsub_rn(e, __dmul_rn(pix_coord(line0, a.d, sa), sl)) - w.wo -
                                cw0) * inv_step + 2.0
                             : 0.0;
         const float stepf = (float)step;
         const float c0a = (float)(w.wo - step);            // va = c0a + dr * step
-        const float c1a = (float)(2.0 * w.wo - step);      // va + wo
-        const float c2a = (float)(w.wo - step + (double)w.fwi);
-        const float c3a = (float)(w.wo - step - (double)w.fwi);
-        const float c1b = (float)(2.0 * w.wo - 2.0 * step);   // vb + wo, vb = va - step
-        const float c2b = (float)(w.wo - 2.0 * step + (double)w.fwi);
-        const float c3b = (float)(w.wo - 2.0 * step - (double)w.fwi);
         const PackEntry *pline = pack + img0 * pstride + (int64_t)sa * (nminor + 3) + 1;
         // Along-ray coordinate of the centre of pixel k on line L, affine in both indices:
         // t(L, k) = tS + (L - sa) d tl + k d tm, with tS the value at (sa, 0) formed in FP64.
@@ -485,20 +486,18 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
                 K1 = (int)rc;
                 dr = (float)__builtin_amdgcn_fract(rc);
             };
-            // x * Phi / h (and the chord moments) of the two straddled pixels of a located
+            // x * psi_h (and the chord moments) of the two straddled pixels of a located
             // line into the FP32 sums fF / fM of its pair of lines; the prefix into accP
             auto apply = [&](int L, int K1, float dr, const PackEntry (&E)[NC], float (&fF)[NC],
                              float (&fM)[NC]) __attribute__((always_inline)) {
                 float pa = 0.f, pb = 0.f, ma = 0.f, mb = 0.f;
+                const float va = fmaf(dr, stepf, c0a);
+                const float vb = va - stepf;
                 if (PROJ) {
-                    pa = phi_h(fmaf(dr, stepf, c1a), fmaf(dr, stepf, c2a), fmaf(dr, stepf, c3a),
-                               w);
-                    pb = phi_h(fmaf(dr, stepf, c1b), fmaf(dr, stepf, c2b), fmaf(dr, stepf, c3b),
-                               w);
+                    pa = psi_h(va, w.fwo, w.fwi, w.fk);
+                    pb = psi_h(vb, w.fwo, w.fwi, w.fk);
                 }
                 if (MOM) {
-                    const float va = fmaf(dr, stepf, c0a);
-                    const float vb = va - stepf;
                     const float tLf = fmaf((float)(L - sa), dtlf, tBf);
                     const float ta = fmaf((float)K1, ksf, tLf);   // straddled pixel a
                     const float tb = ta + ksf;                      // its neighbour b
@@ -830,10 +829,7 @@ __global__ __launch_bounds__(BwdShape<PX>::threads) void bwd_tiles_k(BwdArgs a)
                 ay[px] += yy[0].y + yy[E].y;     // times d^2 / 2, applied per chunk
 #pragma unroll
                 for (int i = 1; i <= E; ++i) {
-                    const float v = fmaf(-fr, fds, q.cm[i - 1]);
-                    const float c1 = __builtin_amdgcn_fmed3f(v, -q.wo, q.wo);
-                    const float qq = c1 - __builtin_amdgcn_fmed3f(v, -q.wi, q.wi);
-                    const float psi = fmaf(-q.fk, qq * fabsf(qq), c1);
+                    const float psi = psi_h(fmaf(-fr, fds, q.cm[i - 1]), q.wo, q.wi, q.fk);
                     ap[px] = fmaf(psi, yy[i].x, ap[px]);   // psi_i h (y_{i-1} - y_i)
                 }
             }
