@@ -13,7 +13,9 @@ Each function follows the paper's algorithm in the paper's order:
   * UPDATE-PARAM ............. Alg. "update_param" (damped Gauss-Newton + Armijo)
   * VarPro ................... Section 4.2 eqs. "u_closed_form", "GN_system", supplementary
                                Alg. "update_varpro"
-  * full-space sensitivity ... Section 4.2, eq. "sensitivity" for one global offset (dense)
+  * full-space sensitivity ... Section 4.2, eq. "sensitivity" for one global offset (dense,
+                               and by a fixed number of CG steps as a parameter update with
+                               Armijo on the compressed-basis reduced objective)
   * grid-search start ........ experiments section, "Parameter initialization" (one
                                global offset, reduced least squares on a GKB basis)
   * NL-RMM-GKS ............... Alg. "nl_rmmgks_two_solves", with the optional
@@ -99,6 +101,12 @@ def dA(geo: Geometry, theta, x):
     return P.dtheta(X, theta, geo.nb, geo.view_off).reshape(-1)
 
 
+def dAT(geo: Geometry, theta, y):
+    """Transpose of ``dA``: sum over views of the angle-derivative weights times y."""
+    Y = np.asarray(y).reshape(geo.V, geo.nb)
+    return np.asarray(P.dtheta_t(Y, theta, geo.N, geo.view_off)).reshape(-1)
+
+
 def A_cols(geo: Geometry, theta, X):
     """A applied to every column of X (n x k) -> m x k."""
     k = X.shape[1]
@@ -178,7 +186,8 @@ class Config:
     dp_iters: int = 200
     lam_fix: Optional[float] = None   # fixed lambda instead of DP
     lam_hi: Optional[float] = None    # high-regularisation solve for the parameter update
-    gn: str = "altmin"                # "altmin" | "varpro" | "none"
+    gn: str = "altmin"                # "altmin" | "varpro" | "sensitivity" | "none"
+    sens_iters: int = 50              # CG steps of the sensitivity equation ("sensitivity")
     param_mode: str = "per_view"      # "per_view" | "scalar" (one global shift)
     maxiter_p: int = 1
     mu_rel: float = 1e-6
@@ -477,6 +486,72 @@ def offset_sensitivity(geo: Geometry, theta, u, b, w, lam):
     return up, g, h, -g / h
 
 
+def offset_sensitivity_cg(geo: Geometry, theta, u, b, w, lam, iters):
+    """The full-space sensitivity of one global angle offset p (Section 4.2, eqs.
+    "sensitivity" and "GN_system") with u_p from `iters` conjugate-gradient steps started at
+    0 on M = A^T A + lam Psi^T diag(w) Psi, applied matrix-free:
+      M u_p = -(A_p^T r + A^T A_p u),  r = A u - b,  A_p u = dA u (every view moves with p),
+      J_r = A_p u + A u_p,  g = J_r^T r + lam (Psi u_p)^T diag(w) Psi u,
+      h = J_r^T J_r + lam (Psi u_p)^T diag(w) Psi u_p.
+    Returns (u_p, g, h)."""
+    r = A(geo, theta, u) - b
+    Du = dA(geo, theta, u)
+    rhs = -(dAT(geo, theta, r) + AT(geo, theta, Du))
+
+    def Mv(x):
+        return AT(geo, theta, A(geo, theta, x)) + lam * psiT(geo, w * psi(geo, x))
+
+    x = np.zeros(geo.n)
+    res = rhs.copy()
+    p = res.copy()
+    rr = float(res @ res)
+    for _ in range(iters):
+        q = Mv(p)
+        pq = float(p @ q)
+        alpha = rr / pq if pq != 0.0 else 0.0
+        x = x + alpha * p
+        res = res - alpha * q
+        rr_new = float(res @ res)
+        beta = rr_new / rr if rr != 0.0 else 0.0
+        rr = rr_new
+        p = res + beta * p
+    Jr = Du + A(geo, theta, x)
+    Pu, Pp = psi(geo, u), psi(geo, x)
+    g = float(Jr @ r + lam * Pp @ (w * Pu))
+    h = float(Jr @ Jr + lam * Pp @ (w * Pp))
+    return x, g, h
+
+
+def gn_sensitivity(geo: Geometry, theta, u, V, b, w, PV, lam, cfg: Config):
+    """Parameter update of one global angle offset from the full-space sensitivity equation
+    (Section 4.2): the Gauss-Newton step dp = -g / (h + mu), mu = mu_rel h, of eq. "GN_system"
+    for one parameter with g, h from ``offset_sensitivity_cg`` at the image u, and Armijo
+    backtracking on the reduced objective with u(p) taken in the compressed basis V (the
+    inexact inner solve the paper uses in practice; as in ``gn_varpro``).  Every view moves
+    by the same alpha dp."""
+    Bw = np.sqrt(w)[:, None] * PV
+    status = 0
+    info = {}
+    for _ in range(cfg.maxiter_p):
+        _, g, h = offset_sensitivity_cg(geo, theta, u, b, w, lam, cfg.sens_iters)
+        mu = cfg.mu_rel * h
+        dp = -g / (h + mu) if h + mu > 0.0 else 0.0
+        f0 = varpro_parts(geo, theta, V, b, Bw, lam)[4]
+        gd = g * dp
+        alpha = 0.0
+        for q in range(cfg.armijo_trials):
+            a = cfg.alpha0 * cfg.beta ** q
+            ft = varpro_parts(geo, theta + a * dp, V, b, Bw, lam)[4]
+            if ft <= f0 + cfg.c1 * a * gd:
+                alpha = a
+                break
+        if alpha == 0.0:
+            status |= ST_ARMIJO
+        info = dict(g=g, h=h, dp=dp, alpha=alpha, f0=f0)
+        theta = theta + alpha * dp
+    return theta, status, info
+
+
 def init_state(geo: Geometry, theta0, b, cfg: Config) -> State:
     """GKB basis of kmin+1 vectors at the starting angles, u0 = 0."""
     V = gkb_basis(geo, theta0, b, cfg.kmin + 1)
@@ -505,7 +580,7 @@ def hi_solve(geo: Geometry, theta_k, st: State, b, cfg: Config) -> State:
         if t < S - 1:
             r = mm_residual(geo, theta_k, hs, b, w, lam, z)
             append_direction(geo, theta_k, hs, r, cfg)
-    if cfg.gn == "varpro":
+    if cfg.gn in ("varpro", "sensitivity"):
         compress(hs, RA, RP, hs.lam, hs.z, cfg.kmin)
     return hs
 
@@ -540,6 +615,10 @@ def outer_step(geo: Geometry, st: State, b, delta, cfg: Config):
     elif cfg.gn == "varpro":
         w = weights(geo, ps.u, cfg.eps)
         theta_new, flag, info = gn_varpro(geo, theta_k, ps.V, b, w, ps.PV, ps.lam, cfg)
+    elif cfg.gn == "sensitivity":
+        w = weights(geo, ps.u, cfg.eps)
+        theta_new, flag, info = gn_sensitivity(geo, theta_k, ps.u, ps.V, b, w, ps.PV, ps.lam,
+                                               cfg)
     else:
         theta_new, flag, info = theta_k, 0, {}
     st.status |= flag

@@ -68,8 +68,15 @@ def max_threads() -> int:
     return _load().ora_max_threads()
 
 
+# below this many pixel-views a call runs on one thread (every output element is computed
+# within one loop iteration, so the result does not depend on the thread count)
+SMALL_WORK = 1 << 21
+
+
 def _run(name, src, theta, out_shape, N, nb, vo, nthreads):
     ds, s0 = _geom(N, nb)
+    if nthreads == 0 and src.shape[0] * theta.shape[0] * N * N < SMALL_WORK:
+        nthreads = 1
     out = np.zeros(out_shape)
     ip = vo.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     getattr(_load(), name)(N, nb, s0, ds, vo.shape[0] - 1, ip, src.shape[0],

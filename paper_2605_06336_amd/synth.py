@@ -55,6 +55,7 @@ class Workload:
     passes: int = 1             # streaming passes
     eps: float = 1e-3           # smoothing of the l1 penalty
     velocity: float = 0.0       # dynamic: centre velocity bound per frame
+    offset_deg: float = 0.0     # global shift of every true angle (the experiments' parameter)
 
     @property
     def D(self) -> float:
@@ -155,6 +156,7 @@ def draw(wl: Workload, N: Optional[int] = None, with_image: bool = True) -> Inst
         x_true = ellipse_image(N, cx, cy, a, b, phi, rho)[None] if with_image else None
         view_off = np.array([0, V], dtype=np.int64)
     theta_true = theta_nom + rng.normal(0.0, math.radians(wl.sigma_deg), V)
+    theta_true = theta_true + math.radians(wl.offset_deg)
     blocks = None
     if wl.blocks > 1:
         perm = rng.permutation(V)

@@ -12,6 +12,11 @@
 * The streaming driver with several blocks (Alg. "s_nl_rmmgks_final"): its row, angle and
   noise mapping equals a loop written here with two-dimensional indexing of the sinogram,
   and its result does not depend on the order in which the views are stored.
+* The full-space sensitivity step of one global offset (Section 4.2, eqs. "sensitivity",
+  "GN_system"): u_p by conjugate gradients equals the dense solve; with the image at the
+  minimiser of the majorised problem and a basis spanning the image space, g is the
+  derivative of the reduced objective the line search uses; and that line search
+  backtracks and rejects like the others.
 """
 import dataclasses
 import math
@@ -229,3 +234,71 @@ def test_streaming_invariant_under_view_storage_order():
     stp = M.run_streaming(geo, Bp, Ep, th[perm], blocks_p, cfg, passes=2)
     assert np.allclose(stp.u, st.u, rtol=0, atol=1e-10 * np.abs(st.u).max())
     assert np.allclose(stp.theta[inv], st.theta, rtol=0, atol=1e-12)
+
+
+def sens_setup(N=6, nb=9, V=5, lam=0.05):
+    geo, x, th, _, b, _ = problem(N=N, nb=nb, V=V, shift_deg=0.0, noise=0.0)
+    b = M.A(geo, th + math.radians(1.5), x)          # data at a global offset of 1.5 degrees
+    w = M.weights(geo, x + 0.1 * np.cos(np.arange(geo.n)), 1e-2)
+    A, _ = P.dense(geo.N, geo.nb, th)
+    n = geo.n
+    Psi = np.stack([M.psi(geo, np.eye(n)[:, i]) for i in range(n)], axis=1)
+    u_star = np.linalg.solve(A.T @ A + lam * Psi.T @ (w[:, None] * Psi), A.T @ b)
+    return geo, th, b, w, lam, u_star
+
+
+def test_sensitivity_cg_matches_dense_solve():
+    """u_p by conjugate gradients (enough steps to converge on a tiny grid) equals the dense
+    solve of the sensitivity equation, and so do g and h."""
+    geo, th, b, w, lam, u = sens_setup()
+    up_d, g_d, h_d, _ = M.offset_sensitivity(geo, th, u, b, w, lam)
+    up, g, h = M.offset_sensitivity_cg(geo, th, u, b, w, lam, iters=400)
+    assert np.linalg.norm(up - up_d) <= 1e-8 * np.linalg.norm(up_d)
+    assert abs(g - g_d) <= 1e-8 * abs(g_d) and abs(h - h_d) <= 1e-8 * h_d
+
+
+def test_sensitivity_gradient_is_derivative_of_reduced_objective():
+    """With the image at the exact minimiser of the majorised problem and a basis spanning the
+    whole image space, the reduced objective used by the line search is the paper's f(p)
+    (Section 4.2), and the sensitivity gradient g is its derivative (central differences)."""
+    geo, th, b, w, lam, u = sens_setup()
+    V = np.eye(geo.n)
+    PV = M.psi_cols(geo, V)
+    Bw = np.sqrt(w)[:, None] * PV
+    _, g, h = M.offset_sensitivity_cg(geo, th, u, b, w, lam, iters=400)
+    f = lambda p: M.varpro_parts(geo, th + p, V, b, Bw, lam)[4]   # noqa: E731
+    hstep = 1e-6
+    gfd = (f(hstep) - f(-hstep)) / (2 * hstep)
+    assert abs(g - gfd) <= 1e-5 * abs(gfd), (g, gfd)
+    assert g != 0.0 and h > 0.0
+
+
+def test_sensitivity_step_armijo_backtracking():
+    """The sensitivity step's line search: the accepted step is the first alpha0 beta^q meeting
+    the sufficient-decrease test of the reduced objective along the global offset dp, with the
+    directional derivative from central differences; a sign error in that test would change
+    it here.  All trials rejected: the angles stay."""
+    geo, th, b, w, lam, u = sens_setup()
+    V = np.eye(geo.n)
+    PV = M.psi_cols(geo, V)
+    Bw = np.sqrt(w)[:, None] * PV
+    cfg = M.Config(maxiter_p=1, alpha0=16.0, beta=0.5, c1=0.3, armijo_trials=10, mu_rel=1e-6,
+                   sens_iters=400)
+    th_new, status, info = M.gn_sensitivity(geo, th, u, V, b, w, PV, lam, cfg)
+    f = lambda p: M.varpro_parts(geo, th + p, V, b, Bw, lam)[4]   # noqa: E731
+    dp = info["dp"]
+    hstep = 1e-6
+    gd = (f(hstep * dp) - f(-hstep * dp)) / (2 * hstep)   # derivative along dp
+    assert gd < 0
+    f0 = f(0.0)
+    q = first_accepted(lambda a: f(a * dp), f0, gd, cfg.alpha0, cfg.beta, cfg.c1,
+                       cfg.armijo_trials)
+    assert q is not None and q >= 1, q
+    assert info["alpha"] == cfg.alpha0 * cfg.beta ** q
+    assert first_accepted(lambda a: f(a * dp), f0, -gd, cfg.alpha0, cfg.beta, cfg.c1,
+                          cfg.armijo_trials) != q
+    assert np.array_equal(th_new, th + info["alpha"] * dp)
+    assert f(info["alpha"] * dp) < f0
+    cfg = dataclasses.replace(cfg, alpha0=1e4, armijo_trials=2)
+    th_rej, status, info = M.gn_sensitivity(geo, th, u, V, b, w, PV, lam, cfg)
+    assert status & M.ST_ARMIJO and np.array_equal(th_rej, th)
