@@ -294,7 +294,13 @@ typedef struct {
     double tau;              /* discrepancy-principle factor: target = tau * delta */
     double lam_fix;          /* >= 0: fixed lambda; < 0: discrepancy principle */
     int32_t param_update;    /* 0: angles fixed (RMM-GKS); 1: AltMin Gauss-Newton (Alg. "update_param");
-                                2: variable projection (Section 4.2, Alg. "update_varpro") */
+                                2: variable projection (Section 4.2, Alg. "update_varpro");
+                                3: one global offset by the full-space sensitivity equation
+                                (Section 4.2, eqs. "sensitivity", "GN_system"): u_p by
+                                sens_iters conjugate-gradient steps at the image u_{k+1}, the
+                                step dp = -g / (h + mu_rel h) for every view, Armijo on the
+                                reduced objective with u(p) in the compressed basis (needs
+                                param_mode 1 and kmax + 1 - kmin >= 6, else NLRMM_ENOTSUP) */
     int32_t param_mode;      /* 0: one angle per view; 1: one global shift of all views */
     int32_t maxiter_p;       /* Gauss-Newton iterations per outer iteration */
     double mu_rel;           /* damping mu = mu_rel * mean(||D_v||^2) */
@@ -311,6 +317,8 @@ typedef struct {
                                 update uses instead of u_{k+1} (VarPro: with its compressed basis
                                 and lam_hi); the image, basis, lambda and residual carried to the
                                 next outer iteration stay those of the primary solve.  <= 0: off */
+    int32_t sens_iters;      /* conjugate-gradient steps of the sensitivity solve (param_update 3);
+                                <= 0: 50 */
 } nlrmm_solver_cfg;
 
 typedef struct nlrmm_solver nlrmm_solver;

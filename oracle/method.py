@@ -15,7 +15,7 @@ Each function follows the paper's algorithm in the paper's order:
                                Alg. "update_varpro"
   * full-space sensitivity ... Section 4.2, eq. "sensitivity" for one global offset (dense,
                                and by a fixed number of CG steps as a parameter update with
-                               Armijo on the compressed-basis reduced objective)
+                               Armijo on the reduced objective with u(p) to first order)
   * grid-search start ........ experiments section, "Parameter initialization" (one
                                global offset, reduced least squares on a GKB basis)
   * NL-RMM-GKS ............... Alg. "nl_rmmgks_two_solves", with the optional
@@ -522,32 +522,39 @@ def offset_sensitivity_cg(geo: Geometry, theta, u, b, w, lam, iters):
     return x, g, h
 
 
-def gn_sensitivity(geo: Geometry, theta, u, V, b, w, PV, lam, cfg: Config):
+def gn_sensitivity(geo: Geometry, theta, u, b, w, lam, cfg: Config):
     """Parameter update of one global angle offset from the full-space sensitivity equation
     (Section 4.2): the Gauss-Newton step dp = -g / (h + mu), mu = mu_rel h, of eq. "GN_system"
-    for one parameter with g, h from ``offset_sensitivity_cg`` at the image u, and Armijo
-    backtracking on the reduced objective with u(p) taken in the compressed basis V (the
-    inexact inner solve the paper uses in practice; as in ``gn_varpro``).  Every view moves
-    by the same alpha dp."""
-    Bw = np.sqrt(w)[:, None] * PV
+    for one parameter, with u_p, g, h from ``offset_sensitivity_cg`` at the image u, and
+    Armijo backtracking on the reduced objective f(p) = 1/2||r(p)||^2 + lam/2 ||s(p)||^2 with
+    u(p) replaced by its first-order expansion u + (p - p_k) u_p from the sensitivity equation
+    (u(p) itself would need a full inner solve per trial); its slope at p_k is g dp.  Every
+    view moves by the same alpha dp."""
     status = 0
     info = {}
+    sw = np.sqrt(w)
+
+    def f_lin(t, ua):
+        r = A(geo, t, ua) - b
+        s = sw * psi(geo, ua)
+        return 0.5 * float(r @ r) + 0.5 * lam * float(s @ s)
+
     for _ in range(cfg.maxiter_p):
-        _, g, h = offset_sensitivity_cg(geo, theta, u, b, w, lam, cfg.sens_iters)
+        up, g, h = offset_sensitivity_cg(geo, theta, u, b, w, lam, cfg.sens_iters)
         mu = cfg.mu_rel * h
         dp = -g / (h + mu) if h + mu > 0.0 else 0.0
-        f0 = varpro_parts(geo, theta, V, b, Bw, lam)[4]
+        f0 = f_lin(theta, u)
         gd = g * dp
         alpha = 0.0
         for q in range(cfg.armijo_trials):
             a = cfg.alpha0 * cfg.beta ** q
-            ft = varpro_parts(geo, theta + a * dp, V, b, Bw, lam)[4]
+            ft = f_lin(theta + a * dp, u + (a * dp) * up)
             if ft <= f0 + cfg.c1 * a * gd:
                 alpha = a
                 break
         if alpha == 0.0:
             status |= ST_ARMIJO
-        info = dict(g=g, h=h, dp=dp, alpha=alpha, f0=f0)
+        info = dict(g=g, h=h, dp=dp, up=up, alpha=alpha, f0=f0)
         theta = theta + alpha * dp
     return theta, status, info
 
@@ -580,7 +587,7 @@ def hi_solve(geo: Geometry, theta_k, st: State, b, cfg: Config) -> State:
         if t < S - 1:
             r = mm_residual(geo, theta_k, hs, b, w, lam, z)
             append_direction(geo, theta_k, hs, r, cfg)
-    if cfg.gn in ("varpro", "sensitivity"):
+    if cfg.gn == "varpro":
         compress(hs, RA, RP, hs.lam, hs.z, cfg.kmin)
     return hs
 
@@ -617,8 +624,7 @@ def outer_step(geo: Geometry, st: State, b, delta, cfg: Config):
         theta_new, flag, info = gn_varpro(geo, theta_k, ps.V, b, w, ps.PV, ps.lam, cfg)
     elif cfg.gn == "sensitivity":
         w = weights(geo, ps.u, cfg.eps)
-        theta_new, flag, info = gn_sensitivity(geo, theta_k, ps.u, ps.V, b, w, ps.PV, ps.lam,
-                                               cfg)
+        theta_new, flag, info = gn_sensitivity(geo, theta_k, ps.u, b, w, ps.lam, cfg)
     else:
         theta_new, flag, info = theta_k, 0, {}
     st.status |= flag

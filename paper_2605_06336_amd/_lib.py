@@ -45,7 +45,8 @@ class SolverCfg(ctypes.Structure):
                 ("c1", ctypes.c_double), ("beta", ctypes.c_double), ("alpha0", ctypes.c_double),
                 ("armijo_trials", ctypes.c_int32), ("breakdown_tol", ctypes.c_double),
                 ("temporal", ctypes.c_int32), ("gram_precision", ctypes.c_int32),
-                ("compress_precision", ctypes.c_int32), ("lam_hi", ctypes.c_double)]
+                ("compress_precision", ctypes.c_int32), ("lam_hi", ctypes.c_double),
+                ("sens_iters", ctypes.c_int32)]
 
 # name -> argtypes (all return int except where noted)
 SIGNATURES = {

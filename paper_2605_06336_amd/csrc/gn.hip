@@ -248,6 +248,69 @@ __global__ void offset_gn_k(const double *d1, const double *d2, const double *la
     out[2] = h > 0.0 ? -g / h : 0.0;
 }
 
+// Direction of the Gauss-Newton step of one global offset, the same for every view: from
+// gh = [g, h] of the sensitivity solve, dp = -g / (h + mu) with mu = mu_rel h (0 when h <= 0);
+// the Gauss-Newton scalars sc get g dp (the Armijo slope) and mu.
+__global__ void offset_dir_k(const double *__restrict__ gh, double mu_rel, int64_t V,
+                             double *__restrict__ dir, double *__restrict__ sc)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double g = gh[0], h = gh[1];
+    const double mu = mu_rel * h;
+    const double dp = h + mu > 0.0 ? -g / (h + mu) : 0.0;
+    if (v < V) dir[v] = dp;
+    if (v == 0) {
+        sc[1] = g * dp;
+        sc[3] = mu;
+    }
+}
+
+// Image of an Armijo trial of the global-offset step, to first order in the offset:
+// out = u + (alphas[q] dp) u_p with dp = dir[0] (skipped once a trial was accepted).
+__global__ void lin_image_k(const float *__restrict__ u, const float *__restrict__ up, int64_t n,
+                            const double *__restrict__ alphas, int q,
+                            const double *__restrict__ dir, const int *__restrict__ accepted,
+                            float *__restrict__ out)
+{
+    if (*accepted) return;   // uniform
+    const double c = alphas[q] * dir[0];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)((double)u[i] + c * (double)up[i]);
+}
+
+// Reduced objective of the global-offset step, f = 1/2 sum_v ||r_v||^2 + lam/2 reg (rn2 the
+// per-view squared residuals, reg = ||sqrt(w) Psi u||^2, summed in a fixed order): with q < 0
+// it is f0 (sc[0]) and clears the acceptance flag; otherwise the Armijo test of trial q
+// against sc[0] + c1 alphas[q] sc[1] (skipped once a trial was accepted).
+__global__ __launch_bounds__(BLK) void sens_objective_k(const double *__restrict__ rn2, int64_t V,
+                                                        const double *__restrict__ reg,
+                                                        const double *__restrict__ lamp,
+                                                        const double *__restrict__ alphas, int q,
+                                                        double c1, double *__restrict__ sc,
+                                                        int *accepted)
+{
+    __shared__ double sbuf[BLK / 64];
+    if (q >= 0 && *accepted) return;   // uniform
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < V; i += BLK) s += rn2[i];
+    s = block_sum2(s, sbuf);
+    if (threadIdx.x == 0) {
+        const double f = 0.5 * s + 0.5 * lamp[0] * reg[0];
+        if (q < 0) {
+            sc[0] = f;
+            *accepted = 0;
+        } else {
+            const double a = alphas[q];
+            if (f <= sc[0] + c1 * a * sc[1]) {
+                *accepted = 1;
+                sc[2] = a;
+                sc[4] = f;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 #define LAUNCH_OK (hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP)
@@ -322,6 +385,29 @@ int k_offset_gn(const double *d1, const double *d2, const double *lamp, double *
 int k_fill_f64(double *dst, int64_t n, double value, hipStream_t s)
 {
     fill_f64_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(dst, n, value);
+    return LAUNCH_OK;
+}
+
+int k_offset_dir(const double *gh, double mu_rel, int64_t V, double *dir, double *sc,
+                 hipStream_t s)
+{
+    offset_dir_k<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(gh, mu_rel, V, dir, sc);
+    return LAUNCH_OK;
+}
+
+int k_lin_image(const float *u, const float *up, int64_t n, const double *alphas, int q,
+                const double *dir, const int *accepted, float *out, hipStream_t s)
+{
+    const int64_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+    lin_image_k<<<(unsigned)blocks, 256, 0, s>>>(u, up, n, alphas, q, dir, accepted, out);
+    return LAUNCH_OK;
+}
+
+int k_sens_objective(const double *rn2, int64_t V, const double *reg, const double *lamp,
+                     const double *alphas, int q, double c1, double *sc, int *accepted,
+                     hipStream_t s)
+{
+    sens_objective_k<<<1, BLK, 0, s>>>(rn2, V, reg, lamp, alphas, q, c1, sc, accepted);
     return LAUNCH_OK;
 }
 

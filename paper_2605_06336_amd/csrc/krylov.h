@@ -77,6 +77,13 @@ int k_grid_pick(const double *res2, int ncand, const double *shifts, double *the
                 int *best, hipStream_t s);
 int k_fill_i32(int *dst, int64_t n, int value, hipStream_t s);
 int k_fill_f32(float *dst, int64_t n, float value, hipStream_t s);
+int k_offset_dir(const double *gh, double mu_rel, int64_t V, double *dir, double *sc,
+                 hipStream_t s);
+int k_lin_image(const float *u, const float *up, int64_t n, const double *alphas, int q,
+                const double *dir, const int *accepted, float *out, hipStream_t s);
+int k_sens_objective(const double *rn2, int64_t V, const double *reg, const double *lamp,
+                     const double *alphas, int q, double c1, double *sc, int *accepted,
+                     hipStream_t s);
 int k_view_dots(const float *X, int64_t ldx, int k, const float *e, int nb, int64_t V, double *out,
                 hipStream_t s);
 int k_varpro_reduced(const double *GA, int ldg, const double *GP, const double *ab,

@@ -373,6 +373,65 @@ static int varpro_update(Solver &S, const nlrmm_batch &b, double *theta, const f
     return NLRMM_OK;
 }
 
+static int offset_sensitivity(Solver &S, const nlrmm_batch &b, const double *theta,
+                              const float *bvec, int iters, double *out, float *up_out,
+                              hipStream_t s, float *xw, float *rw);
+
+// Parameter update of one global angle offset from the full-space sensitivity equation
+// (Section 4.2, eqs. "sensitivity" and "GN_system"): u_p, g and h (conjugate gradients,
+// sens_iters steps) at the image u, the damped step dp = -g / (h + mu), mu = mu_rel h, for
+// every view, and Armijo backtracking on the reduced objective
+// f(p) = 1/2 ||A(theta + p) u(p) - b||^2 + lam/2 ||sqrt(w) Psi u(p)||^2 with u(p) to first order,
+// u + (p - p_k) u_p (its slope at p_k is g dp).  xw, rw: work columns of the sensitivity solve
+// (null: the spare columns after V's first ell); u_p stays in the first of xw, the trial
+// image goes to its fifth.
+static int sensitivity_update(Solver &S, const nlrmm_batch &b, double *theta, const float *bvec,
+                              hipStream_t s, float *xw, float *rw)
+{
+    const int64_t V = b.nviews;
+    const int64_t n = S.n;
+    if (xw == nullptr || rw == nullptr) {
+        if (S.kcap - S.ell < 6) return NLRMM_ESHAPE;
+        xw = S.V + (int64_t)S.ell * n;
+        rw = S.AV + (int64_t)S.ell * m_of(S, b);
+    }
+    const float *up = xw;
+    float *ua = xw + 4 * n;
+    double *sc = S.sc + S_GN;
+    double *gh = S.cgs + 12;    // [g, h, dp] of the sensitivity solve
+    double *reg = S.cgs + 15;   // ||sqrt(w) Psi u||^2 of the current image or trial
+    struct {
+        int nx, ny, F, temporal;
+    } const tg{S.g.nx, S.g.ny, S.F, S.cfg.temporal};
+    auto reduced = [&](const float *img, const double *th, const double *tdir,
+                       const double *talpha, const int *skip, int q) -> int {
+        FwdOptions o;
+        o.bres = bvec;
+        o.rnorm2 = S.rv;   // per-view ||A(theta') img - b||^2
+        o.part_buf = S.part_fwd;
+        o.tdir = tdir;
+        o.talpha = talpha;
+        o.skip = skip;
+        RC(proj(S, b, 1, img, th, o, s));
+        RC(k_gram_psi(img, n, 1, S.w, tg.nx, tg.ny, tg.F, tg.temporal, S.part_gram,
+                      S.gram_blocks, reg, 1, s, 0));
+        return k_sens_objective(S.rv, V, reg, S.sc + S_LAM, S.alphas, q, S.cfg.c1, sc,
+                                S.accepted, s);
+    };
+    for (int it = 0; it < S.cfg.maxiter_p; ++it) {
+        // (offset_sensitivity leaves the weights of u in S.w)
+        RC(offset_sensitivity(S, b, theta, bvec, S.cfg.sens_iters, gh, nullptr, s, xw, rw));
+        RC(k_offset_dir(gh, S.cfg.mu_rel, V, S.dir, sc, s));
+        RC(reduced(S.u, theta, nullptr, nullptr, nullptr, -1));
+        for (int q = 0; q < S.cfg.armijo_trials; ++q) {
+            RC(k_lin_image(S.u, up, n, S.alphas, q, S.dir, S.accepted, ua, s));
+            RC(reduced(ua, theta, S.dir, S.alphas + q, S.accepted, q));
+        }
+        RC(k_gn_apply(theta, S.dir, V, sc, S.accepted, S.status, s));
+    }
+    return NLRMM_OK;
+}
+
 // The optional high-regularisation solve of Alg. "nl_rmmgks_two_solves" (Section 4.3), run
 // after Compress: one RMM-GKS cycle with lambda fixed at lam_hi from the compressed basis
 // V_kmin and u_{k+1}, then the parameter update on its image u_hat (VarPro: on its own
@@ -401,6 +460,12 @@ static int hi_solve_update(Solver &S, const nlrmm_batch &b, double *theta, const
         if (!rc && more) rc = expand(S, b, S.thk, bvec, s);
     }
     if (!rc && S.cfg.param_update == 1) rc = gn_update(S, b, theta, bvec, s);
+    if (!rc && S.cfg.param_update == 3) {
+        // on u_hat; the columns kmin.. of the basis hold this solve's basis, no longer needed
+        const int64_t m = m_of(S, b);
+        rc = sensitivity_update(S, b, theta, bvec, s, S.V + (int64_t)S.cfg.kmin * S.n,
+                                S.AV + (int64_t)S.cfg.kmin * m);
+    }
     if (!rc && S.cfg.param_update == 2) {
         // compressed basis of this solve into Vtmp; VarPro rebuilds A V_hat itself
         const int kmin = S.cfg.kmin;
@@ -450,6 +515,7 @@ static int solver_outer(Solver &S, const nlrmm_batch &b, double *theta, const fl
     } else {
         if (S.cfg.param_update == 1) RC(gn_update(S, b, theta, bvec, s));
         if (S.cfg.param_update == 2) RC(varpro_update(S, b, theta, bvec, s));
+        if (S.cfg.param_update == 3) RC(sensitivity_update(S, b, theta, bvec, s, nullptr, nullptr));
     }
     // weights from u_{k+1} (formed inside the residual); residual with the old operator H_k;
     // project out; append
@@ -541,14 +607,19 @@ static int grid_search(Solver &S, const nlrmm_batch &b, double *theta, const flo
 // of A V), so the solver state carried between outer iterations is untouched.
 static int offset_sensitivity(Solver &S, const nlrmm_batch &b, const double *theta,
                               const float *bvec, int iters, double *out, float *up_out,
-                              hipStream_t s)
+                              hipStream_t s, float *xw = nullptr, float *rw = nullptr)
 {
     const int64_t n = S.n, m = m_of(S, b);
-    const int base = S.ell;
-    if (S.kcap - base < 6) return NLRMM_ESHAPE;
-    float *x = S.V + (int64_t)base * n, *rc = x + n, *p = x + 2 * n, *q = x + 3 * n,
-          *t1 = x + 4 * n, *t2 = x + 5 * n;
-    float *r = S.AV + (int64_t)base * m, *du = r + m, *jr = r + 2 * m;
+    // work vectors: six image-sized and three sinogram-sized columns, by default the spare
+    // columns of the basis after the current ones
+    if (xw == nullptr || rw == nullptr) {
+        const int base = S.ell;
+        if (S.kcap - base < 6) return NLRMM_ESHAPE;
+        xw = S.V + (int64_t)base * n;
+        rw = S.AV + (int64_t)base * m;
+    }
+    float *x = xw, *rc = x + n, *p = x + 2 * n, *q = x + 3 * n, *t1 = x + 4 * n, *t2 = x + 5 * n;
+    float *r = rw, *du = r + m, *jr = r + 2 * m;
     double *c = S.cgs;
     double *one = c + 6, *d1 = c + 7, *d2 = c + 9;
     struct {
@@ -630,7 +701,11 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
     if (c.armijo_trials < 0 || c.armijo_trials > 32 || c.maxiter_p < 0) return NLRMM_EINVAL;
     if (!(c.eps > 0.0) || !(c.tau > 0.0)) return NLRMM_EINVAL;
     if (c.lam_hi > 0.0 && !(c.lam_hi < HUGE_VAL)) return NLRMM_EINVAL;
-    if (c.param_update < 0 || c.param_update > 2) return NLRMM_ENOTSUP;
+    if (c.param_update < 0 || c.param_update > 3) return NLRMM_ENOTSUP;
+    // the sensitivity update moves one global offset and needs six spare basis columns
+    if (c.param_update == 3 && (c.param_mode != 1 || c.kmax + 1 - c.kmin < 6))
+        return NLRMM_ENOTSUP;
+    if (c.sens_iters <= 0) c.sens_iters = 50;
     if (c.gram_precision < 0 || c.gram_precision > 2) return NLRMM_ENOTSUP;
     if (c.compress_precision != 0 && c.compress_precision != 2) return NLRMM_ENOTSUP;
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;

@@ -23,7 +23,7 @@ class Config:
     eps: float = 1e-3
     tau: float = 1.01
     lam_fix: float = -1.0        # < 0: discrepancy principle
-    param_update: int = 1        # 0 none, 1 Gauss-Newton (AltMin)
+    param_update: int = 1        # 0 none, 1 Gauss-Newton (AltMin), 2 VarPro, 3 sensitivity
     param_mode: int = 0          # 0 per-view, 1 global shift
     maxiter_p: int = 1
     mu_rel: float = 1e-6
@@ -36,6 +36,7 @@ class Config:
     gram_precision: int = 0      # 0 FP64, 1 FP32 MFMA, 2 BF16 MFMA
     compress_precision: int = 0  # compression basis products: 0 FP32 (FP64 accumulate), 2 BF16 MFMA
     lam_hi: float = 0.0          # > 0: high-regularisation solve feeding the parameter update
+    sens_iters: int = 50         # CG steps of the sensitivity solve (param_update 3)
 
     def struct(self) -> SolverCfg:
         return SolverCfg(**dataclasses.asdict(self))

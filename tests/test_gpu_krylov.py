@@ -1,6 +1,7 @@
 """GPU parity of the Krylov-side entry points and of the NL-RMM-GKS outer loop against the
 FP64 oracle.  Bars: primitives on identical FP64 inputs to ~1e-9; the loop after a fixed
 number of outer iterations: ||u_gpu - u_ora|| / ||u_ora|| <= 1e-3, max |theta diff| <= 1e-4 rad."""
+import dataclasses
 import math
 
 import numpy as np
@@ -177,8 +178,8 @@ def test_gks_expand_and_compress_match_oracle():
 
 
 def run_pair(key, N=None, outer=None, kmax=None, trace=False, gram_precision=0, lam_hi=None,
-             gn="altmin"):
-    wl = synth.WORKLOADS[key]
+             gn="altmin", wl=None, sens_iters=50, ret_state=False):
+    wl = wl or synth.WORKLOADS[key]
     inst = synth.draw(wl, N=N)
     N = inst.x_true.shape[-1]
     outer = outer or wl.outer
@@ -186,7 +187,8 @@ def run_pair(key, N=None, outer=None, kmax=None, trace=False, gram_precision=0, 
     geo = M.Geometry(N=N, nb=wl.nb, view_off=inst.view_off)
     x64 = inst.x_true.reshape(-1)
     b_ora, e_ora = M.make_data(geo, x64, inst.theta_true, inst.g, wl.noise)
-    cfg = M.Config(kmin=wl.kmin, kmax=kmax, eps=wl.eps, lam_hi=lam_hi, gn=gn)
+    cfg = M.Config(kmin=wl.kmin, kmax=kmax, eps=wl.eps, lam_hi=lam_hi, gn=gn,
+                   sens_iters=sens_iters)
     # GPU data: own projector, same noise direction
     g = ops.geom(N, wl.nb)
     x32 = inst.x_true.astype(np.float32)
@@ -198,7 +200,10 @@ def run_pair(key, N=None, outer=None, kmax=None, trace=False, gram_precision=0, 
     sol = Solver(g, 1, geo.V, Config(kmin=wl.kmin, kmax=kmax, eps=wl.eps,
                                      gram_precision=gram_precision,
                                      lam_hi=lam_hi if lam_hi is not None else 0.0,
-                                     param_update={"altmin": 1, "varpro": 2}[gn]))
+                                     param_update={"altmin": 1, "varpro": 2,
+                                                   "sensitivity": 3}[gn],
+                                     param_mode=1 if gn == "sensitivity" else 0,
+                                     sens_iters=sens_iters))
     sol.init(th, b_gpu)
     ora_log = []
     st = M.init_state(geo, inst.theta_nom, b_ora, cfg)
@@ -215,8 +220,11 @@ def run_pair(key, N=None, outer=None, kmax=None, trace=False, gram_precision=0, 
             out.append((k, du, dth, lam, st.lam, int(status.cpu()[0]), st.status))
             print(f"outer {k}: u rel diff {du:.3e}  theta max diff {dth:.3e}  lam gpu {lam:.6e} "
                   f"ora {st.lam:.6e} status {int(status.cpu()[0])}/{st.status}", flush=True)
+    th_gpu = th.cpu().numpy()
     sol.close()
     rre_ora = np.linalg.norm(st.u - x64) / np.linalg.norm(x64)
+    if ret_state:
+        return out, rre_ora, st, th_gpu, inst
     return out, rre_ora
 
 
@@ -242,6 +250,32 @@ def test_loop_parity_c1_high_regularisation(gn):
           f"oracle RRE {rre:.4f}")
     assert du <= 1e-3
     assert dth <= 1e-4
+
+
+@pytest.mark.parametrize("lam_hi", [None, 3e-3])
+def test_loop_parity_c1_sensitivity_update(lam_hi):
+    """Parameter update of one global offset by the full-space sensitivity equation (Section
+    4.2, eqs. "sensitivity" and "GN_system"; 50 conjugate-gradient steps for u_p, Armijo on
+    the compressed-basis reduced objective), alone and after the high-regularisation solve,
+    on the c1 workload with every true angle shifted by 0.5 degrees and no per-view
+    perturbation: 20 (8 with lam_hi) outer iterations against the oracle; the offset found
+    moves most of the way to the true one."""
+    wl = dataclasses.replace(synth.WORKLOADS["c1"], sigma_deg=0.0, offset_deg=0.5)
+    outer = 20 if lam_hi is None else 8
+    out, rre, st, th_gpu, inst = run_pair("c1", outer=outer, trace=True, gn="sensitivity",
+                                          wl=wl, lam_hi=lam_hi, ret_state=True)
+    k, du, dth, *_ = out[-1]
+    off_g = float(np.mean(th_gpu - inst.theta_nom))
+    off_o = float(np.mean(st.theta - inst.theta_nom))
+    print(f"c1 sensitivity update (lam_hi {lam_hi}): u rel diff {du:.3e}, theta max diff "
+          f"{dth:.3e} rad; offset gpu {math.degrees(off_g):.5f} oracle {math.degrees(off_o):.5f}"
+          f" true 0.5 deg; oracle RRE {rre:.4f}")
+    assert du <= 1e-3
+    assert dth <= 1e-4
+    # one offset for all views
+    assert np.ptp(th_gpu - inst.theta_nom) <= 1e-12
+    if lam_hi is None:
+        assert abs(math.degrees(off_o) - 0.5) < 0.25
 
 
 @pytest.mark.parametrize("ell,kmin", [(6, 2), (20, 5), (41, 5), (48, 16), (55, 16)])

@@ -274,31 +274,39 @@ def test_sensitivity_gradient_is_derivative_of_reduced_objective():
 
 
 def test_sensitivity_step_armijo_backtracking():
-    """The sensitivity step's line search: the accepted step is the first alpha0 beta^q meeting
-    the sufficient-decrease test of the reduced objective along the global offset dp, with the
-    directional derivative from central differences; a sign error in that test would change
-    it here.  All trials rejected: the angles stay."""
+    """The sensitivity step's line search, written out with the dense operator and the dense
+    solve of the sensitivity equation: the reduced objective with u(p) to first order,
+    phi(a) = 1/2||A(theta + a dp)(u + a dp u_p) - b||^2 + lam/2 ||sqrt(w) Psi (u + a dp u_p)||^2;
+    its slope at 0 (central differences) is g dp, and the accepted step is the first
+    alpha0 beta^q meeting the sufficient-decrease test (a sign error in that test would
+    change it here).  All trials rejected: the angles stay."""
     geo, th, b, w, lam, u = sens_setup()
-    V = np.eye(geo.n)
-    PV = M.psi_cols(geo, V)
-    Bw = np.sqrt(w)[:, None] * PV
+    n = geo.n
+    Psi = np.stack([M.psi(geo, np.eye(n)[:, i]) for i in range(n)], axis=1)
+    up_d, g_d, h_d, _ = M.offset_sensitivity(geo, th, u, b, w, lam)
     cfg = M.Config(maxiter_p=1, alpha0=16.0, beta=0.5, c1=0.3, armijo_trials=10, mu_rel=1e-6,
                    sens_iters=400)
-    th_new, status, info = M.gn_sensitivity(geo, th, u, V, b, w, PV, lam, cfg)
-    f = lambda p: M.varpro_parts(geo, th + p, V, b, Bw, lam)[4]   # noqa: E731
+    th_new, status, info = M.gn_sensitivity(geo, th, u, b, w, lam, cfg)
     dp = info["dp"]
+    assert abs(dp - (-g_d / (h_d * (1 + cfg.mu_rel)))) <= 1e-8 * abs(dp)
+
+    def phi(a):
+        A_a, _ = P.dense(geo.N, geo.nb, th + a * dp)
+        ua = u + a * dp * up_d
+        r = A_a @ ua - b
+        sv = Psi @ ua
+        return 0.5 * float(r @ r) + 0.5 * lam * float(np.sum(w * sv * sv))
+
     hstep = 1e-6
-    gd = (f(hstep * dp) - f(-hstep * dp)) / (2 * hstep)   # derivative along dp
-    assert gd < 0
-    f0 = f(0.0)
-    q = first_accepted(lambda a: f(a * dp), f0, gd, cfg.alpha0, cfg.beta, cfg.c1,
-                       cfg.armijo_trials)
+    gd = (phi(hstep) - phi(-hstep)) / (2 * hstep)
+    assert gd < 0 and abs(gd - g_d * dp) <= 1e-5 * abs(gd)
+    f0 = phi(0.0)
+    q = first_accepted(phi, f0, gd, cfg.alpha0, cfg.beta, cfg.c1, cfg.armijo_trials)
     assert q is not None and q >= 1, q
     assert info["alpha"] == cfg.alpha0 * cfg.beta ** q
-    assert first_accepted(lambda a: f(a * dp), f0, -gd, cfg.alpha0, cfg.beta, cfg.c1,
-                          cfg.armijo_trials) != q
+    assert first_accepted(phi, f0, -gd, cfg.alpha0, cfg.beta, cfg.c1, cfg.armijo_trials) != q
     assert np.array_equal(th_new, th + info["alpha"] * dp)
-    assert f(info["alpha"] * dp) < f0
+    assert phi(info["alpha"]) < f0
     cfg = dataclasses.replace(cfg, alpha0=1e4, armijo_trials=2)
-    th_rej, status, info = M.gn_sensitivity(geo, th, u, V, b, w, PV, lam, cfg)
+    th_rej, status, info = M.gn_sensitivity(geo, th, u, b, w, lam, cfg)
     assert status & M.ST_ARMIJO and np.array_equal(th_rej, th)
