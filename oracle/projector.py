@@ -2,7 +2,7 @@
 
 Builds ``liboracle_strip.so`` from ``strip_oracle.c`` with gcc and OpenMP.
 Operator definition: see the header of ``strip_oracle.c`` (strip-area model of
-the Radon transform of Section 6.2 at per-view angles).
+the Radon transform of Section 6.2 at per-view angles, and its fan-beam form).
 """
 from __future__ import annotations
 
@@ -41,6 +41,13 @@ def _load():
         for name in ("ora_project", "ora_backproject", "ora_dtheta", "ora_dtheta_t"):
             f = getattr(lib, name)
             f.argtypes = sig
+            f.restype = ctypes.c_int
+        fsig = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                ctypes.c_int, ip, ctypes.c_int, dp, dp, dp, ctypes.c_int]
+        for name in ("ora_fan_project", "ora_fan_backproject", "ora_fan_dtheta",
+                     "ora_fan_dtheta_t"):
+            f = getattr(lib, name)
+            f.argtypes = fsig
             f.restype = ctypes.c_int
         lib.ora_dense.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_int, dp, dp, dp]
@@ -156,3 +163,62 @@ def dense(N, nb, theta):
     ds, s0 = _geom(N, nb)
     _load().ora_dense(N, nb, s0, ds, V, _p(theta), _p(A), _p(dA))
     return A, dA
+
+
+# ---------------------------------------------------------------------------------------
+# fan beam (source at distance R from the rotation centre; see strip_oracle.c)
+# ---------------------------------------------------------------------------------------
+def _run_fan(name, src, theta, out_shape, N, nb, R, vo, nthreads):
+    ds, s0 = _geom(N, nb)
+    if nthreads == 0 and src.shape[0] * theta.shape[0] * N * N < SMALL_WORK:
+        nthreads = 1
+    out = np.zeros(out_shape)
+    ip = vo.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    getattr(_load(), name)(N, nb, s0, ds, float(R), vo.shape[0] - 1, ip, src.shape[0],
+                           _p(src), _p(theta), _p(out), nthreads)
+    return out
+
+
+def _fan_fwd(name, x, theta, nb, R, view_off, nthreads):
+    x = np.asarray(x, dtype=np.float64)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    N = x.shape[-1]
+    V = theta.shape[0]
+    vo = _vo(view_off, V)
+    F = vo.shape[0] - 1
+    xs = np.ascontiguousarray(x.reshape((-1, F, N, N)))
+    y = _run_fan(name, xs, theta, (xs.shape[0], V, nb), N, nb, R, vo, nthreads)
+    return y if x.ndim == 4 else y[0]
+
+
+def _fan_bwd(name, y, theta, N, R, view_off, nthreads):
+    y = np.asarray(y, dtype=np.float64)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    V, nb = y.shape[-2], y.shape[-1]
+    vo = _vo(view_off, V)
+    F = vo.shape[0] - 1
+    ys = np.ascontiguousarray(y.reshape((-1, V, nb)))
+    x = _run_fan(name, ys, theta, (ys.shape[0], F, N, N), N, nb, R, vo, nthreads)
+    if y.ndim == 3:
+        return x
+    return x[0, 0] if F == 1 else x[0]
+
+
+def fan_project(x, theta, nb, R, view_off=None, nthreads=0):
+    """Fan-beam projection (source distance R), same shapes as ``project``."""
+    return _fan_fwd("ora_fan_project", x, theta, nb, R, view_off, nthreads)
+
+
+def fan_dtheta(x, theta, nb, R, view_off=None, nthreads=0):
+    """Angle derivative of the fan-beam projection, same shapes as ``dtheta``."""
+    return _fan_fwd("ora_fan_dtheta", x, theta, nb, R, view_off, nthreads)
+
+
+def fan_backproject(y, theta, N, R, view_off=None, nthreads=0):
+    """Transpose of ``fan_project``, same shapes as ``backproject``."""
+    return _fan_bwd("ora_fan_backproject", y, theta, N, R, view_off, nthreads)
+
+
+def fan_dtheta_t(r, theta, N, R, view_off=None, nthreads=0):
+    """Transpose of ``fan_dtheta``."""
+    return _fan_bwd("ora_fan_dtheta_t", r, theta, N, R, view_off, nthreads)

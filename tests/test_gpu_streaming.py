@@ -25,8 +25,10 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def test_streaming_parity_scaled_c5():
-    """128x128, 180 views in 8 random blocks (23/22 views), kmax 20, two passes."""
+def streaming_pair(seeds=(11, 12)):
+    """The scaled streaming workload (128x128, 180 views in 8 random blocks of 23/22 views,
+    kmax 20, two passes) on the GPU and in the oracle: the oracle once from the exact GKB start
+    and, for each seed, from that start perturbed by a seeded relative 1e-9 (its own spread)."""
     wl = dataclasses.replace(synth.WORKLOADS["c5"], N=128, nb=181, n_views=180, blocks=8,
                              kmax=20)
     inst = synth.draw(wl)
@@ -41,11 +43,14 @@ def test_streaming_parity_scaled_c5():
     S = Streaming(g, inst.blocks, Config(kmin=5, kmax=wl.kmax, eps=wl.eps))
     S.load(inst.theta_nom, (bex + e).astype(np.float32), e)
     S.init()
-    # oracle: same block order, started on the saturated trajectory twice (two seeds) to
-    # measure the method's own spread on this workload
+    S.run(passes=2)
+    u = S.image().cpu().numpy()
+    th = S.angles()
+    S.solver.close()
+    exact = M.run_streaming(geo, b_ora, e_ora, inst.theta_nom, inst.blocks, cfg, passes=2)
     orig_init = M.init_state
-    oracle_runs = []
-    for seed in (11, 12):
+    perturbed = []
+    for seed in seeds:
         rng = np.random.default_rng(seed)
 
         def init_sat(geo_, th_, b_, cfg_, rng=rng):
@@ -56,14 +61,20 @@ def test_streaming_parity_scaled_c5():
 
         M.init_state = init_sat
         try:
-            oracle_runs.append(M.run_streaming(geo, b_ora, e_ora, inst.theta_nom, inst.blocks,
-                                               cfg, passes=2))
+            perturbed.append(M.run_streaming(geo, b_ora, e_ora, inst.theta_nom, inst.blocks,
+                                             cfg, passes=2))
         finally:
             M.init_state = orig_init
-    st, st2 = oracle_runs
-    S.run(passes=2)
-    u = S.image().cpu().numpy()
-    th = S.angles()
+    return inst, u, th, exact, perturbed
+
+
+def test_streaming_parity_scaled_c5():
+    """The library's streaming loop is as close to the exact-start oracle as perturbed starts
+    of the oracle itself are: streaming re-enters the sensitive phase at every block (each
+    22/23-view block's projected problem amplifies rounding of the start), so the bar is the
+    larger of the fixed tolerance and twice the oracle's own spread.  The fixed 1e-3 bar alone
+    is the skipped strict test below."""
+    inst, u, th, st, (st2, _) = streaming_pair(seeds=(11,))
     du, dth = rel(u, st.u), float(np.max(np.abs(th - st.theta)))
     su, sth = rel(st2.u, st.u), float(np.max(np.abs(st2.theta - st.theta)))
     x_true = inst.x_true.reshape(-1)
@@ -73,13 +84,22 @@ def test_streaming_parity_scaled_c5():
     print(f"streaming 2 passes x 8 blocks: GPU vs oracle u {du:.3e} theta {dth:.3e}; "
           f"oracle self-spread u {su:.3e} theta {sth:.3e}; RRE gpu {rre_g:.4f} ora {rre_o:.4f}; "
           f"angle err gpu {ae_g:.4e} ora {ae_o:.4e}")
-    S.solver.close()
-    # streaming re-enters the DP-clamped phase at every block: the bar is the larger of the
-    # fixed tolerance and twice the oracle's own spread under a 1e-9 start perturbation
     assert du <= max(1e-3, 2.0 * su)
     assert dth <= max(1e-4, 2.0 * sth)
     assert abs(rre_g - rre_o) <= 0.05 * rre_o
     assert abs(ae_g - ae_o) <= 0.05 * ae_o
+
+
+@pytest.mark.skip(reason="fails by design of the method, measured: after 2 passes the library "
+                         "differs from the exact-start FP64 oracle by 3.3e-3 in u, and the "
+                         "oracle itself, started 1e-9 away, differs by 3.1e-3 (2.7e-3 after 8 "
+                         "passes): the streamed trajectory does not re-converge, so no FP32 "
+                         "path meets 1e-3 here")
+def test_streaming_parity_scaled_c5_strict():
+    """The fixed bars (u 1e-3, theta 1e-4 rad) on the scaled streaming workload."""
+    inst, u, th, st, _ = streaming_pair(seeds=())
+    assert rel(u, st.u) <= 1e-3
+    assert float(np.max(np.abs(th - st.theta))) <= 1e-4
 
 
 def test_streaming_mixed_precision_policy_scaled_c5():
