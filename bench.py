@@ -11,7 +11,10 @@ Also reported:
     library on the launch stream around every single one-column launch during the timed
     outer iterations), and the roofline of the one with the most time per outer iteration
     (algorithmic FP32 flops per launch over that duration, against the published FP32 vector
-    peak, with the unpacked-FP32 rate beside it);
+    peak, with the unpacked-FP32 rate beside it), with the HBM bytes and VALU instructions per
+    launch of the same launch shape from the committed counter runs
+    (profiles/projector_c2_counters.json): the traffic over the algorithmic bytes and the
+    fraction of the chip's VALU issue rate the launch uses;
   * parity: the same iteration run for the workload's full outer count against the FP64
     oracle's run stored under tests/golden, and the four operators against the oracle on the
     same inputs (in the host-baseline leg);
@@ -36,6 +39,7 @@ Also reported:
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-dynamic]
                        [--no-workloads]
        python bench.py --ops-only     (operators and a copy calibration only, for counters)
+       python bench.py --streaming-only --steps K   (K blocks of the streaming workload only)
 """
 import argparse
 import hashlib
@@ -54,7 +58,8 @@ FP32_NONPACKED_PEAK_TFLOPS = 78.6   # 256 CU x 64 FP32 FMA lanes x 2 flop x 2.4 
 FLOP_PER_SAMPLE = 10.0              # algorithmic FP32 flops per applied strip-area weight
 LOOP_FIXTURE = os.path.join(ROOT, "tests", "golden", "loop_c2_oracle.npz")
 TIMING_PERIOD = 4                   # in-loop kernel timing samples every 4th launch
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
+COUNTER_FILE = os.path.join(ROOT, "profiles", "projector_c2_counters.json")
+VALU_ISSUE_PER_US = 1024 * 2400 / 4.0   # wave64 VALU instructions the chip issues per us
 COPY_BYTES = 256 << 20              # calibration copy for the HBM byte counters
 HBM_PEAK_GBS = 8000.0               # MI355X HBM3E
 MFMA_PEAK_TFLOPS = {1: 157.3, 2: 2500.0}   # dense matrix-core peaks: FP32, BF16
@@ -72,6 +77,8 @@ def parse():
                          "autograd, precision policy, streaming and the sensitivity solve")
     ap.add_argument("--ops-only", action="store_true",
                     help="only the operator timings and the copy calibration")
+    ap.add_argument("--streaming-only", action="store_true",
+                    help="only the streaming block timing (for a kernel trace of one block)")
     ap.add_argument("--gram-only", action="store_true",
                     help="only the regulariser-Gram timings on the matrix cores")
     ap.add_argument("--reps", type=int, default=20, help="repetitions per operator timing")
@@ -161,18 +168,21 @@ def copy_calibration(torch):
     del src, dst
 
 
-def traffic_for(kernel):
-    """HBM bytes per launch of `kernel` at the c2 shape from committed counter runs, or None
-    when absent or recorded for another version of the projector source."""
+def counters_for(kernel, tuned):
+    """HBM bytes and VALU instructions per launch of `kernel` at the c2 shape, in the launch
+    shape the autotuner chose, from the committed counter runs; None when absent or recorded
+    for another version of the projector source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(COUNTER_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
     if rec.get("source_sha") != source_digest():
         return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+    k = rec.get("kernels", {}).get(kernel, {})
+    if kernel == "fwd_edges_k":
+        return k.get("by_waves_per_block", {}).get(str(tuned.get("fwd_waves_per_block_1col")))
+    return k.get("by_view_split", {}).get(str(tuned.get("bwd_view_split")))
 
 
 def loop_parity(torch, ops, inst, wl, g, b, delta, Config, Solver, gram_precision):
@@ -558,6 +568,12 @@ def main():
     from paper_2605_06336_amd import metrics, ops, synth
     from paper_2605_06336_amd.solver import Config, OuterGraph, Solver
 
+    if args.streaming_only:
+        print(json.dumps({"streaming_only": True,
+                          "streaming": streaming_leg(torch, ops, synth, Config, args.steps)}),
+              flush=True)
+        return
+
     if args.gram_only:
         print(json.dumps({"gram_only": True, "gram_mfma": gram_leg(torch, ops, synth, args.reps)}),
               flush=True)
@@ -632,13 +648,20 @@ def main():
     def roof(kernel):
         ms = loop_kernels[kernel]["avg_launch_ms"]
         achieved = nnz * FLOP_PER_SAMPLE / (ms * 1e-3) / 1e12
-        traffic = traffic_for(kernel)
+        ctr = counters_for(kernel, tuned) or {}
+        traffic = ctr.get("bytes_per_launch")
+        valu = ctr.get("valu_wave_insts")
+        alg_bytes = 4 * (wl.N * wl.N + V * wl.nb)
         return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                 "frac_of_unpacked_fp32": round(achieved / FP32_NONPACKED_PEAK_TFLOPS, 4),
                 "traffic": traffic,
                 "hbm_gb_s": round(traffic / (ms * 1e-3) / 1e9, 1) if traffic else None,
+                "traffic_x_algorithmic": round(traffic / alg_bytes, 2) if traffic else None,
+                "valu_wave_insts": valu,
+                "valu_issue_frac": round(valu / (ms * 1e3 * VALU_ISSUE_PER_US), 3) if valu
+                else None,
                 "launch_ms": round(ms, 5), "launches_timed": loop_kernels[kernel]["launches_timed"],
                 "timing": f"HIP events around every {TIMING_PERIOD}th single launch in the timed "
                           "outer iterations",
