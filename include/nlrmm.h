@@ -223,6 +223,49 @@ int nlrmm_project_residual(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_b
                            double *rnorm2, void *stream);
 
 /* ------------------------------------------------------------------------------------
+ * Fan-beam family: the CT geometry of Section 6.2 (a point source at distance R from the
+ * rotation centre; the paper leaves the distances to its toolbox, this is the library's
+ * model).  View theta has n = (cos, sin), t = (-sin, cos), the source at S = -R t and the
+ * detector on the line through the rotation centre (the origin of the image coordinates)
+ * along n, bin j covering s in [s0 + j ds, s0 + (j+1) ds); the ray of detector coordinate s
+ * runs from S through s n.  Near each pixel centre c the rays are taken as parallel along
+ * the ray through c (direction t(alpha), alpha = theta - gamma, tan gamma = (c.n)/(R + c.t)),
+ * which meets the detector at s_c = R (c.n) / (R + c.t), and a shift w across the rays at c
+ * moves s by m w, m = R |c - S| / (R + c.t)^2.  The weight is the strip-area weight of the
+ * pixel for direction alpha, centred at s_c and scaled by m:
+ *   a[v][j][pix] = (m / ds) (Phi_alpha((e_{j+1} - s_c) / m) - Phi_alpha((e_j - s_c) / m)),
+ * Phi_alpha the pixel's cumulative footprint across direction alpha.  It is exact to first
+ * order in the pixel size and becomes the parallel-beam model above as R grows.
+ * Arguments, layouts and the frame batching are those of the parallel-beam family; R is a
+ * host scalar with R >= 1.5 x the largest distance of an image corner from the origin
+ * (NLRMM_EINVAL otherwise: the source stays well outside the image).  Any geometry accepted
+ * by nlrmm_check_geom(0, .) is accepted; ncols * nframes <= 65535.
+ * Projection and derivative: bin-driven gather; transposes: pixel-driven gather; no atomics,
+ * deterministic.  The derivative is the exact angle derivative of this model (the chord
+ * terms of Section 4's Jacobian H_p u for per-view angles).
+ * ------------------------------------------------------------------------------------ */
+
+/* y = A_fan(theta) x.  x [ncols][nframes][ny][nx] float32 -> y [ncols][nviews][nbins]. */
+int nlrmm_fan_project(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                      int32_t ncols, const float *x, const double *theta, double R, float *y,
+                      void *stream);
+
+/* x = A_fan(theta)^T y, the transpose of nlrmm_fan_project (up to FP32 rounding). */
+int nlrmm_fan_backproject(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                          int32_t ncols, const float *y, const double *theta, double R,
+                          float *x, void *stream);
+
+/* dy[v][j] = d (A_fan(theta) x)[v][j] / d theta_v. */
+int nlrmm_fan_project_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                             int32_t ncols, const float *x, const double *theta, double R,
+                             float *dy, void *stream);
+
+/* x = D_fan(theta)^T r, the transpose of nlrmm_fan_project_dtheta. */
+int nlrmm_fan_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom,
+                                 const nlrmm_batch *batch, int32_t ncols, const float *r,
+                                 const double *theta, double R, float *x, void *stream);
+
+/* ------------------------------------------------------------------------------------
  * Krylov side of MM-GKS / RMM-GKS (Section 3; supplementary Algs. "enlarge", "compress").
  * Basis blocks are column-contiguous FP32: V [ncols][n] with n = nframes*ny*nx, and
  * A V [ncols][m] with m = nviews*nbins.  Grams are FP64 row-major with leading dim ldg.

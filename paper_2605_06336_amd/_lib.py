@@ -67,6 +67,10 @@ SIGNATURES = {
     "nlrmm_project_dtheta": [_P, _GP, _BP, _I32, _P, _P, _P, _P, _P, _P, _P, _P],
     "nlrmm_backproject_acc": [_P, _GP, _BP, _I32, _P, _P, _P, _I32, _P],
     "nlrmm_backproject_noalloc": [_P, _GP, _BP, _I32, _P, _P, _P, _P],
+    "nlrmm_fan_project": [_P, _GP, _BP, _I32, _P, _P, ctypes.c_double, _P, _P],
+    "nlrmm_fan_backproject": [_P, _GP, _BP, _I32, _P, _P, ctypes.c_double, _P, _P],
+    "nlrmm_fan_project_dtheta": [_P, _GP, _BP, _I32, _P, _P, ctypes.c_double, _P, _P],
+    "nlrmm_fan_backproject_dtheta": [_P, _GP, _BP, _I32, _P, _P, ctypes.c_double, _P, _P],
     "nlrmm_project_residual": [_P, _GP, _BP, _P, _P, _P, _P, _P, _P],
     "nlrmm_tv_weights": [_P, _GP, _I32, _I32, _P, _D, _P, _P],
     "nlrmm_gram_psi": [_P, _GP, _I32, _I32, _I32, _P, _P, _P, _I32, _I32, _P],

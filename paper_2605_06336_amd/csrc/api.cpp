@@ -239,6 +239,49 @@ int nlrmm_backproject(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch 
     return launch_backproject(ctx, *geom, *batch, ncols, y, theta, x, (hipStream_t)stream);
 }
 
+static int fan_call(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                    int32_t ncols, const float *src, const double *theta, double R, float *dst,
+                    int deriv, int transpose, void *stream)
+{
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if (!ctx || !src || !theta || !dst) return NLRMM_EINVAL;
+    if (!isfinite(R) || !(R >= fan_min_distance(*geom))) return NLRMM_EINVAL;
+    if (ncols < 1 || (int64_t)ncols * (batch ? batch->nframes : 1) > 65535) return NLRMM_ESHAPE;
+    if ((rc = check_batch(batch))) return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    return launch_fan(*geom, *batch, ncols, R, deriv, transpose, theta, src, dst,
+                      (hipStream_t)stream);
+}
+
+int nlrmm_fan_project(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                      int32_t ncols, const float *x, const double *theta, double R, float *y,
+                      void *stream)
+{
+    return fan_call(ctx, geom, batch, ncols, x, theta, R, y, 0, 0, stream);
+}
+
+int nlrmm_fan_backproject(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                          int32_t ncols, const float *y, const double *theta, double R,
+                          float *x, void *stream)
+{
+    return fan_call(ctx, geom, batch, ncols, y, theta, R, x, 0, 1, stream);
+}
+
+int nlrmm_fan_project_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
+                             int32_t ncols, const float *x, const double *theta, double R,
+                             float *dy, void *stream)
+{
+    return fan_call(ctx, geom, batch, ncols, x, theta, R, dy, 1, 0, stream);
+}
+
+int nlrmm_fan_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom,
+                                 const nlrmm_batch *batch, int32_t ncols, const float *r,
+                                 const double *theta, double R, float *x, void *stream)
+{
+    return fan_call(ctx, geom, batch, ncols, r, theta, R, x, 1, 1, stream);
+}
+
 int nlrmm_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
                              int32_t ncols, const float *r, const double *theta, float *x,
                              void *stream)

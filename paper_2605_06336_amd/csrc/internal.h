@@ -148,6 +148,12 @@ int launch_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_b
                               int ncols, const float *y, const double *theta, float *x,
                               hipStream_t s);
 
+// Fan-beam family (fan.hip): the smallest accepted source distance for a geometry, and the
+// launcher of the four operators (deriv: angle derivative; transpose: the transposes).
+double fan_min_distance(const nlrmm_geom &g);
+int launch_fan(const nlrmm_geom &g, const nlrmm_batch &b, int ncols, double R, int deriv,
+               int transpose, const double *theta, const float *src, float *dst, hipStream_t s);
+
 }  // namespace nlrmm
 
 #define NLRMM_HIP_CHECK(expr)                       \

@@ -138,6 +138,66 @@ def backproject(y: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None,
     return out
 
 
+def _fan_forward(name, x, theta, g, R, frames, out):
+    _need(x, torch.float32, "x")
+    _need(theta, torch.float64, "theta")
+    V = theta.numel()
+    b = _batch(frames, V)
+    npix = b.nframes * g.nx * g.ny
+    if x.numel() % npix:
+        raise ValueError("x size is not a multiple of frames*ny*nx")
+    ncols = x.numel() // npix
+    if out is None:
+        out = torch.empty((ncols, V, g.nbins), dtype=torch.float32, device=x.device)
+    _need(out, torch.float32, "out")
+    check(getattr(_lib.lib(), name)(context(x.device.index or 0), ctypes.byref(g),
+                                    ctypes.byref(b), ncols, x.data_ptr(), theta.data_ptr(),
+                                    float(R), out.data_ptr(), _stream(x.device)), name)
+    return out
+
+
+def _fan_transpose(name, y, theta, g, R, frames, out):
+    _need(y, torch.float32, "y")
+    _need(theta, torch.float64, "theta")
+    V = theta.numel()
+    b = _batch(frames, V)
+    if y.numel() % (V * g.nbins):
+        raise ValueError("y size is not a multiple of V*nb")
+    ncols = y.numel() // (V * g.nbins)
+    if out is None:
+        out = torch.empty((ncols, b.nframes, g.ny, g.nx), dtype=torch.float32, device=y.device)
+    _need(out, torch.float32, "out")
+    check(getattr(_lib.lib(), name)(context(y.device.index or 0), ctypes.byref(g),
+                                    ctypes.byref(b), ncols, y.data_ptr(), theta.data_ptr(),
+                                    float(R), out.data_ptr(), _stream(y.device)), name)
+    return out
+
+
+def fan_project(x: torch.Tensor, theta: torch.Tensor, g: Geom, R: float, frames=None,
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Fan-beam y = A_fan(theta) x, source at distance R (nlrmm_fan_project).  Shapes as
+    ``project``."""
+    return _fan_forward("nlrmm_fan_project", x, theta, g, R, frames, out)
+
+
+def fan_backproject(y: torch.Tensor, theta: torch.Tensor, g: Geom, R: float, frames=None,
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Fan-beam x = A_fan(theta)^T y (nlrmm_fan_backproject).  Shapes as ``backproject``."""
+    return _fan_transpose("nlrmm_fan_backproject", y, theta, g, R, frames, out)
+
+
+def fan_project_dtheta(x: torch.Tensor, theta: torch.Tensor, g: Geom, R: float, frames=None,
+                       out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Per-view angle derivative of the fan-beam projection (nlrmm_fan_project_dtheta)."""
+    return _fan_forward("nlrmm_fan_project_dtheta", x, theta, g, R, frames, out)
+
+
+def fan_backproject_dtheta(r: torch.Tensor, theta: torch.Tensor, g: Geom, R: float,
+                           frames=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Transpose of ``fan_project_dtheta`` (nlrmm_fan_backproject_dtheta)."""
+    return _fan_transpose("nlrmm_fan_backproject_dtheta", r, theta, g, R, frames, out)
+
+
 def backproject_noalloc(y: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None,
                         out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """x = A(theta)^T y without any device allocation by the library

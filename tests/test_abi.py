@@ -53,6 +53,13 @@ def test_host_validation_without_device():
                                         None) == -1
     assert lib.nlrmm_solver_offset_sensitivity(None, ctypes.byref(b), 1, 1, 10, 1, None,
                                                None) == -1
+    for name in ("nlrmm_fan_project", "nlrmm_fan_backproject", "nlrmm_fan_project_dtheta",
+                 "nlrmm_fan_backproject_dtheta"):
+        fn = getattr(lib, name)
+        assert fn(None, ctypes.byref(g), ctypes.byref(b), 1, 1, 1, 4.0, 1, None) == -1
+        # the geometry is checked first, then pointers, the source distance and the batch
+        g0 = _lib.Geom(nx=0, ny=8, x0=-1, y0=-1, d=0.25, nbins=13, s0=-1.42, ds=0.2)
+        assert fn(None, ctypes.byref(g0), ctypes.byref(b), 1, 1, 1, 4.0, 1, None) == -2
     assert lib.nlrmm_strerror(-2) == b"inconsistent or unsupported sizes"
     assert lib.nlrmm_version() >= 100
 
