@@ -33,6 +33,8 @@ Also reported:
   * outer it/s of the 256x256 iteration under each precision policy (FP64 Grams, FP32
     matrix-core Grams, BF16 matrix-core Grams and compression products);
   * ms per block of streaming NL-RMM-GKS at 2048x2048 / 1440 views in 64 blocks;
+  * ms per call of the four fan-beam operators at the 256x256 / 360-view shape (source at
+    four image half-widths);
   * the FP64 oracle timed on a bounded sample on the host: the median of three outer
     iterations and one application of each operator.
 
@@ -283,6 +285,44 @@ def workload_operators(torch, ops, metrics, synth, reps):
         del x, y, xo, yo
     torch.cuda.synchronize()
     return out
+
+
+def fan_leg(torch, ops, synth, reps):
+    """ms per call of the four fan-beam operators at the 256x256 / 360-view / 363-bin shape
+    with the source at R = 4 (one kernel per call), pixel-views per second, and the parallel
+    projector's calls at the same shape beside them."""
+    wl = synth.WORKLOADS["c2"]
+    inst = synth.draw(wl)
+    g = ops.geom(wl.N, wl.nb)
+    dev = torch.device("cuda", 0)
+    x = torch.as_tensor(inst.x_true[0].astype(np.float32), device=dev).contiguous()
+    th = torch.as_tensor(inst.theta_true, device=dev)
+    R = 4.0
+    y = ops.fan_project(x, th, g, R)
+    xb = torch.empty((1, 1, wl.N, wl.N), dtype=torch.float32, device=dev)
+    yb = torch.empty_like(y)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        for _ in range(reps):
+            fn()
+        a1.record(stream)
+        torch.cuda.synchronize()
+        return a0.elapsed_time(a1) / reps
+
+    ms = {"project": timed(lambda: ops.fan_project(x, th, g, R, out=yb)),
+          "backproject": timed(lambda: ops.fan_backproject(y, th, g, R, out=xb)),
+          "dtheta": timed(lambda: ops.fan_project_dtheta(x, th, g, R, out=yb)),
+          "dtheta_transpose": timed(lambda: ops.fan_backproject_dtheta(y, th, g, R, out=xb))}
+    pv = wl.N * wl.N * wl.n_views
+    return {"workload": "256x256 image, 360 views, 363 bins, source at R = 4 image half-widths",
+            "ms_per_call": {k: round(v, 4) for k, v in ms.items()},
+            "gpixelviews_per_s": {k: round(pv / (v * 1e-3) / 1e9, 2) for k, v in ms.items()}}
 
 
 def varpro_leg(torch, ops, synth, Config, Solver, steps, warmup, gram_precision):
@@ -678,9 +718,10 @@ def main():
         dyn = dynamic_leg(torch, ops, synth, Config, OuterGraph, Solver, max(3, args.steps // 2),
                           2, args.gram_precision)
 
-    per_workload = varpro = autograd_r = precision = streaming = gram = None
+    per_workload = varpro = autograd_r = precision = streaming = gram = fan = None
     if not args.no_workloads:
         gram = gram_leg(torch, ops, synth, max(3, args.reps // 2))
+        fan = fan_leg(torch, ops, synth, max(3, args.reps // 2))
         per_workload = workload_operators(torch, ops, metrics, synth, max(3, args.reps // 4))
         varpro = varpro_leg(torch, ops, synth, Config, Solver, max(3, args.steps // 2), 2,
                             args.gram_precision)
@@ -730,6 +771,7 @@ def main():
         "precision_policy_c2": precision,
         "streaming_c5": streaming,
         "gram_mfma": gram,
+        "fan_beam_c2": fan,
         "roofline": roofline,
         "roofline_" + other: roofline_other,
         "loop_kernels": loop_kernels,

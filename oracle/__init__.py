@@ -11,4 +11,6 @@ Contents
   method.py       FP64 NumPy implementation of the method: regulariser, MM-GKS
                   enlarge/compress, discrepancy principle, Gauss-Newton (AltMin),
                   variable projection, streaming and dynamic drivers.
+  optical_flow.py FP64 optical-flow regulariser: velocity estimation per frame pair,
+                  bilinear warps, the motion rows of the dynamic operator Theta.
 """

@@ -22,6 +22,10 @@ Each function follows the paper's algorithm in the paper's order:
                                high-regularisation solve of Section 4.3 (lam_hi)
   * s-NL-RMM-GKS ............. Alg. "s_nl_rmmgks_final"
   * dynamic ANISO-TV ......... Section 7 (operator D1, block-diagonal H)
+  * dynamic optical flow ..... Section 7 (SOLVE-OF, eq. "of_forward"; Theta = [Psi; M_hat],
+                               eq. "Theta_OF"; velocities from the current image at the start
+                               of every outer iteration, Alg. "dyn_nl_rmmgks"), in
+                               ``optical_flow.py``
 
 Readings where the paper is silent (all listed in the design notes):
   eps = 1e-3; Psi = unscaled forward differences, (N-1) per line; DP target
@@ -44,6 +48,7 @@ from typing import List, Optional
 import numpy as np
 from scipy.linalg import solve_triangular, cho_factor, cho_solve
 
+from . import optical_flow as OF
 from . import projector as P
 
 # status bits (same meaning as the HIP library's device status word)
@@ -65,6 +70,7 @@ class Geometry:
     nb: int
     view_off: np.ndarray           # int64 [F + 1]
     temporal: bool = False         # dynamic: add the temporal difference L_t
+    flow: Optional[OF.Flow] = None  # dynamic OF: motion rows in place of L_t
 
     @property
     def F(self) -> int:
@@ -116,13 +122,17 @@ def A_cols(geo: Geometry, theta, X):
 
 def psi(geo: Geometry, u):
     """Regulariser Psi u (Section 2.2): per frame [D_x u; D_y u] (forward differences,
-    unscaled, N-1 per line), then for dynamic problems L_t u (frame differences)."""
+    unscaled, N-1 per line), then for dynamic problems L_t u (frame differences, ANISO-TV
+    operator D1 of Section 7) or, with a velocity field, the motion rows M_hat u of the
+    optical-flow operator Theta (eq. "Theta_OF")."""
     U = np.asarray(u).reshape(geo.F, geo.N, geo.N)
     parts = []
     for f in range(geo.F):
         parts.append((U[f, :, 1:] - U[f, :, :-1]).ravel())
         parts.append((U[f, 1:, :] - U[f, :-1, :]).ravel())
-    if geo.temporal and geo.F > 1:
+    if geo.flow is not None and geo.F > 1:
+        parts.append(OF.motion_rows(U, geo.flow))
+    elif geo.temporal and geo.F > 1:
         parts.append((U[1:] - U[:-1]).ravel())
     return np.concatenate(parts)
 
@@ -142,7 +152,9 @@ def psiT(geo: Geometry, s):
         U[f, :, :-1] -= dx
         U[f, 1:, :] += dy
         U[f, :-1, :] -= dy
-    if geo.temporal and F > 1:
+    if geo.flow is not None and F > 1:
+        U += OF.motion_rows_t(s[pos:], F, N, N, geo.flow)
+    elif geo.temporal and F > 1:
         dt = s[pos:].reshape(F - 1, N, N)
         U[1:] += dt
         U[:-1] -= dt
@@ -155,7 +167,9 @@ def psi_cols(geo: Geometry, X):
 
 def npsi(geo: Geometry) -> int:
     n = geo.F * 2 * geo.N * (geo.N - 1)
-    if geo.temporal and geo.F > 1:
+    if geo.flow is not None and geo.F > 1:
+        n += 2 * (geo.F - 1) * geo.N * geo.N
+    elif geo.temporal and geo.F > 1:
         n += (geo.F - 1) * geo.N * geo.N
     return n
 
@@ -196,6 +210,12 @@ class Config:
     alpha0: float = 1.0
     armijo_trials: int = 10
     breakdown_tol: float = 1e-10
+    # optical-flow temporal regulariser (dynamic problems): velocity estimated from the
+    # current image every of_every outer iterations (tau of Alg. "dyn_nl_rmmgks")
+    of: bool = False
+    of_gamma: float = 0.05
+    of_ridge: float = 1e-3
+    of_every: int = 1
 
     @property
     def S(self) -> int:
@@ -598,6 +618,12 @@ def outer_step(geo: Geometry, st: State, b, delta, cfg: Config):
     solve (cfg.lam_hi), UPDATE-PARAM on u_{k+1} (or on u_hat when lam_hi is set), weights
     from u_{k+1}, residual with the old operator H_k and lambda_k, append."""
     theta_k = st.theta.copy()
+    if cfg.of and geo.F > 1 and len(st.log) % cfg.of_every == 0:
+        # OF branch of Alg. "dyn_nl_rmmgks": velocities of every frame pair from u^(k)
+        # (SOLVE-OF, eq. "of_forward"), reverse flow, Theta^(k) = [Psi; M_hat]
+        geo.flow = OF.estimate_flow(st.u.reshape(geo.F, geo.N, geo.N), cfg.of_gamma,
+                                    cfg.of_ridge)
+        st.PV = psi_cols(geo, st.V)
     st.AV = A_cols(geo, theta_k, st.V)
     target = cfg.tau * delta
     S = cfg.S
