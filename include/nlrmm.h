@@ -270,8 +270,11 @@ int nlrmm_fan_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom,
  * Basis blocks are column-contiguous FP32: V [ncols][n] with n = nframes*ny*nx, and
  * A V [ncols][m] with m = nviews*nbins.  Grams are FP64 row-major with leading dim ldg.
  * Psi is the anisotropic TV operator of Section 2.2: per frame the forward differences
- * along x (ny rows of nx-1) then along y (ny-1 rows of nx), unscaled; with temporal != 0
- * and nframes > 1 the frame differences ((nframes-1) blocks of ny*nx) follow.
+ * along x (ny rows of nx-1) then along y (ny-1 rows of nx), unscaled; with temporal == 1
+ * and nframes > 1 the frame differences ((nframes-1) blocks of ny*nx) follow.  The entry
+ * points below that take no velocity field accept temporal 0 or 1 (temporal 2, the
+ * optical-flow rows, goes through the nlrmm_theta_* family: NLRMM_EINVAL or NLRMM_ENOTSUP
+ * here).
  * ------------------------------------------------------------------------------------ */
 
 /* MM weights w = ((Psi u)^2 + eps^2)^(-1/2) (Section 3.1, the squared diagonal of P_eps).
@@ -287,6 +290,54 @@ int nlrmm_tv_weights(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, in
 int nlrmm_gram_psi(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, int32_t temporal,
                    int32_t ell, const float *V, const float *w, double *G, int32_t ldg,
                    int32_t precision, void *stream);
+
+/* ------------------------------------------------------------------------------------
+ * Dynamic regulariser Theta with optical-flow motion rows (Section 7, "Optical Flow
+ * Regularization", eqs. "of_forward" and "Theta_OF").  temporal: 0 none, 1 frame differences
+ * u(t+1) - u(t) (ANISO-TV), 2 motion rows: for every frame pair t (t = 0 .. nframes-2) the
+ * forward consistency u(t) - M(s(t)) u(t+1), then for every pair the reverse consistency
+ * u(t+1) - M(-s(t)) u(t), M(s) the bilinear warp that samples a frame at (k + s_x, l + s_y)
+ * (pixel units, the position clamped to [0, nx-1] x [0, ny-1]).  Theta u = [Psi u; rows]
+ * with the spatial rows of Psi as described above (so its length is nframes * (ny (nx-1) +
+ * (ny-1) nx) plus (nframes-1) nx ny for temporal 1, 2 (nframes-1) nx ny for temporal 2).
+ *   flow  DEVICE [nframes-1][2][ny][nx] float32: s_x then s_y of every pair (temporal 2 with
+ *         nframes > 1 needs it and nx, ny >= 2; otherwise it may be NULL).
+ * ------------------------------------------------------------------------------------ */
+
+/* Velocity estimation (SOLVE-OF, eq. "of_forward") of every frame pair of u
+ * [nframes][ny][nx]: s(t) minimises ||Y s + u_t||^2 + gamma ||L s||^2 + ridge ||s||^2, with
+ * Y = [diag(d_x u(t)), diag(d_y u(t))] (central differences in pixel units, one-sided at the
+ * borders), u_t = u(t+1) - u(t) and L the forward differences of each component (none across
+ * the border); the l2/l2 form of the paper's lp/lq problem, gamma fixed (the paper selects it
+ * by GCV) and a ridge for flat regions.  iters conjugate-gradient steps on the normal
+ * equations from s = 0 for all pairs at once (FP32 vectors, FP64 inner products);
+ * deterministic.  Uses the context's scratch workspace (grown as needed, refused under
+ * capture).  flow [nframes-1][2][ny][nx] overwritten; nframes == 1: nothing to do. */
+int nlrmm_of_estimate(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, const float *u,
+                      double gamma, double ridge, int32_t iters, float *flow, void *stream);
+
+/* out = Theta u (all rows, layout above). */
+int nlrmm_theta_apply(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, int32_t temporal,
+                      const float *flow, const float *u, float *out, void *stream);
+
+/* MM weights w = ((Theta u)^2 + eps^2)^(-1/2) (Section 3.1), one per row of Theta u. */
+int nlrmm_theta_weights(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
+                        int32_t temporal, const float *flow, const float *u, double eps,
+                        float *w, void *stream);
+
+/* r += lambda Theta^T (w * Theta u), the regulariser part of the normal-equation residual
+ * (w NULL: the weights of u formed with eps).  lambda DEVICE double scalar.  The motion rows'
+ * transpose scatters into 64-bit fixed-point accumulators (2^-36 units) in the context's
+ * scratch workspace: the result does not depend on the order of the atomic adds. */
+int nlrmm_theta_grad_add(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
+                         int32_t temporal, const float *flow, const float *u, const float *w,
+                         double eps, const double *lambda, float *r, void *stream);
+
+/* Weighted regulariser Gram (Theta V)^T diag(w) (Theta V) for the first ell columns of V, as
+ * nlrmm_gram_psi (same precisions) with the temporal rows of `temporal` and `flow`. */
+int nlrmm_gram_theta(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, int32_t temporal,
+                     const float *flow, int32_t ell, const float *V, const float *w, double *G,
+                     int32_t ldg, int32_t precision, void *stream);
 
 /* Projected MM-GKS solve (eq. "reduced_problem") from its Grams:
  *   GA = (AV)^T AV, GP = (P Psi V)^T P Psi V, rb = (AV)^T b   (FP64, ell <= 56),
@@ -350,7 +401,8 @@ typedef struct {
     double c1, beta, alpha0; /* Armijo constant, backtracking factor, first step */
     int32_t armijo_trials;   /* <= 32 */
     double breakdown_tol;    /* Krylov breakdown threshold */
-    int32_t temporal;        /* dynamic problems: regulariser includes frame differences */
+    int32_t temporal;        /* dynamic problems: 0 none, 1 frame differences (ANISO-TV, operator
+                                D1 of Section 7), 2 optical-flow motion rows (see of_* below) */
     int32_t gram_precision;  /* regulariser Gram: 0 FP64, 1 FP32 MFMA, 2 BF16 MFMA (nlrmm_gram_psi) */
     int32_t compress_precision; /* compression basis products: 0 FP32/FP64-accumulate, 2 BF16 MFMA */
     double lam_hi;           /* > 0: the optional high-regularisation solve of Section 4.3 (Alg.
@@ -362,6 +414,16 @@ typedef struct {
                                 next outer iteration stay those of the primary solve.  <= 0: off */
     int32_t sens_iters;      /* conjugate-gradient steps of the sensitivity solve (param_update 3);
                                 <= 0: 50 */
+    /* optical-flow temporal regulariser (temporal = 2, dynamic problems; Section 7, the OF
+       branch of Alg. "dyn_nl_rmmgks"): at the start of every of_every-th outer iteration the
+       velocities of all frame pairs are estimated from the current image by of_iters
+       conjugate-gradient steps on eq. "of_forward" (l2/l2 form, of_gamma, of_ridge; see
+       nlrmm_of_estimate), and Theta = [Psi; M_hat] (eq. "Theta_OF") is used until the next
+       estimate.  Not combined with param_update 3 (NLRMM_ENOTSUP).  Defaults when <= 0:
+       of_iters 200, of_gamma 0.05, of_ridge 1e-3, of_every 1. */
+    int32_t of_iters;
+    double of_gamma, of_ridge;
+    int32_t of_every;
 } nlrmm_solver_cfg;
 
 typedef struct nlrmm_solver nlrmm_solver;

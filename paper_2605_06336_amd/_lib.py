@@ -46,7 +46,9 @@ class SolverCfg(ctypes.Structure):
                 ("armijo_trials", ctypes.c_int32), ("breakdown_tol", ctypes.c_double),
                 ("temporal", ctypes.c_int32), ("gram_precision", ctypes.c_int32),
                 ("compress_precision", ctypes.c_int32), ("lam_hi", ctypes.c_double),
-                ("sens_iters", ctypes.c_int32)]
+                ("sens_iters", ctypes.c_int32), ("of_iters", ctypes.c_int32),
+                ("of_gamma", ctypes.c_double), ("of_ridge", ctypes.c_double),
+                ("of_every", ctypes.c_int32)]
 
 # name -> argtypes (all return int except where noted)
 SIGNATURES = {
@@ -67,6 +69,11 @@ SIGNATURES = {
     "nlrmm_project_dtheta": [_P, _GP, _BP, _I32, _P, _P, _P, _P, _P, _P, _P, _P],
     "nlrmm_backproject_acc": [_P, _GP, _BP, _I32, _P, _P, _P, _I32, _P],
     "nlrmm_backproject_noalloc": [_P, _GP, _BP, _I32, _P, _P, _P, _P],
+    "nlrmm_of_estimate": [_P, _GP, _I32, _P, ctypes.c_double, ctypes.c_double, _I32, _P, _P],
+    "nlrmm_theta_apply": [_P, _GP, _I32, _I32, _P, _P, _P, _P],
+    "nlrmm_theta_weights": [_P, _GP, _I32, _I32, _P, _P, ctypes.c_double, _P, _P],
+    "nlrmm_theta_grad_add": [_P, _GP, _I32, _I32, _P, _P, _P, ctypes.c_double, _P, _P, _P],
+    "nlrmm_gram_theta": [_P, _GP, _I32, _I32, _P, _I32, _P, _P, _P, _I32, _I32, _P],
     "nlrmm_fan_project": [_P, _GP, _BP, _I32, _P, _P, ctypes.c_double, _P, _P],
     "nlrmm_fan_backproject": [_P, _GP, _BP, _I32, _P, _P, ctypes.c_double, _P, _P],
     "nlrmm_fan_project_dtheta": [_P, _GP, _BP, _I32, _P, _P, ctypes.c_double, _P, _P],

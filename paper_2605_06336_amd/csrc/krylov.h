@@ -4,9 +4,12 @@
 
 namespace nlrmm {
 
+// temporal: TEMPORAL_NONE / _DIFF / _OF (tv.h); flow: the velocities of the motion rows
+// ([F-1][2][ny][nx]), required with TEMPORAL_OF
 int k_psi_weights(const float *u, int nx, int ny, int F, int temporal, float eps, float *w,
-                  hipStream_t s);
-int k_psi_apply(const float *u, int nx, int ny, int F, int temporal, float *out, hipStream_t s);
+                  hipStream_t s, const float *flow = nullptr);
+int k_psi_apply(const float *u, int nx, int ny, int F, int temporal, float *out, hipStream_t s,
+                const float *flow = nullptr);
 // w == nullptr: the weights are formed from u with eps (equal to k_psi_weights' values)
 int k_tv_grad_add(const float *u, const float *w, int nx, int ny, int F, int temporal,
                   const double *lamp, float *r, hipStream_t s, float eps = 0.0f);
@@ -14,7 +17,19 @@ int k_tv_grad_add(const float *u, const float *w, int nx, int ny, int F, int tem
 // w == nullptr (modes 1, 2): the weights are formed from u with eps inside the kernel
 int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int ny, int F,
                int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s,
-               int mode = 0, const float *u = nullptr, float eps = 0.0f);
+               int mode = 0, const float *u = nullptr, float eps = 0.0f,
+               const float *flow = nullptr);
+// Optical flow (of.hip).  Velocities of every frame pair of u [F][ny][nx] (SOLVE-OF, eq.
+// "of_forward", l2/l2 with a ridge) by `iters` conjugate-gradient steps from zero, into
+// flow [F-1][2][ny][nx]; work: of_work_floats(nx, ny, F) floats, part: of_part_doubles(...).
+size_t of_work_floats(int nx, int ny, int F);
+size_t of_part_doubles(int nx, int ny, int F);
+int k_of_estimate(const float *u, int nx, int ny, int F, float gamma, float ridge, int iters,
+                  float *flow, float *work, double *part, hipStream_t s);
+// r += lam * M_hat^T (w * M_hat u): the motion rows' part of the regulariser gradient (w ==
+// nullptr: weights formed from u with eps); acc: F * nx * ny int64 accumulators.
+int k_of_grad_add(const float *u, const float *w, const float *flow, int nx, int ny, int F,
+                  const double *lamp, float *r, long long *acc, hipStream_t s, float eps);
 // part: per-block partials, md_part_doubles(nblk) doubles.
 int k_multidot(const float *X, int64_t ldx, int nv, const float *y, const float *z, int64_t n,
                double *part, int nblk, double *out, int ostride, hipStream_t s,

@@ -50,9 +50,9 @@ __device__ double block_sum(double v, double *sbuf)
 // ---------------------------------------------------------------------------
 // w = ((Psi u)^2 + eps^2)^(-1/2), one thread per pixel writing its forward differences.
 __global__ void psi_weights_k(const float *__restrict__ u, int nx, int ny, int F, int temporal,
-                              float eps, float *__restrict__ w)
+                              float eps, float *__restrict__ w, const float *__restrict__ flow)
 {
-    const TVGeo g = tvgeo(nx, ny, F, temporal);
+    const TVGeo g = tvgeo(nx, ny, F, temporal, flow);
     const int64_t npix = (int64_t)nx * ny;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npix * F) return;
@@ -63,7 +63,16 @@ __global__ void psi_weights_k(const float *__restrict__ u, int nx, int ny, int F
     if (k < nx - 1) w[f * g.per_frame + (int64_t)l * (nx - 1) + k] = tv_weight(u[i + 1] - uc, e2);
     if (l < ny - 1)
         w[f * g.per_frame + g.dy_off + (int64_t)l * nx + k] = tv_weight(u[i + nx] - uc, e2);
-    if (g.temporal && f < F - 1) w[g.t_off + f * npix + p] = tv_weight(u[i + npix] - uc, e2);
+    if (g.temporal == TEMPORAL_DIFF && f < F - 1)
+        w[g.t_off + f * npix + p] = tv_weight(u[i + npix] - uc, e2);
+    if (g.temporal == TEMPORAL_OF && f < F - 1) {
+        const float *sx = flow + 2 * f * npix, *sy = sx + npix;
+        const OfCell cf = of_cell(sx[p], sy[p], k, l, nx, ny);
+        const OfCell cr = of_cell(-sx[p], -sy[p], k, l, nx, ny);
+        w[g.t_off + f * npix + p] = tv_weight(uc - of_sample(u + (f + 1) * npix, cf, nx), e2);
+        w[g.t_off + (F - 1 + f) * npix + p] =
+            tv_weight(u[i + npix] - of_sample(u + f * npix, cr, nx), e2);
+    }
 }
 
 // r += lam * Psi^T (w * Psi u)  (the regulariser part of the normal-equation residual).
@@ -80,9 +89,9 @@ __global__ void tv_grad_add_k(const float *__restrict__ u, const float *__restri
 
 // Psi u written out (used by tests and by the VarPro regulariser block).
 __global__ void psi_apply_k(const float *__restrict__ u, int nx, int ny, int F, int temporal,
-                            float *__restrict__ s)
+                            float *__restrict__ s, const float *__restrict__ flow)
 {
-    const TVGeo g = tvgeo(nx, ny, F, temporal);
+    const TVGeo g = tvgeo(nx, ny, F, temporal, flow);
     const int64_t npix = (int64_t)nx * ny;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npix * F) return;
@@ -91,7 +100,14 @@ __global__ void psi_apply_k(const float *__restrict__ u, int nx, int ny, int F, 
     const float uc = u[i];
     if (k < nx - 1) s[f * g.per_frame + (int64_t)l * (nx - 1) + k] = u[i + 1] - uc;
     if (l < ny - 1) s[f * g.per_frame + g.dy_off + (int64_t)l * nx + k] = u[i + nx] - uc;
-    if (g.temporal && f < F - 1) s[g.t_off + f * npix + p] = u[i + npix] - uc;
+    if (g.temporal == TEMPORAL_DIFF && f < F - 1) s[g.t_off + f * npix + p] = u[i + npix] - uc;
+    if (g.temporal == TEMPORAL_OF && f < F - 1) {
+        const float *sx = flow + 2 * f * npix, *sy = sx + npix;
+        const OfCell cf = of_cell(sx[p], sy[p], k, l, nx, ny);
+        const OfCell cr = of_cell(-sx[p], -sy[p], k, l, nx, ny);
+        s[g.t_off + f * npix + p] = uc - of_sample(u + (f + 1) * npix, cf, nx);
+        s[g.t_off + (F - 1 + f) * npix + p] = u[i + npix] - of_sample(u + f * npix, cr, nx);
+    }
 }
 
 // Weighted regulariser Gram G[i][j] = sum_e w_e (Psi v_i)_e (Psi v_j)_e for the first ell
@@ -99,15 +115,51 @@ __global__ void psi_apply_k(const float *__restrict__ u, int nx, int ny, int F, 
 // a strided set of 16-pixel chunks: the chunk's weighted difference rows (<= 48 x ell)
 // are staged in LDS as FP64 and every thread accumulates a 4x4 tile of G in FP64.
 constexpr int GP_PIX = 16;
-constexpr int GP_ROWS = GP_PIX * 3;
+constexpr int GP_ROWS = GP_PIX * 4;   // at most four rows per pixel (dx, dy, two motion rows)
 constexpr int GMAX = 64;
+
+// The j-th difference row (kind 0 dx, 1 dy, 2 dt or forward motion, 3 reverse motion) of
+// pixel i for column vc, unweighted, 0 where the row does not exist.
+__device__ __forceinline__ double psi_row(const float *__restrict__ vc, const TVGeo &g, int64_t i,
+                                          int kind)
+{
+    const int64_t npix = (int64_t)g.nx * g.ny;
+    const int64_t f = i / npix, p = i - f * npix;
+    const int l = (int)(p / g.nx), k = (int)(p - (int64_t)l * g.nx);
+    if (kind == 0) return k < g.nx - 1 ? (double)vc[i + 1] - (double)vc[i] : 0.0;
+    if (kind == 1) return l < g.ny - 1 ? (double)vc[i + g.nx] - (double)vc[i] : 0.0;
+    if (f >= g.F - 1) return 0.0;
+    if (g.temporal == TEMPORAL_DIFF) return kind == 2 ? (double)vc[i + npix] - (double)vc[i] : 0.0;
+    const float *sx = g.flow + 2 * f * npix, *sy = sx + npix;
+    if (kind == 2) {
+        const OfCell c = of_cell(sx[p], sy[p], k, l, g.nx, g.ny);
+        return (double)vc[i] - (double)of_sample(vc + (f + 1) * npix, c, g.nx);
+    }
+    const OfCell c = of_cell(-sx[p], -sy[p], k, l, g.nx, g.ny);
+    return (double)vc[i + npix] - (double)of_sample(vc + f * npix, c, g.nx);
+}
+
+// Index of the weight of that row in w.
+__device__ __forceinline__ int64_t psi_row_weight(const TVGeo &g, int64_t i, int kind)
+{
+    const int64_t npix = (int64_t)g.nx * g.ny;
+    const int64_t f = i / npix, p = i - f * npix;
+    const int l = (int)(p / g.nx), k = (int)(p - (int64_t)l * g.nx);
+    if (kind == 0) return f * g.per_frame + (int64_t)l * (g.nx - 1) + k;
+    if (kind == 1) return f * g.per_frame + g.dy_off + (int64_t)l * g.nx + k;
+    if (kind == 2) return g.t_off + f * npix + p;
+    return g.t_off + (g.F - 1 + f) * npix + p;
+}
 
 __global__ __launch_bounds__(BLK) void gram_psi_k(const float *__restrict__ V, int64_t ldv, int ell,
                                                   const float *__restrict__ w, int nx, int ny,
-                                                  int F, int temporal, double *__restrict__ part)
+                                                  int F, int temporal, double *__restrict__ part,
+                                                  const float *__restrict__ flow)
 {
     __shared__ double sB[GP_ROWS][GMAX + 1];
-    const TVGeo g = tvgeo(nx, ny, F, temporal);
+    const TVGeo g = tvgeo(nx, ny, F, temporal, flow);
+    const int KIND = g.temporal == TEMPORAL_OF ? 4 : (g.temporal == TEMPORAL_DIFF ? 3 : 2);
+    const int rows = GP_PIX * KIND;
     const int64_t npix = (int64_t)nx * ny;
     const int64_t ntot = npix * F;
     const int tid = threadIdx.x;
@@ -120,32 +172,21 @@ __global__ __launch_bounds__(BLK) void gram_psi_k(const float *__restrict__ V, i
     const int64_t nchunks = (ntot + GP_PIX - 1) / GP_PIX;
     const bool active = 4 * ti < ell && 4 * tj < ell;
     for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-        // stage rows: row r = 3 * pixel + {0: dx, 1: dy, 2: dt}
-        for (int t = tid; t < GP_ROWS * ell; t += BLK) {
-            const int c = t / GP_ROWS, r = t - c * GP_ROWS;
-            const int pc = r / 3, kind = r - pc * 3;
+        // stage rows: row r = KIND * pixel + kind
+        for (int t = tid; t < rows * ell; t += BLK) {
+            const int c = t / rows, r = t - c * rows;
+            const int pc = r / KIND, kind = r - pc * KIND;
             const int64_t i = ch * GP_PIX + pc;
             double val = 0.0;
             if (i < ntot) {
-                const int64_t f = i / npix, p = i - f * npix;
-                const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
-                const float *vc = V + (int64_t)c * ldv;
-                if (kind == 0 && k < nx - 1) {
-                    const float ww = w[f * g.per_frame + (int64_t)l * (nx - 1) + k];
-                    val = sqrt((double)ww) * ((double)vc[i + 1] - (double)vc[i]);
-                } else if (kind == 1 && l < ny - 1) {
-                    const float ww = w[f * g.per_frame + g.dy_off + (int64_t)l * nx + k];
-                    val = sqrt((double)ww) * ((double)vc[i + nx] - (double)vc[i]);
-                } else if (kind == 2 && g.temporal && f < F - 1) {
-                    const float ww = w[g.t_off + f * npix + p];
-                    val = sqrt((double)ww) * ((double)vc[i + npix] - (double)vc[i]);
-                }
+                const double d = psi_row(V + (int64_t)c * ldv, g, i, kind);
+                if (d != 0.0) val = sqrt((double)w[psi_row_weight(g, i, kind)]) * d;
             }
             sB[r][c] = val;
         }
         __syncthreads();
         if (active) {
-            for (int r = 0; r < GP_ROWS; ++r) {
+            for (int r = 0; r < rows; ++r) {
                 double ra[4], cb[4];
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
@@ -182,8 +223,8 @@ __global__ __launch_bounds__(BLK) void gram_psi_k(const float *__restrict__ V, i
 // lane j + 32 ((i/4) mod 2), register (i mod 4) + 4 (i / 8).
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef short s16x4 __attribute__((ext_vector_type(4)));
-constexpr int MP = 64;            // pixels per chunk
-constexpr int MRMAX = 3 * MP;     // rows per chunk (dx, dy and, with frame differences, dt)
+constexpr int MP = 64;            // pixels per chunk (48 with the two motion rows)
+constexpr int MRMAX = 3 * MP;     // rows per chunk (dx, dy and dt, or dx, dy and two motion rows)
 constexpr int MLDR = MRMAX + 1;   // LDS column stride (floats, odd: conflict-free columns)
 constexpr int MLDH = MRMAX + 4;   // BF16 column stride (shorts; 8-byte units odd)
 
@@ -207,16 +248,19 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
                                                        int ell, const float *__restrict__ w,
                                                        int nx, int ny, int F, int temporal,
                                                        double *__restrict__ part,
-                                                       const float *__restrict__ u, float e2)
+                                                       const float *__restrict__ u, float e2,
+                                                       const float *__restrict__ flow)
 {
     // the chunk's weighted differences, column-major: FP32, or BF16 rounded once at staging
     // (four consecutive rows of a column are then one 8-byte MFMA operand)
     using Elem = typename std::conditional<BF16, short, float>::type;
     constexpr int LD = BF16 ? MLDH : MLDR;
     __shared__ __align__(16) Elem sB[64][LD];
-    const TVGeo g = tvgeo(nx, ny, F, temporal);
-    const int KIND = g.temporal ? 3 : 2;
-    const int MR = KIND * MP;
+    const TVGeo g = tvgeo(nx, ny, F, temporal, flow);
+    const bool motion = g.temporal == TEMPORAL_OF;
+    const int KIND = motion ? 4 : (g.temporal == TEMPORAL_DIFF ? 3 : 2);
+    const int mp = motion ? 48 : MP;       // pixels per chunk: KIND * mp <= MRMAX rows
+    const int MR = KIND * mp;
     const int64_t npix = (int64_t)nx * ny;
     const int64_t ntot = npix * F;
     const int tid = threadIdx.x;
@@ -236,12 +280,15 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
     double accd[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) accd[r] = 0.0;
-    const int64_t nchunks = (ntot + MP - 1) / MP;
+    const int64_t nchunks = (ntot + mp - 1) / mp;
     for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-        const int64_t i = ch * MP + pc;
-        float w0 = 0.f, w1 = 0.f, w2 = 0.f;
+        const int64_t i = ch * mp + pc;
+        const bool stage = pc < mp;            // lanes beyond the chunk stage nothing
+        float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f;
         int64_t ox = -1, oy = -1, ot = -1;   // neighbour offsets of the existing differences
-        if (i < ntot) {
+        OfCell cf{0, 0.f, 0.f, 0.f, 0.f}, cr{0, 0.f, 0.f, 0.f, 0.f};   // motion rows' cells
+        int64_t fo = 0, ro = 0;              // their frames' first pixels (f + 1 and f)
+        if (stage && i < ntot) {
             const int64_t f = i / npix, p = i - f * npix;
             const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
             // weights stored in w, or formed from u (the same values)
@@ -256,39 +303,58 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
                                         : w[f * g.per_frame + g.dy_off + (int64_t)l * nx + k]);
                 oy = nx;
             }
-            if (g.temporal && f < F - 1) {
+            if (g.temporal == TEMPORAL_DIFF && f < F - 1) {
                 w2 = sqrtf(u != nullptr ? tv_weight(u[i + npix] - uc, e2)
                                         : w[g.t_off + f * npix + p]);
                 ot = npix;
             }
+            if (motion && f < F - 1) {
+                const float *sx = flow + 2 * f * npix, *sy = sx + npix;
+                cf = of_cell(sx[p], sy[p], k, l, nx, ny);
+                cr = of_cell(-sx[p], -sy[p], k, l, nx, ny);
+                fo = (f + 1) * npix;
+                ro = f * npix;
+                ot = npix;
+                w2 = sqrtf(u != nullptr ? tv_weight(uc - of_sample(u + fo, cf, nx), e2)
+                                        : w[g.t_off + f * npix + p]);
+                w3 = sqrtf(u != nullptr ? tv_weight(u[i + npix] - of_sample(u + ro, cr, nx), e2)
+                                        : w[g.t_off + (F - 1 + f) * npix + p]);
+            }
         }
         // four columns per step, all their loads issued before any use
         for (int c0 = cg; c0 < ell; c0 += 4 * (BLK / 64)) {
-            float x0[4], x1[4], x2[4], x3[4];
+            float x0[4], x1[4], x2[4], x3[4], m0[4], m1[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int c = c0 + u * (BLK / 64);
-                const bool ok = c < ell && i < ntot;
+                const bool ok = stage && c < ell && i < ntot;
                 const float *vc = V + (int64_t)(ok ? c : 0) * ldv;
                 x0[u] = ok ? vc[i] : 0.0f;
                 x1[u] = (ok && ox > 0) ? vc[i + ox] : x0[u];
                 x2[u] = (ok && oy > 0) ? vc[i + oy] : x0[u];
                 x3[u] = (ok && ot > 0) ? vc[i + ot] : x0[u];
+                // motion rows: the column's frames f + 1 and f warped at the pixel's cells
+                m0[u] = (ok && motion && ot > 0) ? of_sample(vc + fo, cf, nx) : x0[u];
+                m1[u] = (ok && motion && ot > 0) ? of_sample(vc + ro, cr, nx) : x3[u];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int c = c0 + u * (BLK / 64);
-                if (c < ell) {
+                if (stage && c < ell) {
                     Elem *col = &sB[c][KIND * pc];
                     const float d0 = w0 * (x1[u] - x0[u]), d1 = w1 * (x2[u] - x0[u]);
+                    const float d2 = motion ? w2 * (x0[u] - m0[u]) : w2 * (x3[u] - x0[u]);
+                    const float d3 = w3 * (x3[u] - m1[u]);
                     if constexpr (BF16) {
                         col[0] = bf16_rne(d0);
                         col[1] = bf16_rne(d1);
-                        if (KIND == 3) col[2] = bf16_rne(w2 * (x3[u] - x0[u]));
+                        if (KIND >= 3) col[2] = bf16_rne(d2);
+                        if (KIND == 4) col[3] = bf16_rne(d3);
                     } else {
                         col[0] = d0;
                         col[1] = d1;
-                        if (KIND == 3) col[2] = w2 * (x3[u] - x0[u]);
+                        if (KIND >= 3) col[2] = d2;
+                        if (KIND == 4) col[3] = d3;
                     }
                 }
             }
@@ -1449,17 +1515,23 @@ static unsigned grid_for(int64_t n, int per = BLK, int64_t cap = 4096)
 }
 
 int k_psi_weights(const float *u, int nx, int ny, int F, int temporal, float eps, float *w,
-                  hipStream_t s)
+                  hipStream_t s, const float *flow)
 {
+    if (temporal == TEMPORAL_OF && F > 1 && (flow == nullptr || nx < 2 || ny < 2))
+        return NLRMM_EINVAL;
     const int64_t n = (int64_t)nx * ny * F;
-    psi_weights_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(u, nx, ny, F, temporal, eps, w);
+    psi_weights_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(u, nx, ny, F, temporal, eps, w,
+                                                             flow);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 
-int k_psi_apply(const float *u, int nx, int ny, int F, int temporal, float *out, hipStream_t s)
+int k_psi_apply(const float *u, int nx, int ny, int F, int temporal, float *out, hipStream_t s,
+                const float *flow)
 {
+    if (temporal == TEMPORAL_OF && F > 1 && (flow == nullptr || nx < 2 || ny < 2))
+        return NLRMM_EINVAL;
     const int64_t n = (int64_t)nx * ny * F;
-    psi_apply_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(u, nx, ny, F, temporal, out);
+    psi_apply_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(u, nx, ny, F, temporal, out, flow);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 
@@ -1474,19 +1546,22 @@ int k_tv_grad_add(const float *u, const float *w, int nx, int ny, int F, int tem
 
 int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int ny, int F,
                int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s, int mode,
-               const float *u, float eps)
+               const float *u, float eps, const float *flow)
 {
     if (ell > GMAX) return NLRMM_ESHAPE;
     if (w == nullptr && (u == nullptr || mode == 0)) return NLRMM_EINVAL;
+    if (temporal == TEMPORAL_OF && F > 1 && (flow == nullptr || nx < 2 || ny < 2))
+        return NLRMM_EINVAL;
     const float e2 = eps * eps;
     if (mode == 1)
         gram_psi_mfma_k<false><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal,
-                                                              part, w ? nullptr : u, e2);
+                                                              part, w ? nullptr : u, e2, flow);
     else if (mode == 2)
         gram_psi_mfma_k<true><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal,
-                                                             part, w ? nullptr : u, e2);
+                                                             part, w ? nullptr : u, e2, flow);
     else
-        gram_psi_k<<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal, part);
+        gram_psi_k<<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal, part,
+                                                  flow);
     reduce_gram_k<<<(unsigned)(ell * ell), 64, 0, s>>>(part, nblk, ell, G, ldg);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }

@@ -9,6 +9,7 @@
 // projected quantities (Grams, coefficients, lambda) live on the device in FP64.
 #include "internal.h"
 #include "krylov.h"
+#include "tv.h"
 
 #include <math.h>
 #include <new>
@@ -53,6 +54,13 @@ struct Solver {
     double *vp_GA = nullptr, *vp_ab = nullptr, *vp_M = nullptr, *vp_y = nullptr, *vp_gd = nullptr,
            *vp_en2 = nullptr, *vp_ETr = nullptr, *vp_Ate = nullptr, *vp_Y = nullptr;
     int *status = nullptr, *kout = nullptr, *accepted = nullptr;
+    // optical-flow regulariser (temporal mode 2): velocities of the frame pairs, the
+    // conjugate-gradient work of their estimation, the fixed-point accumulators of the motion
+    // rows' transpose; outer iterations run (the velocity update period)
+    float *flow = nullptr, *of_work = nullptr;
+    double *of_part = nullptr;
+    long long *of_acc = nullptr;
+    int64_t outer_count = 0;
     std::vector<void *> allocs;
     // plain mode: one launch per frame (and per column) instead of one batched launch
     int plain = 0;
@@ -201,7 +209,8 @@ static int mm_residual(Solver &S, const nlrmm_batch &b, const double *theta, int
     const int64_t m = m_of(S, b);
     if (!S.rho_ready) RC(k_gemv(S.AV, m, ell, S.z, 1.0, bvec, -1.0, m, S.rho, s));
     S.rho_ready = false;
-    if (!per_frame(S, b)) {
+    const bool motion = S.cfg.temporal == TEMPORAL_OF && S.F > 1;
+    if (!per_frame(S, b) && !motion) {
         // one launch pair: backprojection with the TV-gradient term as its epilogue
         TvEpilogue tv;
         tv.u = S.u;
@@ -214,6 +223,10 @@ static int mm_residual(Solver &S, const nlrmm_batch &b, const double *theta, int
     RC(bproj(S, b, S.rho, theta, S.r, s));
     RC(k_tv_grad_add(S.u, inl ? nullptr : S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal,
                      S.sc + S_LAM, S.r, s, (float)S.cfg.eps));
+    // the motion rows of the optical-flow operator (their transpose is a scatter)
+    if (motion)
+        RC(k_of_grad_add(S.u, inl ? nullptr : S.w, S.flow, S.g.nx, S.g.ny, S.F, S.sc + S_LAM,
+                         S.r, S.of_acc, s, (float)S.cfg.eps));
     return NLRMM_OK;
 }
 
@@ -240,9 +253,10 @@ static int projected_solve(Solver &S, hipStream_t s, const nlrmm_batch *b = null
 {
     // this step's weights (from the u the solve starts from): the Gram and, in the expansion
     // that follows, the residual use them (Alg. "enlarge")
-    RC(k_psi_weights(S.u, S.g.nx, S.g.ny, S.F, S.cfg.temporal, (float)S.cfg.eps, S.w, s));
+    RC(k_psi_weights(S.u, S.g.nx, S.g.ny, S.F, S.cfg.temporal, (float)S.cfg.eps, S.w, s,
+                     S.flow));
     RC(k_gram_psi(S.V, S.n, S.ell, S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.part_gram,
-                  S.gram_blocks, S.GP, S.ld, s, S.cfg.gram_precision));
+                  S.gram_blocks, S.GP, S.ld, s, S.cfg.gram_precision, nullptr, 0.0f, S.flow));
     RC(k_gks_solve(S.GA, S.GP, S.ld, S.rb, S.sc + S_BNORM2, S.ell, S.cfg.lam_fix, S.z,
                    S.sc + S_LAM, S.status, s));
     if (b && bvec) {
@@ -329,9 +343,10 @@ static int varpro_update(Solver &S, const nlrmm_batch &b, double *theta, const f
     const int k = S.ell;
     const int64_t V = b.nviews;
     const int64_t m = m_of(S, b);
-    RC(k_psi_weights(S.u, S.g.nx, S.g.ny, S.F, S.cfg.temporal, (float)S.cfg.eps, S.w, s));
+    RC(k_psi_weights(S.u, S.g.nx, S.g.ny, S.F, S.cfg.temporal, (float)S.cfg.eps, S.w, s,
+                     S.flow));
     RC(k_gram_psi(S.V, S.n, k, S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.part_gram,
-                  S.gram_blocks, S.GP, S.ld, s, S.cfg.gram_precision));
+                  S.gram_blocks, S.GP, S.ld, s, S.cfg.gram_precision, nullptr, 0.0f, S.flow));
     double *sc = S.sc + S_GN;
     for (int it = 0; it < S.cfg.maxiter_p; ++it) {
         RC(proj_plain(S, b, k, S.V, theta, S.Ahat, s));
@@ -497,6 +512,12 @@ static int solver_outer(Solver &S, const nlrmm_batch &b, double *theta, const fl
     const int64_t V = b.nviews;
     const int64_t m = m_of(S, b);
     if (V > S.maxV) return NLRMM_ESHAPE;
+    // optical-flow branch of Alg. "dyn_nl_rmmgks": the velocities of every frame pair from
+    // u^(k) (SOLVE-OF) every of_every outer iterations; Theta^(k) = [Psi; M_hat] follows
+    if (S.cfg.temporal == TEMPORAL_OF && S.F > 1 && S.outer_count % S.cfg.of_every == 0)
+        RC(k_of_estimate(S.u, S.g.nx, S.g.ny, S.F, (float)S.cfg.of_gamma, (float)S.cfg.of_ridge,
+                         S.cfg.of_iters, S.flow, S.of_work, S.of_part, s));
+    ++S.outer_count;
     // theta_k: the operator H_k of this outer iteration
     RC(k_copy_f64(theta, S.thk, V, s));
     RC(k_fill_f64(S.sc + S_TARGET, 1, S.cfg.tau * delta, s));
@@ -706,6 +727,19 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
     if (c.param_update == 3 && (c.param_mode != 1 || c.kmax + 1 - c.kmin < 6))
         return NLRMM_ENOTSUP;
     if (c.sens_iters <= 0) c.sens_iters = 50;
+    // temporal rows: 0 none, 1 frame differences (ANISO-TV), 2 optical-flow motion rows
+    if (c.temporal < 0 || c.temporal > 2) return NLRMM_ENOTSUP;
+    if (c.temporal == TEMPORAL_OF) {
+        if (nframes > 1 && (geom->nx < 2 || geom->ny < 2)) return NLRMM_ESHAPE;
+        // the sensitivity solve forms its regulariser without the motion rows
+        if (c.param_update == 3) return NLRMM_ENOTSUP;
+        if (c.of_iters <= 0) c.of_iters = 200;
+        if (!(c.of_gamma > 0.0)) c.of_gamma = 0.05;
+        if (!(c.of_ridge > 0.0)) c.of_ridge = 1e-3;
+        if (c.of_every <= 0) c.of_every = 1;
+        if (!(c.of_gamma < HUGE_VAL) || !(c.of_ridge < HUGE_VAL) || c.of_iters > 100000)
+            return NLRMM_EINVAL;
+    }
     if (c.gram_precision < 0 || c.gram_precision > 2) return NLRMM_ENOTSUP;
     if (c.compress_precision != 0 && c.compress_precision != 2) return NLRMM_ENOTSUP;
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
@@ -723,7 +757,9 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
     S->nchunks = fwd_chunks(*geom);
     const int64_t big = S->n > S->mmax ? S->n : S->mmax;
     size_blocks(*S, S->n, S->mmax);
-    const int64_t npsi_max = (int64_t)nframes * 2 * geom->nx * geom->ny + (int64_t)nframes * geom->nx * geom->ny;
+    // spatial rows (< 2 per pixel) plus temporal rows (1 per pixel, 2 with optical flow)
+    const int64_t npsi_max = (int64_t)nframes * geom->nx * geom->ny *
+                             (c.temporal == TEMPORAL_OF ? 4 : 3);
     if ((rc = S->alloc(&S->V, (size_t)S->kcap * S->n)) ||
         (rc = S->alloc(&S->AV, (size_t)S->kcap * S->mmax)) ||
         (rc = S->alloc(&S->Vtmp, (size_t)c.kmin * big)) || (rc = S->alloc(&S->u, S->n)) ||
@@ -752,6 +788,20 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
         (rc = S->alloc(&S->vp_Y, (size_t)c.kmin * max_views))) {
         delete S;
         return rc;
+    }
+    if (c.temporal == TEMPORAL_OF && nframes > 1) {
+        const int64_t npix = (int64_t)geom->nx * geom->ny;
+        if ((rc = S->alloc(&S->flow, (size_t)(2 * (nframes - 1) * npix))) ||
+            (rc = S->alloc(&S->of_work, of_work_floats(geom->nx, geom->ny, nframes))) ||
+            (rc = S->alloc(&S->of_part, of_part_doubles(geom->nx, geom->ny, nframes))) ||
+            (rc = S->alloc(&S->of_acc, (size_t)(nframes * npix)))) {
+            delete S;
+            return rc;
+        }
+        if (hipMemset(S->flow, 0, sizeof(float) * 2 * (nframes - 1) * npix) != hipSuccess) {
+            delete S;
+            return NLRMM_EHIP;
+        }
     }
     double al[32];
     for (int q = 0; q < 32; ++q) al[q] = c.alpha0 * pow(c.beta, q);
@@ -817,6 +867,7 @@ int nlrmm_solver_offset_sensitivity(nlrmm_solver *S, const nlrmm_batch *batch,
     if (rc) return rc;
     if (batch->nframes != S->F || batch->nviews > S->maxV) return NLRMM_ESHAPE;
     if (iters < 1) return NLRMM_EINVAL;
+    if (S->cfg.temporal == TEMPORAL_OF && S->F > 1) return NLRMM_ENOTSUP;
     return offset_sensitivity(*S, *batch, theta, b, iters, out, up, (hipStream_t)stream);
 }
 
@@ -949,6 +1000,96 @@ int nlrmm_gram_psi(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, int3
                       S.gram_blocks, G, ldg, (hipStream_t)stream, precision);
 }
 
+static int theta_args(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, int32_t temporal,
+                      const float *flow)
+{
+    if (!ctx) return NLRMM_EINVAL;
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if (nframes < 1) return NLRMM_ESHAPE;
+    if (temporal < 0 || temporal > 2) return NLRMM_ENOTSUP;
+    if (temporal == TEMPORAL_OF && nframes > 1) {
+        if (!flow) return NLRMM_EINVAL;
+        if (geom->nx < 2 || geom->ny < 2) return NLRMM_ESHAPE;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    return NLRMM_OK;
+}
+
+int nlrmm_of_estimate(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, const float *u,
+                      double gamma, double ridge, int32_t iters, float *flow, void *stream)
+{
+    if (!ctx || !u || !flow || !(gamma >= 0.0) || !(ridge >= 0.0) || !(gamma < HUGE_VAL) ||
+        !(ridge < HUGE_VAL) || iters < 0 || iters > 100000)
+        return NLRMM_EINVAL;
+    int rc = theta_args(ctx, geom, nframes, TEMPORAL_OF, flow);
+    if (rc) return rc;
+    if (nframes < 2) return NLRMM_OK;
+    if (nframes - 1 > 65535) return NLRMM_ESHAPE;
+    const size_t wf = of_work_floats(geom->nx, geom->ny, nframes);
+    const size_t pd = of_part_doubles(geom->nx, geom->ny, nframes);
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = ensure_buffer(ctx->kws, sizeof(float) * wf + sizeof(double) * pd + 256, s)))
+        return rc;
+    double *part = (double *)ctx->kws.ptr;
+    float *work = (float *)(part + pd);
+    return k_of_estimate(u, geom->nx, geom->ny, nframes, (float)gamma, (float)ridge, iters, flow,
+                         work, part, s);
+}
+
+int nlrmm_theta_apply(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, int32_t temporal,
+                      const float *flow, const float *u, float *out, void *stream)
+{
+    if (!u || !out) return NLRMM_EINVAL;
+    int rc = theta_args(ctx, geom, nframes, temporal, flow);
+    if (rc) return rc;
+    return k_psi_apply(u, geom->nx, geom->ny, nframes, temporal, out, (hipStream_t)stream, flow);
+}
+
+int nlrmm_theta_weights(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
+                        int32_t temporal, const float *flow, const float *u, double eps,
+                        float *w, void *stream)
+{
+    if (!u || !w || !(eps > 0.0)) return NLRMM_EINVAL;
+    int rc = theta_args(ctx, geom, nframes, temporal, flow);
+    if (rc) return rc;
+    return k_psi_weights(u, geom->nx, geom->ny, nframes, temporal, (float)eps, w,
+                         (hipStream_t)stream, flow);
+}
+
+int nlrmm_theta_grad_add(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
+                         int32_t temporal, const float *flow, const float *u, const float *w,
+                         double eps, const double *lambda, float *r, void *stream)
+{
+    if (!u || !r || !lambda || (!w && !(eps > 0.0))) return NLRMM_EINVAL;
+    int rc = theta_args(ctx, geom, nframes, temporal, flow);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int nx = geom->nx, ny = geom->ny;
+    if ((rc = k_tv_grad_add(u, w, nx, ny, nframes, temporal, lambda, r, s, (float)eps))) return rc;
+    if (temporal != TEMPORAL_OF || nframes < 2) return NLRMM_OK;
+    if ((rc = ensure_buffer(ctx->kws, sizeof(long long) * (size_t)nframes * nx * ny, s)))
+        return rc;
+    return k_of_grad_add(u, w, flow, nx, ny, nframes, lambda, r, (long long *)ctx->kws.ptr, s,
+                         (float)eps);
+}
+
+int nlrmm_gram_theta(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes, int32_t temporal,
+                     const float *flow, int32_t ell, const float *V, const float *w, double *G,
+                     int32_t ldg, int32_t precision, void *stream)
+{
+    if (!V || !w || !G) return NLRMM_EINVAL;
+    if (precision < 0 || precision > 2) return NLRMM_ENOTSUP;
+    int rc = theta_args(ctx, geom, nframes, temporal, flow);
+    if (rc) return rc;
+    if (ell < 1 || ell > 64 || ldg < ell) return NLRMM_ESHAPE;
+    Solver S;
+    const int64_t n = (int64_t)nframes * geom->nx * geom->ny;
+    if ((rc = scratch_view(ctx, S, n, 1, ell + 1, 2, (hipStream_t)stream))) return rc;
+    return k_gram_psi(V, n, ell, w, geom->nx, geom->ny, nframes, temporal, S.part_gram,
+                      S.gram_blocks, G, ldg, (hipStream_t)stream, precision, nullptr, 0.0f, flow);
+}
+
 int nlrmm_gks_solve(nlrmm_ctx *ctx, int32_t ell, const double *GA, const double *GP,
                     int32_t ldg, const double *rb, const double *scal, double lam_fix, double *z,
                     double *out, int32_t *status, void *stream)
@@ -971,6 +1112,7 @@ int nlrmm_gks_expand(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *
         return NLRMM_EINVAL;
     if ((rc = check_batch(batch))) return rc;
     if (ell < 1 || ell > 55 || ldg < ell + 1) return NLRMM_ESHAPE;
+    if (temporal < 0 || temporal > 1) return NLRMM_ENOTSUP;   // no velocity argument here
     if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
     hipStream_t s = (hipStream_t)stream;
     Solver S;

@@ -361,6 +361,90 @@ def gram_psi(V: torch.Tensor, w: torch.Tensor, g: Geom, ell: int, nframes: int =
     return G
 
 
+def theta_rows(g: Geom, nframes: int, temporal: int) -> int:
+    """Length of Theta u: spatial rows plus the temporal rows of mode `temporal` (0 none,
+    1 frame differences, 2 optical-flow motion rows)."""
+    n = nframes * (g.ny * (g.nx - 1) + (g.ny - 1) * g.nx)
+    if nframes > 1 and temporal == 1:
+        n += (nframes - 1) * g.nx * g.ny
+    if nframes > 1 and temporal == 2:
+        n += 2 * (nframes - 1) * g.nx * g.ny
+    return n
+
+
+def _flow_ptr(flow):
+    if flow is None:
+        return None
+    _need(flow, torch.float32, "flow")
+    return flow.data_ptr()
+
+
+def of_estimate(u: torch.Tensor, g: Geom, nframes: int, gamma: float = 0.05,
+                ridge: float = 1e-3, iters: int = 200,
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Velocities of every frame pair of u ([nframes, ny, nx]) by nlrmm_of_estimate:
+    [nframes-1, 2, ny, nx] float32 (s_x, s_y)."""
+    _need(u, torch.float32, "u")
+    if out is None:
+        out = torch.empty((max(nframes - 1, 0), 2, g.ny, g.nx), dtype=torch.float32,
+                          device=u.device)
+    check(_lib.lib().nlrmm_of_estimate(context(u.device.index or 0), ctypes.byref(g), nframes,
+                                       u.data_ptr(), gamma, ridge, iters, out.data_ptr(),
+                                       _stream(u.device)), "nlrmm_of_estimate")
+    return out
+
+
+def theta_apply(u: torch.Tensor, g: Geom, nframes: int, temporal: int,
+                flow: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Theta u (nlrmm_theta_apply)."""
+    _need(u, torch.float32, "u")
+    out = torch.empty(theta_rows(g, nframes, temporal), dtype=torch.float32, device=u.device)
+    check(_lib.lib().nlrmm_theta_apply(context(u.device.index or 0), ctypes.byref(g), nframes,
+                                       temporal, _flow_ptr(flow), u.data_ptr(), out.data_ptr(),
+                                       _stream(u.device)), "nlrmm_theta_apply")
+    return out
+
+
+def theta_weights(u: torch.Tensor, g: Geom, nframes: int, temporal: int,
+                  flow: Optional[torch.Tensor] = None, eps: float = 1e-3) -> torch.Tensor:
+    """w = ((Theta u)^2 + eps^2)^(-1/2) (nlrmm_theta_weights)."""
+    _need(u, torch.float32, "u")
+    out = torch.empty(theta_rows(g, nframes, temporal), dtype=torch.float32, device=u.device)
+    check(_lib.lib().nlrmm_theta_weights(context(u.device.index or 0), ctypes.byref(g), nframes,
+                                         temporal, _flow_ptr(flow), u.data_ptr(), eps,
+                                         out.data_ptr(), _stream(u.device)),
+          "nlrmm_theta_weights")
+    return out
+
+
+def theta_grad_add(u: torch.Tensor, r: torch.Tensor, lam: torch.Tensor, g: Geom, nframes: int,
+                   temporal: int, flow: Optional[torch.Tensor] = None,
+                   w: Optional[torch.Tensor] = None, eps: float = 1e-3) -> torch.Tensor:
+    """r += lam Theta^T (w * Theta u) in place (nlrmm_theta_grad_add); lam a device float64
+    scalar tensor; w None: the weights of u."""
+    _need(u, torch.float32, "u")
+    _need(r, torch.float32, "r")
+    _need(lam, torch.float64, "lam")
+    check(_lib.lib().nlrmm_theta_grad_add(context(u.device.index or 0), ctypes.byref(g),
+                                          nframes, temporal, _flow_ptr(flow), u.data_ptr(),
+                                          None if w is None else w.data_ptr(), eps,
+                                          lam.data_ptr(), r.data_ptr(), _stream(u.device)),
+          "nlrmm_theta_grad_add")
+    return r
+
+
+def gram_theta(V: torch.Tensor, w: torch.Tensor, g: Geom, ell: int, nframes: int, temporal: int,
+               flow: Optional[torch.Tensor] = None, precision: int = 0) -> torch.Tensor:
+    """(Theta V)^T diag(w) (Theta V) for the first ell columns (nlrmm_gram_theta)."""
+    _need(V, torch.float32, "V")
+    G = torch.empty((ell, ell), dtype=torch.float64, device=V.device)
+    check(_lib.lib().nlrmm_gram_theta(context(V.device.index or 0), ctypes.byref(g), nframes,
+                                      temporal, _flow_ptr(flow), ell, V.data_ptr(), w.data_ptr(),
+                                      G.data_ptr(), ell, precision, _stream(V.device)),
+          "nlrmm_gram_theta")
+    return G
+
+
 def gks_solve(GA, GP, rb, scal, ell, lam_fix=-1.0, status=None):
     """Projected solve with the discrepancy principle; returns (z [ell], out [2], status)."""
     dev = GA.device

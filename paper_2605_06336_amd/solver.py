@@ -32,11 +32,15 @@ class Config:
     alpha0: float = 1.0
     armijo_trials: int = 10
     breakdown_tol: float = 1e-10
-    temporal: int = 0
+    temporal: int = 0            # 0 none, 1 frame differences, 2 optical-flow motion rows
     gram_precision: int = 0      # 0 FP64, 1 FP32 MFMA, 2 BF16 MFMA
     compress_precision: int = 0  # compression basis products: 0 FP32 (FP64 accumulate), 2 BF16 MFMA
     lam_hi: float = 0.0          # > 0: high-regularisation solve feeding the parameter update
     sens_iters: int = 50         # CG steps of the sensitivity solve (param_update 3)
+    of_iters: int = 200          # temporal 2: CG steps of the velocity estimation
+    of_gamma: float = 0.05       # temporal 2: smoothness weight of the velocity problem
+    of_ridge: float = 1e-3       # temporal 2: ridge of the velocity problem
+    of_every: int = 1            # temporal 2: velocities re-estimated every of_every outer its
 
     def struct(self) -> SolverCfg:
         return SolverCfg(**dataclasses.asdict(self))

@@ -60,6 +60,13 @@ def test_host_validation_without_device():
         # the geometry is checked first, then pointers, the source distance and the batch
         g0 = _lib.Geom(nx=0, ny=8, x0=-1, y0=-1, d=0.25, nbins=13, s0=-1.42, ds=0.2)
         assert fn(None, ctypes.byref(g0), ctypes.byref(b), 1, 1, 1, 4.0, 1, None) == -2
+    # the optical-flow family: null context, then a temporal mode it does not know
+    assert lib.nlrmm_of_estimate(None, ctypes.byref(g), 3, 1, 0.05, 1e-3, 10, 1, None) == -1
+    assert lib.nlrmm_theta_apply(None, ctypes.byref(g), 3, 2, 1, 1, 1, None) == -1
+    assert lib.nlrmm_theta_weights(None, ctypes.byref(g), 3, 2, 1, 1, 1e-3, 1, None) == -1
+    assert lib.nlrmm_theta_grad_add(None, ctypes.byref(g), 3, 2, 1, 1, None, 1e-3, 1, 1,
+                                    None) == -1
+    assert lib.nlrmm_gram_theta(None, ctypes.byref(g), 3, 2, 1, 4, 1, 1, 1, 4, 0, None) == -1
     assert lib.nlrmm_strerror(-2) == b"inconsistent or unsupported sizes"
     assert lib.nlrmm_version() >= 100
 
