@@ -23,7 +23,9 @@ Also reported:
     per call and per kernel (single launches between HIP events);
   * outer it/s of the 32-frame dynamic workload, batched (one launch over all frames, the
     outer iteration replayed as a HIP graph) against plain (per-frame launches, eager), with
-    the difference of the two reconstructions after the same iterations;
+    the difference of the two reconstructions after the same iterations; the same workload
+    with the optical-flow regulariser (velocities re-estimated every outer iteration) and the
+    time of one velocity estimation;
   * ms of the full-space sensitivity solve of one global offset (50 CG steps) at the same
     workload;
   * Gsamples/s of the three operators at the shape of every workload (64x64 up to
@@ -532,6 +534,36 @@ def dynamic_leg(torch, ops, synth, Config, OuterGraph, Solver, steps, warmup, gr
                                         np.linalg.norm(x_true)), 5),
                      "status": int(status.cpu()[0])}
         sol.close()
+    # the optical-flow temporal regulariser at the same shape (batched, graph replay): the
+    # velocities of all 31 frame pairs re-estimated (200 CG steps) at every outer iteration
+    cfg = Config(kmin=wl.kmin, kmax=wl.kmax, eps=wl.eps, temporal=2,
+                 gram_precision=gram_precision)
+    sol = Solver(g, wl.frames, V, cfg)
+    th = torch.as_tensor(inst.theta_nom.copy(), device="cuda")
+    sol.init(th, b, fr)
+    for _ in range(warmup):
+        sol.outer(th, b, delta, fr)
+    gr = OuterGraph(sol, th, b, delta, fr)
+    ms = timed_steps(torch, gr.replay, steps, stream, "dynamic optical flow")
+    u, _, status = sol.read()
+    torch.cuda.synchronize()
+    u_of = u.cpu().numpy().astype(np.float64)
+    uu = u.view(wl.frames, wl.N, wl.N)
+    flow = ops.of_estimate(uu, g, wl.frames, 0.05, 1e-3, 200)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ops.of_estimate(uu, g, wl.frames, 0.05, 1e-3, 200, out=flow)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sol.close()
+    x_true = inst.x_true.reshape(-1)
+    out["optical_flow"] = {"outer_it_s": round(1000.0 / ms, 4), "ms_per_step": round(ms, 3),
+                           "velocity_estimate_ms": round(e0.elapsed_time(e1), 3),
+                           "rre": round(float(np.linalg.norm(u_of - x_true) /
+                                              np.linalg.norm(x_true)), 5),
+                           "status": int(status.cpu()[0])}
     out["speedup"] = round(out["batched"]["outer_it_s"] / out["plain"]["outer_it_s"], 3)
     out["u_rel_diff_batched_vs_plain"] = float(
         np.linalg.norm(us["batched"] - us["plain"]) / np.linalg.norm(us["plain"]))

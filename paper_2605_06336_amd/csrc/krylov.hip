@@ -243,7 +243,7 @@ __device__ __forceinline__ short bf16_rne(float f)
 // formed: for ell <= 32 the four waves split the rows of the single tile, otherwise waves
 // 0..2 take the tiles (0,0), (0,1), (1,1).  Per-block partials go to part[block][ell][ell]
 // (both triangles).
-template <bool BF16>
+template <bool BF16, bool MOTION>
 __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__ V, int64_t ldv,
                                                        int ell, const float *__restrict__ w,
                                                        int nx, int ny, int F, int temporal,
@@ -257,9 +257,10 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
     constexpr int LD = BF16 ? MLDH : MLDR;
     __shared__ __align__(16) Elem sB[64][LD];
     const TVGeo g = tvgeo(nx, ny, F, temporal, flow);
-    const bool motion = g.temporal == TEMPORAL_OF;
+    // MOTION: the launch has the optical-flow rows (temporal mode 2 with several frames)
+    constexpr bool motion = MOTION;
     const int KIND = motion ? 4 : (g.temporal == TEMPORAL_DIFF ? 3 : 2);
-    const int mp = motion ? 48 : MP;       // pixels per chunk: KIND * mp <= MRMAX rows
+    constexpr int mp = motion ? 48 : MP;   // pixels per chunk: KIND * mp <= MRMAX rows
     const int MR = KIND * mp;
     const int64_t npix = (int64_t)nx * ny;
     const int64_t ntot = npix * F;
@@ -349,12 +350,12 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
                         col[0] = bf16_rne(d0);
                         col[1] = bf16_rne(d1);
                         if (KIND >= 3) col[2] = bf16_rne(d2);
-                        if (KIND == 4) col[3] = bf16_rne(d3);
+                        if (motion) col[3] = bf16_rne(d3);
                     } else {
                         col[0] = d0;
                         col[1] = d1;
                         if (KIND >= 3) col[2] = d2;
-                        if (KIND == 4) col[3] = d3;
+                        if (motion) col[3] = d3;
                     }
                 }
             }
@@ -1553,12 +1554,21 @@ int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int
     if (temporal == TEMPORAL_OF && F > 1 && (flow == nullptr || nx < 2 || ny < 2))
         return NLRMM_EINVAL;
     const float e2 = eps * eps;
-    if (mode == 1)
-        gram_psi_mfma_k<false><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal,
-                                                              part, w ? nullptr : u, e2, flow);
+    const bool motion = temporal == TEMPORAL_OF && F > 1;
+    const float *ww = w ? nullptr : u;
+    if (mode == 1 && motion)
+        gram_psi_mfma_k<false, true><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F,
+                                                                    temporal, part, ww, e2, flow);
+    else if (mode == 1)
+        gram_psi_mfma_k<false, false><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F,
+                                                                     temporal, part, ww, e2,
+                                                                     flow);
+    else if (mode == 2 && motion)
+        gram_psi_mfma_k<true, true><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F,
+                                                                   temporal, part, ww, e2, flow);
     else if (mode == 2)
-        gram_psi_mfma_k<true><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal,
-                                                             part, w ? nullptr : u, e2, flow);
+        gram_psi_mfma_k<true, false><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F,
+                                                                    temporal, part, ww, e2, flow);
     else
         gram_psi_k<<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal, part,
                                                   flow);
