@@ -29,12 +29,13 @@
 // terms in FP32 and combines their differences between a bin's edges.  Sums over pixels or
 // views accumulate in FP64.
 //
-// Projection (bin-driven gather): one lane per (column, view, bin).  The bin's rays are
-// walked line by line through the image (rows when the bin's central ray is closer to the
-// y axis, columns otherwise); on every line the pixels whose footprint can reach the bin
-// lie within a short window around the crossings of the bin's two edge rays (the
-// perspective projection is monotone along a line that the rays cross at under 45 degrees),
-// so each lane evaluates a few candidates per line.  No atomics; deterministic.
+// Projection (bin-driven gather): four lanes per (column, view, group of four bins), each
+// walking every fourth line.  The group's rays are walked line by line through the image
+// (rows when their central ray is closer to the y axis, columns otherwise); on every line the
+// pixels whose footprint can reach the group lie within a short window around the crossings
+// of its two outer edge rays (the perspective projection is monotone along a line that the
+// rays cross at under 45 degrees); each candidate's local parameters serve the group's five
+// edges.  The lanes' sums meet in a fixed butterfly.  No atomics; deterministic.
 //
 // Transpose (pixel-driven gather): one lane per pixel of an 8x8 tile, four waves per block
 // splitting the frame's views; per view a pixel forms its local parameters once, walks the
@@ -204,18 +205,28 @@ __device__ __forceinline__ float fan_dweight(const FanEdge &e1, const FanEdge &e
 }
 
 // ---------------------------------------------------------------------------
-// projection and its angle derivative: one lane per (column, view, bin)
+// projection and its angle derivative: four lanes per (column, view, group of four bins)
 // ---------------------------------------------------------------------------
+constexpr int FAN_G = 4;   // bins per group: the candidates' local parameters serve all four
+constexpr int FAN_Q = 4;   // lanes per group, each walking every fourth line
+
 template <bool DERIV>
 __global__ __launch_bounds__(FAN_FWD_BLK) void fan_fwd_k(FanArgs a)
 {
     const int64_t gid = (int64_t)blockIdx.x * FAN_FWD_BLK + threadIdx.x;
-    const int64_t per_col = a.nviews * a.nb;
-    if (gid >= per_col * a.ncols) return;
-    const int col = (int)(gid / per_col);
-    const int64_t rem = gid - (int64_t)col * per_col;
-    const int64_t v = rem / a.nb;
-    const int j = (int)(rem - v * a.nb);
+    const int q = (int)(gid & (FAN_Q - 1));
+    const int ngroups = (a.nb + FAN_G - 1) / FAN_G;
+    const int64_t per_col = a.nviews * ngroups;
+    // lanes past the last group work on group 0 and write nothing: every lane of the wave
+    // takes part in the closing shuffles
+    const int64_t grp_raw = gid / FAN_Q;
+    const bool valid = grp_raw < per_col * a.ncols;
+    const int64_t grp = valid ? grp_raw : 0;
+    const int col = (int)(grp / per_col);
+    const int64_t rem = grp - (int64_t)col * per_col;
+    const int64_t v = rem / ngroups;
+    const int j0 = (int)(rem - v * ngroups) * FAN_G;
+    const int nj = min(FAN_G, a.nb - j0);     // bins of this group on the detector
     const int f = fan_frame(a.view_off, a.nframes, v);
     const float *x = a.src + ((int64_t)col * a.nframes + f) * a.nx * a.ny;
     double sn, cs;
@@ -223,19 +234,23 @@ __global__ __launch_bounds__(FAN_FWD_BLK) void fan_fwd_k(FanArgs a)
     const double R = a.R;
     const float d = (float)a.d;
     const float inv_ds = (float)(1.0 / a.ds);
-    const double e0 = fan_edge(a.s0, a.ds, j), e1 = fan_edge(a.s0, a.ds, j + 1);
+    double e[FAN_G + 1];
+#pragma unroll
+    for (int i = 0; i <= FAN_G; ++i) e[i] = fan_edge(a.s0, a.ds, j0 + i);
+    const double ea = e[0], eb = fan_edge(a.s0, a.ds, j0 + nj);
     // ray of detector coordinate s: direction u = s n + R t
-    const double em = 0.5 * (e0 + e1);
+    const double em = 0.5 * (ea + eb);
     const double uxm = em * cs - R * sn, uym = fma(em, sn, R * cs);
     const bool rows = fabs(uym) >= fabs(uxm);
-    const double ux0 = e0 * cs - R * sn, uy0 = fma(e0, sn, R * cs);
-    const double ux1 = e1 * cs - R * sn, uy1 = fma(e1, sn, R * cs);
+    const double uxa = ea * cs - R * sn, uya = fma(ea, sn, R * cs);
+    const double uxb = eb * cs - R * sn, uyb = fma(eb, sn, R * cs);
     // along the walked line: the crossing of an edge ray moves by k per unit across lines
-    const double k0 = rows ? ux0 / uy0 : uy0 / ux0;
-    const double k1 = rows ? ux1 / uy1 : uy1 / ux1;
-    const double slope = fmax(fabs(k0), fabs(k1));
-    // footprints reach the bin from pixel centres within d (1 + slope) of the crossings
-    const double reach = a.d * (1.1 + slope);
+    const double ka = rows ? uxa / uya : uya / uxa;
+    const double kb = rows ? uxb / uyb : uyb / uxb;
+    const double slope = fmax(fabs(ka), fabs(kb));
+    // a pixel's footprint spans (d/2)(1 + |slope of its own ray|) along the line; the window
+    // adds a tenth of it and a twentieth of a pixel for the curvature of the projection
+    const double reach = a.d * (0.6 + 0.6 * slope + 0.05);
     const double Sx = R * sn, Sy = -R * cs;
     const int nlines = rows ? a.ny : a.nx;
     const int nalong = rows ? a.nx : a.ny;
@@ -244,34 +259,56 @@ __global__ __launch_bounds__(FAN_FWD_BLK) void fan_fwd_k(FanArgs a)
     const double inv_d = 1.0 / a.d;
     FanLocal lc;
     FanDeriv dg;
-    double acc = 0.0;
-    for (int li = 0; li < nlines; ++li) {
+    double acc[FAN_G];
+#pragma unroll
+    for (int i = 0; i < FAN_G; ++i) acc[i] = 0.0;
+    for (int li = q; li < nlines; li += FAN_Q) {
         const double pl = fan_pix(o_line, a.d, li);
-        const double xa = fma(pl - S_line, k0, S_along), xb = fma(pl - S_line, k1, S_along);
+        const double xa = fma(pl - S_line, ka, S_along), xb = fma(pl - S_line, kb, S_along);
         const double lo = fmin(xa, xb) - reach, hi = fmax(xa, xb) + reach;
         // along-line indices with centres in [lo, hi]
         const double tlo = (lo - o_along) * inv_d - 0.5, thi = (hi - o_along) * inv_d - 0.5;
         if (!(thi >= 0.0 && tlo <= (double)(nalong - 1))) continue;   // also NaN
         const int klo = (int)ceil(fmax(tlo, 0.0));
         const int khi = (int)floor(fmin(thi, (double)(nalong - 1)));
-        for (int ka = klo; ka <= khi; ++ka) {
-            const int kx = rows ? ka : li, ly = rows ? li : ka;
+        for (int kk = klo; kk <= khi; ++kk) {
+            const int kx = rows ? kk : li, ly = rows ? li : kk;
             const float xv = x[(int64_t)ly * a.nx + kx];
             if (xv == 0.0f) continue;
-            const double pa = fan_pix(o_along, a.d, ka);
+            const double pa = fan_pix(o_along, a.d, kk);
             const double xc = rows ? pa : pl, yc = rows ? pl : pa;
             fan_local<DERIV>(xc, yc, cs, sn, R, d, inv_ds, lc, dg);
-            float w;
-            if (DERIV)
-                w = fan_dweight(fan_edge_terms(e1, lc, dg), fan_edge_terms(e0, lc, dg), dg) *
-                    inv_ds;
-            else
-                w = lc.scale * (fan_psi(fan_off(lc, e1), lc.wo, lc.wi, lc.fk) -
-                                fan_psi(fan_off(lc, e0), lc.wo, lc.wi, lc.fk));
-            acc = fma((double)xv, (double)w, acc);
+            const double xd = (double)xv;
+            if (DERIV) {
+                FanEdge tp = fan_edge_terms(e[0], lc, dg);
+#pragma unroll
+                for (int i = 0; i < FAN_G; ++i) {
+                    const FanEdge tn = fan_edge_terms(e[i + 1], lc, dg);
+                    acc[i] = fma(xd, (double)(fan_dweight(tn, tp, dg) * inv_ds), acc[i]);
+                    tp = tn;
+                }
+            } else {
+                float pp = fan_psi(fan_off(lc, e[0]), lc.wo, lc.wi, lc.fk);
+#pragma unroll
+                for (int i = 0; i < FAN_G; ++i) {
+                    const float pn = fan_psi(fan_off(lc, e[i + 1]), lc.wo, lc.wi, lc.fk);
+                    acc[i] = fma(xd, (double)(lc.scale * (pn - pp)), acc[i]);
+                    pp = pn;
+                }
+            }
         }
     }
-    a.dst[gid] = (float)acc;
+    // the four lanes' partial sums: a butterfly (commutative additions, the same bits in
+    // every lane of the group), then lane q writes bin j0 + q
+    double out = 0.0;
+#pragma unroll
+    for (int i = 0; i < FAN_G; ++i) {
+        double t = acc[i];
+        t += __shfl_xor(t, 1, 64);
+        t += __shfl_xor(t, 2, 64);
+        if (i == q) out = t;
+    }
+    if (valid && q < nj) a.dst[((int64_t)col * a.nviews + v) * a.nb + j0 + q] = (float)out;
 }
 
 // ---------------------------------------------------------------------------
@@ -400,7 +437,8 @@ int launch_fan(const nlrmm_geom &g, const nlrmm_batch &b, int ncols, double R, i
 {
     const FanArgs a = fan_args(g, b, ncols, R, theta, src, dst);
     if (!transpose) {
-        const int64_t n = (int64_t)ncols * b.nviews * g.nbins;
+        const int64_t ngroups = (g.nbins + FAN_G - 1) / FAN_G;
+        const int64_t n = (int64_t)ncols * b.nviews * ngroups * FAN_Q;
         const unsigned blocks = (unsigned)((n + FAN_FWD_BLK - 1) / FAN_FWD_BLK);
         if (deriv)
             fan_fwd_k<true><<<blocks, FAN_FWD_BLK, 0, s>>>(a);
