@@ -44,6 +44,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [
                        [--no-workloads]
        python bench.py --ops-only     (operators and a copy calibration only, for counters)
        python bench.py --streaming-only --steps K   (K blocks of the streaming workload only)
+       python bench.py --dynamic-only --steps K --warmup W   (the 32-frame dynamic leg only)
 """
 import argparse
 import hashlib
@@ -81,6 +82,8 @@ def parse():
                          "autograd, precision policy, streaming and the sensitivity solve")
     ap.add_argument("--ops-only", action="store_true",
                     help="only the operator timings and the copy calibration")
+    ap.add_argument("--dynamic-only", action="store_true",
+                    help="only the 32-frame dynamic leg (plain, batched, optical flow)")
     ap.add_argument("--streaming-only", action="store_true",
                     help="only the streaming block timing (for a kernel trace of one block)")
     ap.add_argument("--gram-only", action="store_true",
@@ -639,6 +642,13 @@ def main():
     import torch
     from paper_2605_06336_amd import metrics, ops, synth
     from paper_2605_06336_amd.solver import Config, OuterGraph, Solver
+
+    if args.dynamic_only:
+        print(json.dumps({"dynamic_only": True,
+                          "batched_vs_plain": dynamic_leg(torch, ops, synth, Config, OuterGraph,
+                                                          Solver, args.steps, args.warmup,
+                                                          args.gram_precision)}), flush=True)
+        return
 
     if args.streaming_only:
         print(json.dumps({"streaming_only": True,

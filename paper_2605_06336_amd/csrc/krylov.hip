@@ -237,7 +237,8 @@ __device__ __forceinline__ short bf16_rne(float f)
 }
 
 // G_Psi = (sqrt(w) Psi V)^T (sqrt(w) Psi V) on the matrix cores.  A chunk of MP pixels gives
-// KIND * MP rows (the weighted differences of every column) staged column-major in LDS; each
+// KIND * MP rows (the weighted differences of every column, all dx rows of the chunk, then all
+// dy rows, ...) staged column-major in LDS; each
 // wave multiplies one 32 x 32 tile of the (at most 64 x 64) Gram over the chunk's rows with
 // FP32 accumulation, flushed to FP64 per chunk.  Only tiles on or above the diagonal are
 // formed: for ell <= 32 the four waves split the rows of the single tile, otherwise waves
@@ -342,20 +343,22 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
             for (int u = 0; u < 4; ++u) {
                 const int c = c0 + u * (BLK / 64);
                 if (stage && c < ell) {
-                    Elem *col = &sB[c][KIND * pc];
+                    // kind-major rows (row = kind * mp + pixel): consecutive lanes write
+                    // consecutive LDS words
+                    Elem *col = &sB[c][pc];
                     const float d0 = w0 * (x1[u] - x0[u]), d1 = w1 * (x2[u] - x0[u]);
                     const float d2 = motion ? w2 * (x0[u] - m0[u]) : w2 * (x3[u] - x0[u]);
                     const float d3 = w3 * (x3[u] - m1[u]);
                     if constexpr (BF16) {
                         col[0] = bf16_rne(d0);
-                        col[1] = bf16_rne(d1);
-                        if (KIND >= 3) col[2] = bf16_rne(d2);
-                        if (motion) col[3] = bf16_rne(d3);
+                        col[mp] = bf16_rne(d1);
+                        if (KIND >= 3) col[2 * mp] = bf16_rne(d2);
+                        if (motion) col[3 * mp] = bf16_rne(d3);
                     } else {
                         col[0] = d0;
-                        col[1] = d1;
-                        if (KIND >= 3) col[2] = d2;
-                        if (motion) col[3] = d3;
+                        col[mp] = d1;
+                        if (KIND >= 3) col[2 * mp] = d2;
+                        if (motion) col[3 * mp] = d3;
                     }
                 }
             }
