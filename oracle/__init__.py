@@ -13,4 +13,6 @@ Contents
                   variable projection, streaming and dynamic drivers.
   optical_flow.py FP64 optical-flow regulariser: velocity estimation per frame pair,
                   bilinear warps, the motion rows of the dynamic operator Theta.
+  pat.py          FP64 photoacoustic circular-means operator with a global radial shift,
+                  its transpose and its derivative in the shift.
 """
