@@ -266,6 +266,41 @@ int nlrmm_fan_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom,
                                  const double *theta, double R, float *x, void *stream);
 
 /* ------------------------------------------------------------------------------------
+ * Photoacoustic circular-means family (Section 6.3, "Photoacoustic Tomography with Sensor
+ * Radius Uncertainty": circles of radii r_j(p) = r_j + p around every sensor, one global
+ * radial shift p).  The paper leaves the operator to its toolbox; the library's model:
+ * n_sensors sensors at angles 2 pi a / n_sensors on the circle of radius sensor_radius around
+ * the image origin; radii r_j(p) = (j + 1) radius_step + p (radius_step = 2 / n_radii gives
+ * the paper's r_j = 2 j / n_c); between pixel centres the image is its bilinear interpolant
+ * (0 for indices outside the grid) and a circle integral is the n_samples-point trapezoid
+ * rule:
+ *   y[a][j] = (2 pi r / K) sum_k I(s_a + r (cos, sin)(2 pi k / K)),   K = n_samples.
+ * The derivative in p is that of the sum, (2 pi / K) sum_k [I + r grad I . e_k].  Sample
+ * positions, cells and weights FP64, pixel values FP32, sums FP64; deterministic (the
+ * transpose is a gather).  Layouts: x [ncols][ny][nx] float32, y [ncols][n_sensors][n_radii]
+ * float32; p a host double.  Limits: n_samples <= 8192, ncols * n_sensors * n_radii <= 2^26
+ * (NLRMM_ESHAPE); a non-finite p or radius, a negative sensor radius or a radius step <= 0
+ * gives NLRMM_EINVAL.
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_sensors, n_radii, n_samples;
+    double sensor_radius, radius_step;
+} nlrmm_pat_geom;
+
+/* y = A_pat(p) x: the circle integrals of every column. */
+int nlrmm_pat_project(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_pat_geom *pat,
+                      int32_t ncols, const float *x, double p, float *y, void *stream);
+
+/* dy = d(A_pat(p) x)/dp: the Jacobian column of the global radial shift (Alg.
+ * "update_param" with one parameter). */
+int nlrmm_pat_project_dp(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_pat_geom *pat,
+                         int32_t ncols, const float *x, double p, float *dy, void *stream);
+
+/* x = A_pat(p)^T y, the transpose of nlrmm_pat_project (up to FP32 rounding of the inputs). */
+int nlrmm_pat_backproject(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_pat_geom *pat,
+                          int32_t ncols, const float *y, double p, float *x, void *stream);
+
+/* ------------------------------------------------------------------------------------
  * Krylov side of MM-GKS / RMM-GKS (Section 3; supplementary Algs. "enlarge", "compress").
  * Basis blocks are column-contiguous FP32: V [ncols][n] with n = nframes*ny*nx, and
  * A V [ncols][m] with m = nviews*nbins.  Grams are FP64 row-major with leading dim ldg.

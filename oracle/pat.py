@@ -16,7 +16,9 @@ Readings where the paper leaves the operator to its toolbox (listed in the desig
     the image);
   * a circle integral is the K-point trapezoid rule, K the same for every circle:
     y[a][j] = (2 pi r / K) sum_k I(x_a + r (cos psi_k, sin psi_k)), psi_k = 2 pi k / K,
-    r = r_j(p);
+    r = r_j(p); a shift that takes r below zero is used as it stands (the circle of radius
+    |r| traced from the opposite side, with the negative factor r), which keeps the operator
+    smooth in p through r = 0;
   * its derivative in p is the derivative of that sum, (2 pi / K) sum_k [I + r grad I . e_k]
     with e_k = (cos psi_k, sin psi_k) and grad I the gradient of the bilinear interpolant of
     the sample's cell.

@@ -37,6 +37,12 @@ _GP = ctypes.POINTER(Geom)
 _BP = ctypes.POINTER(Batch)
 
 
+class PatGeom(ctypes.Structure):
+    _fields_ = [("n_sensors", ctypes.c_int32), ("n_radii", ctypes.c_int32),
+                ("n_samples", ctypes.c_int32), ("sensor_radius", ctypes.c_double),
+                ("radius_step", ctypes.c_double)]
+
+
 class SolverCfg(ctypes.Structure):
     _fields_ = [("kmin", ctypes.c_int32), ("kmax", ctypes.c_int32), ("solves", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("tau", ctypes.c_double), ("lam_fix", ctypes.c_double),
@@ -74,6 +80,11 @@ SIGNATURES = {
     "nlrmm_theta_weights": [_P, _GP, _I32, _I32, _P, _P, ctypes.c_double, _P, _P],
     "nlrmm_theta_grad_add": [_P, _GP, _I32, _I32, _P, _P, _P, ctypes.c_double, _P, _P, _P],
     "nlrmm_gram_theta": [_P, _GP, _I32, _I32, _P, _I32, _P, _P, _P, _I32, _I32, _P],
+    "nlrmm_pat_project": [_P, _GP, ctypes.POINTER(PatGeom), _I32, _P, ctypes.c_double, _P, _P],
+    "nlrmm_pat_project_dp": [_P, _GP, ctypes.POINTER(PatGeom), _I32, _P, ctypes.c_double, _P,
+                             _P],
+    "nlrmm_pat_backproject": [_P, _GP, ctypes.POINTER(PatGeom), _I32, _P, ctypes.c_double, _P,
+                              _P],
     "nlrmm_fan_project": [_P, _GP, _BP, _I32, _P, _P, ctypes.c_double, _P, _P],
     "nlrmm_fan_backproject": [_P, _GP, _BP, _I32, _P, _P, ctypes.c_double, _P, _P],
     "nlrmm_fan_project_dtheta": [_P, _GP, _BP, _I32, _P, _P, ctypes.c_double, _P, _P],

@@ -17,7 +17,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnlrmm.so")
 SOURCES = ["api.cpp", "proj.hip", "krylov.hip", "solve_reg_a.hip", "solve_reg_b.hip",
            "solve_reg_c.hip", "solve_reg_d.hip", "solve_reg_e.hip", "solve_reg_f.hip",
-           "gn.hip", "varpro.hip", "solver.cpp", "tune.cpp", "noalloc.hip", "fan.hip", "of.hip"]
+           "gn.hip", "varpro.hip", "solver.cpp", "tune.cpp", "noalloc.hip", "fan.hip", "of.hip", "pat.hip"]
 ARCH = os.environ.get("NLRMM_ARCH", "gfx950")
 
 FLAGS = [

@@ -282,6 +282,35 @@ int nlrmm_fan_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom,
     return fan_call(ctx, geom, batch, ncols, r, theta, R, x, 1, 1, stream);
 }
 
+static int pat_call(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_pat_geom *pat,
+                    int32_t ncols, const float *src, double p, float *dst, int mode, void *stream)
+{
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if (!ctx || !pat || !src || !dst) return NLRMM_EINVAL;
+    if ((rc = pat_check(*geom, *pat, ncols, p))) return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess) return NLRMM_EHIP;
+    return launch_pat(*geom, *pat, ncols, p, mode, src, dst, (hipStream_t)stream);
+}
+
+int nlrmm_pat_project(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_pat_geom *pat,
+                      int32_t ncols, const float *x, double p, float *y, void *stream)
+{
+    return pat_call(ctx, geom, pat, ncols, x, p, y, 0, stream);
+}
+
+int nlrmm_pat_project_dp(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_pat_geom *pat,
+                         int32_t ncols, const float *x, double p, float *dy, void *stream)
+{
+    return pat_call(ctx, geom, pat, ncols, x, p, dy, 1, stream);
+}
+
+int nlrmm_pat_backproject(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_pat_geom *pat,
+                          int32_t ncols, const float *y, double p, float *x, void *stream)
+{
+    return pat_call(ctx, geom, pat, ncols, y, p, x, 2, stream);
+}
+
 int nlrmm_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom *geom, const nlrmm_batch *batch,
                              int32_t ncols, const float *r, const double *theta, float *x,
                              void *stream)

@@ -154,6 +154,12 @@ double fan_min_distance(const nlrmm_geom &g);
 int launch_fan(const nlrmm_geom &g, const nlrmm_batch &b, int ncols, double R, int deriv,
                int transpose, const double *theta, const float *src, float *dst, hipStream_t s);
 
+// Photoacoustic circular-means family (pat.hip): host limits and the launcher (mode 0
+// projection, 1 derivative in p, 2 transpose).
+int pat_check(const nlrmm_geom &g, const nlrmm_pat_geom &pg, int ncols, double p);
+int launch_pat(const nlrmm_geom &g, const nlrmm_pat_geom &pg, int ncols, double p, int mode,
+               const float *src, float *dst, hipStream_t s);
+
 }  // namespace nlrmm
 
 #define NLRMM_HIP_CHECK(expr)                       \

@@ -12,7 +12,7 @@ from typing import Optional
 import torch
 
 from . import _lib
-from ._lib import Batch, Geom, check
+from ._lib import Batch, Geom, PatGeom, check
 
 _ctx = {}
 
@@ -196,6 +196,54 @@ def fan_backproject_dtheta(r: torch.Tensor, theta: torch.Tensor, g: Geom, R: flo
                            frames=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Transpose of ``fan_project_dtheta`` (nlrmm_fan_backproject_dtheta)."""
     return _fan_transpose("nlrmm_fan_backproject_dtheta", r, theta, g, R, frames, out)
+
+
+def pat_geom(n_sensors: int, n_radii: int, n_samples: int, sensor_radius: float = 1.5,
+             radius_step: Optional[float] = None) -> PatGeom:
+    """Circular-means geometry: radii (j + 1) radius_step + p (default step 2 / n_radii)."""
+    return PatGeom(n_sensors=n_sensors, n_radii=n_radii, n_samples=n_samples,
+                   sensor_radius=sensor_radius,
+                   radius_step=2.0 / n_radii if radius_step is None else radius_step)
+
+
+def _pat(name, src, g, pg, p, out, out_shape):
+    _need(src, torch.float32, "input")
+    if out is None:
+        out = torch.empty(out_shape, dtype=torch.float32, device=src.device)
+    _need(out, torch.float32, "out")
+    ncols = out_shape[0]
+    check(getattr(_lib.lib(), name)(context(src.device.index or 0), ctypes.byref(g),
+                                    ctypes.byref(pg), ncols, src.data_ptr(), float(p),
+                                    out.data_ptr(), _stream(src.device)), name)
+    return out
+
+
+def pat_project(x: torch.Tensor, g: Geom, pg: PatGeom, p: float,
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Circle integrals y = A_pat(p) x: x [..., ny, nx] -> [ncols, n_sensors, n_radii]."""
+    ncols = x.numel() // (g.nx * g.ny)
+    if x.numel() != ncols * g.nx * g.ny:
+        raise ValueError("x size is not a multiple of ny*nx")
+    return _pat("nlrmm_pat_project", x, g, pg, p, out, (ncols, pg.n_sensors, pg.n_radii))
+
+
+def pat_project_dp(x: torch.Tensor, g: Geom, pg: PatGeom, p: float,
+                   out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """d(A_pat(p) x)/dp, same shapes as ``pat_project``."""
+    ncols = x.numel() // (g.nx * g.ny)
+    if x.numel() != ncols * g.nx * g.ny:
+        raise ValueError("x size is not a multiple of ny*nx")
+    return _pat("nlrmm_pat_project_dp", x, g, pg, p, out, (ncols, pg.n_sensors, pg.n_radii))
+
+
+def pat_backproject(y: torch.Tensor, g: Geom, pg: PatGeom, p: float,
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """x = A_pat(p)^T y: y [..., n_sensors, n_radii] -> [ncols, ny, nx]."""
+    per = pg.n_sensors * pg.n_radii
+    ncols = y.numel() // per
+    if y.numel() != ncols * per:
+        raise ValueError("y size is not a multiple of n_sensors*n_radii")
+    return _pat("nlrmm_pat_backproject", y, g, pg, p, out, (ncols, g.ny, g.nx))
 
 
 def backproject_noalloc(y: torch.Tensor, theta: torch.Tensor, g: Geom, frames=None,

@@ -60,6 +60,12 @@ def test_host_validation_without_device():
         # the geometry is checked first, then pointers, the source distance and the batch
         g0 = _lib.Geom(nx=0, ny=8, x0=-1, y0=-1, d=0.25, nbins=13, s0=-1.42, ds=0.2)
         assert fn(None, ctypes.byref(g0), ctypes.byref(b), 1, 1, 1, 4.0, 1, None) == -2
+    # the photoacoustic family: null context or geometry
+    pg = _lib.PatGeom(n_sensors=4, n_radii=5, n_samples=64, sensor_radius=1.5, radius_step=0.4)
+    for name in ("nlrmm_pat_project", "nlrmm_pat_project_dp", "nlrmm_pat_backproject"):
+        fn = getattr(lib, name)
+        assert fn(None, ctypes.byref(g), ctypes.byref(pg), 1, 1, 0.1, 1, None) == -1
+        assert fn(None, ctypes.byref(g), None, 1, 1, 0.1, 1, None) == -1
     # the optical-flow family: null context, then a temporal mode it does not know
     assert lib.nlrmm_of_estimate(None, ctypes.byref(g), 3, 1, 0.05, 1e-3, 10, 1, None) == -1
     assert lib.nlrmm_theta_apply(None, ctypes.byref(g), 3, 2, 1, 1, 1, None) == -1
