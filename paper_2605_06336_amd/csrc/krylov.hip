@@ -214,6 +214,27 @@ __global__ __launch_bounds__(BLK) void gram_psi_k(const float *__restrict__ V, i
     }
 }
 
+// The reduction of reduce_vec_k's Gram-column mode (below) run by wave 0 of the first blocks
+// of another launch (the job's outputs need no launch of their own): same order, same values.
+__device__ __forceinline__ void side_reduce(const SideReduce &j)
+{
+    if (j.part == nullptr || threadIdx.x >= 64) return;
+    for (int i = blockIdx.x; i < j.nout; i += gridDim.x) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < j.nblk; b += 64) a += j.part[(int64_t)b * j.nout + i];
+        a = wave_sum(a);
+        if (threadIdx.x == 0) {
+            const int ell = j.nout - 2;
+            if (i <= ell) {
+                j.G[i * j.ldg + ell] = a;
+                j.G[ell * j.ldg + i] = a;
+            } else {
+                j.rb[ell] = a;
+            }
+        }
+    }
+}
+
 // MFMA variant of the weighted regulariser Gram (B^T B with B = sqrt(w) * Psi V, B of
 // up to 192 rows per 64-pixel chunk and <= 64 columns).  The chunk's rows are staged in
 // LDS as FP32; each of the four waves owns one 32x32 tile of the (padded) 64x64 result and
@@ -250,8 +271,11 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
                                                        int nx, int ny, int F, int temporal,
                                                        double *__restrict__ part,
                                                        const float *__restrict__ u, float e2,
-                                                       const float *__restrict__ flow)
+                                                       const float *__restrict__ flow,
+                                                       float *__restrict__ wout,
+                                                       SideReduce side)
 {
+    side_reduce(side);
     // the chunk's weighted differences, column-major: FP32, or BF16 rounded once at staging
     // (four consecutive rows of a column are then one 8-byte MFMA operand)
     using Elem = typename std::conditional<BF16, short, float>::type;
@@ -293,21 +317,29 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
         if (stage && i < ntot) {
             const int64_t f = i / npix, p = i - f * npix;
             const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
-            // weights stored in w, or formed from u (the same values)
+            // weights stored in w, or formed from u (the same values) and then, when wout is
+            // given, stored there by wave 0 (each weight belongs to one pixel of one chunk)
             const float uc = u != nullptr ? u[i] : 0.0f;
+            const bool put = wout != nullptr && u != nullptr && wv == 0;
             if (k < nx - 1) {
-                w0 = sqrtf(u != nullptr ? tv_weight(u[i + 1] - uc, e2)
-                                        : w[f * g.per_frame + (int64_t)l * (nx - 1) + k]);
+                const int64_t at = f * g.per_frame + (int64_t)l * (nx - 1) + k;
+                const float wr = u != nullptr ? tv_weight(u[i + 1] - uc, e2) : w[at];
+                if (put) wout[at] = wr;
+                w0 = sqrtf(wr);
                 ox = 1;
             }
             if (l < ny - 1) {
-                w1 = sqrtf(u != nullptr ? tv_weight(u[i + nx] - uc, e2)
-                                        : w[f * g.per_frame + g.dy_off + (int64_t)l * nx + k]);
+                const int64_t at = f * g.per_frame + g.dy_off + (int64_t)l * nx + k;
+                const float wr = u != nullptr ? tv_weight(u[i + nx] - uc, e2) : w[at];
+                if (put) wout[at] = wr;
+                w1 = sqrtf(wr);
                 oy = nx;
             }
             if (g.temporal == TEMPORAL_DIFF && f < F - 1) {
-                w2 = sqrtf(u != nullptr ? tv_weight(u[i + npix] - uc, e2)
-                                        : w[g.t_off + f * npix + p]);
+                const int64_t at = g.t_off + f * npix + p;
+                const float wr = u != nullptr ? tv_weight(u[i + npix] - uc, e2) : w[at];
+                if (put) wout[at] = wr;
+                w2 = sqrtf(wr);
                 ot = npix;
             }
             if (motion && f < F - 1) {
@@ -317,10 +349,17 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
                 fo = (f + 1) * npix;
                 ro = f * npix;
                 ot = npix;
-                w2 = sqrtf(u != nullptr ? tv_weight(uc - of_sample(u + fo, cf, nx), e2)
-                                        : w[g.t_off + f * npix + p]);
-                w3 = sqrtf(u != nullptr ? tv_weight(u[i + npix] - of_sample(u + ro, cr, nx), e2)
-                                        : w[g.t_off + (F - 1 + f) * npix + p]);
+                const int64_t at2 = g.t_off + f * npix + p, at3 = g.t_off + (F - 1 + f) * npix + p;
+                const float wr2 =
+                    u != nullptr ? tv_weight(uc - of_sample(u + fo, cf, nx), e2) : w[at2];
+                const float wr3 =
+                    u != nullptr ? tv_weight(u[i + npix] - of_sample(u + ro, cr, nx), e2) : w[at3];
+                if (put) {
+                    wout[at2] = wr2;
+                    wout[at3] = wr3;
+                }
+                w2 = sqrtf(wr2);
+                w3 = sqrtf(wr3);
             }
         }
         // four columns per step, all their loads issued before any use
@@ -569,6 +608,208 @@ __global__ __launch_bounds__(64) void reduce_vec_k(const double *__restrict__ pa
         } else {
             rb[ell] = s;
         }
+    }
+}
+
+// The sums of reduce_vec_k formed inside a consumer block, so that a multidot's partials
+// need no launch of their own: acc[i][L] = part[L][i] + part[L + 64][i] + ... in that order
+// (the lane accumulators of reduce_vec_k, all (i, L) pairs spread over the block's threads,
+// consecutive threads on consecutive partials), then each output's 64 accumulators joined
+// by the same butterfly.  The results equal reduce_vec_k's bitwise.  sbuf holds
+// MD_MAX * 64 doubles, sh receives the nout sums; ends with a barrier.
+constexpr int RR_MAXBLK = 512;   // producer blocks a consumer re-reduces (<= 8 per lane)
+
+// K: partials per lane accumulator (nblk <= 64 K); U pairs per thread per round, so that
+// 36 loads are in flight at once (one round of memory latency for up to 36 outputs at K = 4)
+template <int K>
+__device__ void rereduce_k(const double *__restrict__ part, int nblk, int nout, double *sbuf,
+                           double *sh)
+{
+    constexpr int U = 36 / K;
+    const int tid = threadIdx.x;
+    const int npair = nout * 64;
+    for (int q0 = 0; q0 < npair; q0 += BLK * U) {
+        double v[U][K];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = q0 + u * BLK + tid;
+            const int L = q / nout, i = q - L * nout;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int b = L + 64 * k;
+                v[u][k] = (q < npair && b < nblk) ? part[(int64_t)b * nout + i] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = q0 + u * BLK + tid;
+            if (q < npair) {
+                const int L = q / nout, i = q - L * nout;
+                double a = 0.0;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (L + 64 * k < nblk) a += v[u][k];
+                sbuf[i * 64 + L] = a;
+            }
+        }
+    }
+    __syncthreads();
+    const int lane = tid & 63;
+    for (int i = tid >> 6; i < nout; i += BLK / 64) {
+        const double a = wave_sum(sbuf[i * 64 + lane]);
+        if (lane == 0) sh[i] = a;
+    }
+    __syncthreads();
+}
+
+__device__ void rereduce(const double *__restrict__ part, int nblk, int nout, double *sbuf,
+                         double *sh)
+{
+    if (nblk <= 256)
+        rereduce_k<4>(part, nblk, nout, sbuf, sh);
+    else
+        rereduce_k<8>(part, nblk, nout, sbuf, sh);
+}
+
+// First correction of CGS2 fused with the second pass's products (Alg. "enlarge":
+// reorthogonalisation of the new direction).  h = X^T r and ||r||^2 are re-reduced from the
+// partials of the multidot that precedes (pin, nin blocks, nv + 1 outputs; block 0 stores
+// them in hout), r <- r - X h exactly as gemv_k computes it, then the partials of X^T r
+// exactly as multidot_k(X, r) forms them with the same grid (pout[block][i], i < nv).  Every
+// element of r is rewritten and read back by the same thread, so no grid-wide order is
+// needed.
+__global__ __launch_bounds__(BLK) void gemv_multidot_k(const float *__restrict__ X, int64_t ldx,
+                                                       int nv, float *r, int64_t n,
+                                                       const double *__restrict__ pin, int nin,
+                                                       double *__restrict__ pout,
+                                                       double *__restrict__ hout)
+{
+    constexpr int GRP = 16;
+    __shared__ double sbuf[MD_MAX * 64];
+    __shared__ double sh[MD_MAX];
+    const int tid = threadIdx.x;
+    rereduce(pin, nin, nv + 1, sbuf, sh);
+    if (blockIdx.x == 0 && tid <= nv) hout[tid] = sh[tid];
+    double(*sacc)[BLK] = reinterpret_cast<double(*)[BLK]>(sbuf);   // GRP x BLK, free now
+    auto block_reduce = [&](int i0, const double (&acc)[GRP]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int a = 0; a < GRP; ++a) sacc[a][tid] = acc[a];
+        __syncthreads();
+        constexpr int TPO = BLK / GRP;
+        const int a = tid / TPO, l = tid % TPO;
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < BLK / TPO; ++k) t += sacc[a][l + TPO * k];
+        for (int off = TPO / 2; off > 0; off >>= 1) t += __shfl_xor(t, off, TPO);
+        if (l == 0 && i0 + a < nv) pout[(int64_t)blockIdx.x * nv + i0 + a] = t;
+        __syncthreads();
+    };
+    if ((int64_t)gridDim.x * BLK >= n) {
+        const int64_t e = (int64_t)blockIdx.x * BLK + tid;
+        const bool in = e < n;
+        float xv[MD_MAX];
+#pragma unroll
+        for (int i = 0; i < MD_MAX; ++i) xv[i] = (i < nv && in) ? X[(int64_t)i * ldx + e] : 0.0f;
+        double sg = 0.0;
+#pragma unroll
+        for (int i = 0; i < MD_MAX; ++i)
+            if (i < nv) sg = fma((double)xv[i], sh[i], sg);
+        float ye = 0.0f;
+        if (in) {
+            ye = (float)(-1.0 * sg + 1.0 * (double)r[e]);
+            r[e] = ye;
+        }
+#pragma unroll
+        for (int i0 = 0; i0 < MD_MAX; i0 += GRP) {
+            if (i0 < nv) {
+                double acc[GRP];
+#pragma unroll
+                for (int a = 0; a < GRP; ++a) acc[a] = (double)xv[i0 + a] * (double)ye;
+                block_reduce(i0, acc);
+            }
+        }
+        return;
+    }
+    // several elements per thread: the correction first, over exactly the elements (and with
+    // the layout) that multidot_k gives this thread, then multidot_k's loops on the result
+    const bool vec4 = (ldx % 4) == 0 && (n % 4) == 0 &&
+                      (reinterpret_cast<uintptr_t>(X) % 16) == 0 &&
+                      (reinterpret_cast<uintptr_t>(r) % 16) == 0;
+    const int64_t per = vec4 ? 4 : 1, ne = vec4 ? n / 4 : n;
+    for (int64_t q = (int64_t)blockIdx.x * BLK + tid; q < ne; q += (int64_t)gridDim.x * BLK) {
+        for (int64_t e = q * per; e < q * per + per; ++e) {
+            double sg = 0.0;
+            for (int i = 0; i < nv; ++i) sg = fma((double)X[(int64_t)i * ldx + e], sh[i], sg);
+            r[e] = (float)(-1.0 * sg + 1.0 * (double)r[e]);
+        }
+    }
+    for (int i0 = 0; i0 < nv; i0 += GRP) {
+        double acc[GRP];
+#pragma unroll
+        for (int a = 0; a < GRP; ++a) acc[a] = 0.0;
+        if (vec4) {
+            const int64_t ld4 = ldx / 4;
+            const float4 *X4 = reinterpret_cast<const float4 *>(X);
+            const float4 *y4 = reinterpret_cast<const float4 *>(r);
+            for (int64_t e = (int64_t)blockIdx.x * BLK + tid; e < ne;
+                 e += (int64_t)gridDim.x * BLK) {
+                const float4 yv = y4[e];
+#pragma unroll
+                for (int a = 0; a < GRP; ++a) {
+                    const int i = i0 + a;
+                    float4 xv = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (i < nv) xv = X4[(int64_t)i * ld4 + e];
+                    double t = acc[a];
+                    t = fma((double)xv.x, (double)yv.x, t);
+                    t = fma((double)xv.y, (double)yv.y, t);
+                    t = fma((double)xv.z, (double)yv.z, t);
+                    acc[a] = fma((double)xv.w, (double)yv.w, t);
+                }
+            }
+        } else {
+            for (int64_t e = (int64_t)blockIdx.x * BLK + tid; e < n;
+                 e += (int64_t)gridDim.x * BLK) {
+                const double ye = (double)r[e];
+#pragma unroll
+                for (int a = 0; a < GRP; ++a) {
+                    const int i = i0 + a;
+                    if (i < nv) acc[a] = fma((double)X[(int64_t)i * ldx + e], ye, acc[a]);
+                }
+            }
+        }
+        block_reduce(i0, acc);
+    }
+}
+
+// Second correction of CGS2 with its norm: h2 re-reduced from the partials of
+// gemv_multidot_k (block 0 stores it in hout), then gemv_norm_k's work.
+__global__ __launch_bounds__(BLK) void gemv_norm_red_k(const float *__restrict__ X, int64_t ldx,
+                                                       int nv, float *r, int64_t n,
+                                                       const double *__restrict__ pin, int nin,
+                                                       double *__restrict__ hout,
+                                                       double *__restrict__ part)
+{
+    __shared__ double sbuf[MD_MAX * 64];
+    __shared__ double sh[MD_MAX];
+    __shared__ double sw[BLK / 64];
+    rereduce(pin, nin, nv, sbuf, sh);
+    if (blockIdx.x == 0 && (int)threadIdx.x < nv) hout[threadIdx.x] = sh[threadIdx.x];
+    double q = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * BLK + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * BLK) {
+        double sg = 0.0;
+        for (int i = 0; i < nv; ++i) sg = fma((double)X[(int64_t)i * ldx + e], sh[i], sg);
+        const float o = (float)(-1.0 * sg + 1.0 * (double)r[e]);
+        r[e] = o;
+        q = fma((double)o, (double)o, q);
+    }
+    q = wave_sum(q);
+    if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < BLK / 64; ++w) t += sw[w];
+        part[blockIdx.x] = t;
     }
 }
 
@@ -1550,31 +1791,45 @@ int k_tv_grad_add(const float *u, const float *w, int nx, int ny, int F, int tem
 
 int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int ny, int F,
                int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s, int mode,
-               const float *u, float eps, const float *flow)
+               const float *u, float eps, const float *flow, float *wout, const SideReduce *side)
 {
     if (ell > GMAX) return NLRMM_ESHAPE;
-    if (w == nullptr && (u == nullptr || mode == 0)) return NLRMM_EINVAL;
+    if (w == nullptr && u == nullptr) return NLRMM_EINVAL;
     if (temporal == TEMPORAL_OF && F > 1 && (flow == nullptr || nx < 2 || ny < 2))
         return NLRMM_EINVAL;
     const float e2 = eps * eps;
     const bool motion = temporal == TEMPORAL_OF && F > 1;
-    const float *ww = w ? nullptr : u;
-    if (mode == 1 && motion)
-        gram_psi_mfma_k<false, true><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F,
-                                                                    temporal, part, ww, e2, flow);
-    else if (mode == 1)
-        gram_psi_mfma_k<false, false><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F,
-                                                                     temporal, part, ww, e2,
-                                                                     flow);
-    else if (mode == 2 && motion)
-        gram_psi_mfma_k<true, true><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F,
-                                                                   temporal, part, ww, e2, flow);
-    else if (mode == 2)
-        gram_psi_mfma_k<true, false><<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F,
-                                                                    temporal, part, ww, e2, flow);
-    else
+    SideReduce sj{};
+    if (side != nullptr) sj = *side;
+    if (mode == 0) {
+        // the FP64 kernel takes stored weights and no side job: both run as launches first
+        if (sj.part != nullptr)
+            reduce_vec_k<<<(unsigned)sj.nout, 64, 0, s>>>(sj.part, sj.nblk, sj.nout, nullptr, 0,
+                                                          nullptr, sj.G, sj.ldg, sj.rb);
+        if (w == nullptr) {
+            if (wout == nullptr) return NLRMM_EINVAL;
+            const int rc = k_psi_weights(u, nx, ny, F, temporal, eps, wout, s, flow);
+            if (rc) return rc;
+            w = wout;
+        }
         gram_psi_k<<<(unsigned)nblk, BLK, 0, s>>>(V, ldv, ell, w, nx, ny, F, temporal, part,
                                                   flow);
+    } else {
+        const float *ww = w ? nullptr : u;
+        float *wo = w ? nullptr : wout;
+        if (mode == 1 && motion)
+            gram_psi_mfma_k<false, true><<<(unsigned)nblk, BLK, 0, s>>>(
+                V, ldv, ell, w, nx, ny, F, temporal, part, ww, e2, flow, wo, sj);
+        else if (mode == 1)
+            gram_psi_mfma_k<false, false><<<(unsigned)nblk, BLK, 0, s>>>(
+                V, ldv, ell, w, nx, ny, F, temporal, part, ww, e2, flow, wo, sj);
+        else if (mode == 2 && motion)
+            gram_psi_mfma_k<true, true><<<(unsigned)nblk, BLK, 0, s>>>(
+                V, ldv, ell, w, nx, ny, F, temporal, part, ww, e2, flow, wo, sj);
+        else
+            gram_psi_mfma_k<true, false><<<(unsigned)nblk, BLK, 0, s>>>(
+                V, ldv, ell, w, nx, ny, F, temporal, part, ww, e2, flow, wo, sj);
+    }
     reduce_gram_k<<<(unsigned)(ell * ell), 64, 0, s>>>(part, nblk, ell, G, ldg);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
@@ -1606,6 +1861,46 @@ int k_multidot_gram_col(const float *X, int64_t ldx, int ell, const float *xnew,
     multidot_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, ell + 1, xnew, b, n, part, nullptr);
     reduce_vec_k<<<(unsigned)nout, 64, 0, s>>>(part, (int)g, nout, nullptr, 0, nullptr, G, ldg,
                                                rb);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_multidot_gram_col_deferred(const float *X, int64_t ldx, int ell, const float *xnew,
+                                 const float *b, int64_t n, double *part, int nblk, double *G,
+                                 int ldg, double *rb, SideReduce *job, hipStream_t s)
+{
+    const int nout = ell + 2;
+    if (nout > MD_MAX || nblk < 1) return NLRMM_ESHAPE;
+    int64_t g = (n + BLK - 1) / BLK;
+    if (g > nblk) g = nblk;
+    if (g < 1) g = 1;
+    multidot_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, ell + 1, xnew, b, n, part, nullptr);
+    *job = SideReduce{part, (int)g, nout, G, ldg, rb};
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_cgs2(const float *X, int64_t ldx, int nv, float *r, int64_t n, double *part1,
+           double *part2, int nblk, double *h1, double *h2, double tol, float *vout,
+           int *status, hipStream_t s)
+{
+    if (nv + 1 > MD_MAX || nblk < 1) return NLRMM_ESHAPE;
+    int64_t g = (n + BLK - 1) / BLK;
+    if (g > nblk) g = nblk;
+    if (g < 1) g = 1;
+    if (nv < 1 || g > RR_MAXBLK) {
+        // the launch-per-reduction sequence (the same arithmetic)
+        int rc;
+        if ((rc = k_multidot(X, ldx, nv, r, r, n, part1, nblk, h1, 1, s))) return rc;
+        if ((rc = k_gemv(X, ldx, nv, h1, -1.0, r, 1.0, n, r, s))) return rc;
+        if ((rc = k_multidot(X, ldx, nv, r, nullptr, n, part1, nblk, h2, 1, s))) return rc;
+        return k_gemv_norm_normalize(X, ldx, nv, h2, r, n, part1, nblk * 72, h1 + nv, tol, vout,
+                                     status, s);
+    }
+    multidot_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, nv, r, r, n, part1, nullptr);
+    gemv_multidot_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, nv, r, n, part1, (int)g, part2, h1);
+    const unsigned g3 = grid_for(n);
+    gemv_norm_red_k<<<g3, BLK, 0, s>>>(X, ldx, nv, r, n, part2, (int)g, h2, part1);
+    normalize_red_k<<<(unsigned)((n + BLK - 1) / BLK), BLK, 0, s>>>(r, part1, (int)g3, h1 + nv,
+                                                                    tol, n, vout, status);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 

@@ -67,22 +67,26 @@ __device__ __forceinline__ double rcp_nr(double x)
 }
 
 // X <- L^-1 X for the column held by this lane (p[c] = X[c][lane]); L from the LDS copy
-// sLt[k * LD + c] = L[c][k] with reciprocal diagonal sdi.  Each step first loads its whole
-// broadcast column, so the loads are issued back to back rather than one per update.
+// sLt[k * LD + c] = L[c][k] with reciprocal diagonal sdi.  The next step's broadcast column is
+// loaded while the current step's updates run.
 template <int NB, int LD>
 __device__ __forceinline__ void lower_solve_cols(double (&p)[NB], const double *sLt,
                                                  const double *sdi)
 {
+    double lc[NB];
+#pragma unroll
+    for (int c = 1; c < NB; ++c) lc[c] = sLt[c];
     StaticFor<0, NB>::run([&](auto K) __attribute__((always_inline)) {
         constexpr int k = decltype(K)::value;
-        double lc[NB];
+        double ln[NB];
 #pragma unroll
-        for (int c = k + 1; c < NB; ++c) lc[c] = sLt[k * LD + c];
+        for (int c = k + 2; c < NB; ++c) ln[c] = sLt[(k + 1) * LD + c];
         const double dk = sdi[k];
-        __builtin_amdgcn_sched_barrier(0);
         p[k] *= dk;
 #pragma unroll
         for (int c = k + 1; c < NB; ++c) p[c] = fma(-lc[c], p[k], p[c]);
+#pragma unroll
+        for (int c = k + 2; c < NB; ++c) lc[c] = ln[c];
         pin_regs(p);
     });
 }
@@ -104,7 +108,7 @@ __device__ __forceinline__ void tri_step(double (&p)[NB], int lane, double *sv, 
         const double sigma = sqrt(s2);
         alpha = (x0 >= 0.0) ? -sigma : sigma;
         v0 = x0 - alpha;
-        tj = 2.0 / (tail + v0 * v0);
+        tj = 2.0 * rcp_nr(tail + v0 * v0);
     }
     sdd[j] = dj;
     see[j] = alpha;
@@ -154,28 +158,34 @@ struct TriSteps<J, NB, true> {
     }
 };
 
-// ||AV z(lam) - b||^2 from the continuants of I + lam T (see gks_solve_reg_k).
+// ||AV z(lam) - b||^2 from the continuants of I + lam T (see gks_solve_reg_k); e2 holds the
+// squared off-diagonal, l2 = lam^2.  lam^2 e_{k-1}^2 of one step is lam^2 e_k^2 of the next,
+// so a step costs seven FP64 operations.  P is non-decreasing (the pivots of I + lam T are
+// >= 1) and grows by at most 1 + lam ||T|| per step (below 2^91 within the search bracket
+// even for Grams near singularity), so P and S ~ P^2 are rescaled by powers of two, without
+// a branch, every fourth step once |P| exceeds 2^100 (P < 2^470, S < 2^940).
 template <int NB>
-__device__ __forceinline__ double dp_residual(double lam, const double (&dd)[NB],
-                                              const double (&ee)[NB], double out2, double cn2)
+__device__ __forceinline__ double dp_residual(double lam, double l2, const double (&dd)[NB],
+                                              const double (&e2)[NB], double out2, double cn2)
 {
     double P2 = 0.0, P1 = 1.0, S = 0.0;
+    double t = l2 * e2[NB - 1];   // lam^2 e_k^2 of the current step
 #pragma unroll
     for (int k = NB - 1; k >= 1; --k) {
-        const double bk = lam * ee[k];
-        const double bm = lam * ee[k - 1];
-        const double Pk = fma(fma(lam, dd[k], 1.0), P1, -(bk * bk) * P2);
+        const double tm = l2 * e2[k - 1];
+        const double Pk = fma(fma(lam, dd[k], 1.0), P1, -t * P2);
         P2 = P1;
         P1 = Pk;
-        S = (bm * bm) * fma(P2, P2, S);
-        if ((k & 1) == 0 && fabs(P1) > 0x1p200) {
-            P1 *= 0x1p-200;
-            P2 *= 0x1p-200;
-            S *= 0x1p-400;
+        S = fma(tm, S, tm * (P2 * P2));
+        t = tm;
+        if ((k & 3) == 0) {
+            const double sc = fabs(P1) > 0x1p100 ? 0x1p-100 : 1.0;
+            P1 *= sc;
+            P2 *= sc;
+            S *= sc * sc;
         }
     }
-    const double b0 = lam * ee[0];
-    const double Q = fma(lam * dd[0], P1, -(b0 * b0) * P2);
+    const double Q = fma(lam * dd[0], P1, -t * P2);
     const double P0 = P1 + Q;
     return out2 + cn2 * (fma(Q, Q, S) / (P0 * P0));
 }
@@ -218,13 +228,13 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
             bad = 1;
             piv = 1e-300;
         }
-        const double r = 1.0 / piv;
+        const double r = rcp_nr(piv);
         __builtin_amdgcn_sched_barrier(0);
         const double t = a[j] * r;
 #pragma unroll
         for (int k = j + 1; k < NB; ++k) a[k] = fma(-t, lc[k], a[k]);
         const double d = sqrt(piv);
-        const double di = 1.0 / d;
+        const double di = rcp_nr(d);
         a[j] = (lane == j) ? d : a[j] * di;
         sdi[j] = di;
         pin_regs(a);
@@ -315,13 +325,13 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
     __syncthreads();
     // 5. discrepancy principle.  The padded tail (d = e = 0) leaves P and S unchanged, so the
     //    sweep runs over the whole padded size with T in registers.
-    double dd[NB], ee[NB];
+    double dd[NB], e2[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
         dd[k] = sdd[k];
-        ee[k] = see[k];
+        e2[k] = see[k] * see[k];
     }
-    auto phi = [&](double lam) { return dp_residual<NB>(lam, dd, ee, out2, cn2); };
+    auto phi = [&](double lam) { return dp_residual<NB>(lam, lam * lam, dd, e2, out2, cn2); };
     const double t2 = scal[1] * scal[1];
     double lam;
     int flag = 0;
@@ -340,14 +350,46 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
             lam = exp(hi);
             flag = NLRMM_ST_DP_HIGH;
         } else {
-            for (int round = 0; round < 12; ++round) {
-                const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
-                const unsigned long long m = __ballot(phi(exp(x)) >= t2);
+            // Two rounds on a uniform 65-part grid of the bracket, then rounds on a grid around
+            // the regula-falsi point c of the bracket, 32 points on each side: 16 at distances
+            // 1.5e-16 max(1, |c|) times powers of two up to a sixteenth of that side's span, 16
+            // in equal steps from there to the bracket's end.  The points increase with the
+            // lane, so the first lane with f >= 0 (f = residual - target) and its predecessor
+            // are the new bracket: it shrinks at least 16-fold per round, superlinearly once c
+            // is close, and both ends stay verified values of opposite sign.
+            double flo = plo - t2, fhi = phh - t2;
+            for (int round = 0; round < 16; ++round) {
+                double x;
+                if (round < 2) {
+                    x = fma(hi - lo, (double)(lane + 1) * (1.0 / 65.0), lo);
+                } else {
+                    const double c = fma(hi - lo, flo / (flo - fhi), lo);
+                    const bool up = lane >= 32;
+                    const int idx = up ? lane - 32 : 31 - lane;
+                    // innermost points 1.5e-16 |c| away: a bracket found there meets the stop test
+                    const double d0 = 1.5e-16 * fmax(1.0, fabs(c));
+                    const double span = up ? hi - c : c - lo;
+                    const double lin = span * (1.0 / 16.0);
+                    double off;
+                    if (idx < 16) {
+                        const int sh = max(1, (ilogb(lin) - ilogb(d0) + 15) / 15);
+                        off = fmin(ldexp(d0, idx * sh), lin);
+                    } else {
+                        off = lin * (double)(idx - 15);
+                    }
+                    x = up ? fmin(c + off, hi) : fmax(c - off, lo);
+                }
+                const double f = phi(exp(x)) - t2;
+                const unsigned long long m = __ballot(f >= 0.0);
                 const int k = m ? (__ffsll((unsigned long long)m) - 1) : 64;
-                const double nlo = (k == 0) ? lo : lo + (hi - lo) * (double)k / 65.0;
-                const double nhi = (k == 64) ? hi : lo + (hi - lo) * (double)(k + 1) / 65.0;
-                lo = nlo;
-                hi = nhi;
+                if (k < 64) {
+                    hi = lane_bcast(x, k);
+                    fhi = lane_bcast(f, k);
+                }
+                if (k > 0) {
+                    lo = lane_bcast(x, k - 1);
+                    flo = lane_bcast(f, k - 1);
+                }
                 if (hi - lo <= 4e-16 * fmax(1.0, fabs(lo))) break;
             }
             lam = exp(0.5 * (lo + hi));
@@ -356,6 +398,9 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
     const double res2 = phi(lam);
     // 6. y = (I + lam T)^-1 (s ||c|| e1) from the bottom-up pivots (computed in every lane,
     //    reciprocals kept in sy), then the reflectors in reverse order and H0
+    double ee[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) ee[k] = see[k];
     {
         double D = fma(lam, dd[NB - 1], 1.0);
         double r = rcp_nr(D);

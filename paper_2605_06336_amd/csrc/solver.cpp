@@ -48,7 +48,11 @@ struct Solver {
     double *GA = nullptr, *GP = nullptr, *rb = nullptr, *z = nullptr, *T = nullptr,
            *zt = nullptr, *sc = nullptr, *hb = nullptr, *hb2 = nullptr, *gv = nullptr,
            *hv = nullptr, *rv = nullptr, *dir = nullptr, *alphas = nullptr, *thk = nullptr,
-           *part_md = nullptr, *part_gram = nullptr, *part_fwd = nullptr, *gkb = nullptr;
+           *part_md = nullptr, *part_md2 = nullptr, *part_gram = nullptr, *part_fwd = nullptr,
+           *gkb = nullptr;
+    // a data-Gram column whose reduction the next regulariser Gram launch completes
+    SideReduce gc{};
+    bool gc_pending = false;
     // VarPro buffers
     float *Ahat = nullptr, *evec = nullptr;
     double *vp_GA = nullptr, *vp_ab = nullptr, *vp_M = nullptr, *vp_y = nullptr, *vp_gd = nullptr,
@@ -190,13 +194,8 @@ static int gram_from_scratch(Solver &S, int ell, int64_t m, const float *b, hipS
 // hb[ell+1] = ||r_out||^2; then V[:, ell] = r_out / ||r_out|| with the breakdown test.
 static int cgs2_append(Solver &S, int ell, hipStream_t s)
 {
-    RC(k_multidot(S.V, S.n, ell, S.r, S.r, S.n, S.part_md, S.md_blocks, S.hb, 1, s));
-    RC(k_gemv(S.V, S.n, ell, S.hb, -1.0, S.r, 1.0, S.n, S.r, s));
-    RC(k_multidot(S.V, S.n, ell, S.r, nullptr, S.n, S.part_md, S.md_blocks, S.hb2, 1, s));
-    RC(k_gemv_norm_normalize(S.V, S.n, ell, S.hb2, S.r, S.n, S.part_md, S.md_blocks * 72,
-                             S.hb + ell, S.cfg.breakdown_tol, S.V + (int64_t)ell * S.n, S.status,
-                             s));
-    return NLRMM_OK;
+    return k_cgs2(S.V, S.n, ell, S.r, S.n, S.part_md, S.part_md2, S.md_blocks, S.hb, S.hb2,
+                  S.cfg.breakdown_tol, S.V + (int64_t)ell * S.n, S.status, s);
 }
 
 // r = A^T (A V z - b) + lam Psi^T (w * Psi u), with u = V z already in S.u.
@@ -231,17 +230,24 @@ static int mm_residual(Solver &S, const nlrmm_batch &b, const double *theta, int
 }
 
 // Append one GKS direction (Alg. "enlarge" body after u = V z): residual, CGS2, A v and the
-// new row of the data Gram.
+// new row of the data Gram.  defer: the Gram row's reduction is left to the regulariser Gram
+// launch of the projected solve that follows (one launch fewer per expansion).
 static int expand(Solver &S, const nlrmm_batch &b, const double *theta, const float *bvec,
-                  hipStream_t s)
+                  hipStream_t s, bool defer = false)
 {
     const int ell = S.ell;
     const int64_t m = m_of(S, b);
     RC(mm_residual(S, b, theta, ell, bvec, s));
     RC(cgs2_append(S, ell, s));
     RC(proj_plain(S, b, 1, S.V + (int64_t)ell * S.n, theta, S.AV + (int64_t)ell * m, s));
-    RC(k_multidot_gram_col(S.AV, m, ell, S.AV + (int64_t)ell * m, bvec, m, S.part_md,
-                           S.md_blocks, S.GA, S.ld, S.rb, s));
+    if (defer) {
+        RC(k_multidot_gram_col_deferred(S.AV, m, ell, S.AV + (int64_t)ell * m, bvec, m,
+                                        S.part_md, S.md_blocks, S.GA, S.ld, S.rb, &S.gc, s));
+        S.gc_pending = true;
+    } else {
+        RC(k_multidot_gram_col(S.AV, m, ell, S.AV + (int64_t)ell * m, bvec, m, S.part_md,
+                               S.md_blocks, S.GA, S.ld, S.rb, s));
+    }
     S.ell = ell + 1;
     return NLRMM_OK;
 }
@@ -252,11 +258,13 @@ static int projected_solve(Solver &S, hipStream_t s, const nlrmm_batch *b = null
                            const float *bvec = nullptr)
 {
     // this step's weights (from the u the solve starts from): the Gram and, in the expansion
-    // that follows, the residual use them (Alg. "enlarge")
-    RC(k_psi_weights(S.u, S.g.nx, S.g.ny, S.F, S.cfg.temporal, (float)S.cfg.eps, S.w, s,
-                     S.flow));
-    RC(k_gram_psi(S.V, S.n, S.ell, S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.part_gram,
-                  S.gram_blocks, S.GP, S.ld, s, S.cfg.gram_precision, nullptr, 0.0f, S.flow));
+    // that follows, the residual use them (Alg. "enlarge").  The Gram launch forms them and
+    // stores them in S.w, and completes a pending row of the data Gram.
+    const SideReduce *side = S.gc_pending ? &S.gc : nullptr;
+    S.gc_pending = false;
+    RC(k_gram_psi(S.V, S.n, S.ell, nullptr, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.part_gram,
+                  S.gram_blocks, S.GP, S.ld, s, S.cfg.gram_precision, S.u, (float)S.cfg.eps,
+                  S.flow, S.w, side));
     RC(k_gks_solve(S.GA, S.GP, S.ld, S.rb, S.sc + S_BNORM2, S.ell, S.cfg.lam_fix, S.z,
                    S.sc + S_LAM, S.status, s));
     if (b && bvec) {
@@ -472,7 +480,7 @@ static int hi_solve_update(Solver &S, const nlrmm_batch &b, double *theta, const
     for (int t = 0; t < nsolve && !rc; ++t) {
         const bool more = t < nsolve - 1;
         rc = projected_solve(S, s, more ? &b : nullptr, more ? bvec : nullptr);
-        if (!rc && more) rc = expand(S, b, S.thk, bvec, s);
+        if (!rc && more) rc = expand(S, b, S.thk, bvec, s, true);
     }
     if (!rc && S.cfg.param_update == 1) rc = gn_update(S, b, theta, bvec, s);
     if (!rc && S.cfg.param_update == 3) {
@@ -512,6 +520,7 @@ static int solver_outer(Solver &S, const nlrmm_batch &b, double *theta, const fl
     const int64_t V = b.nviews;
     const int64_t m = m_of(S, b);
     if (V > S.maxV) return NLRMM_ESHAPE;
+    S.gc_pending = false;
     // optical-flow branch of Alg. "dyn_nl_rmmgks": the velocities of every frame pair from
     // u^(k) (SOLVE-OF) every of_every outer iterations; Theta^(k) = [Psi; M_hat] follows
     if (S.cfg.temporal == TEMPORAL_OF && S.F > 1 && S.outer_count % S.cfg.of_every == 0)
@@ -528,7 +537,7 @@ static int solver_outer(Solver &S, const nlrmm_batch &b, double *theta, const fl
     for (int t = 0; t < nsolve; ++t) {
         const bool more = t < nsolve - 1;
         RC(projected_solve(S, s, more ? &b : nullptr, more ? bvec : nullptr));
-        if (more) RC(expand(S, b, S.thk, bvec, s));
+        if (more) RC(expand(S, b, S.thk, bvec, s, true));
     }
     RC(compress(S, b, s));
     if (S.cfg.lam_hi > 0.0) {
@@ -775,6 +784,7 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
         (rc = S->alloc(&S->rv, max_views)) || (rc = S->alloc(&S->dir, max_views)) ||
         (rc = S->alloc(&S->alphas, 32)) || (rc = S->alloc(&S->thk, max_views)) ||
         (rc = S->alloc(&S->part_md, md_part_doubles(S->md_blocks))) ||
+        (rc = S->alloc(&S->part_md2, md_part_doubles(S->md_blocks))) ||
         (rc = S->alloc(&S->part_gram, (size_t)S->gram_blocks * 64 * 64)) ||
         (rc = S->alloc(&S->part_fwd, (size_t)3 * c.kmin * max_views * S->nchunks)) ||
         (rc = S->alloc(&S->gkb, 2 * (size_t)S->kcap + 2)) || (rc = S->alloc(&S->status, 1)) ||
@@ -939,7 +949,7 @@ static int scratch_view(nlrmm_ctx *ctx, Solver &S, int64_t n, int64_t m, int kca
     const int64_t big = n > m ? n : m;
     const size_t bytes = al(sizeof(float) * n) * 2 + al(sizeof(float) * m) +
                          al(sizeof(float) * (size_t)kmin * big) +
-                         al(sizeof(double) * md_part_doubles(S.md_blocks)) +
+                         al(sizeof(double) * md_part_doubles(S.md_blocks)) * 2 +
                          al(sizeof(double) * (size_t)S.gram_blocks * 64 * 64) +
                          al(sizeof(double) * (kcap + 4)) * 2 + al(sizeof(double) * kcap * 16) +
                          al(sizeof(double) * (kcap + 4)) + al(sizeof(int) * 4) + 4096;
@@ -956,6 +966,7 @@ static int scratch_view(nlrmm_ctx *ctx, Solver &S, int64_t n, int64_t m, int kca
     S.rho = (float *)take(sizeof(float) * m);
     S.Vtmp = (float *)take(sizeof(float) * (size_t)kmin * big);
     S.part_md = (double *)take(sizeof(double) * md_part_doubles(S.md_blocks));
+    S.part_md2 = (double *)take(sizeof(double) * md_part_doubles(S.md_blocks));
     S.part_gram = (double *)take(sizeof(double) * (size_t)S.gram_blocks * 64 * 64);
     S.hb = (double *)take(sizeof(double) * (kcap + 4));
     S.hb2 = (double *)take(sizeof(double) * (kcap + 4));

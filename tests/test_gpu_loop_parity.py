@@ -90,3 +90,18 @@ def test_loop_parity_c2_full_size():
     assert dth <= 1e-4
     assert abs(lam - float(fx["lam"][-1])) <= 1e-2 * float(fx["lam"][-1])
     assert status == int(fx["status"][-1])
+
+
+def test_loop_parity_c4_full_size():
+    """The dynamic workload at its full size (32 frames of 256x256, 2349 views, 363 bins,
+    ANISO-TV with frame differences, AltMin, kmax 25, 20 outer iterations), batched launches
+    over the frames, against the oracle's run."""
+    u, theta, lam, status = run_gpu("c4")
+    du, dth, fx = compare("c4", u, theta)
+    print(f"c4 after {int(fx['outer'])} outer iterations vs the FP64 oracle: u {du:.3e}, "
+          f"theta max {dth:.3e} rad; lambda gpu {lam:.5e} oracle {float(fx['lam'][-1]):.5e}; "
+          f"status gpu {status} oracle {int(fx['status'][-1])}", flush=True)
+    assert du <= 1e-3
+    assert dth <= 1e-4
+    assert abs(lam - float(fx["lam"][-1])) <= 1e-2 * float(fx["lam"][-1])
+    assert status == int(fx["status"][-1])

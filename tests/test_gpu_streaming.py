@@ -74,7 +74,7 @@ def test_streaming_parity_scaled_c5():
     22/23-view block's projected problem amplifies rounding of the start), so the bar is the
     larger of the fixed tolerance and twice the oracle's own spread.  The fixed 1e-3 bar alone
     is the skipped strict test below."""
-    inst, u, th, st, (st2, _) = streaming_pair(seeds=(11,))
+    inst, u, th, st, (st2,) = streaming_pair(seeds=(11,))
     du, dth = rel(u, st.u), float(np.max(np.abs(th - st.theta)))
     su, sth = rel(st2.u, st.u), float(np.max(np.abs(st2.theta - st.theta)))
     x_true = inst.x_true.reshape(-1)
