@@ -13,25 +13,33 @@ int k_psi_apply(const float *u, int nx, int ny, int F, int temporal, float *out,
 // w == nullptr: the weights are formed from u with eps (equal to k_psi_weights' values)
 int k_tv_grad_add(const float *u, const float *w, int nx, int ny, int F, int temporal,
                   const double *lamp, float *r, hipStream_t s, float eps = 0.0f);
-// A reduction of multidot partials left to another launch: outputs i < nout of
-// part[b][i] (b < nblk), written as the new row and column nout - 2 of the symmetric G
-// (i <= nout - 2) and rb[nout - 2] (the last output), as k_multidot_gram_col writes them.
-struct SideReduce {
-    const double *part;
-    int nblk, nout;
+// A data-Gram column left to the regulariser Gram launch (k_multidot_gram_col's work): the
+// inner products <X_i, xnew> (i <= ell, X's column ell being xnew) and <b, xnew> over n
+// entries, written as the new row and column ell of the symmetric G and rb[ell].  part holds
+// part_cap doubles; md_blocks bounds the blocks of the stand-alone launches.
+struct GramColJob {
+    const float *X;
+    int64_t ldx;
+    int ell;
+    const float *xnew, *b;
+    int64_t n;
+    double *part;
+    int64_t part_cap;
+    int md_blocks;
     double *G;
     int ldg;
     double *rb;
 };
 // mode: 0 FP64 VALU, 1 FP32 MFMA, 2 BF16 MFMA (FP32 accumulation per chunk, FP64 across)
 // w == nullptr: the weights are formed from u with eps (inside the kernel in modes 1, 2);
-// with wout they are also stored there (as k_psi_weights stores them).  side: a pending
-// data-Gram column, completed by this launch (modes 1, 2) or by a launch before it (mode 0).
+// with wout they are also stored there (as k_psi_weights stores them).  col: a pending
+// data-Gram column, computed inside this launch and reduced with the Gram (modes 1, 2), or by
+// k_multidot_gram_col first (mode 0, or when its partials do not fit part_cap).
 int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int ny, int F,
                int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s,
                int mode = 0, const float *u = nullptr, float eps = 0.0f,
                const float *flow = nullptr, float *wout = nullptr,
-               const SideReduce *side = nullptr);
+               const GramColJob *col = nullptr);
 // Optical flow (of.hip).  Velocities of every frame pair of u [F][ny][nx] (SOLVE-OF, eq.
 // "of_forward", l2/l2 with a ridge) by `iters` conjugate-gradient steps from zero, into
 // flow [F-1][2][ny][nx]; work: of_work_floats(nx, ny, F) floats, part: of_part_doubles(...).
@@ -65,16 +73,12 @@ int k_gemv_norm_normalize(const float *X, int64_t ldx, int nv, const double *c, 
 int k_multidot_gram_col(const float *X, int64_t ldx, int ell, const float *xnew, const float *b,
                         int64_t n, double *part, int nblk, double *G, int ldg, double *rb,
                         hipStream_t s);
-// The same column left pending: only the multidot is launched; *job describes the reduction
-// that a later k_gram_psi (side) completes before anything reads G or rb.
-int k_multidot_gram_col_deferred(const float *X, int64_t ldx, int ell, const float *xnew,
-                                 const float *b, int64_t n, double *part, int nblk, double *G,
-                                 int ldg, double *rb, SideReduce *job, hipStream_t s);
 // CGS2 of r against the first nv columns of X and the normalised result into vout (Alg.
 // "enlarge"): h1[0..nv-1] = X^T r, h1[nv] = ||r||^2, r -= X h1, h2 = X^T r, r -= X h2,
 // vout = r / ||r|| with the breakdown test of k_gemv_norm_normalize.  Four launches (each
-// consumer re-reduces its producer's partials) while the inner products need at most 512
-// blocks, the launch-per-reduction sequence otherwise; the results are the same bitwise.
+// consumer sums its producer's partials itself) while the inner products need at most 512
+// blocks, the launch-per-reduction sequence otherwise (the same arithmetic except for the
+// order in which the block partials are added).
 // part1, part2: md_part_doubles(nblk) doubles each.
 int k_cgs2(const float *X, int64_t ldx, int nv, float *r, int64_t n, double *part1,
            double *part2, int nblk, double *h1, double *h2, double tol, float *vout,

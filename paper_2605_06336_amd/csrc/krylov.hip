@@ -214,26 +214,114 @@ __global__ __launch_bounds__(BLK) void gram_psi_k(const float *__restrict__ V, i
     }
 }
 
-// The reduction of reduce_vec_k's Gram-column mode (below) run by wave 0 of the first blocks
-// of another launch (the job's outputs need no launch of their own): same order, same values.
-__device__ __forceinline__ void side_reduce(const SideReduce &j)
+constexpr int MD_MAX = 72;   // inner products per multidot launch
+
+// Inner products <X_i, y> (i < nv) and <z, y> (i == nv when z is given), FP64 accumulation:
+// per-block partials part[block][i].  Each block reduces its share of the elements for
+// groups of 16 outputs through LDS (16 threads per output, then a 16-lane butterfly).  The
+// body is shared by multidot_k and the regulariser Gram launch (which runs it first, in its
+// staging area); sacc: 16 x BLK doubles of LDS; ends with a barrier.  With one element per
+// thread the loads of CH outputs are issued together (all of them in multidot_k; fewer inside
+// the Gram launch, whose own work needs few registers).
+template <int CH>
+__device__ __forceinline__ void multidot_body(const float *__restrict__ X, int64_t ldx, int nv,
+                                              const float *__restrict__ y,
+                                              const float *__restrict__ z, int64_t n,
+                                              double *__restrict__ part, double (*sacc)[BLK])
 {
-    if (j.part == nullptr || threadIdx.x >= 64) return;
-    for (int i = blockIdx.x; i < j.nout; i += gridDim.x) {
-        double a = 0.0;
-        for (int b = threadIdx.x; b < j.nblk; b += 64) a += j.part[(int64_t)b * j.nout + i];
-        a = wave_sum(a);
-        if (threadIdx.x == 0) {
-            const int ell = j.nout - 2;
-            if (i <= ell) {
-                j.G[i * j.ldg + ell] = a;
-                j.G[ell * j.ldg + i] = a;
-            } else {
-                j.rb[ell] = a;
+    constexpr int GRP = 16;            // outputs reduced per LDS round
+    const int tid = threadIdx.x;
+    const int nout = nv + (z != nullptr ? 1 : 0);
+    auto block_reduce = [&](int i0, const double (&acc)[GRP]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int a = 0; a < GRP; ++a) sacc[a][tid] = acc[a];
+        __syncthreads();
+        constexpr int TPO = BLK / GRP;            // threads per output of the group
+        const int a = tid / TPO, l = tid % TPO;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < BLK / TPO; ++k) s += sacc[a][l + TPO * k];
+        for (int off = TPO / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, TPO);
+        if (l == 0 && i0 + a < nout) part[(int64_t)blockIdx.x * nout + i0 + a] = s;
+        __syncthreads();
+    };
+    if ((int64_t)gridDim.x * BLK >= n) {
+        // at most one element per thread: issue the loads of CH outputs first, then reduce
+        // them by groups (the FP64 product of two floats is exact)
+        static_assert(CH % GRP == 0 || CH == MD_MAX, "chunks of whole groups");
+        const int64_t e = (int64_t)blockIdx.x * BLK + tid;
+        const bool in = e < n;
+        const float ye = in ? y[e] : 0.0f;
+        for (int c0 = 0; c0 < nout; c0 += CH) {
+            float xv[CH];
+#pragma unroll
+            for (int ii = 0; ii < CH; ++ii) {
+                const int i = c0 + ii;
+                float v = 0.0f;
+                if (i < nv) v = in ? X[(int64_t)i * ldx + e] : 0.0f;
+                else if (i == nv && z != nullptr) v = in ? z[e] : 0.0f;
+                xv[ii] = v;
+            }
+#pragma unroll
+            for (int g0 = 0; g0 < CH; g0 += GRP) {
+                if (c0 + g0 < nout) {
+                    double acc[GRP];
+#pragma unroll
+                    for (int a = 0; a < GRP; ++a)
+                        acc[a] = g0 + a < CH ? (double)xv[g0 + a] * (double)ye : 0.0;
+                    block_reduce(c0 + g0, acc);
+                }
             }
         }
+        return;
+    }
+    // several elements per thread: 16-byte loads when every column is 16-byte aligned and
+    // n is a multiple of 4 (four times the bytes in flight per load)
+    const bool vec4 = (ldx % 4) == 0 && (n % 4) == 0 &&
+                      (reinterpret_cast<uintptr_t>(X) % 16) == 0 &&
+                      (reinterpret_cast<uintptr_t>(y) % 16) == 0 &&
+                      (z == nullptr || (reinterpret_cast<uintptr_t>(z) % 16) == 0);
+    for (int i0 = 0; i0 < nout; i0 += GRP) {
+        double acc[GRP];
+#pragma unroll
+        for (int a = 0; a < GRP; ++a) acc[a] = 0.0;
+        if (vec4) {
+            const int64_t n4 = n / 4, ld4 = ldx / 4;
+            const float4 *X4 = reinterpret_cast<const float4 *>(X);
+            const float4 *y4 = reinterpret_cast<const float4 *>(y);
+            const float4 *z4 = reinterpret_cast<const float4 *>(z);
+            for (int64_t e = (int64_t)blockIdx.x * BLK + tid; e < n4;
+                 e += (int64_t)gridDim.x * BLK) {
+                const float4 yv = y4[e];
+#pragma unroll
+                for (int a = 0; a < GRP; ++a) {
+                    const int i = i0 + a;
+                    float4 xv = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (i < nv) xv = X4[(int64_t)i * ld4 + e];
+                    else if (i == nv && z != nullptr) xv = z4[e];
+                    double t = acc[a];
+                    t = fma((double)xv.x, (double)yv.x, t);
+                    t = fma((double)xv.y, (double)yv.y, t);
+                    t = fma((double)xv.z, (double)yv.z, t);
+                    acc[a] = fma((double)xv.w, (double)yv.w, t);
+                }
+            }
+        } else {
+            for (int64_t e = (int64_t)blockIdx.x * BLK + tid; e < n;
+                 e += (int64_t)gridDim.x * BLK) {
+                const double ye = (double)y[e];
+#pragma unroll
+                for (int a = 0; a < GRP; ++a) {
+                    const int i = i0 + a;
+                    if (i < nv) acc[a] = fma((double)X[(int64_t)i * ldx + e], ye, acc[a]);
+                    else if (i == nv && z != nullptr) acc[a] = fma((double)z[e], ye, acc[a]);
+                }
+            }
+        }
+        block_reduce(i0, acc);
     }
 }
+
 
 // MFMA variant of the weighted regulariser Gram (B^T B with B = sqrt(w) * Psi V, B of
 // up to 192 rows per 64-pixel chunk and <= 64 columns).  The chunk's rows are staged in
@@ -266,21 +354,28 @@ __device__ __forceinline__ short bf16_rne(float f)
 // 0..2 take the tiles (0,0), (0,1), (1,1).  Per-block partials go to part[block][ell][ell]
 // (both triangles).
 template <bool BF16, bool MOTION>
-__global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__ V, int64_t ldv,
+__global__ __launch_bounds__(BLK, 3) void gram_psi_mfma_k(const float *__restrict__ V, int64_t ldv,
                                                        int ell, const float *__restrict__ w,
                                                        int nx, int ny, int F, int temporal,
                                                        double *__restrict__ part,
                                                        const float *__restrict__ u, float e2,
                                                        const float *__restrict__ flow,
                                                        float *__restrict__ wout,
-                                                       SideReduce side)
+                                                       GramColJob col)
 {
-    side_reduce(side);
     // the chunk's weighted differences, column-major: FP32, or BF16 rounded once at staging
     // (four consecutive rows of a column are then one 8-byte MFMA operand)
     using Elem = typename std::conditional<BF16, short, float>::type;
     constexpr int LD = BF16 ? MLDH : MLDR;
-    __shared__ __align__(16) Elem sB[64][LD];
+    // staging area, also the reduction buffer of a pending data-Gram column (16 x BLK doubles)
+    constexpr size_t SB_BYTES = sizeof(Elem) * 64 * LD;
+    constexpr size_t RAW = SB_BYTES > 16 * BLK * sizeof(double) ? SB_BYTES : 16 * BLK * sizeof(double);
+    __shared__ __align__(16) unsigned char sraw[RAW];
+    Elem(*sB)[LD] = reinterpret_cast<Elem(*)[LD]>(sraw);
+    // a pending data-Gram column first (its inner products need no part of this Gram)
+    if (col.X != nullptr)
+        multidot_body<32>(col.X, col.ldx, col.ell + 1, col.xnew, col.b, col.n, col.part,
+                      reinterpret_cast<double(*)[BLK]>(sraw));
     const TVGeo g = tvgeo(nx, ny, F, temporal, flow);
     // MOTION: the launch has the optical-flow rows (temporal mode 2 with several frames)
     constexpr bool motion = MOTION;
@@ -433,8 +528,8 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
     if (single) {
         // the four row slices of tile (0,0) meet in LDS (the staging area is free after the
         // last chunk's barrier), summed in slice order
-        static_assert(sizeof(sB) >= 3 * 16 * 64 * sizeof(double), "staging too small");
-        double *sacc = reinterpret_cast<double *>(&sB[0][0]);   // [3][16][64]
+        static_assert(RAW >= 3 * 16 * 64 * sizeof(double), "staging too small");
+        double *sacc = reinterpret_cast<double *>(sraw);   // [3][16][64]
         if (wv > 0) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) sacc[((wv - 1) * 16 + r) * 64 + lane] = accd[r];
@@ -464,11 +559,29 @@ __global__ __launch_bounds__(BLK) void gram_psi_mfma_k(const float *__restrict__
 }
 
 // Sum nblk partial ell x ell matrices into G (leading dimension ldg): one wave per entry,
-// fixed summation order.
+// fixed summation order.  Blocks beyond ell * ell reduce a pending data-Gram column (outputs
+// of the multidot run inside the Gram launch, reduce_vec_k's order and values): the new row
+// and column col.ell of col.G and col.rb[col.ell].
 __global__ __launch_bounds__(64) void reduce_gram_k(const double *__restrict__ part, int nblk,
-                                                    int ell, double *__restrict__ G, int ldg)
+                                                    int ell, double *__restrict__ G, int ldg,
+                                                    GramColJob col)
 {
     const int t = blockIdx.x;
+    if (t >= ell * ell) {
+        const int i = t - ell * ell, nout = col.ell + 2;
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += 64) s += col.part[(int64_t)b * nout + i];
+        s = wave_sum(s);
+        if (threadIdx.x == 0) {
+            if (i <= col.ell) {
+                col.G[i * col.ldg + col.ell] = s;
+                col.G[col.ell * col.ldg + i] = s;
+            } else {
+                col.rb[col.ell] = s;
+            }
+        }
+        return;
+    }
     double s = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 64) s += part[(int64_t)b * ell * ell + t];
     s = wave_sum(s);
@@ -483,104 +596,15 @@ __global__ __launch_bounds__(64) void reduce_gram_k(const double *__restrict__ p
 // ---------------------------------------------------------------------------
 // part[blk][i] = sum over this block's entries of X_i[e] * y[e], i < nv; X_i = X + i*ldx.
 // An extra row (i = nv) accumulates y[e] * z[e] when z != null.
-constexpr int MD_MAX = 72;
 
-// Inner products <X_i, y> (i < nv) and <z, y> (i == nv when z is given), FP64 accumulation:
-// per-block partials part[block][i].  Each block reduces its share of the elements for
-// groups of 16 outputs through LDS (16 threads per output, then a 16-lane butterfly).
 __global__ __launch_bounds__(BLK) void multidot_k(const float *__restrict__ X, int64_t ldx, int nv,
                                                   const float *__restrict__ y,
                                                   const float *__restrict__ z, int64_t n,
                                                   double *__restrict__ part, const int *skip)
 {
     if (skip != nullptr && *skip != 0) return;
-    constexpr int GRP = 16;            // outputs reduced per LDS round
-    __shared__ double sacc[GRP][BLK];
-    const int tid = threadIdx.x;
-    const int nout = nv + (z != nullptr ? 1 : 0);
-    auto block_reduce = [&](int i0, const double (&acc)[GRP]) __attribute__((always_inline)) {
-#pragma unroll
-        for (int a = 0; a < GRP; ++a) sacc[a][tid] = acc[a];
-        __syncthreads();
-        constexpr int TPO = BLK / GRP;            // threads per output of the group
-        const int a = tid / TPO, l = tid % TPO;
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < BLK / TPO; ++k) s += sacc[a][l + TPO * k];
-        for (int off = TPO / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, TPO);
-        if (l == 0 && i0 + a < nout) part[(int64_t)blockIdx.x * nout + i0 + a] = s;
-        __syncthreads();
-    };
-    if ((int64_t)gridDim.x * BLK >= n) {
-        // at most one element per thread: issue every load first, then reduce by groups
-        // (the FP64 product of two floats is exact)
-        const int64_t e = (int64_t)blockIdx.x * BLK + tid;
-        const bool in = e < n;
-        const float ye = in ? y[e] : 0.0f;
-        float xv[MD_MAX];
-#pragma unroll
-        for (int i = 0; i < MD_MAX; ++i) {
-            float v = 0.0f;
-            if (i < nv) v = in ? X[(int64_t)i * ldx + e] : 0.0f;
-            else if (i == nv && z != nullptr) v = in ? z[e] : 0.0f;
-            xv[i] = v;
-        }
-#pragma unroll
-        for (int i0 = 0; i0 < MD_MAX; i0 += GRP) {
-            if (i0 < nout) {
-                double acc[GRP];
-#pragma unroll
-                for (int a = 0; a < GRP; ++a) acc[a] = i0 + a < MD_MAX ? (double)xv[i0 + a] * (double)ye : 0.0;
-                block_reduce(i0, acc);
-            }
-        }
-        return;
-    }
-    // several elements per thread: 16-byte loads when every column is 16-byte aligned and
-    // n is a multiple of 4 (four times the bytes in flight per load)
-    const bool vec4 = (ldx % 4) == 0 && (n % 4) == 0 &&
-                      (reinterpret_cast<uintptr_t>(X) % 16) == 0 &&
-                      (reinterpret_cast<uintptr_t>(y) % 16) == 0 &&
-                      (z == nullptr || (reinterpret_cast<uintptr_t>(z) % 16) == 0);
-    for (int i0 = 0; i0 < nout; i0 += GRP) {
-        double acc[GRP];
-#pragma unroll
-        for (int a = 0; a < GRP; ++a) acc[a] = 0.0;
-        if (vec4) {
-            const int64_t n4 = n / 4, ld4 = ldx / 4;
-            const float4 *X4 = reinterpret_cast<const float4 *>(X);
-            const float4 *y4 = reinterpret_cast<const float4 *>(y);
-            const float4 *z4 = reinterpret_cast<const float4 *>(z);
-            for (int64_t e = (int64_t)blockIdx.x * BLK + tid; e < n4;
-                 e += (int64_t)gridDim.x * BLK) {
-                const float4 yv = y4[e];
-#pragma unroll
-                for (int a = 0; a < GRP; ++a) {
-                    const int i = i0 + a;
-                    float4 xv = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (i < nv) xv = X4[(int64_t)i * ld4 + e];
-                    else if (i == nv && z != nullptr) xv = z4[e];
-                    double t = acc[a];
-                    t = fma((double)xv.x, (double)yv.x, t);
-                    t = fma((double)xv.y, (double)yv.y, t);
-                    t = fma((double)xv.z, (double)yv.z, t);
-                    acc[a] = fma((double)xv.w, (double)yv.w, t);
-                }
-            }
-        } else {
-            for (int64_t e = (int64_t)blockIdx.x * BLK + tid; e < n;
-                 e += (int64_t)gridDim.x * BLK) {
-                const double ye = (double)y[e];
-#pragma unroll
-                for (int a = 0; a < GRP; ++a) {
-                    const int i = i0 + a;
-                    if (i < nv) acc[a] = fma((double)X[(int64_t)i * ldx + e], ye, acc[a]);
-                    else if (i == nv && z != nullptr) acc[a] = fma((double)z[e], ye, acc[a]);
-                }
-            }
-        }
-        block_reduce(i0, acc);
-    }
+    __shared__ double sacc[16][BLK];
+    multidot_body<MD_MAX>(X, ldx, nv, y, z, n, part, sacc);
 }
 
 // out[i * ostride] = sum_b part[b][i]: one wave per output, lane-strided partial sums
@@ -611,16 +635,16 @@ __global__ __launch_bounds__(64) void reduce_vec_k(const double *__restrict__ pa
     }
 }
 
-// The sums of reduce_vec_k formed inside a consumer block, so that a multidot's partials
-// need no launch of their own: acc[i][L] = part[L][i] + part[L + 64][i] + ... in that order
-// (the lane accumulators of reduce_vec_k, all (i, L) pairs spread over the block's threads,
-// consecutive threads on consecutive partials), then each output's 64 accumulators joined
-// by the same butterfly.  The results equal reduce_vec_k's bitwise.  sbuf holds
+// A multidot's block partials summed inside a consumer block, so that they need no launch of
+// their own.  Stage 1: acc[L][i] = part[L][i] + part[L + 64][i] + ... (all (L, i) pairs
+// spread over the block's threads, consecutive threads on consecutive partials, every load of
+// a thread in flight at once).  Stage 2: thread i adds the 64 accumulators of output i in a
+// fixed order (eight interleaved sums, then their tree), reading consecutive LDS words across
+// the threads.  Deterministic: the order depends only on nblk and nout.  sbuf holds
 // MD_MAX * 64 doubles, sh receives the nout sums; ends with a barrier.
 constexpr int RR_MAXBLK = 512;   // producer blocks a consumer re-reduces (<= 8 per lane)
 
-// K: partials per lane accumulator (nblk <= 64 K); U pairs per thread per round, so that
-// 36 loads are in flight at once (one round of memory latency for up to 36 outputs at K = 4)
+// K: partials per accumulator (nblk <= 64 K); U pairs per thread per round, 36 loads in flight
 template <int K>
 __device__ void rereduce_k(const double *__restrict__ part, int nblk, int nout, double *sbuf,
                            double *sh)
@@ -644,20 +668,23 @@ __device__ void rereduce_k(const double *__restrict__ part, int nblk, int nout, 
         for (int u = 0; u < U; ++u) {
             const int q = q0 + u * BLK + tid;
             if (q < npair) {
-                const int L = q / nout, i = q - L * nout;
+                const int L = q / nout;
                 double a = 0.0;
 #pragma unroll
                 for (int k = 0; k < K; ++k)
                     if (L + 64 * k < nblk) a += v[u][k];
-                sbuf[i * 64 + L] = a;
+                sbuf[q] = a;   // pair-major: sbuf[L * nout + i]
             }
         }
     }
     __syncthreads();
-    const int lane = tid & 63;
-    for (int i = tid >> 6; i < nout; i += BLK / 64) {
-        const double a = wave_sum(sbuf[i * 64 + lane]);
-        if (lane == 0) sh[i] = a;
+    if (tid < nout) {
+        double a8[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) a8[r] = sbuf[r * nout + tid];
+#pragma unroll
+        for (int L = 8; L < 64; ++L) a8[L & 7] += sbuf[L * nout + tid];
+        sh[tid] = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
     }
     __syncthreads();
 }
@@ -672,10 +699,10 @@ __device__ void rereduce(const double *__restrict__ part, int nblk, int nout, do
 }
 
 // First correction of CGS2 fused with the second pass's products (Alg. "enlarge":
-// reorthogonalisation of the new direction).  h = X^T r and ||r||^2 are re-reduced from the
+// reorthogonalisation of the new direction).  h = X^T r and ||r||^2 are summed from the
 // partials of the multidot that precedes (pin, nin blocks, nv + 1 outputs; block 0 stores
-// them in hout), r <- r - X h exactly as gemv_k computes it, then the partials of X^T r
-// exactly as multidot_k(X, r) forms them with the same grid (pout[block][i], i < nv).  Every
+// them in hout), r <- r - X h as gemv_k computes it, then the partials of X^T r as
+// multidot_k(X, r) forms them with the same grid (pout[block][i], i < nv).  Every
 // element of r is rewritten and read back by the same thread, so no grid-wide order is
 // needed.
 __global__ __launch_bounds__(BLK) void gemv_multidot_k(const float *__restrict__ X, int64_t ldx,
@@ -781,7 +808,7 @@ __global__ __launch_bounds__(BLK) void gemv_multidot_k(const float *__restrict__
     }
 }
 
-// Second correction of CGS2 with its norm: h2 re-reduced from the partials of
+// Second correction of CGS2 with its norm: h2 summed from the partials of
 // gemv_multidot_k (block 0 stores it in hout), then gemv_norm_k's work.
 __global__ __launch_bounds__(BLK) void gemv_norm_red_k(const float *__restrict__ X, int64_t ldx,
                                                        int nv, float *r, int64_t n,
@@ -1791,7 +1818,7 @@ int k_tv_grad_add(const float *u, const float *w, int nx, int ny, int F, int tem
 
 int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int ny, int F,
                int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s, int mode,
-               const float *u, float eps, const float *flow, float *wout, const SideReduce *side)
+               const float *u, float eps, const float *flow, float *wout, const GramColJob *col)
 {
     if (ell > GMAX) return NLRMM_ESHAPE;
     if (w == nullptr && u == nullptr) return NLRMM_EINVAL;
@@ -1799,13 +1826,20 @@ int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int
         return NLRMM_EINVAL;
     const float e2 = eps * eps;
     const bool motion = temporal == TEMPORAL_OF && F > 1;
-    SideReduce sj{};
-    if (side != nullptr) sj = *side;
+    GramColJob cj{};   // X == nullptr: no column inside this launch
+    if (col != nullptr && col->X != nullptr) {
+        if (mode != 0 && col->ell + 2 <= MD_MAX &&
+            (int64_t)nblk * (col->ell + 2) <= col->part_cap) {
+            cj = *col;
+        } else {
+            const int rc = k_multidot_gram_col(col->X, col->ldx, col->ell, col->xnew, col->b,
+                                               col->n, col->part, col->md_blocks, col->G,
+                                               col->ldg, col->rb, s);
+            if (rc) return rc;
+        }
+    }
     if (mode == 0) {
-        // the FP64 kernel takes stored weights and no side job: both run as launches first
-        if (sj.part != nullptr)
-            reduce_vec_k<<<(unsigned)sj.nout, 64, 0, s>>>(sj.part, sj.nblk, sj.nout, nullptr, 0,
-                                                          nullptr, sj.G, sj.ldg, sj.rb);
+        // the FP64 kernel takes stored weights
         if (w == nullptr) {
             if (wout == nullptr) return NLRMM_EINVAL;
             const int rc = k_psi_weights(u, nx, ny, F, temporal, eps, wout, s, flow);
@@ -1819,18 +1853,19 @@ int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int
         float *wo = w ? nullptr : wout;
         if (mode == 1 && motion)
             gram_psi_mfma_k<false, true><<<(unsigned)nblk, BLK, 0, s>>>(
-                V, ldv, ell, w, nx, ny, F, temporal, part, ww, e2, flow, wo, sj);
+                V, ldv, ell, w, nx, ny, F, temporal, part, ww, e2, flow, wo, cj);
         else if (mode == 1)
             gram_psi_mfma_k<false, false><<<(unsigned)nblk, BLK, 0, s>>>(
-                V, ldv, ell, w, nx, ny, F, temporal, part, ww, e2, flow, wo, sj);
+                V, ldv, ell, w, nx, ny, F, temporal, part, ww, e2, flow, wo, cj);
         else if (mode == 2 && motion)
             gram_psi_mfma_k<true, true><<<(unsigned)nblk, BLK, 0, s>>>(
-                V, ldv, ell, w, nx, ny, F, temporal, part, ww, e2, flow, wo, sj);
+                V, ldv, ell, w, nx, ny, F, temporal, part, ww, e2, flow, wo, cj);
         else
             gram_psi_mfma_k<true, false><<<(unsigned)nblk, BLK, 0, s>>>(
-                V, ldv, ell, w, nx, ny, F, temporal, part, ww, e2, flow, wo, sj);
+                V, ldv, ell, w, nx, ny, F, temporal, part, ww, e2, flow, wo, cj);
     }
-    reduce_gram_k<<<(unsigned)(ell * ell), 64, 0, s>>>(part, nblk, ell, G, ldg);
+    const unsigned rblocks = (unsigned)(ell * ell + (cj.X != nullptr ? cj.ell + 2 : 0));
+    reduce_gram_k<<<rblocks, 64, 0, s>>>(part, nblk, ell, G, ldg, cj);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 
@@ -1861,20 +1896,6 @@ int k_multidot_gram_col(const float *X, int64_t ldx, int ell, const float *xnew,
     multidot_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, ell + 1, xnew, b, n, part, nullptr);
     reduce_vec_k<<<(unsigned)nout, 64, 0, s>>>(part, (int)g, nout, nullptr, 0, nullptr, G, ldg,
                                                rb);
-    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
-}
-
-int k_multidot_gram_col_deferred(const float *X, int64_t ldx, int ell, const float *xnew,
-                                 const float *b, int64_t n, double *part, int nblk, double *G,
-                                 int ldg, double *rb, SideReduce *job, hipStream_t s)
-{
-    const int nout = ell + 2;
-    if (nout > MD_MAX || nblk < 1) return NLRMM_ESHAPE;
-    int64_t g = (n + BLK - 1) / BLK;
-    if (g > nblk) g = nblk;
-    if (g < 1) g = 1;
-    multidot_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, ell + 1, xnew, b, n, part, nullptr);
-    *job = SideReduce{part, (int)g, nout, G, ldg, rb};
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 

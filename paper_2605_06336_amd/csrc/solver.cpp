@@ -51,7 +51,7 @@ struct Solver {
            *part_md = nullptr, *part_md2 = nullptr, *part_gram = nullptr, *part_fwd = nullptr,
            *gkb = nullptr;
     // a data-Gram column whose reduction the next regulariser Gram launch completes
-    SideReduce gc{};
+    GramColJob gc{};
     bool gc_pending = false;
     // VarPro buffers
     float *Ahat = nullptr, *evec = nullptr;
@@ -230,8 +230,9 @@ static int mm_residual(Solver &S, const nlrmm_batch &b, const double *theta, int
 }
 
 // Append one GKS direction (Alg. "enlarge" body after u = V z): residual, CGS2, A v and the
-// new row of the data Gram.  defer: the Gram row's reduction is left to the regulariser Gram
-// launch of the projected solve that follows (one launch fewer per expansion).
+// new row of the data Gram.  defer: the Gram row is left to the regulariser Gram launch of the
+// projected solve that follows, which computes and reduces it with its own work (two launches
+// fewer per expansion).
 static int expand(Solver &S, const nlrmm_batch &b, const double *theta, const float *bvec,
                   hipStream_t s, bool defer = false)
 {
@@ -241,8 +242,8 @@ static int expand(Solver &S, const nlrmm_batch &b, const double *theta, const fl
     RC(cgs2_append(S, ell, s));
     RC(proj_plain(S, b, 1, S.V + (int64_t)ell * S.n, theta, S.AV + (int64_t)ell * m, s));
     if (defer) {
-        RC(k_multidot_gram_col_deferred(S.AV, m, ell, S.AV + (int64_t)ell * m, bvec, m,
-                                        S.part_md, S.md_blocks, S.GA, S.ld, S.rb, &S.gc, s));
+        S.gc = GramColJob{S.AV, m, ell, S.AV + (int64_t)ell * m, bvec, m, S.part_md,
+                          (int64_t)md_part_doubles(S.md_blocks), S.md_blocks, S.GA, S.ld, S.rb};
         S.gc_pending = true;
     } else {
         RC(k_multidot_gram_col(S.AV, m, ell, S.AV + (int64_t)ell * m, bvec, m, S.part_md,
@@ -260,7 +261,7 @@ static int projected_solve(Solver &S, hipStream_t s, const nlrmm_batch *b = null
     // this step's weights (from the u the solve starts from): the Gram and, in the expansion
     // that follows, the residual use them (Alg. "enlarge").  The Gram launch forms them and
     // stores them in S.w, and completes a pending row of the data Gram.
-    const SideReduce *side = S.gc_pending ? &S.gc : nullptr;
+    const GramColJob *side = S.gc_pending ? &S.gc : nullptr;
     S.gc_pending = false;
     RC(k_gram_psi(S.V, S.n, S.ell, nullptr, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.part_gram,
                   S.gram_blocks, S.GP, S.ld, s, S.cfg.gram_precision, S.u, (float)S.cfg.eps,
