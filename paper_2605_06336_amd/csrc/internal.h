@@ -133,15 +133,30 @@ struct TvEpilogue {
     int temporal = 0;
     float e2 = 0.0f;                // eps^2
 };
+// Block partials of the inner products <X_i, x> (i < nv) and <x, x> of the image the
+// backprojection writes, formed by its split-sum launch when the view split has one (the
+// multidot that would read x next is then not needed): one element per thread on
+// ceil(n / 256) blocks, the partials part[block][i] as k_multidot forms them.  Taken only
+// when that grid is at most nblk_cap blocks; fused and nblk report what was done.
+struct MdEpilogue {
+    const float *X = nullptr;
+    int64_t ldx = 0;
+    int nv = 0;
+    double *part = nullptr;
+    int nblk_cap = 0;
+    bool fused = false;
+    int nblk = 0;
+};
 int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
                        const float *y, const double *theta, float *x, hipStream_t s,
-                       int accumulate = 0, const TvEpilogue *tv = nullptr);
+                       int accumulate = 0, const TvEpilogue *tv = nullptr,
+                       MdEpilogue *md = nullptr);
 // The same with the view split's partial images in a caller buffer of part_cap bytes (no
 // workspace growth; NLRMM_ESHAPE when the split needs more); part_buf null: the workspace.
 int launch_backproject_into(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
                             const float *y, const double *theta, float *x, hipStream_t s,
                             int accumulate, const TvEpilogue *tv, float *part_buf,
-                            size_t part_cap);
+                            size_t part_cap, MdEpilogue *md = nullptr);
 // Bytes of partial images the backprojection of this shape uses (0 without a view split).
 size_t bwd_split_bytes(const nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols);
 int launch_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,

@@ -79,10 +79,14 @@ int k_multidot_gram_col(const float *X, int64_t ldx, int ell, const float *xnew,
 // consumer sums its producer's partials itself) while the inner products need at most 512
 // blocks, the launch-per-reduction sequence otherwise (the same arithmetic except for the
 // order in which the block partials are added).
-// part1, part2: md_part_doubles(nblk) doubles each.
+// part1, part2: md_part_doubles(nblk) doubles each.  p1_blocks > 0: part1 already holds the
+// first products <X_i, r>, <r, r> from that many blocks (formed by the launch that wrote r;
+// it must be the grid the first launch here would use, at most 512 blocks).
 int k_cgs2(const float *X, int64_t ldx, int nv, float *r, int64_t n, double *part1,
            double *part2, int nblk, double *h1, double *h2, double tol, float *vout,
-           int *status, hipStream_t s);
+           int *status, hipStream_t s, int p1_blocks = 0);
+// Largest producer grid whose partials k_cgs2's consumers sum themselves.
+constexpr int CGS2_FUSED_MAXBLK = 512;
 // precision 0: FP32 operands, FP64 accumulation (vector units); 2: BF16 operands, FP32
 // accumulation (matrix cores)
 int k_block_update(const float *X, int64_t ldx, int nin, const double *T, int ldt, int kout,

@@ -9,6 +9,7 @@
 // Everything that decides (lambda, breakdown, compression size) is decided on the device.
 #include "internal.h"
 #include "krylov.h"
+#include "multidot.h"
 #include "solve_reg_launch.h"
 #include "tv.h"
 #include "wave.h"
@@ -21,11 +22,14 @@ namespace nlrmm {
 namespace {
 
 constexpr int BLK = 256;
+static_assert(BLK == md::MD_BLK, "one block shape for the shared multidot body");
 constexpr int SOLVE_MAX = 56;
 using wave::dpp_mov;
 using wave::lane_bcast;
 using wave::wave_sum;
 using wave::wave_sum_dpp;
+using md::MD_MAX;
+using md::multidot_body;
 
 constexpr int SOLVE_NT = 256;   // threads of the single-workgroup projected solves   // largest projected problem: two 56x57 FP64 matrices in LDS
 
@@ -213,115 +217,6 @@ __global__ __launch_bounds__(BLK) void gram_psi_k(const float *__restrict__ V, i
             }
     }
 }
-
-constexpr int MD_MAX = 72;   // inner products per multidot launch
-
-// Inner products <X_i, y> (i < nv) and <z, y> (i == nv when z is given), FP64 accumulation:
-// per-block partials part[block][i].  Each block reduces its share of the elements for
-// groups of 16 outputs through LDS (16 threads per output, then a 16-lane butterfly).  The
-// body is shared by multidot_k and the regulariser Gram launch (which runs it first, in its
-// staging area); sacc: 16 x BLK doubles of LDS; ends with a barrier.  With one element per
-// thread the loads of CH outputs are issued together (all of them in multidot_k; fewer inside
-// the Gram launch, whose own work needs few registers).
-template <int CH>
-__device__ __forceinline__ void multidot_body(const float *__restrict__ X, int64_t ldx, int nv,
-                                              const float *__restrict__ y,
-                                              const float *__restrict__ z, int64_t n,
-                                              double *__restrict__ part, double (*sacc)[BLK])
-{
-    constexpr int GRP = 16;            // outputs reduced per LDS round
-    const int tid = threadIdx.x;
-    const int nout = nv + (z != nullptr ? 1 : 0);
-    auto block_reduce = [&](int i0, const double (&acc)[GRP]) __attribute__((always_inline)) {
-#pragma unroll
-        for (int a = 0; a < GRP; ++a) sacc[a][tid] = acc[a];
-        __syncthreads();
-        constexpr int TPO = BLK / GRP;            // threads per output of the group
-        const int a = tid / TPO, l = tid % TPO;
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < BLK / TPO; ++k) s += sacc[a][l + TPO * k];
-        for (int off = TPO / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, TPO);
-        if (l == 0 && i0 + a < nout) part[(int64_t)blockIdx.x * nout + i0 + a] = s;
-        __syncthreads();
-    };
-    if ((int64_t)gridDim.x * BLK >= n) {
-        // at most one element per thread: issue the loads of CH outputs first, then reduce
-        // them by groups (the FP64 product of two floats is exact)
-        static_assert(CH % GRP == 0 || CH == MD_MAX, "chunks of whole groups");
-        const int64_t e = (int64_t)blockIdx.x * BLK + tid;
-        const bool in = e < n;
-        const float ye = in ? y[e] : 0.0f;
-        for (int c0 = 0; c0 < nout; c0 += CH) {
-            float xv[CH];
-#pragma unroll
-            for (int ii = 0; ii < CH; ++ii) {
-                const int i = c0 + ii;
-                float v = 0.0f;
-                if (i < nv) v = in ? X[(int64_t)i * ldx + e] : 0.0f;
-                else if (i == nv && z != nullptr) v = in ? z[e] : 0.0f;
-                xv[ii] = v;
-            }
-#pragma unroll
-            for (int g0 = 0; g0 < CH; g0 += GRP) {
-                if (c0 + g0 < nout) {
-                    double acc[GRP];
-#pragma unroll
-                    for (int a = 0; a < GRP; ++a)
-                        acc[a] = g0 + a < CH ? (double)xv[g0 + a] * (double)ye : 0.0;
-                    block_reduce(c0 + g0, acc);
-                }
-            }
-        }
-        return;
-    }
-    // several elements per thread: 16-byte loads when every column is 16-byte aligned and
-    // n is a multiple of 4 (four times the bytes in flight per load)
-    const bool vec4 = (ldx % 4) == 0 && (n % 4) == 0 &&
-                      (reinterpret_cast<uintptr_t>(X) % 16) == 0 &&
-                      (reinterpret_cast<uintptr_t>(y) % 16) == 0 &&
-                      (z == nullptr || (reinterpret_cast<uintptr_t>(z) % 16) == 0);
-    for (int i0 = 0; i0 < nout; i0 += GRP) {
-        double acc[GRP];
-#pragma unroll
-        for (int a = 0; a < GRP; ++a) acc[a] = 0.0;
-        if (vec4) {
-            const int64_t n4 = n / 4, ld4 = ldx / 4;
-            const float4 *X4 = reinterpret_cast<const float4 *>(X);
-            const float4 *y4 = reinterpret_cast<const float4 *>(y);
-            const float4 *z4 = reinterpret_cast<const float4 *>(z);
-            for (int64_t e = (int64_t)blockIdx.x * BLK + tid; e < n4;
-                 e += (int64_t)gridDim.x * BLK) {
-                const float4 yv = y4[e];
-#pragma unroll
-                for (int a = 0; a < GRP; ++a) {
-                    const int i = i0 + a;
-                    float4 xv = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (i < nv) xv = X4[(int64_t)i * ld4 + e];
-                    else if (i == nv && z != nullptr) xv = z4[e];
-                    double t = acc[a];
-                    t = fma((double)xv.x, (double)yv.x, t);
-                    t = fma((double)xv.y, (double)yv.y, t);
-                    t = fma((double)xv.z, (double)yv.z, t);
-                    acc[a] = fma((double)xv.w, (double)yv.w, t);
-                }
-            }
-        } else {
-            for (int64_t e = (int64_t)blockIdx.x * BLK + tid; e < n;
-                 e += (int64_t)gridDim.x * BLK) {
-                const double ye = (double)y[e];
-#pragma unroll
-                for (int a = 0; a < GRP; ++a) {
-                    const int i = i0 + a;
-                    if (i < nv) acc[a] = fma((double)X[(int64_t)i * ldx + e], ye, acc[a]);
-                    else if (i == nv && z != nullptr) acc[a] = fma((double)z[e], ye, acc[a]);
-                }
-            }
-        }
-        block_reduce(i0, acc);
-    }
-}
-
 
 // MFMA variant of the weighted regulariser Gram (B^T B with B = sqrt(w) * Psi V, B of
 // up to 192 rows per 64-pixel chunk and <= 64 columns).  The chunk's rows are staged in
@@ -1901,13 +1796,16 @@ int k_multidot_gram_col(const float *X, int64_t ldx, int ell, const float *xnew,
 
 int k_cgs2(const float *X, int64_t ldx, int nv, float *r, int64_t n, double *part1,
            double *part2, int nblk, double *h1, double *h2, double tol, float *vout,
-           int *status, hipStream_t s)
+           int *status, hipStream_t s, int p1_blocks)
 {
     if (nv + 1 > MD_MAX || nblk < 1) return NLRMM_ESHAPE;
     int64_t g = (n + BLK - 1) / BLK;
     if (g > nblk) g = nblk;
     if (g < 1) g = 1;
-    if (nv < 1 || g > RR_MAXBLK) {
+    if (p1_blocks > 0) {
+        // the first products came with r, from the launch that wrote it
+        if (p1_blocks != g || g > RR_MAXBLK) return NLRMM_EINVAL;
+    } else if (nv < 1 || g > RR_MAXBLK) {
         // the launch-per-reduction sequence (the same arithmetic)
         int rc;
         if ((rc = k_multidot(X, ldx, nv, r, r, n, part1, nblk, h1, 1, s))) return rc;
@@ -1916,7 +1814,7 @@ int k_cgs2(const float *X, int64_t ldx, int nv, float *r, int64_t n, double *par
         return k_gemv_norm_normalize(X, ldx, nv, h2, r, n, part1, nblk * 72, h1 + nv, tol, vout,
                                      status, s);
     }
-    multidot_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, nv, r, r, n, part1, nullptr);
+    if (p1_blocks == 0) multidot_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, nv, r, r, n, part1, nullptr);
     gemv_multidot_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, nv, r, n, part1, (int)g, part2, h1);
     const unsigned g3 = grid_for(n);
     gemv_norm_red_k<<<g3, BLK, 0, s>>>(X, ldx, nv, r, n, part2, (int)g, h2, part1);

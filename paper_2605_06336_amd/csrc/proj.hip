@@ -34,6 +34,7 @@
 // transposes up to FP32 rounding of the offsets.  The derivative's transpose
 // gathers the chord moments at the same edges the same way.
 #include "internal.h"
+#include "multidot.h"
 #include "tv.h"
 
 #include <math.h>
@@ -996,19 +997,39 @@ __global__ __launch_bounds__(MOM_BLK) void bwd_moment_tiles_k(BwdArgs a)
     if (act1) out[(ibase + l1) * a.nx + k] = (float)(acc1 / a.ds);
 }
 
-__global__ void sum_splits_k(const float *__restrict__ part, int nsplit, int64_t n,
-                             float *__restrict__ x, int accumulate, TvEpilogue tv, int nx, int ny,
-                             int nframes)
+// MD: also the block partials of <X_i, x> (i < nv) and <x, x> over the written image (one
+// element per thread; blocks of 256 threads, as multidot_k forms them).
+struct MdDev {
+    const float *X;
+    int64_t ldx;
+    int nv;
+    double *part;
+};
+
+template <bool MD>
+__global__ __launch_bounds__(256) void sum_splits_k(const float *__restrict__ part, int nsplit,
+                                                    int64_t n, float *__restrict__ x,
+                                                    int accumulate, TvEpilogue tv, int nx, int ny,
+                                                    int nframes, MdDev md)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = accumulate ? (double)x[i] : 0.0;
-    for (int k = 0; k < nsplit; ++k) s += (double)part[k * n + i];
-    float v = (float)s;
-    if (tv.u != nullptr)
-        v += (float)tv.lamp[0] *
-             tv_grad_at(tv.u, tv.w, tvgeo(nx, ny, nframes, tv.temporal), i, tv.e2);
-    x[i] = v;
+    if (i < n) {
+        double s = accumulate ? (double)x[i] : 0.0;
+        for (int k = 0; k < nsplit; ++k) s += (double)part[k * n + i];
+        float v = (float)s;
+        if (tv.u != nullptr)
+            v += (float)tv.lamp[0] *
+                 tv_grad_at(tv.u, tv.w, tvgeo(nx, ny, nframes, tv.temporal), i, tv.e2);
+        x[i] = v;
+    } else if (!MD) {
+        return;
+    }
+    if constexpr (MD) {
+        // every thread takes part (the block reductions have barriers); each reads back only
+        // the element it wrote
+        __shared__ double sacc[16][md::MD_BLK];
+        md::multidot_body<md::MD_MAX>(md.X, md.ldx, md.nv, x, x, n, md.part, sacc);
+    }
 }
 
 int edges_inside(const nlrmm_geom &g)
@@ -1308,8 +1329,8 @@ int launch_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_b
     }
     if (a.nsplit > 1) {
         const int64_t n = (int64_t)ncols * b.nframes * g.nx * g.ny;
-        sum_splits_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a.part, a.nsplit, n, x, 0,
-                                                                 a.tv, g.nx, g.ny, b.nframes);
+        sum_splits_k<false><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
+            a.part, a.nsplit, n, x, 0, a.tv, g.nx, g.ny, b.nframes, MdDev{});
     }
     NLRMM_HIP_CHECK(hipGetLastError());
     return NLRMM_OK;
@@ -1317,9 +1338,10 @@ int launch_backproject_dtheta(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_b
 
 int launch_backproject(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
                        const float *y, const double *theta, float *x, hipStream_t s,
-                       int accumulate, const TvEpilogue *tv)
+                       int accumulate, const TvEpilogue *tv, MdEpilogue *md)
 {
-    return launch_backproject_into(ctx, g, b, ncols, y, theta, x, s, accumulate, tv, nullptr, 0);
+    return launch_backproject_into(ctx, g, b, ncols, y, theta, x, s, accumulate, tv, nullptr, 0,
+                                   md);
 }
 
 size_t bwd_split_bytes(const nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols)
@@ -1330,8 +1352,12 @@ size_t bwd_split_bytes(const nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_ba
 int launch_backproject_into(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b, int ncols,
                             const float *y, const double *theta, float *x, hipStream_t s,
                             int accumulate, const TvEpilogue *tv, float *part_buf,
-                            size_t part_cap)
+                            size_t part_cap, MdEpilogue *md)
 {
+    if (md) {
+        md->fused = false;
+        md->nblk = 0;
+    }
     if (tv && tv->u && ncols != 1) return NLRMM_ENOTSUP;
     if (!bwd_geom_ok(g)) return NLRMM_ESHAPE;
     const int E = edges_inside(g);
@@ -1386,8 +1412,18 @@ int launch_backproject_into(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_bat
     timing_mark(ctx, 1, 1, s);
     if (a.nsplit > 1) {
         const int64_t n = (int64_t)ncols * b.nframes * g.nx * g.ny;
-        sum_splits_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a.part, a.nsplit, n, x, accumulate,
-                                                                 a.tv, g.nx, g.ny, b.nframes);
+        const int64_t nblk = (n + 255) / 256;
+        if (md && md->X && ncols == 1 && nblk <= md->nblk_cap && md->nv >= 1 &&
+            md->nv + 1 <= md::MD_MAX) {
+            sum_splits_k<true><<<(unsigned)nblk, 256, 0, s>>>(
+                a.part, a.nsplit, n, x, accumulate, a.tv, g.nx, g.ny, b.nframes,
+                MdDev{md->X, md->ldx, md->nv, md->part});
+            md->fused = true;
+            md->nblk = (int)nblk;
+        } else {
+            sum_splits_k<false><<<(unsigned)nblk, 256, 0, s>>>(
+                a.part, a.nsplit, n, x, accumulate, a.tv, g.nx, g.ny, b.nframes, MdDev{});
+        }
     }
     NLRMM_HIP_CHECK(hipGetLastError());
     return NLRMM_OK;

@@ -192,18 +192,33 @@ static int gram_from_scratch(Solver &S, int ell, int64_t m, const float *b, hipS
 
 // r <- r - V V^T r twice (CGS2) against the first ell columns; hb[ell] = ||r_in||^2,
 // hb[ell+1] = ||r_out||^2; then V[:, ell] = r_out / ||r_out|| with the breakdown test.
-static int cgs2_append(Solver &S, int ell, hipStream_t s)
+static int cgs2_append(Solver &S, int ell, hipStream_t s, int p1_blocks = 0)
 {
     return k_cgs2(S.V, S.n, ell, S.r, S.n, S.part_md, S.part_md2, S.md_blocks, S.hb, S.hb2,
-                  S.cfg.breakdown_tol, S.V + (int64_t)ell * S.n, S.status, s);
+                  S.cfg.breakdown_tol, S.V + (int64_t)ell * S.n, S.status, s, p1_blocks);
+}
+
+// The first CGS2 products of the residual, formed by the backprojection's split-sum launch
+// when it has one (the multidot's grid: one element per thread, within its block budget).
+static MdEpilogue cgs2_products(const Solver &S, int ell)
+{
+    MdEpilogue md;
+    md.X = S.V;
+    md.ldx = S.n;
+    md.nv = ell;
+    md.part = S.part_md;
+    md.nblk_cap = S.md_blocks < CGS2_FUSED_MAXBLK ? S.md_blocks : CGS2_FUSED_MAXBLK;
+    return md;
 }
 
 // r = A^T (A V z - b) + lam Psi^T (w * Psi u), with u = V z already in S.u.
 // weights_of_u: the weights are those of the current u (formed on the fly); otherwise the
 // stored S.w (the weights of the step's solve).
 static int mm_residual(Solver &S, const nlrmm_batch &b, const double *theta, int ell,
-                       const float *bvec, hipStream_t s, bool weights_of_u = false)
+                       const float *bvec, hipStream_t s, bool weights_of_u = false,
+                       MdEpilogue *md = nullptr)
 {
+    if (md) md->fused = false;
     const bool inl = weights_of_u && S.w_from_u;
     const int64_t m = m_of(S, b);
     if (!S.rho_ready) RC(k_gemv(S.AV, m, ell, S.z, 1.0, bvec, -1.0, m, S.rho, s));
@@ -217,7 +232,7 @@ static int mm_residual(Solver &S, const nlrmm_batch &b, const double *theta, int
         tv.lamp = S.sc + S_LAM;
         tv.temporal = S.cfg.temporal;
         tv.e2 = (float)S.cfg.eps * (float)S.cfg.eps;
-        return launch_backproject(S.ctx, S.g, b, 1, S.rho, theta, S.r, s, 0, &tv);
+        return launch_backproject(S.ctx, S.g, b, 1, S.rho, theta, S.r, s, 0, &tv, md);
     }
     RC(bproj(S, b, S.rho, theta, S.r, s));
     RC(k_tv_grad_add(S.u, inl ? nullptr : S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal,
@@ -238,8 +253,9 @@ static int expand(Solver &S, const nlrmm_batch &b, const double *theta, const fl
 {
     const int ell = S.ell;
     const int64_t m = m_of(S, b);
-    RC(mm_residual(S, b, theta, ell, bvec, s));
-    RC(cgs2_append(S, ell, s));
+    MdEpilogue md = cgs2_products(S, ell);
+    RC(mm_residual(S, b, theta, ell, bvec, s, false, &md));
+    RC(cgs2_append(S, ell, s, md.fused ? md.nblk : 0));
     RC(proj_plain(S, b, 1, S.V + (int64_t)ell * S.n, theta, S.AV + (int64_t)ell * m, s));
     if (defer) {
         S.gc = GramColJob{S.AV, m, ell, S.AV + (int64_t)ell * m, bvec, m, S.part_md,
@@ -550,8 +566,9 @@ static int solver_outer(Solver &S, const nlrmm_batch &b, double *theta, const fl
     }
     // weights from u_{k+1} (formed inside the residual); residual with the old operator H_k;
     // project out; append
-    RC(mm_residual(S, b, S.thk, S.ell, bvec, s, true));
-    RC(cgs2_append(S, S.ell, s));
+    MdEpilogue md = cgs2_products(S, S.ell);
+    RC(mm_residual(S, b, S.thk, S.ell, bvec, s, true, &md));
+    RC(cgs2_append(S, S.ell, s, md.fused ? md.nblk : 0));
     S.ell += 1;
     (void)m;
     return NLRMM_OK;
