@@ -36,6 +36,7 @@
 #include "internal.h"
 #include "multidot.h"
 #include "tv.h"
+#include "wave.h"
 
 #include <math.h>
 
@@ -226,43 +227,6 @@ __global__ __launch_bounds__(BLK) void pack_lines_k(const float *__restrict__ x,
     if (tid == 0) tot[img * nlines + line] = sP[n];
 }
 
-// Exclusive prefix of the line totals: pre[img][0..nlines]; blockIdx.y selects rows (0) or
-// columns (1).
-__global__ __launch_bounds__(BLK) void line_prefix_k(const double *__restrict__ rowtot,
-                                                     const double *__restrict__ coltot, int nx,
-                                                     int ny, double *__restrict__ rowpre,
-                                                     double *__restrict__ colpre)
-{
-    __shared__ double swave[BLK / 64];
-    const bool rows = blockIdx.y == 0;
-    const double *tot = rows ? rowtot : coltot;
-    const int nlines = rows ? ny : nx;
-    double *pre = rows ? rowpre : colpre;
-    const int64_t img = blockIdx.x;
-    const double *t = tot + img * nlines;
-    double *p = pre + img * (int64_t)(nlines + 1);
-    const int tid = threadIdx.x;
-    const int cpt = (nlines + BLK - 1) / BLK;
-    const int i0 = min(tid * cpt, nlines), i1 = min(i0 + cpt, nlines);
-    double ls = 0.0;
-    for (int i = i0; i < i1; ++i) ls += t[i];
-    const int lane = tid & 63, wv = tid >> 6;
-    double incl = ls;
-    for (int off = 1; off < 64; off <<= 1) {
-        const double u = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += u;
-    }
-    if (lane == 63) swave[wv] = incl;
-    __syncthreads();
-    double run = incl - ls;
-    for (int w = 0; w < wv; ++w) run += swave[w];
-    for (int i = i0; i < i1; ++i) {
-        p[i] = run;
-        run += t[i];
-    }
-    if (tid == BLK - 1) p[nlines] = run;
-}
-
 // ---------------------------------------------------------------------------
 // forward: projection and angle derivative, edge-driven
 // ---------------------------------------------------------------------------
@@ -293,8 +257,8 @@ struct FwdArgs {
     const PackEntry *colpack;   // [img][nx][ny+3]
     const PackEntry *rowpack_m; // mirrored lines, same layout
     const PackEntry *colpack_m;
-    const double *rowpre;       // [img][ny+1]
-    const double *colpre;       // [img][nx+1]
+    const double *rowtot;       // line totals [img][ny]
+    const double *coltot;       // [img][nx]
     const double *theta;
     const int64_t *view_off;
     int nframes;
@@ -377,9 +341,9 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
     // descending walks read the mirrored packs, so every walk advances through its pack
     const PackEntry *pack = steep ? (asc ? a.rowpack : a.rowpack_m)
                                   : (asc ? a.colpack : a.colpack_m);
-    const double *pre = steep ? a.rowpre : a.colpre;
+    const double *ltot = steep ? a.rowtot : a.coltot;
     const int64_t pstride = (int64_t)nlines * (nminor + 3);
-    const int64_t tstride = nlines + 1;
+    const int64_t tstride = nlines;
     const int64_t img0 = (int64_t)c0 * a.nframes + f;
     const int64_t cstride = a.nframes;   // images between consecutive columns
 
@@ -576,22 +540,40 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
         };
         if (asc) walk(std::true_type{});
         else walk(std::false_type{});
-        if (PROJ && seg == 0 && live) {
+        if (PROJ && seg == 0) {
             // lines outside the union that lie wholly on the lower side of this edge: for
-            // sl > 0 the lines below la, for sl < 0 the lines above lb
+            // sl > 0 the lines below la, for sl < 0 the lines above lb.  A live edge has
+            // WA <= la <= lb + 1 <= WB + 1, so these are the lines below WA (sl > 0) or above
+            // WB (sl < 0): two sums over the line totals shared by the wave (lanes strided
+            // over the lines, a fixed DPP reduction); the other terms are kept for exactness.
+            auto range = [&](const double *lt, int l0, int l1) {
+                double t = 0.0;
+                for (int l = l0; l < l1; ++l) t += lt[l];
+                return t;
+            };
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                if (c < nc) {
-                    const double *lt = pre + (img0 + c * cstride) * tstride;
-                    double add = 0.0;
-                    if (sl > 0.0) {
-                        add += lt[min(la, WA)];
-                        if (la > WB + 1) add += lt[la] - lt[WB + 1];
-                    } else if (sl < 0.0) {
-                        if (lb + 1 < WA) add += lt[WA] - lt[lb + 1];
-                        add += lt[nlines] - lt[max(lb + 1, WB + 1)];
+                if (c < nc && sl != 0.0) {
+                    const double *lt = ltot + (img0 + c * cstride) * tstride;
+                    double below = 0.0, above = 0.0;
+                    for (int l = lane; l < nlines; l += 64) {
+                        const double t = lt[l];
+                        if (l < WA) below += t;
+                        else if (l > WB) above += t;
                     }
-                    accP[c] += add;
+                    below = wave::wave_sum_dpp(below);
+                    above = wave::wave_sum_dpp(above);
+                    if (live) {
+                        double add = 0.0;
+                        if (sl > 0.0) {
+                            add += la >= WA ? below : range(lt, 0, la);
+                            if (la > WB + 1) add += range(lt, WB + 1, la);
+                        } else {
+                            if (lb + 1 < WA) add += range(lt, lb + 1, WA);
+                            add += lb <= WB ? above : range(lt, lb + 1, nlines);
+                        }
+                        accP[c] += add;
+                    }
                 }
             }
         }
@@ -1067,8 +1049,6 @@ static size_t fwd_ws_bytes(const nlrmm_geom &g, int nframes, int gcols, int64_t 
     b += 2 * al(sizeof(PackEntry) * nimg * ny * (nx + 3));   // row packs, direct and mirrored
     b += 2 * al(sizeof(PackEntry) * nimg * nx * (ny + 3));   // column packs, likewise
     b += al(sizeof(double) * nimg * (ny + nx));              // line totals
-    b += al(sizeof(double) * nimg * (ny + 1));               // row-total prefixes
-    b += al(sizeof(double) * nimg * (nx + 1));               // column-total prefixes
     b += al(sizeof(double) * 2 * (size_t)ncols_total * V * nchunks);   // reduction partials
     return b;
 }
@@ -1140,10 +1120,6 @@ int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
     p += al(sizeof(PackEntry) * (int64_t)gcols * F * nx * (ny + 3));
     double *tot = (double *)p;
     p += al(sizeof(double) * (int64_t)gcols * F * (ny + nx));
-    double *rowpre = (double *)p;
-    p += al(sizeof(double) * (int64_t)gcols * F * (ny + 1));
-    double *colpre = (double *)p;
-    p += al(sizeof(double) * (int64_t)gcols * F * (nx + 1));
     if (red && part == nullptr) part = (double *)p;
 
     const int64_t npix = nx * ny;
@@ -1151,20 +1127,18 @@ int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
         const int nc = ncols - cbeg < gcols ? ncols - cbeg : gcols;
         const int64_t nimg = (int64_t)nc * F;
         const float *xg = x + (int64_t)cbeg * F * npix;
-        // row and column packs of every image in one launch, then both line prefixes
+        // row and column packs of every image in one launch (with the line totals)
         double *ctot = tot + nimg * ny;
         pack_lines_k<<<dim3((unsigned)(ny + nx), (unsigned)nimg), BLK, 0, s>>>(
             xg, (int)nx, (int)ny, rowpack, colpack, rowpack_m, colpack_m, tot, ctot);
-        line_prefix_k<<<dim3((unsigned)nimg, 2), BLK, 0, s>>>(tot, ctot, (int)nx, (int)ny, rowpre,
-                                                             colpre);
 
         FwdArgs a;
         a.rowpack = rowpack;
         a.colpack = colpack;
         a.rowpack_m = rowpack_m;
         a.colpack_m = colpack_m;
-        a.rowpre = rowpre;
-        a.colpre = colpre;
+        a.rowtot = tot;
+        a.coltot = ctot;
         a.theta = theta;
         a.view_off = b.view_off;
         a.nframes = F;
