@@ -108,6 +108,17 @@ struct FwdOptions {
     double *part_buf = nullptr;    // caller-provided partials [3][col][V][nchunks]
     bool keep_parts = false;       // leave per-chunk partials unreduced (caller reduces)
     bool write_resid = false;      // with bres: y receives y - b
+    // Normalisation folded into the packing launch (one column; x is then not read): the image
+    // packed, and written to norm_out, is norm_src / ||norm_src|| with the squared norm summed
+    // from norm_nblk block partials norm_part as the Krylov normalisation sums them; that sets
+    // norm_scal[1] to it and tests for breakdown against sqrt(norm_scal[0]) (norm_status).
+    const float *norm_src = nullptr;
+    const double *norm_part = nullptr;
+    int norm_nblk = 0;
+    double *norm_scal = nullptr;
+    double norm_tol = 0.0;
+    float *norm_out = nullptr;
+    int *norm_status = nullptr;
 };
 
 // Geometry limits of the projector kernels (proj.hip): the forward family needs nx, ny <=

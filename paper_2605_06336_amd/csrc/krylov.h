@@ -82,9 +82,15 @@ int k_multidot_gram_col(const float *X, int64_t ldx, int ell, const float *xnew,
 // part1, part2: md_part_doubles(nblk) doubles each.  p1_blocks > 0: part1 already holds the
 // first products <X_i, r>, <r, r> from that many blocks (formed by the launch that wrote r;
 // it must be the grid the first launch here would use, at most 512 blocks).
+// norm_blocks: the normalisation is left to the caller (k_normalize_red, or the projection's
+// packing launch); part1 then holds the squared norm's partials from *norm_blocks blocks.
 int k_cgs2(const float *X, int64_t ldx, int nv, float *r, int64_t n, double *part1,
            double *part2, int nblk, double *h1, double *h2, double tol, float *vout,
-           int *status, hipStream_t s, int p1_blocks = 0);
+           int *status, hipStream_t s, int p1_blocks = 0, int *norm_blocks = nullptr);
+// vout = r / sqrt(sum of part[0..nblk)), scal[1] = that sum, breakdown test against
+// sqrt(scal[0]) (the last launch of k_cgs2).
+int k_normalize_red(const float *r, const double *part, int nblk, double *scal, double tol,
+                    int64_t n, float *vout, int *status, hipStream_t s);
 // Largest producer grid whose partials k_cgs2's consumers sum themselves.
 constexpr int CGS2_FUSED_MAXBLK = 512;
 // precision 0: FP32 operands, FP64 accumulation (vector units); 2: BF16 operands, FP32

@@ -1796,30 +1796,49 @@ int k_multidot_gram_col(const float *X, int64_t ldx, int ell, const float *xnew,
 
 int k_cgs2(const float *X, int64_t ldx, int nv, float *r, int64_t n, double *part1,
            double *part2, int nblk, double *h1, double *h2, double tol, float *vout,
-           int *status, hipStream_t s, int p1_blocks)
+           int *status, hipStream_t s, int p1_blocks, int *norm_blocks)
 {
     if (nv + 1 > MD_MAX || nblk < 1) return NLRMM_ESHAPE;
     int64_t g = (n + BLK - 1) / BLK;
     if (g > nblk) g = nblk;
     if (g < 1) g = 1;
+    const unsigned g3 = grid_for(n);   // blocks of the norm partials (<= 4096 <= 72 nblk)
     if (p1_blocks > 0) {
         // the first products came with r, from the launch that wrote it
         if (p1_blocks != g || g > RR_MAXBLK) return NLRMM_EINVAL;
     } else if (nv < 1 || g > RR_MAXBLK) {
-        // the launch-per-reduction sequence (the same arithmetic)
+        // a launch per reduction (the same arithmetic except for the order of the block sums)
         int rc;
         if ((rc = k_multidot(X, ldx, nv, r, r, n, part1, nblk, h1, 1, s))) return rc;
         if ((rc = k_gemv(X, ldx, nv, h1, -1.0, r, 1.0, n, r, s))) return rc;
         if ((rc = k_multidot(X, ldx, nv, r, nullptr, n, part1, nblk, h2, 1, s))) return rc;
-        return k_gemv_norm_normalize(X, ldx, nv, h2, r, n, part1, nblk * 72, h1 + nv, tol, vout,
-                                     status, s);
+        gemv_norm_k<<<g3, BLK, 0, s>>>(X, ldx, nv, h2, r, n, r, part1);
+        if (norm_blocks) {
+            *norm_blocks = (int)g3;
+        } else {
+            normalize_red_k<<<(unsigned)((n + BLK - 1) / BLK), BLK, 0, s>>>(
+                r, part1, (int)g3, h1 + nv, tol, n, vout, status);
+        }
+        return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
     }
     if (p1_blocks == 0) multidot_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, nv, r, r, n, part1, nullptr);
     gemv_multidot_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, nv, r, n, part1, (int)g, part2, h1);
-    const unsigned g3 = grid_for(n);
     gemv_norm_red_k<<<g3, BLK, 0, s>>>(X, ldx, nv, r, n, part2, (int)g, h2, part1);
-    normalize_red_k<<<(unsigned)((n + BLK - 1) / BLK), BLK, 0, s>>>(r, part1, (int)g3, h1 + nv,
-                                                                    tol, n, vout, status);
+    if (norm_blocks) {
+        *norm_blocks = (int)g3;
+    } else {
+        normalize_red_k<<<(unsigned)((n + BLK - 1) / BLK), BLK, 0, s>>>(r, part1, (int)g3,
+                                                                        h1 + nv, tol, n, vout,
+                                                                        status);
+    }
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_normalize_red(const float *r, const double *part, int nblk, double *scal, double tol,
+                    int64_t n, float *vout, int *status, hipStream_t s)
+{
+    normalize_red_k<<<(unsigned)((n + BLK - 1) / BLK), BLK, 0, s>>>(r, part, nblk, scal, tol, n,
+                                                                    vout, status);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 

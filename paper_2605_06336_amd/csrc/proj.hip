@@ -162,29 +162,71 @@ __device__ __forceinline__ T wave_sum(T v)
 // so that the walk needs only the odd part psi_h); tot = the line's sum.  The mirrored
 // pack holds the same entries for the reversed line (pixel i of it is pixel n-1-i), so a
 // walk against the pixel order reads its prefix directly.
+// Normalisation applied while packing (see FwdOptions): src / sqrt(sum of part), written to
+// out by the row blocks.
+struct NormJob {
+    const float *src;
+    const double *part;
+    int nblk;
+    double *scal;
+    double tol;
+    float *out;
+    int *status;
+};
+
 __global__ __launch_bounds__(BLK) void pack_lines_k(const float *__restrict__ x, int nx, int ny,
                                                     PackEntry *__restrict__ rowpack,
                                                     PackEntry *__restrict__ colpack,
                                                     PackEntry *__restrict__ rowpack_m,
                                                     PackEntry *__restrict__ colpack_m,
                                                     double *__restrict__ rowtot,
-                                                    double *__restrict__ coltot)
+                                                    double *__restrict__ coltot, NormJob nj)
 {
     __shared__ float sx[MAX_LINE + 2];
     __shared__ double sP[MAX_LINE + 1];
     __shared__ double swave[BLK / 64];
+    __shared__ double sinv;
     const bool is_row = (int)blockIdx.x < ny;
     const int64_t line = is_row ? blockIdx.x : blockIdx.x - ny;
     const int n = is_row ? nx : ny;
     const int nlines = is_row ? ny : nx;
     const int64_t img = blockIdx.y;
-    const float *src = x + img * (int64_t)nx * ny;
+    const bool norm = nj.part != nullptr;
+    const float *src = (norm ? nj.src : x) + img * (int64_t)nx * ny;
     const int64_t step = is_row ? 1 : nx;
     const float *row = src + (is_row ? line * nx : line);
     PackEntry *pack = is_row ? rowpack : colpack;
     double *tot = is_row ? rowtot : coltot;
     const int tid = threadIdx.x;
-    for (int i = tid; i < n; i += BLK) sx[i] = row[i * step];
+    if (norm) {
+        // the squared norm as the Krylov normalisation sums it (lane-strided partials, then
+        // the butterfly), its breakdown test once
+        if (tid < 64) {
+            double t = 0.0;
+            for (int b = tid; b < nj.nblk; b += 64) t += nj.part[b];
+            t = wave_sum(t);
+            const double raw = sqrt(fmax(nj.scal[0], 0.0));
+            const double perp = sqrt(fmax(t, 0.0));
+            if (tid == 0) {
+                sinv = perp > 0.0 ? 1.0 / perp : 0.0;
+                if (blockIdx.x == 0 && blockIdx.y == 0) {
+                    nj.scal[1] = t;
+                    if (!(perp > nj.tol * raw)) atomicOr(nj.status, NLRMM_ST_BREAKDOWN);
+                    if (!isfinite(perp)) atomicOr(nj.status, NLRMM_ST_NONFINITE);
+                }
+            }
+        }
+        __syncthreads();
+        const double inv = sinv;
+        float *orow = nj.out + img * (int64_t)nx * ny + line * nx;
+        for (int i = tid; i < n; i += BLK) {
+            const float v = (float)((double)row[i * step] * inv);
+            sx[i] = v;
+            if (is_row) orow[i] = v;
+        }
+    } else {
+        for (int i = tid; i < n; i += BLK) sx[i] = row[i * step];
+    }
     if (tid < 2) sx[n + tid] = 0.0f;
     __syncthreads();
     const int cpt = (n + BLK - 1) / BLK;
@@ -1099,6 +1141,9 @@ int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
     const bool proj = o.y != nullptr || o.bres != nullptr;
     const bool red = o.gdot || o.dnorm2 || o.rnorm2;
     if (o.bres && !proj) return NLRMM_ENOTSUP;
+    if (o.norm_part && (ncols != 1 || !o.norm_src || !o.norm_scal || !o.norm_out ||
+                        !o.norm_status || o.norm_nblk < 1))
+        return NLRMM_ENOTSUP;
     const int GC = 8;                       // columns prepared per group
     const int gcols = ncols < GC ? ncols : GC;
     size_t need = fwd_ws_bytes(g, F, gcols, V, nchunks, 0);
@@ -1129,8 +1174,10 @@ int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
         const float *xg = x + (int64_t)cbeg * F * npix;
         // row and column packs of every image in one launch (with the line totals)
         double *ctot = tot + nimg * ny;
+        NormJob nj{o.norm_src, o.norm_part, o.norm_nblk, o.norm_scal, o.norm_tol, o.norm_out,
+                   o.norm_status};
         pack_lines_k<<<dim3((unsigned)(ny + nx), (unsigned)nimg), BLK, 0, s>>>(
-            xg, (int)nx, (int)ny, rowpack, colpack, rowpack_m, colpack_m, tot, ctot);
+            xg, (int)nx, (int)ny, rowpack, colpack, rowpack_m, colpack_m, tot, ctot, nj);
 
         FwdArgs a;
         a.rowpack = rowpack;

@@ -192,10 +192,12 @@ static int gram_from_scratch(Solver &S, int ell, int64_t m, const float *b, hipS
 
 // r <- r - V V^T r twice (CGS2) against the first ell columns; hb[ell] = ||r_in||^2,
 // hb[ell+1] = ||r_out||^2; then V[:, ell] = r_out / ||r_out|| with the breakdown test.
-static int cgs2_append(Solver &S, int ell, hipStream_t s, int p1_blocks = 0)
+static int cgs2_append(Solver &S, int ell, hipStream_t s, int p1_blocks = 0,
+                       int *norm_blocks = nullptr)
 {
     return k_cgs2(S.V, S.n, ell, S.r, S.n, S.part_md, S.part_md2, S.md_blocks, S.hb, S.hb2,
-                  S.cfg.breakdown_tol, S.V + (int64_t)ell * S.n, S.status, s, p1_blocks);
+                  S.cfg.breakdown_tol, S.V + (int64_t)ell * S.n, S.status, s, p1_blocks,
+                  norm_blocks);
 }
 
 // The first CGS2 products of the residual, formed by the backprojection's split-sum launch
@@ -255,8 +257,27 @@ static int expand(Solver &S, const nlrmm_batch &b, const double *theta, const fl
     const int64_t m = m_of(S, b);
     MdEpilogue md = cgs2_products(S, ell);
     RC(mm_residual(S, b, theta, ell, bvec, s, false, &md));
-    RC(cgs2_append(S, ell, s, md.fused ? md.nblk : 0));
-    RC(proj_plain(S, b, 1, S.V + (int64_t)ell * S.n, theta, S.AV + (int64_t)ell * m, s));
+    // the new column's normalisation rides on the packing launch of its projection (batched
+    // launches; per-frame launches normalise first)
+    float *vnew = S.V + (int64_t)ell * S.n;
+    int nblk3 = 0;
+    RC(cgs2_append(S, ell, s, md.fused ? md.nblk : 0, &nblk3));
+    if (per_frame(S, b)) {
+        RC(k_normalize_red(S.r, S.part_md, nblk3, S.hb + ell, S.cfg.breakdown_tol, S.n, vnew,
+                           S.status, s));
+        RC(proj_plain(S, b, 1, vnew, theta, S.AV + (int64_t)ell * m, s));
+    } else {
+        FwdOptions o;
+        o.y = S.AV + (int64_t)ell * m;
+        o.norm_src = S.r;
+        o.norm_part = S.part_md;
+        o.norm_nblk = nblk3;
+        o.norm_scal = S.hb + ell;
+        o.norm_tol = S.cfg.breakdown_tol;
+        o.norm_out = vnew;
+        o.norm_status = S.status;
+        RC(proj(S, b, 1, vnew, theta, o, s));
+    }
     if (defer) {
         S.gc = GramColJob{S.AV, m, ell, S.AV + (int64_t)ell * m, bvec, m, S.part_md,
                           (int64_t)md_part_doubles(S.md_blocks), S.md_blocks, S.GA, S.ld, S.rb};
