@@ -33,8 +33,8 @@ struct GramColJob {
 // mode: 0 FP64 VALU, 1 FP32 MFMA, 2 BF16 MFMA (FP32 accumulation per chunk, FP64 across)
 // w == nullptr: the weights are formed from u with eps (inside the kernel in modes 1, 2);
 // with wout they are also stored there (as k_psi_weights stores them).  col: a pending
-// data-Gram column, computed inside this launch and reduced with the Gram (modes 1, 2), or by
-// k_multidot_gram_col first (mode 0, or when its partials do not fit part_cap).
+// data-Gram column, computed inside this launch and reduced with the Gram (mode 1), or by
+// k_multidot_gram_col first (modes 0 and 2, or when its partials do not fit part_cap).
 int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int ny, int F,
                int temporal, double *part, int nblk, double *G, int ldg, hipStream_t s,
                int mode = 0, const float *u = nullptr, float eps = 0.0f,

@@ -262,15 +262,21 @@ __global__ __launch_bounds__(BLK, 3) void gram_psi_mfma_k(const float *__restric
     // (four consecutive rows of a column are then one 8-byte MFMA operand)
     using Elem = typename std::conditional<BF16, short, float>::type;
     constexpr int LD = BF16 ? MLDH : MLDR;
+    // A pending data-Gram column is taken by the FP32 instances only: its registers would
+    // halve the occupancy of the BF16 ones (whose LDS tile allows six waves per SIMD).
+    constexpr bool COLJOB = !BF16;
     // staging area, also the reduction buffer of a pending data-Gram column (16 x BLK doubles)
     constexpr size_t SB_BYTES = sizeof(Elem) * 64 * LD;
-    constexpr size_t RAW = SB_BYTES > 16 * BLK * sizeof(double) ? SB_BYTES : 16 * BLK * sizeof(double);
+    constexpr size_t CB = COLJOB ? 16 * BLK * sizeof(double) : 0;
+    constexpr size_t RAW = SB_BYTES > CB ? SB_BYTES : CB;
     __shared__ __align__(16) unsigned char sraw[RAW];
     Elem(*sB)[LD] = reinterpret_cast<Elem(*)[LD]>(sraw);
     // a pending data-Gram column first (its inner products need no part of this Gram)
-    if (col.X != nullptr)
-        multidot_body<32>(col.X, col.ldx, col.ell + 1, col.xnew, col.b, col.n, col.part,
-                      reinterpret_cast<double(*)[BLK]>(sraw));
+    if constexpr (COLJOB) {
+        if (col.X != nullptr)
+            multidot_body<32>(col.X, col.ldx, col.ell + 1, col.xnew, col.b, col.n, col.part,
+                              reinterpret_cast<double(*)[BLK]>(sraw));
+    }
     const TVGeo g = tvgeo(nx, ny, F, temporal, flow);
     // MOTION: the launch has the optical-flow rows (temporal mode 2 with several frames)
     constexpr bool motion = MOTION;
@@ -1723,7 +1729,7 @@ int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int
     const bool motion = temporal == TEMPORAL_OF && F > 1;
     GramColJob cj{};   // X == nullptr: no column inside this launch
     if (col != nullptr && col->X != nullptr) {
-        if (mode != 0 && col->ell + 2 <= MD_MAX &&
+        if (mode == 1 && col->ell + 2 <= MD_MAX &&
             (int64_t)nblk * (col->ell + 2) <= col->part_cap) {
             cj = *col;
         } else {
