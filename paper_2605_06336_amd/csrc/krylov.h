@@ -103,9 +103,12 @@ int k_normalize_into(const float *r, const double *scal, double tol, int64_t n, 
                      int *status, double *norm_out, hipStream_t s);
 // method: 0 Jacobi eigen-decomposition (4 waves), 1 register-resident tridiagonal form,
 // 2 LDS tridiagonal form
+// Lst (method 1 only; ldg * ldg + ldg doubles): receives the Cholesky factor of GA and its
+// reciprocal diagonal; linc: it holds them for the leading ell - 1 rows and columns of this GA
+// (one row and column appended since), so only the new row is formed.
 int k_gks_solve(const double *GA, const double *GP, int ldg, const double *rb, const double *scal,
                 int ell, double lam_fix, double *z, double *out, int *status, hipStream_t s,
-                int method = 1);
+                int method = 1, double *Lst = nullptr, int linc = 0);
 // method: 0 Jacobi (4 waves), 1 tridiagonal + Sturm bisection + inverse iteration (1 wave)
 int k_compress_eig(const double *GA, const double *GP, int ldg, const double *lam, int ell,
                    int kmin, const double *z, double *T, int ldt, double *zout, int *kout,

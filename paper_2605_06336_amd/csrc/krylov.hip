@@ -1913,16 +1913,17 @@ int k_normalize_into(const float *r, const double *scal, double tol, int64_t n, 
 
 int k_gks_solve(const double *GA, const double *GP, int ldg, const double *rb, const double *scal,
                 int ell, double lam_fix, double *z, double *out, int *status, hipStream_t s,
-                int method)
+                int method, double *Lst, int linc)
 {
     if (ell < 1 || ell > SOLVE_MAX) return NLRMM_ESHAPE;
+    if ((Lst != nullptr || linc) && method != 1) return NLRMM_EINVAL;
     if (method == 1) {
         const int nb = (ell + 8) / 8 * 8;   // padded size >= ell + 1
         switch (nb) {
 #define NLRMM_REG_CASE(NB)                                                                        \
     case NB:                                                                                      \
         return reg::launch_gks_solve_reg<NB>(GA, GP, ldg, rb, scal, ell, lam_fix, z, out, status, \
-                                             s);
+                                             s, Lst, linc);
             NLRMM_REG_CASE(8)
             NLRMM_REG_CASE(16)
             NLRMM_REG_CASE(24)

@@ -190,14 +190,15 @@ __device__ __forceinline__ double dp_residual(double lam, double l2, const doubl
     return out2 + cn2 * (fma(Q, Q, S) / (P0 * P0));
 }
 
-template <int NB>
+template <int NB, bool INC>
 __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__ GA,
                                                      const double *__restrict__ GP, int ldg,
                                                      const double *__restrict__ rb,
                                                      const double *__restrict__ scal, int ell,
                                                      double lam_fix, double *__restrict__ z,
                                                      double *__restrict__ out,
-                                                     int *__restrict__ status)
+                                                     int *__restrict__ status,
+                                                     double *__restrict__ Lst)
 {
     constexpr int LD = NB + 2;
     __shared__ double sLt[NB * LD];   // sLt[k * LD + c] = L[c][k]
@@ -209,37 +210,85 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
     const double trA = wave_sum_dpp(lane < n ? GA[lane * ldg + lane] : 0.0);
     const double trP = wave_sum_dpp(lane < n ? GP[lane * ldg + lane] : 0.0);
     double a[NB], p[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c)
-        a[c] = (lane < n && c < n) ? GA[lane * ldg + c] : (lane == c ? 1.0 : 0.0);
-    // 1. Cholesky GA = L L^T (lane i ends with row i of L; its upper part is never read).
-    //    The unscaled column is broadcast while the pivot reciprocal is formed, and the update
-    //    uses A_ij A_kj / pivot, so the square root stays off the dependency chain.
     int bad = 0;
-    StaticFor<0, NB>::run([&](auto J) __attribute__((always_inline)) {
-        constexpr int j = decltype(J)::value;
-        sv[lane] = a[j];
-        __syncthreads();
-        double lc[NB];
+    // L (rows, lane i = row i) and its reciprocal diagonal are kept in Lst[i * ldg + k] and
+    // Lst[ldg * ldg + i] for the next solve.  INC: Lst holds the factor of the leading
+    // ell - 1 rows and columns of this GA (the previous solve's, before one row and column
+    // were appended), so only the new row is formed (a kernel of its own: one straight path
+    // keeps the row in registers).
+    double *const Ldi = Lst != nullptr ? Lst + (int64_t)ldg * ldg : nullptr;
+    if constexpr (INC) {
+        // New row by forward substitution x = L^-1 g, g = GA[ell-1][0..ell-2]: lane k holds row
+        // k of L, its g_k, its reciprocal diagonal and the running sum s_k; step j takes x_j
+        // = (g_j - s_j) / L_jj from lane j and every lane adds L_kj x_j.  Lane ell-1 collects
+        // the x_j (its row) and their squares, so at step ell-1 its own value is the pivot
+        // g_nn - sum x_j^2; the steps beyond are identity rows (x = 0).  No branches: the row
+        // stays in registers.
+        const int nm = n - 1;
 #pragma unroll
-        for (int k = j + 1; k < NB; ++k) lc[k] = sv[k];
-        double piv = lane_bcast(a[j], j);
+        for (int c = 0; c < NB; ++c)
+            a[c] = (lane < nm && c < nm) ? Lst[lane * ldg + c] : ((lane >= n && lane == c) ? 1.0 : 0.0);
+        const double g = lane < n ? GA[lane * ldg + nm] : 0.0;
+        const double inv = lane < nm ? Ldi[lane] : 1.0;
+        double acc = 0.0, piv = 0.0;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const double xj = lane_bcast((g - acc) * inv, j);
+            piv = (j == nm) ? xj : piv;
+            a[j] = (lane == nm && j < nm) ? xj : a[j];
+            acc = fma(a[j], xj, acc);
+        }
         if (!(piv > 0.0)) {
             bad = 1;
             piv = 1e-300;
         }
-        const double r = rcp_nr(piv);
-        __builtin_amdgcn_sched_barrier(0);
-        const double t = a[j] * r;
-#pragma unroll
-        for (int k = j + 1; k < NB; ++k) a[k] = fma(-t, lc[k], a[k]);
         const double d = sqrt(piv);
         const double di = rcp_nr(d);
-        a[j] = (lane == j) ? d : a[j] * di;
-        sdi[j] = di;
-        pin_regs(a);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) a[j] = (lane == nm && j == nm) ? d : a[j];
+        sdi[lane] = lane < nm ? inv : (lane == nm ? di : 1.0);
         __syncthreads();
-    });
+    } else {
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            a[c] = (lane < n && c < n) ? GA[lane * ldg + c] : (lane == c ? 1.0 : 0.0);
+        // 1. Cholesky GA = L L^T (lane i ends with row i of L; its upper part is never read).
+        //    The unscaled column is broadcast while the pivot reciprocal is formed, and the
+        //    update uses A_ij A_kj / pivot, so the square root stays off the dependency chain.
+        StaticFor<0, NB>::run([&](auto J) __attribute__((always_inline)) {
+            constexpr int j = decltype(J)::value;
+            sv[lane] = a[j];
+            __syncthreads();
+            double lc[NB];
+    #pragma unroll
+            for (int k = j + 1; k < NB; ++k) lc[k] = sv[k];
+            double piv = lane_bcast(a[j], j);
+            if (!(piv > 0.0)) {
+                bad = 1;
+                piv = 1e-300;
+            }
+            const double r = rcp_nr(piv);
+            __builtin_amdgcn_sched_barrier(0);
+            const double t = a[j] * r;
+    #pragma unroll
+            for (int k = j + 1; k < NB; ++k) a[k] = fma(-t, lc[k], a[k]);
+            const double d = sqrt(piv);
+            const double di = rcp_nr(d);
+            a[j] = (lane == j) ? d : a[j] * di;
+            sdi[j] = di;
+            pin_regs(a);
+            __syncthreads();
+        });
+    }
+    if (Lst != nullptr) {
+        // this factor for the next solve (only the new row when it was appended)
+        if (lane < n && (!INC || lane == n - 1)) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+                if (c < n) Lst[lane * ldg + c] = a[c];
+        }
+        if (lane < n) Ldi[lane] = sdi[lane];
+    }
     if (row) {
 #pragma unroll
         for (int k = 0; k < NB; ++k) sLt[k * LD + lane] = a[k];
@@ -710,9 +759,15 @@ __global__ __launch_bounds__(64) void compress_reg_k(const double *__restrict__ 
 template <int NB>
 int launch_gks_solve_reg(const double *GA, const double *GP, int ldg, const double *rb,
                          const double *scal, int ell, double lam_fix, double *z, double *out,
-                         int *status, hipStream_t s)
+                         int *status, hipStream_t s, double *Lst, int linc)
 {
-    gks_solve_reg_k<NB><<<1, 64, 0, s>>>(GA, GP, ldg, rb, scal, ell, lam_fix, z, out, status);
+    if (linc && (Lst == nullptr || ell < 1)) return NLRMM_EINVAL;
+    if (linc)
+        gks_solve_reg_k<NB, true><<<1, 64, 0, s>>>(GA, GP, ldg, rb, scal, ell, lam_fix, z, out,
+                                                   status, Lst);
+    else
+        gks_solve_reg_k<NB, false><<<1, 64, 0, s>>>(GA, GP, ldg, rb, scal, ell, lam_fix, z, out,
+                                                    status, Lst);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 

@@ -6,7 +6,7 @@ namespace reg {
 
 template int launch_gks_solve_reg<48>(const double *, const double *, int, const double *,
                                           const double *, int, double, double *, double *,
-                                          int *, hipStream_t);
+                                          int *, hipStream_t, double *, int);
 template int launch_compress_reg<48>(const double *, const double *, int, const double *,
                                          int, int, const double *, double *, int, double *,
                                          int *, int *, hipStream_t);

@@ -6,10 +6,13 @@
 namespace nlrmm {
 namespace reg {
 
+// Lst (optional, ldg * ldg + ldg doubles): receives the Cholesky factor of GA (rows) and its
+// reciprocal diagonal; linc: it already holds them for the leading ell - 1 rows and columns
+// of this GA, so only the appended row is formed.
 template <int NB>
 int launch_gks_solve_reg(const double *GA, const double *GP, int ldg, const double *rb,
                          const double *scal, int ell, double lam_fix, double *z, double *out,
-                         int *status, hipStream_t s);
+                         int *status, hipStream_t s, double *Lst, int linc);
 template <int NB>
 int launch_compress_reg(const double *GA, const double *GP, int ldg, const double *lam, int ell,
                         int kmin, const double *z, double *T, int ldt, double *zout, int *kout,

@@ -53,6 +53,11 @@ struct Solver {
     // a data-Gram column whose reduction the next regulariser Gram launch completes
     GramColJob gc{};
     bool gc_pending = false;
+    // Cholesky factor of GA kept between projected solves (ld * ld + ld doubles): valid for
+    // l_ell columns; ga_appended: an expansion appended one row and column since
+    double *Lst = nullptr;
+    int l_ell = 0;
+    bool ga_appended = false;
     // VarPro buffers
     float *Ahat = nullptr, *evec = nullptr;
     double *vp_GA = nullptr, *vp_ab = nullptr, *vp_M = nullptr, *vp_y = nullptr, *vp_gd = nullptr,
@@ -179,6 +184,8 @@ static int bproj(Solver &S, const nlrmm_batch &b, const float *y, const double *
 // G_A = (AV)^T AV and rb = (AV)^T b for the first ell columns, plus ||b||^2.
 static int gram_from_scratch(Solver &S, int ell, int64_t m, const float *b, hipStream_t s)
 {
+    S.l_ell = 0;   // GA is rebuilt: the kept factor no longer applies
+    S.ga_appended = false;
     for (int j = 0; j < ell; ++j)
         RC(k_multidot(S.AV, m, j + 1, S.AV + (int64_t)j * m, nullptr, m, S.part_md, S.md_blocks,
                       S.GA + j, S.ld, s));
@@ -287,6 +294,7 @@ static int expand(Solver &S, const nlrmm_batch &b, const double *theta, const fl
                                S.md_blocks, S.GA, S.ld, S.rb, s));
     }
     S.ell = ell + 1;
+    S.ga_appended = true;
     return NLRMM_OK;
 }
 
@@ -303,8 +311,13 @@ static int projected_solve(Solver &S, hipStream_t s, const nlrmm_batch *b = null
     RC(k_gram_psi(S.V, S.n, S.ell, nullptr, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.part_gram,
                   S.gram_blocks, S.GP, S.ld, s, S.cfg.gram_precision, S.u, (float)S.cfg.eps,
                   S.flow, S.w, side));
+    // the factor of GA is extended by one row when an expansion appended one since the last
+    // solve, else formed anew
+    const int linc = (S.Lst != nullptr && S.ga_appended && S.l_ell == S.ell - 1) ? 1 : 0;
     RC(k_gks_solve(S.GA, S.GP, S.ld, S.rb, S.sc + S_BNORM2, S.ell, S.cfg.lam_fix, S.z,
-                   S.sc + S_LAM, S.status, s));
+                   S.sc + S_LAM, S.status, s, 1, S.Lst, linc));
+    S.l_ell = S.Lst != nullptr ? S.ell : 0;
+    S.ga_appended = false;
     if (b && bvec) {
         // u = V z and the data residual A V z - b of the expansion that follows, one launch
         const int64_t m = m_of(S, *b);
@@ -331,6 +344,8 @@ static int compress(Solver &S, const nlrmm_batch &b, hipStream_t s)
                       S.cfg.compress_precision));
     RC(k_copy_cols(S.Vtmp, m, S.AV, m, kmin, m, s));
     RC(k_gram_transform(S.GA, S.ld, S.rb, S.ell, S.T, kmin, S.kout, s));
+    S.l_ell = 0;   // GA transformed: the kept factor no longer applies
+    S.ga_appended = false;
     RC(k_copy_f64(S.zt, S.z, kmin, s));
     S.ell = kmin;
     RC(k_gemv(S.V, S.n, kmin, S.z, 1.0, nullptr, 0.0, S.n, S.u, s));
@@ -559,6 +574,7 @@ static int solver_outer(Solver &S, const nlrmm_batch &b, double *theta, const fl
     const int64_t m = m_of(S, b);
     if (V > S.maxV) return NLRMM_ESHAPE;
     S.gc_pending = false;
+    S.ga_appended = false;
     // optical-flow branch of Alg. "dyn_nl_rmmgks": the velocities of every frame pair from
     // u^(k) (SOLVE-OF) every of_every outer iterations; Theta^(k) = [Psi; M_hat] follows
     if (S.cfg.temporal == TEMPORAL_OF && S.F > 1 && S.outer_count % S.cfg.of_every == 0)
@@ -815,6 +831,7 @@ int nlrmm_solver_create(nlrmm_ctx *ctx, const nlrmm_geom *geom, int32_t nframes,
         (rc = S->alloc(&S->cgs, 16)) ||
         (rc = S->alloc(&S->r, S->n)) || (rc = S->alloc(&S->rho, S->mmax)) ||
         (rc = S->alloc(&S->w, npsi_max)) || (rc = S->alloc(&S->GA, S->ld * S->ld)) ||
+        (rc = S->alloc(&S->Lst, S->ld * S->ld + S->ld)) ||
         (rc = S->alloc(&S->GP, S->ld * S->ld)) || (rc = S->alloc(&S->rb, S->ld)) ||
         (rc = S->alloc(&S->z, S->ld)) || (rc = S->alloc(&S->T, S->ld * c.kmin)) ||
         (rc = S->alloc(&S->zt, S->ld)) || (rc = S->alloc(&S->sc, S_NB)) ||
