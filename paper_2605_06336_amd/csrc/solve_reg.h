@@ -57,6 +57,11 @@ __device__ __forceinline__ void pin_regs(double (&v)[NB])
     for (int k = 0; k < NB; ++k) asm volatile("" : "+v"(v[k]));
 }
 
+// The kernels here run as a single wave (one 64-lane workgroup).  The LDS operations of a wave
+// complete in program order, so a compiler-level wave barrier (no s_barrier, no wait for
+// outstanding memory operations) is enough to order the lanes' exchanges through LDS.
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+
 // Reciprocal to full double precision: hardware estimate refined by two Newton steps.
 __device__ __forceinline__ double rcp_nr(double x)
 {
@@ -116,7 +121,7 @@ __device__ __forceinline__ void tri_step(double (&p)[NB], int lane, double *sv, 
     const double vi = (tj != 0.0 && lane > j) ? ((lane == j + 1) ? v0 : xi) : 0.0;
     if (tj != 0.0) {
         sv[lane] = vi;
-        __syncthreads();
+        wave_sync();
         double vc[NB];
 #pragma unroll
         for (int c = j + 1; c < NB; ++c) vc[c] = sv[c];
@@ -128,7 +133,7 @@ __device__ __forceinline__ void tri_step(double (&p)[NB], int lane, double *sv, 
         const double mu = 0.5 * tj * wave_sum_dpp(pi * vi);
         const double wi = pi - mu * vi;
         sw[lane] = wi;
-        __syncthreads();
+        wave_sync();
         double wc[NB];
 #pragma unroll
         for (int c = j + 1; c < NB; ++c) wc[c] = sw[c];
@@ -136,7 +141,7 @@ __device__ __forceinline__ void tri_step(double (&p)[NB], int lane, double *sv, 
 #pragma unroll
         for (int c = j + 1; c < NB; ++c) p[c] -= vi * wc[c] + wi * vc[c];
         pin_regs(p);
-        __syncthreads();
+        wave_sync();
     }
     p[j] = vi;
 }
@@ -247,7 +252,7 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
 #pragma unroll
         for (int j = 0; j < NB; ++j) a[j] = (lane == nm && j == nm) ? d : a[j];
         sdi[lane] = lane < nm ? inv : (lane == nm ? di : 1.0);
-        __syncthreads();
+        wave_sync();
     } else {
 #pragma unroll
         for (int c = 0; c < NB; ++c)
@@ -258,7 +263,7 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
         StaticFor<0, NB>::run([&](auto J) __attribute__((always_inline)) {
             constexpr int j = decltype(J)::value;
             sv[lane] = a[j];
-            __syncthreads();
+            wave_sync();
             double lc[NB];
     #pragma unroll
             for (int k = j + 1; k < NB; ++k) lc[k] = sv[k];
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
             a[j] = (lane == j) ? d : a[j] * di;
             sdi[j] = di;
             pin_regs(a);
-            __syncthreads();
+            wave_sync();
         });
     }
     if (Lst != nullptr) {
@@ -297,7 +302,7 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
 #pragma unroll
     for (int c = 0; c < NB; ++c)
         p[c] = (lane < n && c < n) ? GP[lane * ldg + c] : ((lane == n && c < n) ? rb[c] : 0.0);
-    __syncthreads();
+    wave_sync();
     // 2. K = L^-1 GP L^-T: column-wise forward substitutions, transposes through LDS
     lower_solve_cols<NB, LD>(p, sLt, sdi);
     if (lane == n) {
@@ -308,16 +313,16 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
 #pragma unroll
         for (int k = 0; k < NB; ++k) sX[k * LD + lane] = (lane < n) ? p[k] : 0.0;
     }
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int c = 0; c < NB; ++c) p[c] = row ? sX[lane * LD + c] : 0.0;
-    __syncthreads();
+    wave_sync();
     lower_solve_cols<NB, LD>(p, sLt, sdi);
     if (row) {
 #pragma unroll
         for (int c = 0; c < NB; ++c) sX[c * LD + lane] = p[c];
     }
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int c = 0; c < NB; ++c) p[c] = row ? 0.5 * (p[c] + sX[lane * LD + c]) : 0.0;
     // 3. reflector H0 with H0 c = s ||c|| e1; K <- H0 K H0
@@ -330,7 +335,7 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
     const double vtv = wave_sum_dpp(hv * hv);
     const double t0 = vtv > 0.0 ? 2.0 / vtv : 0.0;
     sv[lane] = hv;
-    __syncthreads();
+    wave_sync();
     {
         double vc[NB];
 #pragma unroll
@@ -343,7 +348,7 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
         const double mu = 0.5 * t0 * wave_sum_dpp(pi * hv);
         const double wi = pi - mu * hv;
         sw[lane] = wi;
-        __syncthreads();
+        wave_sync();
         double wc[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) wc[c] = sw[c];
@@ -351,7 +356,7 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
 #pragma unroll
         for (int c = 0; c < NB; ++c) p[c] -= hv * wc[c] + wi * vc[c];
         pin_regs(p);
-        __syncthreads();
+        wave_sync();
     }
     // 4. Householder tridiagonalisation; reflector j kept in register j of lanes > j, and
     //    stored to row j of sX at the end (sX is free after step 2)
@@ -371,7 +376,7 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
 #pragma unroll
         for (int j = 0; j + 2 < NB; ++j) sX[j * LD + lane] = (lane > j) ? p[j] : 0.0;
     }
-    __syncthreads();
+    wave_sync();
     // 5. discrepancy principle.  The padded tail (d = e = 0) leaves P and S unchanged, so the
     //    sweep runs over the whole padded size with T in registers.
     double dd[NB], e2[NB];
@@ -462,7 +467,7 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
             sy[i] = r;
         }
     }
-    __syncthreads();
+    wave_sync();
     double yl;
     {
         double rD[NB];
@@ -587,10 +592,10 @@ __global__ __launch_bounds__(64) void compress_reg_k(const double *__restrict__ 
 #pragma unroll
         for (int c = 0; c < NB; ++c) sX[c * LD + lane] = p[c];
     }
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int c = 0; c < NB; ++c) p[c] = row ? 0.5 * (p[c] + sX[lane * LD + c]) : 0.0;
-    __syncthreads();
+    wave_sync();
     // 1. tridiagonalise
     TriSteps<0, NB>::run(p, lane, sv, sw, sdd, see, stau);
     {
@@ -608,7 +613,7 @@ __global__ __launch_bounds__(64) void compress_reg_k(const double *__restrict__ 
 #pragma unroll
         for (int j = 0; j + 2 < NB; ++j) sX[j * LD + lane] = (lane > j) ? p[j] : 0.0;
     }
-    __syncthreads();
+    wave_sync();
     double dd[NB], ee[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
@@ -642,7 +647,7 @@ __global__ __launch_bounds__(64) void compress_reg_k(const double *__restrict__ 
         }
         if (lane == 0) smu[t] = 0.5 * (lo + hi);
     }
-    __syncthreads();
+    wave_sync();
     // 3. inverse iteration, lane t < kw for eigenvalue t (tridiagonal basis)
     double y[NB];
     {
@@ -681,7 +686,7 @@ __global__ __launch_bounds__(64) void compress_reg_k(const double *__restrict__ 
 #pragma unroll
         for (int i = 0; i < NB; ++i) sY[lane * LD + i] = y[i];
     }
-    __syncthreads();
+    wave_sync();
     double wv[KW];   // lane i holds component i of every vector
 #pragma unroll
     for (int t = 0; t < KW; ++t) wv[t] = (t < kw && row) ? sY[t * LD + lane] : 0.0;
@@ -737,7 +742,7 @@ __global__ __launch_bounds__(64) void compress_reg_k(const double *__restrict__ 
             if (lane < n) T[lane * ldt + t] = wv[t];
         }
     }
-    __syncthreads();
+    wave_sync();
     double cl = zl;
 #pragma unroll
     for (int t = 0; t < KW; ++t)
