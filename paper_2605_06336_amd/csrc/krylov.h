@@ -93,6 +93,11 @@ int k_normalize_red(const float *r, const double *part, int nblk, double *scal, 
                     int64_t n, float *vout, int *status, hipStream_t s);
 // Largest producer grid whose partials k_cgs2's consumers sum themselves.
 constexpr int CGS2_FUSED_MAXBLK = 512;
+// The data Gram from scratch in two launches: G = X^T X (both triangles), rb = X^T b and
+// bn2[0] = b^T b for nc <= 10 columns of X (the same values as one multidot per column);
+// part: md_part_doubles(nblk) doubles.
+int k_gram_cols(const float *X, int64_t ldx, int nc, const float *b, int64_t n, double *part,
+                int nblk, double *G, int ldg, double *rb, double *bn2, hipStream_t s);
 // precision 0: FP32 operands, FP64 accumulation (vector units); 2: BF16 operands, FP32
 // accumulation (matrix cores)
 int k_block_update(const float *X, int64_t ldx, int nin, const double *T, int ldt, int kout,

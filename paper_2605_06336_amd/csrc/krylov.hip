@@ -359,10 +359,13 @@ __global__ __launch_bounds__(BLK, 3) void gram_psi_mfma_k(const float *__restric
             }
         }
         // four columns per step, all their loads issued before any use
-        for (int c0 = cg; c0 < ell; c0 += 4 * (BLK / 64)) {
-            float x0[4], x1[4], x2[4], x3[4], m0[4], m1[4];
+        // UC columns per wave per round, their loads issued together (eight in the FP32
+        // instances, whose occupancy the LDS tile fixes; four in the BF16 ones)
+        constexpr int UC = BF16 ? 4 : 8;
+        for (int c0 = cg; c0 < ell; c0 += UC * (BLK / 64)) {
+            float x0[UC], x1[UC], x2[UC], x3[UC], m0[UC], m1[UC];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < UC; ++u) {
                 const int c = c0 + u * (BLK / 64);
                 const bool ok = stage && c < ell && i < ntot;
                 const float *vc = V + (int64_t)(ok ? c : 0) * ldv;
@@ -375,7 +378,7 @@ __global__ __launch_bounds__(BLK, 3) void gram_psi_mfma_k(const float *__restric
                 m1[u] = (ok && motion && ot > 0) ? of_sample(vc + ro, cr, nx) : x3[u];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < UC; ++u) {
                 const int c = c0 + u * (BLK / 64);
                 if (stage && c < ell) {
                     // kind-major rows (row = kind * mp + pixel): consecutive lanes write
@@ -738,6 +741,97 @@ __global__ __launch_bounds__(BLK) void gemv_norm_red_k(const float *__restrict__
         double t = 0.0;
         for (int w = 0; w < BLK / 64; ++w) t += sw[w];
         part[blockIdx.x] = t;
+    }
+}
+
+// The data Gram from scratch: every inner product of the columns of [X, b] (nc <= 10 columns
+// of X in slots 0 .. nc-1, b in slot 10, zeros between) in one launch.  Pairs (i, j), i <= j,
+// in a fixed order, so every register index is static; FP64 sums of the exact products,
+// block partials part[block][pair] reduced through LDS in groups of 16 as multidot_k reduces
+// its outputs (the same values as one multidot per column).
+constexpr int PG_SLOTS = 11;
+constexpr int PG_PAIRS = PG_SLOTS * (PG_SLOTS + 1) / 2;   // 66
+
+__host__ __device__ constexpr int pg_first(int p)
+{
+    int i = 0;
+    while (p >= PG_SLOTS - i) {
+        p -= PG_SLOTS - i;
+        ++i;
+    }
+    return i;
+}
+__host__ __device__ constexpr int pg_second(int p)
+{
+    int i = 0;
+    while (p >= PG_SLOTS - i) {
+        p -= PG_SLOTS - i;
+        ++i;
+    }
+    return i + p;
+}
+
+__global__ __launch_bounds__(BLK) void gram_cols_k(const float *__restrict__ X, int64_t ldx,
+                                                   int nc, const float *__restrict__ b,
+                                                   int64_t n, double *__restrict__ part)
+{
+    constexpr int GRP = 16;
+    __shared__ double sacc[GRP][BLK];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int g0 = 0; g0 < PG_PAIRS; g0 += GRP) {
+        double acc[GRP];
+#pragma unroll
+        for (int a = 0; a < GRP; ++a) acc[a] = 0.0;
+        for (int64_t e = (int64_t)blockIdx.x * BLK + tid; e < n; e += (int64_t)gridDim.x * BLK) {
+            float v[PG_SLOTS];
+#pragma unroll
+            for (int k = 0; k < PG_SLOTS - 1; ++k) v[k] = k < nc ? X[(int64_t)k * ldx + e] : 0.0f;
+            v[PG_SLOTS - 1] = b[e];
+#pragma unroll
+            for (int a = 0; a < GRP; ++a) {
+                const int pidx = g0 + a;
+                if (pidx < PG_PAIRS)
+                    acc[a] = fma((double)v[pg_first(pidx)], (double)v[pg_second(pidx)], acc[a]);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < GRP; ++a) sacc[a][tid] = acc[a];
+        __syncthreads();
+        constexpr int TPO = BLK / GRP;
+        const int a = tid / TPO, l = tid % TPO;
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < BLK / TPO; ++k) t += sacc[a][l + TPO * k];
+        for (int off = TPO / 2; off > 0; off >>= 1) t += __shfl_xor(t, off, TPO);
+        if (l == 0 && g0 + a < PG_PAIRS) part[(int64_t)blockIdx.x * PG_PAIRS + g0 + a] = t;
+        __syncthreads();
+    }
+}
+
+// One wave per pair: its nblk partials summed as reduce_vec_k sums them, written as G[i][j]
+// and G[j][i] (i, j < nc), rb[i] (the pair of column i with b) or bn2 (b with itself).
+__global__ __launch_bounds__(64) void gram_cols_reduce_k(const double *__restrict__ part,
+                                                         int nblk, int nc,
+                                                         double *__restrict__ G, int ldg,
+                                                         double *__restrict__ rb,
+                                                         double *__restrict__ bn2)
+{
+    const int p = blockIdx.x;
+    const int i = pg_first(p), j = pg_second(p);
+    const bool bi = i == PG_SLOTS - 1, bj = j == PG_SLOTS - 1;
+    if ((!bi && i >= nc) || (!bj && j >= nc)) return;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += 64) s += part[(int64_t)k * PG_PAIRS + p];
+    s = wave_sum(s);
+    if (threadIdx.x != 0) return;
+    if (!bi && !bj) {
+        G[i * ldg + j] = s;
+        G[j * ldg + i] = s;
+    } else if (!bi) {
+        rb[i] = s;
+    } else {
+        bn2[0] = s;
     }
 }
 
@@ -1845,6 +1939,19 @@ int k_normalize_red(const float *r, const double *part, int nblk, double *scal, 
 {
     normalize_red_k<<<(unsigned)((n + BLK - 1) / BLK), BLK, 0, s>>>(r, part, nblk, scal, tol, n,
                                                                     vout, status);
+    return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
+}
+
+int k_gram_cols(const float *X, int64_t ldx, int nc, const float *b, int64_t n, double *part,
+                int nblk, double *G, int ldg, double *rb, double *bn2, hipStream_t s)
+{
+    if (nc < 1 || nc > PG_SLOTS - 1 || nblk < 1) return NLRMM_ESHAPE;
+    if ((size_t)nblk * PG_PAIRS > md_part_doubles(nblk)) return NLRMM_ESHAPE;
+    int64_t g = (n + BLK - 1) / BLK;
+    if (g > nblk) g = nblk;
+    if (g < 1) g = 1;
+    gram_cols_k<<<(unsigned)g, BLK, 0, s>>>(X, ldx, nc, b, n, part);
+    gram_cols_reduce_k<<<(unsigned)PG_PAIRS, 64, 0, s>>>(part, (int)g, nc, G, ldg, rb, bn2);
     return hipGetLastError() == hipSuccess ? NLRMM_OK : NLRMM_EHIP;
 }
 

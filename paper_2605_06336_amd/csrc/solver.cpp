@@ -186,6 +186,9 @@ static int gram_from_scratch(Solver &S, int ell, int64_t m, const float *b, hipS
 {
     S.l_ell = 0;   // GA is rebuilt: the kept factor no longer applies
     S.ga_appended = false;
+    if (ell >= 1 && ell <= 10)
+        return k_gram_cols(S.AV, m, ell, b, m, S.part_md, S.md_blocks, S.GA, S.ld, S.rb,
+                           S.sc + S_BNORM2, s);
     for (int j = 0; j < ell; ++j)
         RC(k_multidot(S.AV, m, j + 1, S.AV + (int64_t)j * m, nullptr, m, S.part_md, S.md_blocks,
                       S.GA + j, S.ld, s));
