@@ -557,7 +557,8 @@ __device__ __forceinline__ int sturm_below(double x, const double (&dd)[NB], con
 
 // Compression in one wave (same result as compress_eig_k): S = GA + lam GP is reduced to a
 // tridiagonal T = Q^T S Q (Householder, reflectors kept in registers), the kmin - 1 largest
-// eigenvalues of T are found by 65-way Sturm bisection, lane t computes the eigenvector of
+// eigenvalues of T are found together by Sturm bisection (a group of lanes each), lane t
+// computes the eigenvector of
 // eigenvalue t by two steps of inverse iteration (LDL^T of T - mu I, pivots perturbed away
 // from zero), the vectors are orthonormalised in order (classical Gram-Schmidt, twice) and
 // mapped back by Q.  The sign rule, W^T z, the remainder c and the outputs follow
@@ -631,21 +632,29 @@ __global__ __launch_bounds__(64) void compress_reg_k(const double *__restrict__ 
     const double span = fmax(ghi - glo, 1e-300);
     glo -= 1e-12 * span;
     ghi += 1e-12 * span;
-    for (int t = 0; t < kw; ++t) {
-        // smallest x with #(eig < x) >= NB - t, i.e. just above the (t+1)-th largest
-        const int need = NB - t;
+    {
+        // All kw eigenvalues at once: the wave splits into groups of gs lanes (16, 8 or 4),
+        // group t bisects the smallest x with #(eig < x) >= NB - t (just above the (t+1)-th
+        // largest eigenvalue) on a (gs + 1)-part grid of its own bracket each round.
+        const int gs = kw <= 4 ? 16 : (kw <= 8 ? 8 : 4);
+        const int grp = lane / gs, li = lane - grp * gs;
+        const int need = NB - grp;
+        const double step = 1.0 / (double)(gs + 1);
+        const unsigned long long gmask = (1ull << gs) - 1;
         double lo = glo, hi = ghi;
-        for (int round = 0; round < 14; ++round) {
-            const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+        for (int round = 0; round < 48; ++round) {
+            const double x = fma(hi - lo, (double)(li + 1) * step, lo);
             const unsigned long long m = __ballot(sturm_below<NB>(x, dd, ee) >= need);
-            const int k = m ? (__ffsll((unsigned long long)m) - 1) : 64;
-            const double nlo = (k == 0) ? lo : lo + (hi - lo) * (double)k / 65.0;
-            const double nhi = (k == 64) ? hi : lo + (hi - lo) * (double)(k + 1) / 65.0;
+            const unsigned long long bits = (m >> (grp * gs)) & gmask;
+            const int k = bits ? (__ffsll(bits) - 1) : gs;
+            const double nlo = (k == 0) ? lo : fma(hi - lo, (double)k * step, lo);
+            const double nhi = (k == gs) ? hi : fma(hi - lo, (double)(k + 1) * step, lo);
             lo = nlo;
             hi = nhi;
-            if (hi - lo <= 2e-16 * fmax(fabs(lo), fabs(hi))) break;
+            const bool done = grp >= kw || hi - lo <= 2e-16 * fmax(fabs(lo), fabs(hi));
+            if (__ballot(!done) == 0) break;
         }
-        if (lane == 0) smu[t] = 0.5 * (lo + hi);
+        if (li == 0 && grp < kw) smu[grp] = 0.5 * (lo + hi);
     }
     wave_sync();
     // 3. inverse iteration, lane t < kw for eigenvalue t (tridiagonal basis)
@@ -653,25 +662,25 @@ __global__ __launch_bounds__(64) void compress_reg_k(const double *__restrict__ 
     {
         const double mu = lane < kw ? smu[lane] : 0.0;
         const double tiny = 0x1p-52 * fmax(fabs(mu), span);
-        double q[NB];
-        // LDL^T pivots of T - mu I
+        double rq[NB];
+        // LDL^T pivots of T - mu I, kept as reciprocals (refined hardware estimates)
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             double v = dd[i] - mu;
-            if (i > 0) v -= ee[i - 1] * ee[i - 1] / q[i - 1];
+            if (i > 0) v -= ee[i - 1] * ee[i - 1] * rq[i - 1];
             if (fabs(v) < tiny) v = v < 0.0 ? -tiny : tiny;
-            q[i] = v;
+            rq[i] = rcp_nr(v);
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) y[i] = i < n ? 1.0 + 1e-3 * i : 0.0;
         for (int it = 0; it < 2; ++it) {
             // solve L D L^T y = y: forward (unit L, l_i = e_{i-1} / q_{i-1}), diagonal, back
 #pragma unroll
-            for (int i = 1; i < NB; ++i) y[i] -= (ee[i - 1] / q[i - 1]) * y[i - 1];
+            for (int i = 1; i < NB; ++i) y[i] -= (ee[i - 1] * rq[i - 1]) * y[i - 1];
 #pragma unroll
-            for (int i = 0; i < NB; ++i) y[i] /= q[i];
+            for (int i = 0; i < NB; ++i) y[i] *= rq[i];
 #pragma unroll
-            for (int i = NB - 2; i >= 0; --i) y[i] -= (ee[i] / q[i]) * y[i + 1];
+            for (int i = NB - 2; i >= 0; --i) y[i] -= (ee[i] * rq[i]) * y[i + 1];
             double nrm = 0.0;
 #pragma unroll
             for (int i = 0; i < NB; ++i) nrm = fma(y[i], y[i], nrm);
