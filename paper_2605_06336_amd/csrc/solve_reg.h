@@ -108,18 +108,18 @@ __device__ __forceinline__ void tri_step(double (&p)[NB], int lane, double *sv, 
     const double x0 = lane_bcast(p[j], j + 1);
     const double dj = lane_bcast(p[j], j);
     const double tail = s2 - x0 * x0;
-    double tj = 0.0, alpha = x0, v0 = 0.0;
-    if (tail > 0.0) {
-        const double sigma = sqrt(s2);
-        alpha = (x0 >= 0.0) ? -sigma : sigma;
-        v0 = x0 - alpha;
-        tj = 2.0 * rcp_nr(tail + v0 * v0);
-    }
+    // no branches: every step is straight-line code (a step without a reflector has v = 0,
+    // tau = 0 and leaves p unchanged), so the steps schedule as one block
+    const bool refl = tail > 0.0;
+    const double sigma = sqrt(s2);
+    const double alpha = refl ? ((x0 >= 0.0) ? -sigma : sigma) : x0;
+    const double v0 = refl ? x0 - alpha : 0.0;
+    const double tj = refl ? 2.0 * rcp_nr(tail + v0 * v0) : 0.0;
     sdd[j] = dj;
     see[j] = alpha;
     stau[j] = tj;
     const double vi = (tj != 0.0 && lane > j) ? ((lane == j + 1) ? v0 : xi) : 0.0;
-    if (tj != 0.0) {
+    {
         sv[lane] = vi;
         wave_sync();
         double vc[NB];
