@@ -485,12 +485,11 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
     }
 #pragma unroll
     for (int j = NB - 3; j >= 0; --j) {
+        // unconditional (tau = 0 leaves y unchanged), so the reflector loads are issued early
         const double tj = stau[j];
-        if (tj != 0.0) {
-            const double vi = row ? sX[j * LD + lane] : 0.0;
-            const double dot = wave_sum_dpp(vi * yl);
-            yl = fma(-tj * dot, vi, yl);
-        }
+        const double vi = row ? sX[j * LD + lane] : 0.0;
+        const double dot = wave_sum_dpp(vi * yl);
+        yl = fma(-tj * dot, vi, yl);
     }
     {
         const double dot = wave_sum_dpp(hv * yl);
@@ -717,15 +716,14 @@ __global__ __launch_bounds__(64) void compress_reg_k(const double *__restrict__ 
     // 5. back to the basis of S: w = H_1 ... H_{NB-2} y
 #pragma unroll
     for (int j = NB - 3; j >= 0; --j) {
+        // unconditional (tau = 0 leaves the vectors unchanged)
         const double tj = stau[j];
-        if (tj != 0.0) {
-            const double vi = row ? sX[j * LD + lane] : 0.0;
+        const double vi = row ? sX[j * LD + lane] : 0.0;
 #pragma unroll
-            for (int t = 0; t < KW; ++t) {
-                if (t < kw) {
-                    const double dot = wave_sum_dpp(vi * wv[t]);
-                    wv[t] = fma(-tj * dot, vi, wv[t]);
-                }
+        for (int t = 0; t < KW; ++t) {
+            if (t < kw) {
+                const double dot = wave_sum_dpp(vi * wv[t]);
+                wv[t] = fma(-tj * dot, vi, wv[t]);
             }
         }
     }
