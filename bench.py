@@ -330,6 +330,47 @@ def fan_leg(torch, ops, synth, reps):
             "gpixelviews_per_s": {k: round(pv / (v * 1e-3) / 1e9, 2) for k, v in ms.items()}}
 
 
+def pat_leg(torch, ops, synth, reps):
+    """ms per call of the photoacoustic circular-means operators (projection, its derivative in
+    the radial shift, transpose) at the 64x64 shape (64 sensors, 64 radii, 512 samples per
+    circle, p = 0.432) and the 50x50 frames (32 sensors, 50 radii, 256 samples, p = 0.1924,
+    20 frames in one call), with circle samples per second."""
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        for _ in range(reps):
+            fn()
+        a1.record(stream)
+        torch.cuda.synchronize()
+        return a0.elapsed_time(a1) / reps
+
+    res = {}
+    for name, (N, na, nc, K, p, cols) in {"64x64": (64, 64, 64, 512, 0.432, 1),
+                                          "50x50_frames": (50, 32, 50, 256, 0.1924, 20)}.items():
+        x = torch.as_tensor(synth.random_image(N, seed=N, frames=cols).astype(np.float32),
+                            device=dev).contiguous()
+        g = ops.geom(N, 3)
+        pg = ops.pat_geom(na, nc, K)
+        y = ops.pat_project(x, g, pg, p)
+        yb = torch.empty_like(y)
+        xb = torch.empty((cols, N, N), dtype=torch.float32, device=dev)
+        ms = {"project": timed(lambda: ops.pat_project(x, g, pg, p, out=yb)),
+              "project_dp": timed(lambda: ops.pat_project_dp(x, g, pg, p, out=yb)),
+              "backproject": timed(lambda: ops.pat_backproject(y, g, pg, p, out=xb))}
+        samples = cols * na * nc * K
+        res[name] = {"image": N, "sensors": na, "radii": nc, "samples_per_circle": K,
+                     "columns": cols, "ms_per_call": {k: round(v, 4) for k, v in ms.items()},
+                     "gsamples_per_s": {k: round(samples / (v * 1e-3) / 1e9, 2)
+                                        for k, v in ms.items()}}
+    return res
+
+
 def varpro_leg(torch, ops, synth, Config, Solver, steps, warmup, gram_precision):
     """Outer it/s of VarPro NL-RMM-GKS on the 512x512 / 720-view / 725-bin workload (S = 15
     projected solves per outer iteration, kmax 25)."""
@@ -760,10 +801,11 @@ def main():
         dyn = dynamic_leg(torch, ops, synth, Config, OuterGraph, Solver, max(3, args.steps // 2),
                           2, args.gram_precision)
 
-    per_workload = varpro = autograd_r = precision = streaming = gram = fan = None
+    per_workload = varpro = autograd_r = precision = streaming = gram = fan = pat = None
     if not args.no_workloads:
         gram = gram_leg(torch, ops, synth, max(3, args.reps // 2))
         fan = fan_leg(torch, ops, synth, max(3, args.reps // 2))
+        pat = pat_leg(torch, ops, synth, max(3, args.reps // 2))
         per_workload = workload_operators(torch, ops, metrics, synth, max(3, args.reps // 4))
         varpro = varpro_leg(torch, ops, synth, Config, Solver, max(3, args.steps // 2), 2,
                             args.gram_precision)
@@ -814,6 +856,7 @@ def main():
         "streaming_c5": streaming,
         "gram_mfma": gram,
         "fan_beam_c2": fan,
+        "photoacoustic": pat,
         "roofline": roofline,
         "roofline_" + other: roofline_other,
         "loop_kernels": loop_kernels,

@@ -16,11 +16,13 @@
 // Projection: one wave per (column, sensor, radius), the K samples split over the lanes, the
 // lanes' sums added by a fixed butterfly (a negative r = r_j + p is used as it stands: the
 // circle of radius |r| traced from the opposite side, with the negative factor 2 pi r / K).
-// Transpose (gather, no atomics): one lane per pixel; for every sensor the radii whose
-// |r| is within d sqrt(2) of the pixel's distance and, on each,
-// the samples within the angle the pixel's bilinear support subtends; a sample adds its
+// Transpose (gather, no atomics): 16, 32 or 64 lanes per pixel (whichever first covers the
+// sensors), lane s taking sensors s, s + lpp, ...; for each sensor the radii whose |r| is
+// within d sqrt(2) of the pixel's distance and, on each, the samples within asin(d sqrt(2)/|r|)
+// of the pixel's direction seen from the sensor; a sample adds its
 // value times the bilinear weight of the pixel's corner when the pixel is a corner of its
-// cell (the same FP64 cell test as the projection).
+// cell (the same FP64 directions, from LDS up to 2048 samples per circle, and the same FP64
+// cell test as the projection); the lanes' sums are joined by a fixed butterfly.
 #include "internal.h"
 
 #include <math.h>
@@ -31,6 +33,7 @@ namespace {
 constexpr int PAT_BLK = 256;
 constexpr int PAT_KMAX = 8192;       // samples per circle
 constexpr int PAT_DIR_CHUNK = 1024;  // directions staged in LDS per pass
+constexpr int PAT_BWD_KLDS = 2048;   // transpose: all directions in LDS up to this K
 
 struct PatArgs {
     int nx, ny, ncols, na, nc, K;
@@ -122,17 +125,33 @@ __global__ __launch_bounds__(PAT_BLK) void pat_fwd_k(PatArgs a)
 
 __global__ __launch_bounds__(PAT_BLK) void pat_bwd_k(PatArgs a)
 {
-    const int64_t gid = (int64_t)blockIdx.x * PAT_BLK + threadIdx.x;
+    // the K sample directions of every circle, the same FP64 values as the projection's
+    __shared__ double2 dirs[PAT_BWD_KLDS];
+    const bool staged = a.K <= PAT_BWD_KLDS;
+    if (staged) {
+        for (int t = threadIdx.x; t < a.K; t += PAT_BLK) {
+            double sn, cs;
+            sincospi(2.0 * t / a.K, &sn, &cs);
+            dirs[t] = make_double2(cs, sn);
+        }
+    }
+    __syncthreads();
+    // lpp lanes per pixel (16, 32 or 64: the first that covers the sensors), 64 / lpp pixels
+    // per wave
+    const int lpp = a.na <= 16 ? 16 : (a.na <= 32 ? 32 : 64);
+    const int lane = threadIdx.x & 63, sl = lane & (lpp - 1);
+    const int64_t gid = ((int64_t)blockIdx.x * PAT_BLK + threadIdx.x) / lpp;
     const int64_t npix = (int64_t)a.nx * a.ny;
-    if (gid >= npix * a.ncols) return;
-    const int col = (int)(gid / npix);
-    const int64_t pix = gid - col * npix;
+    const bool live = gid < npix * a.ncols;   // no barrier follows: idle lanes just add 0
+    const int64_t gl = live ? gid : 0;
+    const int col = (int)(gl / npix);
+    const int64_t pix = gl - col * npix;
     const int l = (int)(pix / a.nx), k = (int)(pix - (int64_t)l * a.nx);
     const double xc = pat_pix(a.x0, a.d, k), yc = pat_pix(a.y0, a.d, l);
     const float *y = a.src + (int64_t)col * a.na * a.nc;
     const double reach = a.d * M_SQRT2;
     double acc = 0.0;
-    for (int sa = 0; sa < a.na; ++sa) {
+    for (int sa = sl; live && sa < a.na; sa += lpp) {
         double ss, sc;
         sincospi(2.0 * sa / a.na, &ss, &sc);
         const double sx = a.rho * sc, sy = a.rho * ss;
@@ -153,14 +172,16 @@ __global__ __launch_bounds__(PAT_BLK) void pat_bwd_k(PatArgs a)
                 const double r = (j + 1) * a.dr + a.p;
                 if (!(sg * r > 0.0)) continue;   // each radius on its own side once
                 const double ar = fabs(r);
-                // samples within the angle the support subtends (a chord below 2 d sqrt(2))
-                const double sarg = 2.0 * reach / ar;
+                // samples within the angle the support subtends: a sample within d sqrt(2) of
+                // the pixel is at most asin(d sqrt(2) / |r|) from the pixel's direction, seen
+                // from the sensor (one sample of margin)
+                const double sarg = reach / ar;
                 int kb, kn;
                 if (sarg >= 1.0) {
                     kb = 0;
                     kn = a.K;
                 } else {
-                    const double half = 2.0 * asin(sarg) * a.K / (2.0 * M_PI) + 1.0;
+                    const double half = asin(sarg) * a.K / (2.0 * M_PI) + 1.0;
                     const double kc = (side ? psi + M_PI : psi) * a.K / (2.0 * M_PI);
                     kb = (int)floor(kc - half);
                     kn = min(a.K, (int)ceil(kc + half) - kb + 1);
@@ -170,7 +191,13 @@ __global__ __launch_bounds__(PAT_BLK) void pat_bwd_k(PatArgs a)
                     int kk = (kb + t) % a.K;
                     if (kk < 0) kk += a.K;
                     double sn, cs;
-                    sincospi(2.0 * kk / a.K, &sn, &cs);
+                    if (staged) {
+                        const double2 e = dirs[kk];
+                        cs = e.x;
+                        sn = e.y;
+                    } else {
+                        sincospi(2.0 * kk / a.K, &sn, &cs);
+                    }
                     const PatCell c = pat_cell(fma(r, cs, sx), fma(r, sn, sy), a);
                     const int dk = k - c.k0, dl = l - c.l0;
                     if (dk < 0 || dk > 1 || dl < 0 || dl > 1) continue;
@@ -181,7 +208,9 @@ __global__ __launch_bounds__(PAT_BLK) void pat_bwd_k(PatArgs a)
             }
         }
     }
-    a.dst[gid] = (float)acc;
+    // the sensors' sums joined in a fixed order
+    for (int off = lpp / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (live && sl == 0) a.dst[gid] = (float)acc;
 }
 
 }  // namespace
@@ -218,8 +247,10 @@ int launch_pat(const nlrmm_geom &g, const nlrmm_pat_geom &pg, int ncols, double 
     a.src = src;
     a.dst = dst;
     if (mode == 2) {
-        const int64_t n = (int64_t)ncols * g.nx * g.ny;
-        pat_bwd_k<<<(unsigned)((n + PAT_BLK - 1) / PAT_BLK), PAT_BLK, 0, s>>>(a);
+        const int64_t n = (int64_t)ncols * g.nx * g.ny;   // lpp lanes per pixel
+        const int lpp = pg.n_sensors <= 16 ? 16 : (pg.n_sensors <= 32 ? 32 : 64);
+        const int64_t per = PAT_BLK / lpp;
+        pat_bwd_k<<<(unsigned)((n + per - 1) / per), PAT_BLK, 0, s>>>(a);
     } else {
         const int64_t lanes = (int64_t)ncols * a.na * a.nc * 64;
         const unsigned blocks = (unsigned)((lanes + PAT_BLK - 1) / PAT_BLK);
