@@ -27,6 +27,10 @@ enum {
     S_NB = 16,      // scalars
 };
 
+// Largest image (pixels times frames) whose IRN weights the Gram launch forms itself; larger
+// ones get them from their own launch first.
+constexpr int64_t GRAM_FUSED_WEIGHTS_MAX = int64_t(1) << 19;
+
 struct Solver {
     nlrmm_ctx *ctx = nullptr;
     nlrmm_geom g{};
@@ -307,13 +311,20 @@ static int projected_solve(Solver &S, hipStream_t s, const nlrmm_batch *b = null
                            const float *bvec = nullptr)
 {
     // this step's weights (from the u the solve starts from): the Gram and, in the expansion
-    // that follows, the residual use them (Alg. "enlarge").  The Gram launch forms them and
-    // stores them in S.w, and completes a pending row of the data Gram.
+    // that follows, the residual use them (Alg. "enlarge").  On small images the Gram launch
+    // forms them and stores them in S.w (each of its waves forms them again for its own
+    // columns, which costs more than the saved launch beyond about half a million pixels);
+    // it also completes a pending row of the data Gram.
     const GramColJob *side = S.gc_pending ? &S.gc : nullptr;
     S.gc_pending = false;
-    RC(k_gram_psi(S.V, S.n, S.ell, nullptr, S.g.nx, S.g.ny, S.F, S.cfg.temporal, S.part_gram,
-                  S.gram_blocks, S.GP, S.ld, s, S.cfg.gram_precision, S.u, (float)S.cfg.eps,
-                  S.flow, S.w, side));
+    const bool wfused = S.n <= GRAM_FUSED_WEIGHTS_MAX;
+    if (!wfused)
+        RC(k_psi_weights(S.u, S.g.nx, S.g.ny, S.F, S.cfg.temporal, (float)S.cfg.eps, S.w, s,
+                         S.flow));
+    RC(k_gram_psi(S.V, S.n, S.ell, wfused ? nullptr : S.w, S.g.nx, S.g.ny, S.F, S.cfg.temporal,
+                  S.part_gram, S.gram_blocks, S.GP, S.ld, s, S.cfg.gram_precision,
+                  wfused ? S.u : nullptr, (float)S.cfg.eps, S.flow, wfused ? S.w : nullptr,
+                  side));
     // the factor of GA is extended by one row when an expansion appended one since the last
     // solve, else formed anew
     const int linc = (S.Lst != nullptr && S.ga_appended && S.l_ell == S.ell - 1) ? 1 : 0;
