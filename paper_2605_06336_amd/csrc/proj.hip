@@ -269,6 +269,42 @@ __global__ __launch_bounds__(BLK) void pack_lines_k(const float *__restrict__ x,
     if (tid == 0) tot[img * nlines + line] = sP[n];
 }
 
+// Exclusive prefix of the line totals, pre[img][0..nlines] (blockIdx.y: rows 0, columns 1),
+// for images whose lines are too many for the forward kernel to sum the skipped ones itself.
+__global__ __launch_bounds__(BLK) void line_prefix_k(const double *__restrict__ rowtot,
+                                                     const double *__restrict__ coltot, int nx,
+                                                     int ny, double *__restrict__ rowpre,
+                                                     double *__restrict__ colpre)
+{
+    __shared__ double swave[BLK / 64];
+    const bool rows = blockIdx.y == 0;
+    const int nlines = rows ? ny : nx;
+    const int64_t img = blockIdx.x;
+    const double *t = (rows ? rowtot : coltot) + img * nlines;
+    double *pre = (rows ? rowpre : colpre) + img * (int64_t)(nlines + 1);
+    const int tid = threadIdx.x;
+    // each thread a contiguous run of lines; an exclusive scan of the run sums over the block
+    const int run = (nlines + BLK - 1) / BLK;
+    const int i0 = min(tid * run, nlines), i1 = min(i0 + run, nlines);
+    double own = 0.0;
+    for (int i = i0; i < i1; ++i) own += t[i];
+    const int lane = tid & 63, wv = tid >> 6;
+    double incl = own;
+    for (int off = 1; off < 64; off <<= 1) {
+        const double u = __shfl_up(incl, off, 64);
+        incl += lane >= off ? u : 0.0;
+    }
+    if (lane == 63) swave[wv] = incl;
+    __syncthreads();
+    double acc = incl - own;
+    for (int w = 0; w < wv; ++w) acc += swave[w];
+    for (int i = i0; i < i1; ++i) {
+        pre[i] = acc;
+        acc += t[i];
+    }
+    if (tid == BLK - 1) pre[nlines] = acc;
+}
+
 // ---------------------------------------------------------------------------
 // forward: projection and angle derivative, edge-driven
 // ---------------------------------------------------------------------------
@@ -301,6 +337,8 @@ struct FwdArgs {
     const PackEntry *colpack_m;
     const double *rowtot;       // line totals [img][ny]
     const double *coltot;       // [img][nx]
+    const double *rowpre;       // exclusive prefixes of the totals [img][ny + 1], or null: the
+    const double *colpre;       // kernel then sums the skipped lines itself; [img][nx + 1]
     const double *theta;
     const int64_t *view_off;
     int nframes;
@@ -384,6 +422,7 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
     const PackEntry *pack = steep ? (asc ? a.rowpack : a.rowpack_m)
                                   : (asc ? a.colpack : a.colpack_m);
     const double *ltot = steep ? a.rowtot : a.coltot;
+    const double *lpre = steep ? a.rowpre : a.colpre;
     const int64_t pstride = (int64_t)nlines * (nminor + 3);
     const int64_t tstride = nlines;
     const int64_t img0 = (int64_t)c0 * a.nframes + f;
@@ -586,8 +625,9 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
             // lines outside the union that lie wholly on the lower side of this edge: for
             // sl > 0 the lines below la, for sl < 0 the lines above lb.  A live edge has
             // WA <= la <= lb + 1 <= WB + 1, so these are the lines below WA (sl > 0) or above
-            // WB (sl < 0): two sums over the line totals shared by the wave (lanes strided
-            // over the lines, a fixed DPP reduction); the other terms are kept for exactness.
+            // WB (sl < 0).  With prefixes of the line totals each is a difference of two of
+            // them; otherwise the wave sums the totals on its side of the union (lanes strided
+            // over the lines, a fixed DPP reduction) and keeps exact sums for the other terms.
             auto range = [&](const double *lt, int l0, int l1) {
                 double t = 0.0;
                 for (int l = l0; l < l1; ++l) t += lt[l];
@@ -596,23 +636,34 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 if (c < nc && sl != 0.0) {
-                    const double *lt = ltot + (img0 + c * cstride) * tstride;
-                    double below = 0.0, above = 0.0;
-                    for (int l = lane; l < nlines; l += 64) {
-                        const double t = lt[l];
-                        if (l < WA) below += t;
-                        else if (l > WB) above += t;
+                    if (lpre != nullptr) {
+                        const double *pr = lpre + (img0 + c * cstride) * (tstride + 1);
+                        if (live) {
+                            double add = 0.0;
+                            if (sl > 0.0) {
+                                add += pr[min(la, WA)];
+                                if (la > WB + 1) add += pr[la] - pr[WB + 1];
+                            } else {
+                                if (lb + 1 < WA) add += pr[WA] - pr[lb + 1];
+                                add += pr[nlines] - pr[max(lb + 1, WB + 1)];
+                            }
+                            accP[c] += add;
+                        }
+                        continue;
                     }
-                    below = wave::wave_sum_dpp(below);
-                    above = wave::wave_sum_dpp(above);
+                    const double *lt = ltot + (img0 + c * cstride) * tstride;
+                    const int s0 = sl > 0.0 ? 0 : WB + 1, s1 = sl > 0.0 ? WA : nlines;
+                    double side = 0.0;
+                    for (int l = s0 + lane; l < s1; l += 64) side += lt[l];
+                    side = wave::wave_sum_dpp(side);
                     if (live) {
                         double add = 0.0;
                         if (sl > 0.0) {
-                            add += la >= WA ? below : range(lt, 0, la);
+                            add += la >= WA ? side : range(lt, 0, la);
                             if (la > WB + 1) add += range(lt, WB + 1, la);
                         } else {
                             if (lb + 1 < WA) add += range(lt, lb + 1, WA);
-                            add += lb <= WB ? above : range(lt, lb + 1, nlines);
+                            add += lb <= WB ? side : range(lt, lb + 1, nlines);
                         }
                         accP[c] += add;
                     }
@@ -1080,6 +1131,15 @@ int bwd_geom_ok(const nlrmm_geom &g)
     return E >= 1 && E <= 4 && bwd_window(g) <= WMAX;
 }
 
+// Images with more lines than this get prefix sums of their line totals from a launch of
+// their own: the forward kernel's own sums over the skipped lines would take each wave
+// several loads per lane and line group.
+constexpr int FWD_PREFIX_MIN_LINES = 1024;
+static bool fwd_prefixed(const nlrmm_geom &g)
+{
+    return g.nx > FWD_PREFIX_MIN_LINES || g.ny > FWD_PREFIX_MIN_LINES;
+}
+
 // Workspace for the forward pass of `gcols` columns.
 static size_t fwd_ws_bytes(const nlrmm_geom &g, int nframes, int gcols, int64_t V, int nchunks,
                            int ncols_total)
@@ -1091,6 +1151,7 @@ static size_t fwd_ws_bytes(const nlrmm_geom &g, int nframes, int gcols, int64_t 
     b += 2 * al(sizeof(PackEntry) * nimg * ny * (nx + 3));   // row packs, direct and mirrored
     b += 2 * al(sizeof(PackEntry) * nimg * nx * (ny + 3));   // column packs, likewise
     b += al(sizeof(double) * nimg * (ny + nx));              // line totals
+    if (fwd_prefixed(g)) b += al(sizeof(double) * nimg * (ny + nx + 2));   // their prefixes
     b += al(sizeof(double) * 2 * (size_t)ncols_total * V * nchunks);   // reduction partials
     return b;
 }
@@ -1165,6 +1226,12 @@ int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
     p += al(sizeof(PackEntry) * (int64_t)gcols * F * nx * (ny + 3));
     double *tot = (double *)p;
     p += al(sizeof(double) * (int64_t)gcols * F * (ny + nx));
+    const bool prefixed = fwd_prefixed(g);
+    double *pre = nullptr;
+    if (prefixed) {
+        pre = (double *)p;
+        p += al(sizeof(double) * (int64_t)gcols * F * (ny + nx + 2));
+    }
     if (red && part == nullptr) part = (double *)p;
 
     const int64_t npix = nx * ny;
@@ -1178,6 +1245,13 @@ int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
                    o.norm_status};
         pack_lines_k<<<dim3((unsigned)(ny + nx), (unsigned)nimg), BLK, 0, s>>>(
             xg, (int)nx, (int)ny, rowpack, colpack, rowpack_m, colpack_m, tot, ctot, nj);
+        double *rowpre = nullptr, *colpre = nullptr;
+        if (prefixed) {
+            rowpre = pre;
+            colpre = pre + nimg * (ny + 1);
+            line_prefix_k<<<dim3((unsigned)nimg, 2), BLK, 0, s>>>(tot, ctot, (int)nx, (int)ny,
+                                                                 rowpre, colpre);
+        }
 
         FwdArgs a;
         a.rowpack = rowpack;
@@ -1186,6 +1260,8 @@ int launch_project_ex(nlrmm_ctx *ctx, const nlrmm_geom &g, const nlrmm_batch &b,
         a.colpack_m = colpack_m;
         a.rowtot = tot;
         a.coltot = ctot;
+        a.rowpre = rowpre;
+        a.colpre = colpre;
         a.theta = theta;
         a.view_off = b.view_off;
         a.nframes = F;

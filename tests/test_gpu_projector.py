@@ -205,6 +205,33 @@ def test_nonsquare_grid_adjoint():
     assert np.max(np.abs(mass - ref)) <= 1e-6 * ref
 
 
+@pytest.mark.parametrize("nx,ny", [(1040, 1040), (1040, 40)])
+def test_wide_images_prefixed_line_sums(nx, ny):
+    """More than 1024 lines: the projection sums the lines its walks skip from prefixes of
+    the line totals instead of summing them in the kernel.  A grid of ny < nx rows is
+    centred like the square one, so it equals the square oracle on the image padded with
+    (nx - ny) / 2 zero rows above and below."""
+    nb = 1111
+    th = angles(6, 31)
+    rng = np.random.default_rng(nx + ny)
+    x = rng.uniform(0, 1, (ny, nx)).astype(np.float32)
+    g = ops.geom(nx, nb, ny=ny)
+    tht = dev(th, torch.float64)
+    print(f"case nx={nx} ny={ny} nb={nb} V={th.size}", flush=True)
+    res = ops.project_dtheta(dev(x, torch.float32), tht, g, want_dy=True, want_y=True)
+    pad = (nx - ny) // 2
+    xs = np.zeros((nx, nx))
+    xs[pad:pad + ny] = x
+    y_ref = P.project(xs, th, nb)
+    D_ref = P.dtheta(xs, th, nb)
+    y = res["y"].cpu().numpy()[0]
+    D = res["dy"].cpu().numpy()[0]
+    assert rel(y, y_ref) <= TOL, rel(y, y_ref)
+    assert per_view(y, y_ref, nb) <= TOL, per_view(y, y_ref, nb)
+    assert rel(D, D_ref) <= TOL, rel(D, D_ref)
+    assert per_view(D, D_ref, nb) <= TOL, per_view(D, D_ref, nb)
+
+
 def test_full_size_c3_projection_and_derivative():
     """512^2 image, 720 views, 725 bins (the VarPro workload) against the oracle."""
     wl = synth.WORKLOADS["c3"]
