@@ -29,6 +29,7 @@ struct GramColJob {
     double *G;
     int ldg;
     double *rb;
+    int cblk;   // blocks of the launch that take the column (set by the launcher)
 };
 // mode: 0 FP64 VALU, 1 FP32 MFMA, 2 BF16 MFMA (FP32 accumulation per chunk, FP64 across)
 // w == nullptr: the weights are formed from u with eps (inside the kernel in modes 1, 2);

@@ -271,11 +271,18 @@ __global__ __launch_bounds__(BLK, 3) void gram_psi_mfma_k(const float *__restric
     constexpr size_t RAW = SB_BYTES > CB ? SB_BYTES : CB;
     __shared__ __align__(16) unsigned char sraw[RAW];
     Elem(*sB)[LD] = reinterpret_cast<Elem(*)[LD]>(sraw);
-    // a pending data-Gram column first (its inner products need no part of this Gram)
+    // a pending data-Gram column is taken by the launch's last col.cblk blocks (its inner
+    // products need no part of this Gram, so they run beside the Gram's blocks)
+    int64_t gbid = blockIdx.x, gnb = gridDim.x;
     if constexpr (COLJOB) {
-        if (col.X != nullptr)
-            multidot_body<32>(col.X, col.ldx, col.ell + 1, col.xnew, col.b, col.n, col.part,
-                              reinterpret_cast<double(*)[BLK]>(sraw));
+        if (col.X != nullptr) {
+            gnb -= col.cblk;
+            if (gbid >= gnb) {
+                multidot_body<32>(col.X, col.ldx, col.ell + 1, col.xnew, col.b, col.n, col.part,
+                                  reinterpret_cast<double(*)[BLK]>(sraw), gbid - gnb, col.cblk);
+                return;
+            }
+        }
     }
     const TVGeo g = tvgeo(nx, ny, F, temporal, flow);
     // MOTION: the launch has the optical-flow rows (temporal mode 2 with several frames)
@@ -303,7 +310,7 @@ __global__ __launch_bounds__(BLK, 3) void gram_psi_mfma_k(const float *__restric
 #pragma unroll
     for (int r = 0; r < 16; ++r) accd[r] = 0.0;
     const int64_t nchunks = (ntot + mp - 1) / mp;
-    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    for (int64_t ch = gbid; ch < nchunks; ch += gnb) {
         const int64_t i = ch * mp + pc;
         const bool stage = pc < mp;            // lanes beyond the chunk stage nothing
         float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f;
@@ -428,7 +435,7 @@ __global__ __launch_bounds__(BLK, 3) void gram_psi_mfma_k(const float *__restric
         }
         __syncthreads();
     }
-    double *out = part + (int64_t)blockIdx.x * ell * ell;
+    double *out = part + gbid * ell * ell;
     if (single) {
         // the four row slices of tile (0,0) meet in LDS (the staging area is free after the
         // last chunk's barrier), summed in slice order
@@ -474,7 +481,7 @@ __global__ __launch_bounds__(64) void reduce_gram_k(const double *__restrict__ p
     if (t >= ell * ell) {
         const int i = t - ell * ell, nout = col.ell + 2;
         double s = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += 64) s += col.part[(int64_t)b * nout + i];
+        for (int b = threadIdx.x; b < col.cblk; b += 64) s += col.part[(int64_t)b * nout + i];
         s = wave_sum(s);
         if (threadIdx.x == 0) {
             if (i <= col.ell) {
@@ -508,7 +515,7 @@ __global__ __launch_bounds__(BLK) void multidot_k(const float *__restrict__ X, i
 {
     if (skip != nullptr && *skip != 0) return;
     __shared__ double sacc[16][BLK];
-    multidot_body<MD_MAX>(X, ldx, nv, y, z, n, part, sacc);
+    multidot_body<MD_MAX>(X, ldx, nv, y, z, n, part, sacc, blockIdx.x, gridDim.x);
 }
 
 // out[i * ostride] = sum_b part[b][i]: one wave per output, lane-strided partial sums
@@ -1823,9 +1830,13 @@ int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int
     const bool motion = temporal == TEMPORAL_OF && F > 1;
     GramColJob cj{};   // X == nullptr: no column inside this launch
     if (col != nullptr && col->X != nullptr) {
-        if (mode == 1 && col->ell + 2 <= MD_MAX &&
-            (int64_t)nblk * (col->ell + 2) <= col->part_cap) {
+        // blocks of its own, four elements per thread (one 16-byte load per column), so that
+        // they and the Gram's blocks are resident together on 256x256 images
+        int64_t cb = (col->n + 4 * BLK - 1) / (4 * BLK);
+        cb = cb < col->md_blocks ? cb : col->md_blocks;
+        if (mode == 1 && col->ell + 2 <= MD_MAX && cb * (col->ell + 2) <= col->part_cap) {
             cj = *col;
+            cj.cblk = (int)cb;
         } else {
             const int rc = k_multidot_gram_col(col->X, col->ldx, col->ell, col->xnew, col->b,
                                                col->n, col->part, col->md_blocks, col->G,
@@ -1847,10 +1858,10 @@ int k_gram_psi(const float *V, int64_t ldv, int ell, const float *w, int nx, int
         const float *ww = w ? nullptr : u;
         float *wo = w ? nullptr : wout;
         if (mode == 1 && motion)
-            gram_psi_mfma_k<false, true><<<(unsigned)nblk, BLK, 0, s>>>(
+            gram_psi_mfma_k<false, true><<<(unsigned)(nblk + cj.cblk), BLK, 0, s>>>(
                 V, ldv, ell, w, nx, ny, F, temporal, part, ww, e2, flow, wo, cj);
         else if (mode == 1)
-            gram_psi_mfma_k<false, false><<<(unsigned)nblk, BLK, 0, s>>>(
+            gram_psi_mfma_k<false, false><<<(unsigned)(nblk + cj.cblk), BLK, 0, s>>>(
                 V, ldv, ell, w, nx, ny, F, temporal, part, ww, e2, flow, wo, cj);
         else if (mode == 2 && motion)
             gram_psi_mfma_k<true, true><<<(unsigned)nblk, BLK, 0, s>>>(

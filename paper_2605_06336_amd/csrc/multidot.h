@@ -22,7 +22,8 @@ template <int CH>
 __device__ __forceinline__ void multidot_body(const float *__restrict__ X, int64_t ldx, int nv,
                                               const float *__restrict__ y,
                                               const float *__restrict__ z, int64_t n,
-                                              double *__restrict__ part, double (*sacc)[MD_BLK])
+                                              double *__restrict__ part, double (*sacc)[MD_BLK],
+                                              int64_t bid, int64_t nbk)
 {
     constexpr int GRP = 16;            // outputs reduced per LDS round
     const int tid = threadIdx.x;
@@ -37,14 +38,14 @@ __device__ __forceinline__ void multidot_body(const float *__restrict__ X, int64
 #pragma unroll
         for (int k = 0; k < MD_BLK / TPO; ++k) s += sacc[a][l + TPO * k];
         for (int off = TPO / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, TPO);
-        if (l == 0 && i0 + a < nout) part[(int64_t)blockIdx.x * nout + i0 + a] = s;
+        if (l == 0 && i0 + a < nout) part[bid * nout + i0 + a] = s;
         __syncthreads();
     };
-    if ((int64_t)gridDim.x * MD_BLK >= n) {
+    if (nbk * MD_BLK >= n) {
         // at most one element per thread: issue the loads of CH outputs first, then reduce
         // them by groups (the FP64 product of two floats is exact)
         static_assert(CH % GRP == 0 || CH == MD_MAX, "chunks of whole groups");
-        const int64_t e = (int64_t)blockIdx.x * MD_BLK + tid;
+        const int64_t e = bid * MD_BLK + tid;
         const bool in = e < n;
         const float ye = in ? y[e] : 0.0f;
         for (int c0 = 0; c0 < nout; c0 += CH) {
@@ -85,8 +86,7 @@ __device__ __forceinline__ void multidot_body(const float *__restrict__ X, int64
             const float4 *X4 = reinterpret_cast<const float4 *>(X);
             const float4 *y4 = reinterpret_cast<const float4 *>(y);
             const float4 *z4 = reinterpret_cast<const float4 *>(z);
-            for (int64_t e = (int64_t)blockIdx.x * MD_BLK + tid; e < n4;
-                 e += (int64_t)gridDim.x * MD_BLK) {
+            for (int64_t e = bid * MD_BLK + tid; e < n4; e += nbk * MD_BLK) {
                 const float4 yv = y4[e];
 #pragma unroll
                 for (int a = 0; a < GRP; ++a) {
@@ -102,8 +102,7 @@ __device__ __forceinline__ void multidot_body(const float *__restrict__ X, int64
                 }
             }
         } else {
-            for (int64_t e = (int64_t)blockIdx.x * MD_BLK + tid; e < n;
-                 e += (int64_t)gridDim.x * MD_BLK) {
+            for (int64_t e = bid * MD_BLK + tid; e < n; e += nbk * MD_BLK) {
                 const double ye = (double)y[e];
 #pragma unroll
                 for (int a = 0; a < GRP; ++a) {

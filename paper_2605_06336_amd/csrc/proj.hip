@@ -1103,7 +1103,8 @@ __global__ __launch_bounds__(256) void sum_splits_k(const float *__restrict__ pa
         // every thread takes part (the block reductions have barriers); each reads back only
         // the element it wrote
         __shared__ double sacc[16][md::MD_BLK];
-        md::multidot_body<md::MD_MAX>(md.X, md.ldx, md.nv, x, x, n, md.part, sacc);
+        md::multidot_body<md::MD_MAX>(md.X, md.ldx, md.nv, x, x, n, md.part, sacc, blockIdx.x,
+                                      gridDim.x);
     }
 }
 
