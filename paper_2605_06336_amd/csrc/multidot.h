@@ -12,6 +12,25 @@ namespace md {
 constexpr int MD_MAX = 72;    // inner products per launch
 constexpr int MD_BLK = 256;   // threads per block
 
+// sum over b = first, first + step, ... < count of p[b * stride], in that order, with U loads
+// in flight at a time (a loop that waits for each load pays one memory latency per term).
+// The loads are unconditional, their index clamped to the last term: a load under a branch
+// is waited for before the branch closes.  Terms past count add +0.0, which changes no sum.
+template <int U = 8>
+__device__ __forceinline__ double strided_sum(const double *__restrict__ p, int64_t stride,
+                                              int count, int first, int step)
+{
+    double s = 0.0;
+    for (int b0 = first; b0 < count; b0 += U * step) {
+        double v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) v[k] = p[(int64_t)min(b0 + k * step, count - 1) * stride];
+#pragma unroll
+        for (int k = 0; k < U; ++k) s += b0 + k * step < count ? v[k] : 0.0;
+    }
+    return s;
+}
+
 // Inner products <X_i, y> (i < nv) and <z, y> (i == nv when z is given), FP64 accumulation:
 // per-block partials part[block][i].  Each block reduces its share of the elements for
 // groups of 16 outputs through LDS (16 threads per output, then a 16-lane butterfly).  Every

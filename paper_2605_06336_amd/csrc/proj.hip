@@ -202,8 +202,7 @@ __global__ __launch_bounds__(BLK) void pack_lines_k(const float *__restrict__ x,
         // the squared norm as the Krylov normalisation sums it (lane-strided partials, then
         // the butterfly), its breakdown test once
         if (tid < 64) {
-            double t = 0.0;
-            for (int b = tid; b < nj.nblk; b += 64) t += nj.part[b];
+            double t = md::strided_sum(nj.part, 1, nj.nblk, tid, 64);
             t = wave_sum(t);
             const double raw = sqrt(fmax(nj.scal[0], 0.0));
             const double perp = sqrt(fmax(t, 0.0));
@@ -1081,6 +1080,18 @@ struct MdDev {
     double *part;
 };
 
+template <int NS>
+__device__ __forceinline__ double split_sum(const float *__restrict__ part, int64_t n, int64_t i,
+                                            double s)
+{
+    float pv[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) pv[k] = part[k * n + i];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) s += (double)pv[k];
+    return s;
+}
+
 template <bool MD>
 __global__ __launch_bounds__(256) void sum_splits_k(const float *__restrict__ part, int nsplit,
                                                     int64_t n, float *__restrict__ x,
@@ -1089,8 +1100,18 @@ __global__ __launch_bounds__(256) void sum_splits_k(const float *__restrict__ pa
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
+        // the partials of all splits loaded together (the tuned split counts), then summed
+        // in split order
         double s = accumulate ? (double)x[i] : 0.0;
-        for (int k = 0; k < nsplit; ++k) s += (double)part[k * n + i];
+        switch (nsplit) {
+            case 1: s = split_sum<1>(part, n, i, s); break;
+            case 2: s = split_sum<2>(part, n, i, s); break;
+            case 4: s = split_sum<4>(part, n, i, s); break;
+            case 8: s = split_sum<8>(part, n, i, s); break;
+            case 16: s = split_sum<16>(part, n, i, s); break;
+            default:
+                for (int k = 0; k < nsplit; ++k) s += (double)part[k * n + i];
+        }
         float v = (float)s;
         if (tv.u != nullptr)
             v += (float)tv.lamp[0] *
