@@ -480,8 +480,7 @@ __global__ __launch_bounds__(64) void reduce_gram_k(const double *__restrict__ p
     const int t = blockIdx.x;
     if (t >= ell * ell) {
         const int i = t - ell * ell, nout = col.ell + 2;
-        double s = 0.0;
-        for (int b = threadIdx.x; b < col.cblk; b += 64) s += col.part[(int64_t)b * nout + i];
+        double s = md::strided_sum(col.part + i, nout, col.cblk, threadIdx.x, 64);
         s = wave_sum(s);
         if (threadIdx.x == 0) {
             if (i <= col.ell) {
@@ -493,8 +492,7 @@ __global__ __launch_bounds__(64) void reduce_gram_k(const double *__restrict__ p
         }
         return;
     }
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 64) s += part[(int64_t)b * ell * ell + t];
+    double s = md::strided_sum(part + t, (int64_t)ell * ell, nblk, threadIdx.x, 64);
     s = wave_sum(s);
     if (threadIdx.x == 0) {
         const int i = t / ell, j = t - i * ell;
@@ -528,8 +526,7 @@ __global__ __launch_bounds__(64) void reduce_vec_k(const double *__restrict__ pa
 {
     if (skip != nullptr && *skip != 0) return;
     const int i = blockIdx.x;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 64) s += part[(int64_t)b * nout + i];
+    double s = md::strided_sum(part + i, nout, nblk, threadIdx.x, 64);
     s = wave_sum(s);
     if (threadIdx.x != 0) return;
     if (G == nullptr) {
