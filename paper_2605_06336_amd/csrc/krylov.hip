@@ -564,13 +564,14 @@ __device__ void rereduce_k(const double *__restrict__ part, int nblk, int nout, 
         double v[U][K];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int q = q0 + u * BLK + tid;
+            // unconditional loads at clamped indices (a load under a branch is waited for
+            // before the branch closes, which would serialise them); the sums below skip the
+            // clamped ones
+            const int q = min(q0 + u * BLK + tid, npair - 1);
             const int L = q / nout, i = q - L * nout;
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int b = L + 64 * k;
-                v[u][k] = (q < npair && b < nblk) ? part[(int64_t)b * nout + i] : 0.0;
-            }
+            for (int k = 0; k < K; ++k)
+                v[u][k] = part[(int64_t)min(L + 64 * k, nblk - 1) * nout + i];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -642,9 +643,15 @@ __global__ __launch_bounds__(BLK) void gemv_multidot_k(const float *__restrict__
     if ((int64_t)gridDim.x * BLK >= n) {
         const int64_t e = (int64_t)blockIdx.x * BLK + tid;
         const bool in = e < n;
+        // the columns' loads issued together: unconditional, at a clamped column and element
+        // (a load under a per-lane branch is waited for before the branch closes), the
+        // clamped ones zeroed after
+        const int64_t ec = in ? e : 0;
         float xv[MD_MAX];
 #pragma unroll
-        for (int i = 0; i < MD_MAX; ++i) xv[i] = (i < nv && in) ? X[(int64_t)i * ldx + e] : 0.0f;
+        for (int i = 0; i < MD_MAX; ++i) xv[i] = X[(int64_t)min(i, nv - 1) * ldx + ec];
+#pragma unroll
+        for (int i = 0; i < MD_MAX; ++i) xv[i] = (i < nv && in) ? xv[i] : 0.0f;
         double sg = 0.0;
 #pragma unroll
         for (int i = 0; i < MD_MAX; ++i)
