@@ -317,34 +317,52 @@ __global__ __launch_bounds__(BLK, 3) void gram_psi_mfma_k(const float *__restric
         int64_t ox = -1, oy = -1, ot = -1;   // neighbour offsets of the existing differences
         OfCell cf{0, 0.f, 0.f, 0.f, 0.f}, cr{0, 0.f, 0.f, 0.f, 0.f};   // motion rows' cells
         int64_t fo = 0, ro = 0;              // their frames' first pixels (f + 1 and f)
-        if (stage && i < ntot) {
-            const int64_t f = i / npix, p = i - f * npix;
-            const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
-            // weights stored in w, or formed from u (the same values) and then, when wout is
-            // given, stored there by wave 0 (each weight belongs to one pixel of one chunk)
-            const float uc = u != nullptr ? u[i] : 0.0f;
-            const bool put = wout != nullptr && u != nullptr && wv == 0;
-            if (k < nx - 1) {
-                const int64_t at = f * g.per_frame + (int64_t)l * (nx - 1) + k;
-                const float wr = u != nullptr ? tv_weight(u[i + 1] - uc, e2) : w[at];
-                if (put) wout[at] = wr;
-                w0 = sqrtf(wr);
-                ox = 1;
-            }
-            if (l < ny - 1) {
-                const int64_t at = f * g.per_frame + g.dy_off + (int64_t)l * nx + k;
-                const float wr = u != nullptr ? tv_weight(u[i + nx] - uc, e2) : w[at];
-                if (put) wout[at] = wr;
-                w1 = sqrtf(wr);
-                oy = nx;
-            }
-            if (g.temporal == TEMPORAL_DIFF && f < F - 1) {
-                const int64_t at = g.t_off + f * npix + p;
-                const float wr = u != nullptr ? tv_weight(u[i + npix] - uc, e2) : w[at];
-                if (put) wout[at] = wr;
-                w2 = sqrtf(wr);
-                ot = npix;
-            }
+        // Every load of the staging is unconditional, at an index that always exists (lanes
+        // that stage nothing read element 0, a missing neighbour reads the pixel itself, a
+        // missing weight entry reads entry 0), and the values are selected afterwards: a load
+        // under a per-lane branch is waited for before the branch closes, which would put
+        // one memory latency per column on the chain.
+        const bool live = stage && i < ntot;
+        const int64_t ib = live ? i : 0;
+        const int64_t f = ib / npix, p = ib - f * npix;
+        const int l = (int)(p / nx), k = (int)(p - (int64_t)l * nx);
+        const bool hx = live && k < nx - 1, hy = live && l < ny - 1;
+        const bool ht = live && g.temporal == TEMPORAL_DIFF && f < F - 1;
+        const int64_t atx = hx ? f * g.per_frame + (int64_t)l * (nx - 1) + k : 0;
+        const int64_t aty = hy ? f * g.per_frame + g.dy_off + (int64_t)l * nx + k : 0;
+        const int64_t att = ht ? g.t_off + f * npix + p : 0;
+        // weights stored in w, or formed from u (the same values) and then, when wout is
+        // given, stored there by wave 0 (each weight belongs to one pixel of one chunk)
+        float uc = 0.0f, wx, wy, wt;
+        if (u != nullptr) {
+            uc = u[ib];
+            const float ux = u[ib + (hx ? 1 : 0)], uy = u[ib + (hy ? nx : 0)];
+            const float ut = u[ib + (ht ? npix : 0)];
+            wx = tv_weight(ux - uc, e2);
+            wy = tv_weight(uy - uc, e2);
+            wt = tv_weight(ut - uc, e2);
+        } else {
+            wx = w[atx];
+            wy = w[aty];
+            wt = w[att];
+        }
+        const bool put = wout != nullptr && u != nullptr && wv == 0;
+        if (hx) {
+            if (put) wout[atx] = wx;
+            w0 = sqrtf(wx);
+            ox = 1;
+        }
+        if (hy) {
+            if (put) wout[aty] = wy;
+            w1 = sqrtf(wy);
+            oy = nx;
+        }
+        if (ht) {
+            if (put) wout[att] = wt;
+            w2 = sqrtf(wt);
+            ot = npix;
+        }
+        if (live) {
             if (motion && f < F - 1) {
                 const float *sx = flow + 2 * f * npix, *sy = sx + npix;
                 cf = of_cell(sx[p], sy[p], k, l, nx, ny);
@@ -374,12 +392,26 @@ __global__ __launch_bounds__(BLK, 3) void gram_psi_mfma_k(const float *__restric
 #pragma unroll
             for (int u = 0; u < UC; ++u) {
                 const int c = c0 + u * (BLK / 64);
-                const bool ok = stage && c < ell && i < ntot;
+                const bool ok = live && c < ell;
                 const float *vc = V + (int64_t)(ok ? c : 0) * ldv;
-                x0[u] = ok ? vc[i] : 0.0f;
-                x1[u] = (ok && ox > 0) ? vc[i + ox] : x0[u];
-                x2[u] = (ok && oy > 0) ? vc[i + oy] : x0[u];
-                x3[u] = (ok && ot > 0) ? vc[i + ot] : x0[u];
+                if constexpr (!BF16) {
+                    const int64_t ic = ok ? i : 0;
+                    const float a0 = vc[ic];
+                    const float a1 = vc[ic + (ok && ox > 0 ? ox : 0)];
+                    const float a2 = vc[ic + (ok && oy > 0 ? oy : 0)];
+                    const float a3 = vc[ic + (ok && ot > 0 ? ot : 0)];
+                    x0[u] = ok ? a0 : 0.0f;
+                    x1[u] = (ok && ox > 0) ? a1 : x0[u];
+                    x2[u] = (ok && oy > 0) ? a2 : x0[u];
+                    x3[u] = (ok && ot > 0) ? a3 : x0[u];
+                } else {
+                    // (the BF16 instances keep the guarded form: the unconditional one needs
+                    // registers that would cost them a wave per SIMD)
+                    x0[u] = ok ? vc[i] : 0.0f;
+                    x1[u] = (ok && ox > 0) ? vc[i + ox] : x0[u];
+                    x2[u] = (ok && oy > 0) ? vc[i + oy] : x0[u];
+                    x3[u] = (ok && ot > 0) ? vc[i + ot] : x0[u];
+                }
                 // motion rows: the column's frames f + 1 and f warped at the pixel's cells
                 m0[u] = (ok && motion && ot > 0) ? of_sample(vc + fo, cf, nx) : x0[u];
                 m1[u] = (ok && motion && ot > 0) ? of_sample(vc + ro, cr, nx) : x3[u];
