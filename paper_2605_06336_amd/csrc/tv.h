@@ -113,14 +113,29 @@ __device__ __forceinline__ float tv_grad_at(const float *__restrict__ u,
         }
         return acc;
     }
+    // the loads are unconditional, at indices that always exist (a missing neighbour reads
+    // the pixel itself, a missing weight the frame's first entry), and the missing terms are
+    // dropped afterwards: a load under a per-lane branch is waited for before the branch
+    // closes, one memory latency per term
     const float *wf = w + f * g.per_frame;
-    if (k < nx - 1) acc -= wf[(int64_t)l * (nx - 1) + k] * (u[i + 1] - uc);
-    if (k > 0) acc += wf[(int64_t)l * (nx - 1) + k - 1] * (uc - u[i - 1]);
-    if (l < ny - 1) acc -= wf[g.dy_off + (int64_t)l * nx + k] * (u[i + nx] - uc);
-    if (l > 0) acc += wf[g.dy_off + (int64_t)(l - 1) * nx + k] * (uc - u[i - nx]);
+    const bool xp = k < nx - 1, xm = k > 0, yp = l < ny - 1, ym = l > 0;
+    const float uxp = u[i + (xp ? 1 : 0)], uxm = u[i - (xm ? 1 : 0)];
+    const float uyp = u[i + (yp ? nx : 0)], uym = u[i - (ym ? nx : 0)];
+    const float wxp = wf[xp ? (int64_t)l * (nx - 1) + k : 0];
+    const float wxm = wf[xm ? (int64_t)l * (nx - 1) + k - 1 : 0];
+    const float wyp = wf[yp ? g.dy_off + (int64_t)l * nx + k : 0];
+    const float wym = wf[ym ? g.dy_off + (int64_t)(l - 1) * nx + k : 0];
+    if (xp) acc -= wxp * (uxp - uc);
+    if (xm) acc += wxm * (uc - uxm);
+    if (yp) acc -= wyp * (uyp - uc);
+    if (ym) acc += wym * (uc - uym);
     if (g.temporal == TEMPORAL_DIFF) {
-        if (f < g.F - 1) acc -= w[g.t_off + f * npix + p] * (u[i + npix] - uc);
-        if (f > 0) acc += w[g.t_off + (f - 1) * npix + p] * (uc - u[i - npix]);
+        const bool tp = f < g.F - 1, tm = f > 0;
+        const float utp = u[i + (tp ? npix : 0)], utm = u[i - (tm ? npix : 0)];
+        const float wtp = w[tp ? g.t_off + f * npix + p : 0];
+        const float wtm = w[tm ? g.t_off + (f - 1) * npix + p : 0];
+        if (tp) acc -= wtp * (utp - uc);
+        if (tm) acc += wtm * (uc - utm);
     }
     return acc;
 }
