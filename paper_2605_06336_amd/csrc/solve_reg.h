@@ -212,8 +212,11 @@ __global__ __launch_bounds__(64) void gks_solve_reg_k(const double *__restrict__
     const int n = ell;
     const int lane = threadIdx.x;
     const bool row = lane < NB;
-    const double trA = wave_sum_dpp(lane < n ? GA[lane * ldg + lane] : 0.0);
-    const double trP = wave_sum_dpp(lane < n ? GP[lane * ldg + lane] : 0.0);
+    // both diagonals' loads in flight together (unconditional, lanes past n read entry 0)
+    const int ld = lane < n ? lane : 0;
+    const double gad = GA[ld * ldg + ld], gpd = GP[ld * ldg + ld];
+    const double trA = wave_sum_dpp(lane < n ? gad : 0.0);
+    const double trP = wave_sum_dpp(lane < n ? gpd : 0.0);
     double a[NB], p[NB];
     int bad = 0;
     // L (rows, lane i = row i) and its reciprocal diagonal are kept in Lst[i * ldg + k] and
