@@ -95,9 +95,13 @@ def parse():
 
 
 def source_digest():
-    """Digest of the projector source: counters recorded for another version are void."""
-    with open(os.path.join(ROOT, "paper_2605_06336_amd", "csrc", "proj.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Digest of the projector source and the headers it includes: counters recorded for
+    another version are void."""
+    h = hashlib.sha256()
+    for name in ("proj.hip", "internal.h", "multidot.h", "tv.h", "wave.h"):
+        with open(os.path.join(ROOT, "paper_2605_06336_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def make_data(torch, ops, inst, wl, g, fr=None):
