@@ -652,8 +652,8 @@ __global__ __launch_bounds__(64 * FSEG) void fwd_edges_k(FwdArgs a)
                     }
                     const double *lt = ltot + (img0 + c * cstride) * tstride;
                     const int s0 = sl > 0.0 ? 0 : WB + 1, s1 = sl > 0.0 ? WA : nlines;
-                    double side = 0.0;
-                    for (int l = s0 + lane; l < s1; l += 64) side += lt[l];
+                    // a lane's lines with eight loads in flight, in line order
+                    double side = md::strided_sum(lt + s0, 1, s1 - s0, lane, 64);
                     side = wave::wave_sum_dpp(side);
                     if (live) {
                         double add = 0.0;
