@@ -913,15 +913,16 @@ struct GemvJob {
 
 __global__ __launch_bounds__(BLK) void gemv2_k(GemvJob j0, GemvJob j1, unsigned g0)
 {
-    __shared__ double sc[MD_MAX];
     const bool first = blockIdx.x < g0;
     const GemvJob &j = first ? j0 : j1;
     const int64_t blk = first ? blockIdx.x : blockIdx.x - g0;
     const int64_t nblk = first ? g0 : gridDim.x - g0;
-    for (int i = threadIdx.x; i < j.nv; i += BLK) sc[i] = j.c[i];
-    __syncthreads();
+    // the coefficients read where they are (one address for the whole block): no LDS staging
+    // and no barrier ahead of the first column loads
+    const double *__restrict__ sc = j.c;
     for (int64_t e = blk * BLK + threadIdx.x; e < j.n; e += nblk * BLK) {
         double s = 0.0;
+#pragma unroll 8
         for (int i = 0; i < j.nv; ++i) s = fma((double)j.X[(int64_t)i * j.ldx + e], sc[i], s);
         double r = j.beta * s;
         if (j.a) r += j.alpha * (double)j.a[e];
