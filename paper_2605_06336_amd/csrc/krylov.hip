@@ -1952,8 +1952,9 @@ int k_cgs2(const float *X, int64_t ldx, int nv, float *r, int64_t n, double *par
     if (g < 1) g = 1;
     const unsigned g3 = grid_for(n);   // blocks of the norm partials (<= 4096 <= 72 nblk)
     if (p1_blocks > 0) {
-        // the first products came with r, from the launch that wrote it
-        if (p1_blocks != g || g > RR_MAXBLK) return NLRMM_EINVAL;
+        // the first products came with r, from the launch that wrote it (the fused kernels
+        // need at least one column: their loads clamp the column index to nv - 1)
+        if (p1_blocks != g || g > RR_MAXBLK || nv < 1) return NLRMM_EINVAL;
     } else if (nv < 1 || g > RR_MAXBLK) {
         // a launch per reduction (the same arithmetic except for the order of the block sums)
         int rc;
